@@ -1,0 +1,80 @@
+/*
+ * ocean_oracle.h -- declarations of the plain FP64 CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load this library; the product library never includes,
+ * links or calls it. It shares no header, helper or table with the GPU path.
+ *
+ * The oracle advances a hydrostatic Boussinesq ocean on an Arakawa C-grid by
+ * one explicit baroclinic step followed by the sub-cycled split-explicit
+ * barotropic loop (paper Sec. 5.2 "New numerical methods" and Sec. 5.3
+ * "Optimization of ocean free surface dynamics"). Everything is double
+ * precision, plain loops, no blocking or fusion.
+ */
+#ifndef OCEAN_ORACLE_H
+#define OCEAN_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Grid, physical constants and time-stepping parameters in one flat record. */
+typedef struct orc_desc {
+    int32_t nx, ny, nz;            /* interior cells; k = 0 is the bottom layer   */
+    int32_t periodic_x, periodic_y;/* 1 = periodic, 0 = bounded by walls          */
+    int32_t coords;                /* 0 = Cartesian beta-plane, 1 = lat-lon sphere */
+    int32_t n_substeps;            /* barotropic substeps per baroclinic step     */
+    int32_t reserved;
+    double x0, y0, dx, dy;         /* Cartesian: metres. lat-lon: lon0, lat_south, dlon, dlat in degrees */
+    double f0, beta;               /* beta-plane Coriolis f = f0 + beta (y - Ly/2) */
+    double radius, omega;          /* sphere radius (m) and rotation rate (1/s)   */
+    double dt, chi;                /* baroclinic step (s) and AB2 offset          */
+    double g, alpha, rho0, t_ref;  /* gravity, thermal expansion, density, EOS reference T */
+    double kappa;                  /* vertical diffusivity = viscosity (m^2/s)    */
+    double restore_tau;            /* surface restoring time (s); <= 0 turns it off */
+} orc_desc;
+
+typedef struct orc_model orc_model;
+
+/* Field identifiers for orc_set_field / orc_get_field. 3D fields are [k][j][i]
+ * (nz*ny*nx), 2D fields [j][i] (ny*nx); W is (nz+1)*ny*nx on z-faces. */
+enum {
+    ORC_U = 0, ORC_V = 1, ORC_T = 2, ORC_ETA = 3, ORC_UBT = 4, ORC_VBT = 5,
+    ORC_ETA_MEAN = 6, ORC_UBT_MEAN = 7, ORC_VBT_MEAN = 8, ORC_W = 9,
+    ORC_GU_PREV = 10, ORC_GV_PREV = 11, ORC_GT_PREV = 12,
+    ORC_TAUX = 13, ORC_TAUY = 14, ORC_TSTAR = 15, ORC_P = 16
+};
+
+/* Tendency term selectors for orc_eval_tendencies. */
+enum { ORC_TERM_ADV = 1, ORC_TERM_COR = 2, ORC_TERM_PGF = 4, ORC_TERM_WIND = 8,
+       ORC_TERM_RESTORE = 16, ORC_TERM_ALL = 31 };
+
+/* Number of doubles written by orc_diagnostics. */
+#define ORC_NDIAG 16
+
+orc_model* orc_create(const orc_desc* d, const double* dz, const int32_t* kbottom);
+void       orc_destroy(orc_model* m);
+int        orc_set_field(orc_model* m, int field, const double* src);
+int        orc_get_field(orc_model* m, int field, double* dst);
+void       orc_set_first_step(orc_model* m, int first);
+int        orc_get_first_step(const orc_model* m);
+void       orc_step(orc_model* m, int n);
+void       orc_diagnostics(const orc_model* m, double* out);
+
+/* Stage-level entry points used by the physics and unit pins. */
+void   orc_eval_tendencies(const orc_model* m, int terms, double* gu, double* gv, double* gt);
+double orc_weno5z(double a, double b, double c, double d, double e);
+double orc_weno3(double b, double c, double d);
+double orc_reconstruct(const double* s, const int32_t* ok);
+void   orc_thomas(int n, const double* a, const double* b, const double* c,
+                  const double* d, double* x);
+double orc_neumaier_sum(const double* x, int64_t n);
+void   orc_column_zflux(int nz, const double* phi, const int32_t* wet,
+                        const double* wface, double* flux);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

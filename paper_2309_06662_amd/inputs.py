@@ -1,0 +1,267 @@
+"""Seeded synthetic inputs and workload recipes.
+
+This module is the only code shared by the product path and the CPU oracle's
+tests. It holds no arithmetic of the ocean method itself: it builds the inputs
+the method is given -- layer thicknesses, the wet-layer count of every column
+(bathymetry), the initial temperature, wind stress and the restoring target --
+from a counter-based random generator, and it lists the workloads.
+
+Stand-ins. The paper's realistic runs use ECCO2 forcing and real bathymetry and
+its aqua-planet runs an idealised two-ridge geometry (paper Sec. 6); neither is
+available here. The generators below give inputs of the same shapes and sizes:
+near-global lat-lon grids periodic in longitude, seamount-and-ridge bathymetry
+up to 5.5 km deep with two ridges that split the ocean into two basins north of
+50S, exponential stratification with small seeded noise, a zonal wind stress
+that varies as cos(latitude), and surface temperature restoring.
+
+Random numbers: splitmix64 (Steele, Lea and Flood, 2014) evaluated at a counter,
+so any element can be drawn independently of the others. A draw is
+mix64(base(seed, stream) + (n + 1) * GOLDEN) with base = mix64(seed ^ (stream << 32)).
+Uniforms take the top 53 bits; normals use Box-Muller (cosine branch) on the
+uniform pair drawn at counters 2n and 2n+1. Streams: 0 temperature noise,
+1 bathymetry, 2 ensemble-member parameters.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, Optional
+
+import numpy as np
+
+GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+STREAM_TEMPERATURE = 0
+STREAM_BATHYMETRY = 1
+STREAM_MEMBERS = 2
+
+
+def _mix64(z: np.ndarray) -> np.ndarray:
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def _base(seed: int, stream: int) -> np.uint64:
+    s = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) ^ (np.uint64(stream) << np.uint64(32))
+    return _mix64(np.array([s], dtype=np.uint64))[0]
+
+
+def draw_u64(seed: int, stream: int, counters: np.ndarray) -> np.ndarray:
+    """Raw 64-bit splitmix64 outputs at the given counters."""
+    n = np.asarray(counters, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = _base(seed, stream) + (n + np.uint64(1)) * GOLDEN
+    return _mix64(z)
+
+
+def uniform(seed: int, stream: int, counters: np.ndarray) -> np.ndarray:
+    """Uniform deviates in [0, 1) from the top 53 bits."""
+    return (draw_u64(seed, stream, counters) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def normal(seed: int, stream: int, counters: np.ndarray) -> np.ndarray:
+    """Standard normal deviates, Box-Muller cosine branch on draws 2n and 2n+1."""
+    n = np.asarray(counters, dtype=np.uint64)
+    u1 = uniform(seed, stream, n * np.uint64(2))
+    u2 = uniform(seed, stream, n * np.uint64(2) + np.uint64(1))
+    return np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * math.pi * u2)
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """A synthetic basin: grid, constants, forcing recipe and stepping parameters."""
+
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    coords: str = "cartesian"          # "cartesian" beta-plane or "latlon"
+    periodic_x: bool = False
+    periodic_y: bool = False
+    x0: float = 0.0                     # Cartesian: m. lat-lon: longitude of the west edge (deg)
+    y0: float = 0.0                     # lat-lon: latitude of the south edge (deg)
+    dx: float = 50e3                    # Cartesian: m. lat-lon: degrees of longitude
+    dy: float = 50e3                    # Cartesian: m. lat-lon: degrees of latitude
+    depth: float = 4000.0
+    bathymetry: str = "flat"            # "flat" or "seamounts"
+    halo: int = 3
+    f0: float = 1e-4
+    beta: float = 2e-11
+    radius: float = 6.371e6
+    omega: float = 7.292115e-5
+    g: float = 9.81
+    alpha: float = 2e-4
+    rho0: float = 1025.0
+    t_ref: float = 0.0
+    kappa: float = 1e-5
+    dt: float = 1200.0
+    n_substeps: int = 30
+    chi: float = 0.0
+    tau0: float = 0.1                   # wind-stress amplitude, N/m^2
+    restore_days: float = 0.0           # <= 0: no restoring
+    strat_t0: float = 20.0              # T = strat_t0 * exp(z / strat_scale) + noise
+    strat_scale: float = 1000.0
+    noise_std: float = 0.01
+    seed: int = 0
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def replace(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+# Closed beta-plane basin, 64x64x16, dx = dy = 50 km, 4 km flat bottom, 30 substeps.
+BETA_BASIN_64 = Workload(name="beta_basin_64x64x16", nx=64, ny=64, nz=16)
+
+# Near-global lat-lon at 1/4 degree: 1440x600x50 over 80S-80N, periodic in longitude,
+# seamount-and-ridge bathymetry to 5.5 km, restoring, dt = 600 s, 60 substeps.
+LATLON_QUARTER = Workload(
+    name="latlon_1440x600x50", nx=1440, ny=600, nz=50, coords="latlon", periodic_x=True,
+    x0=0.0, y0=-80.0, dx=0.25, dy=160.0 / 600.0, depth=5500.0, bathymetry="seamounts",
+    dt=600.0, n_substeps=60, restore_days=30.0)
+
+# One GPU's share at 1/12 degree: 4320x1800x100 over 75S-75N, 5-point halos,
+# dt = 300 s, 60 substeps.
+LATLON_TWELFTH = Workload(
+    name="latlon_4320x1800x100", nx=4320, ny=1800, nz=100, coords="latlon", periodic_x=True,
+    x0=0.0, y0=-75.0, dx=1.0 / 12.0, dy=1.0 / 12.0, depth=5500.0, bathymetry="seamounts",
+    halo=5, dt=300.0, n_substeps=60, restore_days=30.0)
+
+WORKLOADS = {w.name: w for w in (BETA_BASIN_64, LATLON_QUARTER, LATLON_TWELFTH)}
+
+
+def layer_thickness(w: Workload) -> np.ndarray:
+    """Uniform layers over the full depth, bottom to top."""
+    return np.full(w.nz, w.depth / w.nz, dtype=np.float64)
+
+
+def layer_centre_z(w: Workload) -> np.ndarray:
+    """Height of every layer centre (m, negative below the surface), bottom to top."""
+    dz = layer_thickness(w)
+    top = np.cumsum(dz) - w.depth
+    return top - 0.5 * dz
+
+
+def _centres_deg(w: Workload):
+    lon = w.x0 + (np.arange(w.nx) + 0.5) * w.dx
+    lat = w.y0 + (np.arange(w.ny) + 0.5) * w.dy
+    return lon, lat
+
+
+def seafloor_depth(w: Workload) -> np.ndarray:
+    """Sea-floor depth D(lon, lat) in metres, [ny, nx].
+
+    D = depth - sum over 200 seamounts h exp(-r^2 / (2 sigma^2))
+              - sum over two ridges depth exp(-dlon^2 / (2 * 2deg^2)) north of 50S,
+    clipped to [0, depth]. Seamount heights U(1000, 5000) m, widths U(1, 4) deg,
+    longitudes U(0, 360), latitudes U(-70, 70); r^2 = (dlon cos(lat_s))^2 + dlat^2
+    in degrees with dlon wrapped to [-180, 180). Ridges sit at 0 and 90 deg E.
+    """
+    lon, lat = _centres_deg(w)
+    d = np.full((w.ny, w.nx), w.depth, dtype=np.float64)
+    if w.bathymetry == "flat":
+        return d
+    if w.coords != "latlon":
+        raise ValueError("seamount bathymetry needs a lat-lon grid")
+    n_mounts = 200
+    u = uniform(w.seed, STREAM_BATHYMETRY, np.arange(4 * n_mounts, dtype=np.uint64)).reshape(n_mounts, 4)
+    h = 1000.0 + 4000.0 * u[:, 0]
+    sig = 1.0 + 3.0 * u[:, 1]
+    lon_s = 360.0 * u[:, 2]
+    lat_s = -70.0 + 140.0 * u[:, 3]
+    for s in range(n_mounts):
+        dl = (lon - lon_s[s] + 180.0) % 360.0 - 180.0
+        ex = np.exp(-((dl * math.cos(math.radians(lat_s[s]))) ** 2) / (2.0 * sig[s] ** 2))
+        ey = np.exp(-((lat - lat_s[s]) ** 2) / (2.0 * sig[s] ** 2))
+        d -= h[s] * np.outer(ey, ex)
+    north = (lat > -50.0).astype(np.float64)
+    for lon_r in (0.0, 90.0):
+        dl = (lon - lon_r + 180.0) % 360.0 - 180.0
+        d -= w.depth * np.outer(north, np.exp(-dl ** 2 / (2.0 * 2.0 ** 2)))
+    return np.clip(d, 0.0, w.depth)
+
+
+def wet_layers(w: Workload) -> np.ndarray:
+    """Number of wet layers per column counted from the surface, int32 [ny, nx].
+
+    Full cells: K = floor(D / dz + 1/2); columns with fewer than two wet layers
+    are land.
+    """
+    if w.bathymetry == "flat":
+        return np.full((w.ny, w.nx), w.nz, dtype=np.int32)
+    dz = w.depth / w.nz
+    k = np.floor(seafloor_depth(w) / dz + 0.5).astype(np.int32)
+    k = np.clip(k, 0, w.nz)
+    k[k < 2] = 0
+    return k
+
+
+def initial_temperature(w: Workload, levels: Optional[range] = None) -> np.ndarray:
+    """T = strat_t0 exp(z / strat_scale) + noise_std N(0, 1), [nz, ny, nx] (or the given levels).
+
+    The noise of cell (i, j, k) is the normal deviate at counter i + nx (j + ny k)
+    of the temperature stream.
+    """
+    zc = layer_centre_z(w)
+    ks = range(w.nz) if levels is None else levels
+    out = np.empty((len(ks), w.ny, w.nx), dtype=np.float64)
+    plane = np.arange(w.nx * w.ny, dtype=np.uint64)
+    for q, k in enumerate(ks):
+        base = w.strat_t0 * math.exp(zc[k] / w.strat_scale)
+        if w.noise_std != 0.0:
+            n = normal(w.seed, STREAM_TEMPERATURE, plane + np.uint64(k * w.nx * w.ny))
+            out[q] = base + w.noise_std * n.reshape(w.ny, w.nx)
+        else:
+            out[q] = base
+    return out
+
+
+def wind_stress(w: Workload):
+    """Zonal stress at u-points and meridional stress at v-points, each [ny, nx] (N/m^2).
+
+    Lat-lon: tau_x = tau0 cos(lat of the row). Beta-plane: tau_x = tau0 cos(pi (y - Ly/2) / Ly),
+    the basin mapped onto latitudes -90..90. tau_y = 0.
+    """
+    if w.coords == "latlon":
+        _, lat = _centres_deg(w)
+        prof = w.tau0 * np.cos(np.radians(lat))
+    else:
+        ly = w.ny * w.dy
+        y = (np.arange(w.ny) + 0.5) * w.dy
+        prof = w.tau0 * np.cos(math.pi * (y - 0.5 * ly) / ly)
+    taux = np.repeat(prof[:, None], w.nx, axis=1).astype(np.float64)
+    return taux, np.zeros_like(taux)
+
+
+def restoring_target(w: Workload) -> np.ndarray:
+    """Surface restoring temperature T* = 20 cos(lat) degC, [ny, nx] (zero when restoring is off)."""
+    if w.restore_days <= 0.0:
+        return np.zeros((w.ny, w.nx), dtype=np.float64)
+    if w.coords == "latlon":
+        _, lat = _centres_deg(w)
+        prof = 20.0 * np.cos(np.radians(lat))
+    else:
+        ly = w.ny * w.dy
+        y = (np.arange(w.ny) + 0.5) * w.dy
+        prof = 20.0 * np.cos(math.pi * (y - 0.5 * ly) / ly)
+    return np.repeat(prof[:, None], w.nx, axis=1).astype(np.float64)
+
+
+def make_inputs(w: Workload) -> Dict[str, np.ndarray]:
+    """All inputs of a workload: dz, kbottom, T0, taux, tauy, tstar."""
+    taux, tauy = wind_stress(w)
+    return {
+        "dz": layer_thickness(w),
+        "kbottom": wet_layers(w),
+        "T0": initial_temperature(w),
+        "taux": taux,
+        "tauy": tauy,
+        "tstar": restoring_target(w),
+    }

@@ -1,0 +1,172 @@
+"""Physics pins of the oracle's full step: what the equations fix independently
+of the discretisation details (paper Sec. 5.2, 5.3).
+
+- a resting stratified ocean stays at rest; every column then only diffuses;
+- tracer content and free-surface volume are conserved to round-off (flux form);
+- the free surface moves by the divergence of the averaged transport, and the
+  3D velocity integrates to the barotropic transport after the correction;
+- a basin-mode gravity wave has the discrete forward-backward frequency, close
+  to the continuous sqrt(gH) value;
+- a uniform inertial oscillation follows the AB2 recurrence of dz/dt = -i f z;
+- restarting from a saved state is bitwise identical to running straight on.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_06662_amd import inputs
+from tests.helpers import masks, metrics, small_latlon
+
+
+def test_rest_state_stays_at_rest():
+    w = inputs.BETA_BASIN_64.replace(nx=16, ny=12, noise_std=0.0, tau0=0.0)
+    inp = inputs.make_inputs(w)
+    m = oracle.OracleModel.from_inputs(w, inp)
+    # a uniform surface offset exerts no force and is its own substep average
+    m.set("eta", np.full((w.ny, w.nx), 0.125))
+    m.step(20)
+    for name in ("u", "v", "U", "V", "U_mean", "V_mean"):
+        assert np.all(m.get(name) == 0.0), name
+    assert np.all(m.get("eta") == 0.125) and np.all(m.get("eta_mean") == 0.125)
+    assert np.all(m.get("w") == 0.0)
+    T = m.get("T")
+    assert np.all(T == T[:, :1, :1])
+    # a single column run the same way matches every column bitwise
+    c = w.replace(nx=1, ny=1, periodic_x=True, periodic_y=True)
+    mc = oracle.OracleModel.from_inputs(c, inputs.make_inputs(c))
+    mc.step(20)
+    assert np.array_equal(mc.get("T")[:, 0, 0], T[:, 0, 0])
+    assert not np.array_equal(T[:, 0, 0], inp["T0"][:, 0, 0])  # diffusion acted
+
+
+def _tracer_content(T, w, kb, dz):
+    wet, _, _ = masks(w, kb)
+    _, _, _, area = metrics(w)
+    vol = area[None, :, None] * dz[:, None, None]
+    return math.fsum((vol * T)[wet].ravel())
+
+
+@pytest.mark.parametrize("case", ["beta", "latlon"])
+def test_conservation_and_consistency(case):
+    if case == "beta":
+        w = inputs.BETA_BASIN_64.replace(nx=24, ny=20)
+        nsteps = 12
+    else:
+        w = small_latlon(restore_days=0.0, tau0=0.2)
+        nsteps = 6
+    inp = inputs.make_inputs(w)
+    kb, dz = inp["kbottom"], inp["dz"]
+    m = oracle.OracleModel.from_inputs(w, inp)
+    wet, mu, mv = masks(w, kb)
+    dxc, dxv, dy, area = metrics(w)
+    c0 = _tracer_content(inp["T0"], w, kb, dz)
+    col = kb > 0
+    for _ in range(nsteps):
+        eta0 = m.get("eta")
+        m.step(1)
+        eta, U, V, u, v = (m.get(n) for n in ("eta", "U", "V", "u", "v"))
+        Um, Vm, em = m.get("U_mean"), m.get("V_mean"), m.get("eta_mean")
+        # volume: sum A eta and sum A eta_mean vanish to round-off
+        for e in (eta, em):
+            a = (area[:, None] * e)[col]
+            assert abs(math.fsum(a)) <= 1e-12 * np.abs(a).sum() + 1e-300
+        # eta^{n+1} - eta^n = -dt div(U_mean)
+        Vn = np.concatenate([Vm[1:], np.zeros_like(Vm[:1])], axis=0) if not w.periodic_y else np.roll(Vm, -1, 0)
+        Ue = np.roll(Um, -1, axis=1) if w.periodic_x else np.concatenate([Um[:, 1:], np.zeros_like(Um[:, :1])], 1)
+        div = (dy * (Ue - Um) + dxv[1:, None] * Vn - dxv[:-1, None] * Vm) / area[:, None]
+        resid = eta - eta0 + w.dt * div
+        assert np.max(np.abs(resid)) <= 1e-12 * max(np.max(np.abs(eta)), 1e-30)
+        # sum_k dz u = U after the correction
+        for f, mk, B in ((u, mu, U), (v, mv, V)):
+            s = (dz[:, None, None] * f * mk).sum(axis=0)
+            assert np.max(np.abs(s - B)) <= 1e-12 * max(np.max(np.abs(B)), 1e-30)
+    c1 = _tracer_content(m.get("T"), w, kb, dz)
+    assert abs(c1 - c0) <= 1e-12 * abs(c0)
+    assert m.diagnostics()["nonfinite"] == 0
+    assert np.max(np.abs(m.get("u"))) > 0
+
+
+def test_gravity_wave_frequency():
+    """Closed channel, flat 4 km, f = 0, T = 0: eta = 0.01 cos(pi x / L) is a
+    discrete eigenmode. Sampled once per baroclinic step, eta obeys
+    eta^{n+1} + eta^{n-1} = 2 cos(omega dt) eta^n with the forward-backward
+    frequency omega = (2/dtau) asin((c dtau/dx) sin(pi dx / (2L))), c = sqrt(gH)."""
+    w = inputs.BETA_BASIN_64.replace(ny=2, nz=2, f0=0.0, beta=0.0, tau0=0.0, noise_std=0.0,
+                                     strat_t0=0.0, kappa=0.0)
+    inp = inputs.make_inputs(w)
+    m = oracle.OracleModel.from_inputs(w, inp)
+    L = w.nx * w.dx
+    x = (np.arange(w.nx) + 0.5) * w.dx
+    m.set("eta", np.broadcast_to(0.01 * np.cos(math.pi * x / L), (w.ny, w.nx)).copy())
+    hist = [m.get("eta")]
+    for _ in range(100):
+        m.step(1)
+        hist.append(m.get("eta"))
+    e = np.array(hist)
+    num = np.sum((e[2:] + e[:-2]) * e[1:-1])
+    den = np.sum(2.0 * e[1:-1] ** 2)
+    omega = math.acos(num / den) / w.dt
+    c = math.sqrt(w.g * w.depth)
+    dtau = w.dt / w.n_substeps
+    expect = 2.0 / dtau * math.asin(c * dtau / w.dx * math.sin(math.pi * w.dx / (2 * L)))
+    assert abs(omega - expect) <= 1e-5 * expect
+    # and the continuous long-wave period 2L/c is within the discretisation error
+    assert abs(2 * math.pi / omega - 2 * L / c) / (2 * L / c) < 2e-4
+
+
+@pytest.mark.parametrize("chi", [0.0, 0.1])
+def test_inertial_oscillation_follows_ab2(chi):
+    """Uniform flow on a doubly periodic f-plane: z = u + i v obeys
+    z^{n+1} = z^n - i f dt [(3/2+chi) z^n - (1/2+chi) z^{n-1}], z^1 = (1 - i f dt) z^0."""
+    f, dt = 1e-4, 1200.0
+    w = inputs.Workload(name="inertial", nx=4, ny=4, nz=3, periodic_x=True, periodic_y=True,
+                        f0=f, beta=0.0, tau0=0.0, noise_std=0.0, dt=dt, chi=chi)
+    inp = inputs.make_inputs(w)
+    m = oracle.OracleModel.from_inputs(w, inp)
+    shape = (w.nz, w.ny, w.nx)
+    m.set("u", np.full(shape, 0.1))
+    m.set("U", np.full((w.ny, w.nx), 0.1 * w.depth))
+    zs = [0.1 + 0j]
+    for n in range(100):
+        Ub = m.get("U")
+        m.step(1)
+        # no surface slope: U^m grows linearly over the substeps, so the average of
+        # U^0..U^{Ns-1} sits (Ns-1)/(2Ns) of the way from U^n to U^{n+1}
+        frac = (w.n_substeps - 1) / (2.0 * w.n_substeps)
+        Um_expect = Ub + frac * (m.get("U") - Ub)
+        assert np.max(np.abs(m.get("U_mean") - Um_expect)) <= 1e-12 * np.max(np.abs(Ub))
+        u, v = m.get("u"), m.get("v")
+        assert np.ptp(u) <= 1e-13 and np.ptp(v) <= 1e-13  # uniform up to round-off
+        zs.append(complex(u[0, 0, 0], v[0, 0, 0]))
+    pred = [zs[0], (1 - 1j * f * dt) * zs[0]]
+    for n in range(1, 100):
+        pred.append(pred[n] - 1j * f * dt * ((1.5 + chi) * pred[n] - (0.5 + chi) * pred[n - 1]))
+    err = max(abs(a - b) for a, b in zip(zs, pred))
+    assert err <= 1e-12 * abs(zs[0])
+    # the growing root of the recurrence fixes frequency and amplitude drift
+    th = f * dt
+    roots = np.roots([1.0, -(1.0 - 1j * th * (1.5 + chi)), -1j * th * (0.5 + chi)])
+    lam = roots[np.argmax(np.abs(roots))]
+    assert abs(abs(zs[-1]) / abs(zs[-31]) - abs(lam) ** 30) < 1e-6
+    if chi == 0.0:
+        assert abs(-np.angle(lam) / th - 1.006054) < 2e-6
+        assert abs(abs(lam) - 1.0000534) < 2e-7
+
+
+def test_restart_is_bitwise():
+    w = small_latlon(nx=24, ny=14, nz=5)
+    inp = inputs.make_inputs(w)
+    a = oracle.OracleModel.from_inputs(w, inp)
+    a.step(3)
+    saved = {n: a.get(n) for n in ("u", "v", "T", "eta", "U", "V", "gu_prev", "gv_prev", "gt_prev")}
+    first = a.first_step
+    a.step(3)
+    b = oracle.OracleModel.from_inputs(w, inp)
+    for n, arr in saved.items():
+        b.set(n, arr)
+    b.first_step = first
+    b.step(3)
+    for n in ("u", "v", "T", "eta", "U", "V", "eta_mean", "U_mean", "V_mean"):
+        assert np.array_equal(a.get(n), b.get(n)), n
