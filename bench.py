@@ -1,0 +1,205 @@
+#!/usr/bin/env python
+"""Throughput of the split-explicit ocean step on one MI355X.
+
+Metric: cell-updates per second (all interior cells, land included, per step)
+and simulated years per day, at 1/12 degree (4320 x 1800 x 100, one GPU's
+share of the paper's 1/48-degree runs), FP32 bulk arithmetic (the reported
+value) and FP64 beside it, with the achieved fraction of the roofline of the
+dominant kernel and the CPU oracle timed on a bounded sample of the same
+workload.
+
+Inputs are synthetic and seeded (paper Sec. 6 forcing and bathymetry are not
+available): see paper_2309_06662_amd/inputs.py. Every input is resident in HBM
+before the timed region starts; the timed region is K whole steps (tendency +
+AB2, barotropic substeps, column solve + correction), bracketed by device
+synchronisation.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2309_06662_amd import inputs, metrics  # noqa: E402
+
+METRIC = "cell-updates/s & SYPD at 1/12° on 1 GPU, FP32 vs FP64; % of HBM roofline"
+
+# Published MI355X peaks.
+HBM_PEAK_GBS = 8000.0
+ALU_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+
+# Algorithmic work of the fused tendency + AB2 kernel per cell.
+# Bytes: read u, v, T, G^{n-1} x3 and write u*, v*, T*, G^n x3 = 12 words.
+TEND_WORDS_PER_CELL = 12
+# Flops: 9 WENO-Z face reconstructions (three per advected field: x, y, z)
+# at 74 operations each (17 candidate values, 18 differences, 15 smoothness
+# indicators, 1 tau, 6 ratios, 9 weights, 8 normalisation) = 666, plus 9 flux
+# products, 24 for three flux divergences, 18 Coriolis, 9 pressure and its
+# gradients, 21 transports and vertical transport, 14 reference-profile terms,
+# 12 AB2, 4 slow-forcing sums and 3 surface forcing = 780.
+TEND_FLOPS_PER_CELL = 780
+
+
+def _src_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic_from_profiles(workload, precision, esize):
+    """HBM bytes per launch of the tendency kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"k_tend_{workload}_{precision}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        if rec.get("source_sha256_16") != _src_hash(os.path.join(ROOT, "paper_2309_06662_amd", "csrc", "k_tend.hip")):
+            return None
+        return rec.get("hbm_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def run_gpu(w, precision, inp, steps, warmup):
+    import torch
+
+    from paper_2309_06662_amd import ocn
+
+    m = ocn.Model(w, precision, inp)
+    m.step(warmup)
+    m.synchronize()
+    m.stage_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.step(steps)
+    m.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages, n = m.stage_times()
+    m.stage_timing(False)
+    diag = m.diagnostics(allow_unstable=True)
+    m.close()
+    del m
+    torch.cuda.empty_cache()
+    return elapsed, {k: v / max(n, 1) for k, v in stages.items()}, diag
+
+
+def roofline(w, precision, stage_ms):
+    esize = 4 if precision == "fp32" else 8
+    t = stage_ms["tendency"] * 1e-3
+    cells = w.cells
+    gbs = TEND_WORDS_PER_CELL * esize * cells / t / 1e9
+    tfl = TEND_FLOPS_PER_CELL * cells / t / 1e12
+    hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    alu = {"bound": "alu", "achieved": round(tfl, 2), "peak": ALU_PEAK_TFLOPS[precision], "unit": "TFLOP/s",
+           "frac": round(tfl / ALU_PEAK_TFLOPS[precision], 4)}
+    main, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
+    main = dict(main, kernel="k_tend", traffic=_traffic_from_profiles(w.name, precision, esize))
+    return main, other
+
+
+def cpu_baseline(w, max_seconds=30.0):
+    """The oracle on a bounded window of the same 1/12-degree workload: a
+    240 x 120 column window (all 100 levels) of the same analytic basin,
+    stepped until about 10 s of work, single-threaded."""
+    import oracle
+
+    win = w.replace(name=w.name + "_window", nx=240, ny=120, periodic_x=False, x0=150.0, y0=-10.0)
+    inp = inputs.make_inputs(win)
+    m = oracle.OracleModel.from_inputs(win, inp)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        m.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > 10.0 or steps >= 20 or el > max_seconds:
+            break
+    rate = metrics.cell_updates_per_second(win.nx, win.ny, win.nz, steps, el)
+    return {"value": rate, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{win.nx}x{win.ny}x{win.nz} window of the 1/12-degree basin (lon 150-170E, 10S-0), "
+                      f"{steps} steps, {el:.1f} s, FP64, one thread",
+            "sypd_at_full_size": metrics.sypd(w.dt, w.cells / rate)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=inputs.LATLON_TWELFTH.name, choices=sorted(inputs.WORKLOADS))
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the decomposition it would use is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    w = inputs.WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    inp = inputs.make_inputs(w)
+    print(f"[bench] inputs for {w.name} generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    results = {}
+    for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
+        el, stages, diag = run_gpu(w, prec, inp, args.steps, args.warmup)
+        ms = el / args.steps * 1e3
+        results[prec] = {
+            "ms_per_step": ms,
+            "cell_updates_per_s": metrics.cell_updates_per_second(w.nx, w.ny, w.nz, args.steps, el),
+            "sypd": metrics.sypd(w.dt, ms * 1e-3),
+            "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+            "finite": diag["nonfinite"] == 0,
+        }
+        print(f"[bench] {prec}: {ms:.3f} ms/step, stages {results[prec]['stage_ms']}, "
+              f"finite={diag['nonfinite'] == 0}", file=sys.stderr, flush=True)
+
+    main_rec = results["fp32"]
+    roof, other = roofline(w, "fp32", main_rec["stage_ms"])
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w)
+        print(f"[bench] cpu baseline: {cpu['value']:.3e} cell-updates/s ({cpu['sample']})", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": METRIC,
+        "value": main_rec["cell_updates_per_s"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_rec["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic seeded basin (analytic seamount-and-ridge bathymetry, exponential stratification "
+                "with N(0, 0.01) noise, cos-latitude wind, restoring)",
+        "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "dt_s": w.dt, "n_substeps": w.n_substeps,
+                   "halo": w.halo, "precision": "FP32 bulk, FP64 barotropic substeps, averages and sums"},
+        "sypd": main_rec["sypd"],
+        "stage_ms": main_rec["stage_ms"],
+        "roofline": roof,
+        "roofline_other_view": other,
+        "cpu_baseline": cpu,
+    }
+    if "fp64" in results:
+        r64 = results["fp64"]
+        line["fp64"] = {"value": r64["cell_updates_per_s"], "ms_per_step": r64["ms_per_step"], "sypd": r64["sypd"],
+                        "stage_ms": r64["stage_ms"], "roofline": roofline(w, "fp64", r64["stage_ms"])[0]}
+        line["fp32_speedup_over_fp64"] = r64["ms_per_step"] / main_rec["ms_per_step"]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

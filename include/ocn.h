@@ -1,0 +1,194 @@
+/*
+ * ocn.h -- C ABI of the MI355X split-explicit hydrostatic ocean step.
+ *
+ * One explicit baroclinic step of the hydrostatic Boussinesq equations on a
+ * finite-volume Arakawa C-grid (WENO advection of tracers and momentum,
+ * Coriolis, hydrostatic pressure gradient of a linear equation of state, AB2
+ * update, backward-Euler vertical diffusion by a tridiagonal solve per column),
+ * followed by the sub-cycled split-explicit barotropic free-surface loop
+ * (paper Sec. 5.2 "New numerical methods" and Sec. 5.3 "Optimization of ocean
+ * free surface dynamics"). The user sets up a grid (resolution, extent, levels,
+ * bathymetry), an initial state and forcing, advances n steps of size dt and
+ * reads the state and diagnostics (the problem as stated in paper Sec. 6).
+ *
+ * Memory and streams. The library never allocates device memory: the caller
+ * passes one device arena (for example a torch uint8 tensor on the GPU) whose
+ * size ocn_state_arena_bytes reports, and a HIP stream. Every kernel and copy
+ * of a state runs on that stream. Host buffers passed to get/set calls belong
+ * to the caller and are used only during the call.
+ *
+ * Errors. Every call returns an ocn_status; no C++ exception crosses the ABI.
+ * Invalid arguments return OCN_E_INVALID with no side effect and a message in
+ * ocn_last_error(). HIP failures return OCN_E_DEVICE with the HIP error text.
+ * ocn_step is asynchronous: a device fault surfaces at the next synchronising
+ * call. Handles are not thread-safe; distinct handles are independent.
+ *
+ * Layout on the host. 3D fields are double [k][j][i] with k = 0 the bottom
+ * layer, nz*ny*nx values; 2D fields are double [j][i], ny*nx values. u lives on
+ * west faces x_{i-1/2}, v on south faces y_{j-1/2}, T at cell centres; the
+ * barotropic U, V are depth-integrated velocities (m^2/s) on the same faces.
+ */
+#ifndef OCN_H
+#define OCN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OCN_ABI_VERSION 1u
+
+typedef enum {
+    OCN_OK = 0,
+    OCN_E_INVALID = -1,     /* bad argument; nothing changed                       */
+    OCN_E_NOMEM = -2,       /* arena too small or host allocation failed           */
+    OCN_E_DEVICE = -3,      /* a HIP call failed                                   */
+    OCN_E_UNSTABLE = -4,    /* diagnostics found non-finite values                 */
+    OCN_E_STATE = -5,       /* call not allowed in the current state               */
+    OCN_E_UNSUPPORTED = -6  /* valid request this build does not implement         */
+} ocn_status;
+
+/* Arithmetic of the 3D path. OCN_FP32: tendencies, AB2 and the column solve in
+ * FP32 with temperature stored as an anomaly from a per-level FP64 reference
+ * profile; the barotropic state, its substeps and averages, the depth sums of
+ * the slow forcing and of the correction, and all diagnostics sums stay FP64.
+ * (Paper Sec. 2: both 64- and 32-bit runs are measured.) */
+typedef enum { OCN_FP64 = 0, OCN_FP32 = 1 } ocn_precision;
+typedef enum { OCN_CARTESIAN = 0, OCN_LATLON = 1 } ocn_coords;
+
+typedef struct ocn_grid_desc {
+    int32_t nx, ny, nz;       /* interior cells, >= 1 each                          */
+    int32_t halo;             /* halo width of the padded layout, 3..8              */
+    int32_t periodic_x;       /* 1 periodic, 0 walls                                */
+    int32_t periodic_y;       /* 1 periodic (Cartesian only), 0 walls               */
+    int32_t coords;           /* ocn_coords                                         */
+    int32_t reserved;         /* must be 0                                          */
+    double x0, y0, dx, dy;    /* Cartesian: m (x0, y0 unused). lat-lon: degrees:
+                                 west edge, south edge, dlon, dlat                  */
+    double f0, beta;          /* beta-plane Coriolis f = f0 + beta (y - Ly/2)       */
+    double radius, omega;     /* sphere radius (m), rotation rate (1/s)             */
+    const double* dz;         /* nz layer thicknesses (m), bottom to top; required  */
+    const int32_t* kbottom;   /* ny*nx wet layers per column counted from the surface
+                                 (0 = land); NULL = every column full depth         */
+} ocn_grid_desc;
+
+typedef struct ocn_params {
+    int32_t precision;        /* ocn_precision                                      */
+    int32_t n_substeps;       /* barotropic substeps per step, >= 1                 */
+    int32_t reserved0, reserved1;
+    double dt;                /* baroclinic step (s)                                */
+    double chi;               /* AB2 offset: G = (3/2+chi) G^n - (1/2+chi) G^{n-1}  */
+    double g;                 /* gravity (m/s^2)                                    */
+    double alpha;             /* thermal expansion (1/K): b = g alpha (T - t_ref)   */
+    double rho0;              /* reference density (kg/m^3)                         */
+    double t_ref;             /* equation-of-state reference temperature (degC)     */
+    double kappa;             /* vertical diffusivity = viscosity (m^2/s)           */
+    double restore_tau;       /* surface restoring time (s); <= 0 disables          */
+} ocn_params;
+
+/* Field identifiers. */
+typedef enum {
+    OCN_FIELD_U = 0,          /* 3D zonal velocity (m/s)                            */
+    OCN_FIELD_V = 1,          /* 3D meridional velocity (m/s)                       */
+    OCN_FIELD_T = 2,          /* 3D temperature (degC)                              */
+    OCN_FIELD_ETA = 3,        /* 2D free surface (m)                                */
+    OCN_FIELD_UBT = 4,        /* 2D barotropic transport U (m^2/s)                  */
+    OCN_FIELD_VBT = 5,        /* 2D barotropic transport V (m^2/s)                  */
+    OCN_FIELD_ETA_MEAN = 6,   /* 2D substep average of eta over the last step       */
+    OCN_FIELD_UBT_MEAN = 7,   /* 2D substep average of U over the last step         */
+    OCN_FIELD_VBT_MEAN = 8,   /* 2D substep average of V over the last step         */
+    OCN_FIELD_W = 9,          /* (nz+1)*ny*nx vertical velocity on z-faces, get only */
+    OCN_FIELD_GU_PREV = 10,   /* 3D AB2 history of u                                */
+    OCN_FIELD_GV_PREV = 11,   /* 3D AB2 history of v                                */
+    OCN_FIELD_GT_PREV = 12,   /* 3D AB2 history of T                                */
+    OCN_FIELD_TAUX = 13,      /* 2D zonal wind stress at u-points (N/m^2)           */
+    OCN_FIELD_TAUY = 14,      /* 2D meridional wind stress at v-points (N/m^2)      */
+    OCN_FIELD_TSTAR = 15,     /* 2D surface restoring temperature (degC)            */
+    OCN_FIELD_TREF = 16       /* nz reference profile of the stored T anomaly        */
+} ocn_field;
+
+typedef struct ocn_diag {
+    int64_t step;             /* steps taken                                        */
+    double time;              /* model time (s)                                     */
+    double tracer_content;    /* sum V_c T over wet cells (degC m^3)                */
+    double volume;            /* sum A_c eta over wet columns (m^3)                 */
+    double volume_mean;       /* sum A_c eta_mean over wet columns (m^3)            */
+    double kinetic_energy;    /* 1/2 sum (V_u u^2 + V_v v^2) (m^5/s^2)              */
+    double max_abs_u, max_abs_v, max_abs_w;
+    double t_min, t_max;      /* over wet cells                                     */
+    double eta_min, eta_max;  /* over wet columns                                   */
+    double cfl_adv;           /* max(|u| dt/dx, |v| dt/dy, |w| dt/dz)               */
+    double wet_area;          /* sum A_c over wet columns (m^2)                     */
+    int64_t nonfinite;        /* non-finite values among u, v, T, eta, U, V         */
+} ocn_diag;
+
+typedef struct ocn_grid ocn_grid;
+typedef struct ocn_state ocn_state;
+
+/* Version of this ABI (OCN_ABI_VERSION). */
+uint32_t ocn_abi_version(void);
+
+/* Text of the last error on the calling thread; valid until its next call. */
+const char* ocn_last_error(void);
+
+/* Build the grid: copies desc, dz and kbottom (the caller may free them after
+ * the call) and derives metrics and masks on the host. Finite-volume C-grid of
+ * paper Sec. 5.2 on a Cartesian beta-plane or a lat-lon sphere (Sec. 6). */
+int  ocn_grid_create(const ocn_grid_desc* desc, ocn_grid** out);
+void ocn_grid_destroy(ocn_grid* grid);
+
+/* Device bytes one state of this grid and precision needs. */
+int ocn_state_arena_bytes(const ocn_grid* grid, const ocn_params* params, size_t* bytes);
+
+/* Create a state at rest (u = v = T = eta = U = V = 0, no forcing) inside the
+ * caller's device arena (256-byte aligned, at least ocn_state_arena_bytes bytes)
+ * on the caller's HIP stream (hipStream_t, NULL for the default stream). The
+ * grid must outlive the state. The arena is written only by this library until
+ * ocn_state_destroy. */
+int  ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_arena,
+                    size_t arena_bytes, void* hip_stream, ocn_state** out);
+void ocn_state_destroy(ocn_state* state);
+
+/* Copy a host field in (set) or out (get); count must equal the field's size.
+ * Set stores u and v with dry points zeroed. Setting TREF is allowed only
+ * before T is first set; otherwise the first set of T takes as reference the
+ * mean of that T over the wet cells of each level. Both calls synchronise the
+ * stream. */
+int ocn_set_field(ocn_state* state, int32_t field, const double* host, size_t count);
+int ocn_get_field(ocn_state* state, int32_t field, double* host, size_t count);
+
+/* AB2 start flag: 1 makes the next step forward Euler (paper Sec. 5.2 AB2). */
+int ocn_set_first_step(ocn_state* state, int32_t first);
+int ocn_get_first_step(ocn_state* state, int32_t* first);
+
+/* Enqueue n >= 0 steps on the state's stream; returns without waiting. Each
+ * step: fused tendency + AB2 kernel (w and hydrostatic pressure integrated in
+ * the vertical march, slow barotropic forcing summed in FP64), the barotropic
+ * substeps (FP64, forward-backward), then the column kernel (backward-Euler
+ * vertical diffusion of T, u, v and the depth-mean correction of u, v). */
+int ocn_step(ocn_state* state, int32_t n);
+
+/* Reduce diagnostics on the device (compensated FP64 sums in a fixed order),
+ * synchronise and copy them out. Returns OCN_E_UNSTABLE (with *out filled)
+ * when any prognostic value is non-finite. */
+int ocn_diagnostics(ocn_state* state, ocn_diag* out);
+
+/* Wait for all work enqueued on the state's stream. */
+int ocn_synchronize(ocn_state* state);
+
+/* Per-stage timing with HIP events recorded on the state's stream. While
+ * enabled (enable = 1), every ocn_step records an event before the tendency
+ * kernel, after it, after the barotropic substeps and after the column kernel.
+ * ocn_stage_times synchronises the stream, writes up to n accumulated stage
+ * times in milliseconds (0 tendency, 1 barotropic substeps, 2 column solve and
+ * correction) and the number of timed steps, then clears the accumulators.
+ * Enabling or disabling also clears them. */
+int ocn_stage_timing(ocn_state* state, int32_t enable);
+int ocn_stage_times(ocn_state* state, double* ms, int32_t n, int64_t* steps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

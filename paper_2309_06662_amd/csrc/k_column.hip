@@ -1,0 +1,186 @@
+// k_column.hip -- implicit vertical diffusion and the depth-mean correction.
+//
+// Backward-Euler vertical diffusion (paper Sec. 5.2: vertically implicit
+// diffusion with a tridiagonal solver) of T, u and v, one thread per column,
+// one wave per 64 adjacent columns so that every level of a field is read and
+// written as coalesced row segments. Elimination runs bottom to top with the
+// eliminated right-hand side kept in LDS; back-substitution runs top to bottom.
+//
+// With a constant diffusivity the matrix of a column depends only on its number
+// of wet layers K (the wet layers of T, u and v columns all start at the
+// surface), so the eliminated super-diagonal c' and the pivots come from a
+// table indexed by K built once on the host. The temperature anomaly solve
+// carries the diffusion of the reference profile on its right-hand side.
+//
+// For u and v the same kernel then applies the split-explicit correction
+// (paper Sec. 5.3): the depth mean of u** is replaced by U^{Ns}/H, using the
+// barotropic transport at the end of the substeps, and it leaves the column
+// sum sum_k dz u m_u of the stored result, which seeds the vertical transport
+// of the next step. Columns next to a periodic boundary also write their
+// wrapped copies into the halo.
+#include "ocn_dev.h"
+
+namespace ocn {
+
+constexpr int CW = 64;       // columns per workgroup
+
+template <typename R>
+__device__ __forceinline__ void store_wrapped(const DevState& S, R* f, int i, int j, int k, R val) {
+    for_each_image(S, i, j, S.h, [&](int x, int y) { f[idx3(S, x, y, k)] = val; });
+}
+
+__device__ __forceinline__ void store_wrapped2(const DevState& S, double* f, int i, int j, double val) {
+    f[idx2(S, i, j)] = val;
+    for_each_image(S, i, j, S.h, [&](int x, int y) { f[idx2(S, x, y)] = val; });
+}
+
+// blockIdx.z: 0 = T, 1 = u, 2 = v
+template <typename R>
+__global__ __launch_bounds__(CW) void k_column(const DevState S) {
+    extern __shared__ __align__(16) unsigned char smem_col[];
+    R* sd = reinterpret_cast<R*>(smem_col);  // nz * CW eliminated right-hand sides
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * CW + t, j = blockIdx.y;
+    const int field = blockIdx.z;
+    if (i >= S.nx) return;
+    const int nz = S.nz;
+
+    const int kc = S.kb[idxk(S, i, j)];
+    int K = kc;
+    if (field == 1) K = min(kc, S.kb[idxk(S, i - 1, j)]);
+    if (field == 2) K = min(kc, S.kb[idxk(S, i, j - 1)]);
+
+    const R* src = f3<R>(field == 0 ? S.ts : field == 1 ? S.us : S.vs);
+    R* dst = f3<R>(field == 0 ? S.t : field == 1 ? S.u : S.v);
+    const R* cp = static_cast<const R*>(S.thomas_cp) + (long long)K * nz;
+    const R* den = static_cast<const R*>(S.thomas_den) + (long long)K * nz;
+    const R* asub = static_cast<const R*>(S.thomas_a);
+    const int kbot = nz - K;  // lowest wet layer
+
+    // Temperature is stored as T' = T - tref(k): diffusing T means diffusing T'
+    // with the diffusion of the fixed profile added to the right-hand side,
+    // dt dz L(tref) = -c_k (tref_{k+1} - tref_k) + a_k (tref_k - tref_{k-1}).
+    const R* dtr = static_cast<const R*>(S.dtr);
+    // elimination, bottom to top: d'_k = (dz_k phi*_k - a_k d'_{k-1}) / den_k
+    R dprev = R(0);
+    for (int k = 0; k < nz; ++k) {
+        R rhs = R(S.dz[k]) * src[idx3(S, i, j, k)];
+        // a_k couples to k-1 across face k, wet when k-1 and k are both wet layers
+        const R a = (k > kbot) ? asub[k] : R(0);
+        if (field == 0) {
+            const R c = (k >= kbot && k < nz - 1) ? asub[k + 1] : R(0);
+            rhs += -c * dtr[k * 4 + 2] - a * dtr[k * 4 + 1];
+        }
+        const R dk = (rhs - a * dprev) / den[k];
+        sd[k * CW + t] = dk;
+        dprev = dk;
+    }
+    // back-substitution, top to bottom: x_k = d'_k - c'_k x_{k+1}
+    R xnext = R(0);
+    double colsum = 0.0;
+    for (int k = nz - 1; k >= 0; --k) {
+        const R x = sd[k * CW + t] - cp[k] * xnext;
+        xnext = x;
+        if (field == 0) {
+            const long long o = idx3(S, i, j, k);
+            dst[o] = x;
+            store_wrapped(S, dst, i, j, k, x);
+        } else {
+            sd[k * CW + t] = x;
+            if (k >= kbot) colsum += double(S.dz[k]) * double(x);
+        }
+    }
+    if (field == 0) return;
+
+    // depth-mean correction: u = u** + (U^{Ns} - sum dz u**) / H on wet layers
+    const double H = (field == 1) ? S.hu[idx2(S, i, j)] : S.hv[idx2(S, i, j)];
+    const double B = (field == 1) ? S.ubt[idx2(S, i, j)] : S.vbt[idx2(S, i, j)];
+    const double corr = (H > 0.0) ? (B - colsum) / H : 0.0;
+    double newsum = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        R val = R(0);
+        if (k >= kbot && H > 0.0) {
+            val = R(double(sd[k * CW + t]) + corr);
+            newsum += double(S.dz[k]) * double(val);
+        }
+        const long long o = idx3(S, i, j, k);
+        dst[o] = val;
+        store_wrapped(S, dst, i, j, k, val);
+    }
+    store_wrapped2(S, field == 1 ? S.cu : S.cv, i, j, newsum);
+}
+
+// Column sums sum_k dz u m_u and sum_k dz v m_v of the stored velocities (used
+// after u or v is set from the host).
+template <typename R>
+__global__ __launch_bounds__(CW) void k_colsum(const DevState S) {
+    const int i = blockIdx.x * CW + threadIdx.x, j = blockIdx.y, field = blockIdx.z;
+    if (i >= S.nx) return;
+    const int kc = S.kb[idxk(S, i, j)];
+    const int K = (field == 0) ? min(kc, S.kb[idxk(S, i - 1, j)]) : min(kc, S.kb[idxk(S, i, j - 1)]);
+    const R* f = f3<R>(field == 0 ? S.u : S.v);
+    double s = 0.0;
+    for (int k = S.nz - K; k < S.nz; ++k) s += double(S.dz[k]) * double(f[idx3(S, i, j, k)]);
+    store_wrapped2(S, field == 0 ? S.cu : S.cv, i, j, s);
+}
+
+// Vertical velocity on every z-face from continuity, integrated upward from the
+// bottom (a diagnostic output; faces 0..nz-1 into ts, the surface face into scratch2d).
+template <typename R>
+__global__ __launch_bounds__(CW) void k_wfaces(const DevState S) {
+    const int i = blockIdx.x * CW + threadIdx.x, j = blockIdx.y;
+    if (i >= S.nx) return;
+    const int nz = S.nz;
+    const int* kb = S.kb;
+    const int K0 = kb[idxk(S, i, j)];
+    const int Ku0 = min(kb[idxk(S, i - 1, j)], K0), Ku1 = min(K0, kb[idxk(S, i + 1, j)]);
+    const int Kv0 = min(kb[idxk(S, i, j - 1)], K0), Kv1 = min(K0, kb[idxk(S, i, j + 1)]);
+    const R* u = f3<R>(S.u);
+    const R* v = f3<R>(S.v);
+    R* out = f3<R>(S.ts);
+    const double area = S.area[j];
+    double W = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        out[idx3(S, i, j, k)] = R(W / area);
+        const int kw = nz - k;
+        const double dz = S.dz[k];
+        const double ue = (Ku1 >= kw) ? double(u[idx3(S, i + 1, j, k)]) * S.dy * dz : 0.0;
+        const double uw = (Ku0 >= kw) ? double(u[idx3(S, i, j, k)]) * S.dy * dz : 0.0;
+        const double vn = (Kv1 >= kw) ? double(v[idx3(S, i, j + 1, k)]) * S.dxv[j + 1] * dz : 0.0;
+        const double vs = (Kv0 >= kw) ? double(v[idx3(S, i, j, k)]) * S.dxv[j] * dz : 0.0;
+        W = W - (ue - uw + vn - vs);
+    }
+    S.scratch2d[idx2(S, i, j)] = W / area;
+}
+
+template <typename R>
+hipError_t launch_column(const DevState& s, hipStream_t st) {
+    const size_t lds = (size_t)s.nz * CW * sizeof(R);
+    if (lds > 64 * 1024) return hipErrorInvalidValue;  // per-workgroup LDS limit
+    dim3 grid((s.nx + CW - 1) / CW, s.ny, 3);
+    hipLaunchKernelGGL(k_column<R>, grid, dim3(CW), lds, st, s);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_colsum(const DevState& s, hipStream_t st) {
+    dim3 grid((s.nx + CW - 1) / CW, s.ny, 2);
+    hipLaunchKernelGGL(k_colsum<R>, grid, dim3(CW), 0, st, s);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_w_faces(const DevState& s, double* /*unused*/, hipStream_t st) {
+    dim3 grid((s.nx + CW - 1) / CW, s.ny, 1);
+    hipLaunchKernelGGL(k_wfaces<R>, grid, dim3(CW), 0, st, s);
+    return hipGetLastError();
+}
+
+template hipError_t launch_column<double>(const DevState&, hipStream_t);
+template hipError_t launch_column<float>(const DevState&, hipStream_t);
+template hipError_t launch_colsum<double>(const DevState&, hipStream_t);
+template hipError_t launch_colsum<float>(const DevState&, hipStream_t);
+template hipError_t launch_w_faces<double>(const DevState&, double*, hipStream_t);
+template hipError_t launch_w_faces<float>(const DevState&, double*, hipStream_t);
+
+}  // namespace ocn

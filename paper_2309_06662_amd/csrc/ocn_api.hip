@@ -1,0 +1,774 @@
+// ocn_api.hip -- host runtime behind the C ABI declared in include/ocn.h.
+//
+// Builds the grid metrics and masks on the host, lays the state out in the
+// caller's device arena, moves fields between host doubles and the padded
+// device layout, and enqueues the kernels of a step on the caller's stream.
+#include "../../include/ocn.h"
+#include "ocn_dev.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using ocn::DevState;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(OCN_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+constexpr double kPi = 3.14159265358979323846;
+
+}  // namespace
+
+struct ocn_grid {
+    ocn_grid_desc d;
+    int nx, ny, nz, h;
+    std::vector<double> dz, dzc;
+    std::vector<int32_t> kb;              // ny * nx interior
+    // row metrics for j = -h .. ny + h (index j + h)
+    std::vector<double> dxc, dxv, area, fcor, metric;
+    double dy;
+    int row(int j) const { return j + h; }
+};
+
+struct ocn_state {
+    const ocn_grid* g = nullptr;
+    ocn_params p{};
+    DevState d{};
+    hipStream_t st = nullptr;
+    void* arena = nullptr;
+    size_t bytes = 0;
+    int esize = 8;          // bytes per element of the 3D field type
+    int first = 1;
+    int64_t step = 0;
+    double time = 0.0;
+    bool t_set = false;
+    std::vector<double> tref;   // nz
+    std::vector<double> tstar;  // ny * nx, absolute
+    // stage timing (events recorded on the state's stream)
+    bool timing = false;
+    std::vector<hipEvent_t> events;  // 4 per timed step
+    int64_t timed_steps = 0;
+    // host-side layout facts
+    size_t ox3 = 0, ox2 = 0, oxk = 0;
+    size_t n3 = 0, n2 = 0, nk = 0;  // padded element counts
+};
+
+namespace {
+
+int record(ocn_state* s) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    s->events.push_back(e);
+    HIPCHK(hipEventRecord(e, s->st));
+    return OCN_OK;
+}
+
+void drop_events(ocn_state* s) {
+    for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+    s->events.clear();
+    s->timed_steps = 0;
+}
+
+}  // namespace
+
+namespace {
+
+// Wrap an index into the interior for periodic directions; -1 outside a wall.
+int wrap(int i, int n, bool periodic) {
+    if (i >= 0 && i < n) return i;
+    if (!periodic) return -1;
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+struct Layout {
+    size_t total = 0;
+    size_t add(size_t bytes) {
+        size_t off = round_up(total, 256);
+        total = off + round_up(bytes, 256);
+        return off;
+    }
+};
+
+// Offsets of every array of a state in the arena (same order as assign()).
+struct Plan {
+    size_t esize, a3, ox3, p3, rows, n3;
+    size_t ox2, p2, n2;
+    size_t oxk, pk, nk;
+    size_t nrow;  // metric rows
+    size_t diag_blocks;
+    size_t off_f3[9], off_f2[20], off_kb, off_rows[5], off_dz, off_dzc, off_tref, off_dtr, off_cp, off_den, off_a;
+    size_t off_part, off_out;
+    size_t total;
+};
+
+Plan make_plan(const ocn_grid* g, int precision) {
+    Plan P{};
+    P.esize = precision == OCN_FP32 ? 4 : 8;
+    const size_t h = g->h;
+    P.rows = g->ny + 2 * h;
+    const size_t a3 = 128 / P.esize;
+    P.ox3 = round_up(h, a3);
+    P.p3 = round_up(P.ox3 + g->nx + h, a3);
+    P.n3 = P.p3 * P.rows * g->nz;
+    P.ox2 = round_up(h, 16);
+    P.p2 = round_up(P.ox2 + g->nx + h, 16);
+    P.n2 = P.p2 * P.rows;
+    P.oxk = round_up(h, 32);
+    P.pk = round_up(P.oxk + g->nx + h, 32);
+    P.nk = P.pk * P.rows;
+    P.nrow = g->ny + 2 * h + 1;
+    P.diag_blocks = ((g->nx + 63) / 64) * ((g->ny + 3) / 4);
+    Layout L;
+    for (auto& o : P.off_f3) o = L.add(P.n3 * P.esize);
+    for (auto& o : P.off_f2) o = L.add(P.n2 * sizeof(double));
+    P.off_kb = L.add(P.nk * sizeof(int32_t));
+    for (auto& o : P.off_rows) o = L.add(P.nrow * sizeof(double));
+    P.off_dz = L.add(g->nz * sizeof(double));
+    P.off_dzc = L.add((g->nz + 1) * sizeof(double));
+    P.off_tref = L.add(g->nz * sizeof(double));
+    P.off_dtr = L.add(g->nz * 4 * P.esize);
+    P.off_cp = L.add((size_t)(g->nz + 1) * g->nz * P.esize);
+    P.off_den = L.add((size_t)(g->nz + 1) * g->nz * P.esize);
+    P.off_a = L.add(g->nz * P.esize);
+    P.off_part = L.add(P.diag_blocks * ocn::DG_COUNT * sizeof(double));
+    P.off_out = L.add(ocn::DG_COUNT * sizeof(double));
+    P.total = L.total;
+    return P;
+}
+
+bool valid_params(const ocn_params* p, std::string& why) {
+    if (!p) { why = "params is NULL"; return false; }
+    if (p->precision != OCN_FP64 && p->precision != OCN_FP32) { why = "precision must be OCN_FP64 or OCN_FP32"; return false; }
+    if (p->n_substeps < 1) { why = "n_substeps must be >= 1"; return false; }
+    if (!(p->dt > 0.0) || !std::isfinite(p->dt)) { why = "dt must be positive"; return false; }
+    if (!(p->kappa >= 0.0)) { why = "kappa must be >= 0"; return false; }
+    if (!(p->rho0 > 0.0)) { why = "rho0 must be positive"; return false; }
+    return true;
+}
+
+// Fill a padded host image of a 3D field from interior doubles (periodic halo
+// copies, zero beyond walls).
+template <typename R>
+void pack3(const ocn_state* s, const double* src, const double* sub_per_level, std::vector<R>& out) {
+    const ocn_grid* g = s->g;
+    const int nx = g->nx, ny = g->ny, nz = g->nz, h = g->h;
+    const size_t p3 = s->d.p3, rows = ny + 2 * h;
+    out.assign(s->n3, R(0));
+    for (int k = 0; k < nz; ++k)
+        for (int jj = -h; jj < ny + h; ++jj) {
+            const int j = wrap(jj, ny, g->d.periodic_y);
+            if (j < 0) continue;
+            R* dst = out.data() + ((size_t)k * rows + (jj + h)) * p3 + s->ox3;
+            const double* row = src + ((size_t)k * ny + j) * nx;
+            const double sub = sub_per_level ? sub_per_level[k] : 0.0;
+            for (int ii = -h; ii < nx + h; ++ii) {
+                const int i = wrap(ii, nx, g->d.periodic_x);
+                if (i < 0) continue;
+                dst[ii] = R(row[i] - sub);
+            }
+        }
+}
+
+template <typename R>
+void unpack3(const ocn_state* s, const std::vector<R>& img, const double* add_per_level, double* dst, int nlev) {
+    const ocn_grid* g = s->g;
+    const int nx = g->nx, ny = g->ny, h = g->h;
+    const size_t p3 = s->d.p3, rows = ny + 2 * h;
+    for (int k = 0; k < nlev; ++k)
+        for (int j = 0; j < ny; ++j) {
+            const R* row = img.data() + ((size_t)k * rows + (j + h)) * p3 + s->ox3;
+            const double add = add_per_level ? add_per_level[k] : 0.0;
+            for (int i = 0; i < nx; ++i) dst[((size_t)k * ny + j) * nx + i] = double(row[i]) + add;
+        }
+}
+
+void pack2(const ocn_state* s, const double* src, std::vector<double>& out) {
+    const ocn_grid* g = s->g;
+    const int nx = g->nx, ny = g->ny, h = g->h;
+    const size_t p2 = s->d.p2;
+    out.assign(s->n2, 0.0);
+    for (int jj = -h; jj < ny + h; ++jj) {
+        const int j = wrap(jj, ny, g->d.periodic_y);
+        if (j < 0) continue;
+        for (int ii = -h; ii < nx + h; ++ii) {
+            const int i = wrap(ii, nx, g->d.periodic_x);
+            if (i < 0) continue;
+            out[(size_t)(jj + h) * p2 + s->ox2 + ii] = src[(size_t)j * nx + i];
+        }
+    }
+}
+
+void unpack2(const ocn_state* s, const std::vector<double>& img, double* dst) {
+    const ocn_grid* g = s->g;
+    const int nx = g->nx, ny = g->ny, h = g->h;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) dst[(size_t)j * nx + i] = img[(size_t)(j + h) * s->d.p2 + s->ox2 + i];
+}
+
+// Device base address (padded origin) of a 3D or 2D array from its interior pointer.
+void* base3(const ocn_state* s, void* interior) {
+    return static_cast<unsigned char*>(interior) - ((size_t)s->g->h * s->d.p3 + s->ox3) * s->esize;
+}
+double* base2(const ocn_state* s, double* interior) { return interior - ((size_t)s->g->h * s->d.p2 + s->ox2); }
+
+int kb_at(const ocn_grid* g, int i, int j) {
+    const int ii = wrap(i, g->nx, g->d.periodic_x), jj = wrap(j, g->ny, g->d.periodic_y);
+    if (ii < 0 || jj < 0) return 0;
+    return g->kb[(size_t)jj * g->nx + ii];
+}
+
+template <typename R>
+int upload_tables(ocn_state* s) {
+    const ocn_grid* g = s->g;
+    const int nz = g->nz;
+    // reference-profile steps
+    std::vector<R> dtr(nz * 4, R(0));
+    const int offs[4] = {-2, -1, 1, 2};
+    for (int k = 0; k < nz; ++k)
+        for (int q = 0; q < 4; ++q) {
+            const int l = k + offs[q];
+            dtr[k * 4 + q] = (l >= 0 && l < nz) ? R(s->tref[l] - s->tref[k]) : R(0);
+        }
+    HIPCHK(hipMemcpyAsync(s->d.dtr, dtr.data(), dtr.size() * sizeof(R), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(s->d.tref, s->tref.data(), nz * sizeof(double), hipMemcpyHostToDevice, s->st));
+    // restoring target as an anomaly of the top layer
+    std::vector<double> ts(s->tstar.size());
+    for (size_t c = 0; c < ts.size(); ++c) ts[c] = s->tstar[c] - s->tref[nz - 1];
+    std::vector<double> img;
+    pack2(s, ts.data(), img);
+    HIPCHK(hipMemcpyAsync(base2(s, s->d.tstar), img.data(), img.size() * sizeof(double), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return OCN_OK;
+}
+
+template <typename R>
+int init_static(ocn_state* s) {
+    const ocn_grid* g = s->g;
+    const int nx = g->nx, ny = g->ny, nz = g->nz, h = g->h;
+    DevState& d = s->d;
+    // wet-layer counts with halo
+    std::vector<int32_t> kbimg((size_t)d.pk * (ny + 2 * h), 0);
+    for (int j = -h; j < ny + h; ++j)
+        for (int i = -h; i < nx + h; ++i) kbimg[(size_t)(j + h) * d.pk + s->oxk + i] = kb_at(g, i, j);
+    HIPCHK(hipMemcpyAsync(d.kb - ((size_t)h * d.pk + s->oxk), kbimg.data(), kbimg.size() * 4, hipMemcpyHostToDevice, s->st));
+    // row metrics
+    const size_t nr = ny + 2 * h + 1;
+    double* rows[5] = {d.dxc, d.dxv, d.area, d.fcor, d.metric};
+    const std::vector<double>* src[5] = {&g->dxc, &g->dxv, &g->area, &g->fcor, &g->metric};
+    for (int q = 0; q < 5; ++q)
+        HIPCHK(hipMemcpyAsync(rows[q] - h, src[q]->data(), nr * sizeof(double), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(d.dz, g->dz.data(), nz * sizeof(double), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(d.dzc, g->dzc.data(), (nz + 1) * sizeof(double), hipMemcpyHostToDevice, s->st));
+    // column depths of u and v points (sum of wet layer thicknesses, bottom to top)
+    std::vector<double> hu((size_t)nx * ny), hv((size_t)nx * ny);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const int Ku = std::min(kb_at(g, i, j), kb_at(g, i - 1, j));
+            const int Kv = std::min(kb_at(g, i, j), kb_at(g, i, j - 1));
+            double a = 0.0, b = 0.0;
+            for (int k = 0; k < nz; ++k) {
+                if (k >= nz - Ku) a += g->dz[k];
+                if (k >= nz - Kv) b += g->dz[k];
+            }
+            hu[(size_t)j * nx + i] = a;
+            hv[(size_t)j * nx + i] = b;
+        }
+    std::vector<double> img;
+    pack2(s, hu.data(), img);
+    HIPCHK(hipMemcpyAsync(base2(s, d.hu), img.data(), img.size() * sizeof(double), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    pack2(s, hv.data(), img);
+    HIPCHK(hipMemcpyAsync(base2(s, d.hv), img.data(), img.size() * sizeof(double), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    // Thomas tables for constant diffusivity, one per wet-layer count K
+    const double dt = s->p.dt, kap = s->p.kappa;
+    std::vector<R> cp((size_t)(nz + 1) * nz), den((size_t)(nz + 1) * nz), asub(nz, R(0));
+    for (int k = 1; k < nz; ++k) asub[k] = R(-dt * kap / g->dzc[k]);
+    for (int K = 0; K <= nz; ++K) {
+        const int kbot = nz - K;
+        double cprev = 0.0;
+        for (int k = 0; k < nz; ++k) {
+            const double a = (k > kbot) ? -dt * kap / g->dzc[k] : 0.0;
+            const double c = (k >= kbot && k < nz - 1) ? -dt * kap / g->dzc[k + 1] : 0.0;
+            const double b = g->dz[k] - a - c;
+            const double dn = b - a * cprev;
+            const double cpk = c / dn;
+            cp[(size_t)K * nz + k] = R(cpk);
+            den[(size_t)K * nz + k] = R(dn);
+            cprev = cpk;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(d.thomas_cp, cp.data(), cp.size() * sizeof(R), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(d.thomas_den, den.data(), den.size() * sizeof(R), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(d.thomas_a, asub.data(), asub.size() * sizeof(R), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return upload_tables<R>(s);
+}
+
+template <typename R>
+int set3(ocn_state* s, void* interior, const double* host, const double* sub, int mask_kind) {
+    const ocn_grid* g = s->g;
+    const int nx = g->nx, ny = g->ny, nz = g->nz;
+    std::vector<double> tmp;
+    const double* src = host;
+    if (mask_kind) {  // zero dry velocity points
+        tmp.assign(host, host + (size_t)nx * ny * nz);
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int K = mask_kind == 1 ? std::min(kb_at(g, i, j), kb_at(g, i - 1, j))
+                                             : std::min(kb_at(g, i, j), kb_at(g, i, j - 1));
+                for (int k = 0; k < nz - K; ++k) tmp[((size_t)k * ny + j) * nx + i] = 0.0;
+            }
+        src = tmp.data();
+    }
+    std::vector<R> img;
+    pack3<R>(s, src, sub, img);
+    HIPCHK(hipMemcpyAsync(base3(s, interior), img.data(), img.size() * sizeof(R), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return OCN_OK;
+}
+
+template <typename R>
+int get3(ocn_state* s, void* interior, double* host, const double* add, int nlev) {
+    std::vector<R> img(s->n3);
+    HIPCHK(hipMemcpyAsync(img.data(), base3(s, interior), img.size() * sizeof(R), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    unpack3<R>(s, img, add, host, nlev);
+    return OCN_OK;
+}
+
+int set2(ocn_state* s, double* interior, const double* host) {
+    std::vector<double> img;
+    pack2(s, host, img);
+    HIPCHK(hipMemcpyAsync(base2(s, interior), img.data(), img.size() * sizeof(double), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return OCN_OK;
+}
+
+int get2(ocn_state* s, double* interior, double* host) {
+    std::vector<double> img(s->n2);
+    HIPCHK(hipMemcpyAsync(img.data(), base2(s, interior), img.size() * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    unpack2(s, img, host);
+    return OCN_OK;
+}
+
+template <typename R>
+int set_field_t(ocn_state* s, int32_t f, const double* host) {
+    const ocn_grid* g = s->g;
+    const int nz = g->nz;
+    DevState& d = s->d;
+    switch (f) {
+    case OCN_FIELD_U:
+    case OCN_FIELD_V: {
+        int rc = set3<R>(s, f == OCN_FIELD_U ? d.u : d.v, host, nullptr, f == OCN_FIELD_U ? 1 : 2);
+        if (rc) return rc;
+        HIPCHK(ocn::launch_colsum<R>(d, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
+        return OCN_OK;
+    }
+    case OCN_FIELD_T: {
+        if (!s->t_set) {
+            // reference profile: mean of T over the wet cells of each level
+            const size_t n2 = (size_t)g->nx * g->ny;
+            for (int k = 0; k < nz; ++k) {
+                double sum = 0.0, all = 0.0;
+                size_t n = 0;
+                for (int j = 0; j < g->ny; ++j)
+                    for (int i = 0; i < g->nx; ++i) {
+                        const double v = host[(size_t)k * n2 + (size_t)j * g->nx + i];
+                        all += v;
+                        if (g->kb[(size_t)j * g->nx + i] >= nz - k) { sum += v; ++n; }
+                    }
+                s->tref[k] = n ? sum / n : all / n2;
+            }
+            s->t_set = true;
+            int rc = upload_tables<R>(s);
+            if (rc) return rc;
+        }
+        return set3<R>(s, d.t, host, s->tref.data(), 0);
+    }
+    case OCN_FIELD_GU_PREV: return set3<R>(s, d.gu, host, nullptr, 0);
+    case OCN_FIELD_GV_PREV: return set3<R>(s, d.gv, host, nullptr, 0);
+    case OCN_FIELD_GT_PREV: return set3<R>(s, d.gt, host, nullptr, 0);
+    case OCN_FIELD_ETA: return set2(s, d.eta, host);
+    case OCN_FIELD_UBT: return set2(s, d.ubt, host);
+    case OCN_FIELD_VBT: return set2(s, d.vbt, host);
+    case OCN_FIELD_ETA_MEAN: return set2(s, d.eta_mean, host);
+    case OCN_FIELD_UBT_MEAN: return set2(s, d.ubt_mean, host);
+    case OCN_FIELD_VBT_MEAN: return set2(s, d.vbt_mean, host);
+    case OCN_FIELD_TAUX: return set2(s, d.taux, host);
+    case OCN_FIELD_TAUY: return set2(s, d.tauy, host);
+    case OCN_FIELD_TSTAR: {
+        s->tstar.assign(host, host + (size_t)g->nx * g->ny);
+        return upload_tables<R>(s);
+    }
+    case OCN_FIELD_TREF: {
+        if (s->t_set) return fail(OCN_E_STATE, "TREF can only be set before T");
+        s->tref.assign(host, host + nz);
+        return upload_tables<R>(s);
+    }
+    default: return fail(OCN_E_INVALID, "field cannot be set");
+    }
+}
+
+template <typename R>
+int get_field_t(ocn_state* s, int32_t f, double* host) {
+    DevState& d = s->d;
+    const ocn_grid* g = s->g;
+    switch (f) {
+    case OCN_FIELD_U: return get3<R>(s, d.u, host, nullptr, g->nz);
+    case OCN_FIELD_V: return get3<R>(s, d.v, host, nullptr, g->nz);
+    case OCN_FIELD_T: return get3<R>(s, d.t, host, s->tref.data(), g->nz);
+    case OCN_FIELD_GU_PREV: return get3<R>(s, d.gu, host, nullptr, g->nz);
+    case OCN_FIELD_GV_PREV: return get3<R>(s, d.gv, host, nullptr, g->nz);
+    case OCN_FIELD_GT_PREV: return get3<R>(s, d.gt, host, nullptr, g->nz);
+    case OCN_FIELD_ETA: return get2(s, d.eta, host);
+    case OCN_FIELD_UBT: return get2(s, d.ubt, host);
+    case OCN_FIELD_VBT: return get2(s, d.vbt, host);
+    case OCN_FIELD_ETA_MEAN: return get2(s, d.eta_mean, host);
+    case OCN_FIELD_UBT_MEAN: return get2(s, d.ubt_mean, host);
+    case OCN_FIELD_VBT_MEAN: return get2(s, d.vbt_mean, host);
+    case OCN_FIELD_TAUX: return get2(s, d.taux, host);
+    case OCN_FIELD_TAUY: return get2(s, d.tauy, host);
+    case OCN_FIELD_TSTAR: {
+        std::copy(s->tstar.begin(), s->tstar.end(), host);
+        return OCN_OK;
+    }
+    case OCN_FIELD_TREF: {
+        std::copy(s->tref.begin(), s->tref.end(), host);
+        return OCN_OK;
+    }
+    case OCN_FIELD_W: {
+        HIPCHK(ocn::launch_w_faces<R>(d, nullptr, s->st));
+        const size_t n2 = (size_t)g->nx * g->ny;
+        int rc = get3<R>(s, d.ts, host, nullptr, g->nz);
+        if (rc) return rc;
+        return get2(s, d.scratch2d, host + (size_t)g->nz * n2);
+    }
+    default: return fail(OCN_E_INVALID, "unknown field");
+    }
+}
+
+size_t field_count(const ocn_grid* g, int32_t f) {
+    const size_t n2 = (size_t)g->nx * g->ny, n3 = n2 * g->nz;
+    switch (f) {
+    case OCN_FIELD_U: case OCN_FIELD_V: case OCN_FIELD_T:
+    case OCN_FIELD_GU_PREV: case OCN_FIELD_GV_PREV: case OCN_FIELD_GT_PREV: return n3;
+    case OCN_FIELD_W: return n2 * (g->nz + 1);
+    case OCN_FIELD_TREF: return g->nz;
+    case OCN_FIELD_ETA: case OCN_FIELD_UBT: case OCN_FIELD_VBT: case OCN_FIELD_ETA_MEAN:
+    case OCN_FIELD_UBT_MEAN: case OCN_FIELD_VBT_MEAN: case OCN_FIELD_TAUX: case OCN_FIELD_TAUY:
+    case OCN_FIELD_TSTAR: return n2;
+    default: return 0;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t ocn_abi_version(void) { return OCN_ABI_VERSION; }
+
+const char* ocn_last_error(void) { return g_err.c_str(); }
+
+int ocn_grid_create(const ocn_grid_desc* desc, ocn_grid** out) {
+    try {
+        if (!desc || !out) return fail(OCN_E_INVALID, "desc and out must not be NULL");
+        const ocn_grid_desc& d = *desc;
+        if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(OCN_E_INVALID, "nx, ny, nz must be >= 1");
+        if (d.halo < 3 || d.halo > 8) return fail(OCN_E_INVALID, "halo must be in 3..8");
+        if (d.coords != OCN_CARTESIAN && d.coords != OCN_LATLON) return fail(OCN_E_INVALID, "bad coords");
+        if (d.coords == OCN_LATLON && d.periodic_y) return fail(OCN_E_INVALID, "a lat-lon grid cannot be periodic in y");
+        if (!d.dz) return fail(OCN_E_INVALID, "dz must not be NULL");
+        if (!(d.dx > 0) || !(d.dy > 0)) return fail(OCN_E_INVALID, "dx and dy must be positive");
+        if (d.reserved != 0) return fail(OCN_E_INVALID, "reserved must be 0");
+        if (d.nz > 1024) return fail(OCN_E_UNSUPPORTED, "nz above 1024");
+        if (d.coords == OCN_LATLON) {
+            const double south = d.y0 - d.halo * d.dy, north = d.y0 + (d.ny + d.halo) * d.dy;
+            if (south <= -90.0 || north >= 90.0) return fail(OCN_E_INVALID, "lat-lon grid and halo must stay inside (-90, 90)");
+        }
+        for (int k = 0; k < d.nz; ++k)
+            if (!(d.dz[k] > 0)) return fail(OCN_E_INVALID, "dz must be positive");
+        ocn_grid* g = new ocn_grid();
+        g->d = d;
+        g->d.dz = nullptr;
+        g->d.kbottom = nullptr;
+        g->nx = d.nx; g->ny = d.ny; g->nz = d.nz; g->h = d.halo;
+        g->dz.assign(d.dz, d.dz + d.nz);
+        g->dzc.assign(d.nz + 1, 0.0);
+        for (int k = 1; k < d.nz; ++k) g->dzc[k] = 0.5 * (d.dz[k - 1] + d.dz[k]);
+        g->kb.assign((size_t)d.nx * d.ny, d.nz);
+        if (d.kbottom)
+            for (size_t c = 0; c < g->kb.size(); ++c) g->kb[c] = std::max(0, std::min<int32_t>(d.nz, d.kbottom[c]));
+        const int nr = d.ny + 2 * d.halo + 1;
+        g->dxc.resize(nr); g->dxv.resize(nr); g->area.resize(nr); g->fcor.resize(nr); g->metric.resize(nr);
+        const double rad = kPi / 180.0;
+        g->dy = d.coords == OCN_LATLON ? d.radius * d.dy * rad : d.dy;
+        for (int q = 0; q < nr; ++q) {
+            int j = q - d.halo;
+            if (d.periodic_y) j = wrap(j, d.ny, true);
+            if (d.coords == OCN_LATLON) {
+                const double latc = d.y0 + (j + 0.5) * d.dy, lats = d.y0 + j * d.dy;
+                g->dxc[q] = d.radius * std::cos(latc * rad) * (d.dx * rad);
+                g->dxv[q] = d.radius * std::cos(lats * rad) * (d.dx * rad);
+                g->fcor[q] = 2.0 * d.omega * std::sin(latc * rad);
+                g->metric[q] = std::tan(latc * rad) / d.radius;
+            } else {
+                g->dxc[q] = d.dx;
+                g->dxv[q] = d.dx;
+                g->fcor[q] = d.f0 + d.beta * ((j + 0.5) * d.dy - 0.5 * d.ny * d.dy);
+                g->metric[q] = 0.0;
+            }
+            g->area[q] = g->dxc[q] * g->dy;
+        }
+        *out = g;
+        return OCN_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(OCN_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(OCN_E_INVALID, "unexpected error");
+    }
+}
+
+void ocn_grid_destroy(ocn_grid* grid) { delete grid; }
+
+int ocn_state_arena_bytes(const ocn_grid* grid, const ocn_params* params, size_t* bytes) {
+    if (!grid || !bytes) return fail(OCN_E_INVALID, "grid and bytes must not be NULL");
+    std::string why;
+    if (!valid_params(params, why)) return fail(OCN_E_INVALID, why);
+    *bytes = make_plan(grid, params->precision).total;
+    return OCN_OK;
+}
+
+int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_arena, size_t arena_bytes,
+                   void* hip_stream, ocn_state** out) {
+    try {
+        if (!grid || !out || !device_arena) return fail(OCN_E_INVALID, "grid, arena and out must not be NULL");
+        std::string why;
+        if (!valid_params(params, why)) return fail(OCN_E_INVALID, why);
+        if (reinterpret_cast<uintptr_t>(device_arena) % 256) return fail(OCN_E_INVALID, "arena must be 256-byte aligned");
+        const Plan P = make_plan(grid, params->precision);
+        if (arena_bytes < P.total) return fail(OCN_E_NOMEM, "arena smaller than ocn_state_arena_bytes");
+        if ((size_t)grid->nz * 64 * P.esize > 64 * 1024) return fail(OCN_E_UNSUPPORTED, "nz too large for the column kernel");
+
+        ocn_state* s = new ocn_state();
+        s->g = grid;
+        s->p = *params;
+        s->st = static_cast<hipStream_t>(hip_stream);
+        s->arena = device_arena;
+        s->bytes = arena_bytes;
+        s->esize = (int)P.esize;
+        s->ox3 = P.ox3; s->ox2 = P.ox2; s->oxk = P.oxk;
+        s->n3 = P.n3; s->n2 = P.n2; s->nk = P.nk;
+        s->tref.assign(grid->nz, 0.0);
+        s->tstar.assign((size_t)grid->nx * grid->ny, 0.0);
+
+        unsigned char* A = static_cast<unsigned char*>(device_arena);
+        DevState& d = s->d;
+        const int h = grid->h;
+        d.nx = grid->nx; d.ny = grid->ny; d.nz = grid->nz; d.h = h;
+        d.periodic_x = grid->d.periodic_x ? 1 : 0;
+        d.periodic_y = grid->d.periodic_y ? 1 : 0;
+        d.latlon = grid->d.coords == OCN_LATLON;
+        d.p3 = (int)P.p3; d.p2 = (int)P.p2; d.pk = (int)P.pk;
+        d.plane3 = (long long)P.p3 * (long long)P.rows;
+        const size_t o3 = ((size_t)h * P.p3 + P.ox3) * P.esize;
+        void** f3s[9] = {&d.u, &d.v, &d.t, &d.us, &d.vs, &d.ts, &d.gu, &d.gv, &d.gt};
+        for (int q = 0; q < 9; ++q) *f3s[q] = A + P.off_f3[q] + o3;
+        double** f2s[20] = {&d.eta, &d.ubt, &d.vbt, &d.se, &d.su, &d.sv, &d.eta_mean, &d.ubt_mean, &d.vbt_mean,
+                            &d.gU, &d.gV, &d.hu, &d.hv, &d.cu, &d.cv, &d.taux, &d.tauy, &d.tstar, &d.scratch2d,
+                            nullptr};
+        const size_t o2 = (size_t)h * P.p2 + P.ox2;
+        for (int q = 0; q < 19; ++q) *f2s[q] = reinterpret_cast<double*>(A + P.off_f2[q]) + o2;
+        d.kb = reinterpret_cast<int*>(A + P.off_kb) + ((size_t)h * P.pk + P.oxk);
+        double** rows[5] = {&d.dxc, &d.dxv, &d.area, &d.fcor, &d.metric};
+        for (int q = 0; q < 5; ++q) *rows[q] = reinterpret_cast<double*>(A + P.off_rows[q]) + h;
+        d.dy = grid->dy;
+        d.dz = reinterpret_cast<double*>(A + P.off_dz);
+        d.dzc = reinterpret_cast<double*>(A + P.off_dzc);
+        d.tref = reinterpret_cast<double*>(A + P.off_tref);
+        d.dtr = A + P.off_dtr;
+        d.thomas_cp = A + P.off_cp;
+        d.thomas_den = A + P.off_den;
+        d.thomas_a = A + P.off_a;
+        d.diag_part = reinterpret_cast<double*>(A + P.off_part);
+        d.diag_out = reinterpret_cast<double*>(A + P.off_out);
+        d.diag_blocks = (int)P.diag_blocks;
+        d.dt = params->dt;
+        d.chi = params->chi;
+        d.g = params->g;
+        d.alpha = params->alpha;
+        d.rho0 = params->rho0;
+        d.kappa = params->kappa;
+        d.restore_inv = params->restore_tau > 0.0 ? 1.0 / params->restore_tau : 0.0;
+        d.n_substeps = params->n_substeps;
+
+        hipError_t e = hipMemsetAsync(device_arena, 0, P.total, s->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+        if (e != hipSuccess) {
+            delete s;
+            return fail(OCN_E_DEVICE, std::string("arena clear: ") + hipGetErrorString(e));
+        }
+        int rc = params->precision == OCN_FP32 ? init_static<float>(s) : init_static<double>(s);
+        if (rc) {
+            delete s;
+            return rc;
+        }
+        *out = s;
+        return OCN_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(OCN_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(OCN_E_INVALID, "unexpected error");
+    }
+}
+
+void ocn_state_destroy(ocn_state* state) {
+    if (state) {
+        (void)hipStreamSynchronize(state->st);
+        drop_events(state);
+        delete state;
+    }
+}
+
+int ocn_set_field(ocn_state* s, int32_t field, const double* host, size_t count) {
+    try {
+        if (!s || !host) return fail(OCN_E_INVALID, "state and host must not be NULL");
+        const size_t n = field_count(s->g, field);
+        if (n == 0 || field == OCN_FIELD_W) return fail(OCN_E_INVALID, "field cannot be set");
+        if (count != n) return fail(OCN_E_INVALID, "count does not match the field size");
+        return s->esize == 4 ? set_field_t<float>(s, field, host) : set_field_t<double>(s, field, host);
+    } catch (const std::bad_alloc&) {
+        return fail(OCN_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(OCN_E_INVALID, "unexpected error");
+    }
+}
+
+int ocn_get_field(ocn_state* s, int32_t field, double* host, size_t count) {
+    try {
+        if (!s || !host) return fail(OCN_E_INVALID, "state and host must not be NULL");
+        const size_t n = field_count(s->g, field);
+        if (n == 0) return fail(OCN_E_INVALID, "unknown field");
+        if (count != n) return fail(OCN_E_INVALID, "count does not match the field size");
+        return s->esize == 4 ? get_field_t<float>(s, field, host) : get_field_t<double>(s, field, host);
+    } catch (const std::bad_alloc&) {
+        return fail(OCN_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(OCN_E_INVALID, "unexpected error");
+    }
+}
+
+int ocn_set_first_step(ocn_state* s, int32_t first) {
+    if (!s) return fail(OCN_E_INVALID, "state must not be NULL");
+    s->first = first ? 1 : 0;
+    return OCN_OK;
+}
+
+int ocn_get_first_step(ocn_state* s, int32_t* first) {
+    if (!s || !first) return fail(OCN_E_INVALID, "state and first must not be NULL");
+    *first = s->first;
+    return OCN_OK;
+}
+
+
+int ocn_step(ocn_state* s, int32_t n) {
+    if (!s) return fail(OCN_E_INVALID, "state must not be NULL");
+    if (n < 0) return fail(OCN_E_INVALID, "n must be >= 0");
+    const bool f32 = s->esize == 4;
+    int rc;
+    for (int q = 0; q < n; ++q) {
+        if (s->timing && (rc = record(s))) return rc;
+        HIPCHK(f32 ? ocn::launch_tendency<float>(s->d, s->first, s->st) : ocn::launch_tendency<double>(s->d, s->first, s->st));
+        if (s->timing && (rc = record(s))) return rc;
+        HIPCHK(ocn::launch_barotropic(s->d, s->st));
+        if (s->timing && (rc = record(s))) return rc;
+        HIPCHK(f32 ? ocn::launch_column<float>(s->d, s->st) : ocn::launch_column<double>(s->d, s->st));
+        if (s->timing) {
+            if ((rc = record(s))) return rc;
+            s->timed_steps += 1;
+        }
+        s->first = 0;
+        s->step += 1;
+        s->time += s->p.dt;
+    }
+    return OCN_OK;
+}
+
+int ocn_stage_timing(ocn_state* s, int32_t enable) {
+    if (!s) return fail(OCN_E_INVALID, "state must not be NULL");
+    HIPCHK(hipStreamSynchronize(s->st));
+    drop_events(s);
+    s->timing = enable != 0;
+    return OCN_OK;
+}
+
+int ocn_stage_times(ocn_state* s, double* ms, int32_t n, int64_t* steps) {
+    if (!s || (!ms && n > 0) || n < 0) return fail(OCN_E_INVALID, "bad arguments");
+    HIPCHK(hipStreamSynchronize(s->st));
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (size_t b = 0; b + 3 < s->events.size(); b += 4)
+        for (int q = 0; q < 3; ++q) {
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, s->events[b + q], s->events[b + q + 1]));
+            acc[q] += t;
+        }
+    for (int q = 0; q < n && q < 3; ++q) ms[q] = acc[q];
+    if (steps) *steps = s->timed_steps;
+    drop_events(s);
+    return OCN_OK;
+}
+
+int ocn_diagnostics(ocn_state* s, ocn_diag* out) {
+    if (!s || !out) return fail(OCN_E_INVALID, "state and out must not be NULL");
+    HIPCHK(s->esize == 4 ? ocn::launch_diagnostics<float>(s->d, s->st) : ocn::launch_diagnostics<double>(s->d, s->st));
+    double r[ocn::DG_COUNT];
+    HIPCHK(hipMemcpyAsync(r, s->d.diag_out, sizeof(r), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    out->step = s->step;
+    out->time = s->time;
+    out->tracer_content = r[ocn::DG_TRACER];
+    out->volume = r[ocn::DG_VOLUME];
+    out->volume_mean = r[ocn::DG_VOLUME_MEAN];
+    out->kinetic_energy = r[ocn::DG_KE];
+    out->wet_area = r[ocn::DG_WET_AREA];
+    out->max_abs_u = r[ocn::DG_MAX_U];
+    out->max_abs_v = r[ocn::DG_MAX_V];
+    out->max_abs_w = r[ocn::DG_MAX_W];
+    out->cfl_adv = r[ocn::DG_CFL];
+    out->t_max = r[ocn::DG_T_MAX];
+    out->t_min = -r[ocn::DG_NEG_T_MIN];
+    out->eta_max = r[ocn::DG_ETA_MAX];
+    out->eta_min = -r[ocn::DG_NEG_ETA_MIN];
+    out->nonfinite = (int64_t)r[ocn::DG_NONFINITE];
+    if (out->nonfinite > 0) return fail(OCN_E_UNSTABLE, "non-finite values in the state");
+    return OCN_OK;
+}
+
+int ocn_synchronize(ocn_state* s) {
+    if (!s) return fail(OCN_E_INVALID, "state must not be NULL");
+    HIPCHK(hipStreamSynchronize(s->st));
+    return OCN_OK;
+}
+
+}  // extern "C"

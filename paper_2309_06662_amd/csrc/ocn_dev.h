@@ -1,0 +1,111 @@
+// ocn_dev.h -- device-side view of one ocean state, shared by the HIP kernels
+// and the host runtime of the library.
+//
+// Layout in HBM. Every 3D field is x-fastest [k][j][i] with a halo of h cells
+// on each side in x and y and none in z. Rows are padded so that the interior
+// of every row starts on a 128-byte boundary; the pointers below point at the
+// interior origin (i = 0, j = 0, k = 0), so (i, j) run from -h to n + h - 1.
+// 2D fields (FP64 barotropic state, column sums, forcing) and the int32 wet
+// layer counts use the same horizontal padding with their own pitch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ocn {
+
+// Diagnostics slots reduced on the device.
+enum DiagSlot {
+    DG_TRACER = 0, DG_VOLUME, DG_VOLUME_MEAN, DG_KE, DG_WET_AREA,  // compensated sums
+    DG_NSUM = 5,
+    DG_MAX_U = 5, DG_MAX_V, DG_MAX_W, DG_CFL, DG_T_MAX, DG_NEG_T_MIN, DG_ETA_MAX, DG_NEG_ETA_MIN,  // maxima
+    DG_NONFINITE = 13,
+    DG_COUNT = 14
+};
+
+struct DevState {
+    // sizes
+    int nx, ny, nz, h;
+    int periodic_x, periodic_y, latlon;
+    int p3;            // row pitch of 3D fields (elements of the field type)
+    int p2;            // row pitch of 2D double fields
+    int pk;            // row pitch of the int32 wet-layer counts
+    long long plane3;  // (ny + 2h) * p3
+    // 3D fields of the field type (double or float), interior origin
+    void *u, *v, *t;        // state; t holds T - tref(k)
+    void *us, *vs, *ts;     // AB2 predictor phi*
+    void *gu, *gv, *gt;     // AB2 history G^{n-1}, overwritten with G^n
+    // 2D FP64
+    double *eta, *ubt, *vbt;             // barotropic state
+    double *se, *su, *sv;                // substep running sums
+    double *eta_mean, *ubt_mean, *vbt_mean;
+    double *gU, *gV;                     // slow forcing: depth integral of the AB2 momentum tendency
+    double *hu, *hv;                     // depth of u and v columns
+    double *cu, *cv;                     // sum_k dz u m_u of the current u, v (vertical-transport seed)
+    double *taux, *tauy;                 // wind stress
+    double *tstar;                       // restoring target minus tref(top)
+    double *scratch2d;                   // one 2D field of scratch
+    // int32 wet layers per column counted from the surface (halo wrapped, walls 0)
+    int* kb;
+    // row metrics, index j from -h to ny + h (FP64), interior origin
+    double *dxc, *dxv, *area, *fcor, *metric;
+    double dy;
+    // level tables
+    double* dz;       // nz
+    double* dzc;      // nz + 1: centre spacing below layer k (dzc[0] and dzc[nz] unused)
+    double* tref;     // nz
+    void* dtr;        // nz * 4 of the field type: tref(k+o) - tref(k), o = -2, -1, +1, +2
+    void* thomas_cp;  // (nz + 1) * nz of the field type: Thomas c' per wet-layer count
+    void* thomas_den; // (nz + 1) * nz: Thomas pivots per wet-layer count
+    void* thomas_a;   // nz: sub-diagonal -dt kappa / dzc_k of a wet face k
+    // diagnostics scratch
+    double* diag_part;  // blocks * DG_COUNT
+    double* diag_out;   // DG_COUNT
+    int diag_blocks;
+    // scalars
+    double dt, chi, g, alpha, rho0, kappa, restore_inv;
+    int n_substeps;
+};
+
+template <typename R>
+__device__ __forceinline__ R* f3(void* p) { return static_cast<R*>(p); }
+
+__host__ __device__ inline long long idx3(const DevState& s, int i, int j, int k) {
+    return (long long)k * s.plane3 + (long long)j * s.p3 + i;
+}
+__host__ __device__ inline long long idx2(const DevState& s, int i, int j) {
+    return (long long)j * s.p2 + i;
+}
+__host__ __device__ inline long long idxk(const DevState& s, int i, int j) {
+    return (long long)j * s.pk + i;
+}
+
+// Visit every periodic image (x, y) of interior point (i, j) that lies inside
+// the halo band of width ext (ext_x, ext_y), excluding (i, j) itself.
+template <class F>
+__device__ __forceinline__ void for_each_image(const DevState& s, int i, int j, int ext, F&& f) {
+    int xlo = i, xhi = i, ylo = j, yhi = j;
+    if (s.periodic_x) {
+        while (xlo - s.nx >= -ext) xlo -= s.nx;
+        while (xhi + s.nx < s.nx + ext) xhi += s.nx;
+    }
+    if (s.periodic_y) {
+        while (ylo - s.ny >= -ext) ylo -= s.ny;
+        while (yhi + s.ny < s.ny + ext) yhi += s.ny;
+    }
+    for (int y = ylo; y <= yhi; y += s.ny)
+        for (int x = xlo; x <= xhi; x += s.nx)
+            if (x != i || y != j) f(x, y);
+}
+
+// Launchers (defined in the kernel translation units).
+template <typename R> hipError_t launch_tendency(const DevState& s, int first, hipStream_t st);
+template <typename R> hipError_t launch_column(const DevState& s, hipStream_t st);
+template <typename R> hipError_t launch_colsum(const DevState& s, hipStream_t st);
+template <typename R> hipError_t launch_diagnostics(const DevState& s, hipStream_t st);
+template <typename R> hipError_t launch_w_faces(const DevState& s, double* out_faces_dev, hipStream_t st);
+hipError_t launch_barotropic(const DevState& s, hipStream_t st);
+
+}  // namespace ocn

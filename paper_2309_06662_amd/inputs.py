@@ -23,8 +23,10 @@ uniform pair drawn at counters 2n and 2n+1. Streams: 0 temperature noise,
 """
 from __future__ import annotations
 
+import concurrent.futures as _cf
 import dataclasses
 import math
+import os
 from typing import Dict, Optional
 
 import numpy as np
@@ -70,6 +72,21 @@ def normal(seed: int, stream: int, counters: np.ndarray) -> np.ndarray:
     u1 = uniform(seed, stream, n * np.uint64(2))
     u2 = uniform(seed, stream, n * np.uint64(2) + np.uint64(1))
     return np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * math.pi * u2)
+
+
+def _parallel_blocks(n: int, fn, block: int = 64):
+    """Run fn(start, stop) over [0, n) in blocks on a thread pool (numpy releases
+    the GIL in its array loops); blocks are disjoint, so the result does not
+    depend on scheduling."""
+    spans = [(a, min(a + block, n)) for a in range(0, n, block)]
+    if len(spans) <= 1:
+        for a, b in spans:
+            fn(a, b)
+        return
+    workers = min(len(spans), os.cpu_count() or 1, 16)
+    with _cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        for f in [ex.submit(fn, a, b) for a, b in spans]:
+            f.result()
 
 
 @dataclasses.dataclass(frozen=True)
@@ -176,15 +193,20 @@ def seafloor_depth(w: Workload) -> np.ndarray:
     sig = 1.0 + 3.0 * u[:, 1]
     lon_s = 360.0 * u[:, 2]
     lat_s = -70.0 + 140.0 * u[:, 3]
-    for s in range(n_mounts):
-        dl = (lon - lon_s[s] + 180.0) % 360.0 - 180.0
-        ex = np.exp(-((dl * math.cos(math.radians(lat_s[s]))) ** 2) / (2.0 * sig[s] ** 2))
-        ey = np.exp(-((lat - lat_s[s]) ** 2) / (2.0 * sig[s] ** 2))
-        d -= h[s] * np.outer(ey, ex)
     north = (lat > -50.0).astype(np.float64)
-    for lon_r in (0.0, 90.0):
-        dl = (lon - lon_r + 180.0) % 360.0 - 180.0
-        d -= w.depth * np.outer(north, np.exp(-dl ** 2 / (2.0 * 2.0 ** 2)))
+
+    def rows(j0, j1):
+        # every row block runs the same per-element arithmetic in the same order
+        for s in range(n_mounts):
+            dl = (lon - lon_s[s] + 180.0) % 360.0 - 180.0
+            ex = np.exp(-((dl * math.cos(math.radians(lat_s[s]))) ** 2) / (2.0 * sig[s] ** 2))
+            ey = np.exp(-((lat[j0:j1] - lat_s[s]) ** 2) / (2.0 * sig[s] ** 2))
+            d[j0:j1] -= h[s] * np.outer(ey, ex)
+        for lon_r in (0.0, 90.0):
+            dl = (lon - lon_r + 180.0) % 360.0 - 180.0
+            d[j0:j1] -= w.depth * np.outer(north[j0:j1], np.exp(-dl ** 2 / (2.0 * 2.0 ** 2)))
+
+    _parallel_blocks(w.ny, rows)
     return np.clip(d, 0.0, w.depth)
 
 
@@ -210,16 +232,20 @@ def initial_temperature(w: Workload, levels: Optional[range] = None) -> np.ndarr
     of the temperature stream.
     """
     zc = layer_centre_z(w)
-    ks = range(w.nz) if levels is None else levels
+    ks = list(range(w.nz) if levels is None else levels)
     out = np.empty((len(ks), w.ny, w.nx), dtype=np.float64)
     plane = np.arange(w.nx * w.ny, dtype=np.uint64)
-    for q, k in enumerate(ks):
+
+    def level(q):
+        k = ks[q]
         base = w.strat_t0 * math.exp(zc[k] / w.strat_scale)
         if w.noise_std != 0.0:
             n = normal(w.seed, STREAM_TEMPERATURE, plane + np.uint64(k * w.nx * w.ny))
             out[q] = base + w.noise_std * n.reshape(w.ny, w.nx)
         else:
             out[q] = base
+
+    _parallel_blocks(len(ks), lambda a, b: [level(q) for q in range(a, b)], block=1)
     return out
 
 

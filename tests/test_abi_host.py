@@ -1,0 +1,82 @@
+"""The C-ABI library loads, exports every function include/ocn.h declares, and
+validates arguments on the host (no GPU call is made here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2309_06662_amd import inputs, ocn
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "ocn.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ocn_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(ocn.ABI_FUNCTIONS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ocn.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert L.ocn_abi_version() == 1
+
+
+def _grid(w, **over):
+    inp = inputs.make_inputs(w)
+    desc, keep = ocn.grid_desc(w, inp["dz"], inp["kbottom"])
+    for k, v in over.items():
+        setattr(desc, k, v)
+    h = C.c_void_p()
+    rc = ocn.lib().ocn_grid_create(C.byref(desc), C.byref(h))
+    return rc, h, keep
+
+
+def test_grid_create_validates_arguments():
+    w = inputs.BETA_BASIN_64.replace(nx=8, ny=6, nz=4)
+    rc, h, _ = _grid(w)
+    assert rc == ocn.OCN_OK
+    ocn.lib().ocn_grid_destroy(h)
+    for bad in ({"nx": 0}, {"halo": 2}, {"halo": 9}, {"coords": 5}, {"reserved": 1}, {"dx": -1.0}):
+        rc, h, _ = _grid(w, **bad)
+        assert rc == ocn.OCN_E_INVALID, bad
+        assert ocn.lib().ocn_last_error()
+    ll = inputs.LATLON_QUARTER.replace(nx=16, ny=10, nz=4, dx=22.5, dy=16.0, bathymetry="flat")
+    rc, h, _ = _grid(ll, periodic_y=1)
+    assert rc == ocn.OCN_E_INVALID
+    rc, h, _ = _grid(ll.replace(y0=-89.0))
+    assert rc == ocn.OCN_E_INVALID
+    assert ocn.lib().ocn_grid_create(None, C.byref(C.c_void_p())) == ocn.OCN_E_INVALID
+
+
+def test_arena_size_scales_with_precision_and_validates_params():
+    w = inputs.BETA_BASIN_64.replace(nx=40, ny=30, nz=10)
+    rc, h, keep = _grid(w)
+    assert rc == 0
+    n64, n32 = C.c_size_t(), C.c_size_t()
+    L = ocn.lib()
+    p = ocn.params(w, "fp64")
+    assert L.ocn_state_arena_bytes(h, C.byref(p), C.byref(n64)) == 0
+    p32 = ocn.params(w, "fp32")
+    assert L.ocn_state_arena_bytes(h, C.byref(p32), C.byref(n32)) == 0
+    # nine 3D fields dominate: the FP32 arena is a bit over half the FP64 one
+    assert 0.45 * n64.value < n32.value < 0.8 * n64.value
+    assert n64.value >= 9 * 40 * 30 * 10 * 8
+    bad = ocn.params(w, "fp64")
+    bad.n_substeps = 0
+    assert L.ocn_state_arena_bytes(h, C.byref(bad), C.byref(n64)) == ocn.OCN_E_INVALID
+    bad = ocn.params(w, "fp64")
+    bad.dt = -5.0
+    assert L.ocn_state_arena_bytes(h, C.byref(bad), C.byref(n64)) == ocn.OCN_E_INVALID
+    # state calls reject NULL handles without touching a device
+    assert L.ocn_step(None, 1) == ocn.OCN_E_INVALID
+    assert L.ocn_synchronize(None) == ocn.OCN_E_INVALID
+    assert L.ocn_state_init(h, C.byref(p), None, 0, None, C.byref(C.c_void_p())) == ocn.OCN_E_INVALID
+    L.ocn_grid_destroy(h)
