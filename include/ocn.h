@@ -178,6 +178,19 @@ int ocn_diagnostics(ocn_state* state, ocn_diag* out);
 /* Wait for all work enqueued on the state's stream. */
 int ocn_synchronize(ocn_state* state);
 
+/* Checkpoint and resume. ocn_checkpoint_bytes reports the size of a
+ * checkpoint; ocn_checkpoint_save copies the state as stored on the device
+ * (prognostic fields including halos, AB2 history, barotropic state and
+ * averages, the reference profile, step count, time and the AB2 start flag)
+ * into the caller's host buffer; ocn_checkpoint_load restores it into a state
+ * of the same grid, precision and halo. Forcing fields are not included: set
+ * them again. Stepping on from a loaded checkpoint is bitwise identical to
+ * stepping on from the saved state. Both calls synchronise the stream;
+ * a size or grid mismatch returns OCN_E_INVALID. */
+int ocn_checkpoint_bytes(ocn_state* state, size_t* bytes);
+int ocn_checkpoint_save(ocn_state* state, void* host, size_t bytes);
+int ocn_checkpoint_load(ocn_state* state, const void* host, size_t bytes);
+
 /* Per-stage timing with HIP events recorded on the state's stream. While
  * enabled (enable = 1), every ocn_step records an event before the tendency
  * kernel, after it, after the barotropic substeps and after the column kernel.

@@ -765,6 +765,85 @@ int ocn_diagnostics(ocn_state* s, ocn_diag* out) {
     return OCN_OK;
 }
 
+namespace {
+
+struct CkptHeader {
+    uint64_t magic;
+    int32_t version, esize, nx, ny, nz, h;
+    int32_t first, t_set;
+    int64_t step;
+    double time;
+};
+constexpr uint64_t kCkptMagic = 0x4f434e434b505431ull;  // "OCNCKPT1"
+
+// (device pointer, bytes) of every region a checkpoint carries, in order
+std::vector<std::pair<void*, size_t>> ckpt_regions(ocn_state* s) {
+    DevState& d = s->d;
+    std::vector<std::pair<void*, size_t>> r;
+    for (void* f : {d.u, d.v, d.t, d.gu, d.gv, d.gt}) r.push_back({base3(s, f), s->n3 * s->esize});
+    for (double* f : {d.eta, d.ubt, d.vbt, d.eta_mean, d.ubt_mean, d.vbt_mean, d.cu, d.cv})
+        r.push_back({base2(s, f), s->n2 * sizeof(double)});
+    return r;
+}
+
+size_t ckpt_size(ocn_state* s) {
+    size_t n = sizeof(CkptHeader) + s->g->nz * sizeof(double);
+    for (auto& r : ckpt_regions(s)) n += r.second;
+    return n;
+}
+
+}  // namespace
+
+int ocn_checkpoint_bytes(ocn_state* s, size_t* bytes) {
+    if (!s || !bytes) return fail(OCN_E_INVALID, "state and bytes must not be NULL");
+    *bytes = ckpt_size(s);
+    return OCN_OK;
+}
+
+int ocn_checkpoint_save(ocn_state* s, void* host, size_t bytes) {
+    if (!s || !host) return fail(OCN_E_INVALID, "state and host must not be NULL");
+    if (bytes != ckpt_size(s)) return fail(OCN_E_INVALID, "buffer size differs from ocn_checkpoint_bytes");
+    unsigned char* p = static_cast<unsigned char*>(host);
+    CkptHeader h{kCkptMagic, 1, s->esize, s->g->nx, s->g->ny, s->g->nz, s->g->h, s->first, s->t_set ? 1 : 0,
+                 s->step, s->time};
+    std::memcpy(p, &h, sizeof(h));
+    p += sizeof(h);
+    std::memcpy(p, s->tref.data(), s->g->nz * sizeof(double));
+    p += s->g->nz * sizeof(double);
+    for (auto& r : ckpt_regions(s)) {
+        HIPCHK(hipMemcpyAsync(p, r.first, r.second, hipMemcpyDeviceToHost, s->st));
+        p += r.second;
+    }
+    HIPCHK(hipStreamSynchronize(s->st));
+    return OCN_OK;
+}
+
+int ocn_checkpoint_load(ocn_state* s, const void* host, size_t bytes) {
+    if (!s || !host) return fail(OCN_E_INVALID, "state and host must not be NULL");
+    if (bytes != ckpt_size(s)) return fail(OCN_E_INVALID, "buffer size differs from ocn_checkpoint_bytes");
+    const unsigned char* p = static_cast<const unsigned char*>(host);
+    CkptHeader h;
+    std::memcpy(&h, p, sizeof(h));
+    if (h.magic != kCkptMagic || h.version != 1 || h.esize != s->esize || h.nx != s->g->nx || h.ny != s->g->ny ||
+        h.nz != s->g->nz || h.h != s->g->h)
+        return fail(OCN_E_INVALID, "checkpoint does not match this state's grid or precision");
+    p += sizeof(h);
+    std::vector<double> tref(s->g->nz);
+    std::memcpy(tref.data(), p, s->g->nz * sizeof(double));
+    p += s->g->nz * sizeof(double);
+    for (auto& r : ckpt_regions(s)) {
+        HIPCHK(hipMemcpyAsync(r.first, p, r.second, hipMemcpyHostToDevice, s->st));
+        p += r.second;
+    }
+    HIPCHK(hipStreamSynchronize(s->st));
+    s->tref = tref;
+    s->t_set = h.t_set != 0;
+    s->first = h.first;
+    s->step = h.step;
+    s->time = h.time;
+    return s->esize == 4 ? upload_tables<float>(s) : upload_tables<double>(s);
+}
+
 int ocn_synchronize(ocn_state* s) {
     if (!s) return fail(OCN_E_INVALID, "state must not be NULL");
     HIPCHK(hipStreamSynchronize(s->st));

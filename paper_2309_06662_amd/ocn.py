@@ -30,7 +30,8 @@ FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev"}
 ABI_FUNCTIONS = ["ocn_abi_version", "ocn_last_error", "ocn_grid_create", "ocn_grid_destroy",
                  "ocn_state_arena_bytes", "ocn_state_init", "ocn_state_destroy", "ocn_set_field",
                  "ocn_get_field", "ocn_set_first_step", "ocn_get_first_step", "ocn_step",
-                 "ocn_diagnostics", "ocn_synchronize", "ocn_stage_timing", "ocn_stage_times"]
+                 "ocn_diagnostics", "ocn_synchronize", "ocn_stage_timing", "ocn_stage_times",
+                 "ocn_checkpoint_bytes", "ocn_checkpoint_save", "ocn_checkpoint_load"]
 
 
 class OcnError(RuntimeError):
@@ -89,6 +90,9 @@ def lib():
         L.ocn_step.argtypes = [C.c_void_p, C.c_int32]
         L.ocn_diagnostics.argtypes = [C.c_void_p, C.POINTER(Diag)]
         L.ocn_synchronize.argtypes = [C.c_void_p]
+        L.ocn_checkpoint_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
+        L.ocn_checkpoint_save.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+        L.ocn_checkpoint_load.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
         L.ocn_stage_timing.argtypes = [C.c_void_p, C.c_int32]
         L.ocn_stage_times.argtypes = [C.c_void_p, _D, C.c_int32, C.POINTER(C.c_int64)]
         _lib = L
@@ -208,6 +212,17 @@ class Model:
 
     def step(self, n: int = 1):
         _check(lib().ocn_step(self.handle, int(n)), "ocn_step")
+
+    def checkpoint(self) -> bytes:
+        n = C.c_size_t()
+        _check(lib().ocn_checkpoint_bytes(self.handle, C.byref(n)), "ocn_checkpoint_bytes")
+        buf = C.create_string_buffer(n.value)
+        _check(lib().ocn_checkpoint_save(self.handle, buf, n.value), "ocn_checkpoint_save")
+        return buf.raw
+
+    def restore(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(lib().ocn_checkpoint_load(self.handle, buf, len(blob)), "ocn_checkpoint_load")
 
     def stage_timing(self, enable: bool):
         _check(lib().ocn_stage_timing(self.handle, int(bool(enable))), "ocn_stage_timing")
