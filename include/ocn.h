@@ -77,7 +77,12 @@ typedef struct ocn_grid_desc {
 typedef struct ocn_params {
     int32_t precision;        /* ocn_precision                                      */
     int32_t n_substeps;       /* barotropic substeps per step, >= 1                 */
-    int32_t reserved0, reserved1;
+    int32_t baro_fuse;        /* substeps per barotropic launch: 0 = library default,
+                                 1 = one substep per launch pair, 2..6 = that many
+                                 substeps per launch on an LDS tile whose halo is as
+                                 wide as the substep count (the paper's wide
+                                 barotropic halo, Sec. 5.3, applied within one GPU) */
+    int32_t reserved1;        /* must be 0                                          */
     double dt;                /* baroclinic step (s)                                */
     double chi;               /* AB2 offset: G = (3/2+chi) G^n - (1/2+chi) G^{n-1}  */
     double g;                 /* gravity (m/s^2)                                    */

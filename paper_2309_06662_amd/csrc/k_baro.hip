@@ -9,6 +9,8 @@
 // periodic copies of its value into the one-cell halo the next launch reads.
 #include "ocn_dev.h"
 
+#include <algorithm>
+
 namespace ocn {
 
 constexpr int BX = 64, BY = 4;
@@ -58,13 +60,172 @@ __global__ __launch_bounds__(BX * BY) void k_baro_uv(const DevState S, const dou
     }
 }
 
+hipError_t launch_barotropic_fused(const DevState& s, hipStream_t st);
+
 hipError_t launch_barotropic(const DevState& s, hipStream_t st) {
+    if (s.baro_fuse >= 2) return launch_barotropic_fused(s, st);
     dim3 block(BX, BY);
     dim3 grid((s.nx + BX - 1) / BX, (s.ny + BY - 1) / BY);
     const double dtau = s.dt / s.n_substeps;
     for (int m = 0; m < s.n_substeps; ++m) {
         hipLaunchKernelGGL(k_baro_eta, grid, block, 0, st, s, dtau, m);
         hipLaunchKernelGGL(k_baro_uv, grid, block, 0, st, s, dtau, (int)(m == s.n_substeps - 1));
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ocn
+
+namespace ocn {
+
+// Temporally blocked substeps: one launch advances s substeps of a 64 x 16
+// tile held in LDS with an s-wide halo. Each substep the region of correct
+// values shrinks by one cell on every side, so after s substeps the tile
+// interior is exact; the halo cells are recomputed redundantly instead of
+// exchanged. Every point carries the same arithmetic as the one-substep path.
+constexpr int FBX = 64, FBY = 16, FSMAX = 6;
+constexpr int FEW = FBX + 2 * FSMAX, FEH = FBY + 2 * FSMAX, FEN = FEW * FEH;
+constexpr int FT = 512, FQ = (FEN + FT - 1) / FT;
+
+__global__ __launch_bounds__(FT) void k_baro_fused(const DevState S, const double dtau, const int s,
+                                                   const int first, const int last) {
+    __shared__ double sE[FEN], sU[FEN], sV[FEN];
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x * FBX, j0 = blockIdx.y * FBY;
+    const int ew = FBX + 2 * s;  // extent of this launch's tile (row stride stays FEW)
+    const int eh = FBY + 2 * s;
+    const int nx = S.nx, ny = S.ny;
+
+    // per owned point: forcing, depths, metrics, accumulators
+    double gU[FQ], gV[FQ], Hu[FQ], Hv[FQ], rdxc[FQ], dxv0[FQ], dxv1[FQ], rarea[FQ];
+    double aE[FQ], aU[FQ], aV[FQ];
+    int gofs[FQ];
+    bool inner[FQ];
+#pragma unroll
+    for (int q = 0; q < FQ; ++q) {
+        const int e = tid + q * FT;
+        const int li = e % FEW, lj = e / FEW;
+        const bool in_tile = (e < FEN) && (li < ew) && (lj < eh);
+        int gi = i0 - s + li, gj = j0 - s + lj;
+        bool inside = in_tile;
+        if (S.periodic_x) gi = ((gi % nx) + nx) % nx;
+        else inside = inside && gi >= 0 && gi < nx;
+        if (S.periodic_y) gj = ((gj % ny) + ny) % ny;
+        else inside = inside && gj >= 0 && gj < ny;
+        const int jm = min(max(gj, 0), ny - 1);
+        const long long c = idx2(S, inside ? gi : 0, inside ? jm : 0);
+        gofs[q] = (int)c;
+        gU[q] = inside ? S.gU[c] : 0.0;
+        gV[q] = inside ? S.gV[c] : 0.0;
+        Hu[q] = inside ? S.hu[c] : 0.0;
+        Hv[q] = inside ? S.hv[c] : 0.0;
+        rdxc[q] = 1.0 / S.dxc[jm];
+        dxv0[q] = S.dxv[jm];
+        dxv1[q] = S.dxv[jm + 1];
+        rarea[q] = 1.0 / S.area[jm];
+        const int ti = i0 - s + li, tj = j0 - s + lj;  // unwrapped position
+        inner[q] = in_tile && li >= s && li < s + FBX && lj >= s && lj < s + FBY && ti < nx && tj < ny;
+        if (e < FEN) {
+            sE[e] = inside ? S.eta[c] : 0.0;
+            sU[e] = inside ? S.ubt[c] : 0.0;
+            sV[e] = inside ? S.vbt[c] : 0.0;
+        }
+        aE[q] = (inner[q] && !first) ? S.se[c] : 0.0;
+        aU[q] = (inner[q] && !first) ? S.su[c] : 0.0;
+        aV[q] = (inner[q] && !first) ? S.sv[c] : 0.0;
+    }
+    __syncthreads();
+
+    const double dy = S.dy, g = S.g;
+    for (int m = 0; m < s; ++m) {
+        // free surface from the divergence of the transports
+        double en[FQ];
+#pragma unroll
+        for (int q = 0; q < FQ; ++q) {
+            const int e = tid + q * FT;
+            en[q] = 0.0;
+            if (e < FEN) {
+                const int li = e % FEW, lj = e / FEW;
+                const int ee = (li + 1 < ew) ? e + 1 : e;    // tile edge: garbage stays in the halo
+                const int en_ = (lj + 1 < eh) ? e + FEW : e;
+                const double div = dy * (sU[ee] - sU[e]) + dxv1[q] * sV[en_] - dxv0[q] * sV[e];
+                en[q] = sE[e] - dtau * rarea[q] * div;
+                if (inner[q]) {
+                    aU[q] += sU[e];
+                    aV[q] += sV[e];
+                    aE[q] += en[q];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < FQ; ++q) {
+            const int e = tid + q * FT;
+            if (e < FEN) sE[e] = en[q];
+        }
+        __syncthreads();
+        // transports from the new surface slope plus the slow forcing
+        double un[FQ], vn[FQ];
+#pragma unroll
+        for (int q = 0; q < FQ; ++q) {
+            const int e = tid + q * FT;
+            un[q] = 0.0;
+            vn[q] = 0.0;
+            if (e < FEN) {
+                const int li = e % FEW, lj = e / FEW;
+                const int ew_ = (li >= 1) ? e - 1 : e;
+                const int es_ = (lj >= 1) ? e - FEW : e;
+                un[q] = Hu[q] > 0.0 ? sU[e] + dtau * (-g * Hu[q] * (sE[e] - sE[ew_]) * rdxc[q] + gU[q]) : 0.0;
+                vn[q] = Hv[q] > 0.0 ? sV[e] + dtau * (-g * Hv[q] * (sE[e] - sE[es_]) / dy + gV[q]) : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < FQ; ++q) {
+            const int e = tid + q * FT;
+            if (e < FEN) { sU[e] = un[q]; sV[e] = vn[q]; }
+        }
+        __syncthreads();
+    }
+
+    // write the interior back (with its periodic halo copies) and the running sums
+#pragma unroll
+    for (int q = 0; q < FQ; ++q) {
+        if (!inner[q]) continue;
+        const int e = tid + q * FT;
+        const int li = e % FEW, lj = e / FEW;
+        const int gi = i0 - s + li, gj = j0 - s + lj;
+        const long long c = gofs[q];
+        S.eta[c] = sE[e];
+        S.ubt[c] = sU[e];
+        S.vbt[c] = sV[e];
+        for_each_image(S, gi, gj, S.h, [&](int x, int y) {
+            const long long o = idx2(S, x, y);
+            S.eta[o] = sE[e];
+            S.ubt[o] = sU[e];
+            S.vbt[o] = sV[e];
+        });
+        if (last) {
+            const double ns = double(S.n_substeps);
+            S.eta_mean[c] = aE[q] / ns;
+            S.ubt_mean[c] = aU[q] / ns;
+            S.vbt_mean[c] = aV[q] / ns;
+        } else {
+            S.se[c] = aE[q];
+            S.su[c] = aU[q];
+            S.sv[c] = aV[q];
+        }
+    }
+}
+
+hipError_t launch_barotropic_fused(const DevState& s, hipStream_t st) {
+    const int sub = std::min(s.baro_fuse, FSMAX);
+    dim3 grid((s.nx + FBX - 1) / FBX, (s.ny + FBY - 1) / FBY);
+    const double dtau = s.dt / s.n_substeps;
+    for (int m0 = 0; m0 < s.n_substeps; m0 += sub) {
+        const int ss = std::min(sub, s.n_substeps - m0);
+        hipLaunchKernelGGL(k_baro_fused, grid, dim3(FT), 0, st, s, dtau, ss, (int)(m0 == 0),
+                           (int)(m0 + ss == s.n_substeps));
     }
     return hipGetLastError();
 }

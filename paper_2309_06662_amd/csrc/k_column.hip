@@ -38,59 +38,68 @@ __device__ __forceinline__ void store_wrapped2(const DevState& S, double* f, int
 template <typename R>
 __global__ __launch_bounds__(CW) void k_column(const DevState S) {
     extern __shared__ __align__(16) unsigned char smem_col[];
-    R* sd = reinterpret_cast<R*>(smem_col);  // nz * CW eliminated right-hand sides
+    R* sd = reinterpret_cast<R*>(smem_col);  // nz * CW: the column, then its eliminated rhs, then the solution
     const int t = threadIdx.x;
     const int i = blockIdx.x * CW + t, j = blockIdx.y;
     const int field = blockIdx.z;
-    if (i >= S.nx) return;
     const int nz = S.nz;
+    const bool live = i < S.nx;
+    const int ic = live ? i : S.nx - 1;
 
-    const int kc = S.kb[idxk(S, i, j)];
+    const int kc = S.kb[idxk(S, ic, j)];
     int K = kc;
-    if (field == 1) K = min(kc, S.kb[idxk(S, i - 1, j)]);
-    if (field == 2) K = min(kc, S.kb[idxk(S, i, j - 1)]);
+    if (field == 1) K = min(kc, S.kb[idxk(S, ic - 1, j)]);
+    if (field == 2) K = min(kc, S.kb[idxk(S, ic, j - 1)]);
 
-    const R* src = f3<R>(field == 0 ? S.ts : field == 1 ? S.us : S.vs);
+    const R* src = f3<R>(field == 0 ? S.ts : field == 1 ? S.us : S.vs) + idx3(S, ic, j, 0);
     R* dst = f3<R>(field == 0 ? S.t : field == 1 ? S.u : S.v);
-    const R* cp = static_cast<const R*>(S.thomas_cp) + (long long)K * nz;
-    const R* den = static_cast<const R*>(S.thomas_den) + (long long)K * nz;
+    const R* cp = static_cast<const R* >(S.thomas_cp) + (long long)K * nz;
+    const R* rden = static_cast<const R*>(S.thomas_den) + (long long)K * nz;  // reciprocal pivots
     const R* asub = static_cast<const R*>(S.thomas_a);
-    const int kbot = nz - K;  // lowest wet layer
-
-    // Temperature is stored as T' = T - tref(k): diffusing T means diffusing T'
-    // with the diffusion of the fixed profile added to the right-hand side,
-    // dt dz L(tref) = -c_k (tref_{k+1} - tref_k) + a_k (tref_k - tref_{k-1}).
     const R* dtr = static_cast<const R*>(S.dtr);
-    // elimination, bottom to top: d'_k = (dz_k phi*_k - a_k d'_{k-1}) / den_k
+    const int kbot = nz - K;  // lowest wet layer
+    const long long pl = S.plane3;
+
+    // Stage the column phi* in LDS: the loads are independent, so a wave keeps
+    // many rows in flight instead of waiting on one level at a time.
+#pragma unroll 8
+    for (int k = 0; k < nz; ++k) sd[k * CW + t] = src[k * pl];
+
+    // Elimination, bottom to top: d'_k = (dz_k phi*_k - a_k d'_{k-1}) / den_k.
+    // Temperature is stored as T' = T - tref(k): diffusing T is diffusing T'
+    // with dt dz L(tref) = -c_k (tref_{k+1} - tref_k) + a_k (tref_k - tref_{k-1})
+    // added to its right-hand side.
     R dprev = R(0);
     for (int k = 0; k < nz; ++k) {
-        R rhs = R(S.dz[k]) * src[idx3(S, i, j, k)];
-        // a_k couples to k-1 across face k, wet when k-1 and k are both wet layers
-        const R a = (k > kbot) ? asub[k] : R(0);
+        R rhs = R(S.dz[k]) * sd[k * CW + t];
+        const R a = (k > kbot) ? asub[k] : R(0);  // face k wet: layers k-1 and k
         if (field == 0) {
             const R c = (k >= kbot && k < nz - 1) ? asub[k + 1] : R(0);
             rhs += -c * dtr[k * 4 + 2] - a * dtr[k * 4 + 1];
         }
-        const R dk = (rhs - a * dprev) / den[k];
+        const R dk = (rhs - a * dprev) * rden[k];
         sd[k * CW + t] = dk;
         dprev = dk;
     }
-    // back-substitution, top to bottom: x_k = d'_k - c'_k x_{k+1}
+    // Back-substitution, top to bottom: x_k = d'_k - c'_k x_{k+1}.
     R xnext = R(0);
     double colsum = 0.0;
     for (int k = nz - 1; k >= 0; --k) {
         const R x = sd[k * CW + t] - cp[k] * xnext;
         xnext = x;
-        if (field == 0) {
-            const long long o = idx3(S, i, j, k);
-            dst[o] = x;
-            store_wrapped(S, dst, i, j, k, x);
-        } else {
-            sd[k * CW + t] = x;
-            if (k >= kbot) colsum += double(S.dz[k]) * double(x);
-        }
+        sd[k * CW + t] = x;
+        if (k >= kbot) colsum += double(S.dz[k]) * double(x);
     }
-    if (field == 0) return;
+    if (!live) return;
+
+    if (field == 0) {
+        for (int k = 0; k < nz; ++k) {
+            const R x = sd[k * CW + t];
+            dst[idx3(S, i, j, k)] = x;
+            store_wrapped(S, dst, i, j, k, x);
+        }
+        return;
+    }
 
     // depth-mean correction: u = u** + (U^{Ns} - sum dz u**) / H on wet layers
     const double H = (field == 1) ? S.hu[idx2(S, i, j)] : S.hv[idx2(S, i, j)];
@@ -103,8 +112,7 @@ __global__ __launch_bounds__(CW) void k_column(const DevState S) {
             val = R(double(sd[k * CW + t]) + corr);
             newsum += double(S.dz[k]) * double(val);
         }
-        const long long o = idx3(S, i, j, k);
-        dst[o] = val;
+        dst[idx3(S, i, j, k)] = val;
         store_wrapped(S, dst, i, j, k, val);
     }
     store_wrapped2(S, field == 1 ? S.cu : S.cv, i, j, newsum);

@@ -10,8 +10,11 @@
 // phi* = phi + dt ((3/2+chi) G^n - (1/2+chi) G^{n-1}), and the depth integral
 // of the AB2 momentum tendency that forces the barotropic mode.
 //
-// Mapping. A 64x4 workgroup owns a tile of (64-1) x (4-1) columns and marches
-// from the surface to the bottom. Thread (tx, ty) sits on point
+// Mapping. A 64 x TY workgroup (TY = 8 in FP32, 4 in FP64) owns a tile of
+// 63 x (TY-1) columns and marches from the surface to the bottom. Tiles are
+// handed out so that the eight XCDs each sweep a contiguous band of the grid:
+// neighbouring tiles share an L2 and, marching in near lockstep, reuse each
+// other's halo rows from it. Thread (tx, ty) sits on point
 // (i0 - 1 + tx, j0 - 1 + ty); at each level it computes, into LDS, the quantities
 // that live at its point: the T flux through the east and north faces, the u
 // flux through the cell centre and the north-west corner, the v flux through
@@ -39,17 +42,24 @@
 namespace ocn {
 
 constexpr int TX = 64;
-constexpr int TY = 4;
-constexpr int LW = TX + 5;   // tile columns: points i0-1-2 .. i0-1+TX-1+3
-constexpr int LH = TY + 5;
-constexpr int LN = LW * LH;
-constexpr int KW = TX + 6;   // wet-count tile: one more column and row on the low side,
-constexpr int KH = TY + 6;   // for the masks of velocity points at the stencil ends
-constexpr int KN = KW * KH;
+
+template <typename R> struct TendShape;
+template <> struct TendShape<float> { static constexpr int TY = 8; };
+template <> struct TendShape<double> { static constexpr int TY = 4; };
 
 template <typename R> struct Eps;
 template <> struct Eps<double> { static constexpr double v = 1e-8; };
 template <> struct Eps<float> { static constexpr float v = 1e-8f; };
+
+// Reciprocals: the hardware estimate in FP32 (1 ulp); in FP64 the estimate
+// refined by two Newton steps.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
 
 // Fifth-order WENO-Z face value (Borges et al. 2008) on Jiang-Shu smoothness
 // indicators; c is the upwind cell, the face lies between c and d.
@@ -67,13 +77,13 @@ __device__ __forceinline__ R weno5z(R a, R b, R c, R d, R e) {
     const R b1 = k13 * s1 * s1 + R(0.25) * r1 * r1;
     const R b2 = k13 * s2 * s2 + R(0.25) * r2 * r2;
     const R tau = fabs(b0 - b2);
-    const R z0 = tau / (b0 + Eps<R>::v);
-    const R z1 = tau / (b1 + Eps<R>::v);
-    const R z2 = tau / (b2 + Eps<R>::v);
+    const R z0 = tau * rcp(b0 + Eps<R>::v);
+    const R z1 = tau * rcp(b1 + Eps<R>::v);
+    const R z2 = tau * rcp(b2 + Eps<R>::v);
     const R a0 = R(0.1) * (R(1) + z0 * z0);
     const R a1 = R(0.6) * (R(1) + z1 * z1);
     const R a2 = R(0.3) * (R(1) + z2 * z2);
-    return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+    return (a0 * q0 + a1 * q1 + a2 * q2) * rcp(a0 + a1 + a2);
 }
 
 // Third-order WENO-JS face value on (b, c, d), c upwind.
@@ -83,9 +93,9 @@ __device__ __forceinline__ R weno3(R b, R c, R d) {
     const R q1 = R(0.5) * (c + d);
     const R e0 = (c - b) * (c - b) + Eps<R>::v;
     const R e1 = (d - c) * (d - c) + Eps<R>::v;
-    const R a0 = (R(1) / R(3)) / (e0 * e0);
-    const R a1 = (R(2) / R(3)) / (e1 * e1);
-    return (a0 * q0 + a1 * q1) / (a0 + a1);
+    const R a0 = (R(1) / R(3)) * rcp(e0 * e0);
+    const R a1 = (R(2) / R(3)) * rcp(e1 * e1);
+    return (a0 * q0 + a1 * q1) * rcp(a0 + a1);
 }
 
 // Order-adaptive reconstruction: WENO5 when all five points are valid, WENO3
@@ -98,7 +108,7 @@ __device__ __forceinline__ R recon(R a, R b, R c, R d, R e, bool oa, bool ob, bo
 }
 
 // Flux F * phi_face through a face with the six values p0..p5 at points -3..+2
-// around it (face between points -1 and 0).
+// around it (face between points -1 and 0); ok flags each point.
 template <typename R>
 __device__ __forceinline__ R upwind_flux(R F, const R* p, const bool* ok) {
     if (F == R(0)) return R(0);
@@ -110,19 +120,54 @@ __device__ __forceinline__ R upwind_flux(R F, const R* p, const bool* ok) {
     return F * recon(a, b, c, d, e, oa, ob, oc, od, oe);
 }
 
+// Same with all six points valid (the open-ocean case).
 template <typename R>
-__global__ __launch_bounds__(TX * TY) void k_tend(const DevState S, const int first) {
+__device__ __forceinline__ R upwind_flux_wet(R F, const R* p) {
+    const bool pos = F > R(0);
+    const R a = pos ? p[0] : p[5], b = pos ? p[1] : p[4], c = pos ? p[2] : p[3];
+    const R d = pos ? p[3] : p[2], e = pos ? p[4] : p[1];
+    return F * weno5z(a, b, c, d, e);
+}
+
+// Hardware workgroups are dealt to the 8 XCDs round-robin; give XCD x the
+// contiguous range of tiles [x*q + min(x, r), ...) of the row-major tile order.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb / 8, r = nb % 8;
+    const int x = b % 8, slot = b / 8;
+    return (x < r) ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
+}
+
+// Occupancy target per precision: four waves per SIMD (two FP32 workgroups of
+// 8 waves per CU) keeps the FP32 kernel within 128 VGPRs.
+template <typename R> struct TendWaves;
+template <> struct TendWaves<float> { static constexpr int n = 4; };
+template <> struct TendWaves<double> { static constexpr int n = 2; };
+
+template <typename R>
+__global__ __launch_bounds__(TX * TendShape<R>::TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R>::n)))
+void k_tend(const DevState S, const int first, const int gx) {
+    constexpr int TY = TendShape<R>::TY;
+    constexpr int NT = TX * TY;
+    constexpr int LW = TX + 5, LH = TY + 5, LN = LW * LH;  // value tiles: points -2 .. +3 around the block
+    constexpr int KW = TX + 6, KH = TY + 6, KN = KW * KH;  // wet counts: one more on the low side
+    constexpr int NS = (LN + NT - 1) / NT;                 // tile slots per thread
+
     __shared__ R sT[LN], sU[LN], sV[LN];
     __shared__ int sK[KN];
-    __shared__ R fxT[TY * TX], fyT[TY * TX], fxu[TY * TX], fyu[TY * TX], fxv[TY * TX], fyv[TY * TX];
-    __shared__ R sQv[TY * TX], sQu[TY * TX], sP[TY * TX], sWm[TY * TX];
+    __shared__ R fxT[NT], fyT[NT], fxu[NT], fyu[NT], fxv[NT], fyv[NT];
+    __shared__ R sQv[NT], sQu[NT], sP[NT], sWm[NT];
 
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-    const int i0 = blockIdx.x * (TX - 1), j0 = blockIdx.y * (TY - 1);
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int bx = tile % gx, by = tile / gx;
+    const int i0 = bx * (TX - 1), j0 = by * (TY - 1);
     const int pi = i0 - 1 + tx, pj = j0 - 1 + ty;
     const int nx = S.nx, ny = S.ny, nz = S.nz, h = S.h;
     const bool used = (pi < nx) && (pj < ny);
     const bool cell = used && tx >= 1 && ty >= 1;
+    const bool need_x = used && ty >= 1;  // quantities a cell reads from its west neighbour
+    const bool need_y = used && tx >= 1;  // ... from its south neighbour
+    const bool need_c = need_x || need_y;
 
     const R* __restrict__ gT = f3<R>(S.t);
     const R* __restrict__ gU = f3<R>(S.u);
@@ -130,26 +175,54 @@ __global__ __launch_bounds__(TX * TY) void k_tend(const DevState S, const int fi
     const R* __restrict__ dtr = static_cast<const R*>(S.dtr);
 
     // wet-layer counts of the tile (static over the march), origin (i0-4, j0-4)
-    for (int q = tid; q < KN; q += TX * TY) {
+    for (int q = tid; q < KN; q += NT) {
         const int li = q % KW, lj = q / KW;
-        const int gi = min(max(i0 - 4 + li, -h), nx + h - 1);
-        const int gj = min(max(j0 - 4 + lj, -h), ny + h - 1);
+        const int gi = min(max(i0 - 4 + li, -S.hk), nx + S.hk - 1);
+        const int gj = min(max(j0 - 4 + lj, -S.hk), ny + S.hk - 1);
         sK[q] = S.kb[idxk(S, gi, gj)];
+    }
+    // this thread's slots of the value tiles (origin (i0-3, j0-3)), as offsets in a level
+    int slot_off[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int e = tid + q * NT;
+        const int li = e % LW, lj = e / LW;
+        const int gi = min(max(i0 - 3 + li, -h), nx + h - 1);
+        const int gj = min(max(j0 - 3 + lj, -h), ny + h - 1);
+        slot_off[q] = gj * S.p3 + gi;
     }
     __syncthreads();
 
-    const int me = (ty + 2) * LW + (tx + 2);   // this point in the value tiles
-    const int mk = (ty + 3) * KW + (tx + 3);   // this point in the wet-count tile
-    const int Kc = sK[mk];
-    const int Ku = min(Kc, sK[mk - 1]);
-    const int Kv = min(Kc, sK[mk - KW]);
+    const int me = (ty + 2) * LW + (tx + 2);  // this point in the value tiles
+    const int mk = (ty + 3) * KW + (tx + 3);  // this point in the wet-count tile
+    auto Kat = [&](int a, int b) { return sK[mk + a + b * KW]; };
+    const int Kc = Kat(0, 0);
+    const int Ku = min(Kc, Kat(-1, 0));
+    const int Kv = min(Kc, Kat(0, -1));
+    const int KuE = min(Kc, Kat(1, 0)), KuSE = min(Kat(0, -1), Kat(1, -1));
+    const int KvN = min(Kc, Kat(0, 1)), KvNW = min(Kat(-1, 0), Kat(-1, 1));
+    // smallest wet count over each horizontal stencil: all six points are
+    // valid at level k when it reaches nz - k
+    int mTx = Kc, mTy = Kc, mux = Kc, muy = Kc, mvx = Kc, mvy = Kc;
+#pragma unroll
+    for (int r = -3; r <= 3; ++r) {
+        mux = min(mux, Kat(r, 0));
+        mvy = min(mvy, Kat(0, r));
+        if (r >= -2) {
+            mTx = min(mTx, Kat(r, 0));
+            mTy = min(mTy, Kat(0, r));
+            muy = min(muy, min(Kat(-1, r), Kat(0, r)));
+            mvx = min(mvx, min(Kat(r, -1), Kat(r, 0)));
+        }
+    }
 
     // row metrics of the point (clamped for points past the domain, which are unused)
     const int jr = min(max(pj, -h), ny + h - 2);
     const int ir = min(max(pi, -h), nx + h - 2);
     const R dxc = R(S.dxc[jr]), dxv0 = R(S.dxv[jr]), dxv1 = R(S.dxv[jr + 1]);
     const R area = R(S.area[jr]), fc = R(S.fcor[jr]), met = R(S.metric[jr]);
-    const R dy = R(S.dy);
+    const R inv_area = R(1.0 / S.area[jr]), inv_areav = R(1.0 / (S.dxv[jr] * S.dy)), inv_dxc = R(1.0 / S.dxc[jr]);
+    const R dy = R(S.dy), inv_dy = R(1.0 / S.dy);
     const R ga = R(S.g * S.alpha);
     const R dt = R(S.dt);
     const R c_new = first ? R(1) : R(1.5 + S.chi);
@@ -165,22 +238,30 @@ __global__ __launch_bounds__(TX * TY) void k_tend(const DevState S, const int fi
     R wt[6], wu[6], wv[6];
 #pragma unroll
     for (int r = 0; r < 6; ++r) { wt[r] = R(0); wu[r] = R(0); wv[r] = R(0); }
+    const long long pl = S.plane3;
+    const long long own = idx3(S, cell ? pi : 0, cell ? pj : 0, 0);
     if (cell) {
 #pragma unroll
         for (int r = 1; r < 6; ++r) {
             const int k = nz + 2 - r;  // before the first shift: levels nz+1 .. nz-3
             if (k >= 0 && k < nz) {
-                const long long o = idx3(S, pi, pj, k);
-                wt[r] = gT[o]; wu[r] = gU[o]; wv[r] = gV[o];
+                wt[r] = gT[own + k * pl]; wu[r] = gU[own + k * pl]; wv[r] = gV[own + k * pl];
             }
         }
+    }
+
+    // prefetch of the top level's tile slots
+    R pT[NS], pU[NS], pV[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const long long o = (long long)(nz - 1) * pl + slot_off[q];
+        pT[q] = gT[o]; pU[q] = gU[o]; pV[q] = gV[o];
     }
 
     R fzT_top = R(0), fzu_top = R(0), fzv_top = R(0);  // fluxes through the top face of level k
     R Wm_top = R(0);                                     // masked W on that face
     R p_prev = R(0), b_prev = R(0);
     double gUacc = 0.0, gVacc = 0.0;
-    const long long pl = S.plane3;
     const R wind_u = cell ? R(S.taux[idx2(S, pi, pj)] / (S.rho0 * S.dz[nz - 1])) : R(0);
     const R wind_v = cell ? R(S.tauy[idx2(S, pi, pj)] / (S.rho0 * S.dz[nz - 1])) : R(0);
     const R tstar = cell ? R(S.tstar[idx2(S, pi, pj)]) : R(0);
@@ -192,73 +273,118 @@ __global__ __launch_bounds__(TX * TY) void k_tend(const DevState S, const int fi
         for (int r = 0; r < 5; ++r) { wt[r] = wt[r + 1]; wu[r] = wu[r + 1]; wv[r] = wv[r + 1]; }
         wt[5] = R(0); wu[5] = R(0); wv[5] = R(0);
         if (cell && k - 3 >= 0) {
-            const long long o = idx3(S, pi, pj, k - 3);
+            const long long o = own + (long long)(k - 3) * pl;
             wt[5] = gT[o]; wu[5] = gU[o]; wv[5] = gV[o];
         }
-        // stage level k of the tile
-        for (int q = tid; q < LN; q += TX * TY) {
-            const int li = q % LW, lj = q / LW;
-            const int gi = min(max(i0 - 3 + li, -h), nx + h - 1);
-            const int gj = min(max(j0 - 3 + lj, -h), ny + h - 1);
-            const long long o = (long long)k * pl + (long long)gj * S.p3 + gi;
-            sT[q] = gT[o]; sU[q] = gU[o]; sV[q] = gV[o];
+        // stage level k from the prefetch registers, then prefetch level k-1
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int e = tid + q * NT;
+            if (e < LN) { sT[e] = pT[q]; sU[e] = pU[q]; sV[e] = pV[q]; }
+        }
+        if (k >= 1) {
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const long long o = (long long)(k - 1) * pl + slot_off[q];
+                pT[q] = gT[o]; pU[q] = gU[o]; pV[q] = gV[o];
+            }
         }
         __syncthreads();
 
         const R dzk = R(S.dz[k]);
+        const R inv_dz = R(1.0 / S.dz[k]);
         const int kwet = nz - k;  // a column with K wet layers is wet at k iff K >= nz - k
-        // masks at offset (a, b) from this point
-        auto wet = [&](int a, int b) { return sK[mk + a + b * KW] >= kwet; };
+        auto wet = [&](int a, int b) { return Kat(a, b) >= kwet; };
         auto mu = [&](int a, int b) { return wet(a, b) && wet(a - 1, b); };
         auto mv = [&](int a, int b) { return wet(a, b) && wet(a, b - 1); };
-        auto U3 = [&](int a, int b) { return mu(a, b) ? sU[me + a + b * LW] * dy * dzk : R(0); };
-        auto V3 = [&](int a, int b, R dxv) { return mv(a, b) ? sV[me + a + b * LW] * dxv * dzk : R(0); };
+        auto at = [&](const R* f, int a, int b) { return f[me + a + b * LW]; };
 
         // ---- quantities at this point ----
-        {
-            const R U00 = U3(0, 0), U10 = U3(1, 0), U1m = U3(1, -1);
-            const R V00 = V3(0, 0, dxv0), V01 = V3(0, 1, dxv1), Vm1 = V3(-1, 1, dxv1);
+        if (used) {
+            const R U00 = (Ku >= kwet) ? at(sU, 0, 0) * dy * dzk : R(0);
+            const R U10 = (KuE >= kwet) ? at(sU, 1, 0) * dy * dzk : R(0);
+            const R V00 = (Kv >= kwet) ? at(sV, 0, 0) * dxv0 * dzk : R(0);
+            const R V01 = (KvN >= kwet) ? at(sV, 0, 1) * dxv1 * dzk : R(0);
             R p[6];
             bool ok[6];
-            // T through the east face
+            if (need_x) {
+                const R U1m = (KuSE >= kwet) ? at(sU, 1, -1) * dy * dzk : R(0);
+                // T through the east face
 #pragma unroll
-            for (int r = 0; r < 6; ++r) { p[r] = sT[me - 2 + r]; ok[r] = wet(r - 2, 0); }
-            fxT[tid] = upwind_flux(U10, p, ok);
-            // T through the north face
+                for (int r = 0; r < 6; ++r) p[r] = at(sT, r - 2, 0);
+                if (mTx >= kwet) fxT[tid] = (U10 == R(0)) ? R(0) : upwind_flux_wet(U10, p);
+                else {
 #pragma unroll
-            for (int r = 0; r < 6; ++r) { p[r] = sT[me + (r - 2) * LW]; ok[r] = wet(0, r - 2); }
-            fyT[tid] = upwind_flux(V01, p, ok);
-            // u through the cell centre (between u(pi) and u(pi+1))
+                    for (int r = 0; r < 6; ++r) ok[r] = wet(r - 2, 0);
+                    fxT[tid] = upwind_flux(U10, p, ok);
+                }
+                // u through the cell centre (between u(pi) and u(pi+1))
+                const R Fu = R(0.5) * (U00 + U10);
 #pragma unroll
-            for (int r = 0; r < 6; ++r) { p[r] = sU[me - 2 + r]; ok[r] = mu(r - 2, 0); }
-            fxu[tid] = upwind_flux(R(0.5) * (U00 + U10), p, ok);
-            // u through the north-west corner (between u(pi,pj) and u(pi,pj+1))
+                for (int r = 0; r < 6; ++r) p[r] = at(sU, r - 2, 0);
+                if (mux >= kwet) fxu[tid] = (Fu == R(0)) ? R(0) : upwind_flux_wet(Fu, p);
+                else {
 #pragma unroll
-            for (int r = 0; r < 6; ++r) { p[r] = sU[me + (r - 2) * LW]; ok[r] = mu(0, r - 2); }
-            fyu[tid] = upwind_flux(R(0.5) * (Vm1 + V01), p, ok);
-            // v through the south-east corner (between v(pi,pj) and v(pi+1,pj))
+                    for (int r = 0; r < 6; ++r) ok[r] = mu(r - 2, 0);
+                    fxu[tid] = upwind_flux(Fu, p, ok);
+                }
+                // v through the south-east corner (between v(pi,pj) and v(pi+1,pj))
+                const R Fv = R(0.5) * (U1m + U10);
 #pragma unroll
-            for (int r = 0; r < 6; ++r) { p[r] = sV[me - 2 + r]; ok[r] = mv(r - 2, 0); }
-            fxv[tid] = upwind_flux(R(0.5) * (U1m + U10), p, ok);
-            // v through the cell centre (between v(pj) and v(pj+1))
+                for (int r = 0; r < 6; ++r) p[r] = at(sV, r - 2, 0);
+                if (mvx >= kwet) fxv[tid] = (Fv == R(0)) ? R(0) : upwind_flux_wet(Fv, p);
+                else {
 #pragma unroll
-            for (int r = 0; r < 6; ++r) { p[r] = sV[me + (r - 2) * LW]; ok[r] = mv(0, r - 2); }
-            fyv[tid] = upwind_flux(R(0.5) * (V00 + V01), p, ok);
-
-            // Coriolis: Q = (f + u_c tan(phi)/a) V_c on wet cells
-            const R uc = R(0.5) * (sU[me] + sU[me + 1]);
-            const R vc = R(0.5) * (sV[me] + sV[me + LW]);
-            const R Q = wet(0, 0) ? (fc + met * uc) * area * dzk : R(0);
-            sQv[tid] = Q * vc;
-            sQu[tid] = Q * uc;
-
+                    for (int r = 0; r < 6; ++r) ok[r] = mv(r - 2, 0);
+                    fxv[tid] = upwind_flux(Fv, p, ok);
+                }
+            }
+            if (need_y) {
+                const R Vm1 = (KvNW >= kwet) ? at(sV, -1, 1) * dxv1 * dzk : R(0);
+                // T through the north face
+#pragma unroll
+                for (int r = 0; r < 6; ++r) p[r] = at(sT, 0, r - 2);
+                if (mTy >= kwet) fyT[tid] = (V01 == R(0)) ? R(0) : upwind_flux_wet(V01, p);
+                else {
+#pragma unroll
+                    for (int r = 0; r < 6; ++r) ok[r] = wet(0, r - 2);
+                    fyT[tid] = upwind_flux(V01, p, ok);
+                }
+                // u through the north-west corner (between u(pi,pj) and u(pi,pj+1))
+                const R Fu = R(0.5) * (Vm1 + V01);
+#pragma unroll
+                for (int r = 0; r < 6; ++r) p[r] = at(sU, 0, r - 2);
+                if (muy >= kwet) fyu[tid] = (Fu == R(0)) ? R(0) : upwind_flux_wet(Fu, p);
+                else {
+#pragma unroll
+                    for (int r = 0; r < 6; ++r) ok[r] = mu(0, r - 2);
+                    fyu[tid] = upwind_flux(Fu, p, ok);
+                }
+                // v through the cell centre (between v(pj) and v(pj+1))
+                const R Fv = R(0.5) * (V00 + V01);
+#pragma unroll
+                for (int r = 0; r < 6; ++r) p[r] = at(sV, 0, r - 2);
+                if (mvy >= kwet) fyv[tid] = (Fv == R(0)) ? R(0) : upwind_flux_wet(Fv, p);
+                else {
+#pragma unroll
+                    for (int r = 0; r < 6; ++r) ok[r] = mv(0, r - 2);
+                    fyv[tid] = upwind_flux(Fv, p, ok);
+                }
+            }
+            if (need_c) {
+                // Coriolis: Q = (f + u_c tan(phi)/a) V_c on wet cells
+                const R uc = R(0.5) * (at(sU, 0, 0) + at(sU, 1, 0));
+                const R vc = R(0.5) * (at(sV, 0, 0) + at(sV, 0, 1));
+                const R Q = (Kc >= kwet) ? (fc + met * uc) * area * dzk : R(0);
+                sQv[tid] = Q * vc;
+                sQu[tid] = Q * uc;
+            }
             // hydrostatic pressure of the anomaly, from p = 0 at z = 0 downward
-            const R b = ga * sT[me];
+            const R b = ga * at(sT, 0, 0);
             const R pk = (k == nz - 1) ? -R(0.5) * dzk * b : p_prev - R(S.dzc[k + 1]) * (R(0.5) * (b + b_prev));
             p_prev = pk;
             b_prev = b;
             sP[tid] = pk;
-
             // vertical transport on the bottom face of level k
             const double div = double(U10) - double(U00) + (double(V01) - double(V00));
             Wc = Wc + div;
@@ -271,7 +397,7 @@ __global__ __launch_bounds__(TX * TY) void k_tend(const DevState S, const int fi
         const R Wm_b = sWm[tid];
         if (cell) {
             const int c = tid, cw = tid - 1, cs = tid - TX;
-            const long long o = idx3(S, pi, pj, k);
+            const long long o = own + (long long)k * pl;
 
             // vertical fluxes through the bottom face (between levels k-1 and k)
             R fzT_bot = R(0), fzu_bot = R(0), fzv_bot = R(0);
@@ -325,7 +451,6 @@ __global__ __launch_bounds__(TX * TY) void k_tend(const DevState S, const int fi
             // tracer
             R GT = R(0);
             if (Kc >= kwet) {
-                const R vol = area * dzk;
                 R E_top;
                 if (k == nz - 1) {
                     E_top = R(Wsurf) * R(S.tref[k]);  // volume flux through the surface, full T
@@ -334,23 +459,23 @@ __global__ __launch_bounds__(TX * TY) void k_tend(const DevState S, const int fi
                     E_top = (Wm_top > R(0)) ? R(0) : Wm_top * (-dtr[k * 4 + 2]);
                 }
                 const R divF = (fxT[c] - fxT[cw]) + (fyT[c] - fyT[cs]) + (fzT_top - fzT_bot);
-                GT = (-divF + (E_top - E_bot)) / vol;
+                GT = (-divF + (E_top - E_bot)) * (inv_area * inv_dz);
                 if (k == nz - 1) GT += (tstar - wt[2]) * rinv;
             }
             // u momentum
             R GUm = R(0);
             if (Ku >= kwet) {
-                const R vol = area * dzk;
+                const R ivol = inv_area * inv_dz;
                 const R divF = (fxu[c] - fxu[cw]) + (fyu[c] - fyu[cs]) + (fzu_top - fzu_bot);
-                GUm = -divF / vol + (sQv[cw] + sQv[c]) / (R(2) * vol) - (sP[c] - sP[cw]) / dxc;
+                GUm = -divF * ivol + (sQv[cw] + sQv[c]) * (R(0.5) * ivol) - (sP[c] - sP[cw]) * inv_dxc;
                 if (k == nz - 1) GUm += wind_u;
             }
             // v momentum
             R GVm = R(0);
             if (Kv >= kwet) {
-                const R vol = dxv0 * dy * dzk;
+                const R ivol = inv_areav * inv_dz;
                 const R divF = (fxv[c] - fxv[cw]) + (fyv[c] - fyv[cs]) + (fzv_top - fzv_bot);
-                GVm = -divF / vol - (sQu[cs] + sQu[c]) / (R(2) * vol) - (sP[c] - sP[cs]) / dy;
+                GVm = -divF * ivol - (sQu[cs] + sQu[c]) * (R(0.5) * ivol) - (sP[c] - sP[cs]) * inv_dy;
                 if (k == nz - 1) GVm += wind_v;
             }
 
@@ -385,9 +510,10 @@ __global__ __launch_bounds__(TX * TY) void k_tend(const DevState S, const int fi
 
 template <typename R>
 hipError_t launch_tendency(const DevState& s, int first, hipStream_t st) {
-    dim3 block(TX, TY);
-    dim3 grid((s.nx + TX - 2) / (TX - 1), (s.ny + TY - 2) / (TY - 1));
-    hipLaunchKernelGGL(k_tend<R>, grid, block, 0, st, s, first);
+    constexpr int TY = TendShape<R>::TY;
+    const int gx = (s.nx + TX - 2) / (TX - 1);
+    const int gy = (s.ny + TY - 2) / (TY - 1);
+    hipLaunchKernelGGL(k_tend<R>, dim3(gx * gy), dim3(TX, TY), 0, st, s, first, gx);
     return hipGetLastError();
 }
 

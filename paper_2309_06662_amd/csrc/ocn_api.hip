@@ -132,9 +132,9 @@ Plan make_plan(const ocn_grid* g, int precision) {
     P.ox2 = round_up(h, 16);
     P.p2 = round_up(P.ox2 + g->nx + h, 16);
     P.n2 = P.p2 * P.rows;
-    P.oxk = round_up(h, 32);
-    P.pk = round_up(P.oxk + g->nx + h, 32);
-    P.nk = P.pk * P.rows;
+    P.oxk = round_up(h + 1, 32);
+    P.pk = round_up(P.oxk + g->nx + h + 1, 32);
+    P.nk = P.pk * (g->ny + 2 * (h + 1));
     P.nrow = g->ny + 2 * h + 1;
     P.diag_blocks = ((g->nx + 63) / 64) * ((g->ny + 3) / 4);
     Layout L;
@@ -162,6 +162,8 @@ bool valid_params(const ocn_params* p, std::string& why) {
     if (!(p->dt > 0.0) || !std::isfinite(p->dt)) { why = "dt must be positive"; return false; }
     if (!(p->kappa >= 0.0)) { why = "kappa must be >= 0"; return false; }
     if (!(p->rho0 > 0.0)) { why = "rho0 must be positive"; return false; }
+    if (p->baro_fuse < 0 || p->baro_fuse > 6) { why = "baro_fuse must be in 0..6"; return false; }
+    if (p->reserved1 != 0) { why = "reserved1 must be 0"; return false; }
     return true;
 }
 
@@ -265,11 +267,12 @@ int init_static(ocn_state* s) {
     const ocn_grid* g = s->g;
     const int nx = g->nx, ny = g->ny, nz = g->nz, h = g->h;
     DevState& d = s->d;
-    // wet-layer counts with halo
-    std::vector<int32_t> kbimg((size_t)d.pk * (ny + 2 * h), 0);
-    for (int j = -h; j < ny + h; ++j)
-        for (int i = -h; i < nx + h; ++i) kbimg[(size_t)(j + h) * d.pk + s->oxk + i] = kb_at(g, i, j);
-    HIPCHK(hipMemcpyAsync(d.kb - ((size_t)h * d.pk + s->oxk), kbimg.data(), kbimg.size() * 4, hipMemcpyHostToDevice, s->st));
+    // wet-layer counts with a halo of hk = h + 1
+    const int hk = d.hk;
+    std::vector<int32_t> kbimg((size_t)d.pk * (ny + 2 * hk), 0);
+    for (int j = -hk; j < ny + hk; ++j)
+        for (int i = -hk; i < nx + hk; ++i) kbimg[(size_t)(j + hk) * d.pk + s->oxk + i] = kb_at(g, i, j);
+    HIPCHK(hipMemcpyAsync(d.kb - ((size_t)hk * d.pk + s->oxk), kbimg.data(), kbimg.size() * 4, hipMemcpyHostToDevice, s->st));
     // row metrics
     const size_t nr = ny + 2 * h + 1;
     double* rows[5] = {d.dxc, d.dxv, d.area, d.fcor, d.metric};
@@ -313,7 +316,7 @@ int init_static(ocn_state* s) {
             const double dn = b - a * cprev;
             const double cpk = c / dn;
             cp[(size_t)K * nz + k] = R(cpk);
-            den[(size_t)K * nz + k] = R(dn);
+            den[(size_t)K * nz + k] = R(1.0 / dn);  // reciprocal pivot
             cprev = cpk;
         }
     }
@@ -587,6 +590,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         DevState& d = s->d;
         const int h = grid->h;
         d.nx = grid->nx; d.ny = grid->ny; d.nz = grid->nz; d.h = h;
+        d.hk = h + 1;
         d.periodic_x = grid->d.periodic_x ? 1 : 0;
         d.periodic_y = grid->d.periodic_y ? 1 : 0;
         d.latlon = grid->d.coords == OCN_LATLON;
@@ -600,7 +604,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
                             nullptr};
         const size_t o2 = (size_t)h * P.p2 + P.ox2;
         for (int q = 0; q < 19; ++q) *f2s[q] = reinterpret_cast<double*>(A + P.off_f2[q]) + o2;
-        d.kb = reinterpret_cast<int*>(A + P.off_kb) + ((size_t)h * P.pk + P.oxk);
+        d.kb = reinterpret_cast<int*>(A + P.off_kb) + ((size_t)(h + 1) * P.pk + P.oxk);
         double** rows[5] = {&d.dxc, &d.dxv, &d.area, &d.fcor, &d.metric};
         for (int q = 0; q < 5; ++q) *rows[q] = reinterpret_cast<double*>(A + P.off_rows[q]) + h;
         d.dy = grid->dy;
@@ -622,6 +626,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         d.kappa = params->kappa;
         d.restore_inv = params->restore_tau > 0.0 ? 1.0 / params->restore_tau : 0.0;
         d.n_substeps = params->n_substeps;
+        d.baro_fuse = params->baro_fuse == 0 ? 5 : params->baro_fuse;
 
         hipError_t e = hipMemsetAsync(device_arena, 0, P.total, s->st);
         if (e == hipSuccess) e = hipStreamSynchronize(s->st);

@@ -5,8 +5,9 @@
 // on each side in x and y and none in z. Rows are padded so that the interior
 // of every row starts on a 128-byte boundary; the pointers below point at the
 // interior origin (i = 0, j = 0, k = 0), so (i, j) run from -h to n + h - 1.
-// 2D fields (FP64 barotropic state, column sums, forcing) and the int32 wet
-// layer counts use the same horizontal padding with their own pitch.
+// 2D fields (FP64 barotropic state, column sums, forcing) use the same
+// horizontal padding with their own pitch; the int32 wet-layer counts carry one
+// more halo cell than the fields, for the masks at the far end of a stencil.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,6 +29,7 @@ enum DiagSlot {
 struct DevState {
     // sizes
     int nx, ny, nz, h;
+    int hk;            // halo of the wet-layer counts: h + 1 (velocity masks at stencil ends)
     int periodic_x, periodic_y, latlon;
     int p3;            // row pitch of 3D fields (elements of the field type)
     int p2;            // row pitch of 2D double fields
@@ -47,7 +49,8 @@ struct DevState {
     double *taux, *tauy;                 // wind stress
     double *tstar;                       // restoring target minus tref(top)
     double *scratch2d;                   // one 2D field of scratch
-    // int32 wet layers per column counted from the surface (halo wrapped, walls 0)
+    // int32 wet layers per column counted from the surface, with a halo of hk
+    // (periodic images wrapped, zero beyond walls)
     int* kb;
     // row metrics, index j from -h to ny + h (FP64), interior origin
     double *dxc, *dxv, *area, *fcor, *metric;
@@ -58,7 +61,7 @@ struct DevState {
     double* tref;     // nz
     void* dtr;        // nz * 4 of the field type: tref(k+o) - tref(k), o = -2, -1, +1, +2
     void* thomas_cp;  // (nz + 1) * nz of the field type: Thomas c' per wet-layer count
-    void* thomas_den; // (nz + 1) * nz: Thomas pivots per wet-layer count
+    void* thomas_den; // (nz + 1) * nz: reciprocal Thomas pivots per wet-layer count
     void* thomas_a;   // nz: sub-diagonal -dt kappa / dzc_k of a wet face k
     // diagnostics scratch
     double* diag_part;  // blocks * DG_COUNT
@@ -67,6 +70,7 @@ struct DevState {
     // scalars
     double dt, chi, g, alpha, rho0, kappa, restore_inv;
     int n_substeps;
+    int baro_fuse;  // substeps per barotropic launch
 };
 
 template <typename R>

@@ -49,7 +49,7 @@ class GridDesc(C.Structure):
 
 
 class Params(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("n_substeps", C.c_int32), ("reserved0", C.c_int32),
+    _fields_ = [("precision", C.c_int32), ("n_substeps", C.c_int32), ("baro_fuse", C.c_int32),
                 ("reserved1", C.c_int32), ("dt", C.c_double), ("chi", C.c_double), ("g", C.c_double),
                 ("alpha", C.c_double), ("rho0", C.c_double), ("t_ref", C.c_double), ("kappa", C.c_double),
                 ("restore_tau", C.c_double)]
@@ -120,10 +120,11 @@ def grid_desc(w: "_inputs.Workload", dz: np.ndarray, kbottom: Optional[np.ndarra
     return d, (dz, kb)
 
 
-def params(w: "_inputs.Workload", precision: str) -> Params:
+def params(w: "_inputs.Workload", precision: str, baro_fuse: int = 0) -> Params:
     p = Params()
     p.precision = OCN_FP32 if precision == "fp32" else OCN_FP64
     p.n_substeps = w.n_substeps
+    p.baro_fuse = baro_fuse
     p.dt, p.chi, p.g, p.alpha, p.rho0, p.t_ref, p.kappa = w.dt, w.chi, w.g, w.alpha, w.rho0, w.t_ref, w.kappa
     p.restore_tau = w.restore_days * 86400.0 if w.restore_days > 0 else 0.0
     return p
@@ -148,7 +149,7 @@ class Model:
     """One ocean state on a GPU. Fields are float64 numpy arrays: 3D [nz, ny, nx], 2D [ny, nx]."""
 
     def __init__(self, w, precision: str = "fp64", inp: Optional[Dict[str, np.ndarray]] = None,
-                 device: str = "cuda:0", stream=None):
+                 device: str = "cuda:0", stream=None, baro_fuse: int = 0):
         import torch  # device memory and the stream only
 
         if precision not in ("fp64", "fp32"):
@@ -159,7 +160,7 @@ class Model:
         if inp is None:
             inp = _inputs.make_inputs(w)
         self.grid = Grid(w, inp["dz"], inp["kbottom"])
-        self._params = params(w, precision)
+        self._params = params(w, precision, baro_fuse)
         nbytes = C.c_size_t()
         _check(lib().ocn_state_arena_bytes(self.grid.handle, C.byref(self._params), C.byref(nbytes)),
                "ocn_state_arena_bytes")

@@ -35,12 +35,12 @@ def _wet_masks(w, kb):
             "U_mean": col, "V_mean": col}
 
 
-def _pair(w, precision="fp64", inp=None, setup=None):
+def _pair(w, precision="fp64", inp=None, setup=None, baro_fuse=0):
     if inp is None:
         inp = inputs.make_inputs(w)
-    print(f"case {w.name} {precision} {w.nx}x{w.ny}x{w.nz}", flush=True)
+    print(f"case {w.name} {precision} {w.nx}x{w.ny}x{w.nz} baro_fuse={baro_fuse}", flush=True)
     ref = oracle.OracleModel.from_inputs(w, inp)
-    gpu = _ocn().Model(w, precision, inp)
+    gpu = _ocn().Model(w, precision, inp, baro_fuse=baro_fuse)
     if setup is not None:
         setup(ref, gpu)
     return ref, gpu, inp
@@ -64,6 +64,17 @@ def test_beta_basin_fp64_ten_steps(seed):
     ref, gpu, inp = _pair(w)
     ref.step(10)
     gpu.step(10)
+    _compare(ref, gpu, w, inp["kbottom"], 1e-11)
+
+
+@pytest.mark.parametrize("fuse", [1, 2, 3, 6])
+def test_barotropic_fusion_depths_fp64(fuse):
+    """Every substep-fusion depth matches the oracle; 40 substeps do not divide
+    by 3 or 6, so the last launch of a step runs fewer substeps."""
+    w = small_latlon(nx=100, ny=40, nz=8, dt=900.0, n_substeps=40)
+    ref, gpu, inp = _pair(w, baro_fuse=fuse)
+    ref.step(3)
+    gpu.step(3)
     _compare(ref, gpu, w, inp["kbottom"], 1e-11)
 
 
@@ -119,8 +130,13 @@ def test_small_and_shallow_domains_fp64(shape):
     _compare(ref, gpu, w, inp["kbottom"], 1e-11)
 
 
-def test_uneven_bathymetry_bounded_box_fp64():
-    w = inputs.BETA_BASIN_64.replace(name="steps_70x14x9", nx=70, ny=14, nz=9, depth=2700.0)
+@pytest.mark.parametrize("periodic", [False, True])
+def test_uneven_bathymetry_fp64(periodic):
+    """Random wet-layer counts with land everywhere, including next to periodic
+    seams in x and y (the velocity masks at the far end of a stencil read wet
+    counts one cell beyond the field halo)."""
+    w = inputs.BETA_BASIN_64.replace(name="steps_70x14x9", nx=70, ny=14, nz=9, depth=2700.0,
+                                     periodic_x=periodic, periodic_y=periodic, beta=0.0 if periodic else 2e-11)
     inp = inputs.make_inputs(w)
     rng = np.random.default_rng(5)
     kb = rng.integers(0, w.nz + 1, size=(w.ny, w.nx)).astype(np.int32)
