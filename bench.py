@@ -91,6 +91,46 @@ def run_gpu(w, precision, inp, steps, warmup):
     return elapsed, {k: v / max(n, 1) for k, v in stages.items()}, diag
 
 
+def run_ensemble(steps, warmup, n_members=64):
+    """64 seeded beta-plane basins of uneven sizes in FP32: batched stepping
+    (one launch per stage, graph-replayed, autotuned tiles) against stepping
+    each member alone with the same kernels."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2309_06662_amd import ocn
+
+    ws = inputs.ensemble_members(n_members)
+    ens = ocn.Ensemble(ws, "fp32")
+    tune = ens.autotune(trial_steps=2)
+    ens.step(warmup)
+    ens.synchronize()
+    t0 = time.perf_counter()
+    ens.step(steps)
+    ens.synchronize()
+    batched = time.perf_counter() - t0
+    with torch.cuda.stream(ens.stream):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for mem in ens.members:
+                ocn._check(ocn.lib().ocn_step(mem.handle, 1), "ocn_step")
+        ens.synchronize()
+        sequential = time.perf_counter() - t0
+    finite = all(m.diagnostics(allow_unstable=True)["nonfinite"] == 0 for m in ens.members)
+    cells = ens.cells
+    ens.close()
+    del ens
+    torch.cuda.empty_cache()
+    return {"members": n_members, "cells": cells, "precision": "fp32", "steps": steps,
+            "batched_ms_per_step": batched / steps * 1e3,
+            "batched_cell_updates_per_s": cells * steps / batched,
+            "sequential_ms_per_step": sequential / steps * 1e3,
+            "sequential_cell_updates_per_s": cells * steps / sequential,
+            "speedup_batched_over_sequential": sequential / batched,
+            "autotune": tune, "finite": finite}
+
+
 def roofline(w, precision, stage_ms):
     esize = 4 if precision == "fp32" else 8
     t = stage_ms["tendency"] * 1e-3
@@ -138,6 +178,7 @@ def main():
     ap.add_argument("--workload", default=inputs.LATLON_TWELFTH.name, choices=sorted(inputs.WORKLOADS))
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble measurement")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -163,6 +204,12 @@ def main():
         }
         print(f"[bench] {prec}: {ms:.3f} ms/step, stages {results[prec]['stage_ms']}, "
               f"finite={diag['nonfinite'] == 0}", file=sys.stderr, flush=True)
+
+    ens = None
+    if not args.no_ensemble:
+        ens = run_ensemble(args.steps, args.warmup)
+        print(f"[bench] ensemble: batched {ens['batched_ms_per_step']:.3f} ms/step, sequential "
+              f"{ens['sequential_ms_per_step']:.3f} ms/step, tiles {ens['autotune']}", file=sys.stderr, flush=True)
 
     main_rec = results["fp32"]
     roof, other = roofline(w, "fp32", main_rec["stage_ms"])
@@ -198,6 +245,8 @@ def main():
         line["fp64"] = {"value": r64["cell_updates_per_s"], "ms_per_step": r64["ms_per_step"], "sypd": r64["sypd"],
                         "stage_ms": r64["stage_ms"], "roofline": roofline(w, "fp64", r64["stage_ms"])[0]}
         line["fp32_speedup_over_fp64"] = r64["ms_per_step"] / main_rec["ms_per_step"]
+    if ens is not None:
+        line["ensemble"] = ens
     print(json.dumps(line), flush=True)
 
 

@@ -183,6 +183,63 @@ int ocn_diagnostics(ocn_state* state, ocn_diag* out);
 /* Wait for all work enqueued on the state's stream. */
 int ocn_synchronize(ocn_state* state);
 
+/* Batched ensembles (many independent basins stepped together). An ensemble
+ * holds n member states of possibly different grids but one ocn_params, laid
+ * out in one caller arena of ocn_ensemble_arena_bytes. ocn_ensemble_step
+ * advances every member with one launch of the tendency kernel and one of the
+ * column kernel for the whole ensemble, and one barotropic launch per group of
+ * fused substeps; after the first step (forward Euler) the launches of a step
+ * are captured once into a HIP graph on the ensemble's stream and replayed
+ * (no capture when the stream is NULL). Each member's arithmetic is the same
+ * as when it is stepped alone with the same tile settings, so results are
+ * bitwise identical to stepping the members one by one. Motivation: climate
+ * uncertainty needs ensembles of simulations (paper Sec. 3).
+ *
+ * ocn_ensemble_member returns a borrowed handle of member m for the state
+ * calls (set/get fields, diagnostics, checkpoints); do not destroy it.
+ * ocn_ensemble_set_tiles selects the tendency workgroup rows (4 or 8; 0 =
+ * precision default) and the barotropic substeps per launch (2..6; 0 =
+ * default); every choice gives bitwise-identical results. ocn_ensemble_autotune
+ * times trial_steps steps of each choice, keeps the fastest, restores the
+ * state it started from and reports the choice and its time per step. */
+typedef struct ocn_ensemble ocn_ensemble;
+int  ocn_ensemble_arena_bytes(const ocn_grid* const* grids, int32_t n, const ocn_params* params, size_t* bytes);
+int  ocn_ensemble_init(const ocn_grid* const* grids, int32_t n, const ocn_params* params, void* device_arena,
+                       size_t arena_bytes, void* hip_stream, ocn_ensemble** out);
+void ocn_ensemble_destroy(ocn_ensemble* ens);
+int  ocn_ensemble_member(ocn_ensemble* ens, int32_t m, ocn_state** member);
+int  ocn_ensemble_step(ocn_ensemble* ens, int32_t n);
+int  ocn_ensemble_set_tiles(ocn_ensemble* ens, int32_t tend_rows, int32_t baro_fuse);
+int  ocn_ensemble_autotune(ocn_ensemble* ens, int32_t trial_steps, int32_t* tend_rows, int32_t* baro_fuse,
+                           double* ms_per_step);
+
+/* Per-column closure network: Linear -> ReLU -> Linear -> ReLU -> Linear with
+ * BF16 operands on the matrix cores and FP32 accumulation, FP32 master weights
+ * and Adam; it maps a column's features to its vertical-diffusivity profile
+ * (paper Sec. 3 motivates learned parameterizations, Sec. 6 uses a
+ * vertical-mixing closure). Layer widths must be multiples of 8. Parameters
+ * are packed FP32: W1 (din x h1, row-major), b1, W2 (h1 x h2), b2, W3
+ * (h2 x dout), b3. Batches are device pointers to FP32 row-major matrices,
+ * rows <= max_batch: x (rows x din), targets and outputs (rows x dout).
+ * ocn_mlp_gradients returns the mean-squared loss sum (y - t)^2 / (2 rows dout)
+ * and its gradients (synchronises); ocn_mlp_train_step also applies one Adam
+ * step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr, and when
+ * loss is non-NULL synchronises to return the loss before the update.
+ * ocn_mlp_set_params resets the Adam moments. */
+typedef struct ocn_mlp ocn_mlp;
+int  ocn_mlp_arena_bytes(int32_t din, int32_t h1, int32_t h2, int32_t dout, int32_t max_batch, size_t* bytes);
+int  ocn_mlp_init(int32_t din, int32_t h1, int32_t h2, int32_t dout, int32_t max_batch, void* device_arena,
+                  size_t arena_bytes, void* hip_stream, ocn_mlp** out);
+void ocn_mlp_destroy(ocn_mlp* net);
+int  ocn_mlp_param_count(const ocn_mlp* net, size_t* count);
+int  ocn_mlp_set_params(ocn_mlp* net, const float* host, size_t count);
+int  ocn_mlp_get_params(ocn_mlp* net, float* host, size_t count);
+int  ocn_mlp_forward(ocn_mlp* net, const float* x_dev, int32_t rows, float* y_dev);
+int  ocn_mlp_gradients(ocn_mlp* net, const float* x_dev, const float* t_dev, int32_t rows, float* grads_host,
+                       size_t count, float* loss_host);
+int  ocn_mlp_train_step(ocn_mlp* net, const float* x_dev, const float* t_dev, int32_t rows, float lr,
+                        float* loss_host);
+
 /* Checkpoint and resume. ocn_checkpoint_bytes reports the size of a
  * checkpoint; ocn_checkpoint_save copies the state as stored on the device
  * (prognostic fields including halos, AB2 history, barotropic state and

@@ -51,7 +51,7 @@ def lib():
     if _lib is None:
         path = _build.LIB
         if (not os.path.exists(path)) or os.path.getmtime(path) < max(
-                os.path.getmtime(_build.SRC), os.path.getmtime(os.path.join(_build.HERE, "ocean_oracle.h"))):
+                [os.path.getmtime(f) for f in _build.SRCS] + [os.path.getmtime(os.path.join(_build.HERE, "ocean_oracle.h"))]):
             _build.build()
         L = C.CDLL(path)
         L.orc_create.restype = C.c_void_p
@@ -75,6 +75,10 @@ def lib():
         L.orc_neumaier_sum.restype = C.c_double
         L.orc_neumaier_sum.argtypes = [_D, C.c_int64]
         L.orc_column_zflux.argtypes = [C.c_int, _D, C.POINTER(C.c_int32), _D, _D]
+        L.orc_mlp_forward.argtypes = [_D, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int] + [_D] * 9
+        L.orc_mlp_backward.restype = C.c_double
+        L.orc_mlp_backward.argtypes = [_D, _D, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int] + [_D] * 12
+        L.orc_adam.argtypes = [_D, _D, _D, _D, C.c_int64, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
         _lib = L
     return _lib
 
@@ -203,3 +207,37 @@ def column_zflux(phi, wet, wface) -> np.ndarray:
     out = np.zeros(len(phi) + 1)
     lib().orc_column_zflux(len(phi), _dptr(phi), _iptr(wet), _dptr(wface), _dptr(out))
     return out
+
+
+def _c(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def mlp_forward(X, W1, b1, W2, b2, W3, b3):
+    """Network output and hidden activations: (Y, H1, H2)."""
+    X, W1, b1, W2, b2, W3, b3 = (_c(a) for a in (X, W1, b1, W2, b2, W3, b3))
+    n, din = X.shape
+    h1, h2, dout = W1.shape[1], W2.shape[1], W3.shape[1]
+    H1, H2, Y = np.zeros((n, h1)), np.zeros((n, h2)), np.zeros((n, dout))
+    lib().orc_mlp_forward(_dptr(X), n, din, h1, h2, dout, _dptr(W1), _dptr(b1), _dptr(W2), _dptr(b2), _dptr(W3),
+                          _dptr(b3), _dptr(H1), _dptr(H2), _dptr(Y))
+    return Y, H1, H2
+
+
+def mlp_backward(X, T, W1, b1, W2, b2, W3, b3):
+    """Mean-squared loss L = sum (Y - T)^2 / (2 n dout) and its gradients (gW1, gb1, gW2, gb2, gW3, gb3)."""
+    X, T, W1, b1, W2, b2, W3, b3 = (_c(a) for a in (X, T, W1, b1, W2, b2, W3, b3))
+    n, din = X.shape
+    h1, h2, dout = W1.shape[1], W2.shape[1], W3.shape[1]
+    grads = [np.zeros_like(a) for a in (W1, b1, W2, b2, W3, b3)]
+    loss = lib().orc_mlp_backward(_dptr(X), _dptr(T), n, din, h1, h2, dout, _dptr(W1), _dptr(b1), _dptr(W2),
+                                  _dptr(b2), _dptr(W3), _dptr(b3), *[_dptr(g) for g in grads])
+    return loss, grads
+
+
+def adam(p, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam update of float64 arrays p, m, v with gradient g at step t."""
+    for a in (p, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _c(g)
+    lib().orc_adam(_dptr(p), _dptr(g), _dptr(m), _dptr(v), p.size, int(t), lr, beta1, beta2, eps)

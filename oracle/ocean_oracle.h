@@ -74,6 +74,18 @@ double orc_neumaier_sum(const double* x, int64_t n);
 void   orc_column_zflux(int nz, const double* phi, const int32_t* wet,
                         const double* wface, double* flux);
 
+/* Closure network (mlp_oracle.c): row-major matrices, X n x din, W1 din x h1,
+ * W2 h1 x h2, W3 h2 x dout; Y = relu(relu(X W1 + b1) W2 + b2) W3 + b3. */
+void   orc_mlp_forward(const double* X, int n, int din, int h1, int h2, int dout, const double* W1,
+                       const double* b1, const double* W2, const double* b2, const double* W3, const double* b3,
+                       double* H1, double* H2, double* Y);
+double orc_mlp_backward(const double* X, const double* T, int n, int din, int h1, int h2, int dout,
+                        const double* W1, const double* b1, const double* W2, const double* b2, const double* W3,
+                        const double* b3, double* gW1, double* gb1, double* gW2, double* gb2, double* gW3,
+                        double* gb3);
+void   orc_adam(double* p, const double* g, double* m, double* v, int64_t n, int t, double lr, double beta1,
+                double beta2, double eps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,15 +83,15 @@ namespace ocn {
 // values shrinks by one cell on every side, so after s substeps the tile
 // interior is exact; the halo cells are recomputed redundantly instead of
 // exchanged. Every point carries the same arithmetic as the one-substep path.
-constexpr int FBX = 64, FBY = 16, FSMAX = 6;
+constexpr int FBX = kBaroTileX, FBY = kBaroTileY, FSMAX = 6;
 constexpr int FEW = FBX + 2 * FSMAX, FEH = FBY + 2 * FSMAX, FEN = FEW * FEH;
 constexpr int FT = 512, FQ = (FEN + FT - 1) / FT;
 
-__global__ __launch_bounds__(FT) void k_baro_fused(const DevState S, const double dtau, const int s,
-                                                   const int first, const int last) {
+__device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const int by, const double dtau,
+                                          const int s, const int first, const int last) {
     __shared__ double sE[FEN], sU[FEN], sV[FEN];
     const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * FBX, j0 = blockIdx.y * FBY;
+    const int i0 = bx * FBX, j0 = by * FBY;
     const int ew = FBX + 2 * s;  // extent of this launch's tile (row stride stays FEW)
     const int eh = FBY + 2 * s;
     const int nx = S.nx, ny = S.ny;
@@ -216,6 +216,32 @@ __global__ __launch_bounds__(FT) void k_baro_fused(const DevState S, const doubl
             S.sv[c] = aV[q];
         }
     }
+}
+
+__global__ __launch_bounds__(FT) void k_baro_fused(const DevState S, const double dtau, const int s,
+                                                   const int first, const int last) {
+    baro_tile(S, blockIdx.x, blockIdx.y, dtau, s, first, last);
+}
+
+// Ensemble: entry blockIdx.x of the table is (member, bx, by).
+__global__ __launch_bounds__(FT) void k_baro_fused_batched(const DevState* __restrict__ members,
+                                                           const int4* __restrict__ tiles, const double dtau,
+                                                           const int s, const int first, const int last) {
+    const int4 e = tiles[blockIdx.x];
+    baro_tile(members[e.x], e.y, e.z, dtau, s, first, last);
+}
+
+hipError_t launch_barotropic_batched(const DevState* members, const int4* tiles, int ntiles, int n_substeps,
+                                     int fuse, double dt, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    const int sub = std::max(2, std::min(fuse, FSMAX));
+    const double dtau = dt / n_substeps;
+    for (int m0 = 0; m0 < n_substeps; m0 += sub) {
+        const int ss = std::min(sub, n_substeps - m0);
+        hipLaunchKernelGGL(k_baro_fused_batched, dim3(ntiles), dim3(FT), 0, st, members, tiles, dtau, ss,
+                           (int)(m0 == 0), (int)(m0 + ss == n_substeps));
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_barotropic_fused(const DevState& s, hipStream_t st) {

@@ -34,14 +34,11 @@ __device__ __forceinline__ void store_wrapped2(const DevState& S, double* f, int
     for_each_image(S, i, j, S.h, [&](int x, int y) { f[idx2(S, x, y)] = val; });
 }
 
-// blockIdx.z: 0 = T, 1 = u, 2 = v
+// One block of 64 columns (bx, j) of one field: 0 = T, 1 = u, 2 = v.
 template <typename R>
-__global__ __launch_bounds__(CW) void k_column(const DevState S) {
-    extern __shared__ __align__(16) unsigned char smem_col[];
-    R* sd = reinterpret_cast<R*>(smem_col);  // nz * CW: the column, then its eliminated rhs, then the solution
+__device__ __forceinline__ void column_block(const DevState& S, R* sd, const int bx, const int j, const int field) {
     const int t = threadIdx.x;
-    const int i = blockIdx.x * CW + t, j = blockIdx.y;
-    const int field = blockIdx.z;
+    const int i = bx * CW + t;
     const int nz = S.nz;
     const bool live = i < S.nx;
     const int ic = live ? i : S.nx - 1;
@@ -160,6 +157,34 @@ __global__ __launch_bounds__(CW) void k_wfaces(const DevState S) {
     }
     S.scratch2d[idx2(S, i, j)] = W / area;
 }
+
+template <typename R>
+__global__ __launch_bounds__(CW) void k_column(const DevState S) {
+    extern __shared__ __align__(16) unsigned char smem_col[];
+    // nz * CW: the column, then its eliminated rhs, then the solution
+    column_block<R>(S, reinterpret_cast<R*>(smem_col), blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Ensemble: entry blockIdx.x of the table is (member, bx, j); blockIdx.y is the field.
+template <typename R>
+__global__ __launch_bounds__(CW) void k_column_batched(const DevState* __restrict__ members,
+                                                       const int4* __restrict__ tiles) {
+    extern __shared__ __align__(16) unsigned char smem_col[];
+    const int4 e = tiles[blockIdx.x];
+    column_block<R>(members[e.x], reinterpret_cast<R*>(smem_col), e.y, e.z, blockIdx.y);
+}
+
+template <typename R>
+hipError_t launch_column_batched(const DevState* members, const int4* tiles, int ntiles, int max_nz, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    const size_t lds = (size_t)max_nz * CW * sizeof(R);
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_column_batched<R>, dim3(ntiles, 3), dim3(CW), lds, st, members, tiles);
+    return hipGetLastError();
+}
+
+template hipError_t launch_column_batched<double>(const DevState*, const int4*, int, int, hipStream_t);
+template hipError_t launch_column_batched<float>(const DevState*, const int4*, int, int, hipStream_t);
 
 template <typename R>
 hipError_t launch_column(const DevState& s, hipStream_t st) {

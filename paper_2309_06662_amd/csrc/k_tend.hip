@@ -143,10 +143,10 @@ template <typename R> struct TendWaves;
 template <> struct TendWaves<float> { static constexpr int n = 4; };
 template <> struct TendWaves<double> { static constexpr int n = 2; };
 
-template <typename R>
-__global__ __launch_bounds__(TX * TendShape<R>::TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R>::n)))
-void k_tend(const DevState S, const int first, const int gx) {
-    constexpr int TY = TendShape<R>::TY;
+// One tile (bx, by) of one state. Called by the single-state kernel and by the
+// batched kernel that steps an ensemble of basins in one launch.
+template <typename R, int TY>
+__device__ __forceinline__ void tend_tile(const DevState& S, const int first, const int bx, const int by) {
     constexpr int NT = TX * TY;
     constexpr int LW = TX + 5, LH = TY + 5, LN = LW * LH;  // value tiles: points -2 .. +3 around the block
     constexpr int KW = TX + 6, KH = TY + 6, KN = KW * KH;  // wet counts: one more on the low side
@@ -158,8 +158,6 @@ void k_tend(const DevState S, const int first, const int gx) {
     __shared__ R sQv[NT], sQu[NT], sP[NT], sWm[NT];
 
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int bx = tile % gx, by = tile / gx;
     const int i0 = bx * (TX - 1), j0 = by * (TY - 1);
     const int pi = i0 - 1 + tx, pj = j0 - 1 + ty;
     const int nx = S.nx, ny = S.ny, nz = S.nz, h = S.h;
@@ -508,16 +506,49 @@ void k_tend(const DevState S, const int first, const int gx) {
     }
 }
 
+template <typename R, int TY>
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R>::n)))
+void k_tend(const DevState S, const int first, const int gx) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    tend_tile<R, TY>(S, first, tile % gx, tile / gx);
+}
+
+// Ensemble: entry b of the tile table names (member, bx, by); the host orders
+// the table so that each XCD receives contiguous tiles of a member.
+template <typename R, int TY>
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R>::n)))
+void k_tend_batched(const DevState* __restrict__ members, const int4* __restrict__ tiles, const int first) {
+    const int4 e = tiles[blockIdx.x];
+    tend_tile<R, TY>(members[e.x], first, e.y, e.z);
+}
+
+int tend_tile_rows(int precision_bytes, int ty_choice) {
+    if (ty_choice == 4 || ty_choice == 8) return ty_choice;
+    return precision_bytes == 4 ? TendShape<float>::TY : TendShape<double>::TY;
+}
+
 template <typename R>
 hipError_t launch_tendency(const DevState& s, int first, hipStream_t st) {
-    constexpr int TY = TendShape<R>::TY;
+    const int TY = tend_tile_rows(sizeof(R), s.tend_ty);
     const int gx = (s.nx + TX - 2) / (TX - 1);
     const int gy = (s.ny + TY - 2) / (TY - 1);
-    hipLaunchKernelGGL(k_tend<R>, dim3(gx * gy), dim3(TX, TY), 0, st, s, first, gx);
+    if (TY == 8) hipLaunchKernelGGL((k_tend<R, 8>), dim3(gx * gy), dim3(TX, 8), 0, st, s, first, gx);
+    else hipLaunchKernelGGL((k_tend<R, 4>), dim3(gx * gy), dim3(TX, 4), 0, st, s, first, gx);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_tendency_batched(const DevState* members, const int4* tiles, int ntiles, int ty, int first,
+                                   hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    if (ty == 8) hipLaunchKernelGGL((k_tend_batched<R, 8>), dim3(ntiles), dim3(TX, 8), 0, st, members, tiles, first);
+    else hipLaunchKernelGGL((k_tend_batched<R, 4>), dim3(ntiles), dim3(TX, 4), 0, st, members, tiles, first);
     return hipGetLastError();
 }
 
 template hipError_t launch_tendency<double>(const DevState&, int, hipStream_t);
 template hipError_t launch_tendency<float>(const DevState&, int, hipStream_t);
+template hipError_t launch_tendency_batched<double>(const DevState*, const int4*, int, int, int, hipStream_t);
+template hipError_t launch_tendency_batched<float>(const DevState*, const int4*, int, int, int, hipStream_t);
 
 }  // namespace ocn

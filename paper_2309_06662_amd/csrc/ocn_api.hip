@@ -37,6 +37,10 @@ constexpr double kPi = 3.14159265358979323846;
 
 }  // namespace
 
+namespace ocn {
+int set_error(int code, const char* msg) { return fail(code, msg); }
+}  // namespace ocn
+
 struct ocn_grid {
     ocn_grid_desc d;
     int nx, ny, nz, h;
@@ -627,6 +631,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         d.restore_inv = params->restore_tau > 0.0 ? 1.0 / params->restore_tau : 0.0;
         d.n_substeps = params->n_substeps;
         d.baro_fuse = params->baro_fuse == 0 ? 5 : params->baro_fuse;
+        d.tend_ty = 0;
 
         hipError_t e = hipMemsetAsync(device_arena, 0, P.total, s->st);
         if (e == hipSuccess) e = hipStreamSynchronize(s->st);
@@ -856,3 +861,302 @@ int ocn_synchronize(ocn_state* s) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Ensembles
+
+struct ocn_ensemble {
+    std::vector<ocn_state*> members;
+    ocn_params p{};
+    hipStream_t st = nullptr;
+    int esize = 8;
+    int max_nz = 1;
+    int first = 1;
+    int tend_ty = 0;   // 0 = precision default
+    int fuse = 5;
+    DevState* d_members = nullptr;
+    int4* d_tend = nullptr;
+    int4* d_col = nullptr;
+    int4* d_baro = nullptr;
+    int n_tend = 0, n_col = 0, n_baro = 0;
+    size_t cap_tend = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+struct EnsPlan {
+    std::vector<size_t> member_off, member_bytes;
+    size_t off_dev, off_tend, off_col, off_baro, total;
+    size_t cap_tend, cap_col, cap_baro;
+};
+
+size_t tend_tiles(const ocn_grid* g, int ty) {
+    return (size_t)((g->nx + 62) / 63) * (size_t)((g->ny + ty - 2) / (ty - 1));
+}
+
+int ens_plan(const ocn_grid* const* grids, int n, const ocn_params* params, EnsPlan& P) {
+    Layout L;
+    P.cap_tend = P.cap_col = P.cap_baro = 0;
+    for (int m = 0; m < n; ++m) {
+        const size_t b = make_plan(grids[m], params->precision).total;
+        P.member_off.push_back(L.add(b));
+        P.member_bytes.push_back(b);
+        P.cap_tend += tend_tiles(grids[m], 4);  // the larger of the two tile shapes
+        P.cap_col += (size_t)((grids[m]->nx + 63) / 64) * grids[m]->ny;
+        P.cap_baro += (size_t)((grids[m]->nx + ocn::kBaroTileX - 1) / ocn::kBaroTileX) *
+                      ((grids[m]->ny + ocn::kBaroTileY - 1) / ocn::kBaroTileY);
+    }
+    P.off_dev = L.add(n * sizeof(DevState));
+    P.off_tend = L.add(P.cap_tend * sizeof(int4));
+    P.off_col = L.add(P.cap_col * sizeof(int4));
+    P.off_baro = L.add(P.cap_baro * sizeof(int4));
+    P.total = L.total;
+    return OCN_OK;
+}
+
+// Host copy of the XCD dealing used by the single-state tendency kernel.
+int xcd_slot(int b, int nb) {
+    const int q = nb / 8, r = nb % 8;
+    const int x = b % 8, slot = b / 8;
+    return (x < r) ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
+}
+
+int ens_tables(ocn_ensemble* e) {
+    const int ty = ocn::tend_tile_rows(e->esize, e->tend_ty);
+    std::vector<int4> logical;
+    for (int m = 0; m < (int)e->members.size(); ++m) {
+        const ocn_grid* g = e->members[m]->g;
+        const int gx = (g->nx + 62) / 63, gy = (g->ny + ty - 2) / (ty - 1);
+        for (int by = 0; by < gy; ++by)
+            for (int bx = 0; bx < gx; ++bx) logical.push_back(make_int4(m, bx, by, 0));
+    }
+    const int nb = (int)logical.size();
+    if ((size_t)nb > e->cap_tend) return fail(OCN_E_INVALID, "tile table overflow");
+    std::vector<int4> hw(nb);
+    for (int b = 0; b < nb; ++b) hw[b] = logical[xcd_slot(b, nb)];
+    HIPCHK(hipMemcpyAsync(e->d_tend, hw.data(), nb * sizeof(int4), hipMemcpyHostToDevice, e->st));
+    e->n_tend = nb;
+    std::vector<int4> col, baro;
+    for (int m = 0; m < (int)e->members.size(); ++m) {
+        const ocn_grid* g = e->members[m]->g;
+        for (int j = 0; j < g->ny; ++j)
+            for (int bx = 0; bx < (g->nx + 63) / 64; ++bx) col.push_back(make_int4(m, bx, j, 0));
+        for (int by = 0; by < (g->ny + ocn::kBaroTileY - 1) / ocn::kBaroTileY; ++by)
+            for (int bx = 0; bx < (g->nx + ocn::kBaroTileX - 1) / ocn::kBaroTileX; ++bx)
+                baro.push_back(make_int4(m, bx, by, 0));
+    }
+    HIPCHK(hipMemcpyAsync(e->d_col, col.data(), col.size() * sizeof(int4), hipMemcpyHostToDevice, e->st));
+    HIPCHK(hipMemcpyAsync(e->d_baro, baro.data(), baro.size() * sizeof(int4), hipMemcpyHostToDevice, e->st));
+    e->n_col = (int)col.size();
+    e->n_baro = (int)baro.size();
+    // member states with the ensemble's tile settings
+    std::vector<DevState> ds;
+    for (ocn_state* s : e->members) {
+        s->d.tend_ty = e->tend_ty;
+        s->d.baro_fuse = e->fuse;
+        ds.push_back(s->d);
+    }
+    HIPCHK(hipMemcpyAsync(e->d_members, ds.data(), ds.size() * sizeof(DevState), hipMemcpyHostToDevice, e->st));
+    HIPCHK(hipStreamSynchronize(e->st));
+    return OCN_OK;
+}
+
+void drop_graph(ocn_ensemble* e) {
+    if (e->exec) (void)hipGraphExecDestroy(e->exec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    e->exec = nullptr;
+    e->graph = nullptr;
+}
+
+int ens_enqueue(ocn_ensemble* e, int first) {
+    const bool f32 = e->esize == 4;
+    const int ty = ocn::tend_tile_rows(e->esize, e->tend_ty);
+    HIPCHK(f32 ? ocn::launch_tendency_batched<float>(e->d_members, e->d_tend, e->n_tend, ty, first, e->st)
+               : ocn::launch_tendency_batched<double>(e->d_members, e->d_tend, e->n_tend, ty, first, e->st));
+    HIPCHK(ocn::launch_barotropic_batched(e->d_members, e->d_baro, e->n_baro, e->p.n_substeps, e->fuse, e->p.dt, e->st));
+    HIPCHK(f32 ? ocn::launch_column_batched<float>(e->d_members, e->d_col, e->n_col, e->max_nz, e->st)
+               : ocn::launch_column_batched<double>(e->d_members, e->d_col, e->n_col, e->max_nz, e->st));
+    return OCN_OK;
+}
+
+int ens_step(ocn_ensemble* e, int n) {
+    int rc;
+    for (int q = 0; q < n; ++q) {
+        if (e->first || !e->st) {
+            if ((rc = ens_enqueue(e, e->first))) return rc;
+        } else {
+            if (!e->exec) {
+                HIPCHK(hipStreamBeginCapture(e->st, hipStreamCaptureModeThreadLocal));
+                rc = ens_enqueue(e, 0);
+                hipGraph_t g = nullptr;
+                hipError_t ce = hipStreamEndCapture(e->st, &g);
+                if (rc) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return rc;
+                }
+                if (ce != hipSuccess) return fail(OCN_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+                e->graph = g;
+                HIPCHK(hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0));
+            }
+            HIPCHK(hipGraphLaunch(e->exec, e->st));
+        }
+        e->first = 0;
+        for (ocn_state* s : e->members) {
+            s->first = 0;
+            s->step += 1;
+            s->time += s->p.dt;
+        }
+    }
+    return OCN_OK;
+}
+
+}  // namespace
+
+int ocn_ensemble_arena_bytes(const ocn_grid* const* grids, int32_t n, const ocn_params* params, size_t* bytes) {
+    if (!grids || n < 1 || !bytes) return fail(OCN_E_INVALID, "grids, n >= 1 and bytes are required");
+    std::string why;
+    if (!valid_params(params, why)) return fail(OCN_E_INVALID, why);
+    for (int m = 0; m < n; ++m)
+        if (!grids[m]) return fail(OCN_E_INVALID, "NULL grid");
+    EnsPlan P;
+    ens_plan(grids, n, params, P);
+    *bytes = P.total;
+    return OCN_OK;
+}
+
+int ocn_ensemble_init(const ocn_grid* const* grids, int32_t n, const ocn_params* params, void* device_arena,
+                      size_t arena_bytes, void* hip_stream, ocn_ensemble** out) {
+    try {
+        if (!grids || n < 1 || !out || !device_arena) return fail(OCN_E_INVALID, "bad arguments");
+        std::string why;
+        if (!valid_params(params, why)) return fail(OCN_E_INVALID, why);
+        if (reinterpret_cast<uintptr_t>(device_arena) % 256) return fail(OCN_E_INVALID, "arena must be 256-byte aligned");
+        for (int m = 0; m < n; ++m)
+            if (!grids[m]) return fail(OCN_E_INVALID, "NULL grid");
+        EnsPlan P;
+        ens_plan(grids, n, params, P);
+        if (arena_bytes < P.total) return fail(OCN_E_NOMEM, "arena smaller than ocn_ensemble_arena_bytes");
+        ocn_ensemble* e = new ocn_ensemble();
+        e->p = *params;
+        e->st = static_cast<hipStream_t>(hip_stream);
+        e->esize = params->precision == OCN_FP32 ? 4 : 8;
+        e->fuse = params->baro_fuse < 2 ? 5 : params->baro_fuse;
+        unsigned char* A = static_cast<unsigned char*>(device_arena);
+        for (int m = 0; m < n; ++m) {
+            ocn_state* s = nullptr;
+            int rc = ocn_state_init(grids[m], params, A + P.member_off[m], P.member_bytes[m], hip_stream, &s);
+            if (rc) {
+                for (ocn_state* q : e->members) ocn_state_destroy(q);
+                delete e;
+                return rc;
+            }
+            e->members.push_back(s);
+            e->max_nz = std::max(e->max_nz, grids[m]->nz);
+        }
+        e->d_members = reinterpret_cast<DevState*>(A + P.off_dev);
+        e->d_tend = reinterpret_cast<int4*>(A + P.off_tend);
+        e->d_col = reinterpret_cast<int4*>(A + P.off_col);
+        e->d_baro = reinterpret_cast<int4*>(A + P.off_baro);
+        e->cap_tend = P.cap_tend;
+        int rc = ens_tables(e);
+        if (rc) {
+            ocn_ensemble_destroy(e);
+            return rc;
+        }
+        *out = e;
+        return OCN_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(OCN_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(OCN_E_INVALID, "unexpected error");
+    }
+}
+
+void ocn_ensemble_destroy(ocn_ensemble* e) {
+    if (!e) return;
+    if (e->st) (void)hipStreamSynchronize(e->st);
+    drop_graph(e);
+    for (ocn_state* s : e->members) ocn_state_destroy(s);
+    delete e;
+}
+
+int ocn_ensemble_member(ocn_ensemble* e, int32_t m, ocn_state** member) {
+    if (!e || !member || m < 0 || m >= (int)e->members.size()) return fail(OCN_E_INVALID, "bad member index");
+    *member = e->members[m];
+    return OCN_OK;
+}
+
+int ocn_ensemble_step(ocn_ensemble* e, int32_t n) {
+    if (!e) return fail(OCN_E_INVALID, "ensemble must not be NULL");
+    if (n < 0) return fail(OCN_E_INVALID, "n must be >= 0");
+    // a member set to forward Euler (for example after loading a checkpoint
+    // taken at step 0) makes the next ensemble step a first step
+    for (ocn_state* s : e->members)
+        if (s->first) e->first = 1;
+    return ens_step(e, n);
+}
+
+int ocn_ensemble_set_tiles(ocn_ensemble* e, int32_t tend_rows, int32_t baro_fuse) {
+    if (!e) return fail(OCN_E_INVALID, "ensemble must not be NULL");
+    if (!(tend_rows == 0 || tend_rows == 4 || tend_rows == 8)) return fail(OCN_E_INVALID, "tend_rows must be 0, 4 or 8");
+    if (!(baro_fuse == 0 || (baro_fuse >= 2 && baro_fuse <= 6))) return fail(OCN_E_INVALID, "baro_fuse must be 0 or 2..6");
+    if (e->st) HIPCHK(hipStreamSynchronize(e->st));
+    drop_graph(e);
+    e->tend_ty = tend_rows;
+    e->fuse = baro_fuse == 0 ? 5 : baro_fuse;
+    return ens_tables(e);
+}
+
+int ocn_ensemble_autotune(ocn_ensemble* e, int32_t trial_steps, int32_t* tend_rows, int32_t* baro_fuse,
+                          double* ms_per_step) {
+    if (!e || trial_steps < 1) return fail(OCN_E_INVALID, "ensemble and trial_steps >= 1 are required");
+    if (!e->st) return fail(OCN_E_UNSUPPORTED, "autotuning needs a non-default stream");
+    // save every member so the trials leave the ensemble where it was
+    std::vector<std::vector<unsigned char>> saved(e->members.size());
+    for (size_t m = 0; m < e->members.size(); ++m) {
+        size_t nb = 0;
+        int rc = ocn_checkpoint_bytes(e->members[m], &nb);
+        if (rc) return rc;
+        saved[m].resize(nb);
+        if ((rc = ocn_checkpoint_save(e->members[m], saved[m].data(), nb))) return rc;
+    }
+    const int first0 = e->first;
+    const int rows_c[2] = {4, 8};
+    const int fuse_c[4] = {2, 3, 5, 6};
+    double best = 1e300;
+    int brow = 0, bfuse = 5;
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    int rc = OCN_OK;
+    for (int r : rows_c) {
+        for (int f : fuse_c) {
+            if ((rc = ocn_ensemble_set_tiles(e, r, f))) break;
+            e->first = 0;
+            if ((rc = ens_step(e, 1))) break;  // capture and warm up
+            HIPCHK(hipEventRecord(a, e->st));
+            if ((rc = ens_step(e, trial_steps))) break;
+            HIPCHK(hipEventRecord(b, e->st));
+            HIPCHK(hipEventSynchronize(b));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, a, b));
+            const double per = ms / trial_steps;
+            if (per < best) { best = per; brow = r; bfuse = f; }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    if ((rc = ocn_ensemble_set_tiles(e, brow, bfuse))) return rc;
+    for (size_t m = 0; m < e->members.size(); ++m)
+        if ((rc = ocn_checkpoint_load(e->members[m], saved[m].data(), saved[m].size()))) return rc;
+    e->first = first0;
+    for (ocn_state* s : e->members) s->first = first0;
+    if (tend_rows) *tend_rows = brow;
+    if (baro_fuse) *baro_fuse = bfuse;
+    if (ms_per_step) *ms_per_step = best;
+    return OCN_OK;
+}

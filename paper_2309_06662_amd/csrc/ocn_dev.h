@@ -71,6 +71,7 @@ struct DevState {
     double dt, chi, g, alpha, rho0, kappa, restore_inv;
     int n_substeps;
     int baro_fuse;  // substeps per barotropic launch
+    int tend_ty;    // rows of threads per tendency workgroup (4 or 8; 0 = precision default)
 };
 
 template <typename R>
@@ -111,5 +112,17 @@ template <typename R> hipError_t launch_colsum(const DevState& s, hipStream_t st
 template <typename R> hipError_t launch_diagnostics(const DevState& s, hipStream_t st);
 template <typename R> hipError_t launch_w_faces(const DevState& s, double* out_faces_dev, hipStream_t st);
 hipError_t launch_barotropic(const DevState& s, hipStream_t st);
+int tend_tile_rows(int precision_bytes, int ty_choice);
+
+// Batched launches over an ensemble: members is a device array of states,
+// tiles a device table of (member, tile x, tile y[, field]) entries.
+template <typename R>
+hipError_t launch_tendency_batched(const DevState* members, const int4* tiles, int ntiles, int ty, int first,
+                                   hipStream_t st);
+template <typename R>
+hipError_t launch_column_batched(const DevState* members, const int4* tiles, int ntiles, int max_nz, hipStream_t st);
+hipError_t launch_barotropic_batched(const DevState* members, const int4* tiles, int ntiles, int n_substeps,
+                                     int fuse, double dt, hipStream_t st);
+constexpr int kBaroTileX = 64, kBaroTileY = 16;
 
 }  // namespace ocn

@@ -154,6 +154,27 @@ LATLON_TWELFTH = Workload(
 WORKLOADS = {w.name: w for w in (BETA_BASIN_64, LATLON_QUARTER, LATLON_TWELFTH)}
 
 
+def ensemble_members(n: int = 64, seed: int = 0, precision_note: str = "fp32"):
+    """Members of a batched ensemble of closed beta-plane basins.
+
+    Member m draws five uniforms at counters 5m..5m+4 of the member stream:
+    nx in {128, 160, ..., 512}, ny in {128, 160, ..., 256}, nz in {32, 40, ..., 64},
+    wind amplitude tau0 ~ U(0.05, 0.2) N/m^2 and stratification scale ~ U(500, 1500) m.
+    Every basin has dx = dy = 50 km, a 4 km flat bottom, dt = 1200 s and 30
+    substeps; member m takes seed + m for its temperature noise.
+    """
+    u = uniform(seed, STREAM_MEMBERS, np.arange(5 * n, dtype=np.uint64)).reshape(n, 5)
+    out = []
+    for m in range(n):
+        nx = 128 + 32 * int(u[m, 0] * 13)
+        ny = 128 + 32 * int(u[m, 1] * 5)
+        nz = 32 + 8 * int(u[m, 2] * 5)
+        out.append(BETA_BASIN_64.replace(
+            name=f"member{m:02d}_{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, tau0=0.05 + 0.15 * float(u[m, 3]),
+            strat_scale=500.0 + 1000.0 * float(u[m, 4]), seed=seed + m))
+    return out
+
+
 def layer_thickness(w: Workload) -> np.ndarray:
     """Uniform layers over the full depth, bottom to top."""
     return np.full(w.nz, w.depth / w.nz, dtype=np.float64)

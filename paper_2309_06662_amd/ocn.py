@@ -31,7 +31,12 @@ ABI_FUNCTIONS = ["ocn_abi_version", "ocn_last_error", "ocn_grid_create", "ocn_gr
                  "ocn_state_arena_bytes", "ocn_state_init", "ocn_state_destroy", "ocn_set_field",
                  "ocn_get_field", "ocn_set_first_step", "ocn_get_first_step", "ocn_step",
                  "ocn_diagnostics", "ocn_synchronize", "ocn_stage_timing", "ocn_stage_times",
-                 "ocn_checkpoint_bytes", "ocn_checkpoint_save", "ocn_checkpoint_load"]
+                 "ocn_checkpoint_bytes", "ocn_checkpoint_save", "ocn_checkpoint_load",
+                 "ocn_ensemble_arena_bytes", "ocn_ensemble_init", "ocn_ensemble_destroy", "ocn_ensemble_member",
+                 "ocn_ensemble_step", "ocn_ensemble_set_tiles", "ocn_ensemble_autotune",
+                 "ocn_mlp_arena_bytes", "ocn_mlp_init", "ocn_mlp_destroy", "ocn_mlp_param_count",
+                 "ocn_mlp_set_params", "ocn_mlp_get_params", "ocn_mlp_forward", "ocn_mlp_gradients",
+                 "ocn_mlp_train_step"]
 
 
 class OcnError(RuntimeError):
@@ -93,7 +98,27 @@ def lib():
         L.ocn_checkpoint_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
         L.ocn_checkpoint_save.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
         L.ocn_checkpoint_load.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+        L.ocn_ensemble_arena_bytes.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(Params),
+                                               C.POINTER(C.c_size_t)]
+        L.ocn_ensemble_init.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(Params), C.c_void_p, C.c_size_t,
+                                        C.c_void_p, C.POINTER(C.c_void_p)]
+        L.ocn_ensemble_destroy.argtypes = [C.c_void_p]
+        L.ocn_ensemble_member.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]
+        L.ocn_ensemble_step.argtypes = [C.c_void_p, C.c_int32]
+        L.ocn_ensemble_set_tiles.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+        L.ocn_ensemble_autotune.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                            C.POINTER(C.c_double)]
         L.ocn_stage_timing.argtypes = [C.c_void_p, C.c_int32]
+        _F = C.POINTER(C.c_float)
+        L.ocn_mlp_arena_bytes.argtypes = [C.c_int32] * 5 + [C.POINTER(C.c_size_t)]
+        L.ocn_mlp_init.argtypes = [C.c_int32] * 5 + [C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]
+        L.ocn_mlp_destroy.argtypes = [C.c_void_p]
+        L.ocn_mlp_param_count.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
+        L.ocn_mlp_set_params.argtypes = [C.c_void_p, _F, C.c_size_t]
+        L.ocn_mlp_get_params.argtypes = [C.c_void_p, _F, C.c_size_t]
+        L.ocn_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
+        L.ocn_mlp_gradients.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, _F, C.c_size_t, _F]
+        L.ocn_mlp_train_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, _F]
         L.ocn_stage_times.argtypes = [C.c_void_p, _D, C.c_int32, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
@@ -244,3 +269,183 @@ class Model:
         if not (rc == OCN_E_UNSTABLE and allow_unstable):
             _check(rc, "ocn_diagnostics")
         return {name: getattr(d, name) for name, _ in Diag._fields_}
+
+
+class _Member(Model):
+    """A borrowed member state of an ensemble: the state calls of Model, no ownership."""
+
+    def __init__(self, ens, m, w):
+        self.w = w
+        self.precision = ens.precision
+        self.nx, self.ny, self.nz = w.nx, w.ny, w.nz
+        h = C.c_void_p()
+        _check(lib().ocn_ensemble_member(ens.handle, m, C.byref(h)), "ocn_ensemble_member")
+        self.handle = h
+        self._ens = ens
+
+    def close(self):
+        self.handle = None
+
+    __del__ = close
+
+    def step(self, n: int = 1):
+        raise RuntimeError("members advance through Ensemble.step")
+
+
+class Ensemble:
+    """Independent basins stepped together: one tendency launch and one column
+    launch per step for all members, barotropic launches per substep group, the
+    step replayed from a HIP graph on a dedicated stream."""
+
+    def __init__(self, workloads, precision: str = "fp32", inputs_list=None, device: str = "cuda:0",
+                 baro_fuse: int = 0):
+        import torch
+
+        self.precision = precision
+        self.workloads = list(workloads)
+        if inputs_list is None:
+            inputs_list = [_inputs.make_inputs(w) for w in self.workloads]
+        p0 = self.workloads[0]
+        for w in self.workloads:
+            if (w.dt, w.n_substeps, w.kappa, w.chi, w.g, w.alpha, w.rho0, w.t_ref, w.restore_days) != \
+                    (p0.dt, p0.n_substeps, p0.kappa, p0.chi, p0.g, p0.alpha, p0.rho0, p0.t_ref, p0.restore_days):
+                raise ValueError("ensemble members must share time step and physical parameters")
+        self.grids = [Grid(w, inp["dz"], inp["kbottom"]) for w, inp in zip(self.workloads, inputs_list)]
+        self._params = params(p0, precision, baro_fuse)
+        n = len(self.grids)
+        arr = (C.c_void_p * n)(*[g.handle.value for g in self.grids])
+        nbytes = C.c_size_t()
+        _check(lib().ocn_ensemble_arena_bytes(arr, n, C.byref(self._params), C.byref(nbytes)),
+               "ocn_ensemble_arena_bytes")
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.arena.data_ptr() + 255) // 256 * 256
+        self.stream = torch.cuda.Stream(self.device)   # graph capture needs a non-default stream
+        h = C.c_void_p()
+        _check(lib().ocn_ensemble_init(arr, n, C.byref(self._params), C.c_void_p(aligned), C.c_size_t(nbytes.value),
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(h)), "ocn_ensemble_init")
+        self.handle = h
+        self.members = [_Member(self, m, w) for m, w in enumerate(self.workloads)]
+        for mem, inp in zip(self.members, inputs_list):
+            for name in ("T0", "taux", "tauy", "tstar"):
+                if name in inp:
+                    mem.set("T" if name == "T0" else name, inp[name])
+
+    def close(self):
+        if getattr(self, "handle", None):
+            for mem in self.members:
+                mem.close()
+            lib().ocn_ensemble_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+    def step(self, n: int = 1):
+        _check(lib().ocn_ensemble_step(self.handle, int(n)), "ocn_ensemble_step")
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def set_tiles(self, tend_rows: int = 0, baro_fuse: int = 0):
+        _check(lib().ocn_ensemble_set_tiles(self.handle, int(tend_rows), int(baro_fuse)), "ocn_ensemble_set_tiles")
+
+    def autotune(self, trial_steps: int = 3) -> dict:
+        r, f, ms = C.c_int32(), C.c_int32(), C.c_double()
+        _check(lib().ocn_ensemble_autotune(self.handle, int(trial_steps), C.byref(r), C.byref(f), C.byref(ms)),
+               "ocn_ensemble_autotune")
+        return {"tend_rows": r.value, "baro_fuse": f.value, "ms_per_step": ms.value}
+
+    @property
+    def cells(self) -> int:
+        return sum(w.cells for w in self.workloads)
+
+
+class Mlp:
+    """The closure network (Linear-ReLU-Linear-ReLU-Linear) on the GPU's matrix
+    cores: BF16 products with FP32 accumulation, FP32 master weights and Adam.
+
+    Parameters travel as one packed FP32 vector: W1 (din x h1, row-major), b1,
+    W2 (h1 x h2), b2, W3 (h2 x dout), b3. Batches are FP32 torch tensors on the
+    device, rows x din in and rows x dout out.
+    """
+
+    def __init__(self, din: int, h1: int, h2: int, dout: int, max_batch: int, device: str = "cuda:0"):
+        import torch
+        L = lib()
+        self.shape = (din, h1, h2, dout)
+        self.max_batch = max_batch
+        self.device = torch.device(device)
+        nbytes = C.c_size_t()
+        _check(L.ocn_mlp_arena_bytes(din, h1, h2, dout, max_batch, C.byref(nbytes)), "ocn_mlp_arena_bytes")
+        self._arena = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        base = self._arena.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(L.ocn_mlp_init(din, h1, h2, dout, max_batch, C.c_void_p(aligned), nbytes.value,
+                              C.c_void_p(self.stream.cuda_stream), C.byref(h)), "ocn_mlp_init")
+        self._h = h
+        n = C.c_size_t()
+        _check(L.ocn_mlp_param_count(h, C.byref(n)), "ocn_mlp_param_count")
+        self.nparam = n.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.ocn_mlp_destroy(h)
+            self._h = None
+
+    def unpack(self, flat: np.ndarray):
+        din, h1, h2, dout = self.shape
+        sizes = [(din, h1), (h1,), (h1, h2), (h2,), (h2, dout), (dout,)]
+        out, o = [], 0
+        for sz in sizes:
+            n = int(np.prod(sz))
+            out.append(flat[o:o + n].reshape(sz))
+            o += n
+        return out
+
+    def set_params(self, flat: np.ndarray):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        assert a.size == self.nparam
+        _check(lib().ocn_mlp_set_params(self._h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size),
+               "ocn_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.nparam, dtype=np.float32)
+        _check(lib().ocn_mlp_get_params(self._h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size),
+               "ocn_mlp_get_params")
+        return a
+
+    def _dev(self, x, cols):
+        import torch
+        assert x.dtype == torch.float32 and x.is_contiguous() and x.device == self.device
+        assert x.dim() == 2 and x.shape[1] == cols and 1 <= x.shape[0] <= self.max_batch
+        return x.shape[0]
+
+    def forward(self, x):
+        import torch
+        rows = self._dev(x, self.shape[0])
+        y = torch.empty(rows, self.shape[3], dtype=torch.float32, device=self.device)
+        _check(lib().ocn_mlp_forward(self._h, C.c_void_p(x.data_ptr()), rows, C.c_void_p(y.data_ptr())),
+               "ocn_mlp_forward")
+        return y
+
+    def gradients(self, x, t):
+        rows = self._dev(x, self.shape[0])
+        assert self._dev(t, self.shape[3]) == rows
+        g = np.empty(self.nparam, dtype=np.float32)
+        loss = C.c_float()
+        _check(lib().ocn_mlp_gradients(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), rows,
+                                       g.ctypes.data_as(C.POINTER(C.c_float)), g.size, C.byref(loss)),
+               "ocn_mlp_gradients")
+        return float(loss.value), g
+
+    def train_step(self, x, t, lr: float, want_loss: bool = True):
+        rows = self._dev(x, self.shape[0])
+        assert self._dev(t, self.shape[3]) == rows
+        loss = C.c_float()
+        _check(lib().ocn_mlp_train_step(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), rows,
+                                        float(lr), C.byref(loss) if want_loss else None),
+               "ocn_mlp_train_step")
+        return float(loss.value) if want_loss else None

@@ -80,3 +80,35 @@ def test_arena_size_scales_with_precision_and_validates_params():
     assert L.ocn_synchronize(None) == ocn.OCN_E_INVALID
     assert L.ocn_state_init(h, C.byref(p), None, 0, None, C.byref(C.c_void_p())) == ocn.OCN_E_INVALID
     L.ocn_grid_destroy(h)
+
+
+def test_ensemble_arena_and_argument_checks():
+    L = ocn.lib()
+    ws = [inputs.BETA_BASIN_64.replace(nx=20 + 7 * m, ny=15 + 3 * m, nz=4 + m) for m in range(3)]
+    grids = [ocn.Grid(w, inputs.layer_thickness(w), inputs.wet_layers(w)) for w in ws]
+    arr = (C.c_void_p * 3)(*[g.handle.value for g in grids])
+    p = ocn.params(ws[0], "fp32")
+    total, one = C.c_size_t(), C.c_size_t()
+    assert L.ocn_ensemble_arena_bytes(arr, 3, C.byref(p), C.byref(total)) == 0
+    parts = 0
+    for g in grids:
+        assert L.ocn_state_arena_bytes(g.handle, C.byref(p), C.byref(one)) == 0
+        parts += one.value
+    assert total.value > parts  # members plus the member table and tile tables
+    assert L.ocn_ensemble_arena_bytes(arr, 0, C.byref(p), C.byref(total)) == ocn.OCN_E_INVALID
+    bad = (C.c_void_p * 2)(grids[0].handle.value, None)
+    assert L.ocn_ensemble_arena_bytes(bad, 2, C.byref(p), C.byref(total)) == ocn.OCN_E_INVALID
+    assert L.ocn_ensemble_step(None, 1) == ocn.OCN_E_INVALID
+    assert L.ocn_ensemble_set_tiles(None, 4, 2) == ocn.OCN_E_INVALID
+
+
+def test_ensemble_members_recipe():
+    ms = inputs.ensemble_members(64, seed=0)
+    assert len(ms) == 64
+    assert all(128 <= m.nx <= 512 and m.nx % 32 == 0 for m in ms)
+    assert all(128 <= m.ny <= 256 and m.ny % 32 == 0 for m in ms)
+    assert all(32 <= m.nz <= 64 and m.nz % 8 == 0 for m in ms)
+    assert all(0.05 <= m.tau0 <= 0.2 and 500 <= m.strat_scale <= 1500 for m in ms)
+    total = sum(m.cells for m in ms)
+    assert 1.0e8 < total < 3.0e8
+    assert ms == inputs.ensemble_members(64, seed=0)
