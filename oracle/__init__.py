@@ -15,7 +15,7 @@ from . import build as _build
 ORC_U, ORC_V, ORC_T, ORC_ETA, ORC_UBT, ORC_VBT = 0, 1, 2, 3, 4, 5
 ORC_ETA_MEAN, ORC_UBT_MEAN, ORC_VBT_MEAN, ORC_W = 6, 7, 8, 9
 ORC_GU_PREV, ORC_GV_PREV, ORC_GT_PREV = 10, 11, 12
-ORC_TAUX, ORC_TAUY, ORC_TSTAR, ORC_P = 13, 14, 15, 16
+ORC_TAUX, ORC_TAUY, ORC_TSTAR, ORC_P, ORC_KAPPA = 13, 14, 15, 16, 17
 TERM_ADV, TERM_COR, TERM_PGF, TERM_WIND, TERM_RESTORE, TERM_ALL = 1, 2, 4, 8, 16, 31
 NDIAG = 16
 DIAG_NAMES = ["step", "time", "tracer_content", "volume", "volume_mean", "kinetic_energy",
@@ -25,8 +25,8 @@ DIAG_NAMES = ["step", "time", "tracer_content", "volume", "volume_mean", "kineti
 FIELD_IDS = {"u": ORC_U, "v": ORC_V, "T": ORC_T, "eta": ORC_ETA, "U": ORC_UBT, "V": ORC_VBT,
              "eta_mean": ORC_ETA_MEAN, "U_mean": ORC_UBT_MEAN, "V_mean": ORC_VBT_MEAN,
              "w": ORC_W, "gu_prev": ORC_GU_PREV, "gv_prev": ORC_GV_PREV, "gt_prev": ORC_GT_PREV,
-             "taux": ORC_TAUX, "tauy": ORC_TAUY, "tstar": ORC_TSTAR, "p": ORC_P}
-FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "p"}
+             "taux": ORC_TAUX, "tauy": ORC_TAUY, "tstar": ORC_TSTAR, "p": ORC_P, "kappa": ORC_KAPPA}
+FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "p", "kappa"}
 
 
 class OrcDesc(C.Structure):
@@ -75,6 +75,8 @@ def lib():
         L.orc_neumaier_sum.restype = C.c_double
         L.orc_neumaier_sum.argtypes = [_D, C.c_int64]
         L.orc_column_zflux.argtypes = [C.c_int, _D, C.POINTER(C.c_int32), _D, _D]
+        L.orc_closure_features.argtypes = [C.c_void_p, C.c_int, _D, _D, _D]
+        L.orc_closure_kappa.argtypes = [C.c_void_p, _D, C.c_double, _D]
         L.orc_mlp_forward.argtypes = [_D, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int] + [_D] * 9
         L.orc_mlp_backward.restype = C.c_double
         L.orc_mlp_backward.argtypes = [_D, _D, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int] + [_D] * 12
@@ -141,6 +143,9 @@ class OracleModel:
         return (self.nz, self.ny, self.nx) if name in FIELDS_3D else (self.ny, self.nx)
 
     def set(self, name: str, arr: np.ndarray):
+        if name == "kappa" and arr is None:  # back to the constant diffusivity
+            lib().orc_set_field(self._h, ORC_KAPPA, None)
+            return
         a = np.ascontiguousarray(arr, dtype=np.float64).reshape(self._shape(name))
         if lib().orc_set_field(self._h, FIELD_IDS[name], _dptr(a)) != 0:
             raise ValueError(name)
@@ -166,6 +171,22 @@ class OracleModel:
         out = np.zeros(NDIAG, dtype=np.float64)
         lib().orc_diagnostics(self._h, _dptr(out))
         return dict(zip(DIAG_NAMES, out.tolist()))
+
+    def closure_features(self, din: int, mean=None, std=None) -> np.ndarray:
+        """Per-column network inputs, (ny*nx) x din (feature order in ocean_oracle.c)."""
+        mean = np.zeros(din) if mean is None else _c(mean)
+        std = np.ones(din) if std is None else _c(std)
+        X = np.zeros((self.ny * self.nx, din))
+        if lib().orc_closure_features(self._h, din, _dptr(mean), _dptr(std), _dptr(X)) != 0:
+            raise ValueError("din must be at least 4 nz + 3")
+        return X
+
+    def closure_kappa(self, Y, kappa0: float) -> np.ndarray:
+        """Face diffusivity [nz, ny, nx] from network outputs Y ((ny*nx) x nz, log10 kappa at centres)."""
+        Y = _c(Y).reshape(self.ny * self.nx, self.nz)
+        kw = np.zeros((self.nz, self.ny, self.nx))
+        lib().orc_closure_kappa(self._h, _dptr(Y), kappa0, _dptr(kw))
+        return kw
 
     def tendencies(self, terms: int = TERM_ALL):
         shape = (self.nz, self.ny, self.nx)

@@ -39,6 +39,7 @@ struct orc_model {
     double *gu_prev, *gv_prev, *gt_prev;      /* AB2 history */
     double *eta_mean, *U_mean, *V_mean;       /* substep averages of the last step */
     double *taux, *tauy, *tstar;              /* surface forcing (N/m^2, N/m^2, degC) */
+    double *kw;          /* prescribed diffusivity on z-faces (m^2/s), or NULL for the constant */
     int first_step;
     int64_t step;
     double time;
@@ -468,21 +469,25 @@ void orc_eval_tendencies(const orc_model* m, int terms, double* gu, double* gv, 
 /* ------------------------------------------------------------------------- */
 /* Backward-Euler vertical diffusion of one column (Sec. 5.2: vertically
  * implicit diffusion, backward Euler, tridiagonal solver). Face diffusivities:
- * kappa on interior wet faces of the tracer column; momentum takes the mean of
- * the two neighbouring tracer-face values on faces wet for that velocity point
- * (reading: the same constant acts on T, u and v). Zero flux at the bottom and
+ * kappa (the constant, or the prescribed face field) on interior wet faces of
+ * the tracer column; momentum takes the mean of the two neighbouring
+ * tracer-face values on faces wet for that velocity point (reading: the same
+ * diffusivity acts on T, u and v, unit Prandtl number). Zero flux at the bottom and
  * at the surface, so the column integral sum dz*phi is preserved. kind: 0 T,
  * 1 u, 2 v. */
+static double tracer_face_kappa(const orc_model* m, int i, int j, int kf) {
+    if (!w_wet(m, i, j, kf)) return 0.0;
+    return m->kw ? at3(m, m->kw, i, j, kf) : m->d.kappa;
+}
 static double face_kappa(const orc_model* m, int kind, int i, int j, int kf) {
-    const double kap = m->d.kappa;
     if (kf <= 0 || kf >= m->nz) return 0.0;
-    if (kind == 0) return w_wet(m, i, j, kf) ? kap : 0.0;
+    if (kind == 0) return tracer_face_kappa(m, i, j, kf);
     if (kind == 1) {
         if (!(u_wet(m, i, j, kf) && u_wet(m, i, j, kf - 1))) return 0.0;
-        return 0.5 * ((w_wet(m, i - 1, j, kf) ? kap : 0.0) + (w_wet(m, i, j, kf) ? kap : 0.0));
+        return 0.5 * (tracer_face_kappa(m, i - 1, j, kf) + tracer_face_kappa(m, i, j, kf));
     }
     if (!(v_wet(m, i, j, kf) && v_wet(m, i, j, kf - 1))) return 0.0;
-    return 0.5 * ((w_wet(m, i, j - 1, kf) ? kap : 0.0) + (w_wet(m, i, j, kf) ? kap : 0.0));
+    return 0.5 * (tracer_face_kappa(m, i, j - 1, kf) + tracer_face_kappa(m, i, j, kf));
 }
 
 static void implicit_column(const orc_model* m, int kind, int i, int j, const double* phistar, double* out) {
@@ -757,7 +762,7 @@ orc_model* orc_create(const orc_desc* d, const double* dz, const int32_t* kbotto
 void orc_destroy(orc_model* m) {
     if (!m) return;
     double* all[] = {m->dz, m->u, m->v, m->T, m->gu_prev, m->gv_prev, m->gt_prev, m->eta, m->U, m->V,
-                     m->eta_mean, m->U_mean, m->V_mean, m->taux, m->tauy, m->tstar};
+                     m->eta_mean, m->U_mean, m->V_mean, m->taux, m->tauy, m->tstar, m->kw};
     for (size_t q = 0; q < sizeof(all) / sizeof(all[0]); ++q) free(all[q]);
     free(m->kb);
     free(m);
@@ -788,6 +793,13 @@ static double* field_ptr(orc_model* m, int f, size_t* n) {
 /* Setting u or v stores the masked values (a dry velocity point is zero). */
 int orc_set_field(orc_model* m, int f, const double* src) {
     size_t n = 0;
+    if (f == ORC_KAPPA) {  /* NULL returns to the constant diffusivity */
+        const size_t n3 = (size_t)m->nx * m->ny * m->nz;
+        if (!src) { free(m->kw); m->kw = NULL; return 0; }
+        if (!m->kw) m->kw = (double*)malloc(sizeof(double) * n3);
+        memcpy(m->kw, src, sizeof(double) * n3);
+        return 0;
+    }
     double* p = field_ptr(m, f, &n);
     if (!p || !src) return -1;
     memcpy(p, src, sizeof(double) * n);
@@ -817,6 +829,12 @@ int orc_get_field(orc_model* m, int f, double* dst) {
         compute_p(m, m->T, dst);
         return 0;
     }
+    if (f == ORC_KAPPA) {  /* the tracer diffusivity in use on every face (0 where dry) */
+        for (int k = 0; k < m->nz; ++k)
+            for (int j = 0; j < m->ny; ++j)
+                for (int i = 0; i < m->nx; ++i) dst[id3(m, i, j, k)] = face_kappa(m, 0, i, j, k);
+        return 0;
+    }
     size_t n = 0;
     double* p = field_ptr(m, f, &n);
     if (!p) return -1;
@@ -826,3 +844,75 @@ int orc_get_field(orc_model* m, int f, double* dst) {
 
 void orc_set_first_step(orc_model* m, int first) { m->first_step = first ? 1 : 0; }
 int orc_get_first_step(const orc_model* m) { return m->first_step; }
+
+/* ------------------------------------------------------------------------- */
+/* Learned-closure plumbing: the per-column input vector of the network and the
+ * map from its output to face diffusivities. The paper motivates learned
+ * parameterizations (Sec. 3) and runs with a vertical-mixing closure (Sec. 6);
+ * the network replaces the diffusivity of the implicit vertical diffusion.
+ *
+ * Features of column (i, j), in this order (nz = number of layers):
+ *   [0, nz)        T at layer centres
+ *   [nz, 2nz)      u at centres, mean of the west and east faces
+ *   [2nz, 3nz)     v at centres, mean of the south and north faces
+ *   [3nz, 4nz)     N^2 = g alpha dT/dz on face k (slot k; the bottom face k = 0
+ *                  and faces without water on both sides count as dry)
+ *   4nz, 4nz+1     wind stress at the centre, means of the two faces' tau_x, tau_y
+ *   4nz+2          surface restoring flux dz_top (T* - T_top) / tau (K m/s), 0 when off
+ *   [4nz+3, din)   zero padding
+ * A wet entry is normalised, (x - mean) / std; dry entries (layers below the
+ * sea floor, dry faces, land columns) are 0. X is (ny nx) x din, row j nx + i. */
+int orc_closure_features(const orc_model* m, int din, const double* mean, const double* std, double* X) {
+    const int nz = m->nz;
+    if (din < 4 * nz + 3) return -1;
+    for (int j = 0; j < m->ny; ++j)
+        for (int i = 0; i < m->nx; ++i) {
+            double* x = X + id2(m, i, j) * (size_t)din;
+            for (int f = 0; f < din; ++f) x[f] = 0.0;
+            const int K = m->kb[id2(m, i, j)];
+            if (K == 0) continue;
+#define PUT(f, val) x[f] = ((val) - mean[f]) / std[f]
+            for (int k = nz - K; k < nz; ++k) {
+                PUT(k, at3(m, m->T, i, j, k));
+                PUT(nz + k, 0.5 * (at3(m, m->u, i, j, k) + at3(m, m->u, i + 1, j, k)));
+                PUT(2 * nz + k, 0.5 * (at3(m, m->v, i, j, k) + at3(m, m->v, i, j + 1, k)));
+                if (w_wet(m, i, j, k)) {
+                    const double dzc = 0.5 * (m->dz[k - 1] + m->dz[k]);
+                    PUT(3 * nz + k, m->d.g * m->d.alpha * (at3(m, m->T, i, j, k) - at3(m, m->T, i, j, k - 1)) / dzc);
+                }
+            }
+            PUT(4 * nz, 0.5 * (at2(m, m->taux, i, j) + at2(m, m->taux, i + 1, j)));
+            PUT(4 * nz + 1, 0.5 * (at2(m, m->tauy, i, j) + at2(m, m->tauy, i, j + 1)));
+            const double q = m->d.restore_tau > 0.0
+                                 ? m->dz[nz - 1] * (m->tstar[id2(m, i, j)] - at3(m, m->T, i, j, nz - 1)) / m->d.restore_tau
+                                 : 0.0;
+            PUT(4 * nz + 2, q);
+#undef PUT
+        }
+    return 0;
+}
+
+/* Network output -> face diffusivity. Y is (ny nx) x nz: log10 of the
+ * diffusivity at the centres of the column's layers. A centre value is
+ * 10^y clipped to [1e-7, 1] m^2/s, or kappa0 when y is not finite; face k
+ * (between layers k-1 and k) takes the mean of its two centres where both are
+ * wet, else 0. kw is nz x ny x nx like ORC_KAPPA (slot 0 unused, 0). */
+void orc_closure_kappa(const orc_model* m, const double* Y, double kappa0, double* kw) {
+    const int nz = m->nz;
+    for (int j = 0; j < m->ny; ++j)
+        for (int i = 0; i < m->nx; ++i) {
+            const double* y = Y + id2(m, i, j) * (size_t)nz;
+            for (int k = 0; k < nz; ++k) {
+                double v = 0.0;
+                if (w_wet(m, i, j, k)) {
+                    double c[2];
+                    for (int q = 0; q < 2; ++q) {
+                        const double yy = y[k - 1 + q];
+                        c[q] = isfinite(yy) ? fmin(1.0, fmax(1e-7, pow(10.0, yy))) : kappa0;
+                    }
+                    v = 0.5 * (c[0] + c[1]);
+                }
+                kw[id3(m, i, j, k)] = v;
+            }
+        }
+}

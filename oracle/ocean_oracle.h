@@ -44,7 +44,9 @@ enum {
     ORC_U = 0, ORC_V = 1, ORC_T = 2, ORC_ETA = 3, ORC_UBT = 4, ORC_VBT = 5,
     ORC_ETA_MEAN = 6, ORC_UBT_MEAN = 7, ORC_VBT_MEAN = 8, ORC_W = 9,
     ORC_GU_PREV = 10, ORC_GV_PREV = 11, ORC_GT_PREV = 12,
-    ORC_TAUX = 13, ORC_TAUY = 14, ORC_TSTAR = 15, ORC_P = 16
+    ORC_TAUX = 13, ORC_TAUY = 14, ORC_TSTAR = 15, ORC_P = 16,
+    ORC_KAPPA = 17   /* z-face diffusivity, nz*ny*nx, slot k = face between layers k-1 and k;
+                        setting NULL returns to the constant */
 };
 
 /* Tendency term selectors for orc_eval_tendencies. */
@@ -73,6 +75,10 @@ void   orc_thomas(int n, const double* a, const double* b, const double* c,
 double orc_neumaier_sum(const double* x, int64_t n);
 void   orc_column_zflux(int nz, const double* phi, const int32_t* wet,
                         const double* wface, double* flux);
+
+/* Closure inputs and outputs (see ocean_oracle.c for the feature order). */
+int    orc_closure_features(const orc_model* m, int din, const double* mean, const double* std, double* X);
+void   orc_closure_kappa(const orc_model* m, const double* Y, double kappa0, double* kw);
 
 /* Closure network (mlp_oracle.c): row-major matrices, X n x din, W1 din x h1,
  * W2 h1 x h2, W3 h2 x dout; Y = relu(relu(X W1 + b1) W2 + b2) W3 + b3. */
