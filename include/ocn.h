@@ -111,7 +111,11 @@ typedef enum {
     OCN_FIELD_TAUX = 13,      /* 2D zonal wind stress at u-points (N/m^2)           */
     OCN_FIELD_TAUY = 14,      /* 2D meridional wind stress at v-points (N/m^2)      */
     OCN_FIELD_TSTAR = 15,     /* 2D surface restoring temperature (degC)            */
-    OCN_FIELD_TREF = 16       /* nz reference profile of the stored T anomaly        */
+    OCN_FIELD_TREF = 16,      /* nz reference profile of the stored T anomaly        */
+    OCN_FIELD_KAPPA = 17      /* 3D tracer diffusivity on z-faces (m^2/s): slot k is
+                                 the face between layers k-1 and k; get returns 0 on
+                                 dry faces (and the constant when no closure is
+                                 attached); set only with a prescribed-field closure */
 } ocn_field;
 
 typedef struct ocn_diag {
@@ -240,6 +244,42 @@ int  ocn_mlp_gradients(ocn_mlp* net, const float* x_dev, const float* t_dev, int
 int  ocn_mlp_train_step(ocn_mlp* net, const float* x_dev, const float* t_dev, int32_t rows, float lr,
                         float* loss_host);
 
+/* Vertical-diffusivity closure (paper Sec. 5.2 implicit vertical diffusion;
+ * Sec. 3 motivates learned parameterizations, Sec. 6 runs with a
+ * vertical-mixing closure). With a closure attached the implicit diffusion
+ * uses a diffusivity per z-face and column: T on its own faces, u and v the
+ * mean of their two neighbouring columns' faces. Two modes:
+ *  - net == NULL: a prescribed field, set with ocn_set_field(OCN_FIELD_KAPPA)
+ *    (initialised to the constant kappa) or ocn_closure_kappa;
+ *  - net != NULL: at the start of every ocn_step the state's columns are fed
+ *    to the network (features as ocn_closure_features, normalised by norm:
+ *    din means then din standard deviations, host FP32) and its outputs mapped
+ *    as ocn_closure_kappa does; the network needs din >= 4 nz + 3 and
+ *    dout == nz, and its current weights are read at every step.
+ * The workspace (device, 256-byte aligned, ocn_closure_workspace_bytes) holds
+ * the face field and, with a network, its activations for every column; it
+ * must outlive the attachment. The network must outlive it too. The variable
+ * diffusivity solve needs 2 nz 64 element sizes <= 64 KiB. Ensembles and
+ * checkpoints do not carry a closure. */
+int ocn_closure_workspace_bytes(const ocn_state* state, const ocn_mlp* net, size_t* bytes);
+int ocn_closure_attach(ocn_state* state, const ocn_mlp* net, const float* norm, size_t norm_count,
+                       void* device_workspace, size_t workspace_bytes);
+int ocn_closure_detach(ocn_state* state);
+/* Network inputs of every column of the current state into x (device FP32,
+ * (ny nx) x din row-major, row j nx + i), din >= 4 nz + 3 and 64 (din + 1) 4
+ * bytes <= 64 KiB. Order: T (nz levels, bottom first), u and v averaged to
+ * the centre (nz each), N^2 = g alpha dT/dz on face k (nz; face 0 and dry
+ * faces 0), wind stress averaged to the centre (2), surface restoring flux
+ * dz_top (T* - T_top) / tau in K m/s (1, 0 when off), zeros. Wet entries are
+ * (x - mean) / std with norm_dev (device FP32, din means then din deviations)
+ * or raw when norm_dev is NULL; dry entries are 0. Asynchronous. */
+int ocn_closure_features(ocn_state* state, int32_t din, const float* norm_dev, float* x_dev);
+/* Network outputs (device FP32, (ny nx) rows of leading dimension ldy >= nz:
+ * log10 diffusivity at layer centres) to the attached face field: a centre
+ * value is 10^y clipped to [1e-7, 1] m^2/s, or the constant kappa where y is
+ * not finite; a wet face takes the mean of its two centres. Asynchronous. */
+int ocn_closure_kappa(ocn_state* state, const float* y_dev, int32_t ldy);
+
 /* Checkpoint and resume. ocn_checkpoint_bytes reports the size of a
  * checkpoint; ocn_checkpoint_save copies the state as stored on the device
  * (prognostic fields including halos, AB2 history, barotropic state and
@@ -254,12 +294,13 @@ int ocn_checkpoint_save(ocn_state* state, void* host, size_t bytes);
 int ocn_checkpoint_load(ocn_state* state, const void* host, size_t bytes);
 
 /* Per-stage timing with HIP events recorded on the state's stream. While
- * enabled (enable = 1), every ocn_step records an event before the tendency
- * kernel, after it, after the barotropic substeps and after the column kernel.
- * ocn_stage_times synchronises the stream, writes up to n accumulated stage
- * times in milliseconds (0 tendency, 1 barotropic substeps, 2 column solve and
- * correction) and the number of timed steps, then clears the accumulators.
- * Enabling or disabling also clears them. */
+ * enabled (enable = 1), every ocn_step records an event at its start, after
+ * the closure update, after the tendency kernel, after the barotropic
+ * substeps and after the column kernel. ocn_stage_times synchronises the
+ * stream, writes up to n accumulated stage times in milliseconds (0 tendency,
+ * 1 barotropic substeps, 2 column solve and correction, 3 closure update) and
+ * the number of timed steps, then clears the accumulators. Enabling or
+ * disabling also clears them. */
 int ocn_stage_timing(ocn_state* state, int32_t enable);
 int ocn_stage_times(ocn_state* state, double* ms, int32_t n, int64_t* steps);
 

@@ -115,6 +115,93 @@ __device__ __forceinline__ void column_block(const DevState& S, R* sd, const int
     store_wrapped2(S, field == 1 ? S.cu : S.cv, i, j, newsum);
 }
 
+// The same solve with a diffusivity that varies by face and column (a
+// prescribed field or the learned closure): the tridiagonal coefficients are
+// formed on the fly, a_k = -dt kappa_k / dzc_k on the wet face k below layer
+// k, c_k = a_{k+1}; the eliminated super-diagonal c' is kept in a second LDS
+// array. u and v take the mean of the two neighbouring tracer-face values.
+template <typename R>
+__device__ __forceinline__ void column_block_vk(const DevState& S, R* sd, R* sc, const int bx, const int j,
+                                                const int field) {
+    const int t = threadIdx.x;
+    const int i = bx * CW + t;
+    const int nz = S.nz;
+    const bool live = i < S.nx;
+    const int ic = live ? i : S.nx - 1;
+
+    const int kc = S.kb[idxk(S, ic, j)];
+    int K = kc;
+    if (field == 1) K = min(kc, S.kb[idxk(S, ic - 1, j)]);
+    if (field == 2) K = min(kc, S.kb[idxk(S, ic, j - 1)]);
+
+    const R* src = f3<R>(field == 0 ? S.ts : field == 1 ? S.us : S.vs) + idx3(S, ic, j, 0);
+    R* dst = f3<R>(field == 0 ? S.t : field == 1 ? S.u : S.v);
+    const R* dtr = static_cast<const R*>(S.dtr);
+    const R* kwf = static_cast<const R*>(S.kw);
+    const long long o0 = idx3(S, ic, j, 0);
+    const long long on = field == 1 ? idx3(S, ic - 1, j, 0) : idx3(S, ic, j - 1, 0);
+    const int kbot = nz - K;
+    const long long pl = S.plane3;
+    const R rdt = R(S.dt);
+
+    auto coef = [&](int k) -> R {  // a_k of face k, 0 unless the face is wet
+        if (k <= kbot || k >= nz) return R(0);
+        R kap = kwf[o0 + k * pl];
+        if (field != 0) kap = R(0.5) * (kwf[on + k * pl] + kap);
+        return -rdt * kap / R(S.dzc[k]);
+    };
+
+#pragma unroll 8
+    for (int k = 0; k < nz; ++k) sd[k * CW + t] = src[k * pl];
+
+    R dprev = R(0), cprev = R(0), ak = R(0);
+    for (int k = 0; k < nz; ++k) {
+        const R ck = coef(k + 1);
+        R rhs = R(S.dz[k]) * sd[k * CW + t];
+        if (field == 0) rhs += -ck * dtr[k * 4 + 2] - ak * dtr[k * 4 + 1];
+        const R rden = R(1) / (R(S.dz[k]) - ak - ck - ak * cprev);
+        const R cpk = ck * rden;
+        const R dk = (rhs - ak * dprev) * rden;
+        sd[k * CW + t] = dk;
+        sc[k * CW + t] = cpk;
+        dprev = dk;
+        cprev = cpk;
+        ak = ck;
+    }
+    R xnext = R(0);
+    double colsum = 0.0;
+    for (int k = nz - 1; k >= 0; --k) {
+        const R x = sd[k * CW + t] - sc[k * CW + t] * xnext;
+        xnext = x;
+        sd[k * CW + t] = x;
+        if (k >= kbot) colsum += double(S.dz[k]) * double(x);
+    }
+    if (!live) return;
+
+    if (field == 0) {
+        for (int k = 0; k < nz; ++k) {
+            const R x = sd[k * CW + t];
+            dst[idx3(S, i, j, k)] = x;
+            store_wrapped(S, dst, i, j, k, x);
+        }
+        return;
+    }
+    const double H = (field == 1) ? S.hu[idx2(S, i, j)] : S.hv[idx2(S, i, j)];
+    const double B = (field == 1) ? S.ubt[idx2(S, i, j)] : S.vbt[idx2(S, i, j)];
+    const double corr = (H > 0.0) ? (B - colsum) / H : 0.0;
+    double newsum = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        R val = R(0);
+        if (k >= kbot && H > 0.0) {
+            val = R(double(sd[k * CW + t]) + corr);
+            newsum += double(S.dz[k]) * double(val);
+        }
+        dst[idx3(S, i, j, k)] = val;
+        store_wrapped(S, dst, i, j, k, val);
+    }
+    store_wrapped2(S, field == 1 ? S.cu : S.cv, i, j, newsum);
+}
+
 // Column sums sum_k dz u m_u and sum_k dz v m_v of the stored velocities (used
 // after u or v is set from the host).
 template <typename R>
@@ -162,7 +249,11 @@ template <typename R>
 __global__ __launch_bounds__(CW) void k_column(const DevState S) {
     extern __shared__ __align__(16) unsigned char smem_col[];
     // nz * CW: the column, then its eliminated rhs, then the solution
-    column_block<R>(S, reinterpret_cast<R*>(smem_col), blockIdx.x, blockIdx.y, blockIdx.z);
+    R* sd = reinterpret_cast<R*>(smem_col);
+    if (S.kw)
+        column_block_vk<R>(S, sd, sd + S.nz * CW, blockIdx.x, blockIdx.y, blockIdx.z);
+    else
+        column_block<R>(S, sd, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // Ensemble: entry blockIdx.x of the table is (member, bx, j); blockIdx.y is the field.
@@ -188,7 +279,7 @@ template hipError_t launch_column_batched<float>(const DevState*, const int4*, i
 
 template <typename R>
 hipError_t launch_column(const DevState& s, hipStream_t st) {
-    const size_t lds = (size_t)s.nz * CW * sizeof(R);
+    const size_t lds = (size_t)s.nz * CW * sizeof(R) * (s.kw ? 2 : 1);
     if (lds > 64 * 1024) return hipErrorInvalidValue;  // per-workgroup LDS limit
     dim3 grid((s.nx + CW - 1) / CW, s.ny, 3);
     hipLaunchKernelGGL(k_column<R>, grid, dim3(CW), lds, st, s);

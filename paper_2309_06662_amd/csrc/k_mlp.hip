@@ -368,6 +368,31 @@ int backward(ocn_mlp* n, const float* t, int rows) {
 
 }  // namespace
 
+namespace ocn {
+
+void mlp_shape(const ::ocn_mlp* n, int* din, int* h1, int* h2, int* dout) {
+    *din = n->din; *h1 = n->h1; *h2 = n->h2; *dout = n->dout;
+}
+
+// Forward pass of the network over rows already in BF16, on the caller's
+// stream and buffers (no split-K, so no scratch is needed).
+hipError_t mlp_infer(const ::ocn_mlp* n, const uint16_t* Xb, int rows, uint16_t* H1b, uint16_t* H2b, float* Y,
+                     hipStream_t st) {
+    const float* b1 = n->params + (size_t)n->din * n->h1;
+    const float* b2 = b1 + n->h1 + (size_t)n->h1 * n->h2;
+    const float* b3 = b2 + n->h2 + (size_t)n->h2 * n->dout;
+    hipError_t e = gemm_bf16(gemm(Xb, n->W1b, H1b, rows, n->h1, n->din, n->din, n->h1, n->h1, 0, 0,
+                                  G_BIAS | G_RELU | G_OUT_BF16, b1, nullptr, 0, 1), nullptr, 0, st);
+    if (e != hipSuccess) return e;
+    e = gemm_bf16(gemm(H1b, n->W2b, H2b, rows, n->h2, n->h1, n->h1, n->h2, n->h2, 0, 0, G_BIAS | G_RELU | G_OUT_BF16,
+                       b2, nullptr, 0, 1), nullptr, 0, st);
+    if (e != hipSuccess) return e;
+    return gemm_bf16(gemm(H2b, n->W3b, Y, rows, n->dout, n->h2, n->h2, n->dout, n->dout, 0, 0, G_BIAS, b3, nullptr,
+                          0, 1), nullptr, 0, st);
+}
+
+}  // namespace ocn
+
 extern "C" {
 
 int ocn_mlp_arena_bytes(int32_t din, int32_t h1, int32_t h2, int32_t dout, int32_t max_batch, size_t* bytes) {

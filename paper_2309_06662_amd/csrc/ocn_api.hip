@@ -73,6 +73,13 @@ struct ocn_state {
     // host-side layout facts
     size_t ox3 = 0, ox2 = 0, oxk = 0;
     size_t n3 = 0, n2 = 0, nk = 0;  // padded element counts
+    // vertical-diffusivity closure (null net: prescribed field)
+    bool closure = false;
+    const ocn_mlp* net = nullptr;
+    int din = 0, h1 = 0, h2 = 0, dout = 0;
+    float* norm = nullptr;        // device: mean[din], std[din]
+    uint16_t *xb = nullptr, *h1b = nullptr, *h2b = nullptr;
+    float* y = nullptr;
 };
 
 namespace {
@@ -429,6 +436,10 @@ int set_field_t(ocn_state* s, int32_t f, const double* host) {
         s->tstar.assign(host, host + (size_t)g->nx * g->ny);
         return upload_tables<R>(s);
     }
+    case OCN_FIELD_KAPPA: {
+        if (!s->closure || s->net) return fail(OCN_E_STATE, "KAPPA is set only with a prescribed-field closure attached");
+        return set3<R>(s, d.kw, host, nullptr, 0);
+    }
     case OCN_FIELD_TREF: {
         if (s->t_set) return fail(OCN_E_STATE, "TREF can only be set before T");
         s->tref.assign(host, host + nz);
@@ -465,6 +476,22 @@ int get_field_t(ocn_state* s, int32_t f, double* host) {
         std::copy(s->tref.begin(), s->tref.end(), host);
         return OCN_OK;
     }
+    case OCN_FIELD_KAPPA: {  // tracer diffusivity on every z-face, 0 where the face is dry
+        const int nx = g->nx, ny = g->ny, nz = g->nz;
+        if (s->closure) {
+            int rc = get3<R>(s, d.kw, host, nullptr, nz);
+            if (rc) return rc;
+        }
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    double& v = host[((size_t)k * ny + j) * nx + i];
+                    const bool wet = k > nz - kb_at(g, i, j);
+                    if (!s->closure) v = s->p.kappa;
+                    if (!wet) v = 0.0;
+                }
+        return OCN_OK;
+    }
     case OCN_FIELD_W: {
         HIPCHK(ocn::launch_w_faces<R>(d, nullptr, s->st));
         const size_t n2 = (size_t)g->nx * g->ny;
@@ -479,7 +506,7 @@ int get_field_t(ocn_state* s, int32_t f, double* host) {
 size_t field_count(const ocn_grid* g, int32_t f) {
     const size_t n2 = (size_t)g->nx * g->ny, n3 = n2 * g->nz;
     switch (f) {
-    case OCN_FIELD_U: case OCN_FIELD_V: case OCN_FIELD_T:
+    case OCN_FIELD_U: case OCN_FIELD_V: case OCN_FIELD_T: case OCN_FIELD_KAPPA:
     case OCN_FIELD_GU_PREV: case OCN_FIELD_GV_PREV: case OCN_FIELD_GT_PREV: return n3;
     case OCN_FIELD_W: return n2 * (g->nz + 1);
     case OCN_FIELD_TREF: return g->nz;
@@ -702,12 +729,53 @@ int ocn_get_first_step(ocn_state* s, int32_t* first) {
 }
 
 
+namespace {
+
+// Learned closure: features of every column -> network -> face diffusivity.
+int closure_update(ocn_state* s) {
+    const bool f32 = s->esize == 4;
+    const int rows = s->g->nx * s->g->ny;
+    HIPCHK(f32 ? ocn::launch_features<float>(s->d, s->din, s->norm, s->xb, 1, s->st)
+               : ocn::launch_features<double>(s->d, s->din, s->norm, s->xb, 1, s->st));
+    HIPCHK(ocn::mlp_infer(s->net, s->xb, rows, s->h1b, s->h2b, s->y, s->st));
+    HIPCHK(f32 ? ocn::launch_kappa_map<float>(s->d, s->y, s->dout, s->p.kappa, s->st)
+               : ocn::launch_kappa_map<double>(s->d, s->y, s->dout, s->p.kappa, s->st));
+    return OCN_OK;
+}
+
+struct ClosurePlan {
+    size_t kw, norm, xb, h1b, h2b, y, total;
+};
+
+size_t up256(size_t x) { return (x + 255) / 256 * 256; }
+
+ClosurePlan closure_plan(const ocn_state* s, int din, int h1, int h2, int dout) {
+    ClosurePlan P{};
+    const size_t rows = (size_t)s->g->nx * s->g->ny;
+    size_t off = 0;
+    auto add = [&](size_t b) { size_t o = off; off = up256(off + b); return o; };
+    P.kw = add(s->n3 * s->esize);
+    if (din > 0) {
+        P.norm = add((size_t)2 * din * sizeof(float));
+        P.xb = add(rows * din * 2);
+        P.h1b = add(rows * h1 * 2);
+        P.h2b = add(rows * h2 * 2);
+        P.y = add(rows * dout * sizeof(float));
+    }
+    P.total = off;
+    return P;
+}
+
+}  // namespace
+
 int ocn_step(ocn_state* s, int32_t n) {
     if (!s) return fail(OCN_E_INVALID, "state must not be NULL");
     if (n < 0) return fail(OCN_E_INVALID, "n must be >= 0");
     const bool f32 = s->esize == 4;
     int rc;
     for (int q = 0; q < n; ++q) {
+        if (s->timing && (rc = record(s))) return rc;
+        if (s->closure && s->net && (rc = closure_update(s))) return rc;
         if (s->timing && (rc = record(s))) return rc;
         HIPCHK(f32 ? ocn::launch_tendency<float>(s->d, s->first, s->st) : ocn::launch_tendency<double>(s->d, s->first, s->st));
         if (s->timing && (rc = record(s))) return rc;
@@ -725,6 +793,84 @@ int ocn_step(ocn_state* s, int32_t n) {
     return OCN_OK;
 }
 
+int ocn_closure_workspace_bytes(const ocn_state* s, const ocn_mlp* net, size_t* bytes) {
+    if (!s || !bytes) return fail(OCN_E_INVALID, "state and bytes must not be NULL");
+    int din = 0, h1 = 0, h2 = 0, dout = 0;
+    if (net) ocn::mlp_shape(net, &din, &h1, &h2, &dout);
+    *bytes = closure_plan(s, din, h1, h2, dout).total;
+    return OCN_OK;
+}
+
+int ocn_closure_attach(ocn_state* s, const ocn_mlp* net, const float* norm, size_t norm_count, void* workspace,
+                       size_t bytes) {
+    if (!s || !workspace) return fail(OCN_E_INVALID, "state and workspace must not be NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(OCN_E_INVALID, "workspace must be 256-byte aligned");
+    const int nz = s->g->nz;
+    if ((size_t)2 * nz * 64 * s->esize > 64 * 1024)
+        return fail(OCN_E_UNSUPPORTED, "nz too large for the variable-diffusivity column solve");
+    int din = 0, h1 = 0, h2 = 0, dout = 0;
+    if (net) {
+        ocn::mlp_shape(net, &din, &h1, &h2, &dout);
+        if (dout != nz) return fail(OCN_E_INVALID, "network output width must equal nz");
+        if (din < 4 * nz + 3) return fail(OCN_E_INVALID, "network input width must be at least 4 nz + 3");
+        if (ocn::features_lds(din) > 64 * 1024) return fail(OCN_E_UNSUPPORTED, "network input too wide");
+        if (!norm || norm_count != (size_t)2 * din) return fail(OCN_E_INVALID, "norm must hold 2 din values");
+        for (int f = 0; f < din; ++f)
+            if (!std::isfinite(norm[f]) || !(norm[din + f] > 0.f) || !std::isfinite(norm[din + f]))
+                return fail(OCN_E_INVALID, "norm: means must be finite and deviations positive");
+    }
+    const ClosurePlan P = closure_plan(s, din, h1, h2, dout);
+    if (bytes < P.total) return fail(OCN_E_NOMEM, "workspace smaller than ocn_closure_workspace_bytes");
+    HIPCHK(hipStreamSynchronize(s->st));
+    unsigned char* W = static_cast<unsigned char*>(workspace);
+    const size_t o3 = ((size_t)s->g->h * s->d.p3 + s->ox3) * s->esize;
+    HIPCHK(s->esize == 4 ? ocn::launch_fill<float>(W + P.kw, (long long)s->n3, s->p.kappa, s->st)
+                         : ocn::launch_fill<double>(W + P.kw, (long long)s->n3, s->p.kappa, s->st));
+    s->d.kw = W + P.kw + o3;
+    s->closure = true;
+    s->net = net;
+    s->din = din; s->h1 = h1; s->h2 = h2; s->dout = dout;
+    if (net) {
+        s->norm = reinterpret_cast<float*>(W + P.norm);
+        s->xb = reinterpret_cast<uint16_t*>(W + P.xb);
+        s->h1b = reinterpret_cast<uint16_t*>(W + P.h1b);
+        s->h2b = reinterpret_cast<uint16_t*>(W + P.h2b);
+        s->y = reinterpret_cast<float*>(W + P.y);
+        HIPCHK(hipMemcpyAsync(s->norm, norm, (size_t)2 * din * sizeof(float), hipMemcpyHostToDevice, s->st));
+    }
+    HIPCHK(hipStreamSynchronize(s->st));
+    return OCN_OK;
+}
+
+int ocn_closure_detach(ocn_state* s) {
+    if (!s) return fail(OCN_E_INVALID, "state must not be NULL");
+    HIPCHK(hipStreamSynchronize(s->st));
+    s->closure = false;
+    s->net = nullptr;
+    s->d.kw = nullptr;
+    s->norm = nullptr; s->xb = s->h1b = s->h2b = nullptr; s->y = nullptr;
+    s->din = s->h1 = s->h2 = s->dout = 0;
+    return OCN_OK;
+}
+
+int ocn_closure_features(ocn_state* s, int32_t din, const float* norm_dev, float* x_dev) {
+    if (!s || !x_dev) return fail(OCN_E_INVALID, "state and x must not be NULL");
+    if (din < 4 * s->g->nz + 3) return fail(OCN_E_INVALID, "din must be at least 4 nz + 3");
+    if (ocn::features_lds(din) > 64 * 1024) return fail(OCN_E_UNSUPPORTED, "din too large");
+    HIPCHK(s->esize == 4 ? ocn::launch_features<float>(s->d, din, norm_dev, x_dev, 0, s->st)
+                         : ocn::launch_features<double>(s->d, din, norm_dev, x_dev, 0, s->st));
+    return OCN_OK;
+}
+
+int ocn_closure_kappa(ocn_state* s, const float* y_dev, int32_t ldy) {
+    if (!s || !y_dev) return fail(OCN_E_INVALID, "state and y must not be NULL");
+    if (!s->closure) return fail(OCN_E_STATE, "no closure attached");
+    if (ldy < s->g->nz) return fail(OCN_E_INVALID, "ldy must be at least nz");
+    HIPCHK(s->esize == 4 ? ocn::launch_kappa_map<float>(s->d, y_dev, ldy, s->p.kappa, s->st)
+                         : ocn::launch_kappa_map<double>(s->d, y_dev, ldy, s->p.kappa, s->st));
+    return OCN_OK;
+}
+
 int ocn_stage_timing(ocn_state* s, int32_t enable) {
     if (!s) return fail(OCN_E_INVALID, "state must not be NULL");
     HIPCHK(hipStreamSynchronize(s->st));
@@ -736,14 +882,16 @@ int ocn_stage_timing(ocn_state* s, int32_t enable) {
 int ocn_stage_times(ocn_state* s, double* ms, int32_t n, int64_t* steps) {
     if (!s || (!ms && n > 0) || n < 0) return fail(OCN_E_INVALID, "bad arguments");
     HIPCHK(hipStreamSynchronize(s->st));
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (size_t b = 0; b + 3 < s->events.size(); b += 4)
-        for (int q = 0; q < 3; ++q) {
+    // events per step: closure | tendency | barotropic | column
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (size_t b = 0; b + 4 < s->events.size(); b += 5)
+        for (int q = 0; q < 4; ++q) {
             float t = 0.f;
             HIPCHK(hipEventElapsedTime(&t, s->events[b + q], s->events[b + q + 1]));
             acc[q] += t;
         }
-    for (int q = 0; q < n && q < 3; ++q) ms[q] = acc[q];
+    const double order[4] = {acc[1], acc[2], acc[3], acc[0]};  // tendency, barotropic, column, closure
+    for (int q = 0; q < n && q < 4; ++q) ms[q] = order[q];
     if (steps) *steps = s->timed_steps;
     drop_events(s);
     return OCN_OK;

@@ -15,6 +15,8 @@
 #include <cstddef>
 #include <cstdint>
 
+struct ocn_mlp;
+
 namespace ocn {
 
 // Diagnostics slots reduced on the device.
@@ -63,6 +65,9 @@ struct DevState {
     void* thomas_cp;  // (nz + 1) * nz of the field type: Thomas c' per wet-layer count
     void* thomas_den; // (nz + 1) * nz: reciprocal Thomas pivots per wet-layer count
     void* thomas_a;   // nz: sub-diagonal -dt kappa / dzc_k of a wet face k
+    // vertical diffusivity on z-faces (3D of the field type, slot k = face
+    // between layers k-1 and k, with periodic images), or null for the constant
+    void* kw;
     // diagnostics scratch
     double* diag_part;  // blocks * DG_COUNT
     double* diag_out;   // DG_COUNT
@@ -109,6 +114,17 @@ __device__ __forceinline__ void for_each_image(const DevState& s, int i, int j, 
 template <typename R> hipError_t launch_tendency(const DevState& s, int first, hipStream_t st);
 template <typename R> hipError_t launch_column(const DevState& s, hipStream_t st);
 template <typename R> hipError_t launch_colsum(const DevState& s, hipStream_t st);
+// closure inputs/outputs (k_closure.hip)
+size_t features_lds(int din);
+template <typename R> hipError_t launch_fill(void* p, long long n, double v, hipStream_t st);
+template <typename R>
+hipError_t launch_features(const DevState& s, int din, const float* norm, void* out, int out_bf16, hipStream_t st);
+template <typename R>
+hipError_t launch_kappa_map(const DevState& s, const float* Y, int ldy, double kappa0, hipStream_t st);
+// closure network inference (k_mlp.hip): BF16 X (rows x din) -> FP32 Y (rows x dout)
+void mlp_shape(const ::ocn_mlp* net, int* din, int* h1, int* h2, int* dout);
+hipError_t mlp_infer(const ::ocn_mlp* net, const uint16_t* Xb, int rows, uint16_t* H1b, uint16_t* H2b, float* Y,
+                     hipStream_t st);
 template <typename R> hipError_t launch_diagnostics(const DevState& s, hipStream_t st);
 template <typename R> hipError_t launch_w_faces(const DevState& s, double* out_faces_dev, hipStream_t st);
 hipError_t launch_barotropic(const DevState& s, hipStream_t st);

@@ -23,8 +23,9 @@ OCN_FP64, OCN_FP32 = 0, 1
 OCN_CARTESIAN, OCN_LATLON = 0, 1
 
 FIELDS = {"u": 0, "v": 1, "T": 2, "eta": 3, "U": 4, "V": 5, "eta_mean": 6, "U_mean": 7, "V_mean": 8,
-          "w": 9, "gu_prev": 10, "gv_prev": 11, "gt_prev": 12, "taux": 13, "tauy": 14, "tstar": 15, "tref": 16}
-FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev"}
+          "w": 9, "gu_prev": 10, "gv_prev": 11, "gt_prev": 12, "taux": 13, "tauy": 14, "tstar": 15, "tref": 16,
+          "kappa": 17}
+FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "kappa"}
 
 # Functions declared in include/ocn.h.
 ABI_FUNCTIONS = ["ocn_abi_version", "ocn_last_error", "ocn_grid_create", "ocn_grid_destroy",
@@ -36,7 +37,8 @@ ABI_FUNCTIONS = ["ocn_abi_version", "ocn_last_error", "ocn_grid_create", "ocn_gr
                  "ocn_ensemble_step", "ocn_ensemble_set_tiles", "ocn_ensemble_autotune",
                  "ocn_mlp_arena_bytes", "ocn_mlp_init", "ocn_mlp_destroy", "ocn_mlp_param_count",
                  "ocn_mlp_set_params", "ocn_mlp_get_params", "ocn_mlp_forward", "ocn_mlp_gradients",
-                 "ocn_mlp_train_step"]
+                 "ocn_mlp_train_step", "ocn_closure_workspace_bytes", "ocn_closure_attach",
+                 "ocn_closure_detach", "ocn_closure_features", "ocn_closure_kappa"]
 
 
 class OcnError(RuntimeError):
@@ -119,6 +121,11 @@ def lib():
         L.ocn_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
         L.ocn_mlp_gradients.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, _F, C.c_size_t, _F]
         L.ocn_mlp_train_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, _F]
+        L.ocn_closure_workspace_bytes.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]
+        L.ocn_closure_attach.argtypes = [C.c_void_p, C.c_void_p, _F, C.c_size_t, C.c_void_p, C.c_size_t]
+        L.ocn_closure_detach.argtypes = [C.c_void_p]
+        L.ocn_closure_features.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+        L.ocn_closure_kappa.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
         L.ocn_stage_times.argtypes = [C.c_void_p, _D, C.c_int32, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
@@ -254,11 +261,51 @@ class Model:
         _check(lib().ocn_stage_timing(self.handle, int(bool(enable))), "ocn_stage_timing")
 
     def stage_times(self):
-        """Accumulated (tendency, barotropic, column) milliseconds and step count; clears them."""
-        ms = np.zeros(3)
+        """Accumulated per-stage milliseconds and step count; clears them."""
+        ms = np.zeros(4)
         n = C.c_int64()
-        _check(lib().ocn_stage_times(self.handle, ms.ctypes.data_as(_D), 3, C.byref(n)), "ocn_stage_times")
-        return {"tendency": ms[0], "barotropic": ms[1], "column": ms[2]}, int(n.value)
+        _check(lib().ocn_stage_times(self.handle, ms.ctypes.data_as(_D), 4, C.byref(n)), "ocn_stage_times")
+        return {"tendency": ms[0], "barotropic": ms[1], "column": ms[2], "closure": ms[3]}, int(n.value)
+
+    def attach_closure(self, net: Optional["Mlp"] = None, norm: Optional[np.ndarray] = None):
+        """Use a per-face diffusivity: a prescribed field (net None; set it with set("kappa", ...))
+        or the network net, normalising its inputs with norm = [means (din), stds (din)]."""
+        import torch
+        n = C.c_size_t()
+        nh = net._h if net is not None else None
+        _check(lib().ocn_closure_workspace_bytes(self.handle, nh, C.byref(n)), "ocn_closure_workspace_bytes")
+        self._closure_ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self._closure_ws.data_ptr() + 255) // 256 * 256
+        if net is not None:
+            self._norm = np.ascontiguousarray(norm, dtype=np.float32)
+            nptr, ncount = self._norm.ctypes.data_as(C.POINTER(C.c_float)), self._norm.size
+        else:
+            nptr, ncount = None, 0
+        self._closure_net = net
+        _check(lib().ocn_closure_attach(self.handle, nh, nptr, ncount, C.c_void_p(aligned), n.value),
+               "ocn_closure_attach")
+
+    def detach_closure(self):
+        _check(lib().ocn_closure_detach(self.handle), "ocn_closure_detach")
+        self._closure_net = None
+
+    def closure_features(self, din: int, norm: Optional[np.ndarray] = None):
+        """Network inputs of every column as a device FP32 tensor [(ny*nx), din]."""
+        import torch
+        x = torch.empty(self.nx * self.ny, din, dtype=torch.float32, device=self.device)
+        nd = None
+        if norm is not None:
+            nd = torch.from_numpy(np.ascontiguousarray(norm, dtype=np.float32)).to(self.device)
+        _check(lib().ocn_closure_features(self.handle, din, C.c_void_p(nd.data_ptr()) if nd is not None else None,
+                                          C.c_void_p(x.data_ptr())), "ocn_closure_features")
+        self.synchronize()
+        return x
+
+    def closure_kappa(self, y):
+        """Map network outputs (device FP32 [(ny*nx), ldy >= nz]) to the attached face field."""
+        assert y.dtype.is_floating_point and y.is_contiguous()
+        _check(lib().ocn_closure_kappa(self.handle, C.c_void_p(y.data_ptr()), y.shape[1]), "ocn_closure_kappa")
+        self.synchronize()
 
     def synchronize(self):
         _check(lib().ocn_synchronize(self.handle), "ocn_synchronize")
