@@ -83,13 +83,23 @@ namespace ocn {
 // values shrinks by one cell on every side, so after s substeps the tile
 // interior is exact; the halo cells are recomputed redundantly instead of
 // exchanged. Every point carries the same arithmetic as the one-substep path.
+// A tile's halo is its neighbours' interior, which they overwrite during the
+// same launch, so launches read one buffer of eta, U, V and write the other
+// (parity selects which); after an odd number of launches a copy kernel
+// returns the result to the primary buffers.
 constexpr int FBX = kBaroTileX, FBY = kBaroTileY, FSMAX = 6;
 constexpr int FEW = FBX + 2 * FSMAX, FEH = FBY + 2 * FSMAX, FEN = FEW * FEH;
 constexpr int FT = 512, FQ = (FEN + FT - 1) / FT;
 
 __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const int by, const double dtau,
-                                          const int s, const int first, const int last) {
+                                          const int s, const int first, const int last, const int parity) {
     __shared__ double sE[FEN], sU[FEN], sV[FEN];
+    const double* __restrict__ inE = parity ? S.eta2 : S.eta;
+    const double* __restrict__ inU = parity ? S.ubt2 : S.ubt;
+    const double* __restrict__ inV = parity ? S.vbt2 : S.vbt;
+    double* __restrict__ outE = parity ? S.eta : S.eta2;
+    double* __restrict__ outU = parity ? S.ubt : S.ubt2;
+    double* __restrict__ outV = parity ? S.vbt : S.vbt2;
     const int tid = threadIdx.x;
     const int i0 = bx * FBX, j0 = by * FBY;
     const int ew = FBX + 2 * s;  // extent of this launch's tile (row stride stays FEW)
@@ -126,9 +136,9 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
         const int ti = i0 - s + li, tj = j0 - s + lj;  // unwrapped position
         inner[q] = in_tile && li >= s && li < s + FBX && lj >= s && lj < s + FBY && ti < nx && tj < ny;
         if (e < FEN) {
-            sE[e] = inside ? S.eta[c] : 0.0;
-            sU[e] = inside ? S.ubt[c] : 0.0;
-            sV[e] = inside ? S.vbt[c] : 0.0;
+            sE[e] = inside ? inE[c] : 0.0;
+            sU[e] = inside ? inU[c] : 0.0;
+            sV[e] = inside ? inV[c] : 0.0;
         }
         aE[q] = (inner[q] && !first) ? S.se[c] : 0.0;
         aU[q] = (inner[q] && !first) ? S.su[c] : 0.0;
@@ -196,14 +206,14 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
         const int li = e % FEW, lj = e / FEW;
         const int gi = i0 - s + li, gj = j0 - s + lj;
         const long long c = gofs[q];
-        S.eta[c] = sE[e];
-        S.ubt[c] = sU[e];
-        S.vbt[c] = sV[e];
+        outE[c] = sE[e];
+        outU[c] = sU[e];
+        outV[c] = sV[e];
         for_each_image(S, gi, gj, S.h, [&](int x, int y) {
             const long long o = idx2(S, x, y);
-            S.eta[o] = sE[e];
-            S.ubt[o] = sU[e];
-            S.vbt[o] = sV[e];
+            outE[o] = sE[e];
+            outU[o] = sU[e];
+            outV[o] = sV[e];
         });
         if (last) {
             const double ns = double(S.n_substeps);
@@ -219,27 +229,56 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
 }
 
 __global__ __launch_bounds__(FT) void k_baro_fused(const DevState S, const double dtau, const int s,
-                                                   const int first, const int last) {
-    baro_tile(S, blockIdx.x, blockIdx.y, dtau, s, first, last);
+                                                   const int first, const int last, const int parity) {
+    baro_tile(S, blockIdx.x, blockIdx.y, dtau, s, first, last, parity);
+}
+
+// Second buffers back to the primary ones (whole padded arrays, halos included).
+__global__ __launch_bounds__(256) void k_baro_copyback(const DevState S) {
+    const long long o2 = (long long)S.h * S.p2 + S.ox2;
+    const long long n = (long long)S.p2 * (S.ny + 2 * S.h);
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    (S.eta - o2)[e] = (S.eta2 - o2)[e];
+    (S.ubt - o2)[e] = (S.ubt2 - o2)[e];
+    (S.vbt - o2)[e] = (S.vbt2 - o2)[e];
+}
+
+__global__ __launch_bounds__(256) void k_baro_copyback_batched(const DevState* __restrict__ members, const int m0) {
+    const DevState& S = members[m0 + blockIdx.y];
+    const long long o2 = (long long)S.h * S.p2 + S.ox2;
+    const long long n = (long long)S.p2 * (S.ny + 2 * S.h);
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+        (S.eta - o2)[e] = (S.eta2 - o2)[e];
+        (S.ubt - o2)[e] = (S.ubt2 - o2)[e];
+        (S.vbt - o2)[e] = (S.vbt2 - o2)[e];
+    }
 }
 
 // Ensemble: entry blockIdx.x of the table is (member, bx, by).
 __global__ __launch_bounds__(FT) void k_baro_fused_batched(const DevState* __restrict__ members,
                                                            const int4* __restrict__ tiles, const double dtau,
-                                                           const int s, const int first, const int last) {
+                                                           const int s, const int first, const int last,
+                                                           const int parity) {
     const int4 e = tiles[blockIdx.x];
-    baro_tile(members[e.x], e.y, e.z, dtau, s, first, last);
+    baro_tile(members[e.x], e.y, e.z, dtau, s, first, last, parity);
 }
 
-hipError_t launch_barotropic_batched(const DevState* members, const int4* tiles, int ntiles, int n_substeps,
-                                     int fuse, double dt, hipStream_t st) {
+hipError_t launch_barotropic_batched(const DevState* members, int n_members, const int4* tiles, int ntiles,
+                                     int n_substeps, int fuse, double dt, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     const int sub = std::max(2, std::min(fuse, FSMAX));
     const double dtau = dt / n_substeps;
-    for (int m0 = 0; m0 < n_substeps; m0 += sub) {
+    int parity = 0;
+    for (int m0 = 0; m0 < n_substeps; m0 += sub, parity ^= 1) {
         const int ss = std::min(sub, n_substeps - m0);
         hipLaunchKernelGGL(k_baro_fused_batched, dim3(ntiles), dim3(FT), 0, st, members, tiles, dtau, ss,
-                           (int)(m0 == 0), (int)(m0 + ss == n_substeps));
+                           (int)(m0 == 0), (int)(m0 + ss == n_substeps), parity);
+    }
+    if (parity) {  // the result sits in the second buffers
+        for (int m0 = 0; m0 < n_members; m0 += 65535)
+            hipLaunchKernelGGL(k_baro_copyback_batched, dim3(64, std::min(65535, n_members - m0)), dim3(256), 0, st,
+                               members, m0);
     }
     return hipGetLastError();
 }
@@ -248,10 +287,15 @@ hipError_t launch_barotropic_fused(const DevState& s, hipStream_t st) {
     const int sub = std::min(s.baro_fuse, FSMAX);
     dim3 grid((s.nx + FBX - 1) / FBX, (s.ny + FBY - 1) / FBY);
     const double dtau = s.dt / s.n_substeps;
-    for (int m0 = 0; m0 < s.n_substeps; m0 += sub) {
+    int parity = 0;
+    for (int m0 = 0; m0 < s.n_substeps; m0 += sub, parity ^= 1) {
         const int ss = std::min(sub, s.n_substeps - m0);
         hipLaunchKernelGGL(k_baro_fused, grid, dim3(FT), 0, st, s, dtau, ss, (int)(m0 == 0),
-                           (int)(m0 + ss == s.n_substeps));
+                           (int)(m0 + ss == s.n_substeps), parity);
+    }
+    if (parity) {  // the result sits in the second buffers
+        const long long n = (long long)s.p2 * (s.ny + 2 * s.h);
+        hipLaunchKernelGGL(k_baro_copyback, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s);
     }
     return hipGetLastError();
 }

@@ -126,7 +126,7 @@ struct Plan {
     size_t oxk, pk, nk;
     size_t nrow;  // metric rows
     size_t diag_blocks;
-    size_t off_f3[9], off_f2[20], off_kb, off_rows[5], off_dz, off_dzc, off_tref, off_dtr, off_cp, off_den, off_a;
+    size_t off_f3[9], off_f2[22], off_kb, off_rows[5], off_dz, off_dzc, off_tref, off_dtr, off_cp, off_den, off_a;
     size_t off_part, off_out;
     size_t total;
 };
@@ -626,15 +626,16 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         d.periodic_y = grid->d.periodic_y ? 1 : 0;
         d.latlon = grid->d.coords == OCN_LATLON;
         d.p3 = (int)P.p3; d.p2 = (int)P.p2; d.pk = (int)P.pk;
+        d.ox2 = (int)P.ox2;
         d.plane3 = (long long)P.p3 * (long long)P.rows;
         const size_t o3 = ((size_t)h * P.p3 + P.ox3) * P.esize;
         void** f3s[9] = {&d.u, &d.v, &d.t, &d.us, &d.vs, &d.ts, &d.gu, &d.gv, &d.gt};
         for (int q = 0; q < 9; ++q) *f3s[q] = A + P.off_f3[q] + o3;
-        double** f2s[20] = {&d.eta, &d.ubt, &d.vbt, &d.se, &d.su, &d.sv, &d.eta_mean, &d.ubt_mean, &d.vbt_mean,
+        double** f2s[22] = {&d.eta, &d.ubt, &d.vbt, &d.se, &d.su, &d.sv, &d.eta_mean, &d.ubt_mean, &d.vbt_mean,
                             &d.gU, &d.gV, &d.hu, &d.hv, &d.cu, &d.cv, &d.taux, &d.tauy, &d.tstar, &d.scratch2d,
-                            nullptr};
+                            &d.eta2, &d.ubt2, &d.vbt2};
         const size_t o2 = (size_t)h * P.p2 + P.ox2;
-        for (int q = 0; q < 19; ++q) *f2s[q] = reinterpret_cast<double*>(A + P.off_f2[q]) + o2;
+        for (int q = 0; q < 22; ++q) *f2s[q] = reinterpret_cast<double*>(A + P.off_f2[q]) + o2;
         d.kb = reinterpret_cast<int*>(A + P.off_kb) + ((size_t)(h + 1) * P.pk + P.oxk);
         double** rows[5] = {&d.dxc, &d.dxv, &d.area, &d.fcor, &d.metric};
         for (int q = 0; q < 5; ++q) *rows[q] = reinterpret_cast<double*>(A + P.off_rows[q]) + h;
@@ -1123,7 +1124,7 @@ int ens_enqueue(ocn_ensemble* e, int first) {
     const int ty = ocn::tend_tile_rows(e->esize, e->tend_ty);
     HIPCHK(f32 ? ocn::launch_tendency_batched<float>(e->d_members, e->d_tend, e->n_tend, ty, first, e->st)
                : ocn::launch_tendency_batched<double>(e->d_members, e->d_tend, e->n_tend, ty, first, e->st));
-    HIPCHK(ocn::launch_barotropic_batched(e->d_members, e->d_baro, e->n_baro, e->p.n_substeps, e->fuse, e->p.dt, e->st));
+    HIPCHK(ocn::launch_barotropic_batched(e->d_members, (int)e->members.size(), e->d_baro, e->n_baro, e->p.n_substeps, e->fuse, e->p.dt, e->st));
     HIPCHK(f32 ? ocn::launch_column_batched<float>(e->d_members, e->d_col, e->n_col, e->max_nz, e->st)
                : ocn::launch_column_batched<double>(e->d_members, e->d_col, e->n_col, e->max_nz, e->st));
     return OCN_OK;

@@ -35,6 +35,7 @@ struct DevState {
     int periodic_x, periodic_y, latlon;
     int p3;            // row pitch of 3D fields (elements of the field type)
     int p2;            // row pitch of 2D double fields
+    int ox2;           // offset of the interior in a 2D row (elements)
     int pk;            // row pitch of the int32 wet-layer counts
     long long plane3;  // (ny + 2h) * p3
     // 3D fields of the field type (double or float), interior origin
@@ -51,6 +52,7 @@ struct DevState {
     double *taux, *tauy;                 // wind stress
     double *tstar;                       // restoring target minus tref(top)
     double *scratch2d;                   // one 2D field of scratch
+    double *eta2, *ubt2, *vbt2;          // second buffers of the temporally blocked substeps
     // int32 wet layers per column counted from the surface, with a halo of hk
     // (periodic images wrapped, zero beyond walls)
     int* kb;
@@ -137,8 +139,8 @@ hipError_t launch_tendency_batched(const DevState* members, const int4* tiles, i
                                    hipStream_t st);
 template <typename R>
 hipError_t launch_column_batched(const DevState* members, const int4* tiles, int ntiles, int max_nz, hipStream_t st);
-hipError_t launch_barotropic_batched(const DevState* members, const int4* tiles, int ntiles, int n_substeps,
-                                     int fuse, double dt, hipStream_t st);
+hipError_t launch_barotropic_batched(const DevState* members, int n_members, const int4* tiles, int ntiles,
+                                     int n_substeps, int fuse, double dt, hipStream_t st);
 constexpr int kBaroTileX = 64, kBaroTileY = 16;
 
 }  // namespace ocn

@@ -7,12 +7,13 @@
   reached from the same inputs; FP32 output, so 1e-6 relative per column.
 * Output map: identical network outputs (including non-finite and clipped
   values) give the oracle's face field within 1e-14 (FP64) / 1e-6 (FP32).
-* Network mode end to end: the oracle chain (features, FP64 network on
-  BF16-rounded inputs and weights, map, step) against the GPU's BF16 network
-  inside its step. The hidden activations are rounded to BF16 on the GPU only,
-  which moves log10 kappa by about 1e-2 and kappa by about 2 percent; the
-  diffusive change per step is dt kappa / dz^2 ~ 1e-3 of the field here, so
-  the states agree to about 1e-5 of that: 1e-6 relative L2 is the bound.
+* Network mode end to end: the oracle chain (oracle features, the network
+  in the GPU's declared precision -- BF16 inputs, weights and hidden
+  activations, wide accumulation -- the oracle's output map and the oracle's
+  step) against the GPU's network inside its step. What remains is FP32
+  versus FP64 accumulation in the products and the rare BF16 rounding tie it
+  flips: kappa within 1e-3, states within 1e-6 relative L2. The plain FP64
+  network (no BF16 activations) stays within 5 percent in kappa.
 """
 import numpy as np
 import pytest
@@ -173,12 +174,21 @@ def test_network_closure_end_to_end():
     norm = np.concatenate([mean, std]).astype(np.float32)
     mean64, std64 = norm[:din].astype(np.float64), norm[din:].astype(np.float64)
 
+    W1, b1, W2, b2, W3, b3 = Pb
+
+    def bf16_network(X):
+        H1 = _bf16(np.maximum(_bf16(X) @ W1 + b1, 0.0))
+        H2 = _bf16(np.maximum(H1 @ W2 + b2, 0.0))
+        return H2 @ W3 + b3
+
     gpu = ocn.Model(w, "fp64", inp)
     gpu.attach_closure(net, norm)
     for step in range(3):
         X = ref.closure_features(din, mean64, std64)
-        Y, _, _ = oracle.mlp_forward(_bf16(X), *Pb)
-        kw = ref.closure_kappa(Y, w.kappa)
+        kw = ref.closure_kappa(bf16_network(X), w.kappa)
+        if step == 0:
+            Yp, _, _ = oracle.mlp_forward(_bf16(X), *Pb)
+            kp = ref.closure_kappa(Yp, w.kappa)
         ref.set("kappa", kw)
         ref.step(1)
         gpu.step(1)
@@ -186,5 +196,9 @@ def test_network_closure_end_to_end():
         m = kw != 0
         kerr = np.max(np.abs(kg[m] / kw[m] - 1.0))
         print(f"step {step + 1}: max kappa relative difference {kerr:.2e}", flush=True)
-        assert kerr <= 0.05
+        assert kerr <= 1e-3
+        if step == 0:
+            perr = np.max(np.abs(kg[m] / kp[m] - 1.0))
+            print(f"  vs the plain FP64 network: {perr:.2e}", flush=True)
+            assert perr <= 0.05
     _compare(ref, gpu, w, inp["kbottom"], 1e-6)

@@ -224,3 +224,50 @@ def test_rest_state_stays_at_rest_on_gpu():
         assert np.all(gpu.get(n) == 0.0), n
     T = gpu.get("T")
     assert np.all(T == T[:, :1, :1])
+
+
+def _worst_location(ref, gpu, name):
+    d = np.abs(gpu.get(name) - ref.get(name))
+    idx = np.unravel_index(np.argmax(d), d.shape)
+    return tuple(int(x) for x in idx), float(d[idx])
+
+
+@pytest.mark.parametrize("case", ["halo5", "nz100", "twelfth_window"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+def test_full_size_parameters_on_small_grids(case, precision, tol):
+    """The 1/12-degree configuration's halo (5), depth resolution (100 levels)
+    and grid spacing with its bathymetry, each on a grid the oracle steps in
+    seconds: a 96 x 72 x 100 window of the 1/12-degree basin at 180E, 50S."""
+    if case == "halo5":
+        w = small_latlon(nx=100, ny=40, nz=12, halo=5, dt=900.0, n_substeps=40)
+    elif case == "nz100":
+        w = small_latlon(nx=70, ny=30, nz=100, dt=900.0, n_substeps=40)
+    else:
+        T = inputs.LATLON_TWELFTH
+        ic, jc = 2160, 300
+        w = T.replace(name="twelfth_window_96x72x100", nx=96, ny=72, periodic_x=False,
+                      x0=T.x0 + (ic - 48) * T.dx, y0=T.y0 + (jc - 36) * T.dy)
+    ref, gpu, inp = _pair(w, precision)
+    ref.step(3)
+    gpu.step(3)
+    for n in ("u", "v", "T", "eta"):
+        loc, err = _worst_location(ref, gpu, n)
+        print(f"  {case} {precision} {n}: largest difference {err:.3e} at (k, j, i) = {loc}", flush=True)
+    errs = _compare(ref, gpu, w, inp["kbottom"], tol)
+    print(f"  {case} {precision}:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+
+
+def test_many_barotropic_tiles_fp64():
+    """More barotropic tiles than the GPU holds at once (2048 tiles of 64 x 16
+    columns): tiles that start late must still read their neighbours' values
+    from before the launch. 35 substeps in groups of 5 is an odd number of
+    launches, which ends in the second buffers and copies back."""
+    w = inputs.BETA_BASIN_64.replace(name="beta_2048x1024x2", nx=2048, ny=1024, nz=2, depth=1000.0,
+                                     dx=10e3, dy=10e3, dt=600.0, n_substeps=35)
+    ref, gpu, inp = _pair(w, "fp64")
+    ref.step(2)
+    gpu.step(2)
+    for n in ("U", "V", "eta", "u"):
+        loc, err = _worst_location(ref, gpu, n)
+        print(f"  many tiles {n}: largest difference {err:.3e} at {loc}", flush=True)
+    _compare(ref, gpu, w, inp["kbottom"], 1e-11)
