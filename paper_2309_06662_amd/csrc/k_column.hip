@@ -3,14 +3,17 @@
 // Backward-Euler vertical diffusion (paper Sec. 5.2: vertically implicit
 // diffusion with a tridiagonal solver) of T, u and v, one thread per column,
 // one wave per 64 adjacent columns so that every level of a field is read and
-// written as coalesced row segments. Elimination runs bottom to top with the
-// eliminated right-hand side kept in LDS; back-substitution runs top to bottom.
+// written as coalesced row segments.
 //
 // With a constant diffusivity the matrix of a column depends only on its number
 // of wet layers K (the wet layers of T, u and v columns all start at the
-// surface), so the eliminated super-diagonal c' and the pivots come from a
-// table indexed by K built once on the host. The temperature anomaly solve
-// carries the diffusion of the reference profile on its right-hand side.
+// surface), so the eliminated super-diagonal c' and the reciprocal pivots come
+// from tables indexed by K built once on the host. The whole column is held in
+// registers: the kernel is instantiated for a few level counts (NZB >= nz) and
+// every loop over levels is unrolled, so the column's nz loads are all in
+// flight at once and no LDS limits the number of resident waves. The
+// temperature anomaly solve carries the diffusion of the reference profile on
+// its right-hand side.
 //
 // For u and v the same kernel then applies the split-explicit correction
 // (paper Sec. 5.3): the depth mean of u** is replaced by U^{Ns}/H, using the
@@ -34,85 +37,103 @@ __device__ __forceinline__ void store_wrapped2(const DevState& S, double* f, int
     for_each_image(S, i, j, S.h, [&](int x, int y) { f[idx2(S, x, y)] = val; });
 }
 
+// Level-count buckets of the register-resident solve.
+constexpr int kNzBuckets[] = {16, 32, 48, 64, 80, 100, 128};
+constexpr int kMaxNz = 128;
+
+// Output of one solved column: T as is; u and v with the depth-mean
+// correction u = u** + (U^{Ns} - sum dz u**) / H on wet layers, which also
+// leaves the column sum sum_k dz u m_u of the stored result (it seeds the
+// vertical transport of the next step). Periodic images are written too.
+template <typename R, int NZB>
+__device__ __forceinline__ void column_store(const DevState& S, const R (&x)[NZB], const int i, const int j,
+                                             const int field, const int kbot, const double colsum) {
+    const int nz = S.nz;
+    R* dst = f3<R>(field == 0 ? S.t : field == 1 ? S.u : S.v);
+    if (field == 0) {
+#pragma unroll
+        for (int k = 0; k < NZB; ++k) {
+            if (k < nz) {
+                dst[idx3(S, i, j, k)] = x[k];
+                store_wrapped(S, dst, i, j, k, x[k]);
+            }
+        }
+        return;
+    }
+    const double H = (field == 1) ? S.hu[idx2(S, i, j)] : S.hv[idx2(S, i, j)];
+    const double B = (field == 1) ? S.ubt[idx2(S, i, j)] : S.vbt[idx2(S, i, j)];
+    const double corr = (H > 0.0) ? (B - colsum) / H : 0.0;
+    double newsum = 0.0;
+#pragma unroll
+    for (int k = 0; k < NZB; ++k) {
+        if (k < nz) {
+            R val = R(0);
+            if (k >= kbot && H > 0.0) {
+                val = R(double(x[k]) + corr);
+                newsum += double(S.dz[k]) * double(val);
+            }
+            dst[idx3(S, i, j, k)] = val;
+            store_wrapped(S, dst, i, j, k, val);
+        }
+    }
+    store_wrapped2(S, field == 1 ? S.cu : S.cv, i, j, newsum);
+}
+
 // One block of 64 columns (bx, j) of one field: 0 = T, 1 = u, 2 = v.
-template <typename R>
-__device__ __forceinline__ void column_block(const DevState& S, R* sd, const int bx, const int j, const int field) {
+template <typename R, int NZB>
+__device__ __forceinline__ void column_regs(const DevState& S, const int bx, const int j, const int field) {
     const int t = threadIdx.x;
     const int i = bx * CW + t;
     const int nz = S.nz;
-    const bool live = i < S.nx;
-    const int ic = live ? i : S.nx - 1;
+    const int ic = i < S.nx ? i : S.nx - 1;
 
     const int kc = S.kb[idxk(S, ic, j)];
     int K = kc;
     if (field == 1) K = min(kc, S.kb[idxk(S, ic - 1, j)]);
     if (field == 2) K = min(kc, S.kb[idxk(S, ic, j - 1)]);
+    const int kbot = nz - K;  // lowest wet layer
 
     const R* src = f3<R>(field == 0 ? S.ts : field == 1 ? S.us : S.vs) + idx3(S, ic, j, 0);
-    R* dst = f3<R>(field == 0 ? S.t : field == 1 ? S.u : S.v);
-    const R* cp = static_cast<const R* >(S.thomas_cp) + (long long)K * nz;
+    const R* cp = static_cast<const R*>(S.thomas_cp) + (long long)K * nz;
     const R* rden = static_cast<const R*>(S.thomas_den) + (long long)K * nz;  // reciprocal pivots
     const R* asub = static_cast<const R*>(S.thomas_a);
     const R* dtr = static_cast<const R*>(S.dtr);
-    const int kbot = nz - K;  // lowest wet layer
     const long long pl = S.plane3;
 
-    // Stage the column phi* in LDS: the loads are independent, so a wave keeps
-    // many rows in flight instead of waiting on one level at a time.
-#pragma unroll 8
-    for (int k = 0; k < nz; ++k) sd[k * CW + t] = src[k * pl];
+    R x[NZB];
+#pragma unroll
+    for (int k = 0; k < NZB; ++k) x[k] = (k < nz) ? src[k * pl] : R(0);
 
     // Elimination, bottom to top: d'_k = (dz_k phi*_k - a_k d'_{k-1}) / den_k.
     // Temperature is stored as T' = T - tref(k): diffusing T is diffusing T'
     // with dt dz L(tref) = -c_k (tref_{k+1} - tref_k) + a_k (tref_k - tref_{k-1})
     // added to its right-hand side.
     R dprev = R(0);
-    for (int k = 0; k < nz; ++k) {
-        R rhs = R(S.dz[k]) * sd[k * CW + t];
-        const R a = (k > kbot) ? asub[k] : R(0);  // face k wet: layers k-1 and k
-        if (field == 0) {
-            const R c = (k >= kbot && k < nz - 1) ? asub[k + 1] : R(0);
-            rhs += -c * dtr[k * 4 + 2] - a * dtr[k * 4 + 1];
+#pragma unroll
+    for (int k = 0; k < NZB; ++k) {
+        if (k < nz) {
+            R rhs = R(S.dz[k]) * x[k];
+            const R a = (k > kbot) ? asub[k] : R(0);  // face k wet: layers k-1 and k
+            if (field == 0) {
+                const R c = (k >= kbot && k < nz - 1) ? asub[k + 1] : R(0);
+                rhs += -c * dtr[k * 4 + 2] - a * dtr[k * 4 + 1];
+            }
+            dprev = (rhs - a * dprev) * rden[k];
+            x[k] = dprev;
         }
-        const R dk = (rhs - a * dprev) * rden[k];
-        sd[k * CW + t] = dk;
-        dprev = dk;
     }
     // Back-substitution, top to bottom: x_k = d'_k - c'_k x_{k+1}.
     R xnext = R(0);
     double colsum = 0.0;
-    for (int k = nz - 1; k >= 0; --k) {
-        const R x = sd[k * CW + t] - cp[k] * xnext;
-        xnext = x;
-        sd[k * CW + t] = x;
-        if (k >= kbot) colsum += double(S.dz[k]) * double(x);
-    }
-    if (!live) return;
-
-    if (field == 0) {
-        for (int k = 0; k < nz; ++k) {
-            const R x = sd[k * CW + t];
-            dst[idx3(S, i, j, k)] = x;
-            store_wrapped(S, dst, i, j, k, x);
+#pragma unroll
+    for (int k = NZB - 1; k >= 0; --k) {
+        if (k < nz) {
+            xnext = x[k] - cp[k] * xnext;
+            x[k] = xnext;
+            if (k >= kbot) colsum += double(S.dz[k]) * double(xnext);
         }
-        return;
     }
-
-    // depth-mean correction: u = u** + (U^{Ns} - sum dz u**) / H on wet layers
-    const double H = (field == 1) ? S.hu[idx2(S, i, j)] : S.hv[idx2(S, i, j)];
-    const double B = (field == 1) ? S.ubt[idx2(S, i, j)] : S.vbt[idx2(S, i, j)];
-    const double corr = (H > 0.0) ? (B - colsum) / H : 0.0;
-    double newsum = 0.0;
-    for (int k = 0; k < nz; ++k) {
-        R val = R(0);
-        if (k >= kbot && H > 0.0) {
-            val = R(double(sd[k * CW + t]) + corr);
-            newsum += double(S.dz[k]) * double(val);
-        }
-        dst[idx3(S, i, j, k)] = val;
-        store_wrapped(S, dst, i, j, k, val);
-    }
-    store_wrapped2(S, field == 1 ? S.cu : S.cv, i, j, newsum);
+    if (i < S.nx) column_store<R, NZB>(S, x, i, j, field, kbot, colsum);
 }
 
 // The same solve with a diffusivity that varies by face and column (a
@@ -245,33 +266,68 @@ __global__ __launch_bounds__(CW) void k_wfaces(const DevState S) {
     S.scratch2d[idx2(S, i, j)] = W / area;
 }
 
+// Occupancy target of the register-resident solve: FP32 columns of up to 100
+// levels fit four waves per SIMD.
+template <typename R> struct ColWaves;
+template <> struct ColWaves<float> { static constexpr int n = 4; };
+template <> struct ColWaves<double> { static constexpr int n = 2; };
+
+template <typename R, int NZB>
+__global__ __launch_bounds__(CW) __attribute__((amdgpu_waves_per_eu(ColWaves<R>::n)))
+void k_column(const DevState S) {
+    column_regs<R, NZB>(S, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Variable diffusivity (prescribed field or learned closure), staged in LDS.
 template <typename R>
-__global__ __launch_bounds__(CW) void k_column(const DevState S) {
+__global__ __launch_bounds__(CW) void k_column_vk(const DevState S) {
     extern __shared__ __align__(16) unsigned char smem_col[];
-    // nz * CW: the column, then its eliminated rhs, then the solution
-    R* sd = reinterpret_cast<R*>(smem_col);
-    if (S.kw)
-        column_block_vk<R>(S, sd, sd + S.nz * CW, blockIdx.x, blockIdx.y, blockIdx.z);
-    else
-        column_block<R>(S, sd, blockIdx.x, blockIdx.y, blockIdx.z);
+    R* sd = reinterpret_cast<R*>(smem_col);  // nz * CW eliminated rhs / solution, then nz * CW of c'
+    column_block_vk<R>(S, sd, sd + S.nz * CW, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // Ensemble: entry blockIdx.x of the table is (member, bx, j); blockIdx.y is the field.
-template <typename R>
-__global__ __launch_bounds__(CW) void k_column_batched(const DevState* __restrict__ members,
-                                                       const int4* __restrict__ tiles) {
-    extern __shared__ __align__(16) unsigned char smem_col[];
+template <typename R, int NZB>
+__global__ __launch_bounds__(CW) __attribute__((amdgpu_waves_per_eu(ColWaves<R>::n)))
+void k_column_batched(const DevState* __restrict__ members, const int4* __restrict__ tiles) {
     const int4 e = tiles[blockIdx.x];
-    column_block<R>(members[e.x], reinterpret_cast<R*>(smem_col), e.y, e.z, blockIdx.y);
+    column_regs<R, NZB>(members[e.x], e.y, e.z, blockIdx.y);
 }
+
+// Dispatch a level count to the smallest bucket that holds it.
+template <typename R, template <typename, int> class Launch, typename... A>
+hipError_t with_bucket(int nz, A... args) {
+    if (nz <= 16) return Launch<R, 16>::go(args...);
+    if (nz <= 32) return Launch<R, 32>::go(args...);
+    if (nz <= 48) return Launch<R, 48>::go(args...);
+    if (nz <= 64) return Launch<R, 64>::go(args...);
+    if (nz <= 80) return Launch<R, 80>::go(args...);
+    if (nz <= 100) return Launch<R, 100>::go(args...);
+    if (nz <= kMaxNz) return Launch<R, 128>::go(args...);
+    return hipErrorInvalidValue;
+}
+
+template <typename R, int NZB>
+struct LaunchColumn {
+    static hipError_t go(const DevState& s, hipStream_t st) {
+        dim3 grid((s.nx + CW - 1) / CW, s.ny, 3);
+        hipLaunchKernelGGL((k_column<R, NZB>), grid, dim3(CW), 0, st, s);
+        return hipGetLastError();
+    }
+};
+
+template <typename R, int NZB>
+struct LaunchColumnBatched {
+    static hipError_t go(const DevState* members, const int4* tiles, int ntiles, hipStream_t st) {
+        hipLaunchKernelGGL((k_column_batched<R, NZB>), dim3(ntiles, 3), dim3(CW), 0, st, members, tiles);
+        return hipGetLastError();
+    }
+};
 
 template <typename R>
 hipError_t launch_column_batched(const DevState* members, const int4* tiles, int ntiles, int max_nz, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    const size_t lds = (size_t)max_nz * CW * sizeof(R);
-    if (lds > 64 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_column_batched<R>, dim3(ntiles, 3), dim3(CW), lds, st, members, tiles);
-    return hipGetLastError();
+    return with_bucket<R, LaunchColumnBatched>(max_nz, members, tiles, ntiles, st);
 }
 
 template hipError_t launch_column_batched<double>(const DevState*, const int4*, int, int, hipStream_t);
@@ -279,11 +335,14 @@ template hipError_t launch_column_batched<float>(const DevState*, const int4*, i
 
 template <typename R>
 hipError_t launch_column(const DevState& s, hipStream_t st) {
-    const size_t lds = (size_t)s.nz * CW * sizeof(R) * (s.kw ? 2 : 1);
-    if (lds > 64 * 1024) return hipErrorInvalidValue;  // per-workgroup LDS limit
-    dim3 grid((s.nx + CW - 1) / CW, s.ny, 3);
-    hipLaunchKernelGGL(k_column<R>, grid, dim3(CW), lds, st, s);
-    return hipGetLastError();
+    if (s.kw) {
+        const size_t lds = (size_t)s.nz * CW * sizeof(R) * 2;
+        if (lds > 64 * 1024) return hipErrorInvalidValue;  // per-workgroup LDS limit
+        dim3 grid((s.nx + CW - 1) / CW, s.ny, 3);
+        hipLaunchKernelGGL(k_column_vk<R>, grid, dim3(CW), lds, st, s);
+        return hipGetLastError();
+    }
+    return with_bucket<R, LaunchColumn>(s.nz, s, st);
 }
 
 template <typename R>

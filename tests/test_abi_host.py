@@ -57,7 +57,7 @@ def test_grid_create_validates_arguments():
 
 
 def test_arena_size_scales_with_precision_and_validates_params():
-    w = inputs.BETA_BASIN_64.replace(nx=40, ny=30, nz=10)
+    w = inputs.BETA_BASIN_64.replace(nx=400, ny=300, nz=10)   # sizes only: nothing is allocated
     rc, h, keep = _grid(w)
     assert rc == 0
     n64, n32 = C.c_size_t(), C.c_size_t()
@@ -66,9 +66,11 @@ def test_arena_size_scales_with_precision_and_validates_params():
     assert L.ocn_state_arena_bytes(h, C.byref(p), C.byref(n64)) == 0
     p32 = ocn.params(w, "fp32")
     assert L.ocn_state_arena_bytes(h, C.byref(p32), C.byref(n32)) == 0
-    # nine 3D fields dominate: the FP32 arena is a bit over half the FP64 one
-    assert 0.45 * n64.value < n32.value < 0.8 * n64.value
-    assert n64.value >= 9 * 40 * 30 * 10 * 8
+    # nine 3D fields change element size; the FP64 2D fields and tables do not
+    cells = 400 * 300 * 10
+    assert n64.value >= 9 * cells * 8 + 22 * 400 * 300 * 8
+    assert n64.value - n32.value >= 9 * cells * 4
+    assert n32.value < n64.value
     bad = ocn.params(w, "fp64")
     bad.n_substeps = 0
     assert L.ocn_state_arena_bytes(h, C.byref(bad), C.byref(n64)) == ocn.OCN_E_INVALID
