@@ -616,8 +616,12 @@ static void step_once(orc_model* m) {
             m->U_mean[c] = sU[c] / ns;
             m->V_mean[c] = sV[c] / ns;
         }
-        /* depth-mean correction: replace the depth mean of u** by U^{Ns}/H
-         * (reading: the end-of-loop transport, so sum dz u^{n+1} = U exactly) */
+        /* depth-mean correction: replace the depth mean of u** by Ubar/H, the
+         * substep average of the transport, which is the transport that moved
+         * the free surface over the step (eta^{n+1} - eta^n = -dt div Ubar), so
+         * sum dz u^{n+1} = Ubar exactly. The substeps restart from their
+         * instantaneous end state. (Reading: correcting with the end-of-loop
+         * U^{Ns} instead lets unfiltered fast modes grow.) */
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t c2 = id2(m, i, j);
@@ -628,8 +632,8 @@ static void step_once(orc_model* m) {
                 }
                 for (int k = 0; k < nz; ++k) {
                     size_t c = id3(m, i, j, k);
-                    m->u[c] = (Hu[c2] > 0.0 && u_wet(m, i, j, k)) ? us[c] + (m->U[c2] - su) / Hu[c2] : 0.0;
-                    m->v[c] = (Hv[c2] > 0.0 && v_wet(m, i, j, k)) ? vs[c] + (m->V[c2] - sv) / Hv[c2] : 0.0;
+                    m->u[c] = (Hu[c2] > 0.0 && u_wet(m, i, j, k)) ? us[c] + (m->U_mean[c2] - su) / Hu[c2] : 0.0;
+                    m->v[c] = (Hv[c2] > 0.0 && v_wet(m, i, j, k)) ? vs[c] + (m->V_mean[c2] - sv) / Hv[c2] : 0.0;
                 }
             }
         free(en); free(Un); free(Vn); free(Hu); free(Hv); free(sE); free(sU); free(sV);

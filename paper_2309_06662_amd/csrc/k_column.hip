@@ -16,8 +16,9 @@
 // its right-hand side.
 //
 // For u and v the same kernel then applies the split-explicit correction
-// (paper Sec. 5.3): the depth mean of u** is replaced by U^{Ns}/H, using the
-// barotropic transport at the end of the substeps, and it leaves the column
+// (paper Sec. 5.3): the depth mean of u** is replaced by Ubar/H, the substep
+// average of the barotropic transport (the transport that moved the free
+// surface over the step), and it leaves the column
 // sum sum_k dz u m_u of the stored result, which seeds the vertical transport
 // of the next step. Columns next to a periodic boundary also write their
 // wrapped copies into the halo.
@@ -42,7 +43,7 @@ constexpr int kNzBuckets[] = {16, 32, 48, 64, 80, 100, 128};
 constexpr int kMaxNz = 128;
 
 // Output of one solved column: T as is; u and v with the depth-mean
-// correction u = u** + (U^{Ns} - sum dz u**) / H on wet layers, which also
+// correction u = u** + (Ubar - sum dz u**) / H on wet layers, which also
 // leaves the column sum sum_k dz u m_u of the stored result (it seeds the
 // vertical transport of the next step). Periodic images are written too.
 template <typename R, int NZB>
@@ -61,7 +62,7 @@ __device__ __forceinline__ void column_store(const DevState& S, const R (&x)[NZB
         return;
     }
     const double H = (field == 1) ? S.hu[idx2(S, i, j)] : S.hv[idx2(S, i, j)];
-    const double B = (field == 1) ? S.ubt[idx2(S, i, j)] : S.vbt[idx2(S, i, j)];
+    const double B = (field == 1) ? S.ubt_mean[idx2(S, i, j)] : S.vbt_mean[idx2(S, i, j)];  // substep-averaged transport
     const double corr = (H > 0.0) ? (B - colsum) / H : 0.0;
     double newsum = 0.0;
 #pragma unroll
@@ -208,7 +209,7 @@ __device__ __forceinline__ void column_block_vk(const DevState& S, R* sd, R* sc,
         return;
     }
     const double H = (field == 1) ? S.hu[idx2(S, i, j)] : S.hv[idx2(S, i, j)];
-    const double B = (field == 1) ? S.ubt[idx2(S, i, j)] : S.vbt[idx2(S, i, j)];
+    const double B = (field == 1) ? S.ubt_mean[idx2(S, i, j)] : S.vbt_mean[idx2(S, i, j)];  // substep-averaged transport
     const double corr = (H > 0.0) ? (B - colsum) / H : 0.0;
     double newsum = 0.0;
     for (int k = 0; k < nz; ++k) {

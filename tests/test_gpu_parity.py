@@ -271,3 +271,43 @@ def test_many_barotropic_tiles_fp64():
         loc, err = _worst_location(ref, gpu, n)
         print(f"  many tiles {n}: largest difference {err:.3e} at {loc}", flush=True)
     _compare(ref, gpu, w, inp["kbottom"], 1e-11)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_graph_replay_bitwise_equals_eager(precision):
+    """Steps replayed from a captured graph give bitwise the eager result, replay
+    after replay, with eager steps, host reads and synchronisations in between."""
+    import torch
+
+    ocn = _ocn()
+    w = inputs.BETA_BASIN_64.replace(name="beta_70x40x6", nx=70, ny=40, nz=6)
+    inp = inputs.make_inputs(w)
+    side = torch.cuda.Stream()
+    a = ocn.Model(w, precision, inp, stream=side)
+    b = ocn.Model(w, precision, inp)
+    plan = [(1, False), (2, True), (1, True), (1, False), (3, True), (2, True)]
+    for n, graph in plan:
+        a.step(n, graph=graph)
+        b.step(n)
+        a.synchronize()
+        b.synchronize()
+        for name in ("u", "v", "T", "eta", "U", "V"):
+            assert np.array_equal(a.get(name), b.get(name)), (n, graph, name)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-3)])
+def test_long_run_regional_box(precision, tol):
+    """240 steps (40 hours) of a 1/4-degree regional box with seamounts, wind
+    and restoring: the GPU stays bounded and follows the oracle (the tolerances
+    allow for 240 steps of round-off growth in a forced flow)."""
+    from paper_2309_06662_amd import closure_train
+
+    w, _ = closure_train.regional_pair(nx=32, ny=24, nz=10)
+    ref, gpu, inp = _pair(w, precision)
+    ref.step(240)
+    gpu.step(240)
+    d = gpu.diagnostics()
+    assert d["nonfinite"] == 0 and d["max_abs_u"] < 0.2
+    errs = _compare(ref, gpu, w, inp["kbottom"], tol)
+    print(f"  240 steps {precision}:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
