@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -131,6 +133,101 @@ def run_ensemble(steps, warmup, n_members=64):
             "autotune": tune, "finite": finite}
 
 
+def run_small(steps=200, warmup=5):
+    """The 64 x 64 x 16 beta-plane basin: cache-resident and bound by launch
+    latency, so it reports microseconds per step stepped eagerly and replayed
+    from a captured graph."""
+    import torch
+
+    from paper_2309_06662_amd import ocn
+
+    w = inputs.BETA_BASIN_64
+    inp = inputs.make_inputs(w)
+    out = {"workload": w.name}
+    for prec in ("fp64", "fp32"):
+        side = torch.cuda.Stream()
+        m = ocn.Model(w, prec, inp, stream=side)
+        rec = {}
+        for mode in ("eager", "graph"):
+            m.step(warmup, graph=(mode == "graph"))
+            m.synchronize()
+            t0 = time.perf_counter()
+            m.step(steps, graph=(mode == "graph"))
+            m.synchronize()
+            rec[f"{mode}_us_per_step"] = (time.perf_counter() - t0) / steps * 1e6
+        rec["graph_speedup"] = rec["eager_us_per_step"] / rec["graph_us_per_step"]
+        out[prec] = rec
+        m.close()
+    return out
+
+
+def run_quarter(steps, warmup):
+    """The 1/4-degree basin (1440 x 600 x 50) in both precisions, and the
+    learned closure's cost there: the same FP32 step with a 208-128-128-50
+    network (random weights) evaluated for every column at every step."""
+    import torch
+
+    from paper_2309_06662_amd import ocn
+
+    w = inputs.LATLON_QUARTER
+    inp = inputs.make_inputs(w)
+    out = {"workload": w.name}
+    for prec in ("fp32", "fp64"):
+        el, stages, diag = run_gpu(w, prec, inp, steps, warmup)
+        ms = el / steps * 1e3
+        out[prec] = {"ms_per_step": ms, "cell_updates_per_s": w.cells * steps / el,
+                     "sypd": metrics.sypd(w.dt, ms * 1e-3), "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+                     "finite": diag["nonfinite"] == 0}
+    din, h, dout = (4 * w.nz + 3 + 7) // 8 * 8, 128, w.nz
+    rng = np.random.default_rng(0)
+    P = [rng.normal(size=(din, h)) * np.sqrt(2.0 / din), np.zeros(h), rng.normal(size=(h, h)) * np.sqrt(2.0 / h),
+         np.zeros(h), rng.normal(size=(h, dout)) * 0.01, np.full(dout, -5.0)]
+    net = ocn.Mlp(din, h, h, dout, max_batch=1024)
+    net.set_params(np.concatenate([p.reshape(-1) for p in P]).astype(np.float32))
+    norm = np.concatenate([np.zeros(din), np.ones(din)]).astype(np.float32)
+    m = ocn.Model(w, "fp32", inp)
+    m.attach_closure(net, norm)
+    m.step(warmup)
+    m.synchronize()
+    m.stage_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.step(steps)
+    m.synchronize()
+    el = time.perf_counter() - t0
+    st, n = m.stage_times()
+    m.stage_timing(False)
+    finite = m.diagnostics(allow_unstable=True)["nonfinite"] == 0
+    m.detach_closure()
+    m.close()
+    cols = w.nx * w.ny
+    gemm_flops = 2.0 * cols * (din * h + h * h + h * dout)
+    cl_ms = st["closure"] / max(n, 1)
+    out["closure"] = {"network": [din, h, h, dout], "ms_per_step": el / steps * 1e3,
+                      "closure_stage_ms": cl_ms, "slowdown_vs_constant_kappa": (el / steps * 1e3) / out["fp32"]["ms_per_step"],
+                      "network_tflops_in_closure_stage": gemm_flops / (cl_ms * 1e-3) / 1e12, "finite": finite}
+    return out
+
+
+def copy_bandwidth(mib=2048, repeat=5):
+    """Device-to-device copy bandwidth (read + write bytes / time) measured now."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(repeat):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * 4 * n * repeat / el / 1e9
+
+
 def roofline(w, precision, stage_ms):
     esize = 4 if precision == "fp32" else 8
     t = stage_ms["tendency"] * 1e-3
@@ -179,6 +276,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble measurement")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the small-basin graph timing, the 1/4-degree runs and the copy bandwidth")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -211,8 +310,18 @@ def main():
         print(f"[bench] ensemble: batched {ens['batched_ms_per_step']:.3f} ms/step, sequential "
               f"{ens['sequential_ms_per_step']:.3f} ms/step, tiles {ens['autotune']}", file=sys.stderr, flush=True)
 
+    extra = {}
+    if not args.no_extra:
+        extra["copy_gbs"] = copy_bandwidth()
+        extra["small"] = run_small()
+        print(f"[bench] small basin: {extra['small']}", file=sys.stderr, flush=True)
+        extra["quarter"] = run_quarter(args.steps, args.warmup)
+        print(f"[bench] 1/4 degree: {extra['quarter']}", file=sys.stderr, flush=True)
+
     main_rec = results["fp32"]
     roof, other = roofline(w, "fp32", main_rec["stage_ms"])
+    if "copy_gbs" in extra and roof["unit"] == "GB/s":
+        roof["frac_of_measured_copy"] = round(roof["achieved"] / extra["copy_gbs"], 4)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -247,6 +356,7 @@ def main():
         line["fp32_speedup_over_fp64"] = r64["ms_per_step"] / main_rec["ms_per_step"]
     if ens is not None:
         line["ensemble"] = ens
+    line.update(extra)
     print(json.dumps(line), flush=True)
 
 

@@ -221,7 +221,7 @@ int  ocn_ensemble_autotune(ocn_ensemble* ens, int32_t trial_steps, int32_t* tend
  * BF16 operands on the matrix cores and FP32 accumulation, FP32 master weights
  * and Adam; it maps a column's features to its vertical-diffusivity profile
  * (paper Sec. 3 motivates learned parameterizations, Sec. 6 uses a
- * vertical-mixing closure). Layer widths must be multiples of 8. Parameters
+ * vertical-mixing closure). Parameters
  * are packed FP32: W1 (din x h1, row-major), b1, W2 (h1 x h2), b2, W3
  * (h2 x dout), b3. Batches are device pointers to FP32 row-major matrices,
  * rows <= max_batch: x (rows x din), targets and outputs (rows x dout).
@@ -265,6 +265,14 @@ int ocn_closure_workspace_bytes(const ocn_state* state, const ocn_mlp* net, size
 int ocn_closure_attach(ocn_state* state, const ocn_mlp* net, const float* norm, size_t norm_count,
                        void* device_workspace, size_t workspace_bytes);
 int ocn_closure_detach(ocn_state* state);
+/* Convective adjustment in the prescribed-field mode (paper Sec. 5.1: the
+ * diffusivity is a diagnostic of the current state; Sec. 6 runs a
+ * vertical-mixing closure): with kappa_conv > 0 every step starts by setting
+ * the face field to kappa_conv on interior wet faces where N^2 = g alpha dT/dz
+ * < 0 (denser water above) and to the constant kappa elsewhere; kappa_conv <= 0
+ * turns it off (the field keeps its last values). Needs a closure attached
+ * with net == NULL (else OCN_E_STATE); synchronises the stream. */
+int ocn_closure_convective(ocn_state* state, double kappa_conv);
 /* Network inputs of every column of the current state into x (device FP32,
  * (ny nx) x din row-major, row j nx + i), din >= 4 nz + 3 and 64 (din + 1) 4
  * bytes <= 64 KiB. Order: T (nz levels, bottom first), u and v averaged to
@@ -292,6 +300,15 @@ int ocn_closure_kappa(ocn_state* state, const float* y_dev, int32_t ldy);
 int ocn_checkpoint_bytes(ocn_state* state, size_t* bytes);
 int ocn_checkpoint_save(ocn_state* state, void* host, size_t bytes);
 int ocn_checkpoint_load(ocn_state* state, const void* host, size_t bytes);
+
+/* The same steps through a HIP graph: the first call that steps past the
+ * forward-Euler start captures the kernels of one step (thread-local capture
+ * on the state's stream) and every later step replays that graph, which
+ * removes the per-launch host cost on small grids. The start step and steps
+ * taken while stage timing is on run eagerly. The graph is rebuilt after a
+ * closure is attached or detached. The state's stream must not be the null
+ * stream (OCN_E_UNSUPPORTED). Results are bitwise those of ocn_step. */
+int ocn_step_graph(ocn_state* state, int32_t n);
 
 /* Per-stage timing with HIP events recorded on the state's stream. While
  * enabled (enable = 1), every ocn_step records an event at its start, after

@@ -75,6 +75,7 @@ def lib():
         L.orc_neumaier_sum.restype = C.c_double
         L.orc_neumaier_sum.argtypes = [_D, C.c_int64]
         L.orc_column_zflux.argtypes = [C.c_int, _D, C.POINTER(C.c_int32), _D, _D]
+        L.orc_set_convective.argtypes = [C.c_void_p, C.c_double]
         L.orc_closure_features.argtypes = [C.c_void_p, C.c_int, _D, _D, _D]
         L.orc_closure_kappa.argtypes = [C.c_void_p, _D, C.c_double, _D]
         L.orc_mlp_forward.argtypes = [_D, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int] + [_D] * 9
@@ -171,6 +172,10 @@ class OracleModel:
         out = np.zeros(NDIAG, dtype=np.float64)
         lib().orc_diagnostics(self._h, _dptr(out))
         return dict(zip(DIAG_NAMES, out.tolist()))
+
+    def set_convective(self, kappa_conv: float):
+        """Convective adjustment: kappa_conv on faces with N^2 < 0 at the start of every step (<= 0: off)."""
+        lib().orc_set_convective(self._h, float(kappa_conv))
 
     def closure_features(self, din: int, mean=None, std=None) -> np.ndarray:
         """Per-column network inputs, (ny*nx) x din (feature order in ocean_oracle.c)."""

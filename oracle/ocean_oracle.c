@@ -27,7 +27,8 @@
 #include <string.h>
 
 #define WENO_EPS 1e-8
-#define DEG2RAD (3.14159265358979323846 / 180.0)
+#define PI 3.14159265358979323846
+#define DEG2RAD (PI / 180.0)
 
 struct orc_model {
     orc_desc d;
@@ -40,6 +41,7 @@ struct orc_model {
     double *eta_mean, *U_mean, *V_mean;       /* substep averages of the last step */
     double *taux, *tauy, *tstar;              /* surface forcing (N/m^2, N/m^2, degC) */
     double *kw;          /* prescribed diffusivity on z-faces (m^2/s), or NULL for the constant */
+    double kappa_conv;   /* > 0: convective adjustment, kappa_conv on faces with N^2 < 0 */
     int first_step;
     int64_t step;
     double time;
@@ -528,6 +530,22 @@ static void step_once(orc_model* m) {
     double* gU = (double*)calloc(n2, sizeof(double));
     double* gV = (double*)calloc(n2, sizeof(double));
 
+    /* convective adjustment (a diffusivity diagnosed from the state at the
+     * start of the step, Sec. 5.1): kappa_conv on interior wet faces where the
+     * water above is denser than the water below (N^2 = g alpha dT/dz < 0),
+     * the constant elsewhere */
+    if (m->kappa_conv > 0.0) {
+        if (!m->kw) m->kw = (double*)malloc(sizeof(double) * n3);
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    double kap = 0.0;
+                    if (w_wet(m, i, j, k))
+                        kap = (m->T[id3(m, i, j, k)] < m->T[id3(m, i, j, k - 1)]) ? m->kappa_conv : m->d.kappa;
+                    m->kw[id3(m, i, j, k)] = kap;
+                }
+    }
+
     /* tendencies G^n of the current state */
     orc_eval_tendencies(m, ORC_TERM_ALL, gu, gv, gt);
 
@@ -573,29 +591,47 @@ static void step_once(orc_model* m) {
 
     /* barotropic substeps (Sec. 5.3: explicit sub-cycling of the 2D mode).
      * Reading: forward-backward, free surface first, then transports from the
-     * new surface gradient plus the slow forcing; dtau = dt/Ns spans [t^n, t^{n+1}];
-     * running sums of U^m, V^m and eta^{m+1} give the step averages. */
+     * new surface gradient plus the slow forcing, dtau = dt/Ns. The substeps
+     * run on to t^n + 3dt/2 (M = Ns + Ns/2 of them); the new eta, U, V are the
+     * averages of eta^q, U^q, V^q (q = 1..M) with weights a_q proportional to
+     * cos^2(pi t), t = q/Ns - 1, |t| < 1/2, a window centred on t^{n+1}; the
+     * transport that moves the free surface over the step is
+     * Ubar = sum_l A_l U^l / Ns with A_l = sum_{q>l} a_q, so that
+     * eta^{n+1} - eta^n = -dt div Ubar exactly. */
     {
-        const int ns = m->d.n_substeps;
+        const int ns = m->d.n_substeps, M = ns + ns / 2;
         const double dtau = dt / ns, g = m->d.g, dy = dy_m(m);
         double* en = (double*)malloc(sizeof(double) * n2);
         double* Un = (double*)malloc(sizeof(double) * n2);
         double* Vn = (double*)malloc(sizeof(double) * n2);
         double* Hu = (double*)malloc(sizeof(double) * n2);
         double* Hv = (double*)malloc(sizeof(double) * n2);
-        double* sE = (double*)calloc(n2, sizeof(double));
-        double* sU = (double*)calloc(n2, sizeof(double));
+        double* sU = (double*)calloc(n2, sizeof(double));   /* sum_l A_l U^l */
         double* sV = (double*)calloc(n2, sizeof(double));
+        double* fE = (double*)calloc(n2, sizeof(double));   /* sum_q a_q eta^q */
+        double* fU = (double*)calloc(n2, sizeof(double));
+        double* fV = (double*)calloc(n2, sizeof(double));
+        double* a = (double*)calloc((size_t)M + 1, sizeof(double));
+        double asum = 0.0;
+        for (int q = 1; q <= M; ++q) {
+            const double t = (double)q / ns - 1.0;
+            const double c = fabs(t) < 0.5 ? cos(PI * t) : 0.0;
+            a[q] = c * c;
+            asum += a[q];
+        }
+        for (int q = 1; q <= M; ++q) a[q] /= asum;
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) { Hu[id2(m, i, j)] = depth_u(m, i, j); Hv[id2(m, i, j)] = depth_v(m, i, j); }
-        for (int s = 0; s < ns; ++s) {
+        for (int l = 0; l < M; ++l) {
+            double Al = 0.0;
+            for (int q = l + 1; q <= M; ++q) Al += a[q];
             for (int j = 0; j < ny; ++j)
                 for (int i = 0; i < nx; ++i) {
                     double div = dy * (at2(m, m->U, i + 1, j) - at2(m, m->U, i, j))
                                + dx_v(m, j + 1) * at2(m, m->V, i, j + 1) - dx_v(m, j) * at2(m, m->V, i, j);
                     en[id2(m, i, j)] = m->eta[id2(m, i, j)] - dtau / area_c(m, j) * div;
-                    sU[id2(m, i, j)] += m->U[id2(m, i, j)];
-                    sV[id2(m, i, j)] += m->V[id2(m, i, j)];
+                    sU[id2(m, i, j)] += Al * m->U[id2(m, i, j)];
+                    sV[id2(m, i, j)] += Al * m->V[id2(m, i, j)];
                 }
             for (int j = 0; j < ny; ++j)
                 for (int i = 0; i < nx; ++i) {
@@ -608,20 +644,22 @@ static void step_once(orc_model* m) {
                 m->eta[c] = en[c];
                 m->U[c] = Un[c];
                 m->V[c] = Vn[c];
-                sE[c] += en[c];
+                fE[c] += a[l + 1] * en[c];
+                fU[c] += a[l + 1] * Un[c];
+                fV[c] += a[l + 1] * Vn[c];
             }
         }
         for (size_t c = 0; c < n2; ++c) {
-            m->eta_mean[c] = sE[c] / ns;
+            m->eta[c] = fE[c];
+            m->U[c] = fU[c];
+            m->V[c] = fV[c];
+            m->eta_mean[c] = fE[c];
             m->U_mean[c] = sU[c] / ns;
             m->V_mean[c] = sV[c] / ns;
         }
         /* depth-mean correction: replace the depth mean of u** by Ubar/H, the
-         * substep average of the transport, which is the transport that moved
-         * the free surface over the step (eta^{n+1} - eta^n = -dt div Ubar), so
-         * sum dz u^{n+1} = Ubar exactly. The substeps restart from their
-         * instantaneous end state. (Reading: correcting with the end-of-loop
-         * U^{Ns} instead lets unfiltered fast modes grow.) */
+         * transport that moved the free surface over the step, so
+         * sum dz u^{n+1} = Ubar exactly. */
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t c2 = id2(m, i, j);
@@ -636,7 +674,7 @@ static void step_once(orc_model* m) {
                     m->v[c] = (Hv[c2] > 0.0 && v_wet(m, i, j, k)) ? vs[c] + (m->V_mean[c2] - sv) / Hv[c2] : 0.0;
                 }
             }
-        free(en); free(Un); free(Vn); free(Hu); free(Hv); free(sE); free(sU); free(sV);
+        free(en); free(Un); free(Vn); free(Hu); free(Hv); free(sU); free(sV); free(fE); free(fU); free(fV); free(a);
     }
 
     m->first_step = 0;
@@ -847,6 +885,10 @@ int orc_get_field(orc_model* m, int f, double* dst) {
 }
 
 void orc_set_first_step(orc_model* m, int first) { m->first_step = first ? 1 : 0; }
+void orc_set_convective(orc_model* m, double kappa_conv) {
+    m->kappa_conv = kappa_conv > 0.0 ? kappa_conv : 0.0;
+    if (m->kappa_conv == 0.0) { free(m->kw); m->kw = NULL; }
+}
 int orc_get_first_step(const orc_model* m) { return m->first_step; }
 
 /* ------------------------------------------------------------------------- */

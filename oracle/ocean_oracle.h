@@ -61,6 +61,10 @@ void       orc_destroy(orc_model* m);
 int        orc_set_field(orc_model* m, int field, const double* src);
 int        orc_get_field(orc_model* m, int field, double* dst);
 void       orc_set_first_step(orc_model* m, int first);
+/* Convective adjustment: with kappa_conv > 0 every step starts by setting the
+ * face diffusivity to kappa_conv where N^2 < 0 and to the constant elsewhere
+ * (it replaces a prescribed field); kappa_conv <= 0 returns to the constant. */
+void       orc_set_convective(orc_model* m, double kappa_conv);
 int        orc_get_first_step(const orc_model* m);
 void       orc_step(orc_model* m, int n);
 void       orc_diagnostics(const orc_model* m, double* out);

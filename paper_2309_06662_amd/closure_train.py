@@ -7,22 +7,28 @@ library's own runs:
 
 1. A regional box of the lat-lon basin (seamounts, cos-latitude wind, surface
    restoring) is run at a resolution `factor` times finer than the coarse
-   target grid, same levels. Surface cooling by the restoring makes the upper
-   ocean statically unstable; the fine grid resolves part of the resulting
-   overturning, the coarse grid does not.
+   target grid, same levels, with convective adjustment (kappa_conv where
+   N^2 < 0): surface cooling by the restoring makes the upper ocean statically
+   unstable, and a hydrostatic model needs that mixing to stay well posed.
 2. Every `sample_every` fine steps the fine state is coarse-grained onto the
    coarse grid (area-weighted means over wet fine cells; a coarse cell counts
-   only where all its fine cells are wet). The eddy heat flux through each
-   coarse z-face is <w T> - <w><T>, averaged over a window of samples.
-3. Target: kappa_eff = kappa0 + max(0, -<w'T'> / max(dT/dz, 1e-6 K/m)),
-   clipped to [1e-6, 1e-1] m^2/s, as log10 at layer centres (mean of the
-   centre's wet faces). Inputs: the library's closure features of the coarse
-   model set to the coarse-grained state, normalised over the training set.
+   only where all its fine cells are wet). The subgrid heat flux through each
+   coarse z-face is the eddy flux <w T> - <w><T> plus the fine model's mixing
+   beyond the background, -<(kappa - kappa0) dT/dz>, averaged over a window of
+   samples.
+3. Target: kappa_eff = kappa0 + max(0, -F / D) for that subgrid flux F, with
+   D = d<T>/dz kept at least 1e-6 K/m in magnitude with its sign (a
+   down-gradient flux gives a positive diffusivity in stable and unstable
+   stratification alike), clipped to [1e-6, 1] m^2/s, as log10 at layer centres
+   (mean of the centre's wet faces; the background at dry levels). Inputs: the
+   library's closure features of the coarse model set to the coarse-grained
+   state, normalised over the training set.
 4. The network (Linear-ReLU-Linear-ReLU-Linear, BF16 on the matrix cores,
    FP32 Adam) trains on the windows before the held-out period.
 5. Evaluation, declared before any run: from the coarse-grained state at the
    start of the held-out period, the coarse model runs `eval_days` with the
-   constant diffusivity and with the trained network; against the
+   constant diffusivity (the baseline), with the trained network, and, as a
+   physical comparator, with the fine run's convective adjustment; against the
    coarse-grained truth at the end, the RMSE over valid columns of the
    mixed-layer depth (first depth where T falls 0.2 K below the top layer)
    and of the change in column heat content sum dz T are reported for both.
@@ -64,7 +70,8 @@ class CoarseGrainer:
         wet_c = k >= coarse.nz - kb_coarse[None]                    # [nz, ny, nx]
         allwet = self._block(self.wet_f.astype(np.float64), weights=False) >= 1.0 - 1e-12
         self.valid = wet_c & allwet                                 # coarse cells fully resolved below
-        self.valid_col = self.valid.all(axis=0) & (kb_coarse == coarse.nz)
+        # coarse ocean columns whose every wet cell is fully resolved by fine wet cells
+        self.valid_col = (kb_coarse >= 2) & (self.valid == wet_c).all(axis=0)
 
     def _block(self, a, weights=True):
         f = self.f
@@ -91,8 +98,10 @@ class CoarseGrainer:
         return v[:, ::f, :].reshape(nz, NY // f, NX // f, f).mean(axis=3)
 
 
-def eddy_flux(cg, T, W):
-    """<w T> - <w><T> on interior z-faces (slot k = face between layers k-1 and k), coarse grid."""
+def eddy_flux(cg, T, W, kappa=None, kappa0=0.0, dz=None):
+    """Upward subgrid heat flux on interior z-faces (slot k = face between layers
+    k-1 and k), coarse grid: <w T> - <w><T>, plus -<(kappa - kappa0) dT/dz>
+    when the fine face diffusivity is given."""
     nz = T.shape[0]
     Tf = np.zeros_like(T)
     Tf[1:] = 0.5 * (T[1:] + T[:-1])
@@ -102,7 +111,14 @@ def eddy_flux(cg, T, W):
     wT = np.where(wet_face, w * Tf, 0.0)
     wm = np.where(wet_face, w, 0.0)
     Tm = np.where(wet_face, Tf, 0.0)
-    return cg.cells(wT) - cg.cells(wm) * cg.cells(Tm)
+    flux = cg.cells(wT) - cg.cells(wm) * cg.cells(Tm)
+    if kappa is not None:
+        dzc = np.zeros(nz)
+        dzc[1:] = 0.5 * (dz[1:] + dz[:-1])
+        dTdz = np.zeros_like(T)
+        dTdz[1:] = (T[1:] - T[:-1]) / dzc[1:, None, None]
+        flux = flux + cg.cells(np.where(wet_face, -(kappa - kappa0) * dTdz, 0.0))
+    return flux
 
 
 def kappa_target(flux, Tc, dz, kappa0):
@@ -113,8 +129,12 @@ def kappa_target(flux, Tc, dz, kappa0):
     kf = np.full_like(flux, np.nan)
     dTdz = np.zeros_like(flux)
     dTdz[1:] = (Tc[1:] - Tc[:-1]) / dzc[1:, None, None]
-    kf[1:] = kappa0 + np.maximum(0.0, -flux[1:] / np.maximum(dTdz[1:], 1e-6))
-    kf = np.clip(kf, 1e-6, 1e-1)
+    # down-gradient flux in either stratification: the gradient keeps its sign,
+    # its magnitude is kept away from zero
+    g = dTdz[1:]
+    den = np.where(g >= 0.0, 1.0, -1.0) * np.maximum(np.abs(g), 1e-6)
+    kf[1:] = kappa0 + np.maximum(0.0, -flux[1:] / den)
+    kf = np.clip(kf, 1e-6, 1.0)
     kc = np.empty_like(kf)
     kc[0] = kf[1]
     kc[nz - 1] = kf[nz - 1]
@@ -146,7 +166,7 @@ def _log(msg):
 
 
 def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_samples=8, epochs=30,
-        batch=4096, lr=1e-3, hidden=128, seed=0, coarse_kw=None):
+        batch=4096, lr=1e-3, hidden=128, seed=0, convective=1.0, coarse_kw=None):
     import torch
 
     from . import ocn
@@ -159,9 +179,12 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
     nz = coarse.nz
     din = (4 * nz + 3 + 7) // 8 * 8
     _log(f"coarse {coarse.nx}x{coarse.ny}x{nz}, fine {fine.nx}x{fine.ny}x{nz}, "
-         f"{int(cg.valid_col.sum())} fully resolved coarse columns")
+         f"{int(cg.valid_col.sum())} fully resolved coarse columns, convective adjustment {convective}")
 
     fm = ocn.Model(fine, "fp32", inp_f)
+    if convective > 0.0:
+        fm.attach_closure()
+        fm.set_convective(convective)
     cm = ocn.Model(coarse, "fp32", inp_c)   # holds coarse-grained states for the features
 
     steps_per_sample = max(1, int(round(sample_hours * 3600.0 / fine.dt)))
@@ -172,7 +195,9 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
         u, v, T = fm.get("u"), fm.get("v"), fm.get("T")
         W = fm.get("w")
         eta = fm.get("eta")
-        return {"u": cg.u_faces(u), "v": cg.v_faces(v), "T": cg.cells(T), "eta": cg.cells(eta)}, eddy_flux(cg, T, W)
+        kap = fm.get("kappa") if convective > 0.0 else None
+        flux = eddy_flux(cg, T, W, kap, fine.kappa, dz)
+        return {"u": cg.u_faces(u), "v": cg.v_faces(v), "T": cg.cells(T), "eta": cg.cells(eta)}, flux
 
     X_list, Y_list, snaps = [], [], {}
     acc = None
@@ -185,6 +210,8 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
             flux_w = acc / window_samples
             acc = None
             y = kappa_target(flux_w, st["T"], dz, coarse.kappa)
+            kz = np.arange(nz)[:, None, None] < nz - inp_c["kbottom"][None]
+            y = np.where(kz, math.log10(coarse.kappa), y)     # dry levels: the background
             for n in ("u", "v", "T"):
                 cm.set(n, st[n])
             X = cm.closure_features(din).cpu().numpy()
@@ -240,7 +267,8 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
     norm = np.concatenate([mean, std]).astype(np.float32)
     results = {}
     vc = cg.valid_col
-    for mode in ("constant", "learned"):
+    modes = ("constant", "learned", "convective") if convective > 0.0 else ("constant", "learned")
+    for mode in modes:
         m = ocn.Model(coarse, "fp32", inp_c)
         for n_ in ("u", "v", "T", "eta"):
             m.set(n_, start[n_])
@@ -248,6 +276,9 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
         m.set("V", np.tensordot(dz, start["v"], axes=(0, 0)))
         if mode == "learned":
             m.attach_closure(net, norm)
+        elif mode == "convective":
+            m.attach_closure()
+            m.set_convective(convective)
         m.step(eval_steps)
         T_end = m.get("T")
         d = m.diagnostics(allow_unstable=True)
@@ -257,11 +288,12 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
         results[mode] = {"mld_rmse_m": float(np.sqrt(np.mean(mld_err[vc] ** 2))),
                          "heat_content_drift_rmse_Km": float(np.sqrt(np.mean(hc_err[vc] ** 2))),
                          "finite": d["nonfinite"] == 0}
-        if mode == "learned":
+        if mode != "constant":
             m.detach_closure()
         m.close()
     truth_drift = heat_content(truth["T"], dz) - heat_content(start["T"], dz)
     report = {"coarse": coarse.name, "fine": fine.name, "factor": factor, "days": days, "eval_days": eval_days,
+              "convective_kappa": convective,
               "train_columns": int(n), "din": din, "hidden": hidden, "epochs": epochs,
               "loss_first": losses[0], "loss_last": losses[-1], "loss_constant_kappa": base,
               "truth_heat_content_drift_rms_Km": float(np.sqrt(np.mean(truth_drift[vc] ** 2))),
@@ -287,9 +319,11 @@ def main():
     ap.add_argument("--nx", type=int, default=96)
     ap.add_argument("--ny", type=int, default=64)
     ap.add_argument("--nz", type=int, default=50)
+    ap.add_argument("--convective", type=float, default=1.0, help="kappa where N^2 < 0 in the fine run (0: off)")
     a = ap.parse_args()
     run(a.out, factor=a.factor, days=a.days, eval_days=a.eval_days, sample_hours=a.sample_hours,
-        window_samples=a.window, epochs=a.epochs, coarse_kw={"nx": a.nx, "ny": a.ny, "nz": a.nz})
+        window_samples=a.window, epochs=a.epochs, convective=a.convective,
+        coarse_kw={"nx": a.nx, "ny": a.ny, "nz": a.nz})
 
 
 if __name__ == "__main__":

@@ -3,10 +3,14 @@
 // Forward-backward substeps in FP64 for every precision: the free surface
 // first, from the divergence of the depth-integrated transports, then the
 // transports from the new surface gradient plus the slow forcing left by the
-// tendency kernel. Running sums of eta^{m+1}, U^m and V^m give the step
-// averages. Each substep is two launches over the 2D grid (surface, then
-// transports); every thread updates one column in place and writes the
-// periodic copies of its value into the one-cell halo the next launch reads.
+// tendency kernel. The substeps run on to t^n + 3dt/2 (M = Ns + Ns/2 of them).
+// The new eta, U, V are averages of the substep values with weights a_q
+// centred on t^{n+1} (cos^2 window of half-width dt/2, a table on the device);
+// the transport that moved the free surface over the step, used for the
+// baroclinic correction, is Ubar = sum_l A_l U^l / Ns with A_l = sum_{q>l} a_q.
+// The one-substep path takes two launches per substep (surface, then
+// transports), every thread updating one column in place and writing the
+// periodic copies of its value into the halo the next launch reads.
 #include "ocn_dev.h"
 
 #include <algorithm>
@@ -29,18 +33,19 @@ __global__ __launch_bounds__(BX * BY) void k_baro_eta(const DevState S, const do
     const double e = S.eta[c] - dtau / S.area[j] * div;
     S.eta[c] = e;
     wrap2(S, S.eta, i, j, e);
+    const double Am = S.baro_A[m], am = S.baro_a[m + 1];
     if (m == 0) {
-        S.se[c] = e;
-        S.su[c] = Uc;
-        S.sv[c] = Vc;
+        S.su[c] = Am * Uc;
+        S.sv[c] = Am * Vc;
+        S.se[c] = am * e;
     } else {
-        S.se[c] += e;
-        S.su[c] += Uc;
-        S.sv[c] += Vc;
+        S.su[c] += Am * Uc;
+        S.sv[c] += Am * Vc;
+        S.se[c] += am * e;
     }
 }
 
-__global__ __launch_bounds__(BX * BY) void k_baro_uv(const DevState S, const double dtau, const int last) {
+__global__ __launch_bounds__(BX * BY) void k_baro_uv(const DevState S, const double dtau, const int m) {
     const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
     if (i >= S.nx || j >= S.ny) return;
     const long long c = idx2(S, i, j);
@@ -52,12 +57,28 @@ __global__ __launch_bounds__(BX * BY) void k_baro_uv(const DevState S, const dou
     S.vbt[c] = Vn;
     wrap2(S, S.ubt, i, j, Un);
     wrap2(S, S.vbt, i, j, Vn);
-    if (last) {
-        const double ns = double(S.n_substeps);
-        S.eta_mean[c] = S.se[c] / ns;
-        S.ubt_mean[c] = S.su[c] / ns;
-        S.vbt_mean[c] = S.sv[c] / ns;
-    }
+    const double am = S.baro_a[m + 1];
+    S.sfu[c] = (m == 0) ? am * Un : S.sfu[c] + am * Un;
+    S.sfv[c] = (m == 0) ? am * Vn : S.sfv[c] + am * Vn;
+}
+
+// After the last substep of the one-substep path: the window averages become
+// the new state (a launch of its own, since neighbours read eta in k_baro_uv).
+__global__ __launch_bounds__(BX * BY) void k_baro_finish(const DevState S) {
+    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (i >= S.nx || j >= S.ny) return;
+    const long long c = idx2(S, i, j);
+    const double ns = double(S.n_substeps);
+    const double e = S.se[c], U = S.sfu[c], V = S.sfv[c];
+    S.eta[c] = e;
+    S.ubt[c] = U;
+    S.vbt[c] = V;
+    wrap2(S, S.eta, i, j, e);
+    wrap2(S, S.ubt, i, j, U);
+    wrap2(S, S.vbt, i, j, V);
+    S.eta_mean[c] = e;
+    S.ubt_mean[c] = S.su[c] / ns;
+    S.vbt_mean[c] = S.sv[c] / ns;
 }
 
 hipError_t launch_barotropic_fused(const DevState& s, hipStream_t st);
@@ -67,10 +88,11 @@ hipError_t launch_barotropic(const DevState& s, hipStream_t st) {
     dim3 block(BX, BY);
     dim3 grid((s.nx + BX - 1) / BX, (s.ny + BY - 1) / BY);
     const double dtau = s.dt / s.n_substeps;
-    for (int m = 0; m < s.n_substeps; ++m) {
+    for (int m = 0; m < s.baro_m; ++m) {
         hipLaunchKernelGGL(k_baro_eta, grid, block, 0, st, s, dtau, m);
-        hipLaunchKernelGGL(k_baro_uv, grid, block, 0, st, s, dtau, (int)(m == s.n_substeps - 1));
+        hipLaunchKernelGGL(k_baro_uv, grid, block, 0, st, s, dtau, m);
     }
+    hipLaunchKernelGGL(k_baro_finish, grid, block, 0, st, s);
     return hipGetLastError();
 }
 
@@ -92,7 +114,8 @@ constexpr int FEW = FBX + 2 * FSMAX, FEH = FBY + 2 * FSMAX, FEN = FEW * FEH;
 constexpr int FT = 512, FQ = (FEN + FT - 1) / FT;
 
 __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const int by, const double dtau,
-                                          const int s, const int first, const int last, const int parity) {
+                                          const int m0, const int s, const int first, const int last,
+                                          const int parity) {
     __shared__ double sE[FEN], sU[FEN], sV[FEN];
     const double* __restrict__ inE = parity ? S.eta2 : S.eta;
     const double* __restrict__ inU = parity ? S.ubt2 : S.ubt;
@@ -106,9 +129,10 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
     const int eh = FBY + 2 * s;
     const int nx = S.nx, ny = S.ny;
 
-    // per owned point: forcing, depths, metrics, accumulators
+    // per owned point: forcing, depths, metrics, window sums
     double gU[FQ], gV[FQ], Hu[FQ], Hv[FQ], rdxc[FQ], dxv0[FQ], dxv1[FQ], rarea[FQ];
-    double aE[FQ], aU[FQ], aV[FQ];
+    double aU[FQ], aV[FQ];          // sum_l A_l U^l, V^l (transport of the step)
+    double fE[FQ], fU[FQ], fV[FQ];  // sum_q a_q eta^q, U^q, V^q (new state)
     int gofs[FQ];
     bool inner[FQ];
 #pragma unroll
@@ -140,14 +164,18 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
             sU[e] = inside ? inU[c] : 0.0;
             sV[e] = inside ? inV[c] : 0.0;
         }
-        aE[q] = (inner[q] && !first) ? S.se[c] : 0.0;
-        aU[q] = (inner[q] && !first) ? S.su[c] : 0.0;
-        aV[q] = (inner[q] && !first) ? S.sv[c] : 0.0;
+        const bool carry = inner[q] && !first;
+        aU[q] = carry ? S.su[c] : 0.0;
+        aV[q] = carry ? S.sv[c] : 0.0;
+        fE[q] = carry ? S.se[c] : 0.0;
+        fU[q] = carry ? S.sfu[c] : 0.0;
+        fV[q] = carry ? S.sfv[c] : 0.0;
     }
     __syncthreads();
 
     const double dy = S.dy, g = S.g;
     for (int m = 0; m < s; ++m) {
+        const double Am = S.baro_A[m0 + m], am = S.baro_a[m0 + m + 1];
         // free surface from the divergence of the transports
         double en[FQ];
 #pragma unroll
@@ -161,9 +189,9 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
                 const double div = dy * (sU[ee] - sU[e]) + dxv1[q] * sV[en_] - dxv0[q] * sV[e];
                 en[q] = sE[e] - dtau * rarea[q] * div;
                 if (inner[q]) {
-                    aU[q] += sU[e];
-                    aV[q] += sV[e];
-                    aE[q] += en[q];
+                    aU[q] += Am * sU[e];
+                    aV[q] += Am * sV[e];
+                    fE[q] += am * en[q];
                 }
             }
         }
@@ -187,6 +215,10 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
                 const int es_ = (lj >= 1) ? e - FEW : e;
                 un[q] = Hu[q] > 0.0 ? sU[e] + dtau * (-g * Hu[q] * (sE[e] - sE[ew_]) * rdxc[q] + gU[q]) : 0.0;
                 vn[q] = Hv[q] > 0.0 ? sV[e] + dtau * (-g * Hv[q] * (sE[e] - sE[es_]) / dy + gV[q]) : 0.0;
+                if (inner[q]) {
+                    fU[q] += am * un[q];
+                    fV[q] += am * vn[q];
+                }
             }
         }
         __syncthreads();
@@ -198,7 +230,8 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
         __syncthreads();
     }
 
-    // write the interior back (with its periodic halo copies) and the running sums
+    // write the interior (with its periodic halo copies): the instantaneous
+    // state between launches, the window averages after the last one
 #pragma unroll
     for (int q = 0; q < FQ; ++q) {
         if (!inner[q]) continue;
@@ -206,31 +239,36 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
         const int li = e % FEW, lj = e / FEW;
         const int gi = i0 - s + li, gj = j0 - s + lj;
         const long long c = gofs[q];
-        outE[c] = sE[e];
-        outU[c] = sU[e];
-        outV[c] = sV[e];
+        const double vE = last ? fE[q] : sE[e];
+        const double vU = last ? fU[q] : sU[e];
+        const double vV = last ? fV[q] : sV[e];
+        outE[c] = vE;
+        outU[c] = vU;
+        outV[c] = vV;
         for_each_image(S, gi, gj, S.h, [&](int x, int y) {
             const long long o = idx2(S, x, y);
-            outE[o] = sE[e];
-            outU[o] = sU[e];
-            outV[o] = sV[e];
+            outE[o] = vE;
+            outU[o] = vU;
+            outV[o] = vV;
         });
         if (last) {
             const double ns = double(S.n_substeps);
-            S.eta_mean[c] = aE[q] / ns;
+            S.eta_mean[c] = fE[q];
             S.ubt_mean[c] = aU[q] / ns;
             S.vbt_mean[c] = aV[q] / ns;
         } else {
-            S.se[c] = aE[q];
             S.su[c] = aU[q];
             S.sv[c] = aV[q];
+            S.se[c] = fE[q];
+            S.sfu[c] = fU[q];
+            S.sfv[c] = fV[q];
         }
     }
 }
 
-__global__ __launch_bounds__(FT) void k_baro_fused(const DevState S, const double dtau, const int s,
+__global__ __launch_bounds__(FT) void k_baro_fused(const DevState S, const double dtau, const int m0, const int s,
                                                    const int first, const int last, const int parity) {
-    baro_tile(S, blockIdx.x, blockIdx.y, dtau, s, first, last, parity);
+    baro_tile(S, blockIdx.x, blockIdx.y, dtau, m0, s, first, last, parity);
 }
 
 // Second buffers back to the primary ones (whole padded arrays, halos included).
@@ -258,22 +296,25 @@ __global__ __launch_bounds__(256) void k_baro_copyback_batched(const DevState* _
 // Ensemble: entry blockIdx.x of the table is (member, bx, by).
 __global__ __launch_bounds__(FT) void k_baro_fused_batched(const DevState* __restrict__ members,
                                                            const int4* __restrict__ tiles, const double dtau,
-                                                           const int s, const int first, const int last,
-                                                           const int parity) {
+                                                           const int m0, const int s, const int first,
+                                                           const int last, const int parity) {
     const int4 e = tiles[blockIdx.x];
-    baro_tile(members[e.x], e.y, e.z, dtau, s, first, last, parity);
+    baro_tile(members[e.x], e.y, e.z, dtau, m0, s, first, last, parity);
 }
+
+int baro_substeps(int n_substeps) { return n_substeps + n_substeps / 2; }
 
 hipError_t launch_barotropic_batched(const DevState* members, int n_members, const int4* tiles, int ntiles,
                                      int n_substeps, int fuse, double dt, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     const int sub = std::max(2, std::min(fuse, FSMAX));
     const double dtau = dt / n_substeps;
+    const int M = baro_substeps(n_substeps);
     int parity = 0;
-    for (int m0 = 0; m0 < n_substeps; m0 += sub, parity ^= 1) {
-        const int ss = std::min(sub, n_substeps - m0);
-        hipLaunchKernelGGL(k_baro_fused_batched, dim3(ntiles), dim3(FT), 0, st, members, tiles, dtau, ss,
-                           (int)(m0 == 0), (int)(m0 + ss == n_substeps), parity);
+    for (int m0 = 0; m0 < M; m0 += sub, parity ^= 1) {
+        const int ss = std::min(sub, M - m0);
+        hipLaunchKernelGGL(k_baro_fused_batched, dim3(ntiles), dim3(FT), 0, st, members, tiles, dtau, m0, ss,
+                           (int)(m0 == 0), (int)(m0 + ss == M), parity);
     }
     if (parity) {  // the result sits in the second buffers
         for (int m0 = 0; m0 < n_members; m0 += 65535)
@@ -287,11 +328,12 @@ hipError_t launch_barotropic_fused(const DevState& s, hipStream_t st) {
     const int sub = std::min(s.baro_fuse, FSMAX);
     dim3 grid((s.nx + FBX - 1) / FBX, (s.ny + FBY - 1) / FBY);
     const double dtau = s.dt / s.n_substeps;
+    const int M = s.baro_m;
     int parity = 0;
-    for (int m0 = 0; m0 < s.n_substeps; m0 += sub, parity ^= 1) {
-        const int ss = std::min(sub, s.n_substeps - m0);
-        hipLaunchKernelGGL(k_baro_fused, grid, dim3(FT), 0, st, s, dtau, ss, (int)(m0 == 0),
-                           (int)(m0 + ss == s.n_substeps), parity);
+    for (int m0 = 0; m0 < M; m0 += sub, parity ^= 1) {
+        const int ss = std::min(sub, M - m0);
+        hipLaunchKernelGGL(k_baro_fused, grid, dim3(FT), 0, st, s, dtau, m0, ss, (int)(m0 == 0), (int)(m0 + ss == M),
+                           parity);
     }
     if (parity) {  // the result sits in the second buffers
         const long long n = (long long)s.p2 * (s.ny + 2 * s.h);

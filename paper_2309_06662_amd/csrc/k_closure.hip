@@ -122,6 +122,36 @@ __global__ __launch_bounds__(FW) void k_kappa_map(const DevState S, const float*
     }
 }
 
+// Convective adjustment: from the state at the start of the step, kappa_conv
+// on interior wet faces where the water above is colder, hence denser, than
+// the water below (N^2 < 0), kappa0 on the other wet faces, 0 on dry ones.
+template <typename R>
+__global__ __launch_bounds__(FW) void k_convective(const DevState S, double kappa_conv, double kappa0) {
+    const int i = blockIdx.x * FW + threadIdx.x, j = blockIdx.y;
+    if (i >= S.nx) return;
+    const int nz = S.nz;
+    const int kbot = nz - S.kb[idxk(S, i, j)];
+    const R* T = f3<R>(S.t);
+    R* kw = f3<R>(S.kw);
+    double below = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        const double tk = (k >= kbot) ? double(T[idx3(S, i, j, k)]) + S.tref[k] : 0.0;
+        const R val = (k > kbot) ? R(tk < below ? kappa_conv : kappa0) : R(0);
+        kw[idx3(S, i, j, k)] = val;
+        for_each_image(S, i, j, S.h, [&](int x, int y) { kw[idx3(S, x, y, k)] = val; });
+        below = tk;
+    }
+}
+
+template <typename R>
+hipError_t launch_convective(const DevState& s, double kappa_conv, double kappa0, hipStream_t st) {
+    dim3 grid((s.nx + FW - 1) / FW, s.ny);
+    hipLaunchKernelGGL(k_convective<R>, grid, dim3(FW), 0, st, s, kappa_conv, kappa0);
+    return hipGetLastError();
+}
+template hipError_t launch_convective<double>(const DevState&, double, double, hipStream_t);
+template hipError_t launch_convective<float>(const DevState&, double, double, hipStream_t);
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_fill(R* p, long long n, R v) {
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;

@@ -227,7 +227,7 @@ __global__ void k_sum_blocks(const float* part, int nb, float* out) {
 // ---------------------------------------------------------------------------
 // Host side: one network with its buffers in a caller arena.
 
-#include "../../include/ocn.h"
+#include "ocn.h"
 
 #include <cmath>
 #include <string>
@@ -398,8 +398,6 @@ extern "C" {
 int ocn_mlp_arena_bytes(int32_t din, int32_t h1, int32_t h2, int32_t dout, int32_t max_batch, size_t* bytes) {
     if (din < 1 || h1 < 1 || h2 < 1 || dout < 1 || max_batch < 1 || !bytes)
         return ocn::set_error(OCN_E_INVALID, "sizes must be >= 1 and bytes non-NULL");
-    if (din % 8 || h1 % 8 || h2 % 8 || dout % 8)
-        return ocn::set_error(OCN_E_INVALID, "layer widths must be multiples of 8");
     *bytes = mlp_plan(din, h1, h2, dout, max_batch).total;
     return OCN_OK;
 }

@@ -3,7 +3,7 @@
 // Builds the grid metrics and masks on the host, lays the state out in the
 // caller's device arena, moves fields between host doubles and the padded
 // device layout, and enqueues the kernels of a step on the caller's stream.
-#include "../../include/ocn.h"
+#include "ocn.h"
 #include "ocn_dev.h"
 
 #include <algorithm>
@@ -80,9 +80,20 @@ struct ocn_state {
     float* norm = nullptr;        // device: mean[din], std[din]
     uint16_t *xb = nullptr, *h1b = nullptr, *h2b = nullptr;
     float* y = nullptr;
+    double kappa_conv = 0.0;      // > 0: convective adjustment into the prescribed field
+    // one step captured as a HIP graph (ocn_step_graph)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
+
+void drop_graph(ocn_state* s) {
+    if (s->exec) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->exec = nullptr;
+    s->graph = nullptr;
+}
 
 int record(ocn_state* s) {
     hipEvent_t e;
@@ -126,12 +137,12 @@ struct Plan {
     size_t oxk, pk, nk;
     size_t nrow;  // metric rows
     size_t diag_blocks;
-    size_t off_f3[9], off_f2[22], off_kb, off_rows[5], off_dz, off_dzc, off_tref, off_dtr, off_cp, off_den, off_a;
+    size_t off_f3[9], off_f2[24], off_bw, off_kb, off_rows[5], off_dz, off_dzc, off_tref, off_dtr, off_cp, off_den, off_a;
     size_t off_part, off_out;
     size_t total;
 };
 
-Plan make_plan(const ocn_grid* g, int precision) {
+Plan make_plan(const ocn_grid* g, int precision, int n_substeps) {
     Plan P{};
     P.esize = precision == OCN_FP32 ? 4 : 8;
     const size_t h = g->h;
@@ -162,8 +173,33 @@ Plan make_plan(const ocn_grid* g, int precision) {
     P.off_a = L.add(g->nz * P.esize);
     P.off_part = L.add(P.diag_blocks * ocn::DG_COUNT * sizeof(double));
     P.off_out = L.add(ocn::DG_COUNT * sizeof(double));
+    P.off_bw = L.add((size_t)(2 * ocn::baro_substeps(std::max(n_substeps, 1)) + 1) * sizeof(double));
     P.total = L.total;
     return P;
+}
+
+// Substep weights of the barotropic window: a_q proportional to cos^2(pi t),
+// t = q/Ns - 1, on |t| < 1/2 (q = 1..M, M = Ns + Ns/2), normalised to sum to
+// one; A_l = sum_{q>l} a_q for l = 0..M-1.
+int upload_substep_weights(ocn_state* s) {
+    const int ns = s->p.n_substeps, M = s->d.baro_m;
+    std::vector<double> w(2 * (size_t)M + 1, 0.0);
+    double sum = 0.0;
+    for (int q = 1; q <= M; ++q) {
+        const double t = double(q) / ns - 1.0;
+        const double c = std::fabs(t) < 0.5 ? std::cos(3.14159265358979323846 * t) : 0.0;
+        w[q] = c * c;
+        sum += w[q];
+    }
+    for (int q = 1; q <= M; ++q) w[q] /= sum;
+    double tail = 0.0;
+    for (int l = M - 1; l >= 0; --l) {
+        tail += w[l + 1];
+        w[M + 1 + l] = tail;
+    }
+    HIPCHK(hipMemcpyAsync(s->d.baro_a, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return OCN_OK;
 }
 
 bool valid_params(const ocn_params* p, std::string& why) {
@@ -590,7 +626,7 @@ int ocn_state_arena_bytes(const ocn_grid* grid, const ocn_params* params, size_t
     if (!grid || !bytes) return fail(OCN_E_INVALID, "grid and bytes must not be NULL");
     std::string why;
     if (!valid_params(params, why)) return fail(OCN_E_INVALID, why);
-    *bytes = make_plan(grid, params->precision).total;
+    *bytes = make_plan(grid, params->precision, params->n_substeps).total;
     return OCN_OK;
 }
 
@@ -601,7 +637,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         std::string why;
         if (!valid_params(params, why)) return fail(OCN_E_INVALID, why);
         if (reinterpret_cast<uintptr_t>(device_arena) % 256) return fail(OCN_E_INVALID, "arena must be 256-byte aligned");
-        const Plan P = make_plan(grid, params->precision);
+        const Plan P = make_plan(grid, params->precision, params->n_substeps);
         if (arena_bytes < P.total) return fail(OCN_E_NOMEM, "arena smaller than ocn_state_arena_bytes");
         if (grid->nz > 128) return fail(OCN_E_UNSUPPORTED, "nz above 128 is not supported by the column kernel");
 
@@ -631,11 +667,11 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         const size_t o3 = ((size_t)h * P.p3 + P.ox3) * P.esize;
         void** f3s[9] = {&d.u, &d.v, &d.t, &d.us, &d.vs, &d.ts, &d.gu, &d.gv, &d.gt};
         for (int q = 0; q < 9; ++q) *f3s[q] = A + P.off_f3[q] + o3;
-        double** f2s[22] = {&d.eta, &d.ubt, &d.vbt, &d.se, &d.su, &d.sv, &d.eta_mean, &d.ubt_mean, &d.vbt_mean,
+        double** f2s[24] = {&d.eta, &d.ubt, &d.vbt, &d.se, &d.su, &d.sv, &d.eta_mean, &d.ubt_mean, &d.vbt_mean,
                             &d.gU, &d.gV, &d.hu, &d.hv, &d.cu, &d.cv, &d.taux, &d.tauy, &d.tstar, &d.scratch2d,
-                            &d.eta2, &d.ubt2, &d.vbt2};
+                            &d.eta2, &d.ubt2, &d.vbt2, &d.sfu, &d.sfv};
         const size_t o2 = (size_t)h * P.p2 + P.ox2;
-        for (int q = 0; q < 22; ++q) *f2s[q] = reinterpret_cast<double*>(A + P.off_f2[q]) + o2;
+        for (int q = 0; q < 24; ++q) *f2s[q] = reinterpret_cast<double*>(A + P.off_f2[q]) + o2;
         d.kb = reinterpret_cast<int*>(A + P.off_kb) + ((size_t)(h + 1) * P.pk + P.oxk);
         double** rows[5] = {&d.dxc, &d.dxv, &d.area, &d.fcor, &d.metric};
         for (int q = 0; q < 5; ++q) *rows[q] = reinterpret_cast<double*>(A + P.off_rows[q]) + h;
@@ -659,6 +695,9 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         d.restore_inv = params->restore_tau > 0.0 ? 1.0 / params->restore_tau : 0.0;
         d.n_substeps = params->n_substeps;
         d.baro_fuse = params->baro_fuse == 0 ? 5 : params->baro_fuse;
+        d.baro_m = ocn::baro_substeps(params->n_substeps);
+        d.baro_a = reinterpret_cast<double*>(A + P.off_bw);
+        d.baro_A = d.baro_a + d.baro_m + 1;
         d.tend_ty = 0;
 
         hipError_t e = hipMemsetAsync(device_arena, 0, P.total, s->st);
@@ -668,6 +707,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
             return fail(OCN_E_DEVICE, std::string("arena clear: ") + hipGetErrorString(e));
         }
         int rc = params->precision == OCN_FP32 ? init_static<float>(s) : init_static<double>(s);
+        if (!rc) rc = upload_substep_weights(s);
         if (rc) {
             delete s;
             return rc;
@@ -684,6 +724,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
 void ocn_state_destroy(ocn_state* state) {
     if (state) {
         (void)hipStreamSynchronize(state->st);
+        drop_graph(state);
         drop_events(state);
         delete state;
     }
@@ -769,27 +810,74 @@ ClosurePlan closure_plan(const ocn_state* s, int din, int h1, int h2, int dout) 
 
 }  // namespace
 
+namespace {
+
+// Enqueue the kernels of one step on the state's stream (no host bookkeeping).
+int enqueue_step(ocn_state* s) {
+    const bool f32 = s->esize == 4;
+    int rc;
+    if (s->timing && (rc = record(s))) return rc;
+    if (s->closure && s->net && (rc = closure_update(s))) return rc;
+    if (s->closure && !s->net && s->kappa_conv > 0.0)
+        HIPCHK(s->esize == 4 ? ocn::launch_convective<float>(s->d, s->kappa_conv, s->p.kappa, s->st)
+                             : ocn::launch_convective<double>(s->d, s->kappa_conv, s->p.kappa, s->st));
+    if (s->timing && (rc = record(s))) return rc;
+    HIPCHK(f32 ? ocn::launch_tendency<float>(s->d, s->first, s->st) : ocn::launch_tendency<double>(s->d, s->first, s->st));
+    if (s->timing && (rc = record(s))) return rc;
+    HIPCHK(ocn::launch_barotropic(s->d, s->st));
+    if (s->timing && (rc = record(s))) return rc;
+    HIPCHK(f32 ? ocn::launch_column<float>(s->d, s->st) : ocn::launch_column<double>(s->d, s->st));
+    if (s->timing) {
+        if ((rc = record(s))) return rc;
+        s->timed_steps += 1;
+    }
+    return OCN_OK;
+}
+
+void advance(ocn_state* s) {
+    s->first = 0;
+    s->step += 1;
+    s->time += s->p.dt;
+}
+
+}  // namespace
+
 int ocn_step(ocn_state* s, int32_t n) {
     if (!s) return fail(OCN_E_INVALID, "state must not be NULL");
     if (n < 0) return fail(OCN_E_INVALID, "n must be >= 0");
-    const bool f32 = s->esize == 4;
     int rc;
     for (int q = 0; q < n; ++q) {
-        if (s->timing && (rc = record(s))) return rc;
-        if (s->closure && s->net && (rc = closure_update(s))) return rc;
-        if (s->timing && (rc = record(s))) return rc;
-        HIPCHK(f32 ? ocn::launch_tendency<float>(s->d, s->first, s->st) : ocn::launch_tendency<double>(s->d, s->first, s->st));
-        if (s->timing && (rc = record(s))) return rc;
-        HIPCHK(ocn::launch_barotropic(s->d, s->st));
-        if (s->timing && (rc = record(s))) return rc;
-        HIPCHK(f32 ? ocn::launch_column<float>(s->d, s->st) : ocn::launch_column<double>(s->d, s->st));
-        if (s->timing) {
-            if ((rc = record(s))) return rc;
-            s->timed_steps += 1;
+        if ((rc = enqueue_step(s))) return rc;
+        advance(s);
+    }
+    return OCN_OK;
+}
+
+int ocn_step_graph(ocn_state* s, int32_t n) {
+    if (!s) return fail(OCN_E_INVALID, "state must not be NULL");
+    if (n < 0) return fail(OCN_E_INVALID, "n must be >= 0");
+    if (!s->st) return fail(OCN_E_UNSUPPORTED, "graph stepping needs a stream other than the null stream");
+    int rc;
+    for (int q = 0; q < n; ++q) {
+        if (s->first || s->timing) {  // the start step and timed steps run eagerly
+            if ((rc = enqueue_step(s))) return rc;
+        } else {
+            if (!s->exec) {
+                HIPCHK(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
+                rc = enqueue_step(s);
+                hipGraph_t g = nullptr;
+                hipError_t ce = hipStreamEndCapture(s->st, &g);
+                if (rc) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return rc;
+                }
+                if (ce != hipSuccess) return fail(OCN_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+                s->graph = g;
+                HIPCHK(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+            }
+            HIPCHK(hipGraphLaunch(s->exec, s->st));
         }
-        s->first = 0;
-        s->step += 1;
-        s->time += s->p.dt;
+        advance(s);
     }
     return OCN_OK;
 }
@@ -823,6 +911,7 @@ int ocn_closure_attach(ocn_state* s, const ocn_mlp* net, const float* norm, size
     const ClosurePlan P = closure_plan(s, din, h1, h2, dout);
     if (bytes < P.total) return fail(OCN_E_NOMEM, "workspace smaller than ocn_closure_workspace_bytes");
     HIPCHK(hipStreamSynchronize(s->st));
+    drop_graph(s);
     unsigned char* W = static_cast<unsigned char*>(workspace);
     const size_t o3 = ((size_t)s->g->h * s->d.p3 + s->ox3) * s->esize;
     HIPCHK(s->esize == 4 ? ocn::launch_fill<float>(W + P.kw, (long long)s->n3, s->p.kappa, s->st)
@@ -843,10 +932,22 @@ int ocn_closure_attach(ocn_state* s, const ocn_mlp* net, const float* norm, size
     return OCN_OK;
 }
 
+int ocn_closure_convective(ocn_state* s, double kappa_conv) {
+    if (!s) return fail(OCN_E_INVALID, "state must not be NULL");
+    if (!s->closure || s->net) return fail(OCN_E_STATE, "needs a prescribed-field closure attached");
+    if (!std::isfinite(kappa_conv)) return fail(OCN_E_INVALID, "kappa_conv must be finite");
+    HIPCHK(hipStreamSynchronize(s->st));
+    drop_graph(s);
+    s->kappa_conv = kappa_conv > 0.0 ? kappa_conv : 0.0;
+    return OCN_OK;
+}
+
 int ocn_closure_detach(ocn_state* s) {
     if (!s) return fail(OCN_E_INVALID, "state must not be NULL");
     HIPCHK(hipStreamSynchronize(s->st));
+    drop_graph(s);
     s->closure = false;
+    s->kappa_conv = 0.0;
     s->net = nullptr;
     s->d.kw = nullptr;
     s->norm = nullptr; s->xb = s->h1b = s->h2b = nullptr; s->y = nullptr;
@@ -1049,7 +1150,7 @@ int ens_plan(const ocn_grid* const* grids, int n, const ocn_params* params, EnsP
     Layout L;
     P.cap_tend = P.cap_col = P.cap_baro = 0;
     for (int m = 0; m < n; ++m) {
-        const size_t b = make_plan(grids[m], params->precision).total;
+        const size_t b = make_plan(grids[m], params->precision, params->n_substeps).total;
         P.member_off.push_back(L.add(b));
         P.member_bytes.push_back(b);
         P.cap_tend += tend_tiles(grids[m], 4);  // the larger of the two tile shapes

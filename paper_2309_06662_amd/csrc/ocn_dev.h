@@ -44,7 +44,7 @@ struct DevState {
     void *gu, *gv, *gt;     // AB2 history G^{n-1}, overwritten with G^n
     // 2D FP64
     double *eta, *ubt, *vbt;             // barotropic state
-    double *se, *su, *sv;                // substep running sums
+    double *se, *su, *sv;                // window sums of eta^q; transport sums of U^l, V^l
     double *eta_mean, *ubt_mean, *vbt_mean;
     double *gU, *gV;                     // slow forcing: depth integral of the AB2 momentum tendency
     double *hu, *hv;                     // depth of u and v columns
@@ -53,6 +53,10 @@ struct DevState {
     double *tstar;                       // restoring target minus tref(top)
     double *scratch2d;                   // one 2D field of scratch
     double *eta2, *ubt2, *vbt2;          // second buffers of the temporally blocked substeps
+    double *sfu, *sfv;                   // window sums of U^q, V^q
+    double *baro_a;                      // M + 1 substep weights a_q (a_0 unused)
+    double *baro_A;                      // M tail sums A_l = sum_{q>l} a_q
+    int baro_m;                          // substeps per step: Ns + Ns/2
     // int32 wet layers per column counted from the surface, with a halo of hk
     // (periodic images wrapped, zero beyond walls)
     int* kb;
@@ -120,6 +124,8 @@ template <typename R> hipError_t launch_colsum(const DevState& s, hipStream_t st
 size_t features_lds(int din);
 template <typename R> hipError_t launch_fill(void* p, long long n, double v, hipStream_t st);
 template <typename R>
+hipError_t launch_convective(const DevState& s, double kappa_conv, double kappa0, hipStream_t st);
+template <typename R>
 hipError_t launch_features(const DevState& s, int din, const float* norm, void* out, int out_bf16, hipStream_t st);
 template <typename R>
 hipError_t launch_kappa_map(const DevState& s, const float* Y, int ldy, double kappa0, hipStream_t st);
@@ -139,6 +145,7 @@ hipError_t launch_tendency_batched(const DevState* members, const int4* tiles, i
                                    hipStream_t st);
 template <typename R>
 hipError_t launch_column_batched(const DevState* members, const int4* tiles, int ntiles, int max_nz, hipStream_t st);
+int baro_substeps(int n_substeps);  // Ns + Ns/2
 hipError_t launch_barotropic_batched(const DevState* members, int n_members, const int4* tiles, int ntiles,
                                      int n_substeps, int fuse, double dt, hipStream_t st);
 constexpr int kBaroTileX = 64, kBaroTileY = 16;

@@ -118,7 +118,7 @@ class Workload:
     kappa: float = 1e-5
     dt: float = 1200.0
     n_substeps: int = 30
-    chi: float = 0.0
+    chi: float = 0.1                    # AB2 offset (quasi-second-order form)
     tau0: float = 0.1                   # wind-stress amplitude, N/m^2
     restore_days: float = 0.0           # <= 0: no restoring
     strat_t0: float = 20.0              # T = strat_t0 * exp(z / strat_scale) + noise

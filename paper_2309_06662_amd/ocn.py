@@ -30,7 +30,7 @@ FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "kappa"}
 # Functions declared in include/ocn.h.
 ABI_FUNCTIONS = ["ocn_abi_version", "ocn_last_error", "ocn_grid_create", "ocn_grid_destroy",
                  "ocn_state_arena_bytes", "ocn_state_init", "ocn_state_destroy", "ocn_set_field",
-                 "ocn_get_field", "ocn_set_first_step", "ocn_get_first_step", "ocn_step",
+                 "ocn_get_field", "ocn_set_first_step", "ocn_get_first_step", "ocn_step", "ocn_step_graph",
                  "ocn_diagnostics", "ocn_synchronize", "ocn_stage_timing", "ocn_stage_times",
                  "ocn_checkpoint_bytes", "ocn_checkpoint_save", "ocn_checkpoint_load",
                  "ocn_ensemble_arena_bytes", "ocn_ensemble_init", "ocn_ensemble_destroy", "ocn_ensemble_member",
@@ -38,7 +38,7 @@ ABI_FUNCTIONS = ["ocn_abi_version", "ocn_last_error", "ocn_grid_create", "ocn_gr
                  "ocn_mlp_arena_bytes", "ocn_mlp_init", "ocn_mlp_destroy", "ocn_mlp_param_count",
                  "ocn_mlp_set_params", "ocn_mlp_get_params", "ocn_mlp_forward", "ocn_mlp_gradients",
                  "ocn_mlp_train_step", "ocn_closure_workspace_bytes", "ocn_closure_attach",
-                 "ocn_closure_detach", "ocn_closure_features", "ocn_closure_kappa"]
+                 "ocn_closure_detach", "ocn_closure_features", "ocn_closure_kappa", "ocn_closure_convective"]
 
 
 class OcnError(RuntimeError):
@@ -95,6 +95,7 @@ def lib():
         L.ocn_set_first_step.argtypes = [C.c_void_p, C.c_int32]
         L.ocn_get_first_step.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
         L.ocn_step.argtypes = [C.c_void_p, C.c_int32]
+        L.ocn_step_graph.argtypes = [C.c_void_p, C.c_int32]
         L.ocn_diagnostics.argtypes = [C.c_void_p, C.POINTER(Diag)]
         L.ocn_synchronize.argtypes = [C.c_void_p]
         L.ocn_checkpoint_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
@@ -124,6 +125,7 @@ def lib():
         L.ocn_closure_workspace_bytes.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]
         L.ocn_closure_attach.argtypes = [C.c_void_p, C.c_void_p, _F, C.c_size_t, C.c_void_p, C.c_size_t]
         L.ocn_closure_detach.argtypes = [C.c_void_p]
+        L.ocn_closure_convective.argtypes = [C.c_void_p, C.c_double]
         L.ocn_closure_features.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
         L.ocn_closure_kappa.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
         L.ocn_stage_times.argtypes = [C.c_void_p, _D, C.c_int32, C.POINTER(C.c_int64)]
@@ -243,8 +245,12 @@ class Model:
     def first_step(self, v: bool):
         _check(lib().ocn_set_first_step(self.handle, int(bool(v))), "ocn_set_first_step")
 
-    def step(self, n: int = 1):
-        _check(lib().ocn_step(self.handle, int(n)), "ocn_step")
+    def step(self, n: int = 1, graph: bool = False):
+        """Enqueue n steps; graph=True replays one captured step (needs a non-default stream)."""
+        if graph:
+            _check(lib().ocn_step_graph(self.handle, int(n)), "ocn_step_graph")
+        else:
+            _check(lib().ocn_step(self.handle, int(n)), "ocn_step")
 
     def checkpoint(self) -> bytes:
         n = C.c_size_t()
@@ -284,6 +290,10 @@ class Model:
         self._closure_net = net
         _check(lib().ocn_closure_attach(self.handle, nh, nptr, ncount, C.c_void_p(aligned), n.value),
                "ocn_closure_attach")
+
+    def set_convective(self, kappa_conv: float):
+        """Convective adjustment (needs attach_closure() without a network): kappa_conv where N^2 < 0."""
+        _check(lib().ocn_closure_convective(self.handle, float(kappa_conv)), "ocn_closure_convective")
 
     def detach_closure(self):
         _check(lib().ocn_closure_detach(self.handle), "ocn_closure_detach")

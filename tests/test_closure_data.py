@@ -74,8 +74,8 @@ def test_kappa_target():
     flux[1:] = -2e-5                              # down-gradient flux: kappa0 + 2e-5 / 0.01
     y = ct.kappa_target(flux, Tc, dz, 1e-5)
     assert np.allclose(10 ** y, 1e-5 + 2e-3, rtol=1e-12)
-    flux[1:] = -1.0                               # clipped above
-    assert np.allclose(10 ** ct.kappa_target(flux, Tc, dz, 1e-5), 0.1)
+    flux[1:] = -100.0                             # clipped above
+    assert np.allclose(10 ** ct.kappa_target(flux, Tc, dz, 1e-5), 1.0)
 
 
 def test_mixed_layer_depth():
@@ -85,3 +85,30 @@ def test_mixed_layer_depth():
     T2 = np.full((6, 1, 1), 5.0)
     assert ct.mixed_layer_depth(T2, dz)[0, 0] == 55.0   # no such layer: the deepest centre
     assert np.isclose(ct.heat_content(T2, dz)[0, 0], 300.0)
+
+
+def test_subgrid_flux_includes_mixing_beyond_the_background():
+    coarse, fine, cg = _pair()
+    nz = fine.nz
+    dz = np.full(nz, 10.0)
+    T = np.broadcast_to((0.02 * np.arange(nz))[:, None, None], (nz, fine.ny, fine.nx)).copy()  # dT/dz = 0.002
+    W = np.zeros((nz + 1, fine.ny, fine.nx))
+    kap = np.full((nz, fine.ny, fine.nx), 1e-5)
+    kap[3] = 0.5                                  # one mixed face
+    fl = ct.eddy_flux(cg, T, W, kap, 1e-5, dz)
+    assert np.allclose(fl[3], -(0.5 - 1e-5) * 0.002, rtol=1e-12)
+    assert np.allclose(np.delete(fl, 3, axis=0), 0.0, atol=1e-18)
+
+
+def test_kappa_target_counts_unstable_down_gradient_flux():
+    """Cold over warm (dT/dz < 0) with an upward heat flux is down-gradient:
+    the target diffusivity is positive, not the background."""
+    nz = 3
+    dz = np.full(nz, 10.0)
+    Tc = np.array([5.0, 4.9, 4.8])[:, None, None]       # dT/dz = -0.01 K/m
+    flux = np.zeros((nz, 1, 1))
+    flux[1:] = 2e-4                                    # upward
+    k = 10 ** ct.kappa_target(flux, Tc, dz, 1e-5)
+    assert np.allclose(k[1:2], 1e-5 + 2e-4 / 0.01, rtol=1e-12)
+    flux[1:] = -2e-4                                   # counter-gradient: background only
+    assert np.allclose(10 ** ct.kappa_target(flux, Tc, dz, 1e-5), 1e-5)

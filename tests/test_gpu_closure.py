@@ -12,7 +12,10 @@
   activations, wide accumulation -- the oracle's output map and the oracle's
   step) against the GPU's network inside its step. What remains is FP32
   versus FP64 accumulation in the products and the rare BF16 rounding tie it
-  flips: kappa within 1e-3, states within 1e-6 relative L2. The plain FP64
+  flips: one flip moves a hidden activation by one BF16 ulp (2^-8 relative),
+  log10 kappa by up to about 1e-3 and kappa by up to about 0.3 percent, so
+  kappa agrees within 1e-2 (a few flips) and the states, where diffusion is a
+  small share of each step's change, within 1e-6 relative L2. The plain FP64
   network (no BF16 activations) stays within 5 percent in kappa.
 """
 import numpy as np
@@ -196,9 +199,36 @@ def test_network_closure_end_to_end():
         m = kw != 0
         kerr = np.max(np.abs(kg[m] / kw[m] - 1.0))
         print(f"step {step + 1}: max kappa relative difference {kerr:.2e}", flush=True)
-        assert kerr <= 1e-3
+        assert kerr <= 1e-2
         if step == 0:
             perr = np.max(np.abs(kg[m] / kp[m] - 1.0))
             print(f"  vs the plain FP64 network: {perr:.2e}", flush=True)
             assert perr <= 0.05
     _compare(ref, gpu, w, inp["kbottom"], 1e-6)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+def test_convective_adjustment_matches_oracle(precision, tol):
+    """Convective adjustment (kappa_conv on faces with N^2 < 0, from the state
+    at the start of each step) on a regional box whose top layer starts 10 K
+    too cold in half of the columns."""
+    from paper_2309_06662_amd import closure_train
+
+    w, _ = closure_train.regional_pair(nx=40, ny=24, nz=10)
+    inp = inputs.make_inputs(w)
+    T0 = inp["T0"].copy()
+    T0[-1, :, ::2] -= 10.0
+    inp["T0"] = T0
+    ref = oracle.OracleModel.from_inputs(w, inp)
+    ref.set_convective(0.5)
+    gpu = _ocn().Model(w, precision, inp)
+    gpu.attach_closure()
+    gpu.set_convective(0.5)
+    ref.step(1)
+    gpu.step(1)
+    kr, kg = ref.get("kappa"), gpu.get("kappa")
+    assert np.array_equal(kr == 0.5, np.isclose(kg, 0.5)), "unstable faces differ"
+    assert (kr == 0.5).sum() > 0
+    ref.step(19)
+    gpu.step(19)
+    _compare(ref, gpu, w, inp["kbottom"], tol)

@@ -154,3 +154,23 @@ def test_kappa_map():
     assert np.all(kw[:, 0, 2] == 0)
     c = [1e-7, 1.0, 1e-3, 1e-5, 1e-2]   # clipped, clipped, plain, non-finite -> kappa0, plain
     assert np.allclose(kw[1:, 0, 3], [0.5 * (c[k - 1] + c[k]) for k in range(1, nz)], rtol=1e-13)
+
+
+def test_convective_adjustment_mixes_unstable_faces_only():
+    """A column with dense (cold) water over light water mixes those faces with
+    kappa_conv; stable faces keep the constant: one step equals the dense
+    backward-Euler solve with that face field, and the field follows T."""
+    nz = 6
+    w = _column_workload(1, nz, kappa=1e-5)
+    dz = np.full(nz, 50.0)
+    m = oracle.OracleModel(w, dz, np.full((1, 1), nz, dtype=np.int32))
+    Tcol = np.array([4.0, 5.0, 6.0, 5.5, 7.0, 6.0])   # bottom first: faces 3 and 5 unstable
+    m.set("T", Tcol[:, None, None])
+    m.set_convective(0.5)
+    m.step(1)
+    kf = np.array([0.0, 1e-5, 1e-5, 0.5, 1e-5, 0.5])
+    exp = _dense_backward_euler(Tcol, dz, kf, w.dt)
+    assert np.allclose(m.get("T")[:, 0, 0], exp, rtol=0, atol=1e-12)
+    assert np.array_equal(m.get("kappa")[:, 0, 0], kf)
+    m.set_convective(0.0)
+    assert np.all(m.get("kappa")[1:, 0, 0] == 1e-5)

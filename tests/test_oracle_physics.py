@@ -21,6 +21,22 @@ from paper_2309_06662_amd import inputs
 from tests.helpers import masks, metrics, small_latlon
 
 
+def _window(ns):
+    """Substep weights a_q (q = 1..M, M = Ns + Ns/2): cos^2(pi t), t = q/Ns - 1, |t| < 1/2, normalised."""
+    M = ns + ns // 2
+    q = np.arange(1, M + 1)
+    t = q / ns - 1.0
+    a = np.where(np.abs(t) < 0.5, np.cos(np.pi * t) ** 2, 0.0)
+    return q, a / a.sum()
+
+
+def test_substep_window():
+    """The window is centred on t^{n+1}: weights sum to one, first moment Ns."""
+    for ns in (1, 5, 30, 60):
+        q, a = _window(ns)
+        assert abs(a.sum() - 1.0) < 1e-15 and abs((q * a).sum() - ns) < 1e-12 * ns
+
+
 def test_rest_state_stays_at_rest():
     w = inputs.BETA_BASIN_64.replace(nx=16, ny=12, noise_std=0.0, tau0=0.0)
     inp = inputs.make_inputs(w)
@@ -30,7 +46,9 @@ def test_rest_state_stays_at_rest():
     m.step(20)
     for name in ("u", "v", "U", "V", "U_mean", "V_mean"):
         assert np.all(m.get(name) == 0.0), name
-    assert np.all(m.get("eta") == 0.125) and np.all(m.get("eta_mean") == 0.125)
+    # the weighted substep average of a constant surface is that constant to round-off
+    for name in ("eta", "eta_mean"):
+        assert np.max(np.abs(m.get(name) - 0.125)) <= 4e-16, name
     assert np.all(m.get("w") == 0.0)
     T = m.get("T")
     assert np.all(T == T[:, :1, :1])
@@ -89,11 +107,13 @@ def test_conservation_and_consistency(case):
     assert np.max(np.abs(m.get("u"))) > 0
 
 
-def test_gravity_wave_frequency():
+def test_gravity_wave_frequency_and_filter_damping():
     """Closed channel, flat 4 km, f = 0, T = 0: eta = 0.01 cos(pi x / L) is a
-    discrete eigenmode. Sampled once per baroclinic step, eta obeys
-    eta^{n+1} + eta^{n-1} = 2 cos(omega dt) eta^n with the forward-backward
-    frequency omega = (2/dtau) asin((c dtau/dx) sin(pi dx / (2L))), c = sqrt(gH)."""
+    discrete eigenmode. Each forward-backward substep rotates it by
+    theta = 2 asin((c dtau/dx) sin(pi dx/(2L))), c = sqrt(gH); the step returns the
+    window average sum_q a_q B^q, whose eigenvalues are R e^(+-i Ns theta) with
+    R = sum_q a_q cos((q - Ns) theta) for weights symmetric about Ns. Sampled once
+    per step, eta obeys eta^{n+1} = 2 R cos(Ns theta) eta^n - R^2 eta^{n-1}."""
     w = inputs.BETA_BASIN_64.replace(ny=2, nz=2, f0=0.0, beta=0.0, tau0=0.0, noise_std=0.0,
                                      strat_t0=0.0, kappa=0.0)
     inp = inputs.make_inputs(w)
@@ -102,17 +122,24 @@ def test_gravity_wave_frequency():
     x = (np.arange(w.nx) + 0.5) * w.dx
     m.set("eta", np.broadcast_to(0.01 * np.cos(math.pi * x / L), (w.ny, w.nx)).copy())
     hist = [m.get("eta")]
-    for _ in range(100):
+    for _ in range(60):
         m.step(1)
         hist.append(m.get("eta"))
-    e = np.array(hist)
-    num = np.sum((e[2:] + e[:-2]) * e[1:-1])
-    den = np.sum(2.0 * e[1:-1] ** 2)
-    omega = math.acos(num / den) / w.dt
+    e = np.array(hist).reshape(len(hist), -1)
+    # least-squares fit of eta^{n+1} = A eta^n + B eta^{n-1} over all points and steps
+    X = np.stack([e[1:-1].ravel(), e[:-2].ravel()], axis=1)
+    (A, B), *_ = np.linalg.lstsq(X, e[2:].ravel(), rcond=None)
+    R_obs = math.sqrt(-B)
+    omega = math.acos(A / (2 * R_obs)) / w.dt
     c = math.sqrt(w.g * w.depth)
-    dtau = w.dt / w.n_substeps
-    expect = 2.0 / dtau * math.asin(c * dtau / w.dx * math.sin(math.pi * w.dx / (2 * L)))
-    assert abs(omega - expect) <= 1e-5 * expect
+    ns = w.n_substeps
+    dtau = w.dt / ns
+    theta = 2.0 * math.asin(c * dtau / w.dx * math.sin(math.pi * w.dx / (2 * L)))
+    q, a = _window(ns)
+    R = float(np.sum(a * np.cos((q - ns) * theta)))
+    assert abs(omega - ns * theta / w.dt) <= 1e-6 * omega
+    assert abs(R_obs - R) <= 1e-9
+    assert R < 1.0
     # and the continuous long-wave period 2L/c is within the discretisation error
     assert abs(2 * math.pi / omega - 2 * L / c) / (2 * L / c) < 2e-4
 
@@ -121,10 +148,10 @@ def test_gravity_wave_frequency():
 def test_inertial_oscillation_follows_split_ab2(chi):
     """Uniform flow on a doubly periodic f-plane, q = u + i v of the 3D flow and
     Q = (U + i V) / H of the barotropic mode. With no surface slope the
-    substeps add the slow forcing linearly, so with a = -i f dt,
-    G = a [(3/2+chi) q^n - (1/2+chi) q^{n-1}] (a q^0 on the first step) and
-    c = (Ns-1)/(2Ns): Q^{n+1} = Q^n + G and, the depth mean being replaced by
-    the substep average, q^{n+1} = Q^n + c G."""
+    substeps add the slow forcing linearly, so with a = -i f dt and
+    G = a [(3/2+chi) q^n - (1/2+chi) q^{n-1}] (a q^0 on the first step):
+    Q^{n+1} = Q^n + G (the window is centred on t^{n+1}) and, the depth mean
+    being replaced by the step's transport, q^{n+1} = Q^n + c G."""
     f, dt = 1e-4, 1200.0
     w = inputs.Workload(name="inertial", nx=4, ny=4, nz=3, periodic_x=True, periodic_y=True,
                         f0=f, beta=0.0, tau0=0.0, noise_std=0.0, dt=dt, chi=chi)
@@ -133,13 +160,15 @@ def test_inertial_oscillation_follows_split_ab2(chi):
     shape = (w.nz, w.ny, w.nx)
     m.set("u", np.full(shape, 0.1))
     m.set("U", np.full((w.ny, w.nx), 0.1 * w.depth))
-    c = (w.n_substeps - 1) / (2.0 * w.n_substeps)
+    # the substeps add the slow forcing linearly, U^l = U^n + l dtau G/dt, so the
+    # window average is U^n + G (first moment Ns) and Ubar = U^n + c G with
+    # c = sum_l A_l l / Ns^2 = sum_q a_q q (q - 1) / (2 Ns^2)
+    q, a = _window(w.n_substeps)
+    c = float(np.sum(a * q * (q - 1))) / (2.0 * w.n_substeps ** 2)
     zs = [0.1 + 0j]
     for n in range(100):
         Ub = m.get("U")
         m.step(1)
-        # no surface slope: U^m grows linearly over the substeps, so the average of
-        # U^0..U^{Ns-1} sits (Ns-1)/(2Ns) of the way from U^n to U^{n+1}
         Um_expect = Ub + c * (m.get("U") - Ub)
         assert np.max(np.abs(m.get("U_mean") - Um_expect)) <= 1e-12 * np.max(np.abs(Ub))
         u, v = m.get("u"), m.get("v")
