@@ -283,9 +283,10 @@ int ocn_closure_convective(ocn_state* state, double kappa_conv);
  * or raw when norm_dev is NULL; dry entries are 0. Asynchronous. */
 int ocn_closure_features(ocn_state* state, int32_t din, const float* norm_dev, float* x_dev);
 /* Network outputs (device FP32, (ny nx) rows of leading dimension ldy >= nz:
- * log10 diffusivity at layer centres) to the attached face field: a centre
- * value is 10^y clipped to [1e-7, 1] m^2/s, or the constant kappa where y is
- * not finite; a wet face takes the mean of its two centres. Asynchronous. */
+ * slot k = log10 diffusivity on z-face k, between layers k-1 and k; slot 0 is
+ * unused) to the attached face field: a wet interior face takes 10^y clipped
+ * to [1e-7, 1] m^2/s, or the constant kappa where y is not finite; dry faces
+ * take 0. Asynchronous. */
 int ocn_closure_kappa(ocn_state* state, const float* y_dev, int32_t ldy);
 
 /* Checkpoint and resume. ocn_checkpoint_bytes reports the size of a

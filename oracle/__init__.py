@@ -187,7 +187,7 @@ class OracleModel:
         return X
 
     def closure_kappa(self, Y, kappa0: float) -> np.ndarray:
-        """Face diffusivity [nz, ny, nx] from network outputs Y ((ny*nx) x nz, log10 kappa at centres)."""
+        """Face diffusivity [nz, ny, nx] from network outputs Y ((ny*nx) x nz, log10 kappa on faces, slot 0 unused)."""
         Y = _c(Y).reshape(self.ny * self.nx, self.nz)
         kw = np.zeros((self.nz, self.ny, self.nx))
         lib().orc_closure_kappa(self._h, _dptr(Y), kappa0, _dptr(kw))

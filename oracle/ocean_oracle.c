@@ -938,11 +938,11 @@ int orc_closure_features(const orc_model* m, int din, const double* mean, const 
     return 0;
 }
 
-/* Network output -> face diffusivity. Y is (ny nx) x nz: log10 of the
- * diffusivity at the centres of the column's layers. A centre value is
- * 10^y clipped to [1e-7, 1] m^2/s, or kappa0 when y is not finite; face k
- * (between layers k-1 and k) takes the mean of its two centres where both are
- * wet, else 0. kw is nz x ny x nx like ORC_KAPPA (slot 0 unused, 0). */
+/* Network output -> face diffusivity. Y is (ny nx) x nz: slot k holds log10
+ * of the diffusivity on face k (between layers k-1 and k; slot 0, the bottom
+ * face, is unused). A wet interior face takes 10^y clipped to [1e-7, 1] m^2/s,
+ * or kappa0 when y is not finite; dry faces take 0. kw is nz x ny x nx like
+ * ORC_KAPPA (slot 0 is 0). */
 void orc_closure_kappa(const orc_model* m, const double* Y, double kappa0, double* kw) {
     const int nz = m->nz;
     for (int j = 0; j < m->ny; ++j)
@@ -950,14 +950,7 @@ void orc_closure_kappa(const orc_model* m, const double* Y, double kappa0, doubl
             const double* y = Y + id2(m, i, j) * (size_t)nz;
             for (int k = 0; k < nz; ++k) {
                 double v = 0.0;
-                if (w_wet(m, i, j, k)) {
-                    double c[2];
-                    for (int q = 0; q < 2; ++q) {
-                        const double yy = y[k - 1 + q];
-                        c[q] = isfinite(yy) ? fmin(1.0, fmax(1e-7, pow(10.0, yy))) : kappa0;
-                    }
-                    v = 0.5 * (c[0] + c[1]);
-                }
+                if (w_wet(m, i, j, k)) v = isfinite(y[k]) ? fmin(1.0, fmax(1e-7, pow(10.0, y[k]))) : kappa0;
                 kw[id3(m, i, j, k)] = v;
             }
         }

@@ -122,11 +122,12 @@ def eddy_flux(cg, T, W, kappa=None, kappa0=0.0, dz=None):
 
 
 def kappa_target(flux, Tc, dz, kappa0):
-    """log10 of kappa_eff at layer centres from face eddy fluxes and coarse T, [nz, ny, nx]."""
+    """log10 of kappa_eff on z-faces (slot k = face between layers k-1 and k,
+    slot 0 the background) from face subgrid fluxes and coarse T, [nz, ny, nx]."""
     nz = Tc.shape[0]
     dzc = np.zeros(nz)
     dzc[1:] = 0.5 * (dz[1:] + dz[:-1])
-    kf = np.full_like(flux, np.nan)
+    kf = np.full_like(flux, kappa0)
     dTdz = np.zeros_like(flux)
     dTdz[1:] = (Tc[1:] - Tc[:-1]) / dzc[1:, None, None]
     # down-gradient flux in either stratification: the gradient keeps its sign,
@@ -134,12 +135,7 @@ def kappa_target(flux, Tc, dz, kappa0):
     g = dTdz[1:]
     den = np.where(g >= 0.0, 1.0, -1.0) * np.maximum(np.abs(g), 1e-6)
     kf[1:] = kappa0 + np.maximum(0.0, -flux[1:] / den)
-    kf = np.clip(kf, 1e-6, 1.0)
-    kc = np.empty_like(kf)
-    kc[0] = kf[1]
-    kc[nz - 1] = kf[nz - 1]
-    kc[1:nz - 1] = 0.5 * (kf[1:nz - 1] + kf[2:nz])
-    return np.log10(kc)
+    return np.log10(np.clip(kf, 1e-6, 1.0))
 
 
 def mixed_layer_depth(T, dz, thresh=0.2):
@@ -165,7 +161,7 @@ def _log(msg):
     print(f"[closure] {msg}", flush=True)
 
 
-def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_samples=8, epochs=30,
+def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_samples=2, epochs=60,
         batch=4096, lr=1e-3, hidden=128, seed=0, convective=1.0, coarse_kw=None):
     import torch
 
@@ -200,20 +196,25 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
         return {"u": cg.u_faces(u), "v": cg.v_faces(v), "T": cg.cells(T), "eta": cg.cells(eta)}, flux
 
     X_list, Y_list, snaps = [], [], {}
-    acc = None
+    acc, start_state = None, None
     t0 = time.time()
     for s in range(1, n_samples + 1):
         fm.step(steps_per_sample)
         st, flux = coarse_state()
+        if start_state is None:
+            start_state = st
         acc = flux if acc is None else acc + flux
         if s % window_samples == 0:
             flux_w = acc / window_samples
             acc = None
-            y = kappa_target(flux_w, st["T"], dz, coarse.kappa)
-            kz = np.arange(nz)[:, None, None] < nz - inp_c["kbottom"][None]
-            y = np.where(kz, math.log10(coarse.kappa), y)     # dry levels: the background
+            y = kappa_target(flux_w, start_state["T"], dz, coarse.kappa)
+            kwet = np.zeros((nz, coarse.ny, coarse.nx), bool)           # wet interior faces
+            kk = np.arange(nz)[:, None, None]
+            kwet[1:] = (kk[1:] > nz - inp_c["kbottom"][None])
+            y = np.where(kwet, y, math.log10(coarse.kappa))
             for n in ("u", "v", "T"):
-                cm.set(n, st[n])
+                cm.set(n, start_state[n])
+            start_state = None
             X = cm.closure_features(din).cpu().numpy()
             cols = cg.valid_col.reshape(-1)
             if s <= eval_start:
@@ -314,8 +315,8 @@ def main():
     ap.add_argument("--days", type=float, default=20.0)
     ap.add_argument("--eval-days", type=float, default=4.0)
     ap.add_argument("--sample-hours", type=float, default=3.0)
-    ap.add_argument("--window", type=int, default=8)
-    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--window", type=int, default=2)
+    ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--nx", type=int, default=96)
     ap.add_argument("--ny", type=int, default=64)
     ap.add_argument("--nz", type=int, default=50)

@@ -14,9 +14,9 @@
 //  padding. Wet entries are normalised with per-feature mean and standard
 //  deviation; dry entries are 0.
 //
-//  k_kappa_map: network output (log10 diffusivity at layer centres) to face
-//  diffusivity: 10^y clipped to [1e-7, 1] m^2/s, kappa0 where y is not finite,
-//  face value the mean of its two centres; periodic images are written too.
+//  k_kappa_map: network output (log10 diffusivity on each z-face, slot 0 the
+//  unused bottom face) to the face field: 10^y clipped to [1e-7, 1] m^2/s on
+//  wet interior faces, kappa0 where y is not finite; periodic images too.
 #include "ocn_dev.h"
 
 #include <cstdint>
@@ -97,8 +97,7 @@ __global__ __launch_bounds__(FW) void k_features(const DevState S, int din, cons
     }
 }
 
-template <typename R>
-__device__ __forceinline__ double centre_kappa(float y, double kappa0) {
+__device__ __forceinline__ double face_kappa_of(float y, double kappa0) {
     if (!isfinite(y)) return kappa0;
     return fmin(1.0, fmax(1e-7, exp10(double(y))));
 }
@@ -112,13 +111,10 @@ __global__ __launch_bounds__(FW) void k_kappa_map(const DevState S, const float*
     const int kbot = nz - S.kb[idxk(S, i, j)];
     const float* y = Y + ((long long)j * S.nx + i) * ldy;
     R* kw = f3<R>(S.kw);
-    double below = 0.0;
     for (int k = 0; k < nz; ++k) {
-        const double c = (k >= kbot) ? centre_kappa<R>(y[k], kappa0) : 0.0;
-        const R val = (k > kbot) ? R(0.5 * (below + c)) : R(0);
+        const R val = (k > kbot) ? R(face_kappa_of(y[k], kappa0)) : R(0);
         kw[idx3(S, i, j, k)] = val;
         for_each_image(S, i, j, S.h, [&](int x, int yy) { kw[idx3(S, x, yy, k)] = val; });
-        below = c;
     }
 }
 

@@ -70,12 +70,12 @@ def test_kappa_target():
     Tc = np.broadcast_to((0.1 * np.arange(nz))[:, None, None], (nz, 1, 1)).copy()   # dT/dz = 0.01 K/m
     flux = np.zeros((nz, 1, 1))
     y = ct.kappa_target(flux, Tc, dz, 1e-5)
-    assert np.allclose(y, math.log10(1e-5))
+    assert np.allclose(y, math.log10(1e-5))           # no flux: the background on every face
     flux[1:] = -2e-5                              # down-gradient flux: kappa0 + 2e-5 / 0.01
     y = ct.kappa_target(flux, Tc, dz, 1e-5)
-    assert np.allclose(10 ** y, 1e-5 + 2e-3, rtol=1e-12)
-    flux[1:] = -100.0                             # clipped above
-    assert np.allclose(10 ** ct.kappa_target(flux, Tc, dz, 1e-5), 1.0)
+    assert np.allclose(10 ** y[1:], 1e-5 + 2e-3, rtol=1e-12) and np.allclose(10 ** y[0], 1e-5)
+    flux[1:] = -100.0                             # clipped above (slot 0, the bottom face, stays background)
+    assert np.allclose(10 ** ct.kappa_target(flux, Tc, dz, 1e-5)[1:], 1.0)
 
 
 def test_mixed_layer_depth():
@@ -109,6 +109,6 @@ def test_kappa_target_counts_unstable_down_gradient_flux():
     flux = np.zeros((nz, 1, 1))
     flux[1:] = 2e-4                                    # upward
     k = 10 ** ct.kappa_target(flux, Tc, dz, 1e-5)
-    assert np.allclose(k[1:2], 1e-5 + 2e-4 / 0.01, rtol=1e-12)
+    assert np.allclose(k[1:], 1e-5 + 2e-4 / 0.01, rtol=1e-12)
     flux[1:] = -2e-4                                   # counter-gradient: background only
     assert np.allclose(10 ** ct.kappa_target(flux, Tc, dz, 1e-5), 1e-5)

@@ -8,8 +8,11 @@ steps a column depends only on the initial state within 2 x 94 = 188 columns
 of it. The oracle steps a bounded window of radius 200 columns cut from the
 seeded inputs, twice (the three windows on parallel threads: the oracle runs
 outside the interpreter lock), and the
-centre 5 x 5 patch must match the GPU's state after its second step: FP64
-within 1e-11 relative, FP32 within 1e-4. Both sides start from the same
+centre 25 x 25 patch must match the GPU's state after its second step: FP64
+within 1e-11 relative, FP32 within 1e-4. (On a 5 x 5 patch at 180E, 50S the
+barotropic V moves by 5e-12 between two oracle builds that differ only in
+fused multiply-adds: a field-wide relative norm, as the tolerance is defined,
+needs a patch wider than that rounding-sensitive spot.) Both sides start from the same
 inputs; nothing the GPU computed enters the oracle.
 """
 import functools
@@ -23,7 +26,7 @@ from paper_2309_06662_amd import inputs
 pytestmark = pytest.mark.gpu
 
 R = 200     # window radius in columns
-P = 2       # half-width of the compared patch
+P = 12      # half-width of the compared patch (R - 2 x 94 = 12 columns stay clean)
 STEPS = 2
 W = inputs.LATLON_TWELFTH
 SAMPLES = [(100, 900), (2160, 300), (4300, 1500)]  # (i, j): equator-ish, southern ocean, near the x seam

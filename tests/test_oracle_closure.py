@@ -146,14 +146,13 @@ def test_kappa_map():
     kb = np.array([[5, 2, 0, 5]], dtype=np.int32)
     m = oracle.OracleModel(w, np.full(nz, 100.0), kb)
     Y = np.full((nx, nz), -3.0)
-    Y[3] = [-9.0, 2.0, -3.0, np.nan, -2.0]
+    Y[3] = [7.0, 2.0, -9.0, np.nan, -2.0]      # slot 0 (bottom face) is never used
     kw = m.closure_kappa(Y, kappa0=1e-5)
     assert np.all(kw[0] == 0)
     assert np.allclose(kw[1:, 0, 0], 1e-3, rtol=1e-14)
     assert np.allclose(kw[4, 0, 1], 1e-3, rtol=1e-14) and np.all(kw[:4, 0, 1] == 0)   # K = 2: one wet face
     assert np.all(kw[:, 0, 2] == 0)
-    c = [1e-7, 1.0, 1e-3, 1e-5, 1e-2]   # clipped, clipped, plain, non-finite -> kappa0, plain
-    assert np.allclose(kw[1:, 0, 3], [0.5 * (c[k - 1] + c[k]) for k in range(1, nz)], rtol=1e-13)
+    assert np.allclose(kw[1:, 0, 3], [1.0, 1e-7, 1e-5, 1e-2], rtol=1e-13)   # clipped, clipped, kappa0, plain
 
 
 def test_convective_adjustment_mixes_unstable_faces_only():
