@@ -42,6 +42,29 @@ __device__ __forceinline__ void store_wrapped2(const DevState& S, double* f, int
 constexpr int kNzBuckets[] = {16, 32, 48, 64, 80, 100, 128};
 constexpr int kMaxNz = 128;
 
+// Copy a stored column into its periodic images (edge columns only): the
+// values are read back from the column just written by this thread, so the
+// unrolled level loops above keep the column in registers.
+template <typename R>
+__device__ __forceinline__ void copy_images(const DevState& S, R* dst, int i, int j) {
+    const Images im = column_images(S, i, j, S.h);
+    if (im.n == 0) return;
+    const long long o0 = idx3(S, i, j, 0), pl = S.plane3;
+    for (int k = 0; k < S.nz; ++k) {
+        const long long o = o0 + k * pl;
+        const R val = dst[o];
+        if (im.n > 3) {
+            store_wrapped(S, dst, i, j, k, val);
+            continue;
+        }
+        dst[o + im.o0] = val;
+        if (im.n > 1) {
+            dst[o + im.o1] = val;
+            dst[o + im.o2] = val;
+        }
+    }
+}
+
 // Output of one solved column: T as is; u and v with the depth-mean
 // correction u = u** + (Ubar - sum dz u**) / H on wet layers, which also
 // leaves the column sum sum_k dz u m_u of the stored result (it seeds the
@@ -51,14 +74,12 @@ __device__ __forceinline__ void column_store(const DevState& S, const R (&x)[NZB
                                              const int field, const int kbot, const double colsum) {
     const int nz = S.nz;
     R* dst = f3<R>(field == 0 ? S.t : field == 1 ? S.u : S.v);
+    const long long o0 = idx3(S, i, j, 0), pl = S.plane3;
     if (field == 0) {
 #pragma unroll
-        for (int k = 0; k < NZB; ++k) {
-            if (k < nz) {
-                dst[idx3(S, i, j, k)] = x[k];
-                store_wrapped(S, dst, i, j, k, x[k]);
-            }
-        }
+        for (int k = 0; k < NZB; ++k)
+            if (k < nz) dst[o0 + k * pl] = x[k];
+        copy_images(S, dst, i, j);
         return;
     }
     const double H = (field == 1) ? S.hu[idx2(S, i, j)] : S.hv[idx2(S, i, j)];
@@ -73,10 +94,10 @@ __device__ __forceinline__ void column_store(const DevState& S, const R (&x)[NZB
                 val = R(double(x[k]) + corr);
                 newsum += double(S.dz[k]) * double(val);
             }
-            dst[idx3(S, i, j, k)] = val;
-            store_wrapped(S, dst, i, j, k, val);
+            dst[o0 + k * pl] = val;
         }
     }
+    copy_images(S, dst, i, j);
     store_wrapped2(S, field == 1 ? S.cu : S.cv, i, j, newsum);
 }
 

@@ -62,28 +62,33 @@ __device__ __forceinline__ double rcp(double x) {
 }
 
 // Fifth-order WENO-Z face value (Borges et al. 2008) on Jiang-Shu smoothness
-// indicators; c is the upwind cell, the face lies between c and d.
+// indicators; c is the upwind cell, the face lies between c and d. Written in
+// the differences d1..d4 of neighbouring values: the candidate values become
+// c plus a difference (exact algebra of the three quadratic candidates), and
+// the three WENO-Z ratios tau / (beta_k + eps) share one reciprocal of the
+// product of the three denominators (all >= eps, so the product stays in range).
 template <typename R>
 __device__ __forceinline__ R weno5z(R a, R b, R c, R d, R e) {
-    const R sixth = R(1) / R(6);
-    const R q0 = (R(2) * a - R(7) * b + R(11) * c) * sixth;
-    const R q1 = (-b + R(5) * c + R(2) * d) * sixth;
-    const R q2 = (R(2) * c + R(5) * d - e) * sixth;
-    const R s0 = a - R(2) * b + c, r0 = a - R(4) * b + R(3) * c;
-    const R s1 = b - R(2) * c + d, r1 = b - d;
-    const R s2 = c - R(2) * d + e, r2 = R(3) * c - R(4) * d + e;
+    const R d1 = b - a, d2 = c - b, d3 = d - c, d4 = e - d;
+    const R s0 = d2 - d1, s1 = d3 - d2, s2 = d4 - d3;          // second differences
+    const R r0 = fma(R(2), d2, s0), r1 = d2 + d3, r2 = fma(R(-2), d3, s2);
     const R k13 = R(13) / R(12);
-    const R b0 = k13 * s0 * s0 + R(0.25) * r0 * r0;
-    const R b1 = k13 * s1 * s1 + R(0.25) * r1 * r1;
-    const R b2 = k13 * s2 * s2 + R(0.25) * r2 * r2;
+    const R b0 = fma(k13 * s0, s0, R(0.25) * r0 * r0);
+    const R b1 = fma(k13 * s1, s1, R(0.25) * r1 * r1);
+    const R b2 = fma(k13 * s2, s2, R(0.25) * r2 * r2);
     const R tau = fabs(b0 - b2);
-    const R z0 = tau * rcp(b0 + Eps<R>::v);
-    const R z1 = tau * rcp(b1 + Eps<R>::v);
-    const R z2 = tau * rcp(b2 + Eps<R>::v);
-    const R a0 = R(0.1) * (R(1) + z0 * z0);
-    const R a1 = R(0.6) * (R(1) + z1 * z1);
-    const R a2 = R(0.3) * (R(1) + z2 * z2);
-    return (a0 * q0 + a1 * q1 + a2 * q2) * rcp(a0 + a1 + a2);
+    const R e0 = b0 + Eps<R>::v, e1 = b1 + Eps<R>::v, e2 = b2 + Eps<R>::v;
+    const R p12 = e1 * e2, p02 = e0 * e2, p01 = e0 * e1;
+    const R tr = tau * rcp(p01 * e2);
+    const R z0 = tr * p12, z1 = tr * p02, z2 = tr * p01;
+    const R a0 = fma(R(0.1) * z0, z0, R(0.1));
+    const R a1 = fma(R(0.6) * z1, z1, R(0.6));
+    const R a2 = fma(R(0.3) * z2, z2, R(0.3));
+    // q0 - c = (5 d2 - 2 d1)/6, q1 - c = (d2 + 2 d3)/6, q2 - c = (4 d3 - d4)/6
+    const R q0 = fma(R(5.0 / 6.0), d2, R(-1.0 / 3.0) * d1);
+    const R q1 = fma(R(1.0 / 3.0), d3, R(1.0 / 6.0) * d2);
+    const R q2 = fma(R(2.0 / 3.0), d3, R(-1.0 / 6.0) * d4);
+    return c + fma(a0, q0, fma(a1, q1, a2 * q2)) * rcp(a0 + a1 + a2);
 }
 
 // Third-order WENO-JS face value on (b, c, d), c upwind.

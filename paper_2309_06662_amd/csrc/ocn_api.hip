@@ -694,7 +694,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         d.kappa = params->kappa;
         d.restore_inv = params->restore_tau > 0.0 ? 1.0 / params->restore_tau : 0.0;
         d.n_substeps = params->n_substeps;
-        d.baro_fuse = params->baro_fuse == 0 ? 5 : params->baro_fuse;
+        d.baro_fuse = params->baro_fuse == 0 ? 6 : params->baro_fuse;
         d.baro_m = ocn::baro_substeps(params->n_substeps);
         d.baro_a = reinterpret_cast<double*>(A + P.off_bw);
         d.baro_A = d.baro_a + d.baro_m + 1;
@@ -1355,7 +1355,7 @@ int ocn_ensemble_set_tiles(ocn_ensemble* e, int32_t tend_rows, int32_t baro_fuse
     if (e->st) HIPCHK(hipStreamSynchronize(e->st));
     drop_graph(e);
     e->tend_ty = tend_rows;
-    e->fuse = baro_fuse == 0 ? 5 : baro_fuse;
+    e->fuse = baro_fuse == 0 ? 6 : baro_fuse;
     return ens_tables(e);
 }
 

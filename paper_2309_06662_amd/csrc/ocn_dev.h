@@ -116,6 +116,32 @@ __device__ __forceinline__ void for_each_image(const DevState& s, int i, int j, 
             if (x != i || y != j) f(x, y);
 }
 
+// The periodic images of column (i, j) within a halo band of width ext, as
+// element offsets in a 3D field (the same on every level), computed without
+// a capturing lambda so they stay in registers: at most one image per
+// periodic direction plus the corner. n > 3 (a domain narrower than twice the
+// band) tells the caller to fall back to for_each_image.
+struct Images {
+    int n;
+    long long o0, o1, o2;
+};
+__device__ __forceinline__ Images column_images(const DevState& s, int i, int j, int ext) {
+    Images im{0, 0, 0, 0};
+    if ((s.periodic_x && s.nx < 2 * ext) || (s.periodic_y && s.ny < 2 * ext)) {
+        im.n = 4;
+        return im;
+    }
+    long long ox = 0, oy = 0;
+    if (s.periodic_x) ox = (i < ext) ? s.nx : ((i >= s.nx - ext) ? -s.nx : 0);
+    if (s.periodic_y) oy = (j < ext) ? (long long)s.ny * s.p3 : ((j >= s.ny - ext) ? -(long long)s.ny * s.p3 : 0);
+    if (ox != 0) im.o0 = ox, im.n = 1;
+    if (oy != 0) {
+        if (im.n == 0) im.o0 = oy, im.n = 1;
+        else im.o1 = oy, im.o2 = ox + oy, im.n = 3;
+    }
+    return im;
+}
+
 // Launchers (defined in the kernel translation units).
 template <typename R> hipError_t launch_tendency(const DevState& s, int first, hipStream_t st);
 template <typename R> hipError_t launch_column(const DevState& s, hipStream_t st);
