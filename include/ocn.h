@@ -229,7 +229,11 @@ int  ocn_ensemble_autotune(ocn_ensemble* ens, int32_t trial_steps, int32_t* tend
  * and its gradients (synchronises); ocn_mlp_train_step also applies one Adam
  * step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr, and when
  * loss is non-NULL synchronises to return the loss before the update.
- * ocn_mlp_set_params resets the Adam moments. */
+ * ocn_mlp_set_params resets the Adam moments. Inference (ocn_mlp_forward and
+ * the closure) runs all three layers in one kernel with the weights held in
+ * LDS when din % 8 == 0, din <= 256, h1 and h2 are multiples of 32 up to 128
+ * and dout <= 128; other shapes run layer by layer. Both round the same
+ * operands to BF16; they differ only in FP32 accumulation order. */
 typedef struct ocn_mlp ocn_mlp;
 int  ocn_mlp_arena_bytes(int32_t din, int32_t h1, int32_t h2, int32_t dout, int32_t max_batch, size_t* bytes);
 int  ocn_mlp_init(int32_t din, int32_t h1, int32_t h2, int32_t dout, int32_t max_batch, void* device_arena,
@@ -258,9 +262,9 @@ int  ocn_mlp_train_step(ocn_mlp* net, const float* x_dev, const float* t_dev, in
  *    dout == nz, and its current weights are read at every step.
  * The workspace (device, 256-byte aligned, ocn_closure_workspace_bytes) holds
  * the face field and, with a network, its activations for every column; it
- * must outlive the attachment. The network must outlive it too. The variable
- * diffusivity solve needs 2 nz 64 element sizes <= 64 KiB. Ensembles and
- * checkpoints do not carry a closure. */
+ * must outlive the attachment. The network must outlive it too. Any nz the
+ * state takes (<= 128) is supported. Ensembles and checkpoints do not carry a
+ * closure. */
 int ocn_closure_workspace_bytes(const ocn_state* state, const ocn_mlp* net, size_t* bytes);
 int ocn_closure_attach(ocn_state* state, const ocn_mlp* net, const float* norm, size_t norm_count,
                        void* device_workspace, size_t workspace_bytes);

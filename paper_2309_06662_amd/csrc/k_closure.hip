@@ -5,10 +5,10 @@
 // parameterizations; Sec. 6 uses a vertical-mixing closure). Two kernels sit
 // around the network's products:
 //
-//  k_features: one thread per column, 64 adjacent columns of a row per
-//  workgroup. It builds the column's input vector in LDS, then the workgroup
-//  writes its 64 consecutive rows of the (ny nx) x din matrix as one contiguous
-//  coalesced run (FP32 or BF16). Order: T (nz), u at centres (nz), v at
+//  k_features: 64 adjacent columns of a row per workgroup, sixteen threads
+//  per column taking every sixteenth level. They build the columns' input vectors
+//  in LDS, then the workgroup writes its 64 consecutive rows of the
+//  (ny nx) x din matrix as one contiguous coalesced run (FP32 or BF16). Order: T (nz), u at centres (nz), v at
 //  centres (nz), N^2 = g alpha dT/dz on faces (nz, slot 0 and dry faces 0),
 //  centred wind stress (2), restoring flux dz_top (T* - T_top)/tau (1), zero
 //  padding. Wet entries are normalised with per-feature mean and standard
@@ -32,69 +32,121 @@ __device__ __forceinline__ uint16_t to_bf16(float x) {
     return (uint16_t)(u >> 16);
 }
 
-template <typename R>
-__global__ __launch_bounds__(FW) void k_features(const DevState S, int din, const float* __restrict__ norm,
-                                                 void* __restrict__ out, int out_bf16) {
-    extern __shared__ float sfeat[];  // [FW][din + 1]
-    const int t = threadIdx.x, i0 = blockIdx.x * FW, j = blockIdx.y, i = i0 + t;
-    const int nx = S.nx, nz = S.nz, ld = din + 1;
-    float* my = sfeat + t * ld;
-    for (int f = 0; f < din; ++f) my[f] = 0.f;
+constexpr int FG = 16;  // level groups per workgroup: thread (t, g) takes levels g, g + FG, ...
+constexpr int FL = (128 + FG - 1) / FG;  // levels per thread at the largest nz
+
+// Stores a workgroup's rows (contiguous in the output) from the LDS tile
+// [FW][ld]: whole rows of n values are written by consecutive threads.
+template <typename O>
+__device__ __forceinline__ void store_rows(const O* tile, int ld, int nrows, int n, O* out) {
+    constexpr int NT = FW * FG;
+    const int tid = threadIdx.y * FW + threadIdx.x;
+    if (n >= NT) {
+        for (int r = 0; r < nrows; ++r)
+            for (int f = tid; f < n; f += NT) out[(long long)r * n + f] = tile[r * ld + f];
+    } else {
+        const int rpi = NT / n, r0 = tid / n, f = tid - r0 * n;
+        if (r0 < rpi)
+            for (int r = r0; r < nrows; r += rpi) out[(long long)r * n + f] = tile[r * ld + f];
+    }
+}
+
+__device__ __forceinline__ void put_feature(float* tile, int f, float x) { tile[f] = x; }
+__device__ __forceinline__ void put_feature(uint16_t* tile, int f, float x) { tile[f] = to_bf16(x); }
+
+// O = float (FP32 rows) or uint16_t (BF16 rows). The row tile is staged in
+// the output type, so BF16 rows need half the LDS.
+template <typename R, typename O>
+__global__ __launch_bounds__(FW * FG) void k_features(const DevState S, int din, const float* __restrict__ norm,
+                                                      O* __restrict__ out) {
+    extern __shared__ __align__(16) unsigned char feat_smem[];
+    O* tile = reinterpret_cast<O*>(feat_smem);
+    const int ld = din + (sizeof(O) == 4 ? 1 : 2);
+    // a wave is one level group (the block is 64 wide), so g is uniform across it
+    const int t = threadIdx.x, g = __builtin_amdgcn_readfirstlane(threadIdx.y), i0 = blockIdx.x * FW, j = blockIdx.y;
+    const int i = i0 + t;
+    const int nx = S.nx, nz = S.nz;
+    O* my = tile + t * ld;
 
     if (i < nx) {
         const int K = S.kb[idxk(S, i, j)];
-        if (K > 0) {
-            auto put = [&](int f, double x) {
-                my[f] = norm ? float((x - double(norm[f])) / double(norm[din + f])) : float(x);
-            };
-            const int kbot = nz - K;
-            // east / north neighbours across the domain edge: periodic image or land
-            const int ie = (i + 1 < nx) ? i + 1 : (S.periodic_x ? 0 : -1);
-            const int jn = (j + 1 < S.ny) ? j + 1 : (S.periodic_y ? 0 : -1);
-            const int Kuw = min(K, S.kb[idxk(S, i - 1, j)]);
-            const int Kue = ie >= 0 ? min(K, S.kb[idxk(S, ie, j)]) : 0;
-            const int Kvs = min(K, S.kb[idxk(S, i, j - 1)]);
-            const int Kvn = jn >= 0 ? min(K, S.kb[idxk(S, i, jn)]) : 0;
-            const R* T = f3<R>(S.t);
-            const R* U = f3<R>(S.u);
-            const R* V = f3<R>(S.v);
-            double tprev = 0.0;
-            for (int k = kbot; k < nz; ++k) {
-                const double tk = double(T[idx3(S, i, j, k)]) + S.tref[k];
-                put(k, tk);
-                const double uw = (k >= nz - Kuw) ? double(U[idx3(S, i, j, k)]) : 0.0;
-                const double ue = (k >= nz - Kue) ? double(U[idx3(S, ie, j, k)]) : 0.0;
-                put(nz + k, 0.5 * (uw + ue));
-                const double vs = (k >= nz - Kvs) ? double(V[idx3(S, i, j, k)]) : 0.0;
-                const double vn = (k >= nz - Kvn) ? double(V[idx3(S, i, jn, k)]) : 0.0;
-                put(2 * nz + k, 0.5 * (vs + vn));
-                if (k > kbot) put(3 * nz + k, S.g * S.alpha * (tk - tprev) / S.dzc[k]);
-                tprev = tk;
+        const int kbot = nz - K;
+        auto put = [&](int f, double x) {
+            put_feature(my, f, norm ? float((x - double(norm[f])) / double(norm[din + f])) : float(x));
+        };
+        // east / north neighbours across the domain edge: periodic image or land
+        const int ie = (i + 1 < nx) ? i + 1 : (S.periodic_x ? 0 : -1);
+        const int jn = (j + 1 < S.ny) ? j + 1 : (S.periodic_y ? 0 : -1);
+        const int Kuw = min(K, S.kb[idxk(S, i - 1, j)]);
+        const int Kue = ie >= 0 ? min(K, S.kb[idxk(S, ie, j)]) : 0;
+        const int Kvs = min(K, S.kb[idxk(S, i, j - 1)]);
+        const int Kvn = jn >= 0 ? min(K, S.kb[idxk(S, i, jn)]) : 0;
+        const R* T = f3<R>(S.t);
+        const R* U = f3<R>(S.u);
+        const R* V = f3<R>(S.v);
+        // all loads of this thread's levels first (addresses clamped to valid
+        // points, masks applied afterwards), so they are in flight together
+        const int iec = ie >= 0 ? ie : i, jnc = jn >= 0 ? jn : j;
+        R vT[FL], vTb[FL], vUw[FL], vUe[FL], vVs[FL], vVn[FL];
+#pragma unroll
+        for (int m = 0; m < FL; ++m) {
+            const int k = g + FG * m;
+            if (k < nz) {
+                vT[m] = T[idx3(S, i, j, k)];
+                vTb[m] = T[idx3(S, i, j, max(k - 1, 0))];
+                vUw[m] = U[idx3(S, i, j, k)];
+                vUe[m] = U[idx3(S, iec, j, k)];
+                vVs[m] = V[idx3(S, i, j, k)];
+                vVn[m] = V[idx3(S, i, jnc, k)];
             }
-            const double txe = ie >= 0 ? S.taux[idx2(S, ie, j)] : 0.0;
-            const double tyn = jn >= 0 ? S.tauy[idx2(S, i, jn)] : 0.0;
-            put(4 * nz, 0.5 * (S.taux[idx2(S, i, j)] + txe));
-            put(4 * nz + 1, 0.5 * (S.tauy[idx2(S, i, j)] + tyn));
-            // the stored T and T* are both anomalies from the top reference level
-            const double q = S.restore_inv > 0.0
-                                 ? S.dz[nz - 1] * (S.tstar[idx2(S, i, j)] - double(T[idx3(S, i, j, nz - 1)])) *
-                                       S.restore_inv
-                                 : 0.0;
-            put(4 * nz + 2, q);
+        }
+#pragma unroll
+        for (int m = 0; m < FL; ++m) {
+            const int k = g + FG * m;
+            if (k >= nz) break;
+            if (k < kbot) {
+                put_feature(my, k, 0.f);
+                put_feature(my, nz + k, 0.f);
+                put_feature(my, 2 * nz + k, 0.f);
+                put_feature(my, 3 * nz + k, 0.f);
+                continue;
+            }
+            const double tk = double(vT[m]) + S.tref[k];
+            put(k, tk);
+            const double uw = (k >= nz - Kuw) ? double(vUw[m]) : 0.0;
+            const double ue = (k >= nz - Kue) ? double(vUe[m]) : 0.0;
+            put(nz + k, 0.5 * (uw + ue));
+            const double vs = (k >= nz - Kvs) ? double(vVs[m]) : 0.0;
+            const double vn = (k >= nz - Kvn) ? double(vVn[m]) : 0.0;
+            put(2 * nz + k, 0.5 * (vs + vn));
+            if (k > kbot) {
+                const double tb = double(vTb[m]) + S.tref[k - 1];
+                put(3 * nz + k, S.g * S.alpha * (tk - tb) / S.dzc[k]);
+            } else {
+                put_feature(my, 3 * nz + k, 0.f);
+            }
+        }
+        if (g == 0) {
+            if (K > 0) {
+                const double txe = ie >= 0 ? S.taux[idx2(S, ie, j)] : 0.0;
+                const double tyn = jn >= 0 ? S.tauy[idx2(S, i, jn)] : 0.0;
+                put(4 * nz, 0.5 * (S.taux[idx2(S, i, j)] + txe));
+                put(4 * nz + 1, 0.5 * (S.tauy[idx2(S, i, j)] + tyn));
+                // the stored T and T* are both anomalies from the top reference level
+                const double q = S.restore_inv > 0.0
+                                     ? S.dz[nz - 1] * (S.tstar[idx2(S, i, j)] - double(T[idx3(S, i, j, nz - 1)])) *
+                                           S.restore_inv
+                                     : 0.0;
+                put(4 * nz + 2, q);
+            } else {
+                for (int f = 4 * nz; f < 4 * nz + 3; ++f) put_feature(my, f, 0.f);
+            }
+            for (int f = 4 * nz + 3; f < din; ++f) put_feature(my, f, 0.f);
         }
     }
     __syncthreads();
     // the workgroup's rows j nx + i0 .. j nx + i0 + nrows - 1 are contiguous
-    const int nrows = min(FW, nx - i0);
-    const long long base = ((long long)j * nx + i0) * din;
-    const int total = nrows * din;
-    if (out_bf16) {
-        uint16_t* o = static_cast<uint16_t*>(out) + base;
-        for (int e = t; e < total; e += FW) o[e] = to_bf16(sfeat[(e / din) * ld + e % din]);
-    } else {
-        float* o = static_cast<float*>(out) + base;
-        for (int e = t; e < total; e += FW) o[e] = sfeat[(e / din) * ld + e % din];
-    }
+    store_rows(tile, ld, min(FW, nx - i0), din, out + ((long long)j * nx + i0) * din);
 }
 
 __device__ __forceinline__ double face_kappa_of(float y, double kappa0) {
@@ -102,17 +154,33 @@ __device__ __forceinline__ double face_kappa_of(float y, double kappa0) {
     return fmin(1.0, fmax(1e-7, exp10(double(y))));
 }
 
+// The workgroup's 64 output rows are read into LDS in row order (coalesced),
+// then each thread writes its column's faces level by level (coalesced
+// across the columns).
 template <typename R>
-__global__ __launch_bounds__(FW) void k_kappa_map(const DevState S, const float* __restrict__ Y, int ldy,
-                                                  double kappa0) {
-    const int i = blockIdx.x * FW + threadIdx.x, j = blockIdx.y;
+__global__ __launch_bounds__(FW * FG) void k_kappa_map(const DevState S, const float* __restrict__ Y, int ldy,
+                                                       double kappa0) {
+    extern __shared__ __align__(16) unsigned char kap_smem[];
+    float* sy = reinterpret_cast<float*>(kap_smem);  // [FW][nz + 1]
+    const int nz = S.nz, ld = nz + 1;
+    const int t = threadIdx.x, g = __builtin_amdgcn_readfirstlane(threadIdx.y), i0 = blockIdx.x * FW, j = blockIdx.y;
+    const int i = i0 + t;
+    const int nrows = min(FW, S.nx - i0);
+    {
+        constexpr int NT = FW * FG;
+        const int tid = g * FW + t;
+        const float* src = Y + ((long long)j * S.nx + i0) * ldy;
+        for (int e = tid; e < nrows * ld; e += NT) {
+            const int r = e / ld, k = e - r * ld;
+            if (k < nz) sy[e] = src[(long long)r * ldy + k];
+        }
+    }
+    __syncthreads();
     if (i >= S.nx) return;
-    const int nz = S.nz;
     const int kbot = nz - S.kb[idxk(S, i, j)];
-    const float* y = Y + ((long long)j * S.nx + i) * ldy;
     R* kw = f3<R>(S.kw);
-    for (int k = 0; k < nz; ++k) {
-        const R val = (k > kbot) ? R(face_kappa_of(y[k], kappa0)) : R(0);
+    for (int k = g; k < nz; k += FG) {
+        const R val = (k > kbot) ? R(face_kappa_of(sy[t * ld + k], kappa0)) : R(0);
         kw[idx3(S, i, j, k)] = val;
         for_each_image(S, i, j, S.h, [&](int x, int yy) { kw[idx3(S, x, yy, k)] = val; });
     }
@@ -167,17 +235,22 @@ size_t features_lds(int din) { return (size_t)FW * (din + 1) * sizeof(float); }
 
 template <typename R>
 hipError_t launch_features(const DevState& s, int din, const float* norm, void* out, int out_bf16, hipStream_t st) {
-    const size_t lds = features_lds(din);
+    const size_t lds = out_bf16 ? (size_t)FW * (din + 2) * 2 : features_lds(din);
     if (lds > 64 * 1024) return hipErrorInvalidValue;
     dim3 grid((s.nx + FW - 1) / FW, s.ny);
-    hipLaunchKernelGGL(k_features<R>, grid, dim3(FW), lds, st, s, din, norm, out, out_bf16);
+    if (out_bf16)
+        hipLaunchKernelGGL((k_features<R, uint16_t>), grid, dim3(FW, FG), lds, st, s, din, norm,
+                           static_cast<uint16_t*>(out));
+    else
+        hipLaunchKernelGGL((k_features<R, float>), grid, dim3(FW, FG), lds, st, s, din, norm, static_cast<float*>(out));
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_kappa_map(const DevState& s, const float* Y, int ldy, double kappa0, hipStream_t st) {
+    const size_t lds = (size_t)FW * (s.nz + 1) * sizeof(float);
     dim3 grid((s.nx + FW - 1) / FW, s.ny);
-    hipLaunchKernelGGL(k_kappa_map<R>, grid, dim3(FW), 0, st, s, Y, ldy, kappa0);
+    hipLaunchKernelGGL(k_kappa_map<R>, grid, dim3(FW, FG), lds, st, s, Y, ldy, kappa0);
     return hipGetLastError();
 }
 

@@ -2,8 +2,8 @@
 //
 // Backward-Euler vertical diffusion (paper Sec. 5.2: vertically implicit
 // diffusion with a tridiagonal solver) of T, u and v, one thread per column,
-// one wave per 64 adjacent columns so that every level of a field is read and
-// written as coalesced row segments.
+// 256 adjacent columns per workgroup so that every level of a field is read
+// and written as coalesced 1 KiB row segments.
 //
 // With a constant diffusivity the matrix of a column depends only on its number
 // of wet layers K (the wet layers of T, u and v columns all start at the
@@ -26,7 +26,10 @@
 
 namespace ocn {
 
-constexpr int CW = 64;       // columns per workgroup
+constexpr int CW = 256;      // columns per workgroup of the single-state launches (four waves side by side
+                             // read 1 KiB runs of each level: about 1.5x the rate of one-wave groups)
+constexpr int CWB = 64;      // columns per tile of the batched ensemble launches (tile tables use 64)
+constexpr int CWL = 64;      // columns per workgroup of the LDS-staged variable-diffusivity solve
 
 template <typename R>
 __device__ __forceinline__ void store_wrapped(const DevState& S, R* f, int i, int j, int k, R val) {
@@ -101,11 +104,11 @@ __device__ __forceinline__ void column_store(const DevState& S, const R (&x)[NZB
     store_wrapped2(S, field == 1 ? S.cu : S.cv, i, j, newsum);
 }
 
-// One block of 64 columns (bx, j) of one field: 0 = T, 1 = u, 2 = v.
-template <typename R, int NZB>
+// One block of W columns (bx, j) of one field: 0 = T, 1 = u, 2 = v.
+template <typename R, int NZB, int W>
 __device__ __forceinline__ void column_regs(const DevState& S, const int bx, const int j, const int field) {
     const int t = threadIdx.x;
-    const int i = bx * CW + t;
+    const int i = bx * W + t;
     const int nz = S.nz;
     const int ic = i < S.nx ? i : S.nx - 1;
 
@@ -163,11 +166,11 @@ __device__ __forceinline__ void column_regs(const DevState& S, const int bx, con
 // formed on the fly, a_k = -dt kappa_k / dzc_k on the wet face k below layer
 // k, c_k = a_{k+1}; the eliminated super-diagonal c' is kept in a second LDS
 // array. u and v take the mean of the two neighbouring tracer-face values.
-template <typename R>
+template <typename R, int W>
 __device__ __forceinline__ void column_block_vk(const DevState& S, R* sd, R* sc, const int bx, const int j,
                                                 const int field) {
     const int t = threadIdx.x;
-    const int i = bx * CW + t;
+    const int i = bx * W + t;
     const int nz = S.nz;
     const bool live = i < S.nx;
     const int ic = live ? i : S.nx - 1;
@@ -194,19 +197,24 @@ __device__ __forceinline__ void column_block_vk(const DevState& S, R* sd, R* sc,
         return -rdt * kap / R(S.dzc[k]);
     };
 
+    // stage the column and its face coefficients (sc holds a_k until the
+    // elimination overwrites it with c'_k)
 #pragma unroll 8
-    for (int k = 0; k < nz; ++k) sd[k * CW + t] = src[k * pl];
+    for (int k = 0; k < nz; ++k) {
+        sd[k * W + t] = src[k * pl];
+        sc[k * W + t] = coef(k);
+    }
 
     R dprev = R(0), cprev = R(0), ak = R(0);
     for (int k = 0; k < nz; ++k) {
-        const R ck = coef(k + 1);
-        R rhs = R(S.dz[k]) * sd[k * CW + t];
+        const R ck = (k + 1 < nz) ? sc[(k + 1) * W + t] : R(0);
+        R rhs = R(S.dz[k]) * sd[k * W + t];
         if (field == 0) rhs += -ck * dtr[k * 4 + 2] - ak * dtr[k * 4 + 1];
         const R rden = R(1) / (R(S.dz[k]) - ak - ck - ak * cprev);
         const R cpk = ck * rden;
         const R dk = (rhs - ak * dprev) * rden;
-        sd[k * CW + t] = dk;
-        sc[k * CW + t] = cpk;
+        sd[k * W + t] = dk;
+        sc[k * W + t] = cpk;
         dprev = dk;
         cprev = cpk;
         ak = ck;
@@ -214,16 +222,16 @@ __device__ __forceinline__ void column_block_vk(const DevState& S, R* sd, R* sc,
     R xnext = R(0);
     double colsum = 0.0;
     for (int k = nz - 1; k >= 0; --k) {
-        const R x = sd[k * CW + t] - sc[k * CW + t] * xnext;
+        const R x = sd[k * W + t] - sc[k * W + t] * xnext;
         xnext = x;
-        sd[k * CW + t] = x;
+        sd[k * W + t] = x;
         if (k >= kbot) colsum += double(S.dz[k]) * double(x);
     }
     if (!live) return;
 
     if (field == 0) {
         for (int k = 0; k < nz; ++k) {
-            const R x = sd[k * CW + t];
+            const R x = sd[k * W + t];
             dst[idx3(S, i, j, k)] = x;
             store_wrapped(S, dst, i, j, k, x);
         }
@@ -236,13 +244,78 @@ __device__ __forceinline__ void column_block_vk(const DevState& S, R* sd, R* sc,
     for (int k = 0; k < nz; ++k) {
         R val = R(0);
         if (k >= kbot && H > 0.0) {
-            val = R(double(sd[k * CW + t]) + corr);
+            val = R(double(sd[k * W + t]) + corr);
             newsum += double(S.dz[k]) * double(val);
         }
         dst[idx3(S, i, j, k)] = val;
         store_wrapped(S, dst, i, j, k, val);
     }
     store_wrapped2(S, field == 1 ? S.cu : S.cv, i, j, newsum);
+}
+
+// Register-resident form of the variable-diffusivity solve, for columns whose
+// values and coefficients fit the registers (FP32 up to 100 levels, FP64 up to
+// 32): the column and its face coefficients a_k are loaded up front (all loads
+// in flight together), and c'_k overwrites a_k once level k is eliminated.
+// The arithmetic is that of column_block_vk, level by level.
+template <typename R, int NZB, int W>
+__device__ __forceinline__ void column_regs_vk(const DevState& S, const int bx, const int j, const int field) {
+    const int t = threadIdx.x;
+    const int i = bx * W + t;
+    const int nz = S.nz;
+    const int ic = i < S.nx ? i : S.nx - 1;
+
+    const int kc = S.kb[idxk(S, ic, j)];
+    int K = kc;
+    if (field == 1) K = min(kc, S.kb[idxk(S, ic - 1, j)]);
+    if (field == 2) K = min(kc, S.kb[idxk(S, ic, j - 1)]);
+    const int kbot = nz - K;
+
+    const R* src = f3<R>(field == 0 ? S.ts : field == 1 ? S.us : S.vs) + idx3(S, ic, j, 0);
+    const R* kwf = static_cast<const R*>(S.kw);
+    const R* dtr = static_cast<const R*>(S.dtr);
+    const long long o0 = idx3(S, ic, j, 0);
+    const long long on = field == 1 ? idx3(S, ic - 1, j, 0) : idx3(S, ic, j - 1, 0);
+    const long long pl = S.plane3;
+    const R rdt = R(S.dt);
+
+    R x[NZB], a[NZB];
+#pragma unroll
+    for (int k = 0; k < NZB; ++k) {
+        x[k] = (k < nz) ? src[k * pl] : R(0);
+        a[k] = R(0);
+        if (k < nz && k > kbot) {  // face k wet: layers k-1 and k
+            R kap = kwf[o0 + k * pl];
+            if (field != 0) kap = R(0.5) * (kwf[on + k * pl] + kap);
+            a[k] = -rdt * kap / R(S.dzc[k]);
+        }
+    }
+    R dprev = R(0), cprev = R(0);
+#pragma unroll
+    for (int k = 0; k < NZB; ++k) {
+        if (k < nz) {
+            const R ak = a[k];
+            const R ck = (k + 1 < NZB) ? a[k + 1 < NZB ? k + 1 : k] : R(0);  // a_{k+1} (0 above the top)
+            R rhs = R(S.dz[k]) * x[k];
+            if (field == 0) rhs += -ck * dtr[k * 4 + 2] - ak * dtr[k * 4 + 1];
+            const R rden = R(1) / (R(S.dz[k]) - ak - ck - ak * cprev);
+            cprev = ck * rden;
+            dprev = (rhs - ak * dprev) * rden;
+            x[k] = dprev;
+            a[k] = cprev;
+        }
+    }
+    R xnext = R(0);
+    double colsum = 0.0;
+#pragma unroll
+    for (int k = NZB - 1; k >= 0; --k) {
+        if (k < nz) {
+            xnext = x[k] - a[k] * xnext;
+            x[k] = xnext;
+            if (k >= kbot) colsum += double(S.dz[k]) * double(xnext);
+        }
+    }
+    if (i < S.nx) column_store<R, NZB>(S, x, i, j, field, kbot, colsum);
 }
 
 // Column sums sum_k dz u m_u and sum_k dz v m_v of the stored velocities (used
@@ -297,23 +370,34 @@ template <> struct ColWaves<double> { static constexpr int n = 2; };
 template <typename R, int NZB>
 __global__ __launch_bounds__(CW) __attribute__((amdgpu_waves_per_eu(ColWaves<R>::n)))
 void k_column(const DevState S) {
-    column_regs<R, NZB>(S, blockIdx.x, blockIdx.y, blockIdx.z);
+    column_regs<R, NZB, CW>(S, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
-// Variable diffusivity (prescribed field or learned closure), staged in LDS.
-template <typename R>
-__global__ __launch_bounds__(CW) void k_column_vk(const DevState S) {
+// Register-resident variable-diffusivity solve: two column arrays per thread.
+template <typename R, int NZB> struct VkWaves { static constexpr int n = (sizeof(R) == 4 && NZB <= 48) ? 4 : 2; };
+template <typename R, int NZB> struct VkRegs { static constexpr bool ok = sizeof(R) == 4 ? NZB <= 100 : NZB <= 32; };
+
+template <typename R, int NZB>
+__global__ __launch_bounds__(CW) __attribute__((amdgpu_waves_per_eu(VkWaves<R, NZB>::n)))
+void k_column_vkr(const DevState S) {
+    column_regs_vk<R, NZB, CW>(S, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Variable diffusivity (prescribed field or learned closure), staged in LDS,
+// W columns per workgroup (32 when 64 columns of the two arrays exceed 64 KB).
+template <typename R, int W>
+__global__ __launch_bounds__(W) void k_column_vk(const DevState S) {
     extern __shared__ __align__(16) unsigned char smem_col[];
-    R* sd = reinterpret_cast<R*>(smem_col);  // nz * CW eliminated rhs / solution, then nz * CW of c'
-    column_block_vk<R>(S, sd, sd + S.nz * CW, blockIdx.x, blockIdx.y, blockIdx.z);
+    R* sd = reinterpret_cast<R*>(smem_col);  // nz * W eliminated rhs / solution, then nz * W of c'
+    column_block_vk<R, W>(S, sd, sd + S.nz * W, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // Ensemble: entry blockIdx.x of the table is (member, bx, j); blockIdx.y is the field.
 template <typename R, int NZB>
-__global__ __launch_bounds__(CW) __attribute__((amdgpu_waves_per_eu(ColWaves<R>::n)))
+__global__ __launch_bounds__(CWB) __attribute__((amdgpu_waves_per_eu(ColWaves<R>::n)))
 void k_column_batched(const DevState* __restrict__ members, const int4* __restrict__ tiles) {
     const int4 e = tiles[blockIdx.x];
-    column_regs<R, NZB>(members[e.x], e.y, e.z, blockIdx.y);
+    column_regs<R, NZB, CWB>(members[e.x], e.y, e.z, blockIdx.y);
 }
 
 // Dispatch a level count to the smallest bucket that holds it.
@@ -339,9 +423,30 @@ struct LaunchColumn {
 };
 
 template <typename R, int NZB>
+struct LaunchColumnVk {
+    static hipError_t go(const DevState& s, hipStream_t st) {
+        dim3 grid((s.nx + CW - 1) / CW, s.ny, 3);
+        if constexpr (VkRegs<R, NZB>::ok) {
+            hipLaunchKernelGGL((k_column_vkr<R, NZB>), grid, dim3(CW), 0, st, s);
+        } else {
+            const size_t lds = (size_t)s.nz * CWL * sizeof(R) * 2;
+            if (lds <= 64 * 1024) {
+                dim3 g1((s.nx + CWL - 1) / CWL, s.ny, 3);
+                hipLaunchKernelGGL((k_column_vk<R, CWL>), g1, dim3(CWL), lds, st, s);
+            } else {
+                if (lds / 2 > 64 * 1024) return hipErrorInvalidValue;  // per-workgroup LDS limit
+                dim3 g2((s.nx + CWL / 2 - 1) / (CWL / 2), s.ny, 3);
+                hipLaunchKernelGGL((k_column_vk<R, CWL / 2>), g2, dim3(CWL / 2), lds / 2, st, s);
+            }
+        }
+        return hipGetLastError();
+    }
+};
+
+template <typename R, int NZB>
 struct LaunchColumnBatched {
     static hipError_t go(const DevState* members, const int4* tiles, int ntiles, hipStream_t st) {
-        hipLaunchKernelGGL((k_column_batched<R, NZB>), dim3(ntiles, 3), dim3(CW), 0, st, members, tiles);
+        hipLaunchKernelGGL((k_column_batched<R, NZB>), dim3(ntiles, 3), dim3(CWB), 0, st, members, tiles);
         return hipGetLastError();
     }
 };
@@ -357,13 +462,7 @@ template hipError_t launch_column_batched<float>(const DevState*, const int4*, i
 
 template <typename R>
 hipError_t launch_column(const DevState& s, hipStream_t st) {
-    if (s.kw) {
-        const size_t lds = (size_t)s.nz * CW * sizeof(R) * 2;
-        if (lds > 64 * 1024) return hipErrorInvalidValue;  // per-workgroup LDS limit
-        dim3 grid((s.nx + CW - 1) / CW, s.ny, 3);
-        hipLaunchKernelGGL(k_column_vk<R>, grid, dim3(CW), lds, st, s);
-        return hipGetLastError();
-    }
+    if (s.kw) return with_bucket<R, LaunchColumnVk>(s.nz, s, st);
     return with_bucket<R, LaunchColumn>(s.nz, s, st);
 }
 

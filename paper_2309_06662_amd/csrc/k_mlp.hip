@@ -222,6 +222,205 @@ __global__ void k_sum_blocks(const float* part, int nb, float* out) {
     *out = s;
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference: all three layers of a batch tile in one kernel, with the
+// weights resident in LDS for the whole launch.
+//
+// Each layer is computed transposed, H^T = W^T . A^T: the weights are the
+// MFMA A operand (16 output units x 32 inputs from LDS) and the activations
+// the B operand (16 batch rows). A lane's accumulators then hold, for batch
+// row lane % 16, the output units 16 mb + 4 (lane / 16) + v; two adjacent
+// blocks mb = 2c, 2c + 1 give eight units per lane, which become the lane's
+// B fragment for input chunk c of the next layer if that layer's weight rows
+// list their inputs inside each chunk of 32 in the same order (the packing
+// below does so). Activations never leave the registers; a wave carries
+// IF_RB blocks of 16 batch rows so each weight fragment read from LDS feeds
+// IF_RB products. The grid is one workgroup per CU, striding over tiles.
+constexpr int IF_WAVES = 8, IF_T = IF_WAVES * 64, IF_RB = 2;
+constexpr int IF_ROWS = IF_WAVES * IF_RB * 16;  // batch rows per tile
+constexpr int IF_LDS = 128 * 1024;              // packed weights + biases
+constexpr int IF_KC1 = 8, IF_MB = 8, IF_KC = 4;  // max input chunks of layer 1, output blocks, hidden chunks
+
+struct InferShape {
+    int din, h1, h2, dout;
+    int kc1, mb1, kc2, mb2, kc3, mb3;  // input chunks of 32 and output blocks of 16 of each layer
+    int s1, s2, s3;                     // row strides (bf16 elements) of the packed weight matrices
+    int o2, o3, ob;                     // element offsets of layer 2, layer 3 and the FP32 biases
+    int bytes;                          // size of the packed image, a multiple of 16
+};
+
+// Position p inside the packed input range of layer 2 or 3 -> index of the
+// previous layer's output unit (the accumulator order described above).
+__device__ __forceinline__ int perm_k(int p) {
+    const int c = p >> 5, q = p & 31, g = q >> 3, j = q & 7;
+    return 32 * c + (j < 4 ? 4 * g + j : 12 + 4 * g + j);
+}
+
+// Packed image from the FP32 parameters (W1 din x h1, b1, W2, b2, W3, b3),
+// rounded to BF16 as the GEMM path rounds them; padding entries are zero.
+__global__ __launch_bounds__(256) void k_pack_infer(const float* __restrict__ params, const InferShape S,
+                                                    uint16_t* __restrict__ out) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    const float* W1 = params;
+    const float* b1 = W1 + (size_t)S.din * S.h1;
+    const float* W2 = b1 + S.h1;
+    const float* b2 = W2 + (size_t)S.h1 * S.h2;
+    const float* W3 = b2 + S.h2;
+    const float* b3 = W3 + (size_t)S.h2 * S.dout;
+    const int nb = S.h1 + S.h2 + 16 * S.mb3;
+    if (e < S.o2) {
+        const int m = e / S.s1, p = e % S.s1;
+        out[e] = p < S.din ? f2bf(W1[(size_t)p * S.h1 + m]) : (uint16_t)0;
+    } else if (e < S.o3) {
+        const int m = (e - S.o2) / S.s2, p = (e - S.o2) % S.s2;
+        out[e] = p < S.h1 ? f2bf(W2[(size_t)perm_k(p) * S.h2 + m]) : (uint16_t)0;
+    } else if (e < S.ob) {
+        const int m = (e - S.o3) / S.s3, p = (e - S.o3) % S.s3;
+        out[e] = (p < S.h2 && m < S.dout) ? f2bf(W3[(size_t)perm_k(p) * S.dout + m]) : (uint16_t)0;
+    } else if (e < S.ob + nb) {
+        const int f = e - S.ob;
+        float v = 0.f;
+        if (f < S.h1) v = b1[f];
+        else if (f < S.h1 + S.h2) v = b2[f - S.h1];
+        else if (f - S.h1 - S.h2 < S.dout) v = b3[f - S.h1 - S.h2];
+        reinterpret_cast<float*>(out + S.ob)[f] = v;
+    }
+}
+
+__device__ __forceinline__ __bf16 relu_bf(float x) { return static_cast<__bf16>(x > 0.f ? x : 0.f); }
+
+__global__ __launch_bounds__(IF_T) void k_mlp_infer(const uint16_t* __restrict__ X, int rows, int ldx,
+                                                    const uint16_t* __restrict__ packed, const InferShape S,
+                                                    float* __restrict__ Y, int ldy) {
+    __shared__ __align__(16) uint16_t W[IF_LDS / 2];
+    {
+        const uint4* src = reinterpret_cast<const uint4*>(packed);
+        uint4* dst = reinterpret_cast<uint4*>(W);
+        for (int e = threadIdx.x; e < S.bytes / 16; e += IF_T) dst[e] = src[e];
+    }
+    __syncthreads();
+    const float* bias = reinterpret_cast<const float*>(W + S.ob);
+    const uint16_t* W2 = W + S.o2;
+    const uint16_t* W3 = W + S.o3;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int ntiles = (rows + IF_ROWS - 1) / IF_ROWS;
+    const bf16x8 zero8 = {};
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int row0 = t * IF_ROWS + wave * (IF_RB * 16);
+        // layer 1 inputs: lane holds X[row][32 c + 8 g .. + 7] of its batch row in each block
+        bf16x8 xb[IF_RB][IF_KC1];
+#pragma unroll
+        for (int rb = 0; rb < IF_RB; ++rb) {
+            const int row = row0 + rb * 16 + r16;
+#pragma unroll
+            for (int c = 0; c < IF_KC1; ++c) {
+                const int k = 32 * c + 8 * g;
+                xb[rb][c] = (c < S.kc1 && row < rows && k < S.din)
+                                ? *reinterpret_cast<const bf16x8*>(X + (size_t)row * ldx + k)
+                                : zero8;
+            }
+        }
+        f32x4 acc[IF_MB][IF_RB];
+#pragma unroll
+        for (int mb = 0; mb < IF_MB; ++mb)
+#pragma unroll
+            for (int rb = 0; rb < IF_RB; ++rb) acc[mb][rb] = zero4;
+#pragma unroll
+        for (int c = 0; c < IF_KC1; ++c) {
+            if (c >= S.kc1) break;
+#pragma unroll
+            for (int mb = 0; mb < IF_MB; ++mb) {
+                if (mb >= S.mb1) break;
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(W + (mb * 16 + r16) * S.s1 + 32 * c + 8 * g);
+#pragma unroll
+                for (int rb = 0; rb < IF_RB; ++rb)
+                    acc[mb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xb[rb][c], acc[mb][rb], 0, 0, 0);
+            }
+        }
+        // hidden layers: bias, ReLU, BF16, straight into the next layer's B fragments
+        bf16x8 hb[IF_KC][IF_RB];
+        int boff = 0;
+#pragma unroll
+        for (int layer = 0; layer < 2; ++layer) {
+            const int kc = layer == 0 ? S.kc2 : S.kc3;
+            const int mb_next = layer == 0 ? S.mb2 : S.mb3;
+            const int s = layer == 0 ? S.s2 : S.s3;
+            const uint16_t* Wn = layer == 0 ? W2 : W3;
+#pragma unroll
+            for (int c = 0; c < IF_KC; ++c) {
+#pragma unroll
+                for (int rb = 0; rb < IF_RB; ++rb) {
+                    bf16x8 h = zero8;
+                    if (c < kc) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            h[j] = relu_bf(acc[2 * c][rb][j] + bias[boff + 32 * c + 4 * g + j]);
+                            h[4 + j] = relu_bf(acc[2 * c + 1][rb][j] + bias[boff + 32 * c + 16 + 4 * g + j]);
+                        }
+                    }
+                    hb[c][rb] = h;
+                }
+            }
+            boff += layer == 0 ? S.h1 : S.h2;
+#pragma unroll
+            for (int mb = 0; mb < IF_MB; ++mb)
+#pragma unroll
+                for (int rb = 0; rb < IF_RB; ++rb) acc[mb][rb] = zero4;
+#pragma unroll
+            for (int c = 0; c < IF_KC; ++c) {
+                if (c >= kc) break;
+#pragma unroll
+                for (int mb = 0; mb < IF_MB; ++mb) {
+                    if (mb >= mb_next) break;
+                    const bf16x8 a = *reinterpret_cast<const bf16x8*>(Wn + (mb * 16 + r16) * s + 32 * c + 8 * g);
+#pragma unroll
+                    for (int rb = 0; rb < IF_RB; ++rb)
+                        acc[mb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[c][rb], acc[mb][rb], 0, 0, 0);
+                }
+            }
+        }
+        // outputs: lane holds units 16 mb + 4 g + v of its batch row
+#pragma unroll
+        for (int rb = 0; rb < IF_RB; ++rb) {
+            const int row = row0 + rb * 16 + r16;
+            if (row >= rows) continue;
+#pragma unroll
+            for (int mb = 0; mb < IF_MB; ++mb) {
+                if (mb >= S.mb3) break;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int o = 16 * mb + 4 * g + v;
+                    if (o < S.dout) Y[(size_t)row * ldy + o] = acc[mb][rb][v] + bias[boff + o];
+                }
+            }
+        }
+    }
+}
+
+// Layout of the packed image for a network shape; false if the fused kernel
+// does not take it (then inference runs layer by layer on the GEMM kernel).
+bool infer_shape(int din, int h1, int h2, int dout, InferShape* out) {
+    InferShape S{};
+    S.din = din; S.h1 = h1; S.h2 = h2; S.dout = dout;
+    if (din % 8 || h1 % 32 || h2 % 32 || din > 32 * IF_KC1 || h1 > 32 * IF_KC || h2 > 32 * IF_KC || dout > 16 * IF_MB)
+        return false;
+    S.kc1 = (din + 31) / 32; S.mb1 = h1 / 16;
+    S.kc2 = h1 / 32; S.mb2 = h2 / 16;
+    S.kc3 = h2 / 32; S.mb3 = (dout + 15) / 16;
+    // strides of 8 mod 16 elements put the 16 rows of a fragment read on distinct banks
+    S.s1 = 32 * S.kc1 + 8; S.s2 = h1 + 8; S.s3 = h2 + 8;
+    S.o2 = h1 * S.s1;
+    S.o3 = S.o2 + h2 * S.s2;
+    S.ob = (S.o3 + 16 * S.mb3 * S.s3 + 7) / 8 * 8;
+    S.bytes = (2 * S.ob + 4 * (h1 + h2 + 16 * S.mb3) + 15) / 16 * 16;
+    if (S.bytes > IF_LDS) return false;
+    *out = S;
+    return true;
+}
+
 }  // namespace ocn
 
 // ---------------------------------------------------------------------------
@@ -247,13 +446,19 @@ struct ocn_mlp {
     float *Y, *block_loss, *loss, *scratch;
     size_t scratch_floats;
     int t;                                       // Adam step count
+    bool fused;                                  // shape taken by the fused inference kernel
+    ocn::InferShape is;                          // its packed-weight layout
+    uint16_t* packed;                            // packed BF16 weights + FP32 biases (is.bytes)
+    int cus;                                     // compute units of the device (fused grid size)
 };
 
 namespace {
 
 struct MlpPlan {
     size_t o_params, o_grads, o_am, o_av, o_w1, o_w2, o_w3, o_x, o_h1, o_h2, o_dy, o_dh2, o_dh1, o_y, o_bl, o_loss,
-        o_scr, total, nparam, scratch_floats;
+        o_scr, o_pk, total, nparam, scratch_floats;
+    bool fused;
+    ocn::InferShape is;
 };
 
 size_t up256(size_t x) { return (x + 255) / 256 * 256; }
@@ -281,6 +486,8 @@ MlpPlan mlp_plan(int din, int h1, int h2, int dout, int nb) {
     P.o_bl = add((size_t)((nb * dout + 255) / 256 + 1) * 4);
     P.o_loss = add(4);
     P.o_scr = add(P.scratch_floats * 4);
+    P.fused = ocn::infer_shape(din, h1, h2, dout, &P.is);
+    P.o_pk = add(P.fused ? (size_t)P.is.bytes : 0);
     P.total = off;
     return P;
 }
@@ -303,6 +510,11 @@ int refresh_bf16(ocn_mlp* n) {
     conv(W1, n->din, n->h1, n->W1b);
     conv(W2, n->h1, n->h2, n->W2b);
     conv(W3, n->h2, n->dout, n->W3b);
+    if (n->fused) {
+        const int tot = n->is.ob + n->is.h1 + n->is.h2 + 16 * n->is.mb3;
+        hipLaunchKernelGGL(ocn::k_pack_infer, dim3((tot + 255) / 256), dim3(256), 0, n->st, n->params, n->is,
+                           n->packed);
+    }
     MLPCHK(hipGetLastError());
     return OCN_OK;
 }
@@ -378,6 +590,12 @@ void mlp_shape(const ::ocn_mlp* n, int* din, int* h1, int* h2, int* dout) {
 // stream and buffers (no split-K, so no scratch is needed).
 hipError_t mlp_infer(const ::ocn_mlp* n, const uint16_t* Xb, int rows, uint16_t* H1b, uint16_t* H2b, float* Y,
                      hipStream_t st) {
+    if (n->fused) {
+        const int tiles = (rows + IF_ROWS - 1) / IF_ROWS;
+        hipLaunchKernelGGL(k_mlp_infer, dim3(std::max(1, std::min(tiles, n->cus))), dim3(IF_T), 0, st, Xb, rows,
+                           n->din, n->packed, n->is, Y, n->dout);
+        return hipGetLastError();
+    }
     const float* b1 = n->params + (size_t)n->din * n->h1;
     const float* b2 = b1 + n->h1 + (size_t)n->h1 * n->h2;
     const float* b3 = b2 + n->h2 + (size_t)n->h2 * n->dout;
@@ -435,6 +653,18 @@ int ocn_mlp_init(int32_t din, int32_t h1, int32_t h2, int32_t dout, int32_t max_
     n->scratch = reinterpret_cast<float*>(A + P.o_scr);
     n->scratch_floats = P.scratch_floats;
     n->t = 0;
+    n->fused = P.fused;
+    n->is = P.is;
+    n->packed = reinterpret_cast<uint16_t*>(A + P.o_pk);
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+            delete n;
+            return ocn::set_error(OCN_E_DEVICE, "cannot query the compute-unit count");
+        }
+        n->cus = cus;
+    }
     hipError_t e = hipMemsetAsync(arena, 0, P.total, n->st);
     if (e == hipSuccess) e = hipStreamSynchronize(n->st);
     if (e != hipSuccess) {
@@ -479,6 +709,13 @@ int ocn_mlp_get_params(ocn_mlp* n, float* host, size_t count) {
 
 int ocn_mlp_forward(ocn_mlp* n, const float* x_dev, int32_t rows, float* y_dev) {
     if (!n || !x_dev || !y_dev || rows < 1 || rows > n->max_batch) return ocn::set_error(OCN_E_INVALID, "bad arguments");
+    if (n->fused) {
+        const long long tot = (long long)rows * n->din;
+        hipLaunchKernelGGL(ocn::k_to_bf16, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, n->st, x_dev, rows,
+                           n->din, n->din, n->Xb, n->din);
+        MLPCHK(ocn::mlp_infer(n, n->Xb, rows, n->H1b, n->H2b, y_dev, n->st));
+        return OCN_OK;
+    }
     int rc = forward(n, x_dev, rows);
     if (rc) return rc;
     MLPCHK(hipMemcpyAsync(y_dev, n->Y, (size_t)rows * n->dout * 4, hipMemcpyDeviceToDevice, n->st));

@@ -895,7 +895,7 @@ int ocn_closure_attach(ocn_state* s, const ocn_mlp* net, const float* norm, size
     if (!s || !workspace) return fail(OCN_E_INVALID, "state and workspace must not be NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(OCN_E_INVALID, "workspace must be 256-byte aligned");
     const int nz = s->g->nz;
-    if ((size_t)2 * nz * 64 * s->esize > 64 * 1024)
+    if ((size_t)2 * nz * 32 * s->esize > 64 * 1024)  // the LDS-staged solve at 32 columns per workgroup
         return fail(OCN_E_UNSUPPORTED, "nz too large for the variable-diffusivity column solve");
     int din = 0, h1 = 0, h2 = 0, dout = 0;
     if (net) {

@@ -57,6 +57,10 @@ CASES = {
     "latlon": lambda: (small_latlon(nx=100, ny=40, nz=8, dt=900.0, n_substeps=40), None),
     "steps_periodic": lambda: (inputs.BETA_BASIN_64.replace(name="steps_70x14x9", nx=70, ny=14, nz=9, depth=2700.0,
                                                             periodic_x=True, periodic_y=True, beta=0.0), 5),
+    # deeper columns reach the other solver forms: 40 levels are register-resident in
+    # FP32 and LDS-staged in FP64, 110 levels are LDS-staged in both
+    "deep40": lambda: (inputs.BETA_BASIN_64.replace(name="beta_40x20x40", nx=40, ny=20, nz=40), 7),
+    "deep110": lambda: (inputs.BETA_BASIN_64.replace(name="beta_24x16x110", nx=24, ny=16, nz=110), 8),
 }
 
 
@@ -107,16 +111,17 @@ def test_features_match_oracle(precision):
     gpu = _ocn().Model(w, precision, inp)
     ref.step(3)
     gpu.step(3)
-    din = 4 * w.nz + 3 + 5
     rng = np.random.default_rng(2)
-    mean, std = rng.normal(size=din), rng.uniform(0.5, 2.0, size=din)
-    for norm in (None, np.concatenate([mean, std])):
-        X = gpu.closure_features(din, norm).cpu().numpy().astype(np.float64)
-        E = ref.closure_features(din, *(None, None) if norm is None else (mean, std))
-        err = np.linalg.norm(X - E, axis=1) / np.maximum(np.linalg.norm(E, axis=1), 1e-30)
-        print(f"features {precision} norm={norm is not None}: max per-column rel {err.max():.2e}", flush=True)
-        assert err.max() <= (1e-6 if precision == "fp64" else 2e-5)
-        assert np.array_equal(X == 0, E == 0) or precision == "fp32"
+    for din in (4 * w.nz + 3 + 5, 4 * w.nz + 3):  # padded, and the odd minimum width
+        mean, std = rng.normal(size=din), rng.uniform(0.5, 2.0, size=din)
+        for norm in (None, np.concatenate([mean, std])):
+            X = gpu.closure_features(din, norm).cpu().numpy().astype(np.float64)
+            E = ref.closure_features(din, *(None, None) if norm is None else (mean, std))
+            err = np.linalg.norm(X - E, axis=1) / np.maximum(np.linalg.norm(E, axis=1), 1e-30)
+            print(f"features {precision} din={din} norm={norm is not None}: max per-column rel {err.max():.2e}",
+                  flush=True)
+            assert err.max() <= (1e-6 if precision == "fp64" else 2e-5)
+            assert np.array_equal(X == 0, E == 0) or precision == "fp32"
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-14), ("fp32", 1e-6)])

@@ -21,6 +21,13 @@ pytestmark = pytest.mark.gpu
 SHAPES = [(208, 128, 128, 56, 3000),   # a 50-level column's features, ragged row count, split-K active
           (24, 16, 32, 8, 70),         # tiny: single tiles, K smaller than one stage
           (64, 64, 64, 64, 64)]        # exact tiles
+# Inference runs on the fused kernel when din % 8 == 0, h1 and h2 are multiples of
+# 32 up to 128, din <= 256 and dout <= 128; the second shape above takes the
+# layer-by-layer GEMM path. Extra forward cases for the fused kernel's edges:
+FORWARD_SHAPES = SHAPES + [
+    (208, 128, 128, 50, 1000),   # the closure's 50-level network, 50 outputs (partial block), ragged tile
+    (256, 96, 64, 128, 300),     # widest input, unequal hidden widths, full output blocks
+    (8, 32, 32, 1, 5)]           # one input chunk, one output, fewer rows than a block
 
 
 def bf16_round(a):
@@ -53,7 +60,7 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("shape", FORWARD_SHAPES)
 def test_forward_matches_oracle(shape):
     din, h1, h2, dout, n = shape
     net, X, T, P, xd, td = _setup(din, h1, h2, dout, n, seed=1)
