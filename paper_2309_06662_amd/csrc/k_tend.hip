@@ -10,8 +10,9 @@
 // phi* = phi + dt ((3/2+chi) G^n - (1/2+chi) G^{n-1}), and the depth integral
 // of the AB2 momentum tendency that forces the barotropic mode.
 //
-// Mapping. A 64 x TY workgroup (TY = 8 in FP32, 4 in FP64) owns a tile of
-// 63 x (TY-1) columns and marches from the surface to the bottom. Tiles are
+// Mapping. A TX x TY workgroup (32 x 16 in FP32, 16 x 16 in FP64; the
+// batched ensemble kernel uses 64 x 4 or 64 x 8) owns a tile of
+// (TX-1) x (TY-1) columns and marches from the surface to the bottom. Tiles are
 // handed out so that the eight XCDs each sweep a contiguous band of the grid:
 // neighbouring tiles share an L2 and, marching in near lockstep, reuse each
 // other's halo rows from it. Thread (tx, ty) sits on point
@@ -41,11 +42,14 @@
 
 namespace ocn {
 
-constexpr int TX = 64;
+constexpr int TXB = 64;  // tile width of the batched ensemble launches (the host builds 63-column tiles)
 
+// Workgroup shape of the single-state launch: TX x TY threads own
+// (TX - 1) x (TY - 1) columns, so the ring of threads that only supply
+// neighbour fluxes costs TX TY / ((TX - 1)(TY - 1)) - 1 extra work.
 template <typename R> struct TendShape;
-template <> struct TendShape<float> { static constexpr int TY = 8; };
-template <> struct TendShape<double> { static constexpr int TY = 4; };
+template <> struct TendShape<float> { static constexpr int TX = 32, TY = 16; };
+template <> struct TendShape<double> { static constexpr int TX = 16, TY = 16; };
 
 template <typename R> struct Eps;
 template <> struct Eps<double> { static constexpr double v = 1e-8; };
@@ -150,7 +154,7 @@ template <> struct TendWaves<double> { static constexpr int n = 2; };
 
 // One tile (bx, by) of one state. Called by the single-state kernel and by the
 // batched kernel that steps an ensemble of basins in one launch.
-template <typename R, int TY>
+template <typename R, int TX, int TY>
 __device__ __forceinline__ void tend_tile(const DevState& S, const int first, const int bx, const int by) {
     constexpr int NT = TX * TY;
     constexpr int LW = TX + 5, LH = TY + 5, LN = LW * LH;  // value tiles: points -2 .. +3 around the block
@@ -511,43 +515,50 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     }
 }
 
-template <typename R, int TY>
+template <typename R, int TX, int TY>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R>::n)))
 void k_tend(const DevState S, const int first, const int gx) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    tend_tile<R, TY>(S, first, tile % gx, tile / gx);
+    tend_tile<R, TX, TY>(S, first, tile % gx, tile / gx);
 }
 
 // Ensemble: entry b of the tile table names (member, bx, by); the host orders
 // the table so that each XCD receives contiguous tiles of a member.
 template <typename R, int TY>
-__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R>::n)))
+__global__ __launch_bounds__(TXB * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R>::n)))
 void k_tend_batched(const DevState* __restrict__ members, const int4* __restrict__ tiles, const int first) {
     const int4 e = tiles[blockIdx.x];
-    tend_tile<R, TY>(members[e.x], first, e.y, e.z);
+    tend_tile<R, TXB, TY>(members[e.x], first, e.y, e.z);
 }
 
+// Rows of the 64-wide ensemble tiles: 4 or 8 as chosen, else 8 in FP32 and 4 in FP64.
 int tend_tile_rows(int precision_bytes, int ty_choice) {
     if (ty_choice == 4 || ty_choice == 8) return ty_choice;
-    return precision_bytes == 4 ? TendShape<float>::TY : TendShape<double>::TY;
+    return precision_bytes == 4 ? 8 : 4;
 }
 
-template <typename R>
-hipError_t launch_tendency(const DevState& s, int first, hipStream_t st) {
-    const int TY = tend_tile_rows(sizeof(R), s.tend_ty);
+template <typename R, int TX, int TY>
+hipError_t launch_tend_shape(const DevState& s, int first, hipStream_t st) {
     const int gx = (s.nx + TX - 2) / (TX - 1);
     const int gy = (s.ny + TY - 2) / (TY - 1);
-    if (TY == 8) hipLaunchKernelGGL((k_tend<R, 8>), dim3(gx * gy), dim3(TX, 8), 0, st, s, first, gx);
-    else hipLaunchKernelGGL((k_tend<R, 4>), dim3(gx * gy), dim3(TX, 4), 0, st, s, first, gx);
+    hipLaunchKernelGGL((k_tend<R, TX, TY>), dim3(gx * gy), dim3(TX, TY), 0, st, s, first, gx);
     return hipGetLastError();
+}
+
+// Single state: the precision's shape, or a 64-wide tile of 4 or 8 rows when chosen.
+template <typename R>
+hipError_t launch_tendency(const DevState& s, int first, hipStream_t st) {
+    if (s.tend_ty == 8) return launch_tend_shape<R, TXB, 8>(s, first, st);
+    if (s.tend_ty == 4) return launch_tend_shape<R, TXB, 4>(s, first, st);
+    return launch_tend_shape<R, TendShape<R>::TX, TendShape<R>::TY>(s, first, st);
 }
 
 template <typename R>
 hipError_t launch_tendency_batched(const DevState* members, const int4* tiles, int ntiles, int ty, int first,
                                    hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    if (ty == 8) hipLaunchKernelGGL((k_tend_batched<R, 8>), dim3(ntiles), dim3(TX, 8), 0, st, members, tiles, first);
-    else hipLaunchKernelGGL((k_tend_batched<R, 4>), dim3(ntiles), dim3(TX, 4), 0, st, members, tiles, first);
+    if (ty == 8) hipLaunchKernelGGL((k_tend_batched<R, 8>), dim3(ntiles), dim3(TXB, 8), 0, st, members, tiles, first);
+    else hipLaunchKernelGGL((k_tend_batched<R, 4>), dim3(ntiles), dim3(TXB, 4), 0, st, members, tiles, first);
     return hipGetLastError();
 }
 
