@@ -113,10 +113,18 @@ constexpr int FBX = kBaroTileX, FBY = kBaroTileY, FSMAX = 6;
 constexpr int FEW = FBX + 2 * FSMAX, FEH = FBY + 2 * FSMAX, FEN = FEW * FEH;
 constexpr int FT = 512, FQ = (FEN + FT - 1) / FT;
 
+constexpr int FI = FBX * FBY / FT;  // interior points per thread
+static_assert(FBX * FBY % FT == 0, "interior points must divide evenly over the threads");
+
+// Registers hold only what each halo-inclusive point needs every substep
+// (depths and slow forcing); row metrics sit in small LDS tables, and the
+// window sums live with a second mapping over the interior points only (FI
+// per thread), read from LDS between the barriers the substep has anyway.
 __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const int by, const double dtau,
                                           const int m0, const int s, const int first, const int last,
                                           const int parity) {
     __shared__ double sE[FEN], sU[FEN], sV[FEN];
+    __shared__ double sRdxc[FEH], sDxv0[FEH], sDxv1[FEH], sRarea[FEH];
     const double* __restrict__ inE = parity ? S.eta2 : S.eta;
     const double* __restrict__ inU = parity ? S.ubt2 : S.ubt;
     const double* __restrict__ inV = parity ? S.vbt2 : S.vbt;
@@ -129,12 +137,18 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
     const int eh = FBY + 2 * s;
     const int nx = S.nx, ny = S.ny;
 
-    // per owned point: forcing, depths, metrics, window sums
-    double gU[FQ], gV[FQ], Hu[FQ], Hv[FQ], rdxc[FQ], dxv0[FQ], dxv1[FQ], rarea[FQ];
-    double aU[FQ], aV[FQ];          // sum_l A_l U^l, V^l (transport of the step)
-    double fE[FQ], fU[FQ], fV[FQ];  // sum_q a_q eta^q, U^q, V^q (new state)
-    int gofs[FQ];
-    bool inner[FQ];
+    // row metrics (rows past a closed edge take the nearest row; unused)
+    for (int lj = tid; lj < eh; lj += FT) {
+        int gj = j0 - s + lj;
+        if (S.periodic_y) gj = ((gj % ny) + ny) % ny;
+        const int jm = min(max(gj, 0), ny - 1);
+        sRdxc[lj] = 1.0 / S.dxc[jm];
+        sDxv0[lj] = S.dxv[jm];
+        sDxv1[lj] = S.dxv[jm + 1];
+        sRarea[lj] = 1.0 / S.area[jm];
+    }
+    // halo-inclusive points: forcing and depths, and the state into LDS
+    double gU[FQ], gV[FQ], Hu[FQ], Hv[FQ];
 #pragma unroll
     for (int q = 0; q < FQ; ++q) {
         const int e = tid + q * FT;
@@ -148,28 +162,33 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
         else inside = inside && gj >= 0 && gj < ny;
         const int jm = min(max(gj, 0), ny - 1);
         const long long c = idx2(S, inside ? gi : 0, inside ? jm : 0);
-        gofs[q] = (int)c;
         gU[q] = inside ? S.gU[c] : 0.0;
         gV[q] = inside ? S.gV[c] : 0.0;
         Hu[q] = inside ? S.hu[c] : 0.0;
         Hv[q] = inside ? S.hv[c] : 0.0;
-        rdxc[q] = 1.0 / S.dxc[jm];
-        dxv0[q] = S.dxv[jm];
-        dxv1[q] = S.dxv[jm + 1];
-        rarea[q] = 1.0 / S.area[jm];
-        const int ti = i0 - s + li, tj = j0 - s + lj;  // unwrapped position
-        inner[q] = in_tile && li >= s && li < s + FBX && lj >= s && lj < s + FBY && ti < nx && tj < ny;
         if (e < FEN) {
             sE[e] = inside ? inE[c] : 0.0;
             sU[e] = inside ? inU[c] : 0.0;
             sV[e] = inside ? inV[c] : 0.0;
         }
-        const bool carry = inner[q] && !first;
-        aU[q] = carry ? S.su[c] : 0.0;
-        aV[q] = carry ? S.sv[c] : 0.0;
-        fE[q] = carry ? S.se[c] : 0.0;
-        fU[q] = carry ? S.sfu[c] : 0.0;
-        fV[q] = carry ? S.sfv[c] : 0.0;
+    }
+    // interior points: window sums carried between launches
+    double aU[FI], aV[FI];          // sum_l A_l U^l, V^l (transport of the step)
+    double fE[FI], fU[FI], fV[FI];  // sum_q a_q eta^q, U^q, V^q (new state)
+    int ie[FI];                     // LDS index, -1 outside the domain
+#pragma unroll
+    for (int p = 0; p < FI; ++p) {
+        const int pp = tid + p * FT;
+        const int ti = i0 + pp % FBX, tj = j0 + pp / FBX;
+        const bool live = ti < nx && tj < ny;
+        ie[p] = live ? (s + pp / FBX) * FEW + s + pp % FBX : -1;
+        const long long c = idx2(S, live ? ti : 0, live ? tj : 0);
+        const bool carry = live && !first;
+        aU[p] = carry ? S.su[c] : 0.0;
+        aV[p] = carry ? S.sv[c] : 0.0;
+        fE[p] = carry ? S.se[c] : 0.0;
+        fU[p] = carry ? S.sfu[c] : 0.0;
+        fV[p] = carry ? S.sfv[c] : 0.0;
     }
     __syncthreads();
 
@@ -186,13 +205,8 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
                 const int li = e % FEW, lj = e / FEW;
                 const int ee = (li + 1 < ew) ? e + 1 : e;    // tile edge: garbage stays in the halo
                 const int en_ = (lj + 1 < eh) ? e + FEW : e;
-                const double div = dy * (sU[ee] - sU[e]) + dxv1[q] * sV[en_] - dxv0[q] * sV[e];
-                en[q] = sE[e] - dtau * rarea[q] * div;
-                if (inner[q]) {
-                    aU[q] += Am * sU[e];
-                    aV[q] += Am * sV[e];
-                    fE[q] += am * en[q];
-                }
+                const double div = dy * (sU[ee] - sU[e]) + sDxv1[lj] * sV[en_] - sDxv0[lj] * sV[e];
+                en[q] = sE[e] - dtau * sRarea[lj] * div;
             }
         }
         __syncthreads();
@@ -202,6 +216,13 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
             if (e < FEN) sE[e] = en[q];
         }
         __syncthreads();
+#pragma unroll
+        for (int p = 0; p < FI; ++p) {
+            if (ie[p] < 0) continue;
+            aU[p] += Am * sU[ie[p]];
+            aV[p] += Am * sV[ie[p]];
+            fE[p] += am * sE[ie[p]];
+        }
         // transports from the new surface slope plus the slow forcing
         double un[FQ], vn[FQ];
 #pragma unroll
@@ -213,12 +234,8 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
                 const int li = e % FEW, lj = e / FEW;
                 const int ew_ = (li >= 1) ? e - 1 : e;
                 const int es_ = (lj >= 1) ? e - FEW : e;
-                un[q] = Hu[q] > 0.0 ? sU[e] + dtau * (-g * Hu[q] * (sE[e] - sE[ew_]) * rdxc[q] + gU[q]) : 0.0;
+                un[q] = Hu[q] > 0.0 ? sU[e] + dtau * (-g * Hu[q] * (sE[e] - sE[ew_]) * sRdxc[lj] + gU[q]) : 0.0;
                 vn[q] = Hv[q] > 0.0 ? sV[e] + dtau * (-g * Hv[q] * (sE[e] - sE[es_]) / dy + gV[q]) : 0.0;
-                if (inner[q]) {
-                    fU[q] += am * un[q];
-                    fV[q] += am * vn[q];
-                }
             }
         }
         __syncthreads();
@@ -228,20 +245,26 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
             if (e < FEN) { sU[e] = un[q]; sV[e] = vn[q]; }
         }
         __syncthreads();
+#pragma unroll
+        for (int p = 0; p < FI; ++p) {
+            if (ie[p] < 0) continue;
+            fU[p] += am * sU[ie[p]];
+            fV[p] += am * sV[ie[p]];
+        }
     }
 
     // write the interior (with its periodic halo copies): the instantaneous
     // state between launches, the window averages after the last one
 #pragma unroll
-    for (int q = 0; q < FQ; ++q) {
-        if (!inner[q]) continue;
-        const int e = tid + q * FT;
-        const int li = e % FEW, lj = e / FEW;
-        const int gi = i0 - s + li, gj = j0 - s + lj;
-        const long long c = gofs[q];
-        const double vE = last ? fE[q] : sE[e];
-        const double vU = last ? fU[q] : sU[e];
-        const double vV = last ? fV[q] : sV[e];
+    for (int p = 0; p < FI; ++p) {
+        if (ie[p] < 0) continue;
+        const int pp = tid + p * FT;
+        const int gi = i0 + pp % FBX, gj = j0 + pp / FBX;
+        const long long c = idx2(S, gi, gj);
+        const int e = ie[p];
+        const double vE = last ? fE[p] : sE[e];
+        const double vU = last ? fU[p] : sU[e];
+        const double vV = last ? fV[p] : sV[e];
         outE[c] = vE;
         outU[c] = vU;
         outV[c] = vV;
@@ -253,15 +276,15 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
         });
         if (last) {
             const double ns = double(S.n_substeps);
-            S.eta_mean[c] = fE[q];
-            S.ubt_mean[c] = aU[q] / ns;
-            S.vbt_mean[c] = aV[q] / ns;
+            S.eta_mean[c] = fE[p];
+            S.ubt_mean[c] = aU[p] / ns;
+            S.vbt_mean[c] = aV[p] / ns;
         } else {
-            S.su[c] = aU[q];
-            S.sv[c] = aV[q];
-            S.se[c] = fE[q];
-            S.sfu[c] = fU[q];
-            S.sfv[c] = fV[q];
+            S.su[c] = aU[p];
+            S.sv[c] = aV[p];
+            S.se[c] = fE[p];
+            S.sfu[c] = fU[p];
+            S.sfv[c] = fV[p];
         }
     }
 }
