@@ -15,7 +15,7 @@ from . import build as _build
 ORC_U, ORC_V, ORC_T, ORC_ETA, ORC_UBT, ORC_VBT = 0, 1, 2, 3, 4, 5
 ORC_ETA_MEAN, ORC_UBT_MEAN, ORC_VBT_MEAN, ORC_W = 6, 7, 8, 9
 ORC_GU_PREV, ORC_GV_PREV, ORC_GT_PREV = 10, 11, 12
-ORC_TAUX, ORC_TAUY, ORC_TSTAR, ORC_P, ORC_KAPPA = 13, 14, 15, 16, 17
+ORC_TAUX, ORC_TAUY, ORC_TSTAR, ORC_P, ORC_KAPPA, ORC_VISC = 13, 14, 15, 16, 17, 18
 TERM_ADV, TERM_COR, TERM_PGF, TERM_WIND, TERM_RESTORE, TERM_ALL = 1, 2, 4, 8, 16, 31
 NDIAG = 16
 DIAG_NAMES = ["step", "time", "tracer_content", "volume", "volume_mean", "kinetic_energy",
@@ -25,8 +25,11 @@ DIAG_NAMES = ["step", "time", "tracer_content", "volume", "volume_mean", "kineti
 FIELD_IDS = {"u": ORC_U, "v": ORC_V, "T": ORC_T, "eta": ORC_ETA, "U": ORC_UBT, "V": ORC_VBT,
              "eta_mean": ORC_ETA_MEAN, "U_mean": ORC_UBT_MEAN, "V_mean": ORC_VBT_MEAN,
              "w": ORC_W, "gu_prev": ORC_GU_PREV, "gv_prev": ORC_GV_PREV, "gt_prev": ORC_GT_PREV,
-             "taux": ORC_TAUX, "tauy": ORC_TAUY, "tstar": ORC_TSTAR, "p": ORC_P, "kappa": ORC_KAPPA}
-FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "p", "kappa"}
+             "taux": ORC_TAUX, "tauy": ORC_TAUY, "tstar": ORC_TSTAR, "p": ORC_P, "kappa": ORC_KAPPA,
+             "visc": ORC_VISC}
+FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "p", "kappa", "visc"}
+# Richardson-number mixing constants of the reading (Pacanowski and Philander 1981 form)
+RI_DEFAULTS = {"nu0": 1e-2, "alpha": 5.0, "nu_b": 1e-4, "kappa_b": 1e-5, "conv": 1.0}
 
 
 class OrcDesc(C.Structure):
@@ -76,6 +79,7 @@ def lib():
         L.orc_neumaier_sum.argtypes = [_D, C.c_int64]
         L.orc_column_zflux.argtypes = [C.c_int, _D, C.POINTER(C.c_int32), _D, _D]
         L.orc_set_convective.argtypes = [C.c_void_p, C.c_double]
+        L.orc_set_richardson.argtypes = [C.c_void_p] + [C.c_double] * 5
         L.orc_closure_features.argtypes = [C.c_void_p, C.c_int, _D, _D, _D]
         L.orc_closure_kappa.argtypes = [C.c_void_p, _D, C.c_double, _D]
         L.orc_mlp_forward.argtypes = [_D, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int] + [_D] * 9
@@ -176,6 +180,12 @@ class OracleModel:
     def set_convective(self, kappa_conv: float):
         """Convective adjustment: kappa_conv on faces with N^2 < 0 at the start of every step (<= 0: off)."""
         lib().orc_set_convective(self._h, float(kappa_conv))
+
+    def set_richardson(self, nu0=RI_DEFAULTS["nu0"], alpha=RI_DEFAULTS["alpha"], nu_b=RI_DEFAULTS["nu_b"],
+                       kappa_b=RI_DEFAULTS["kappa_b"], conv=RI_DEFAULTS["conv"]):
+        """Richardson-number mixing from the state at the start of every step (nu0 <= 0: off);
+        the faces of the current state are diagnosed at once ("kappa", "visc")."""
+        lib().orc_set_richardson(self._h, float(nu0), float(alpha), float(nu_b), float(kappa_b), float(conv))
 
     def closure_features(self, din: int, mean=None, std=None) -> np.ndarray:
         """Per-column network inputs, (ny*nx) x din (feature order in ocean_oracle.c)."""

@@ -41,7 +41,10 @@ struct orc_model {
     double *eta_mean, *U_mean, *V_mean;       /* substep averages of the last step */
     double *taux, *tauy, *tstar;              /* surface forcing (N/m^2, N/m^2, degC) */
     double *kw;          /* prescribed diffusivity on z-faces (m^2/s), or NULL for the constant */
+    double *kvw;         /* viscosity on z-faces for u and v, or NULL: they then use kw */
     double kappa_conv;   /* > 0: convective adjustment, kappa_conv on faces with N^2 < 0 */
+    int ri_on;           /* Richardson-number mixing (orc_set_richardson) */
+    double ri_nu0, ri_alpha, ri_nub, ri_kappab, ri_conv;
     int first_step;
     int64_t step;
     double time;
@@ -481,15 +484,74 @@ static double tracer_face_kappa(const orc_model* m, int i, int j, int kf) {
     if (!w_wet(m, i, j, kf)) return 0.0;
     return m->kw ? at3(m, m->kw, i, j, kf) : m->d.kappa;
 }
+/* momentum coefficient on a tracer face: the viscosity field when one is set
+ * (Richardson-number mixing), else the diffusivity */
+static double tracer_face_visc(const orc_model* m, int i, int j, int kf) {
+    if (!m->kvw) return tracer_face_kappa(m, i, j, kf);
+    if (!w_wet(m, i, j, kf)) return 0.0;
+    return at3(m, m->kvw, i, j, kf);
+}
 static double face_kappa(const orc_model* m, int kind, int i, int j, int kf) {
     if (kf <= 0 || kf >= m->nz) return 0.0;
     if (kind == 0) return tracer_face_kappa(m, i, j, kf);
     if (kind == 1) {
         if (!(u_wet(m, i, j, kf) && u_wet(m, i, j, kf - 1))) return 0.0;
-        return 0.5 * (tracer_face_kappa(m, i - 1, j, kf) + tracer_face_kappa(m, i, j, kf));
+        return 0.5 * (tracer_face_visc(m, i - 1, j, kf) + tracer_face_visc(m, i, j, kf));
     }
     if (!(v_wet(m, i, j, kf) && v_wet(m, i, j, kf - 1))) return 0.0;
-    return 0.5 * (tracer_face_kappa(m, i, j - 1, kf) + tracer_face_kappa(m, i, j, kf));
+    return 0.5 * (tracer_face_visc(m, i, j - 1, kf) + tracer_face_visc(m, i, j, kf));
+}
+
+/* Richardson-number vertical mixing (Sec. 6 runs a Richardson-number-based
+ * parameterization of shear and convective mixing; it gives no formula, so
+ * the Pacanowski-Philander (1981) form is the reading). On an interior wet
+ * face k of column (i, j), from the state at the start of the step:
+ *   N^2 = g alpha (T_k - T_{k-1}) / dzc_k,
+ *   S^2 = ((uc_k - uc_{k-1})^2 + (vc_k - vc_{k-1})^2) / dzc_k^2, with uc, vc
+ *         the velocities averaged to the cell centre (a dry or closed-edge
+ *         face counts as 0),
+ *   N^2 < 0: viscosity = diffusivity = conv (convective turbulence);
+ *   else Ri = N^2 / max(S^2, 1e-16), r = 1 / (1 + a Ri),
+ *        viscosity nu = nu0 r^2 + nub, diffusivity kappa = nu r + kappab.
+ * Dry faces and face 0 take 0. */
+static void richardson_faces(orc_model* m) {
+    const int nx = m->nx, ny = m->ny, nz = m->nz;
+    const size_t n3 = (size_t)nx * ny * nz;
+    if (!m->kw) m->kw = (double*)malloc(sizeof(double) * n3);
+    if (!m->kvw) m->kvw = (double*)malloc(sizeof(double) * n3);
+    const double ga = m->d.g * m->d.alpha;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double kap = 0.0, nu = 0.0;
+                if (k >= 1 && w_wet(m, i, j, k)) {
+                    const int ie = (i + 1 < nx) ? i + 1 : (m->d.periodic_x ? 0 : -1);
+                    const int jn = (j + 1 < ny) ? j + 1 : (m->d.periodic_y ? 0 : -1);
+                    double uc[2], vc[2];
+                    for (int q = 0; q < 2; ++q) {
+                        const int kk = k - 1 + q;
+                        const double ue = ie >= 0 ? m->u[id3(m, ie, j, kk)] : 0.0;
+                        const double vn = jn >= 0 ? m->v[id3(m, i, jn, kk)] : 0.0;
+                        uc[q] = 0.5 * (m->u[id3(m, i, j, kk)] + ue);
+                        vc[q] = 0.5 * (m->v[id3(m, i, j, kk)] + vn);
+                    }
+                    const double dzc = 0.5 * (m->dz[k - 1] + m->dz[k]);
+                    const double n2 = ga * (m->T[id3(m, i, j, k)] - m->T[id3(m, i, j, k - 1)]) / dzc;
+                    const double du = uc[1] - uc[0], dv = vc[1] - vc[0];
+                    const double s2 = (du * du + dv * dv) / (dzc * dzc);
+                    if (n2 < 0.0) {
+                        kap = m->ri_conv;
+                        nu = m->ri_conv;
+                    } else {
+                        const double ri = n2 / fmax(s2, 1e-16);
+                        const double r = 1.0 / (1.0 + m->ri_alpha * ri);
+                        nu = m->ri_nu0 * r * r + m->ri_nub;
+                        kap = nu * r + m->ri_kappab;
+                    }
+                }
+                m->kw[id3(m, i, j, k)] = kap;
+                m->kvw[id3(m, i, j, k)] = nu;
+            }
 }
 
 static void implicit_column(const orc_model* m, int kind, int i, int j, const double* phistar, double* out) {
@@ -534,7 +596,8 @@ static void step_once(orc_model* m) {
      * start of the step, Sec. 5.1): kappa_conv on interior wet faces where the
      * water above is denser than the water below (N^2 = g alpha dT/dz < 0),
      * the constant elsewhere */
-    if (m->kappa_conv > 0.0) {
+    if (m->ri_on) richardson_faces(m);
+    else if (m->kappa_conv > 0.0) {
         if (!m->kw) m->kw = (double*)malloc(sizeof(double) * n3);
         for (int k = 0; k < nz; ++k)
             for (int j = 0; j < ny; ++j)
@@ -804,7 +867,7 @@ orc_model* orc_create(const orc_desc* d, const double* dz, const int32_t* kbotto
 void orc_destroy(orc_model* m) {
     if (!m) return;
     double* all[] = {m->dz, m->u, m->v, m->T, m->gu_prev, m->gv_prev, m->gt_prev, m->eta, m->U, m->V,
-                     m->eta_mean, m->U_mean, m->V_mean, m->taux, m->tauy, m->tstar, m->kw};
+                     m->eta_mean, m->U_mean, m->V_mean, m->taux, m->tauy, m->tstar, m->kw, m->kvw};
     for (size_t q = 0; q < sizeof(all) / sizeof(all[0]); ++q) free(all[q]);
     free(m->kb);
     free(m);
@@ -837,7 +900,7 @@ int orc_set_field(orc_model* m, int f, const double* src) {
     size_t n = 0;
     if (f == ORC_KAPPA) {  /* NULL returns to the constant diffusivity */
         const size_t n3 = (size_t)m->nx * m->ny * m->nz;
-        if (!src) { free(m->kw); m->kw = NULL; return 0; }
+        if (!src) { free(m->kw); m->kw = NULL; free(m->kvw); m->kvw = NULL; return 0; }
         if (!m->kw) m->kw = (double*)malloc(sizeof(double) * n3);
         memcpy(m->kw, src, sizeof(double) * n3);
         return 0;
@@ -877,6 +940,13 @@ int orc_get_field(orc_model* m, int f, double* dst) {
                 for (int i = 0; i < m->nx; ++i) dst[id3(m, i, j, k)] = face_kappa(m, 0, i, j, k);
         return 0;
     }
+    if (f == ORC_VISC) {  /* the momentum coefficient on every tracer face (0 where dry or face 0) */
+        for (int k = 0; k < m->nz; ++k)
+            for (int j = 0; j < m->ny; ++j)
+                for (int i = 0; i < m->nx; ++i)
+                    dst[id3(m, i, j, k)] = (k >= 1 && k < m->nz) ? tracer_face_visc(m, i, j, k) : 0.0;
+        return 0;
+    }
     size_t n = 0;
     double* p = field_ptr(m, f, &n);
     if (!p) return -1;
@@ -887,7 +957,24 @@ int orc_get_field(orc_model* m, int f, double* dst) {
 void orc_set_first_step(orc_model* m, int first) { m->first_step = first ? 1 : 0; }
 void orc_set_convective(orc_model* m, double kappa_conv) {
     m->kappa_conv = kappa_conv > 0.0 ? kappa_conv : 0.0;
+    m->ri_on = 0;
+    free(m->kvw);
+    m->kvw = NULL;
     if (m->kappa_conv == 0.0) { free(m->kw); m->kw = NULL; }
+}
+void orc_set_richardson(orc_model* m, double nu0, double alpha, double nub, double kappab, double conv) {
+    free(m->kvw);
+    m->kvw = NULL;
+    free(m->kw);
+    m->kw = NULL;
+    m->kappa_conv = 0.0;
+    m->ri_on = nu0 > 0.0;
+    m->ri_nu0 = nu0;
+    m->ri_alpha = alpha;
+    m->ri_nub = nub;
+    m->ri_kappab = kappab;
+    m->ri_conv = conv;
+    if (m->ri_on) richardson_faces(m);
 }
 int orc_get_first_step(const orc_model* m) { return m->first_step; }
 

@@ -45,8 +45,10 @@ enum {
     ORC_ETA_MEAN = 6, ORC_UBT_MEAN = 7, ORC_VBT_MEAN = 8, ORC_W = 9,
     ORC_GU_PREV = 10, ORC_GV_PREV = 11, ORC_GT_PREV = 12,
     ORC_TAUX = 13, ORC_TAUY = 14, ORC_TSTAR = 15, ORC_P = 16,
-    ORC_KAPPA = 17   /* z-face diffusivity, nz*ny*nx, slot k = face between layers k-1 and k;
+    ORC_KAPPA = 17,  /* z-face diffusivity, nz*ny*nx, slot k = face between layers k-1 and k;
                         setting NULL returns to the constant */
+    ORC_VISC = 18    /* z-face momentum coefficient on tracer faces (get only): the viscosity
+                        of Richardson-number mixing, else the diffusivity */
 };
 
 /* Tendency term selectors for orc_eval_tendencies. */
@@ -65,6 +67,12 @@ void       orc_set_first_step(orc_model* m, int first);
  * face diffusivity to kappa_conv where N^2 < 0 and to the constant elsewhere
  * (it replaces a prescribed field); kappa_conv <= 0 returns to the constant. */
 void       orc_set_convective(orc_model* m, double kappa_conv);
+/* Richardson-number mixing: with nu0 > 0 every step starts by diagnosing the
+ * face viscosity (u, v) and diffusivity (T) from the current state,
+ * Pacanowski-Philander form with constants nu0, alpha, nub, kappab and conv
+ * where N^2 < 0 (see richardson_faces); nu0 <= 0 returns to the constant.
+ * Replaces convective adjustment and any prescribed field. */
+void       orc_set_richardson(orc_model* m, double nu0, double alpha, double nub, double kappab, double conv);
 int        orc_get_first_step(const orc_model* m);
 void       orc_step(orc_model* m, int n);
 void       orc_diagnostics(const orc_model* m, double* out);

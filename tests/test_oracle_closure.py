@@ -173,3 +173,61 @@ def test_convective_adjustment_mixes_unstable_faces_only():
     assert np.array_equal(m.get("kappa")[:, 0, 0], kf)
     m.set_convective(0.0)
     assert np.all(m.get("kappa")[1:, 0, 0] == 1e-5)
+
+
+# --- Richardson-number mixing (Pacanowski-Philander form; constants of the reading:
+# nu0 = 1e-2, alpha = 5, nu_b = 1e-4, kappa_b = 1e-5, conv = 1 m^2/s) ---
+
+def _richardson_column():
+    """Two periodic columns, uniform in x, 100 m layers. Faces (k between layers k-1, k):
+    1: no stratification, shear 0.1 m/s per 100 m      -> Ri = 0
+    2: shear 0.1 m/s per 100 m, N^2 = 0.2 S^2          -> Ri = 1/alpha
+    3: 0.5 K colder above                              -> convective
+    4: 0.5 K warmer above, no shear                    -> Ri huge (background)"""
+    nz = 5
+    w = _column_workload(2, nz, kappa=1e-5)
+    dz = np.full(nz, 100.0)
+    m = oracle.OracleModel(w, dz, np.full((1, 2), nz, dtype=np.int32))
+    s2 = (0.1 / 100.0) ** 2
+    dT2 = 0.2 * s2 * 100.0 / (w.g * w.alpha)        # N^2 = g alpha dT / dzc = 0.2 S^2
+    Tcol = np.array([10.0, 10.0, 10.0 + dT2, 9.5 + dT2, 10.0 + dT2])
+    ucol = np.array([0.0, 0.1, 0.2, 0.5, 0.5])
+    m.set("T", np.repeat(Tcol[:, None, None], 2, axis=2))
+    m.set("u", np.repeat(ucol[:, None, None], 2, axis=2))
+    m.set("U", np.full((1, 2), np.sum(dz * ucol)))
+    return m, w, dz, Tcol, ucol
+
+
+def test_richardson_faces_worked_values():
+    m, w, dz, Tcol, ucol = _richardson_column()
+    m.set_richardson()
+    kap, nu = m.get("kappa")[:, 0, 0], m.get("visc")[:, 0, 0]
+    # worked by hand from nu = nu0 r^2 + nu_b, kappa = nu r + kappa_b, r = 1 / (1 + 5 Ri)
+    exp_nu = [0.0, 1.01e-2, 2.6e-3, 1.0, 1e-4]        # Ri = 0: nu0 + nu_b; Ri = 1/5: nu0/4 + nu_b
+    exp_kap = [0.0, 1.011e-2, 1.31e-3, 1.0, 1e-5]     # Ri = 0: nu + kappa_b; Ri = 1/5: nu/2 + kappa_b
+    assert np.allclose(nu[:4], exp_nu[:4], rtol=1e-12, atol=0)
+    assert np.allclose(kap[:4], exp_kap[:4], rtol=1e-12, atol=0)
+    assert abs(nu[4] - 1e-4) < 1e-15 and abs(kap[4] - 1e-5) < 1e-15   # r ~ 1e-13 on face 4
+    assert np.array_equal(m.get("kappa")[:, 0, 0], m.get("kappa")[:, 0, 1])
+
+
+def test_richardson_mixing_solves_tracer_with_kappa_and_momentum_with_viscosity():
+    """At rest horizontally only vertical diffusion acts: T takes the diagnosed
+    diffusivity, u the diagnosed viscosity (mean of the two identical columns)."""
+    m, w, dz, Tcol, ucol = _richardson_column()
+    m.set_richardson()
+    kap, nu = m.get("kappa")[:, 0, 0].copy(), m.get("visc")[:, 0, 0].copy()
+    m.step(1)   # diagnoses again from the same state, then steps
+    assert np.allclose(m.get("T")[:, 0, 0], _dense_backward_euler(Tcol, dz, kap, w.dt), rtol=0, atol=1e-12)
+    assert np.allclose(m.get("u")[:, 0, 1], _dense_backward_euler(ucol, dz, nu, w.dt), rtol=0, atol=1e-13)
+
+
+def test_richardson_mode_switches():
+    m, w, dz, Tcol, ucol = _richardson_column()
+    m.set_richardson()
+    assert not np.array_equal(m.get("visc"), m.get("kappa"))
+    m.set_convective(1.0)      # convective adjustment replaces it: momentum uses the diffusivity again
+    m.step(1)
+    assert np.array_equal(m.get("visc"), m.get("kappa"))
+    m.set_richardson(nu0=0.0)  # off: back to the constant
+    assert np.all(m.get("kappa")[1:] == w.kappa) and np.all(m.get("visc")[1:] == w.kappa)
