@@ -206,6 +206,30 @@ def run_quarter(steps, warmup):
     out["closure"] = {"network": [din, h, h, dout], "ms_per_step": el / steps * 1e3,
                       "closure_stage_ms": cl_ms, "slowdown_vs_constant_kappa": (el / steps * 1e3) / out["fp32"]["ms_per_step"],
                       "network_tflops_in_closure_stage": gemm_flops / (cl_ms * 1e-3) / 1e12, "finite": finite}
+    # Richardson-number mixing: viscosity and diffusivity diagnosed from the state every step
+    m = ocn.Model(w, "fp32", inp)
+    m.attach_closure()
+    m.set_richardson()
+    m.step(warmup)
+    m.synchronize()
+    m.stage_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.step(steps)
+    m.synchronize()
+    el = time.perf_counter() - t0
+    st, n = m.stage_times()
+    m.stage_timing(False)
+    finite = m.diagnostics(allow_unstable=True)["nonfinite"] == 0
+    m.detach_closure()
+    m.close()
+    ri_ms = st["closure"] / max(n, 1)
+    # the diagnosis reads T, u, v and writes the two face fields: 5 FP32 words per cell
+    out["richardson"] = {"ms_per_step": el / steps * 1e3, "diagnosis_ms": ri_ms,
+                         "diagnosis_gbs": 5 * 4 * w.cells / (ri_ms * 1e-3) / 1e9,
+                         "column_ms": st["column"] / max(n, 1),
+                         "slowdown_vs_constant_kappa": (el / steps * 1e3) / out["fp32"]["ms_per_step"],
+                         "finite": finite}
     return out
 
 

@@ -112,10 +112,14 @@ typedef enum {
     OCN_FIELD_TAUY = 14,      /* 2D meridional wind stress at v-points (N/m^2)      */
     OCN_FIELD_TSTAR = 15,     /* 2D surface restoring temperature (degC)            */
     OCN_FIELD_TREF = 16,      /* nz reference profile of the stored T anomaly        */
-    OCN_FIELD_KAPPA = 17      /* 3D tracer diffusivity on z-faces (m^2/s): slot k is
+    OCN_FIELD_KAPPA = 17,     /* 3D tracer diffusivity on z-faces (m^2/s): slot k is
                                  the face between layers k-1 and k; get returns 0 on
                                  dry faces (and the constant when no closure is
                                  attached); set only with a prescribed-field closure */
+    OCN_FIELD_VISC = 18       /* 3D momentum coefficient on tracer z-faces (m^2/s), get
+                                 only: the viscosity of Richardson-number mixing, else
+                                 the same as KAPPA; u and v faces take the mean of
+                                 their two neighbouring columns */
 } ocn_field;
 
 typedef struct ocn_diag {
@@ -277,6 +281,22 @@ int ocn_closure_detach(ocn_state* state);
  * turns it off (the field keeps its last values). Needs a closure attached
  * with net == NULL (else OCN_E_STATE); synchronises the stream. */
 int ocn_closure_convective(ocn_state* state, double kappa_conv);
+/* Richardson-number vertical mixing in the prescribed-field mode (paper Sec. 6
+ * runs a Richardson-number-based parameterization of shear and convective
+ * mixing and gives no formula; this is the Pacanowski-Philander form). With
+ * nu0 > 0 every step starts by diagnosing, on each interior wet z-face from
+ * the current state, N^2 = g alpha dT/dz and S^2 = |d(u_c, v_c)/dz|^2 (u, v
+ * averaged to the cell centre); where N^2 < 0 the viscosity and diffusivity
+ * are conv, else with Ri = N^2 / max(S^2, 1e-16) and r = 1 / (1 + alpha Ri):
+ * viscosity nu = nu0 r^2 + nu_b (u and v), diffusivity nu r + kappa_b (T).
+ * The faces of the current state are diagnosed at once (OCN_FIELD_KAPPA,
+ * OCN_FIELD_VISC). nu0 <= 0 turns it off and sets every face back to the
+ * constant kappa; enabling it turns convective adjustment off and enabling
+ * that turns it off. Needs a closure attached with net == NULL (else
+ * OCN_E_STATE); alpha, nu_b, kappa_b, conv must be finite and >= 0;
+ * synchronises the stream. */
+int ocn_closure_richardson(ocn_state* state, double nu0, double alpha, double nu_b, double kappa_b,
+                           double conv);
 /* Network inputs of every column of the current state into x (device FP32,
  * (ny nx) x din row-major, row j nx + i), din >= 4 nz + 3 and 64 (din + 1) 4
  * bytes <= 64 KiB. Order: T (nz levels, bottom first), u and v averaged to

@@ -207,6 +207,87 @@ __global__ __launch_bounds__(FW) void k_convective(const DevState S, double kapp
     }
 }
 
+// Richardson-number mixing (Sec. 6 runs a Richardson-number-based mixing
+// parameterization without giving its form; the Pacanowski-Philander form is
+// the reading): on an interior wet face k, from the state at the start of
+// the step, N^2 = g alpha dT/dz and S^2 = |d(u_c, v_c)/dz|^2 with the
+// velocities averaged to the cell centre; where N^2 < 0 both coefficients are
+// conv, else with Ri = N^2 / max(S^2, 1e-16) and r = 1 / (1 + alpha Ri) the
+// viscosity is nu0 r^2 + nu_b and the diffusivity nu r + kappa_b. Dry faces
+// take 0. 256 adjacent columns per workgroup, one thread per column marching
+// up the levels with the lower level's values carried in registers.
+constexpr int RW = 256;
+
+template <typename R>
+__global__ __launch_bounds__(RW) void k_richardson(const DevState S, const RiParams P) {
+    const int i = blockIdx.x * RW + threadIdx.x, j = blockIdx.y;
+    if (i >= S.nx) return;
+    const int nz = S.nz;
+    const int K = S.kb[idxk(S, i, j)];
+    const int kbot = nz - K;
+    const int ie = (i + 1 < S.nx) ? i + 1 : (S.periodic_x ? 0 : -1);
+    const int jn = (j + 1 < S.ny) ? j + 1 : (S.periodic_y ? 0 : -1);
+    const int Kuw = min(K, S.kb[idxk(S, i - 1, j)]);
+    const int Kue = ie >= 0 ? min(K, S.kb[idxk(S, ie, j)]) : 0;
+    const int Kvs = min(K, S.kb[idxk(S, i, j - 1)]);
+    const int Kvn = jn >= 0 ? min(K, S.kb[idxk(S, i, jn)]) : 0;
+    const int iec = ie >= 0 ? ie : i, jnc = jn >= 0 ? jn : j;
+    const R* T = f3<R>(S.t);
+    const R* U = f3<R>(S.u);
+    const R* V = f3<R>(S.v);
+    R* kw = f3<R>(S.kw);
+    R* kv = f3<R>(S.kv);
+    const double ga = S.g * S.alpha;
+    double tb = 0.0, ub = 0.0, vb = 0.0;  // the level below
+#pragma unroll 4
+    for (int k = 0; k < nz; ++k) {
+        double kap = 0.0, nu = 0.0;
+        if (k >= kbot) {
+            const double tk = double(T[idx3(S, i, j, k)]) + S.tref[k];
+            const double uw = (k >= nz - Kuw) ? double(U[idx3(S, i, j, k)]) : 0.0;
+            const double ue = (k >= nz - Kue) ? double(U[idx3(S, iec, j, k)]) : 0.0;
+            const double vs = (k >= nz - Kvs) ? double(V[idx3(S, i, j, k)]) : 0.0;
+            const double vn = (k >= nz - Kvn) ? double(V[idx3(S, i, jnc, k)]) : 0.0;
+            const double uk = 0.5 * (uw + ue), vk = 0.5 * (vs + vn);
+            if (k > kbot) {
+                const double dzc = S.dzc[k];
+                const double n2 = ga * (tk - tb) / dzc;
+                const double du = uk - ub, dv = vk - vb;
+                const double s2 = (du * du + dv * dv) / (dzc * dzc);
+                if (n2 < 0.0) {
+                    kap = P.conv;
+                    nu = P.conv;
+                } else {
+                    const double ri = n2 / fmax(s2, 1e-16);
+                    const double r = 1.0 / (1.0 + P.alpha * ri);
+                    nu = P.nu0 * r * r + P.nu_b;
+                    kap = nu * r + P.kappa_b;
+                }
+            }
+            tb = tk;
+            ub = uk;
+            vb = vk;
+        }
+        const R vkap = R(kap), vnu = R(nu);
+        kw[idx3(S, i, j, k)] = vkap;
+        kv[idx3(S, i, j, k)] = vnu;
+        for_each_image(S, i, j, S.h, [&](int x, int y) {
+            kw[idx3(S, x, y, k)] = vkap;
+            kv[idx3(S, x, y, k)] = vnu;
+        });
+    }
+}
+
+template <typename R>
+hipError_t launch_richardson(const DevState& s, const RiParams& p, hipStream_t st) {
+    if (!s.kw || !s.kv) return hipErrorInvalidValue;
+    dim3 grid((s.nx + RW - 1) / RW, s.ny);
+    hipLaunchKernelGGL(k_richardson<R>, grid, dim3(RW), 0, st, s, p);
+    return hipGetLastError();
+}
+template hipError_t launch_richardson<double>(const DevState&, const RiParams&, hipStream_t);
+template hipError_t launch_richardson<float>(const DevState&, const RiParams&, hipStream_t);
+
 template <typename R>
 hipError_t launch_convective(const DevState& s, double kappa_conv, double kappa0, hipStream_t st) {
     dim3 grid((s.nx + FW - 1) / FW, s.ny);

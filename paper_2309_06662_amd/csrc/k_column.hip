@@ -183,7 +183,7 @@ __device__ __forceinline__ void column_block_vk(const DevState& S, R* sd, R* sc,
     const R* src = f3<R>(field == 0 ? S.ts : field == 1 ? S.us : S.vs) + idx3(S, ic, j, 0);
     R* dst = f3<R>(field == 0 ? S.t : field == 1 ? S.u : S.v);
     const R* dtr = static_cast<const R*>(S.dtr);
-    const R* kwf = static_cast<const R*>(S.kw);
+    const R* kwf = static_cast<const R*>(field != 0 && S.kv ? S.kv : S.kw);  // u, v: viscosity when set
     const long long o0 = idx3(S, ic, j, 0);
     const long long on = field == 1 ? idx3(S, ic - 1, j, 0) : idx3(S, ic, j - 1, 0);
     const int kbot = nz - K;
@@ -272,7 +272,7 @@ __device__ __forceinline__ void column_regs_vk(const DevState& S, const int bx, 
     const int kbot = nz - K;
 
     const R* src = f3<R>(field == 0 ? S.ts : field == 1 ? S.us : S.vs) + idx3(S, ic, j, 0);
-    const R* kwf = static_cast<const R*>(S.kw);
+    const R* kwf = static_cast<const R*>(field != 0 && S.kv ? S.kv : S.kw);  // u, v: viscosity when set
     const R* dtr = static_cast<const R*>(S.dtr);
     const long long o0 = idx3(S, ic, j, 0);
     const long long on = field == 1 ? idx3(S, ic - 1, j, 0) : idx3(S, ic, j - 1, 0);

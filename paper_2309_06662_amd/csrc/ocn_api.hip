@@ -81,6 +81,9 @@ struct ocn_state {
     uint16_t *xb = nullptr, *h1b = nullptr, *h2b = nullptr;
     float* y = nullptr;
     double kappa_conv = 0.0;      // > 0: convective adjustment into the prescribed field
+    bool ri_on = false;           // Richardson-number mixing into the prescribed field
+    ocn::RiParams ri{};
+    void* kv_ws = nullptr;        // the workspace's viscosity field (interior origin)
     // one step captured as a HIP graph (ocn_step_graph)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -528,6 +531,22 @@ int get_field_t(ocn_state* s, int32_t f, double* host) {
                 }
         return OCN_OK;
     }
+    case OCN_FIELD_VISC: {  // momentum coefficient on every tracer z-face, 0 where the face is dry
+        const int nx = g->nx, ny = g->ny, nz = g->nz;
+        if (s->closure) {
+            int rc = get3<R>(s, d.kv ? d.kv : d.kw, host, nullptr, nz);
+            if (rc) return rc;
+        }
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    double& v = host[((size_t)k * ny + j) * nx + i];
+                    const bool wet = k > nz - kb_at(g, i, j);
+                    if (!s->closure) v = s->p.kappa;
+                    if (!wet) v = 0.0;
+                }
+        return OCN_OK;
+    }
     case OCN_FIELD_W: {
         HIPCHK(ocn::launch_w_faces<R>(d, nullptr, s->st));
         const size_t n2 = (size_t)g->nx * g->ny;
@@ -542,7 +561,7 @@ int get_field_t(ocn_state* s, int32_t f, double* host) {
 size_t field_count(const ocn_grid* g, int32_t f) {
     const size_t n2 = (size_t)g->nx * g->ny, n3 = n2 * g->nz;
     switch (f) {
-    case OCN_FIELD_U: case OCN_FIELD_V: case OCN_FIELD_T: case OCN_FIELD_KAPPA:
+    case OCN_FIELD_U: case OCN_FIELD_V: case OCN_FIELD_T: case OCN_FIELD_KAPPA: case OCN_FIELD_VISC:
     case OCN_FIELD_GU_PREV: case OCN_FIELD_GV_PREV: case OCN_FIELD_GT_PREV: return n3;
     case OCN_FIELD_W: return n2 * (g->nz + 1);
     case OCN_FIELD_TREF: return g->nz;
@@ -786,7 +805,7 @@ int closure_update(ocn_state* s) {
 }
 
 struct ClosurePlan {
-    size_t kw, norm, xb, h1b, h2b, y, total;
+    size_t kw, kv, norm, xb, h1b, h2b, y, total;
 };
 
 size_t up256(size_t x) { return (x + 255) / 256 * 256; }
@@ -797,6 +816,7 @@ ClosurePlan closure_plan(const ocn_state* s, int din, int h1, int h2, int dout) 
     size_t off = 0;
     auto add = [&](size_t b) { size_t o = off; off = up256(off + b); return o; };
     P.kw = add(s->n3 * s->esize);
+    if (din == 0) P.kv = add(s->n3 * s->esize);  // viscosity of Richardson mixing (prescribed mode)
     if (din > 0) {
         P.norm = add((size_t)2 * din * sizeof(float));
         P.xb = add(rows * din * 2);
@@ -818,7 +838,10 @@ int enqueue_step(ocn_state* s) {
     int rc;
     if (s->timing && (rc = record(s))) return rc;
     if (s->closure && s->net && (rc = closure_update(s))) return rc;
-    if (s->closure && !s->net && s->kappa_conv > 0.0)
+    if (s->closure && !s->net && s->ri_on)
+        HIPCHK(s->esize == 4 ? ocn::launch_richardson<float>(s->d, s->ri, s->st)
+                             : ocn::launch_richardson<double>(s->d, s->ri, s->st));
+    else if (s->closure && !s->net && s->kappa_conv > 0.0)
         HIPCHK(s->esize == 4 ? ocn::launch_convective<float>(s->d, s->kappa_conv, s->p.kappa, s->st)
                              : ocn::launch_convective<double>(s->d, s->kappa_conv, s->p.kappa, s->st));
     if (s->timing && (rc = record(s))) return rc;
@@ -917,6 +940,10 @@ int ocn_closure_attach(ocn_state* s, const ocn_mlp* net, const float* norm, size
     HIPCHK(s->esize == 4 ? ocn::launch_fill<float>(W + P.kw, (long long)s->n3, s->p.kappa, s->st)
                          : ocn::launch_fill<double>(W + P.kw, (long long)s->n3, s->p.kappa, s->st));
     s->d.kw = W + P.kw + o3;
+    s->d.kv = nullptr;
+    s->kv_ws = net ? nullptr : W + P.kv + o3;
+    s->ri_on = false;
+    s->kappa_conv = 0.0;
     s->closure = true;
     s->net = net;
     s->din = din; s->h1 = h1; s->h2 = h2; s->dout = dout;
@@ -939,6 +966,37 @@ int ocn_closure_convective(ocn_state* s, double kappa_conv) {
     HIPCHK(hipStreamSynchronize(s->st));
     drop_graph(s);
     s->kappa_conv = kappa_conv > 0.0 ? kappa_conv : 0.0;
+    if (s->kappa_conv > 0.0) {  // replaces Richardson mixing: momentum uses the diffusivity again
+        s->ri_on = false;
+        s->d.kv = nullptr;
+    }
+    return OCN_OK;
+}
+
+int ocn_closure_richardson(ocn_state* s, double nu0, double alpha, double nu_b, double kappa_b, double conv) {
+    if (!s) return fail(OCN_E_INVALID, "state must not be NULL");
+    if (!s->closure || s->net || !s->kv_ws) return fail(OCN_E_STATE, "needs a prescribed-field closure attached");
+    if (!std::isfinite(nu0) || !(alpha >= 0.0) || !(nu_b >= 0.0) || !(kappa_b >= 0.0) || !(conv >= 0.0) ||
+        !std::isfinite(alpha) || !std::isfinite(nu_b) || !std::isfinite(kappa_b) || !std::isfinite(conv))
+        return fail(OCN_E_INVALID, "constants must be finite; alpha, nu_b, kappa_b and conv >= 0");
+    HIPCHK(hipStreamSynchronize(s->st));
+    drop_graph(s);
+    if (nu0 > 0.0) {
+        s->ri_on = true;
+        s->ri = ocn::RiParams{nu0, alpha, nu_b, kappa_b, conv};
+        s->kappa_conv = 0.0;
+        s->d.kv = s->kv_ws;
+        HIPCHK(s->esize == 4 ? ocn::launch_richardson<float>(s->d, s->ri, s->st)
+                             : ocn::launch_richardson<double>(s->d, s->ri, s->st));
+    } else {  // off: the constant diffusivity on every face, momentum with it
+        s->ri_on = false;
+        s->d.kv = nullptr;
+        const size_t o3 = ((size_t)s->g->h * s->d.p3 + s->ox3) * s->esize;
+        unsigned char* base = static_cast<unsigned char*>(s->d.kw) - o3;
+        HIPCHK(s->esize == 4 ? ocn::launch_fill<float>(base, (long long)s->n3, s->p.kappa, s->st)
+                             : ocn::launch_fill<double>(base, (long long)s->n3, s->p.kappa, s->st));
+    }
+    HIPCHK(hipStreamSynchronize(s->st));
     return OCN_OK;
 }
 
@@ -948,8 +1006,11 @@ int ocn_closure_detach(ocn_state* s) {
     drop_graph(s);
     s->closure = false;
     s->kappa_conv = 0.0;
+    s->ri_on = false;
     s->net = nullptr;
     s->d.kw = nullptr;
+    s->d.kv = nullptr;
+    s->kv_ws = nullptr;
     s->norm = nullptr; s->xb = s->h1b = s->h2b = nullptr; s->y = nullptr;
     s->din = s->h1 = s->h2 = s->dout = 0;
     return OCN_OK;

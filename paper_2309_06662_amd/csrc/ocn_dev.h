@@ -74,6 +74,7 @@ struct DevState {
     // vertical diffusivity on z-faces (3D of the field type, slot k = face
     // between layers k-1 and k, with periodic images), or null for the constant
     void* kw;
+    void* kv;       // viscosity on z-faces for u and v (Richardson mixing), or null: they use kw
     // diagnostics scratch
     double* diag_part;  // blocks * DG_COUNT
     double* diag_out;   // DG_COUNT
@@ -151,6 +152,11 @@ size_t features_lds(int din);
 template <typename R> hipError_t launch_fill(void* p, long long n, double v, hipStream_t st);
 template <typename R>
 hipError_t launch_convective(const DevState& s, double kappa_conv, double kappa0, hipStream_t st);
+// Richardson-number mixing constants (Pacanowski-Philander form)
+struct RiParams {
+    double nu0, alpha, nu_b, kappa_b, conv;
+};
+template <typename R> hipError_t launch_richardson(const DevState& s, const RiParams& p, hipStream_t st);
 template <typename R>
 hipError_t launch_features(const DevState& s, int din, const float* norm, void* out, int out_bf16, hipStream_t st);
 template <typename R>

@@ -24,8 +24,10 @@ OCN_CARTESIAN, OCN_LATLON = 0, 1
 
 FIELDS = {"u": 0, "v": 1, "T": 2, "eta": 3, "U": 4, "V": 5, "eta_mean": 6, "U_mean": 7, "V_mean": 8,
           "w": 9, "gu_prev": 10, "gv_prev": 11, "gt_prev": 12, "taux": 13, "tauy": 14, "tstar": 15, "tref": 16,
-          "kappa": 17}
-FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "kappa"}
+          "kappa": 17, "visc": 18}
+FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "kappa", "visc"}
+# Richardson-number mixing constants (Pacanowski and Philander 1981 form)
+RI_DEFAULTS = {"nu0": 1e-2, "alpha": 5.0, "nu_b": 1e-4, "kappa_b": 1e-5, "conv": 1.0}
 
 # Functions declared in include/ocn.h.
 ABI_FUNCTIONS = ["ocn_abi_version", "ocn_last_error", "ocn_grid_create", "ocn_grid_destroy",
@@ -38,7 +40,8 @@ ABI_FUNCTIONS = ["ocn_abi_version", "ocn_last_error", "ocn_grid_create", "ocn_gr
                  "ocn_mlp_arena_bytes", "ocn_mlp_init", "ocn_mlp_destroy", "ocn_mlp_param_count",
                  "ocn_mlp_set_params", "ocn_mlp_get_params", "ocn_mlp_forward", "ocn_mlp_gradients",
                  "ocn_mlp_train_step", "ocn_closure_workspace_bytes", "ocn_closure_attach",
-                 "ocn_closure_detach", "ocn_closure_features", "ocn_closure_kappa", "ocn_closure_convective"]
+                 "ocn_closure_detach", "ocn_closure_features", "ocn_closure_kappa", "ocn_closure_convective",
+                 "ocn_closure_richardson"]
 
 
 class OcnError(RuntimeError):
@@ -126,6 +129,7 @@ def lib():
         L.ocn_closure_attach.argtypes = [C.c_void_p, C.c_void_p, _F, C.c_size_t, C.c_void_p, C.c_size_t]
         L.ocn_closure_detach.argtypes = [C.c_void_p]
         L.ocn_closure_convective.argtypes = [C.c_void_p, C.c_double]
+        L.ocn_closure_richardson.argtypes = [C.c_void_p] + [C.c_double] * 5
         L.ocn_closure_features.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
         L.ocn_closure_kappa.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
         L.ocn_stage_times.argtypes = [C.c_void_p, _D, C.c_int32, C.POINTER(C.c_int64)]
@@ -294,6 +298,12 @@ class Model:
     def set_convective(self, kappa_conv: float):
         """Convective adjustment (needs attach_closure() without a network): kappa_conv where N^2 < 0."""
         _check(lib().ocn_closure_convective(self.handle, float(kappa_conv)), "ocn_closure_convective")
+
+    def set_richardson(self, nu0=RI_DEFAULTS["nu0"], alpha=RI_DEFAULTS["alpha"], nu_b=RI_DEFAULTS["nu_b"],
+                       kappa_b=RI_DEFAULTS["kappa_b"], conv=RI_DEFAULTS["conv"]):
+        """Richardson-number mixing (needs attach_closure() without a network); nu0 <= 0 turns it off."""
+        _check(lib().ocn_closure_richardson(self.handle, float(nu0), float(alpha), float(nu_b), float(kappa_b),
+                                            float(conv)), "ocn_closure_richardson")
 
     def detach_closure(self):
         _check(lib().ocn_closure_detach(self.handle), "ocn_closure_detach")

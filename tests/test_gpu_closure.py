@@ -237,3 +237,85 @@ def test_convective_adjustment_matches_oracle(precision, tol):
     ref.step(19)
     gpu.step(19)
     _compare(ref, gpu, w, inp["kbottom"], tol)
+
+
+RI_CASES = ["beta", "latlon", "steps_periodic", "deep40"]
+_STATE_FIELDS = ("u", "v", "T", "eta", "U", "V", "gu_prev", "gv_prev", "gt_prev")
+
+
+def _spun_up(case, steps=4):
+    """The case after a few oracle steps, then given shear and a convective patch so
+    every branch of the mixing formula occurs: currents alternating with depth
+    (u +-0.15, v +-0.1 m/s between levels) over a tenth of the stratification
+    (Ri from about 1e-2 up) and the top two layers of the western third 10 K
+    colder (unstable faces)."""
+    w, kb_seed = CASES[case]()
+    inp = inputs.make_inputs(w)
+    if kb_seed is not None:
+        rng = np.random.default_rng(kb_seed)
+        kb = rng.integers(0, w.nz + 1, size=(w.ny, w.nx)).astype(np.int32)
+        kb[kb == 1] = 0
+        inp["kbottom"] = kb
+    ref = oracle.OracleModel.from_inputs(w, inp)
+    ref.step(steps)
+    sign = (-1.0) ** np.arange(w.nz)
+    ref.set("u", ref.get("u") + 0.15 * sign[:, None, None])
+    ref.set("v", ref.get("v") + 0.1 * sign[::-1, None, None])
+    T = 10.0 + 0.1 * (ref.get("T") - 10.0)   # weaker stratification: Ri of order one
+    T[-2:, :, : max(1, w.nx // 3)] -= 10.0
+    ref.set("T", T)
+    return w, inp, ref
+
+
+def _copy_state(ref, gpu):
+    for n in _STATE_FIELDS:
+        gpu.set(n, ref.get(n))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+@pytest.mark.parametrize("case", RI_CASES)
+def test_richardson_faces_match_oracle(case, precision, tol):
+    """The diagnosis alone, on the same state: the oracle's state is copied in."""
+    w, inp, ref = _spun_up(case)
+    gpu = _ocn().Model(w, precision, inp)
+    _copy_state(ref, gpu)
+    gpu.attach_closure()
+    ref.set_richardson()
+    gpu.set_richardson()
+    nu_ref = ref.get("visc")
+    wet = nu_ref != 0
+    assert np.any(nu_ref == 1.0)                                   # convective faces occur
+    assert np.any((nu_ref > 2e-4) & (nu_ref < 5e-3))               # intermediate Ri occurs
+    for name in ("kappa", "visc"):
+        got, exp = gpu.get(name), ref.get(name)
+        assert np.array_equal(got == 0, exp == 0), name
+        conv = exp == 1.0
+        assert np.array_equal(got == 1.0, conv), name          # the same convective faces
+        nz_ = exp != 0
+        if precision == "fp64":
+            err = np.max(np.abs(got[nz_] / exp[nz_] - 1.0))
+        else:
+            err = np.linalg.norm(got[nz_] - exp[nz_]) / np.linalg.norm(exp[nz_])
+        print(f"{case} {precision} {name}: err {err:.2e}; convective faces {int(conv.sum())} of "
+              f"{int(wet.sum())}, range {exp[nz_].min():.2e}..{exp[nz_].max():.2e}", flush=True)
+        assert err <= tol, (name, err)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+@pytest.mark.parametrize("case", RI_CASES)
+def test_richardson_run_matches_oracle(case, precision, tol):
+    """Six steps with the mixing diagnosed every step, from the perturbed state."""
+    w, inp, ref = _spun_up(case, steps=2)
+    gpu = _ocn().Model(w, precision, inp)
+    _copy_state(ref, gpu)
+    gpu.first_step = ref.first_step
+    gpu.attach_closure()
+    ref.set_richardson()
+    gpu.set_richardson()
+    ref.step(6)
+    gpu.step(6)
+    print(f"case {case} {precision} {w.nx}x{w.ny}x{w.nz}", flush=True)
+    _compare(ref, gpu, w, inp["kbottom"], tol)
+    err = rel_l2(gpu.get("visc"), ref.get("visc"))
+    print(f"  visc rel L2 {err:.2e}", flush=True)
+    assert err <= (1e-9 if precision == "fp64" else 1e-3)
