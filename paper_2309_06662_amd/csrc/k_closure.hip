@@ -5,8 +5,8 @@
 // parameterizations; Sec. 6 uses a vertical-mixing closure). Two kernels sit
 // around the network's products:
 //
-//  k_features: 64 adjacent columns of a row per workgroup, sixteen threads
-//  per column taking every sixteenth level. They build the columns' input vectors
+//  k_features: 64 adjacent columns of a row per workgroup, four threads per
+//  column taking every fourth level. They build the columns' input vectors
 //  in LDS, then the workgroup writes its 64 consecutive rows of the
 //  (ny nx) x din matrix as one contiguous coalesced run (FP32 or BF16). Order: T (nz), u at centres (nz), v at
 //  centres (nz), N^2 = g alpha dT/dz on faces (nz, slot 0 and dry faces 0),
@@ -32,8 +32,8 @@ __device__ __forceinline__ uint16_t to_bf16(float x) {
     return (uint16_t)(u >> 16);
 }
 
-constexpr int FG = 16;  // level groups per workgroup: thread (t, g) takes levels g, g + FG, ...
-constexpr int FL = (128 + FG - 1) / FG;  // levels per thread at the largest nz
+constexpr int FG = 4;   // level groups per workgroup: thread (t, g) takes levels g, g + FG, ...
+constexpr int FCH = 4;  // levels whose loads a thread issues together
 
 // Stores a workgroup's rows (contiguous in the output) from the LDS tile
 // [FW][ld]: whole rows of n values are written by consecutive threads.
@@ -71,8 +71,17 @@ __global__ __launch_bounds__(FW * FG) void k_features(const DevState S, int din,
     if (i < nx) {
         const int K = S.kb[idxk(S, i, j)];
         const int kbot = nz - K;
+        // normalisation in the state's precision: FP64 states divide in FP64;
+        // FP32 states take (x - mean) times the FP32 reciprocal deviation
         auto put = [&](int f, double x) {
-            put_feature(my, f, norm ? float((x - double(norm[f])) / double(norm[din + f])) : float(x));
+            float v;
+            if constexpr (sizeof(R) == 8) {
+                v = norm ? float((x - double(norm[f])) / double(norm[din + f])) : float(x);
+            } else {
+                const float xf = float(x);
+                v = norm ? (xf - norm[f]) * __builtin_amdgcn_rcpf(norm[din + f]) : xf;
+            }
+            put_feature(my, f, v);
         };
         // east / north neighbours across the domain edge: periodic image or land
         const int ie = (i + 1 < nx) ? i + 1 : (S.periodic_x ? 0 : -1);
@@ -84,46 +93,48 @@ __global__ __launch_bounds__(FW * FG) void k_features(const DevState S, int din,
         const R* T = f3<R>(S.t);
         const R* U = f3<R>(S.u);
         const R* V = f3<R>(S.v);
-        // all loads of this thread's levels first (addresses clamped to valid
-        // points, masks applied afterwards), so they are in flight together
+        // the loads of FCH of this thread's levels are issued together
+        // (addresses clamped to valid points, masks applied afterwards)
         const int iec = ie >= 0 ? ie : i, jnc = jn >= 0 ? jn : j;
-        R vT[FL], vTb[FL], vUw[FL], vUe[FL], vVs[FL], vVn[FL];
+        for (int m0 = 0; g + FG * m0 < nz; m0 += FCH) {
+            R vT[FCH], vTb[FCH], vUw[FCH], vUe[FCH], vVs[FCH], vVn[FCH];
 #pragma unroll
-        for (int m = 0; m < FL; ++m) {
-            const int k = g + FG * m;
-            if (k < nz) {
-                vT[m] = T[idx3(S, i, j, k)];
-                vTb[m] = T[idx3(S, i, j, max(k - 1, 0))];
-                vUw[m] = U[idx3(S, i, j, k)];
-                vUe[m] = U[idx3(S, iec, j, k)];
-                vVs[m] = V[idx3(S, i, j, k)];
-                vVn[m] = V[idx3(S, i, jnc, k)];
+            for (int m = 0; m < FCH; ++m) {
+                const int k = g + FG * (m0 + m);
+                if (k < nz) {
+                    vT[m] = T[idx3(S, i, j, k)];
+                    vTb[m] = T[idx3(S, i, j, max(k - 1, 0))];
+                    vUw[m] = U[idx3(S, i, j, k)];
+                    vUe[m] = U[idx3(S, iec, j, k)];
+                    vVs[m] = V[idx3(S, i, j, k)];
+                    vVn[m] = V[idx3(S, i, jnc, k)];
+                }
             }
-        }
 #pragma unroll
-        for (int m = 0; m < FL; ++m) {
-            const int k = g + FG * m;
-            if (k >= nz) break;
-            if (k < kbot) {
-                put_feature(my, k, 0.f);
-                put_feature(my, nz + k, 0.f);
-                put_feature(my, 2 * nz + k, 0.f);
-                put_feature(my, 3 * nz + k, 0.f);
-                continue;
-            }
-            const double tk = double(vT[m]) + S.tref[k];
-            put(k, tk);
-            const double uw = (k >= nz - Kuw) ? double(vUw[m]) : 0.0;
-            const double ue = (k >= nz - Kue) ? double(vUe[m]) : 0.0;
-            put(nz + k, 0.5 * (uw + ue));
-            const double vs = (k >= nz - Kvs) ? double(vVs[m]) : 0.0;
-            const double vn = (k >= nz - Kvn) ? double(vVn[m]) : 0.0;
-            put(2 * nz + k, 0.5 * (vs + vn));
-            if (k > kbot) {
-                const double tb = double(vTb[m]) + S.tref[k - 1];
-                put(3 * nz + k, S.g * S.alpha * (tk - tb) / S.dzc[k]);
-            } else {
-                put_feature(my, 3 * nz + k, 0.f);
+            for (int m = 0; m < FCH; ++m) {
+                const int k = g + FG * (m0 + m);
+                if (k >= nz) break;
+                if (k < kbot) {
+                    put_feature(my, k, 0.f);
+                    put_feature(my, nz + k, 0.f);
+                    put_feature(my, 2 * nz + k, 0.f);
+                    put_feature(my, 3 * nz + k, 0.f);
+                    continue;
+                }
+                const double tk = double(vT[m]) + S.tref[k];
+                put(k, tk);
+                const double uw = (k >= nz - Kuw) ? double(vUw[m]) : 0.0;
+                const double ue = (k >= nz - Kue) ? double(vUe[m]) : 0.0;
+                put(nz + k, 0.5 * (uw + ue));
+                const double vs = (k >= nz - Kvs) ? double(vVs[m]) : 0.0;
+                const double vn = (k >= nz - Kvn) ? double(vVn[m]) : 0.0;
+                put(2 * nz + k, 0.5 * (vs + vn));
+                if (k > kbot) {
+                    const double tb = double(vTb[m]) + S.tref[k - 1];
+                    put(3 * nz + k, S.g * S.alpha * (tk - tb) / S.dzc[k]);
+                } else {
+                    put_feature(my, 3 * nz + k, 0.f);
+                }
             }
         }
         if (g == 0) {
@@ -149,9 +160,16 @@ __global__ __launch_bounds__(FW * FG) void k_features(const DevState S, int din,
     store_rows(tile, ld, min(FW, nx - i0), din, out + ((long long)j * nx + i0) * din);
 }
 
-__device__ __forceinline__ double face_kappa_of(float y, double kappa0) {
+// 10^y clipped to [1e-7, 1], kappa0 where y is not finite; in the state's
+// precision (FP32 states take the FP32 exp10).
+template <typename R> __device__ __forceinline__ R face_kappa_of(float y, double kappa0);
+template <> __device__ __forceinline__ double face_kappa_of<double>(float y, double kappa0) {
     if (!isfinite(y)) return kappa0;
     return fmin(1.0, fmax(1e-7, exp10(double(y))));
+}
+template <> __device__ __forceinline__ float face_kappa_of<float>(float y, double kappa0) {
+    if (!isfinite(y)) return float(kappa0);
+    return fminf(1.0f, fmaxf(1e-7f, exp10f(y)));
 }
 
 // The workgroup's 64 output rows are read into LDS in row order (coalesced),
@@ -180,7 +198,7 @@ __global__ __launch_bounds__(FW * FG) void k_kappa_map(const DevState S, const f
     const int kbot = nz - S.kb[idxk(S, i, j)];
     R* kw = f3<R>(S.kw);
     for (int k = g; k < nz; k += FG) {
-        const R val = (k > kbot) ? R(face_kappa_of(sy[t * ld + k], kappa0)) : R(0);
+        const R val = (k > kbot) ? face_kappa_of<R>(sy[t * ld + k], kappa0) : R(0);
         kw[idx3(S, i, j, k)] = val;
         for_each_image(S, i, j, S.h, [&](int x, int yy) { kw[idx3(S, x, yy, k)] = val; });
     }
@@ -215,7 +233,8 @@ __global__ __launch_bounds__(FW) void k_convective(const DevState S, double kapp
 // conv, else with Ri = N^2 / max(S^2, 1e-16) and r = 1 / (1 + alpha Ri) the
 // viscosity is nu0 r^2 + nu_b and the diffusivity nu r + kappa_b. Dry faces
 // take 0. 256 adjacent columns per workgroup, one thread per column marching
-// up the levels with the lower level's values carried in registers.
+// up the levels (loads issued eight levels at a time) with the lower level's
+// values carried in registers.
 constexpr int RW = 256;
 
 template <typename R>
@@ -239,42 +258,57 @@ __global__ __launch_bounds__(RW) void k_richardson(const DevState S, const RiPar
     R* kv = f3<R>(S.kv);
     const double ga = S.g * S.alpha;
     double tb = 0.0, ub = 0.0, vb = 0.0;  // the level below
-#pragma unroll 4
-    for (int k = 0; k < nz; ++k) {
-        double kap = 0.0, nu = 0.0;
-        if (k >= kbot) {
-            const double tk = double(T[idx3(S, i, j, k)]) + S.tref[k];
-            const double uw = (k >= nz - Kuw) ? double(U[idx3(S, i, j, k)]) : 0.0;
-            const double ue = (k >= nz - Kue) ? double(U[idx3(S, iec, j, k)]) : 0.0;
-            const double vs = (k >= nz - Kvs) ? double(V[idx3(S, i, j, k)]) : 0.0;
-            const double vn = (k >= nz - Kvn) ? double(V[idx3(S, i, jnc, k)]) : 0.0;
-            const double uk = 0.5 * (uw + ue), vk = 0.5 * (vs + vn);
-            if (k > kbot) {
-                const double dzc = S.dzc[k];
-                const double n2 = ga * (tk - tb) / dzc;
-                const double du = uk - ub, dv = vk - vb;
-                const double s2 = (du * du + dv * dv) / (dzc * dzc);
-                if (n2 < 0.0) {
-                    kap = P.conv;
-                    nu = P.conv;
-                } else {
-                    const double ri = n2 / fmax(s2, 1e-16);
-                    const double r = 1.0 / (1.0 + P.alpha * ri);
-                    nu = P.nu0 * r * r + P.nu_b;
-                    kap = nu * r + P.kappa_b;
-                }
-            }
-            tb = tk;
-            ub = uk;
-            vb = vk;
+    constexpr int CH = 8;                 // levels whose loads are issued together
+    for (int k0 = 0; k0 < nz; k0 += CH) {
+        R lT[CH], lUw[CH], lUe[CH], lVs[CH], lVn[CH];
+#pragma unroll
+        for (int m = 0; m < CH; ++m) {
+            const int k = min(k0 + m, nz - 1);  // clamped: valid addresses, results unused past nz
+            lT[m] = T[idx3(S, i, j, k)];
+            lUw[m] = U[idx3(S, i, j, k)];
+            lUe[m] = U[idx3(S, iec, j, k)];
+            lVs[m] = V[idx3(S, i, j, k)];
+            lVn[m] = V[idx3(S, i, jnc, k)];
         }
-        const R vkap = R(kap), vnu = R(nu);
-        kw[idx3(S, i, j, k)] = vkap;
-        kv[idx3(S, i, j, k)] = vnu;
-        for_each_image(S, i, j, S.h, [&](int x, int y) {
-            kw[idx3(S, x, y, k)] = vkap;
-            kv[idx3(S, x, y, k)] = vnu;
-        });
+#pragma unroll
+        for (int m = 0; m < CH; ++m) {
+            const int k = k0 + m;
+            if (k >= nz) break;
+            double kap = 0.0, nu = 0.0;
+            if (k >= kbot) {
+                const double tk = double(lT[m]) + S.tref[k];
+                const double uw = (k >= nz - Kuw) ? double(lUw[m]) : 0.0;
+                const double ue = (k >= nz - Kue) ? double(lUe[m]) : 0.0;
+                const double vs = (k >= nz - Kvs) ? double(lVs[m]) : 0.0;
+                const double vn = (k >= nz - Kvn) ? double(lVn[m]) : 0.0;
+                const double uk = 0.5 * (uw + ue), vk = 0.5 * (vs + vn);
+                if (k > kbot) {
+                    const double dzc = S.dzc[k];
+                    const double n2 = ga * (tk - tb) / dzc;
+                    const double du = uk - ub, dv = vk - vb;
+                    const double s2 = (du * du + dv * dv) / (dzc * dzc);
+                    if (n2 < 0.0) {
+                        kap = P.conv;
+                        nu = P.conv;
+                    } else {
+                        const double ri = n2 / fmax(s2, 1e-16);
+                        const double r = 1.0 / (1.0 + P.alpha * ri);
+                        nu = P.nu0 * r * r + P.nu_b;
+                        kap = nu * r + P.kappa_b;
+                    }
+                }
+                tb = tk;
+                ub = uk;
+                vb = vk;
+            }
+            const R vkap = R(kap), vnu = R(nu);
+            kw[idx3(S, i, j, k)] = vkap;
+            kv[idx3(S, i, j, k)] = vnu;
+            for_each_image(S, i, j, S.h, [&](int x, int y) {
+                kw[idx3(S, x, y, k)] = vkap;
+                kv[idx3(S, x, y, k)] = vnu;
+            });
+        }
     }
 }
 
