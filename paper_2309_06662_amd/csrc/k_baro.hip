@@ -100,7 +100,7 @@ hipError_t launch_barotropic(const DevState& s, hipStream_t st) {
 
 namespace ocn {
 
-// Temporally blocked substeps: one launch advances s substeps of a 64 x 16
+// Temporally blocked substeps: one launch advances s substeps of a 64 x 32
 // tile held in LDS with an s-wide halo. Each substep the region of correct
 // values shrinks by one cell on every side, so after s substeps the tile
 // interior is exact; the halo cells are recomputed redundantly instead of

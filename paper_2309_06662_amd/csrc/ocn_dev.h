@@ -180,6 +180,6 @@ hipError_t launch_column_batched(const DevState* members, const int4* tiles, int
 int baro_substeps(int n_substeps);  // Ns + Ns/2
 hipError_t launch_barotropic_batched(const DevState* members, int n_members, const int4* tiles, int ntiles,
                                      int n_substeps, int fuse, double dt, hipStream_t st);
-constexpr int kBaroTileX = 64, kBaroTileY = 16;
+constexpr int kBaroTileX = 64, kBaroTileY = 32;
 
 }  // namespace ocn

@@ -258,10 +258,11 @@ def test_full_size_parameters_on_small_grids(case, precision, tol):
 
 
 def test_many_barotropic_tiles_fp64():
-    """More barotropic tiles than the GPU holds at once (2048 tiles of 64 x 16
-    columns): tiles that start late must still read their neighbours' values
-    from before the launch. 35 substeps in groups of 5 is an odd number of
-    launches, which ends in the second buffers and copies back."""
+    """More barotropic tiles than the GPU holds at once (1024 tiles of 64 x 32
+    columns, one resident per CU): tiles that start late must still read their
+    neighbours' values from before the launch. 35 substeps run on to 52 (3/2 of
+    the step) in groups of 6: nine launches, an odd number, which ends in the
+    second buffers and copies back."""
     w = inputs.BETA_BASIN_64.replace(name="beta_2048x1024x2", nx=2048, ny=1024, nz=2, depth=1000.0,
                                      dx=10e3, dy=10e3, dt=600.0, n_substeps=35)
     ref, gpu, inp = _pair(w, "fp64")
