@@ -101,7 +101,7 @@ hipError_t launch_barotropic(const DevState& s, hipStream_t st) {
 namespace ocn {
 
 // Temporally blocked substeps: one launch advances s substeps of a 64 x 32
-// tile held in LDS with an s-wide halo. Each substep the region of correct
+// (or, on small grids, 32 x 16) tile held in LDS with an s-wide halo. Each substep the region of correct
 // values shrinks by one cell on every side, so after s substeps the tile
 // interior is exact; the halo cells are recomputed redundantly instead of
 // exchanged. Every point carries the same arithmetic as the one-substep path.
@@ -109,20 +109,27 @@ namespace ocn {
 // same launch, so launches read one buffer of eta, U, V and write the other
 // (parity selects which); after an odd number of launches a copy kernel
 // returns the result to the primary buffers.
-constexpr int FBX = kBaroTileX, FBY = kBaroTileY, FSMAX = 6;
-constexpr int FEW = FBX + 2 * FSMAX, FEH = FBY + 2 * FSMAX, FEN = FEW * FEH;
-constexpr int FT = 512, FQ = (FEN + FT - 1) / FT;
+constexpr int FSMAX = 6, FT = 512;
+// Tile shapes: kBaroTileX x kBaroTileY for large grids and the ensembles;
+// 32 x 16 for grids with fewer large tiles than CUs, where the number of
+// workgroups, not the recomputed halo, sets the time.
+constexpr int kSmallTileX = 32, kSmallTileY = 16;
+constexpr int kManyTiles = 256;
 
-constexpr int FI = FBX * FBY / FT;  // interior points per thread
-static_assert(FBX * FBY % FT == 0, "interior points must divide evenly over the threads");
 
 // Registers hold only what each halo-inclusive point needs every substep
 // (depths and slow forcing); row metrics sit in small LDS tables, and the
 // window sums live with a second mapping over the interior points only (FI
 // per thread), read from LDS between the barriers the substep has anyway.
+template <int BX, int BY>
 __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const int by, const double dtau,
                                           const int m0, const int s, const int first, const int last,
                                           const int parity) {
+    constexpr int FBX = BX, FBY = BY;
+    constexpr int FEW = FBX + 2 * FSMAX, FEH = FBY + 2 * FSMAX, FEN = FEW * FEH;
+    constexpr int FQ = (FEN + FT - 1) / FT;  // halo-inclusive points per thread
+    constexpr int FI = FBX * FBY / FT;       // interior points per thread
+    static_assert(FBX * FBY % FT == 0, "interior points must divide evenly over the threads");
     __shared__ double sE[FEN], sU[FEN], sV[FEN];
     __shared__ double sRdxc[FEH], sDxv0[FEH], sDxv1[FEH], sRarea[FEH];
     const double* __restrict__ inE = parity ? S.eta2 : S.eta;
@@ -289,9 +296,10 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
     }
 }
 
+template <int BX, int BY>
 __global__ __launch_bounds__(FT) void k_baro_fused(const DevState S, const double dtau, const int m0, const int s,
                                                    const int first, const int last, const int parity) {
-    baro_tile(S, blockIdx.x, blockIdx.y, dtau, m0, s, first, last, parity);
+    baro_tile<BX, BY>(S, blockIdx.x, blockIdx.y, dtau, m0, s, first, last, parity);
 }
 
 // Second buffers back to the primary ones (whole padded arrays, halos included).
@@ -322,7 +330,7 @@ __global__ __launch_bounds__(FT) void k_baro_fused_batched(const DevState* __res
                                                            const int m0, const int s, const int first,
                                                            const int last, const int parity) {
     const int4 e = tiles[blockIdx.x];
-    baro_tile(members[e.x], e.y, e.z, dtau, m0, s, first, last, parity);
+    baro_tile<kBaroTileX, kBaroTileY>(members[e.x], e.y, e.z, dtau, m0, s, first, last, parity);
 }
 
 int baro_substeps(int n_substeps) { return n_substeps + n_substeps / 2; }
@@ -349,14 +357,21 @@ hipError_t launch_barotropic_batched(const DevState* members, int n_members, con
 
 hipError_t launch_barotropic_fused(const DevState& s, hipStream_t st) {
     const int sub = std::min(s.baro_fuse, FSMAX);
-    dim3 grid((s.nx + FBX - 1) / FBX, (s.ny + FBY - 1) / FBY);
+    const bool small = (long long)((s.nx + kBaroTileX - 1) / kBaroTileX) * ((s.ny + kBaroTileY - 1) / kBaroTileY) <
+                       kManyTiles;
+    const int bx = small ? kSmallTileX : kBaroTileX, by = small ? kSmallTileY : kBaroTileY;
+    dim3 grid((s.nx + bx - 1) / bx, (s.ny + by - 1) / by);
     const double dtau = s.dt / s.n_substeps;
     const int M = s.baro_m;
     int parity = 0;
     for (int m0 = 0; m0 < M; m0 += sub, parity ^= 1) {
         const int ss = std::min(sub, M - m0);
-        hipLaunchKernelGGL(k_baro_fused, grid, dim3(FT), 0, st, s, dtau, m0, ss, (int)(m0 == 0), (int)(m0 + ss == M),
-                           parity);
+        if (small)
+            hipLaunchKernelGGL((k_baro_fused<kSmallTileX, kSmallTileY>), grid, dim3(FT), 0, st, s, dtau, m0, ss,
+                               (int)(m0 == 0), (int)(m0 + ss == M), parity);
+        else
+            hipLaunchKernelGGL((k_baro_fused<kBaroTileX, kBaroTileY>), grid, dim3(FT), 0, st, s, dtau, m0, ss,
+                               (int)(m0 == 0), (int)(m0 + ss == M), parity);
     }
     if (parity) {  // the result sits in the second buffers
         const long long n = (long long)s.p2 * (s.ny + 2 * s.h);
