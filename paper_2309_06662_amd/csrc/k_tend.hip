@@ -410,6 +410,8 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
             R fzT_bot = R(0), fzu_bot = R(0), fzv_bot = R(0);
             R E_bot = R(0);
             if (k >= 1) {
+                // levels k-3 .. k+2 all inside the column: the open-ocean path
+                const bool zin = (k >= 3) && (k + 2 < nz);
                 if (Wm_b != R(0)) {
                     // reconstruct the full temperature from differences relative to the
                     // upwind cell (anomaly steps plus reference-profile steps)
@@ -424,7 +426,9 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                     const R db = (tb - tcv) + (pos ? dtr[kc * 4 + 1] : dtr[kc * 4 + 2]);
                     const R dd = (td - tcv) + (pos ? dtr[kc * 4 + 2] : dtr[kc * 4 + 1]);
                     const R de = (te - tcv) + (pos ? dtr[kc * 4 + 3] : dtr[kc * 4 + 0]);
-                    const R rel = recon(da, db, R(0), dd, de, okl(la), okl(lb), true, okl(ld), okl(le));
+                    const R rel = (zin && Kc >= nz - (k - 3))
+                                      ? weno5z(da, db, R(0), dd, de)
+                                      : recon(da, db, R(0), dd, de, okl(la), okl(lb), true, okl(ld), okl(le));
                     fzT_bot = Wm_b * (tcv + rel);
                     // reference profile carried through this face, relative to tref(k)
                     E_bot = pos ? Wm_b * (-dtr[k * 4 + 1]) : R(0);
@@ -432,26 +436,36 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                 const R Fu = R(0.5) * (sWm[cw] + Wm_b);
                 if (Fu != R(0)) {
                     R pu[6];
-                    bool oku[6];
 #pragma unroll
-                    for (int r = 0; r < 6; ++r) {
-                        const int l = k - 3 + r;
-                        pu[r] = wu[5 - r];
-                        oku[r] = (l >= 0 && l < nz && Ku >= nz - l);
+                    for (int r = 0; r < 6; ++r) pu[r] = wu[5 - r];
+                    if (zin && Ku >= nz - (k - 3)) {
+                        fzu_bot = upwind_flux_wet(Fu, pu);
+                    } else {
+                        bool oku[6];
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) {
+                            const int l = k - 3 + r;
+                            oku[r] = (l >= 0 && l < nz && Ku >= nz - l);
+                        }
+                        fzu_bot = upwind_flux(Fu, pu, oku);
                     }
-                    fzu_bot = upwind_flux(Fu, pu, oku);
                 }
                 const R Fv = R(0.5) * (sWm[cs] + Wm_b);
                 if (Fv != R(0)) {
                     R pv[6];
-                    bool okv[6];
 #pragma unroll
-                    for (int r = 0; r < 6; ++r) {
-                        const int l = k - 3 + r;
-                        pv[r] = wv[5 - r];
-                        okv[r] = (l >= 0 && l < nz && Kv >= nz - l);
+                    for (int r = 0; r < 6; ++r) pv[r] = wv[5 - r];
+                    if (zin && Kv >= nz - (k - 3)) {
+                        fzv_bot = upwind_flux_wet(Fv, pv);
+                    } else {
+                        bool okv[6];
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) {
+                            const int l = k - 3 + r;
+                            okv[r] = (l >= 0 && l < nz && Kv >= nz - l);
+                        }
+                        fzv_bot = upwind_flux(Fv, pv, okv);
                     }
-                    fzv_bot = upwind_flux(Fv, pv, okv);
                 }
             }
 
