@@ -67,32 +67,37 @@ __device__ __forceinline__ double rcp(double x) {
 
 // Fifth-order WENO-Z face value (Borges et al. 2008) on Jiang-Shu smoothness
 // indicators; c is the upwind cell, the face lies between c and d. Written in
-// the differences d1..d4 of neighbouring values: the candidate values become
-// c plus a difference (exact algebra of the three quadratic candidates), and
-// the three WENO-Z ratios tau / (beta_k + eps) share one reciprocal of the
-// product of the three denominators (all >= eps, so the product stays in range).
+// the differences d1..d4 of neighbouring values, with exact rescalings that
+// save instructions:
+//  - the indicators and eps are taken 4 times larger, beta'_k = 13/3 s_k^2 +
+//    r_k^2 with s the second and r the first difference of stencil k; the
+//    WENO-Z ratios tau / (beta_k + eps) are unchanged, and the three share
+//    one reciprocal of the product of their denominators (all >= 4 eps);
+//  - with w_k = 1 + (tau / (beta_k + eps))^2 the nonlinear weights are
+//    d_k w_k (d = 1/10, 6/10, 3/10), so d_k is folded into the candidate
+//    values: c + sum w_k (d_k q_k) / sum d_k w_k, where q_k - c is the
+//    quadratic candidate of stencil k as a combination of differences.
 template <typename R>
 __device__ __forceinline__ R weno5z(R a, R b, R c, R d, R e) {
     const R d1 = b - a, d2 = c - b, d3 = d - c, d4 = e - d;
     const R s0 = d2 - d1, s1 = d3 - d2, s2 = d4 - d3;          // second differences
     const R r0 = fma(R(2), d2, s0), r1 = d2 + d3, r2 = fma(R(-2), d3, s2);
-    const R k13 = R(13) / R(12);
-    const R b0 = fma(k13 * s0, s0, R(0.25) * r0 * r0);
-    const R b1 = fma(k13 * s1, s1, R(0.25) * r1 * r1);
-    const R b2 = fma(k13 * s2, s2, R(0.25) * r2 * r2);
+    const R k13 = R(13) / R(3);
+    const R b0 = fma(s0 * s0, k13, r0 * r0);
+    const R b1 = fma(s1 * s1, k13, r1 * r1);
+    const R b2 = fma(s2 * s2, k13, r2 * r2);
     const R tau = fabs(b0 - b2);
-    const R e0 = b0 + Eps<R>::v, e1 = b1 + Eps<R>::v, e2 = b2 + Eps<R>::v;
+    const R e0 = b0 + R(4) * Eps<R>::v, e1 = b1 + R(4) * Eps<R>::v, e2 = b2 + R(4) * Eps<R>::v;
     const R p12 = e1 * e2, p02 = e0 * e2, p01 = e0 * e1;
     const R tr = tau * rcp(p01 * e2);
     const R z0 = tr * p12, z1 = tr * p02, z2 = tr * p01;
-    const R a0 = fma(R(0.1) * z0, z0, R(0.1));
-    const R a1 = fma(R(0.6) * z1, z1, R(0.6));
-    const R a2 = fma(R(0.3) * z2, z2, R(0.3));
-    // q0 - c = (5 d2 - 2 d1)/6, q1 - c = (d2 + 2 d3)/6, q2 - c = (4 d3 - d4)/6
-    const R q0 = fma(R(5.0 / 6.0), d2, R(-1.0 / 3.0) * d1);
-    const R q1 = fma(R(1.0 / 3.0), d3, R(1.0 / 6.0) * d2);
-    const R q2 = fma(R(2.0 / 3.0), d3, R(-1.0 / 6.0) * d4);
-    return c + fma(a0, q0, fma(a1, q1, a2 * q2)) * rcp(a0 + a1 + a2);
+    const R w0 = fma(z0, z0, R(1)), w1 = fma(z1, z1, R(1)), w2 = fma(z2, z2, R(1));
+    // d_k (q_k - c): (5 d2 - 2 d1)/60, (d2 + 2 d3)/10, (4 d3 - d4)/20
+    const R q0 = fma(R(1.0 / 12.0), d2, R(-1.0 / 30.0) * d1);
+    const R q1 = fma(R(0.2), d3, R(0.1) * d2);
+    const R q2 = fma(R(0.2), d3, R(-0.05) * d4);
+    const R den = fma(R(0.1), w0, fma(R(0.6), w1, R(0.3) * w2));
+    return c + fma(w0, q0, fma(w1, q1, w2 * q2)) * rcp(den);
 }
 
 // Third-order WENO-JS face value on (b, c, d), c upwind.
