@@ -7,9 +7,11 @@ library's own runs:
 
 1. A regional box of the lat-lon basin (seamounts, cos-latitude wind, surface
    restoring) is run at a resolution `factor` times finer than the coarse
-   target grid, same levels, with convective adjustment (kappa_conv where
-   N^2 < 0): surface cooling by the restoring makes the upper ocean statically
-   unstable, and a hydrostatic model needs that mixing to stay well posed.
+   target grid, same levels, with a mixing parameterization: convective
+   adjustment (kappa_conv where N^2 < 0) or Richardson-number mixing (the
+   library's Pacanowski-Philander reading, convective where N^2 < 0): surface
+   cooling by the restoring makes the upper ocean statically unstable, and a
+   hydrostatic model needs that mixing to stay well posed.
 2. Every `sample_every` fine steps the fine state is coarse-grained onto the
    coarse grid (area-weighted means over wet fine cells; a coarse cell counts
    only where all its fine cells are wet). The subgrid heat flux through each
@@ -28,7 +30,7 @@ library's own runs:
 5. Evaluation, declared before any run: from the coarse-grained state at the
    start of the held-out period, the coarse model runs `eval_days` with the
    constant diffusivity (the baseline), with the trained network, and, as a
-   physical comparator, with the fine run's convective adjustment; against the
+   physical comparator, with the fine run's mixing parameterization; against the
    coarse-grained truth at the end, the RMSE over valid columns of the
    mixed-layer depth (first depth where T falls 0.2 K below the top layer)
    and of the change in column heat content sum dz T are reported for both.
@@ -162,7 +164,11 @@ def _log(msg):
 
 
 def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_samples=2, epochs=60,
-        batch=4096, lr=1e-3, hidden=128, seed=0, convective=1.0, coarse_kw=None):
+        batch=4096, lr=1e-3, hidden=128, seed=0, convective=1.0, coarse_kw=None, mixing="convective"):
+    """mixing: the fine run's parameterization, "convective" (kappa = convective where
+    N^2 < 0) or "richardson" (Richardson-number mixing with its default constants)."""
+    if mixing not in ("convective", "richardson"):
+        raise ValueError("mixing must be 'convective' or 'richardson'")
     import torch
 
     from . import ocn
@@ -175,12 +181,19 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
     nz = coarse.nz
     din = (4 * nz + 3 + 7) // 8 * 8
     _log(f"coarse {coarse.nx}x{coarse.ny}x{nz}, fine {fine.nx}x{fine.ny}x{nz}, "
-         f"{int(cg.valid_col.sum())} fully resolved coarse columns, convective adjustment {convective}")
+         f"{int(cg.valid_col.sum())} fully resolved coarse columns, mixing {mixing}, convective {convective}")
 
+    def attach_mixing(model):
+        model.attach_closure()
+        if mixing == "richardson":
+            model.set_richardson(conv=convective)
+        else:
+            model.set_convective(convective)
+
+    mixed = mixing == "richardson" or convective > 0.0
     fm = ocn.Model(fine, "fp32", inp_f)
-    if convective > 0.0:
-        fm.attach_closure()
-        fm.set_convective(convective)
+    if mixed:
+        attach_mixing(fm)
     cm = ocn.Model(coarse, "fp32", inp_c)   # holds coarse-grained states for the features
 
     steps_per_sample = max(1, int(round(sample_hours * 3600.0 / fine.dt)))
@@ -191,7 +204,7 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
         u, v, T = fm.get("u"), fm.get("v"), fm.get("T")
         W = fm.get("w")
         eta = fm.get("eta")
-        kap = fm.get("kappa") if convective > 0.0 else None
+        kap = fm.get("kappa") if mixed else None
         flux = eddy_flux(cg, T, W, kap, fine.kappa, dz)
         return {"u": cg.u_faces(u), "v": cg.v_faces(v), "T": cg.cells(T), "eta": cg.cells(eta)}, flux
 
@@ -268,7 +281,7 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
     norm = np.concatenate([mean, std]).astype(np.float32)
     results = {}
     vc = cg.valid_col
-    modes = ("constant", "learned", "convective") if convective > 0.0 else ("constant", "learned")
+    modes = ("constant", "learned", mixing) if mixed else ("constant", "learned")
     for mode in modes:
         m = ocn.Model(coarse, "fp32", inp_c)
         for n_ in ("u", "v", "T", "eta"):
@@ -277,9 +290,8 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
         m.set("V", np.tensordot(dz, start["v"], axes=(0, 0)))
         if mode == "learned":
             m.attach_closure(net, norm)
-        elif mode == "convective":
-            m.attach_closure()
-            m.set_convective(convective)
+        elif mode == mixing:
+            attach_mixing(m)
         m.step(eval_steps)
         T_end = m.get("T")
         d = m.diagnostics(allow_unstable=True)
@@ -294,7 +306,7 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
         m.close()
     truth_drift = heat_content(truth["T"], dz) - heat_content(start["T"], dz)
     report = {"coarse": coarse.name, "fine": fine.name, "factor": factor, "days": days, "eval_days": eval_days,
-              "convective_kappa": convective,
+              "mixing": mixing, "convective_kappa": convective,
               "train_columns": int(n), "din": din, "hidden": hidden, "epochs": epochs,
               "loss_first": losses[0], "loss_last": losses[-1], "loss_constant_kappa": base,
               "truth_heat_content_drift_rms_Km": float(np.sqrt(np.mean(truth_drift[vc] ** 2))),
@@ -321,10 +333,12 @@ def main():
     ap.add_argument("--ny", type=int, default=64)
     ap.add_argument("--nz", type=int, default=50)
     ap.add_argument("--convective", type=float, default=1.0, help="kappa where N^2 < 0 in the fine run (0: off)")
+    ap.add_argument("--mixing", choices=("convective", "richardson"), default="convective",
+                    help="the fine run's mixing parameterization")
     a = ap.parse_args()
     run(a.out, factor=a.factor, days=a.days, eval_days=a.eval_days, sample_hours=a.sample_hours,
         window_samples=a.window, epochs=a.epochs, convective=a.convective,
-        coarse_kw={"nx": a.nx, "ny": a.ny, "nz": a.nz})
+        coarse_kw={"nx": a.nx, "ny": a.ny, "nz": a.nz}, mixing=a.mixing)
 
 
 if __name__ == "__main__":

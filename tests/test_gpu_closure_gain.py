@@ -2,7 +2,8 @@
 
 A reduced version of the training pipeline in paper_2309_06662_amd.closure_train:
 a 32 x 24 x 50 coarse box (1/4 degree, 60-54S) against a 4x finer truth run
-with convective adjustment, 16 days, the last 4 held out. The comparison is
+with convective adjustment or with Richardson-number mixing, 16 days, the
+last 4 held out. The comparison is
 declared before the run: from the coarse-grained state at the start of the
 held-out days, the coarse model with the trained network must beat the
 coarse model with the constant diffusivity in the RMSE of both the
@@ -15,12 +16,15 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 
-def test_learned_closure_beats_constant_diffusivity(tmp_path):
+@pytest.mark.parametrize("mixing", ["convective", "richardson"])
+def test_learned_closure_beats_constant_diffusivity(tmp_path, mixing):
+    """mixing: the truth run's parameterization (convective adjustment, or
+    Richardson-number mixing)."""
     from paper_2309_06662_amd import closure_train
 
     rep = closure_train.run(str(tmp_path), factor=4, days=16.0, eval_days=4.0, sample_hours=3.0,
                             window_samples=2, epochs=60, convective=1.0,
-                            coarse_kw={"nx": 32, "ny": 24, "nz": 50})
+                            coarse_kw={"nx": 32, "ny": 24, "nz": 50}, mixing=mixing)
     ev = rep["eval"]
     print("closure evaluation:", ev, flush=True)
     assert all(r["finite"] for r in ev.values())
