@@ -319,3 +319,37 @@ def test_richardson_run_matches_oracle(case, precision, tol):
     err = rel_l2(gpu.get("visc"), ref.get("visc"))
     print(f"  visc rel L2 {err:.2e}", flush=True)
     assert err <= (1e-9 if precision == "fp64" else 1e-3)
+
+
+def test_richardson_modes_and_errors():
+    """Error codes of ocn_closure_richardson and the mode switches: convective
+    adjustment replaces it (momentum back on the diffusivity), nu0 <= 0 sets every
+    face back to the constant, detaching clears it."""
+    ocn = _ocn()
+    w = inputs.BETA_BASIN_64.replace(name="beta_24x20x6", nx=24, ny=20, nz=6)
+    inp = inputs.make_inputs(w)
+    m = ocn.Model(w, "fp64", inp)
+    with pytest.raises(ocn.OcnError) as e:
+        m.set_richardson()                      # no closure attached
+    assert e.value.code == ocn.OCN_E_STATE
+    m.attach_closure()
+    for bad in (dict(alpha=-1.0), dict(nu_b=float("nan")), dict(conv=-0.5), dict(nu0=float("inf"))):
+        with pytest.raises(ocn.OcnError) as e:
+            m.set_richardson(**bad)
+        assert e.value.code == ocn.OCN_E_INVALID, bad
+    m.set_richardson()
+    kap, nu = m.get("kappa"), m.get("visc")
+    wet = kap != 0
+    assert np.all(nu[wet] >= 1e-4) and np.all(kap[wet] >= 1e-5) and not np.array_equal(kap, nu)
+    m.step(2)
+    m.set_convective(1.0)                        # replaces Richardson mixing
+    m.step(1)
+    assert np.array_equal(m.get("visc"), m.get("kappa"))
+    m.set_richardson()
+    m.set_richardson(nu0=0.0)                    # off: the constant on every wet face
+    assert np.all(m.get("kappa")[wet] == w.kappa) and np.array_equal(m.get("visc"), m.get("kappa"))
+    m.set_richardson()
+    m.detach_closure()
+    assert np.all(m.get("visc")[wet] == w.kappa)
+    m.step(1)
+    assert m.diagnostics()["nonfinite"] == 0
