@@ -5,10 +5,10 @@
 // 256 adjacent columns per workgroup so that every level of a field is read
 // and written as coalesced 1 KiB row segments.
 //
-// With a constant diffusivity the matrix of a column depends only on its number
-// of wet layers K (the wet layers of T, u and v columns all start at the
-// surface), so the eliminated super-diagonal c' and the reciprocal pivots come
-// from tables indexed by K built once on the host. The whole column is held in
+// With a constant diffusivity the wet layers of T, u and v columns all start at
+// the surface, so eliminating from the surface down gives pivots that do not
+// depend on the column's depth except in its bottom layer: one level table
+// built once on the host serves every column. The whole column is held in
 // registers: the kernel is instantiated for a few level counts (NZB >= nz) and
 // every loop over levels is unrolled, so the column's nz loads are all in
 // flight at once and no LDS limits the number of resident waves. The
@@ -79,9 +79,12 @@ __device__ __forceinline__ void column_store(const DevState& S, const R (&x)[NZB
     R* dst = f3<R>(field == 0 ? S.t : field == 1 ? S.u : S.v);
     const long long o0 = idx3(S, i, j, 0), pl = S.plane3;
     if (field == 0) {
+        R* q = dst + o0;
 #pragma unroll
-        for (int k = 0; k < NZB; ++k)
-            if (k < nz) dst[o0 + k * pl] = x[k];
+        for (int k = 0; k < NZB; ++k) {
+            if (k < nz) *q = x[k];
+            q += pl;
+        }
         copy_images(S, dst, i, j);
         return;
     }
@@ -89,6 +92,7 @@ __device__ __forceinline__ void column_store(const DevState& S, const R (&x)[NZB
     const double B = (field == 1) ? S.ubt_mean[idx2(S, i, j)] : S.vbt_mean[idx2(S, i, j)];  // substep-averaged transport
     const double corr = (H > 0.0) ? (B - colsum) / H : 0.0;
     double newsum = 0.0;
+    R* q = dst + o0;
 #pragma unroll
     for (int k = 0; k < NZB; ++k) {
         if (k < nz) {
@@ -97,14 +101,20 @@ __device__ __forceinline__ void column_store(const DevState& S, const R (&x)[NZB
                 val = R(double(x[k]) + corr);
                 newsum += double(S.dz[k]) * double(val);
             }
-            dst[o0 + k * pl] = val;
+            *q = val;
         }
+        q += pl;
     }
     copy_images(S, dst, i, j);
     store_wrapped2(S, field == 1 ? S.cu : S.cv, i, j, newsum);
 }
 
 // One block of W columns (bx, j) of one field: 0 = T, 1 = u, 2 = v.
+// Backward Euler with the constant diffusivity, eliminated from the surface
+// down: r'_k = r_k - (c_k / b'_{k+1}) r'_{k+1}, then from the bottom layer up
+// x_k = (r'_k - a_k x_{k-1}) / b'_k, the bottom layer with its own pivot b''.
+// Every coefficient is uniform across the wave (a level table), so the
+// column's only memory traffic is its own values.
 template <typename R, int NZB, int W>
 __device__ __forceinline__ void column_regs(const DevState& S, const int bx, const int j, const int field) {
     const int t = threadIdx.x;
@@ -119,43 +129,54 @@ __device__ __forceinline__ void column_regs(const DevState& S, const int bx, con
     const int kbot = nz - K;  // lowest wet layer
 
     const R* src = f3<R>(field == 0 ? S.ts : field == 1 ? S.us : S.vs) + idx3(S, ic, j, 0);
-    const R* cp = static_cast<const R*>(S.thomas_cp) + (long long)K * nz;
-    const R* rden = static_cast<const R*>(S.thomas_den) + (long long)K * nz;  // reciprocal pivots
-    const R* asub = static_cast<const R*>(S.thomas_a);
+    const R* tab = static_cast<const R*>(S.thomas_tab);
     const R* dtr = static_cast<const R*>(S.dtr);
     const long long pl = S.plane3;
 
     R x[NZB];
+    {
+        const R* q = src;
 #pragma unroll
-    for (int k = 0; k < NZB; ++k) x[k] = (k < nz) ? src[k * pl] : R(0);
-
-    // Elimination, bottom to top: d'_k = (dz_k phi*_k - a_k d'_{k-1}) / den_k.
-    // Temperature is stored as T' = T - tref(k): diffusing T is diffusing T'
-    // with dt dz L(tref) = -c_k (tref_{k+1} - tref_k) + a_k (tref_k - tref_{k-1})
-    // added to its right-hand side.
-    R dprev = R(0);
-#pragma unroll
-    for (int k = 0; k < NZB; ++k) {
-        if (k < nz) {
-            R rhs = R(S.dz[k]) * x[k];
-            const R a = (k > kbot) ? asub[k] : R(0);  // face k wet: layers k-1 and k
-            if (field == 0) {
-                const R c = (k >= kbot && k < nz - 1) ? asub[k + 1] : R(0);
-                rhs += -c * dtr[k * 4 + 2] - a * dtr[k * 4 + 1];
-            }
-            dprev = (rhs - a * dprev) * rden[k];
-            x[k] = dprev;
+        for (int k = 0; k < NZB; ++k) {
+            x[k] = (k < nz) ? *q : R(0);
+            q += pl;
         }
     }
-    // Back-substitution, top to bottom: x_k = d'_k - c'_k x_{k+1}.
-    R xnext = R(0);
-    double colsum = 0.0;
+
+    // Right-hand sides of the wet layers (dry layers keep phi*). Temperature
+    // is stored as T' = T - tref(k): diffusing T is diffusing T' with
+    // dt dz L(tref) = -c_k (tref_{k+1} - tref_k) + a_k (tref_k - tref_{k-1})
+    // added to its right-hand side.
+#pragma unroll
+    for (int k = 0; k < NZB; ++k) {
+        if (k < nz && k >= kbot) {
+            R rhs = R(S.dz[k]) * x[k];
+            if (field == 0) {
+                const R a = (k > kbot) ? tab[4 * k + 3] : R(0);         // face k wet: layers k-1 and k
+                const R c = (k < nz - 1) ? tab[4 * (k + 1) + 3] : R(0);  // face k+1
+                rhs += -c * dtr[k * 4 + 2] - a * dtr[k * 4 + 1];
+            }
+            x[k] = rhs;
+        }
+    }
+    // elimination from the surface down
+    R rn = R(0);
 #pragma unroll
     for (int k = NZB - 1; k >= 0; --k) {
-        if (k < nz) {
-            xnext = x[k] - cp[k] * xnext;
-            x[k] = xnext;
-            if (k >= kbot) colsum += double(S.dz[k]) * double(xnext);
+        if (k < nz && k >= kbot) {
+            rn = fma(-tab[4 * k + 1], rn, x[k]);
+            x[k] = rn;
+        }
+    }
+    // substitution from the bottom layer up
+    R xp = R(0);
+    double colsum = 0.0;
+#pragma unroll
+    for (int k = 0; k < NZB; ++k) {
+        if (k < nz && k >= kbot) {
+            xp = (k == kbot) ? x[k] * tab[4 * k + 2] : (x[k] - tab[4 * k + 3] * xp) * tab[4 * k];
+            x[k] = xp;
+            colsum += double(S.dz[k]) * double(xp);
         }
     }
     if (i < S.nx) column_store<R, NZB>(S, x, i, j, field, kbot, colsum);

@@ -140,7 +140,7 @@ struct Plan {
     size_t oxk, pk, nk;
     size_t nrow;  // metric rows
     size_t diag_blocks;
-    size_t off_f3[9], off_f2[24], off_bw, off_kb, off_rows[5], off_dz, off_dzc, off_tref, off_dtr, off_cp, off_den, off_a;
+    size_t off_f3[9], off_f2[24], off_bw, off_kb, off_rows[5], off_dz, off_dzc, off_tref, off_dtr, off_tab;
     size_t off_part, off_out;
     size_t total;
 };
@@ -171,9 +171,7 @@ Plan make_plan(const ocn_grid* g, int precision, int n_substeps) {
     P.off_dzc = L.add((g->nz + 1) * sizeof(double));
     P.off_tref = L.add(g->nz * sizeof(double));
     P.off_dtr = L.add(g->nz * 4 * P.esize);
-    P.off_cp = L.add((size_t)(g->nz + 1) * g->nz * P.esize);
-    P.off_den = L.add((size_t)(g->nz + 1) * g->nz * P.esize);
-    P.off_a = L.add(g->nz * P.esize);
+    P.off_tab = L.add((size_t)4 * g->nz * P.esize);
     P.off_part = L.add(P.diag_blocks * ocn::DG_COUNT * sizeof(double));
     P.off_out = L.add(ocn::DG_COUNT * sizeof(double));
     P.off_bw = L.add((size_t)(2 * ocn::baro_substeps(std::max(n_substeps, 1)) + 1) * sizeof(double));
@@ -352,27 +350,27 @@ int init_static(ocn_state* s) {
     pack2(s, hv.data(), img);
     HIPCHK(hipMemcpyAsync(base2(s, d.hv), img.data(), img.size() * sizeof(double), hipMemcpyHostToDevice, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
-    // Thomas tables for constant diffusivity, one per wet-layer count K
+    // Constant-diffusivity solve, eliminated from the surface down: the pivots
+    // of the layers above a column's bottom do not depend on its depth, so one
+    // level table serves every column; only the bottom layer's pivot differs,
+    // and it is tabulated per level too.
     const double dt = s->p.dt, kap = s->p.kappa;
-    std::vector<R> cp((size_t)(nz + 1) * nz), den((size_t)(nz + 1) * nz), asub(nz, R(0));
-    for (int k = 1; k < nz; ++k) asub[k] = R(-dt * kap / g->dzc[k]);
-    for (int K = 0; K <= nz; ++K) {
-        const int kbot = nz - K;
-        double cprev = 0.0;
-        for (int k = 0; k < nz; ++k) {
-            const double a = (k > kbot) ? -dt * kap / g->dzc[k] : 0.0;
-            const double c = (k >= kbot && k < nz - 1) ? -dt * kap / g->dzc[k + 1] : 0.0;
-            const double b = g->dz[k] - a - c;
-            const double dn = b - a * cprev;
-            const double cpk = c / dn;
-            cp[(size_t)K * nz + k] = R(cpk);
-            den[(size_t)K * nz + k] = R(1.0 / dn);  // reciprocal pivot
-            cprev = cpk;
-        }
+    std::vector<double> a(nz + 1, 0.0), c(nz, 0.0), bp(nz, 0.0);
+    for (int k = 1; k < nz; ++k) a[k] = -dt * kap / g->dzc[k];  // face k (a[0], a[nz]: no interior face)
+    for (int k = 0; k + 1 < nz; ++k) c[k] = a[k + 1];
+    for (int k = nz - 1; k >= 0; --k) {
+        const double b = g->dz[k] - a[k] - c[k];
+        bp[k] = (k == nz - 1) ? b : b - c[k] * a[k + 1] / bp[k + 1];
     }
-    HIPCHK(hipMemcpyAsync(d.thomas_cp, cp.data(), cp.size() * sizeof(R), hipMemcpyHostToDevice, s->st));
-    HIPCHK(hipMemcpyAsync(d.thomas_den, den.data(), den.size() * sizeof(R), hipMemcpyHostToDevice, s->st));
-    HIPCHK(hipMemcpyAsync(d.thomas_a, asub.data(), asub.size() * sizeof(R), hipMemcpyHostToDevice, s->st));
+    std::vector<R> tab((size_t)4 * nz);
+    for (int k = 0; k < nz; ++k) {
+        const double above = (k + 1 < nz) ? c[k] * a[k + 1] / bp[k + 1] : 0.0;
+        tab[4 * k + 0] = R(1.0 / bp[k]);
+        tab[4 * k + 1] = R((k + 1 < nz) ? c[k] / bp[k + 1] : 0.0);
+        tab[4 * k + 2] = R(1.0 / ((g->dz[k] - c[k]) - above));  // layer k as the bottom layer
+        tab[4 * k + 3] = R(a[k]);
+    }
+    HIPCHK(hipMemcpyAsync(d.thomas_tab, tab.data(), tab.size() * sizeof(R), hipMemcpyHostToDevice, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
     return upload_tables<R>(s);
 }
@@ -699,9 +697,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         d.dzc = reinterpret_cast<double*>(A + P.off_dzc);
         d.tref = reinterpret_cast<double*>(A + P.off_tref);
         d.dtr = A + P.off_dtr;
-        d.thomas_cp = A + P.off_cp;
-        d.thomas_den = A + P.off_den;
-        d.thomas_a = A + P.off_a;
+        d.thomas_tab = A + P.off_tab;
         d.diag_part = reinterpret_cast<double*>(A + P.off_part);
         d.diag_out = reinterpret_cast<double*>(A + P.off_out);
         d.diag_blocks = (int)P.diag_blocks;

@@ -68,9 +68,11 @@ struct DevState {
     double* dzc;      // nz + 1: centre spacing below layer k (dzc[0] and dzc[nz] unused)
     double* tref;     // nz
     void* dtr;        // nz * 4 of the field type: tref(k+o) - tref(k), o = -2, -1, +1, +2
-    void* thomas_cp;  // (nz + 1) * nz of the field type: Thomas c' per wet-layer count
-    void* thomas_den; // (nz + 1) * nz: reciprocal Thomas pivots per wet-layer count
-    void* thomas_a;   // nz: sub-diagonal -dt kappa / dzc_k of a wet face k
+    // constant-diffusivity solve, eliminated from the surface down: per level k
+    // of the field type {1 / b'_k, c_k / b'_{k+1}, 1 / b''_k, a_k}, with b' the
+    // pivot of a layer above the bottom, b'' the pivot of layer k when it is
+    // the bottom layer, a_k = -dt kappa / dzc_k and c_k = a_{k+1} (0 at the top)
+    void* thomas_tab; // 4 nz
     // vertical diffusivity on z-faces (3D of the field type, slot k = face
     // between layers k-1 and k, with periodic images), or null for the constant
     void* kw;
