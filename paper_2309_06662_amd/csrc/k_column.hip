@@ -274,6 +274,11 @@ __device__ __forceinline__ void column_block_vk(const DevState& S, R* sd, R* sc,
     store_wrapped2(S, field == 1 ? S.cu : S.cv, i, j, newsum);
 }
 
+// Reciprocal on the serial elimination chain: the hardware estimate in FP32
+// (1 ulp), the correctly rounded division in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // Register-resident form of the variable-diffusivity solve, for columns whose
 // values and coefficients fit the registers (FP32 up to 100 levels, FP64 up to
 // 32): the column and its face coefficients a_k are loaded up front (all loads
@@ -319,7 +324,7 @@ __device__ __forceinline__ void column_regs_vk(const DevState& S, const int bx, 
             const R ck = (k + 1 < NZB) ? a[k + 1 < NZB ? k + 1 : k] : R(0);  // a_{k+1} (0 above the top)
             R rhs = R(S.dz[k]) * x[k];
             if (field == 0) rhs += -ck * dtr[k * 4 + 2] - ak * dtr[k * 4 + 1];
-            const R rden = R(1) / (R(S.dz[k]) - ak - ck - ak * cprev);
+            const R rden = recip(R(S.dz[k]) - ak - ck - ak * cprev);
             cprev = ck * rden;
             dprev = (rhs - ak * dprev) * rden;
             x[k] = dprev;
