@@ -78,7 +78,7 @@ typedef struct ocn_params {
     int32_t precision;        /* ocn_precision                                      */
     int32_t n_substeps;       /* barotropic substeps per step, >= 1                 */
     int32_t baro_fuse;        /* substeps per barotropic launch: 0 = library default,
-                                 1 = one substep per launch pair, 2..6 = that many
+                                 1 = one substep per launch pair, 2..8 = that many
                                  substeps per launch on an LDS tile whose halo is as
                                  wide as the substep count (the paper's wide
                                  barotropic halo, Sec. 5.3, applied within one GPU) */
@@ -206,7 +206,7 @@ int ocn_synchronize(ocn_state* state);
  * ocn_ensemble_member returns a borrowed handle of member m for the state
  * calls (set/get fields, diagnostics, checkpoints); do not destroy it.
  * ocn_ensemble_set_tiles selects the tendency workgroup rows (4 or 8; 0 =
- * precision default) and the barotropic substeps per launch (2..6; 0 =
+ * precision default) and the barotropic substeps per launch (2..8; 0 =
  * default); every choice gives bitwise-identical results. ocn_ensemble_autotune
  * times trial_steps steps of each choice, keeps the fastest, restores the
  * state it started from and reports the choice and its time per step. */

@@ -109,7 +109,7 @@ namespace ocn {
 // same launch, so launches read one buffer of eta, U, V and write the other
 // (parity selects which); after an odd number of launches a copy kernel
 // returns the result to the primary buffers.
-constexpr int FSMAX = 6, FT = 512;
+constexpr int FSMAX = 8, FT = 512;
 // Tile shapes: kBaroTileX x kBaroTileY for large grids and the ensembles;
 // 32 x 16 for grids with fewer large tiles than CUs, where the number of
 // workgroups, not the recomputed halo, sets the time.

@@ -210,7 +210,7 @@ bool valid_params(const ocn_params* p, std::string& why) {
     if (!(p->dt > 0.0) || !std::isfinite(p->dt)) { why = "dt must be positive"; return false; }
     if (!(p->kappa >= 0.0)) { why = "kappa must be >= 0"; return false; }
     if (!(p->rho0 > 0.0)) { why = "rho0 must be positive"; return false; }
-    if (p->baro_fuse < 0 || p->baro_fuse > 6) { why = "baro_fuse must be in 0..6"; return false; }
+    if (p->baro_fuse < 0 || p->baro_fuse > 8) { why = "baro_fuse must be in 0..8"; return false; }
     if (p->reserved1 != 0) { why = "reserved1 must be 0"; return false; }
     return true;
 }
@@ -709,7 +709,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         d.kappa = params->kappa;
         d.restore_inv = params->restore_tau > 0.0 ? 1.0 / params->restore_tau : 0.0;
         d.n_substeps = params->n_substeps;
-        d.baro_fuse = params->baro_fuse == 0 ? 6 : params->baro_fuse;
+        d.baro_fuse = params->baro_fuse == 0 ? 8 : params->baro_fuse;
         d.baro_m = ocn::baro_substeps(params->n_substeps);
         d.baro_a = reinterpret_cast<double*>(A + P.off_bw);
         d.baro_A = d.baro_a + d.baro_m + 1;
@@ -1180,7 +1180,7 @@ struct ocn_ensemble {
     int max_nz = 1;
     int first = 1;
     int tend_ty = 0;   // 0 = precision default
-    int fuse = 5;
+    int fuse = 8;
     DevState* d_members = nullptr;
     int4* d_tend = nullptr;
     int4* d_col = nullptr;
@@ -1349,7 +1349,7 @@ int ocn_ensemble_init(const ocn_grid* const* grids, int32_t n, const ocn_params*
         e->p = *params;
         e->st = static_cast<hipStream_t>(hip_stream);
         e->esize = params->precision == OCN_FP32 ? 4 : 8;
-        e->fuse = params->baro_fuse < 2 ? 5 : params->baro_fuse;
+        e->fuse = params->baro_fuse < 2 ? 8 : params->baro_fuse;
         unsigned char* A = static_cast<unsigned char*>(device_arena);
         for (int m = 0; m < n; ++m) {
             ocn_state* s = nullptr;
@@ -1408,11 +1408,11 @@ int ocn_ensemble_step(ocn_ensemble* e, int32_t n) {
 int ocn_ensemble_set_tiles(ocn_ensemble* e, int32_t tend_rows, int32_t baro_fuse) {
     if (!e) return fail(OCN_E_INVALID, "ensemble must not be NULL");
     if (!(tend_rows == 0 || tend_rows == 4 || tend_rows == 8)) return fail(OCN_E_INVALID, "tend_rows must be 0, 4 or 8");
-    if (!(baro_fuse == 0 || (baro_fuse >= 2 && baro_fuse <= 6))) return fail(OCN_E_INVALID, "baro_fuse must be 0 or 2..6");
+    if (!(baro_fuse == 0 || (baro_fuse >= 2 && baro_fuse <= 8))) return fail(OCN_E_INVALID, "baro_fuse must be 0 or 2..8");
     if (e->st) HIPCHK(hipStreamSynchronize(e->st));
     drop_graph(e);
     e->tend_ty = tend_rows;
-    e->fuse = baro_fuse == 0 ? 6 : baro_fuse;
+    e->fuse = baro_fuse == 0 ? 8 : baro_fuse;
     return ens_tables(e);
 }
 
@@ -1431,9 +1431,9 @@ int ocn_ensemble_autotune(ocn_ensemble* e, int32_t trial_steps, int32_t* tend_ro
     }
     const int first0 = e->first;
     const int rows_c[2] = {4, 8};
-    const int fuse_c[4] = {2, 3, 5, 6};
+    const int fuse_c[4] = {3, 5, 6, 8};
     double best = 1e300;
-    int brow = 0, bfuse = 5;
+    int brow = 0, bfuse = 8;
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));

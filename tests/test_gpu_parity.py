@@ -67,10 +67,11 @@ def test_beta_basin_fp64_ten_steps(seed):
     _compare(ref, gpu, w, inp["kbottom"], 1e-11)
 
 
-@pytest.mark.parametrize("fuse", [1, 2, 3, 6])
+@pytest.mark.parametrize("fuse", [1, 2, 3, 6, 8])
 def test_barotropic_fusion_depths_fp64(fuse):
-    """Every substep-fusion depth matches the oracle; 40 substeps do not divide
-    by 3 or 6, so the last launch of a step runs fewer substeps."""
+    """Every substep-fusion depth matches the oracle; a step runs 60 substeps
+    (40 and the window's extra half), which 8 does not divide, so the last
+    launch of a step runs fewer substeps."""
     w = small_latlon(nx=100, ny=40, nz=8, dt=900.0, n_substeps=40)
     ref, gpu, inp = _pair(w, baro_fuse=fuse)
     ref.step(3)
