@@ -306,14 +306,22 @@ __device__ __forceinline__ void column_regs_vk(const DevState& S, const int bx, 
     const R rdt = R(S.dt);
 
     R x[NZB], a[NZB];
+    {
+        const R* qx = src;
+        const R* qk = kwf + o0;
+        const R* qn = kwf + on;
 #pragma unroll
-    for (int k = 0; k < NZB; ++k) {
-        x[k] = (k < nz) ? src[k * pl] : R(0);
-        a[k] = R(0);
-        if (k < nz && k > kbot) {  // face k wet: layers k-1 and k
-            R kap = kwf[o0 + k * pl];
-            if (field != 0) kap = R(0.5) * (kwf[on + k * pl] + kap);
-            a[k] = -rdt * kap / R(S.dzc[k]);
+        for (int k = 0; k < NZB; ++k) {
+            x[k] = (k < nz) ? *qx : R(0);
+            a[k] = R(0);
+            if (k < nz && k > kbot) {  // face k wet: layers k-1 and k
+                R kap = *qk;
+                if (field != 0) kap = R(0.5) * (*qn + kap);
+                a[k] = -rdt * kap / R(S.dzc[k]);
+            }
+            qx += pl;
+            qk += pl;
+            qn += pl;
         }
     }
     R dprev = R(0), cprev = R(0);
