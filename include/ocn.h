@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define OCN_ABI_VERSION 1u
+#define OCN_ABI_VERSION 2u
 
 typedef enum {
     OCN_OK = 0,
@@ -91,6 +91,12 @@ typedef struct ocn_params {
     double t_ref;             /* equation-of-state reference temperature (degC)     */
     double kappa;             /* vertical diffusivity = viscosity (m^2/s)           */
     double restore_tau;       /* surface restoring time (s); <= 0 disables          */
+    double pgf_weight;        /* eps in [0, 1]: the momentum step takes the hydrostatic
+                                 pressure gradient of T^n + eps dt Ghat_T, the tracer
+                                 just predicted by AB2 weighted by eps (forward-
+                                 backward treatment of internal gravity waves, a
+                                 reading of the implicit-explicit AB2 of Sec. 5.2);
+                                 the other momentum terms take AB2               */
 } ocn_params;
 
 /* Field identifiers. */
@@ -105,8 +111,9 @@ typedef enum {
     OCN_FIELD_UBT_MEAN = 7,   /* 2D substep average of U over the last step         */
     OCN_FIELD_VBT_MEAN = 8,   /* 2D substep average of V over the last step         */
     OCN_FIELD_W = 9,          /* (nz+1)*ny*nx vertical velocity on z-faces, get only */
-    OCN_FIELD_GU_PREV = 10,   /* 3D AB2 history of u                                */
-    OCN_FIELD_GV_PREV = 11,   /* 3D AB2 history of v                                */
+    OCN_FIELD_GU_PREV = 10,   /* 3D AB2 history of u (terms other than the pressure
+                                 gradient, which is not extrapolated)               */
+    OCN_FIELD_GV_PREV = 11,   /* 3D AB2 history of v (likewise)                     */
     OCN_FIELD_GT_PREV = 12,   /* 3D AB2 history of T                                */
     OCN_FIELD_TAUX = 13,      /* 2D zonal wind stress at u-points (N/m^2)           */
     OCN_FIELD_TAUY = 14,      /* 2D meridional wind stress at v-points (N/m^2)      */

@@ -40,7 +40,7 @@ class OrcDesc(C.Structure):
                 ("f0", C.c_double), ("beta", C.c_double), ("radius", C.c_double), ("omega", C.c_double),
                 ("dt", C.c_double), ("chi", C.c_double), ("g", C.c_double), ("alpha", C.c_double),
                 ("rho0", C.c_double), ("t_ref", C.c_double), ("kappa", C.c_double),
-                ("restore_tau", C.c_double)]
+                ("restore_tau", C.c_double), ("pgf_weight", C.c_double)]
 
 
 _lib = None
@@ -109,6 +109,7 @@ def desc_from_workload(w) -> OrcDesc:
     d.dt, d.chi, d.g, d.alpha, d.rho0, d.t_ref = w.dt, w.chi, w.g, w.alpha, w.rho0, w.t_ref
     d.kappa = w.kappa
     d.restore_tau = w.restore_days * 86400.0 if w.restore_days > 0 else 0.0
+    d.pgf_weight = w.pgf_weight
     return d
 
 

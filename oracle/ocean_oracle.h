@@ -34,6 +34,8 @@ typedef struct orc_desc {
     double g, alpha, rho0, t_ref;  /* gravity, thermal expansion, density, EOS reference T */
     double kappa;                  /* vertical diffusivity = viscosity (m^2/s)    */
     double restore_tau;            /* surface restoring time (s); <= 0 turns it off */
+    double pgf_weight;             /* epsilon: the pressure gradient of the momentum step is
+                                      taken from T^n + epsilon dt Ghat_T (0..1)            */
 } orc_desc;
 
 typedef struct orc_model orc_model;

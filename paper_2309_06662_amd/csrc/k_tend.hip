@@ -159,17 +159,35 @@ template <> struct TendWaves<double> { static constexpr int n = 2; };
 
 // One tile (bx, by) of one state. Called by the single-state kernel and by the
 // batched kernel that steps an ensemble of basins in one launch.
+//
+// Forward-backward pressure. The momentum step takes the hydrostatic pressure
+// of T^n + eps dt Ghat_T, the tracer just predicted by AB2 weighted by eps,
+// not an extrapolated pressure gradient (AB2 alone amplifies the internal
+// gravity waves that converging meridians bring to a frequency times dt near
+// 1). The u point on a cell's west face needs that pressure in the column to
+// its west, and the v point on its south face in the column to its south, so
+// the ring threads (column tx = 0 and row ty = 0) also form the tracer
+// tendency of their own column: they read the AB2 history there (it is
+// double-buffered, so no tile overwrites a value another still reads) and the
+// fluxes through their far faces, which they compute in the flux slots that
+// ring threads otherwise leave idle (u through the north-west corner for the
+// column, u through the cell centre for the row). Every point's pressure goes
+// to LDS; the momentum tendencies of level k are completed one level later,
+// when the pressure of level k of the neighbours is in LDS, so the march keeps
+// three barriers per level.
 template <typename R, int TX, int TY>
 __device__ __forceinline__ void tend_tile(const DevState& S, const int first, const int bx, const int by) {
     constexpr int NT = TX * TY;
-    constexpr int LW = TX + 5, LH = TY + 5, LN = LW * LH;  // value tiles: points -2 .. +3 around the block
-    constexpr int KW = TX + 6, KH = TY + 6, KN = KW * KH;  // wet counts: one more on the low side
-    constexpr int NS = (LN + NT - 1) / NT;                 // tile slots per thread
+    constexpr int LW = TX + 5, LH = TY + 5, LN = LW * LH;  // u, v tiles: points -2 .. +3 around the block
+    constexpr int TW = TX + 6, TH = TY + 6, TN = TW * TH;  // T tile: points -3 .. +3
+    constexpr int KW = TX + 6, KH = TY + 6, KN = KW * KH;  // wet counts: -3 .. +3
+    constexpr int NS = (LN + NT - 1) / NT;                 // u, v tile slots per thread
+    constexpr int NST = (TN + NT - 1) / NT;                // T tile slots per thread
 
-    __shared__ R sT[LN], sU[LN], sV[LN];
+    __shared__ R sT[TN], sU[LN], sV[LN];
     __shared__ int sK[KN];
     __shared__ R fxT[NT], fyT[NT], fxu[NT], fyu[NT], fxv[NT], fyv[NT];
-    __shared__ R sQv[NT], sQu[NT], sP[NT], sWm[NT];
+    __shared__ R sQv[NT], sQu[NT], sP[2 * NT], sWm[NT];
 
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
     const int i0 = bx * (TX - 1), j0 = by * (TY - 1);
@@ -177,6 +195,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     const int nx = S.nx, ny = S.ny, nz = S.nz, h = S.h;
     const bool used = (pi < nx) && (pj < ny);
     const bool cell = used && tx >= 1 && ty >= 1;
+    const bool tcell = used && (tx >= 1 || ty >= 1);  // forms the tracer tendency of its column
     const bool need_x = used && ty >= 1;  // quantities a cell reads from its west neighbour
     const bool need_y = used && tx >= 1;  // ... from its south neighbour
     const bool need_c = need_x || need_y;
@@ -193,8 +212,9 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
         const int gj = min(max(j0 - 4 + lj, -S.hk), ny + S.hk - 1);
         sK[q] = S.kb[idxk(S, gi, gj)];
     }
-    // this thread's slots of the value tiles (origin (i0-3, j0-3)), as offsets in a level
-    int slot_off[NS];
+    // this thread's slots of the value tiles (u, v origin (i0-3, j0-3); T origin
+    // (i0-4, j0-4)), as offsets in a level
+    int slot_off[NS], slot_offT[NST];
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
         const int e = tid + q * NT;
@@ -203,10 +223,24 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
         const int gj = min(max(j0 - 3 + lj, -h), ny + h - 1);
         slot_off[q] = gj * S.p3 + gi;
     }
+#pragma unroll
+    for (int q = 0; q < NST; ++q) {
+        const int e = tid + q * NT;
+        const int li = e % TW, lj = e / TW;
+        // the point 4 cells before a periodic edge lies past a 3-cell halo:
+        // read its interior image
+        int gi = i0 - 4 + li, gj = j0 - 4 + lj;
+        if (gi < -h) gi = S.periodic_x ? gi + nx : -h;
+        if (gj < -h) gj = S.periodic_y ? gj + ny : -h;
+        gi = min(gi, nx + h - 1);
+        gj = min(gj, ny + h - 1);
+        slot_offT[q] = gj * S.p3 + gi;
+    }
     __syncthreads();
 
-    const int me = (ty + 2) * LW + (tx + 2);  // this point in the value tiles
-    const int mk = (ty + 3) * KW + (tx + 3);  // this point in the wet-count tile
+    const int me = (ty + 2) * LW + (tx + 2);   // this point in the u, v tiles
+    const int meT = (ty + 3) * TW + (tx + 3);  // this point in the T tile
+    const int mk = (ty + 3) * KW + (tx + 3);   // this point in the wet-count tile
     auto Kat = [&](int a, int b) { return sK[mk + a + b * KW]; };
     const int Kc = Kat(0, 0);
     const int Ku = min(Kc, Kat(-1, 0));
@@ -215,7 +249,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     const int KvN = min(Kc, Kat(0, 1)), KvNW = min(Kat(-1, 0), Kat(-1, 1));
     // smallest wet count over each horizontal stencil: all six points are
     // valid at level k when it reaches nz - k
-    int mTx = Kc, mTy = Kc, mux = Kc, muy = Kc, mvx = Kc, mvy = Kc;
+    int mTx = Kc, mTy = Kc, mux = Kc, muy = Kc, mvx = Kc, mvy = Kc, mTw = Kc, mTs = Kc;
 #pragma unroll
     for (int r = -3; r <= 3; ++r) {
         mux = min(mux, Kat(r, 0));
@@ -225,6 +259,10 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
             mTy = min(mTy, Kat(0, r));
             muy = min(muy, min(Kat(-1, r), Kat(0, r)));
             mvx = min(mvx, min(Kat(r, -1), Kat(r, 0)));
+        }
+        if (r <= 2) {  // the west and south faces of this point
+            mTw = min(mTw, Kat(r, 0));
+            mTs = min(mTs, Kat(0, r));
         }
     }
 
@@ -237,6 +275,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     const R dy = R(S.dy), inv_dy = R(1.0 / S.dy);
     const R ga = R(S.g * S.alpha);
     const R dt = R(S.dt);
+    const R fbdt = R(S.pgf_w * S.dt);
     const R c_new = first ? R(1) : R(1.5 + S.chi);
     const R c_old = first ? R(0) : R(0.5 + S.chi);
 
@@ -251,54 +290,100 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
 #pragma unroll
     for (int r = 0; r < 6; ++r) { wt[r] = R(0); wu[r] = R(0); wv[r] = R(0); }
     const long long pl = S.plane3;
-    const long long own = idx3(S, cell ? pi : 0, cell ? pj : 0, 0);
-    if (cell) {
+    const long long own = idx3(S, tcell ? pi : 0, tcell ? pj : 0, 0);
+    // the tracer history of a ring column in a periodic halo is read at its
+    // interior image (only interior values are written)
+    const int hi = (pi < 0 && S.periodic_x) ? pi + nx : pi;
+    const int hj = (pj < 0 && S.periodic_y) ? pj + ny : pj;
+    const long long ownh = idx3(S, tcell ? hi : 0, tcell ? hj : 0, 0);
+    if (tcell) {
 #pragma unroll
         for (int r = 1; r < 6; ++r) {
             const int k = nz + 2 - r;  // before the first shift: levels nz+1 .. nz-3
-            if (k >= 0 && k < nz) {
-                wt[r] = gT[own + k * pl]; wu[r] = gU[own + k * pl]; wv[r] = gV[own + k * pl];
-            }
+            if (k >= 0 && k < nz) wt[r] = gT[own + k * pl];
+        }
+    }
+    if (cell) {
+#pragma unroll
+        for (int r = 1; r < 6; ++r) {
+            const int k = nz + 2 - r;
+            if (k >= 0 && k < nz) { wu[r] = gU[own + k * pl]; wv[r] = gV[own + k * pl]; }
         }
     }
 
     // prefetch of the top level's tile slots
-    R pT[NS], pU[NS], pV[NS];
+    R pT[NST], pU[NS], pV[NS];
+#pragma unroll
+    for (int q = 0; q < NST; ++q) pT[q] = gT[(long long)(nz - 1) * pl + slot_offT[q]];
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
         const long long o = (long long)(nz - 1) * pl + slot_off[q];
-        pT[q] = gT[o]; pU[q] = gU[o]; pV[q] = gV[o];
+        pU[q] = gU[o]; pV[q] = gV[o];
     }
 
     R fzT_top = R(0), fzu_top = R(0), fzv_top = R(0);  // fluxes through the top face of level k
     R Wm_top = R(0);                                     // masked W on that face
     R p_prev = R(0), b_prev = R(0);
+    R GUp = R(0), GVp = R(0);  // momentum tendencies of level k+1 without the pressure gradient
     double gUacc = 0.0, gVacc = 0.0;
     const R wind_u = cell ? R(S.taux[idx2(S, pi, pj)] / (S.rho0 * S.dz[nz - 1])) : R(0);
     const R wind_v = cell ? R(S.tauy[idx2(S, pi, pj)] / (S.rho0 * S.dz[nz - 1])) : R(0);
-    const R tstar = cell ? R(S.tstar[idx2(S, pi, pj)]) : R(0);
+    const R tstar = tcell ? R(S.tstar[idx2(S, pi, pj)]) : R(0);
     const R rinv = R(S.restore_inv);
+    R* __restrict__ gto = f3<R>(S.gt_out);
+    const R* __restrict__ gti = f3<R>(S.gt);
+    R* __restrict__ gup = f3<R>(S.gu);
+    R* __restrict__ gvp = f3<R>(S.gv);
+    R* __restrict__ tso = f3<R>(S.ts);
+    R* __restrict__ uso = f3<R>(S.us);
+    R* __restrict__ vso = f3<R>(S.vs);
+
+    // Completes the momentum step of level kk (one above the level being
+    // marched) once the pressure of level kk of every point is in LDS:
+    // AB2 of the other terms plus the forward-backward pressure gradient.
+    auto finish_uv = [&](int kk, const R* P) {
+        const long long o = own + (long long)kk * pl;
+        const int kw = nz - kk;
+        R hU = c_new * GUp - c_old * gup[o];
+        R hV = c_new * GVp - c_old * gvp[o];
+        gup[o] = GUp;
+        gvp[o] = GVp;
+        if (Ku >= kw) hU -= (P[tid] - P[tid - 1]) * inv_dxc;
+        if (Kv >= kw) hV -= (P[tid] - P[tid - TX]) * inv_dy;
+        uso[o] = wu[1] + dt * hU;
+        vso[o] = wv[1] + dt * hV;
+        if (Ku >= kw) gUacc += double(S.dz[kk]) * double(hU);
+        if (Kv >= kw) gVacc += double(S.dz[kk]) * double(hV);
+    };
 
     for (int k = nz - 1; k >= 0; --k) {
         // shift the windows and load level k-3
 #pragma unroll
         for (int r = 0; r < 5; ++r) { wt[r] = wt[r + 1]; wu[r] = wu[r + 1]; wv[r] = wv[r + 1]; }
         wt[5] = R(0); wu[5] = R(0); wv[5] = R(0);
+        if (tcell && k - 3 >= 0) wt[5] = gT[own + (long long)(k - 3) * pl];
         if (cell && k - 3 >= 0) {
             const long long o = own + (long long)(k - 3) * pl;
-            wt[5] = gT[o]; wu[5] = gU[o]; wv[5] = gV[o];
+            wu[5] = gU[o]; wv[5] = gV[o];
         }
         // stage level k from the prefetch registers, then prefetch level k-1
 #pragma unroll
+        for (int q = 0; q < NST; ++q) {
+            const int e = tid + q * NT;
+            if (e < TN) sT[e] = pT[q];
+        }
+#pragma unroll
         for (int q = 0; q < NS; ++q) {
             const int e = tid + q * NT;
-            if (e < LN) { sT[e] = pT[q]; sU[e] = pU[q]; sV[e] = pV[q]; }
+            if (e < LN) { sU[e] = pU[q]; sV[e] = pV[q]; }
         }
         if (k >= 1) {
 #pragma unroll
+            for (int q = 0; q < NST; ++q) pT[q] = gT[(long long)(k - 1) * pl + slot_offT[q]];
+#pragma unroll
             for (int q = 0; q < NS; ++q) {
                 const long long o = (long long)(k - 1) * pl + slot_off[q];
-                pT[q] = gT[o]; pU[q] = gU[o]; pV[q] = gV[o];
+                pU[q] = gU[o]; pV[q] = gV[o];
             }
         }
         __syncthreads();
@@ -310,6 +395,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
         auto mu = [&](int a, int b) { return wet(a, b) && wet(a - 1, b); };
         auto mv = [&](int a, int b) { return wet(a, b) && wet(a, b - 1); };
         auto at = [&](const R* f, int a, int b) { return f[me + a + b * LW]; };
+        auto atT = [&](int a, int b) { return sT[meT + a + b * TW]; };
 
         // ---- quantities at this point ----
         if (used) {
@@ -319,27 +405,35 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
             const R V01 = (KvN >= kwet) ? at(sV, 0, 1) * dxv1 * dzk : R(0);
             R p[6];
             bool ok[6];
-            if (need_x) {
-                const R U1m = (KuSE >= kwet) ? at(sU, 1, -1) * dy * dzk : R(0);
-                // T through the east face
+            // T through the east face (every point: the ring row's cells need it too)
+            {
 #pragma unroll
-                for (int r = 0; r < 6; ++r) p[r] = at(sT, r - 2, 0);
+                for (int r = 0; r < 6; ++r) p[r] = atT(r - 2, 0);
                 if (mTx >= kwet) fxT[tid] = (U10 == R(0)) ? R(0) : upwind_flux_wet(U10, p);
                 else {
 #pragma unroll
                     for (int r = 0; r < 6; ++r) ok[r] = wet(r - 2, 0);
                     fxT[tid] = upwind_flux(U10, p, ok);
                 }
-                // u through the cell centre (between u(pi) and u(pi+1))
-                const R Fu = R(0.5) * (U00 + U10);
+            }
+            // u through the cell centre (between u(pi) and u(pi+1)); in the
+            // ring row: T through the south face
+            if (used && (ty >= 1 || tx >= 1)) {
+                const bool alt = ty == 0;
+                const R* base = alt ? &sT[meT - 3 * TW] : &sU[me - 2];
+                const int stride = alt ? TW : 1;
+                const R F = alt ? V00 : R(0.5) * (U00 + U10);
 #pragma unroll
-                for (int r = 0; r < 6; ++r) p[r] = at(sU, r - 2, 0);
-                if (mux >= kwet) fxu[tid] = (Fu == R(0)) ? R(0) : upwind_flux_wet(Fu, p);
+                for (int r = 0; r < 6; ++r) p[r] = base[r * stride];
+                if (alt ? (mTs >= kwet) : (mux >= kwet)) fxu[tid] = (F == R(0)) ? R(0) : upwind_flux_wet(F, p);
                 else {
 #pragma unroll
-                    for (int r = 0; r < 6; ++r) ok[r] = mu(r - 2, 0);
-                    fxu[tid] = upwind_flux(Fu, p, ok);
+                    for (int r = 0; r < 6; ++r) ok[r] = alt ? wet(0, r - 3) : mu(r - 2, 0);
+                    fxu[tid] = upwind_flux(F, p, ok);
                 }
+            }
+            if (need_x) {
+                const R U1m = (KuSE >= kwet) ? at(sU, 1, -1) * dy * dzk : R(0);
                 // v through the south-east corner (between v(pi,pj) and v(pi+1,pj))
                 const R Fv = R(0.5) * (U1m + U10);
 #pragma unroll
@@ -351,27 +445,35 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                     fxv[tid] = upwind_flux(Fv, p, ok);
                 }
             }
-            if (need_y) {
-                const R Vm1 = (KvNW >= kwet) ? at(sV, -1, 1) * dxv1 * dzk : R(0);
-                // T through the north face
+            // T through the north face (every point: the ring column's cells need it too)
+            {
 #pragma unroll
-                for (int r = 0; r < 6; ++r) p[r] = at(sT, 0, r - 2);
+                for (int r = 0; r < 6; ++r) p[r] = atT(0, r - 2);
                 if (mTy >= kwet) fyT[tid] = (V01 == R(0)) ? R(0) : upwind_flux_wet(V01, p);
                 else {
 #pragma unroll
                     for (int r = 0; r < 6; ++r) ok[r] = wet(0, r - 2);
                     fyT[tid] = upwind_flux(V01, p, ok);
                 }
-                // u through the north-west corner (between u(pi,pj) and u(pi,pj+1))
-                const R Fu = R(0.5) * (Vm1 + V01);
+            }
+            // u through the north-west corner (between u(pi,pj) and u(pi,pj+1));
+            // in the ring column: T through the west face
+            {
+                const bool alt = tx == 0;
+                const R Vm1 = (KvNW >= kwet) ? at(sV, -1, 1) * dxv1 * dzk : R(0);
+                const R* base = alt ? &sT[meT - 3] : &sU[me - 2 * LW];
+                const int stride = alt ? 1 : LW;
+                const R F = alt ? U00 : R(0.5) * (Vm1 + V01);
 #pragma unroll
-                for (int r = 0; r < 6; ++r) p[r] = at(sU, 0, r - 2);
-                if (muy >= kwet) fyu[tid] = (Fu == R(0)) ? R(0) : upwind_flux_wet(Fu, p);
+                for (int r = 0; r < 6; ++r) p[r] = base[r * stride];
+                if (alt ? (mTw >= kwet) : (muy >= kwet)) fyu[tid] = (F == R(0)) ? R(0) : upwind_flux_wet(F, p);
                 else {
 #pragma unroll
-                    for (int r = 0; r < 6; ++r) ok[r] = mu(0, r - 2);
-                    fyu[tid] = upwind_flux(Fu, p, ok);
+                    for (int r = 0; r < 6; ++r) ok[r] = alt ? wet(r - 3, 0) : mu(0, r - 2);
+                    fyu[tid] = upwind_flux(F, p, ok);
                 }
+            }
+            if (need_y) {
                 // v through the cell centre (between v(pj) and v(pj+1))
                 const R Fv = R(0.5) * (V00 + V01);
 #pragma unroll
@@ -391,12 +493,6 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                 sQv[tid] = Q * vc;
                 sQu[tid] = Q * uc;
             }
-            // hydrostatic pressure of the anomaly, from p = 0 at z = 0 downward
-            const R b = ga * at(sT, 0, 0);
-            const R pk = (k == nz - 1) ? -R(0.5) * dzk * b : p_prev - R(S.dzc[k + 1]) * (R(0.5) * (b + b_prev));
-            p_prev = pk;
-            b_prev = b;
-            sP[tid] = pk;
             // vertical transport on the bottom face of level k
             const double div = double(U10) - double(U00) + (double(V01) - double(V00));
             Wc = Wc + div;
@@ -405,9 +501,10 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
         }
         __syncthreads();
 
-        // ---- assembly for the cells of the tile ----
+        // ---- assembly: tracer of every column with a tendency, momentum of the cells ----
         const R Wm_b = sWm[tid];
-        if (cell) {
+        R* const Pk = &sP[(k & 1) * NT];
+        if (tcell) {
             const int c = tid, cw = tid - 1, cs = tid - TX;
             const long long o = own + (long long)k * pl;
 
@@ -438,43 +535,45 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                     // reference profile carried through this face, relative to tref(k)
                     E_bot = pos ? Wm_b * (-dtr[k * 4 + 1]) : R(0);
                 }
-                const R Fu = R(0.5) * (sWm[cw] + Wm_b);
-                if (Fu != R(0)) {
-                    R pu[6];
+                if (cell) {
+                    const R Fu = R(0.5) * (sWm[cw] + Wm_b);
+                    if (Fu != R(0)) {
+                        R pu[6];
 #pragma unroll
-                    for (int r = 0; r < 6; ++r) pu[r] = wu[5 - r];
-                    if (zin && Ku >= nz - (k - 3)) {
-                        fzu_bot = upwind_flux_wet(Fu, pu);
-                    } else {
-                        bool oku[6];
+                        for (int r = 0; r < 6; ++r) pu[r] = wu[5 - r];
+                        if (zin && Ku >= nz - (k - 3)) {
+                            fzu_bot = upwind_flux_wet(Fu, pu);
+                        } else {
+                            bool oku[6];
 #pragma unroll
-                        for (int r = 0; r < 6; ++r) {
-                            const int l = k - 3 + r;
-                            oku[r] = (l >= 0 && l < nz && Ku >= nz - l);
+                            for (int r = 0; r < 6; ++r) {
+                                const int l = k - 3 + r;
+                                oku[r] = (l >= 0 && l < nz && Ku >= nz - l);
+                            }
+                            fzu_bot = upwind_flux(Fu, pu, oku);
                         }
-                        fzu_bot = upwind_flux(Fu, pu, oku);
                     }
-                }
-                const R Fv = R(0.5) * (sWm[cs] + Wm_b);
-                if (Fv != R(0)) {
-                    R pv[6];
+                    const R Fv = R(0.5) * (sWm[cs] + Wm_b);
+                    if (Fv != R(0)) {
+                        R pv[6];
 #pragma unroll
-                    for (int r = 0; r < 6; ++r) pv[r] = wv[5 - r];
-                    if (zin && Kv >= nz - (k - 3)) {
-                        fzv_bot = upwind_flux_wet(Fv, pv);
-                    } else {
-                        bool okv[6];
+                        for (int r = 0; r < 6; ++r) pv[r] = wv[5 - r];
+                        if (zin && Kv >= nz - (k - 3)) {
+                            fzv_bot = upwind_flux_wet(Fv, pv);
+                        } else {
+                            bool okv[6];
 #pragma unroll
-                        for (int r = 0; r < 6; ++r) {
-                            const int l = k - 3 + r;
-                            okv[r] = (l >= 0 && l < nz && Kv >= nz - l);
+                            for (int r = 0; r < 6; ++r) {
+                                const int l = k - 3 + r;
+                                okv[r] = (l >= 0 && l < nz && Kv >= nz - l);
+                            }
+                            fzv_bot = upwind_flux(Fv, pv, okv);
                         }
-                        fzv_bot = upwind_flux(Fv, pv, okv);
                     }
                 }
             }
 
-            // tracer
+            // tracer; a ring column takes its far-face flux from its own idle slot
             R GT = R(0);
             if (Kc >= kwet) {
                 R E_top;
@@ -484,42 +583,46 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                     // upwind cell k+1 when the face transport is downward
                     E_top = (Wm_top > R(0)) ? R(0) : Wm_top * (-dtr[k * 4 + 2]);
                 }
-                const R divF = (fxT[c] - fxT[cw]) + (fyT[c] - fyT[cs]) + (fzT_top - fzT_bot);
+                const R fw = (tx == 0) ? fyu[c] : fxT[cw];
+                const R fs = (ty == 0) ? fxu[c] : fyT[cs];
+                const R divF = (fxT[c] - fw) + (fyT[c] - fs) + (fzT_top - fzT_bot);
                 GT = (-divF + (E_top - E_bot)) * (inv_area * inv_dz);
                 if (k == nz - 1) GT += (tstar - wt[2]) * rinv;
             }
-            // u momentum
-            R GUm = R(0);
-            if (Ku >= kwet) {
-                const R ivol = inv_area * inv_dz;
-                const R divF = (fxu[c] - fxu[cw]) + (fyu[c] - fyu[cs]) + (fzu_top - fzu_bot);
-                GUm = -divF * ivol + (sQv[cw] + sQv[c]) * (R(0.5) * ivol) - (sP[c] - sP[cw]) * inv_dxc;
-                if (k == nz - 1) GUm += wind_u;
+            // AB2 of the tracer (G^n goes to the other history buffer), and the
+            // pressure of T^n + eps dt Ghat_T from p = 0 at z = 0 downward
+            const R hT = c_new * GT - c_old * gti[ownh + (long long)k * pl];
+            if (cell) {
+                gto[o] = GT;
+                tso[o] = wt[2] + dt * hT;
             }
-            // v momentum
-            R GVm = R(0);
-            if (Kv >= kwet) {
-                const R ivol = inv_areav * inv_dz;
-                const R divF = (fxv[c] - fxv[cw]) + (fyv[c] - fyv[cs]) + (fzv_top - fzv_bot);
-                GVm = -divF * ivol - (sQu[cs] + sQu[c]) * (R(0.5) * ivol) - (sP[c] - sP[cs]) * inv_dy;
-                if (k == nz - 1) GVm += wind_v;
-            }
+            const R b = ga * (wt[2] + fbdt * hT);
+            const R pk = (k == nz - 1) ? -R(0.5) * dzk * b : p_prev - R(S.dzc[k + 1]) * (R(0.5) * (b + b_prev));
+            p_prev = pk;
+            b_prev = b;
+            Pk[tid] = pk;
 
-            // AB2 predictor; G^n replaces G^{n-1}
-            R* gtp = f3<R>(S.gt);
-            R* gup = f3<R>(S.gu);
-            R* gvp = f3<R>(S.gv);
-            const R hT = c_new * GT - c_old * gtp[o];
-            const R hU = c_new * GUm - c_old * gup[o];
-            const R hV = c_new * GVm - c_old * gvp[o];
-            gtp[o] = GT;
-            gup[o] = GUm;
-            gvp[o] = GVm;
-            f3<R>(S.ts)[o] = wt[2] + dt * hT;
-            f3<R>(S.us)[o] = wu[2] + dt * hU;
-            f3<R>(S.vs)[o] = wv[2] + dt * hV;
-            if (Ku >= kwet) gUacc += double(S.dz[k]) * double(hU);
-            if (Kv >= kwet) gVacc += double(S.dz[k]) * double(hV);
+            // momentum of the cells: level k+1 completes with its pressure
+            // (written before the last barrier); level k waits for its own
+            if (cell) {
+                if (k + 1 < nz) finish_uv(k + 1, &sP[((k + 1) & 1) * NT]);
+                R GUm = R(0);
+                if (Ku >= kwet) {
+                    const R ivol = inv_area * inv_dz;
+                    const R divF = (fxu[c] - fxu[cw]) + (fyu[c] - fyu[cs]) + (fzu_top - fzu_bot);
+                    GUm = -divF * ivol + (sQv[cw] + sQv[c]) * (R(0.5) * ivol);
+                    if (k == nz - 1) GUm += wind_u;
+                }
+                R GVm = R(0);
+                if (Kv >= kwet) {
+                    const R ivol = inv_areav * inv_dz;
+                    const R divF = (fxv[c] - fxv[cw]) + (fyv[c] - fyv[cs]) + (fzv_top - fzv_bot);
+                    GVm = -divF * ivol - (sQu[cs] + sQu[c]) * (R(0.5) * ivol);
+                    if (k == nz - 1) GVm += wind_v;
+                }
+                GUp = GUm;
+                GVp = GVm;
+            }
 
             fzT_top = fzT_bot;
             fzu_top = fzu_bot;
@@ -528,7 +631,12 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
         Wm_top = Wm_b;
         __syncthreads();
     }
+    // the bottom level's pressure is in LDS after the last barrier; the window
+    // is shifted once more so that w[1] holds level 0
     if (cell) {
+#pragma unroll
+        for (int r = 0; r < 5; ++r) { wu[r] = wu[r + 1]; wv[r] = wv[r + 1]; }
+        finish_uv(0, &sP[0]);
         S.gU[idx2(S, pi, pj)] = gUacc;
         S.gV[idx2(S, pi, pj)] = gVacc;
     }

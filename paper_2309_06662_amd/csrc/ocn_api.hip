@@ -7,6 +7,7 @@
 #include "ocn_dev.h"
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -84,18 +85,23 @@ struct ocn_state {
     bool ri_on = false;           // Richardson-number mixing into the prescribed field
     ocn::RiParams ri{};
     void* kv_ws = nullptr;        // the workspace's viscosity field (interior origin)
-    // one step captured as a HIP graph (ocn_step_graph)
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // the two tracer-history buffers; d.gt is the one the next step reads
+    void* gtb[2] = {nullptr, nullptr};
+    // one step captured as a HIP graph per history buffer (ocn_step_graph)
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    int parity() const { return d.gt == gtb[0] ? 0 : 1; }
 };
 
 namespace {
 
 void drop_graph(ocn_state* s) {
-    if (s->exec) (void)hipGraphExecDestroy(s->exec);
-    if (s->graph) (void)hipGraphDestroy(s->graph);
-    s->exec = nullptr;
-    s->graph = nullptr;
+    for (int q = 0; q < 2; ++q) {
+        if (s->exec[q]) (void)hipGraphExecDestroy(s->exec[q]);
+        if (s->graph[q]) (void)hipGraphDestroy(s->graph[q]);
+        s->exec[q] = nullptr;
+        s->graph[q] = nullptr;
+    }
 }
 
 int record(ocn_state* s) {
@@ -140,7 +146,7 @@ struct Plan {
     size_t oxk, pk, nk;
     size_t nrow;  // metric rows
     size_t diag_blocks;
-    size_t off_f3[9], off_f2[24], off_bw, off_kb, off_rows[5], off_dz, off_dzc, off_tref, off_dtr, off_tab;
+    size_t off_f3[10], off_f2[24], off_bw, off_kb, off_rows[5], off_dz, off_dzc, off_tref, off_dtr, off_tab;
     size_t off_part, off_out;
     size_t total;
 };
@@ -212,6 +218,7 @@ bool valid_params(const ocn_params* p, std::string& why) {
     if (!(p->rho0 > 0.0)) { why = "rho0 must be positive"; return false; }
     if (p->baro_fuse < 0 || p->baro_fuse > 8) { why = "baro_fuse must be in 0..8"; return false; }
     if (p->reserved1 != 0) { why = "reserved1 must be 0"; return false; }
+    if (!(p->pgf_weight >= 0.0 && p->pgf_weight <= 1.0)) { why = "pgf_weight must be in [0, 1]"; return false; }
     return true;
 }
 
@@ -682,8 +689,10 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         d.ox2 = (int)P.ox2;
         d.plane3 = (long long)P.p3 * (long long)P.rows;
         const size_t o3 = ((size_t)h * P.p3 + P.ox3) * P.esize;
-        void** f3s[9] = {&d.u, &d.v, &d.t, &d.us, &d.vs, &d.ts, &d.gu, &d.gv, &d.gt};
-        for (int q = 0; q < 9; ++q) *f3s[q] = A + P.off_f3[q] + o3;
+        void** f3s[10] = {&d.u, &d.v, &d.t, &d.us, &d.vs, &d.ts, &d.gu, &d.gv, &d.gt, &d.gt_out};
+        for (int q = 0; q < 10; ++q) *f3s[q] = A + P.off_f3[q] + o3;
+        s->gtb[0] = d.gt;
+        s->gtb[1] = d.gt_out;
         double** f2s[24] = {&d.eta, &d.ubt, &d.vbt, &d.se, &d.su, &d.sv, &d.eta_mean, &d.ubt_mean, &d.vbt_mean,
                             &d.gU, &d.gV, &d.hu, &d.hv, &d.cu, &d.cv, &d.taux, &d.tauy, &d.tstar, &d.scratch2d,
                             &d.eta2, &d.ubt2, &d.vbt2, &d.sfu, &d.sfv};
@@ -708,6 +717,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         d.rho0 = params->rho0;
         d.kappa = params->kappa;
         d.restore_inv = params->restore_tau > 0.0 ? 1.0 / params->restore_tau : 0.0;
+        d.pgf_w = params->pgf_weight;
         d.n_substeps = params->n_substeps;
         d.baro_fuse = params->baro_fuse == 0 ? 8 : params->baro_fuse;
         d.baro_m = ocn::baro_substeps(params->n_substeps);
@@ -857,6 +867,7 @@ void advance(ocn_state* s) {
     s->first = 0;
     s->step += 1;
     s->time += s->p.dt;
+    std::swap(s->d.gt, s->d.gt_out);  // G^n becomes the history of the next step
 }
 
 }  // namespace
@@ -881,7 +892,8 @@ int ocn_step_graph(ocn_state* s, int32_t n) {
         if (s->first || s->timing) {  // the start step and timed steps run eagerly
             if ((rc = enqueue_step(s))) return rc;
         } else {
-            if (!s->exec) {
+            const int par = s->parity();
+            if (!s->exec[par]) {
                 HIPCHK(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
                 rc = enqueue_step(s);
                 hipGraph_t g = nullptr;
@@ -891,10 +903,10 @@ int ocn_step_graph(ocn_state* s, int32_t n) {
                     return rc;
                 }
                 if (ce != hipSuccess) return fail(OCN_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
-                s->graph = g;
-                HIPCHK(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+                s->graph[par] = g;
+                HIPCHK(hipGraphInstantiate(&s->exec[par], s->graph[par], nullptr, nullptr, 0));
             }
-            HIPCHK(hipGraphLaunch(s->exec, s->st));
+            HIPCHK(hipGraphLaunch(s->exec[par], s->st));
         }
         advance(s);
     }
@@ -1181,14 +1193,17 @@ struct ocn_ensemble {
     int first = 1;
     int tend_ty = 0;   // 0 = precision default
     int fuse = 8;
-    DevState* d_members = nullptr;
+    DevState* d_members = nullptr;  // two tables of the members: as they are, and with
+                                    // their tracer-history buffers swapped
+    std::vector<DevState> tab[2];   // host copies of both tables
+    int epar = 0;                   // the table the next step uses
     int4* d_tend = nullptr;
     int4* d_col = nullptr;
     int4* d_baro = nullptr;
     int n_tend = 0, n_col = 0, n_baro = 0;
     size_t cap_tend = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -1215,7 +1230,7 @@ int ens_plan(const ocn_grid* const* grids, int n, const ocn_params* params, EnsP
         P.cap_baro += (size_t)((grids[m]->nx + ocn::kBaroTileX - 1) / ocn::kBaroTileX) *
                       ((grids[m]->ny + ocn::kBaroTileY - 1) / ocn::kBaroTileY);
     }
-    P.off_dev = L.add(n * sizeof(DevState));
+    P.off_dev = L.add(2 * (size_t)n * sizeof(DevState));
     P.off_tend = L.add(P.cap_tend * sizeof(int4));
     P.off_col = L.add(P.cap_col * sizeof(int4));
     P.off_baro = L.add(P.cap_baro * sizeof(int4));
@@ -1258,43 +1273,65 @@ int ens_tables(ocn_ensemble* e) {
     HIPCHK(hipMemcpyAsync(e->d_baro, baro.data(), baro.size() * sizeof(int4), hipMemcpyHostToDevice, e->st));
     e->n_col = (int)col.size();
     e->n_baro = (int)baro.size();
-    // member states with the ensemble's tile settings
-    std::vector<DevState> ds;
+    // member states with the ensemble's tile settings, and the same with the
+    // tracer-history buffers swapped (the table of the step after)
+    const size_t n = e->members.size();
+    e->tab[0].clear();
+    e->tab[1].clear();
     for (ocn_state* s : e->members) {
         s->d.tend_ty = e->tend_ty;
         s->d.baro_fuse = e->fuse;
-        ds.push_back(s->d);
+        e->tab[0].push_back(s->d);
+        DevState o = s->d;
+        std::swap(o.gt, o.gt_out);
+        e->tab[1].push_back(o);
     }
-    HIPCHK(hipMemcpyAsync(e->d_members, ds.data(), ds.size() * sizeof(DevState), hipMemcpyHostToDevice, e->st));
+    e->epar = 0;
+    for (int q = 0; q < 2; ++q)
+        HIPCHK(hipMemcpyAsync(e->d_members + q * n, e->tab[q].data(), n * sizeof(DevState), hipMemcpyHostToDevice,
+                              e->st));
     HIPCHK(hipStreamSynchronize(e->st));
     return OCN_OK;
 }
 
 void drop_graph(ocn_ensemble* e) {
-    if (e->exec) (void)hipGraphExecDestroy(e->exec);
-    if (e->graph) (void)hipGraphDestroy(e->graph);
-    e->exec = nullptr;
-    e->graph = nullptr;
+    for (int q = 0; q < 2; ++q) {
+        if (e->exec[q]) (void)hipGraphExecDestroy(e->exec[q]);
+        if (e->graph[q]) (void)hipGraphDestroy(e->graph[q]);
+        e->exec[q] = nullptr;
+        e->graph[q] = nullptr;
+    }
 }
 
 int ens_enqueue(ocn_ensemble* e, int first) {
     const bool f32 = e->esize == 4;
     const int ty = ocn::tend_tile_rows(e->esize, e->tend_ty);
-    HIPCHK(f32 ? ocn::launch_tendency_batched<float>(e->d_members, e->d_tend, e->n_tend, ty, first, e->st)
-               : ocn::launch_tendency_batched<double>(e->d_members, e->d_tend, e->n_tend, ty, first, e->st));
-    HIPCHK(ocn::launch_barotropic_batched(e->d_members, (int)e->members.size(), e->d_baro, e->n_baro, e->p.n_substeps, e->fuse, e->p.dt, e->st));
-    HIPCHK(f32 ? ocn::launch_column_batched<float>(e->d_members, e->d_col, e->n_col, e->max_nz, e->st)
-               : ocn::launch_column_batched<double>(e->d_members, e->d_col, e->n_col, e->max_nz, e->st));
+    const DevState* dm = e->d_members + (size_t)e->epar * e->members.size();
+    HIPCHK(f32 ? ocn::launch_tendency_batched<float>(dm, e->d_tend, e->n_tend, ty, first, e->st)
+               : ocn::launch_tendency_batched<double>(dm, e->d_tend, e->n_tend, ty, first, e->st));
+    HIPCHK(ocn::launch_barotropic_batched(dm, (int)e->members.size(), e->d_baro, e->n_baro, e->p.n_substeps, e->fuse, e->p.dt, e->st));
+    HIPCHK(f32 ? ocn::launch_column_batched<float>(dm, e->d_col, e->n_col, e->max_nz, e->st)
+               : ocn::launch_column_batched<double>(dm, e->d_col, e->n_col, e->max_nz, e->st));
     return OCN_OK;
 }
 
 int ens_step(ocn_ensemble* e, int n) {
     int rc;
     for (int q = 0; q < n; ++q) {
+        // a member stepped on its own since the tables were built has its
+        // history buffers the other way round: rebuild the tables
+        for (size_t m = 0; m < e->members.size(); ++m)
+            if (e->members[m]->d.gt != e->tab[e->epar][m].gt) {
+                if (e->st) HIPCHK(hipStreamSynchronize(e->st));
+                drop_graph(e);
+                if ((rc = ens_tables(e))) return rc;
+                break;
+            }
         if (e->first || !e->st) {
             if ((rc = ens_enqueue(e, e->first))) return rc;
         } else {
-            if (!e->exec) {
+            const int par = e->epar;
+            if (!e->exec[par]) {
                 HIPCHK(hipStreamBeginCapture(e->st, hipStreamCaptureModeThreadLocal));
                 rc = ens_enqueue(e, 0);
                 hipGraph_t g = nullptr;
@@ -1304,16 +1341,18 @@ int ens_step(ocn_ensemble* e, int n) {
                     return rc;
                 }
                 if (ce != hipSuccess) return fail(OCN_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
-                e->graph = g;
-                HIPCHK(hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0));
+                e->graph[par] = g;
+                HIPCHK(hipGraphInstantiate(&e->exec[par], e->graph[par], nullptr, nullptr, 0));
             }
-            HIPCHK(hipGraphLaunch(e->exec, e->st));
+            HIPCHK(hipGraphLaunch(e->exec[par], e->st));
         }
         e->first = 0;
+        e->epar ^= 1;
         for (ocn_state* s : e->members) {
             s->first = 0;
             s->step += 1;
             s->time += s->p.dt;
+            std::swap(s->d.gt, s->d.gt_out);
         }
     }
     return OCN_OK;

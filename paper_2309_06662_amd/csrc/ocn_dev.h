@@ -41,7 +41,10 @@ struct DevState {
     // 3D fields of the field type (double or float), interior origin
     void *u, *v, *t;        // state; t holds T - tref(k)
     void *us, *vs, *ts;     // AB2 predictor phi*
-    void *gu, *gv, *gt;     // AB2 history G^{n-1}, overwritten with G^n
+    void *gu, *gv;          // AB2 history G^{n-1} of u, v (other terms than the
+                            // pressure gradient), overwritten with G^n
+    void *gt, *gt_out;      // AB2 history of T: G^{n-1} is read from gt and G^n
+                            // written to gt_out (the host swaps them every step)
     // 2D FP64
     double *eta, *ubt, *vbt;             // barotropic state
     double *se, *su, *sv;                // window sums of eta^q; transport sums of U^l, V^l
@@ -83,6 +86,7 @@ struct DevState {
     int diag_blocks;
     // scalars
     double dt, chi, g, alpha, rho0, kappa, restore_inv;
+    double pgf_w;   // eps: the momentum step's pressure is that of T^n + eps dt Ghat_T
     int n_substeps;
     int baro_fuse;  // substeps per barotropic launch
     int tend_ty;    // rows of threads per tendency workgroup (4 or 8; 0 = precision default)

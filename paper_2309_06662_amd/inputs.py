@@ -119,6 +119,7 @@ class Workload:
     dt: float = 1200.0
     n_substeps: int = 30
     chi: float = 0.1                    # AB2 offset (quasi-second-order form)
+    pgf_weight: float = 0.75            # pressure gradient from T^n + pgf_weight dt Ghat_T
     tau0: float = 0.1                   # wind-stress amplitude, N/m^2
     restore_days: float = 0.0           # <= 0: no restoring
     strat_t0: float = 20.0              # T = strat_t0 * exp(z / strat_scale) + noise

@@ -62,7 +62,7 @@ class Params(C.Structure):
     _fields_ = [("precision", C.c_int32), ("n_substeps", C.c_int32), ("baro_fuse", C.c_int32),
                 ("reserved1", C.c_int32), ("dt", C.c_double), ("chi", C.c_double), ("g", C.c_double),
                 ("alpha", C.c_double), ("rho0", C.c_double), ("t_ref", C.c_double), ("kappa", C.c_double),
-                ("restore_tau", C.c_double)]
+                ("restore_tau", C.c_double), ("pgf_weight", C.c_double)]
 
 
 class Diag(C.Structure):
@@ -165,6 +165,7 @@ def params(w: "_inputs.Workload", precision: str, baro_fuse: int = 0) -> Params:
     p.baro_fuse = baro_fuse
     p.dt, p.chi, p.g, p.alpha, p.rho0, p.t_ref, p.kappa = w.dt, w.chi, w.g, w.alpha, w.rho0, w.t_ref, w.kappa
     p.restore_tau = w.restore_days * 86400.0 if w.restore_days > 0 else 0.0
+    p.pgf_weight = w.pgf_weight
     return p
 
 
@@ -374,8 +375,9 @@ class Ensemble:
             inputs_list = [_inputs.make_inputs(w) for w in self.workloads]
         p0 = self.workloads[0]
         for w in self.workloads:
-            if (w.dt, w.n_substeps, w.kappa, w.chi, w.g, w.alpha, w.rho0, w.t_ref, w.restore_days) != \
-                    (p0.dt, p0.n_substeps, p0.kappa, p0.chi, p0.g, p0.alpha, p0.rho0, p0.t_ref, p0.restore_days):
+            if (w.dt, w.n_substeps, w.kappa, w.chi, w.pgf_weight, w.g, w.alpha, w.rho0, w.t_ref, w.restore_days) != \
+                    (p0.dt, p0.n_substeps, p0.kappa, p0.chi, p0.pgf_weight, p0.g, p0.alpha, p0.rho0, p0.t_ref,
+                     p0.restore_days):
                 raise ValueError("ensemble members must share time step and physical parameters")
         self.grids = [Grid(w, inp["dz"], inp["kbottom"]) for w, inp in zip(self.workloads, inputs_list)]
         self._params = params(p0, precision, baro_fuse)

@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     L = ocn.lib()
     for name in _declared():
         assert hasattr(L, name), name
-    assert L.ocn_abi_version() == 1
+    assert L.ocn_abi_version() == 2
 
 
 def _grid(w, **over):

@@ -1,19 +1,26 @@
-"""Parity at the full 1/12-degree size (4320 x 1800 x 100, the benchmarked
-configuration), on sampled outputs the oracle can compute one by one.
+"""Parity and stability at the full sizes of the two lat-lon grids: 1/12 degree
+(4320 x 1800 x 100, the benchmarked configuration) and 1/4 degree
+(1440 x 600 x 50).
 
-One step moves information at most 3 cells through the tendency stencils (one
-more through the velocity masks) and one cell per barotropic substep (90 at
-this size: 60 substeps per step, run on to 3/2 of the step), so after two
-steps a column depends only on the initial state within 2 x 94 = 188 columns
-of it. The oracle steps a bounded window of radius 200 columns cut from the
-seeded inputs, twice (the three windows on parallel threads: the oracle runs
-outside the interpreter lock), and the
-centre 25 x 25 patch must match the GPU's state after its second step: FP64
-within 1e-11 relative, FP32 within 1e-4. (On a 5 x 5 patch at 180E, 50S the
-barotropic V moves by 5e-12 between two oracle builds that differ only in
-fused multiply-adds: a field-wide relative norm, as the tolerance is defined,
-needs a patch wider than that rounding-sensitive spot.) Both sides start from the same
-inputs; nothing the GPU computed enters the oracle.
+Parity on sampled outputs the oracle can compute one by one. One step moves
+information at most 3 cells through the tendency stencils (one more through
+the velocity masks) and one cell per barotropic substep (90 at both sizes: 60
+substeps per step, run on to 3/2 of the step), so after two steps a column
+depends only on the initial state within 2 x 94 = 188 columns of it. The
+oracle steps a bounded window of radius 200 columns cut from the seeded inputs,
+twice (the windows on parallel threads: the oracle runs outside the
+interpreter lock), and the centre 25 x 25 patch must match the GPU's state
+after its second step: FP64 within 1e-11 relative, FP32 within 1e-4. (On a
+5 x 5 patch at 180E, 50S the barotropic V moves by 5e-12 between two oracle
+builds that differ only in fused multiply-adds: a field-wide relative norm, as
+the tolerance is defined, needs a patch wider than that rounding-sensitive
+spot.) The samples include the high latitudes, where converging meridians
+make the internal waves fastest relative to the grid, and a ridge crest with
+land. Both sides start from the same inputs; nothing the GPU computed enters
+the oracle.
+
+Stability: 100 steps of the whole 1/12-degree grid and 200 of the 1/4-degree
+grid stay finite with bounded velocities and free surface, in both precisions.
 """
 import functools
 
@@ -28,11 +35,16 @@ pytestmark = pytest.mark.gpu
 R = 200     # window radius in columns
 P = 12      # half-width of the compared patch (R - 2 x 94 = 12 columns stay clean)
 STEPS = 2
-W = inputs.LATLON_TWELFTH
-SAMPLES = [(100, 900), (2160, 300), (4300, 1500)]  # (i, j): equator-ish, southern ocean, near the x seam
+TWELFTH = inputs.LATLON_TWELFTH
+QUARTER = inputs.LATLON_QUARTER
+# (i, j) per grid: equator-ish, southern ocean, near the x seam, 70S, a ridge crest with land
+SAMPLES = {
+    TWELFTH.name: [(100, 900), (2160, 300), (4300, 1500), (1800, 60), (1080, 900)],
+    QUARTER.name: [(720, 30), (0, 412), (1100, 560)],
+}
 
 
-def _window(ic, jc):
+def _window(W, ic, jc):
     cols = np.arange(ic - R, ic + R + 1) % W.nx
     j0, j1 = max(0, jc - R), min(W.ny, jc + R + 1)
     rows = np.arange(j0, j1)
@@ -42,10 +54,10 @@ def _window(ic, jc):
     return win, sub, jc - j0
 
 
-@functools.lru_cache(maxsize=None)
-def _inputs():
-    print(f"full-size {W.name}: inputs", flush=True)
-    return inputs.make_inputs(W)
+@functools.lru_cache(maxsize=2)
+def _inputs(name):
+    print(f"full-size {name}: inputs", flush=True)
+    return inputs.make_inputs(inputs.WORKLOADS[name])
 
 
 def _oracle_window(args):
@@ -61,34 +73,35 @@ def _oracle_window(args):
 
 
 @functools.lru_cache(maxsize=None)
-def _oracle_patches():
-    """The oracle's centre patches of every sample (shared by both precisions)."""
+def _oracle_patches(name):
+    """The oracle's centre patches of every sample of a grid (shared by both precisions)."""
     import concurrent.futures as cf
 
-    inp = _inputs()
+    W = inputs.WORKLOADS[name]
+    inp = _inputs(name)
     jobs = []
-    for ic, jc in SAMPLES:
-        win, sub, jcw = _window(ic, jc)
+    for ic, jc in SAMPLES[name]:
+        win, sub, jcw = _window(W, ic, jc)
         print(f"  oracle window {win.nx}x{win.ny}x{win.nz} around ({ic},{jc})", flush=True)
         fields = {"T": sub(inp["T0"]), "taux": sub(inp["taux"]), "tauy": sub(inp["tauy"]), "tstar": sub(inp["tstar"])}
         jobs.append((win, inp["dz"], sub(inp["kbottom"]), fields, jcw))
     with cf.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
-        return dict(zip(SAMPLES, ex.map(_oracle_window, jobs)))
+        return dict(zip(SAMPLES[name], ex.map(_oracle_window, jobs)))
 
 
-def _check(precision, tol):
+def _check(W, precision, tol):
     from paper_2309_06662_amd import ocn
 
-    ref_all = _oracle_patches()
-    inp = _inputs()
+    ref_all = _oracle_patches(W.name)
+    inp = _inputs(W.name)
     gpu = ocn.Model(W, precision, inp)
-    print(f"full-size {precision}: {STEPS} steps on the GPU", flush=True)
+    print(f"full-size {W.name} {precision}: {STEPS} steps on the GPU", flush=True)
     gpu.step(STEPS)
     got_all = {n: gpu.get(n) for n in ("u", "v", "T", "eta", "U", "V")}
     del gpu
     worst = 0.0
-    for ic, jc in SAMPLES:
-        _, sub, jcw = _window(ic, jc)
+    for ic, jc in SAMPLES[W.name]:
+        _, sub, jcw = _window(W, ic, jc)
         ref = ref_all[(ic, jc)]
         for n, a in got_all.items():
             got = sub(a)[..., jcw - P:jcw + P + 1, R - P:R + P + 1]
@@ -100,9 +113,29 @@ def _check(precision, tol):
     assert np.isfinite(worst)
 
 
-def test_fullsize_fp64_sampled_columns():
-    _check("fp64", 1e-11)
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+def test_fullsize_twelfth_sampled_columns(precision, tol):
+    _check(TWELFTH, precision, tol)
 
 
-def test_fullsize_fp32_sampled_columns():
-    _check("fp32", 1e-4)
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+def test_fullsize_quarter_sampled_columns(precision, tol):
+    _check(QUARTER, precision, tol)
+
+
+@pytest.mark.parametrize("name,steps", [(TWELFTH.name, 100), (QUARTER.name, 200)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fullsize_long_run_stays_bounded(name, steps, precision):
+    from paper_2309_06662_amd import ocn
+
+    W = inputs.WORKLOADS[name]
+    gpu = ocn.Model(W, precision, _inputs(name))
+    for done in range(0, steps, 25):
+        gpu.step(25)
+        d = gpu.diagnostics(allow_unstable=True)
+        print(f"  {name} {precision} step {done + 25}: max|u| {d['max_abs_u']:.3e} max|v| {d['max_abs_v']:.3e} "
+              f"eta [{d['eta_min']:.3e}, {d['eta_max']:.3e}] cfl {d['cfl_adv']:.3f} nonfinite {d['nonfinite']}",
+              flush=True)
+        assert d["nonfinite"] == 0
+        assert d["max_abs_u"] < 2.0 and d["max_abs_v"] < 2.0
+        assert max(abs(d["eta_min"]), abs(d["eta_max"])) < 2.0
