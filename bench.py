@@ -14,7 +14,16 @@ before the timed region starts; the timed region is K whole steps (tendency +
 AB2, barotropic substeps, column solve + correction), bracketed by device
 synchronisation.
 
+Every leg reports whether its state stayed finite and its largest speed; the
+run exits with status 3 when the headline leg ended non-finite.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Counter tooling (for the traffic records under profiles/):
+  python bench.py --copy-probe [--mib N]      a plain device copy of known size,
+                                              to calibrate FETCH_SIZE / WRITE_SIZE
+  python bench.py --pmc-summary ...           per-launch HBM bytes of a kernel from
+                                              two counter runs, scaled by the copy's
 """
 import argparse
 import hashlib
@@ -44,8 +53,15 @@ TEND_WORDS_PER_CELL = 12
 # indicators, 1 tau, 6 ratios, 9 weights, 8 normalisation) = 666, plus 9 flux
 # products, 24 for three flux divergences, 18 Coriolis, 9 pressure and its
 # gradients, 21 transports and vertical transport, 14 reference-profile terms,
-# 12 AB2, 4 slow-forcing sums and 3 surface forcing = 780.
-TEND_FLOPS_PER_CELL = 780
+# 12 AB2, 2 for the predicted tracer of the pressure, 4 slow-forcing sums and
+# 3 surface forcing = 782.
+TEND_FLOPS_PER_CELL = 782
+# Barotropic launch (FP64): read eta, U, V, G_U, G_V, H_u, H_v and the five
+# window sums, write eta, U, V and the five sums = 20 words per column.
+BARO_WORDS_PER_COLUMN = 20
+# Column solve with the constant diffusivity: read u*, v*, T* and write u, v, T.
+COLUMN_WORDS_PER_CELL = 6
+KERNEL_SOURCES = {"k_tend": "k_tend.hip", "k_baro_fused": "k_baro.hip", "k_column": "k_column.hip"}
 
 
 def _src_hash(path):
@@ -53,16 +69,20 @@ def _src_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic_from_profiles(workload, precision, esize):
-    """HBM bytes per launch of the tendency kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"k_tend_{workload}_{precision}_pmc.json")
+def _kernel_src(kernel):
+    return os.path.join(ROOT, "paper_2309_06662_amd", "csrc", KERNEL_SOURCES[kernel])
+
+
+def _traffic_from_profiles(workload, precision, kernel="k_tend"):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_pmc.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
             rec = json.load(f)
-        if rec.get("source_sha256_16") != _src_hash(os.path.join(ROOT, "paper_2309_06662_amd", "csrc", "k_tend.hip")):
+        if rec.get("source_sha256_16") != _src_hash(_kernel_src(kernel)):
             return None
         return rec.get("hbm_bytes_per_launch")
     except Exception:
@@ -112,14 +132,19 @@ def run_ensemble(steps, warmup, n_members=64):
     ens.step(steps)
     ens.synchronize()
     batched = time.perf_counter() - t0
-    with torch.cuda.stream(ens.stream):
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            for mem in ens.members:
-                ocn._check(ocn.lib().ocn_step(mem.handle, 1), "ocn_step")
-        ens.synchronize()
-        sequential = time.perf_counter() - t0
-    finite = all(m.diagnostics(allow_unstable=True)["nonfinite"] == 0 for m in ens.members)
+    # the same members one by one, each step replayed from its own captured
+    # graph (two warm-up steps capture the graphs of both history buffers)
+    seq = lambda: [ocn._check(ocn.lib().ocn_step_graph(mem.handle, 1), "ocn_step_graph") for mem in ens.members]
+    for _ in range(2):
+        seq()
+    ens.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        seq()
+    ens.synchronize()
+    sequential = time.perf_counter() - t0
+    diags = [m.diagnostics(allow_unstable=True) for m in ens.members]
+    finite = all(d["nonfinite"] == 0 for d in diags)
     cells = ens.cells
     ens.close()
     del ens
@@ -130,7 +155,8 @@ def run_ensemble(steps, warmup, n_members=64):
             "sequential_ms_per_step": sequential / steps * 1e3,
             "sequential_cell_updates_per_s": cells * steps / sequential,
             "speedup_batched_over_sequential": sequential / batched,
-            "autotune": tune, "finite": finite}
+            "sequential_mode": "each member replayed from its own captured graph",
+            "autotune": tune, "finite": finite, "max_abs_u": max(d["max_abs_u"] for d in diags)}
 
 
 def run_small(steps=200, warmup=5):
@@ -177,7 +203,7 @@ def run_quarter(steps, warmup):
         ms = el / steps * 1e3
         out[prec] = {"ms_per_step": ms, "cell_updates_per_s": w.cells * steps / el,
                      "sypd": metrics.sypd(w.dt, ms * 1e-3), "stage_ms": {k: round(v, 4) for k, v in stages.items()},
-                     "finite": diag["nonfinite"] == 0}
+                     "finite": diag["nonfinite"] == 0, "max_abs_u": diag["max_abs_u"]}
     din, h, dout = (4 * w.nz + 3 + 7) // 8 * 8, 128, w.nz
     rng = np.random.default_rng(0)
     P = [rng.normal(size=(din, h)) * np.sqrt(2.0 / din), np.zeros(h), rng.normal(size=(h, h)) * np.sqrt(2.0 / h),
@@ -197,7 +223,7 @@ def run_quarter(steps, warmup):
     el = time.perf_counter() - t0
     st, n = m.stage_times()
     m.stage_timing(False)
-    finite = m.diagnostics(allow_unstable=True)["nonfinite"] == 0
+    dg = m.diagnostics(allow_unstable=True)
     m.detach_closure()
     m.close()
     cols = w.nx * w.ny
@@ -205,7 +231,8 @@ def run_quarter(steps, warmup):
     cl_ms = st["closure"] / max(n, 1)
     out["closure"] = {"network": [din, h, h, dout], "ms_per_step": el / steps * 1e3,
                       "closure_stage_ms": cl_ms, "slowdown_vs_constant_kappa": (el / steps * 1e3) / out["fp32"]["ms_per_step"],
-                      "network_tflops_in_closure_stage": gemm_flops / (cl_ms * 1e-3) / 1e12, "finite": finite}
+                      "network_tflops_in_closure_stage": gemm_flops / (cl_ms * 1e-3) / 1e12,
+                      "finite": dg["nonfinite"] == 0, "max_abs_u": dg["max_abs_u"]}
     # Richardson-number mixing: viscosity and diffusivity diagnosed from the state every step
     m = ocn.Model(w, "fp32", inp)
     m.attach_closure()
@@ -220,7 +247,7 @@ def run_quarter(steps, warmup):
     el = time.perf_counter() - t0
     st, n = m.stage_times()
     m.stage_timing(False)
-    finite = m.diagnostics(allow_unstable=True)["nonfinite"] == 0
+    dg = m.diagnostics(allow_unstable=True)
     m.detach_closure()
     m.close()
     ri_ms = st["closure"] / max(n, 1)
@@ -229,7 +256,7 @@ def run_quarter(steps, warmup):
                          "diagnosis_gbs": 5 * 4 * w.cells / (ri_ms * 1e-3) / 1e9,
                          "column_ms": st["column"] / max(n, 1),
                          "slowdown_vs_constant_kappa": (el / steps * 1e3) / out["fp32"]["ms_per_step"],
-                         "finite": finite}
+                         "finite": dg["nonfinite"] == 0, "max_abs_u": dg["max_abs_u"]}
     return out
 
 
@@ -252,7 +279,12 @@ def copy_bandwidth(mib=2048, repeat=5):
     return 2.0 * 4 * n * repeat / el / 1e9
 
 
-def roofline(w, precision, stage_ms):
+def roofline(w, precision, stage_ms, n_baro_launches):
+    """Rooflines of the three stages from their HIP-event times per step.
+
+    Tendency: 12 words per cell, or 782 flops per cell against the vector
+    peak, whichever fraction is larger (the dominant kernel). Barotropic: 20
+    FP64 words per column per launch. Column solve: 6 words per cell."""
     esize = 4 if precision == "fp32" else 8
     t = stage_ms["tendency"] * 1e-3
     cells = w.cells
@@ -263,32 +295,142 @@ def roofline(w, precision, stage_ms):
     alu = {"bound": "alu", "achieved": round(tfl, 2), "peak": ALU_PEAK_TFLOPS[precision], "unit": "TFLOP/s",
            "frac": round(tfl / ALU_PEAK_TFLOPS[precision], 4)}
     main, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
-    main = dict(main, kernel="k_tend", traffic=_traffic_from_profiles(w.name, precision, esize))
-    return main, other
+    main = dict(main, kernel="k_tend", traffic=_traffic_from_profiles(w.name, precision, "k_tend"))
+    cols = w.nx * w.ny
+    baro_bytes = BARO_WORDS_PER_COLUMN * 8 * cols  # per launch
+    tb = stage_ms["barotropic"] * 1e-3 / max(n_baro_launches, 1)
+    baro = {"kernel": "k_baro_fused", "bound": "hbm", "launches_per_step": n_baro_launches,
+            "bytes_per_launch": baro_bytes, "achieved": round(baro_bytes / tb / 1e9, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(baro_bytes / tb / 1e9 / HBM_PEAK_GBS, 4),
+            "share_of_step": round(stage_ms["barotropic"] / sum(stage_ms[k] for k in ("tendency", "barotropic", "column")), 4),
+            "traffic": _traffic_from_profiles(w.name, precision, "k_baro_fused")}
+    col_bytes = COLUMN_WORDS_PER_CELL * esize * cells
+    tc = stage_ms["column"] * 1e-3
+    col = {"kernel": "k_column", "bound": "hbm", "bytes_per_launch": col_bytes,
+           "achieved": round(col_bytes / tc / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(col_bytes / tc / 1e9 / HBM_PEAK_GBS, 4)}
+    return main, other, {"barotropic": baro, "column": col}
 
 
-def cpu_baseline(w, max_seconds=30.0):
-    """The oracle on a bounded window of the same 1/12-degree workload: a
-    240 x 120 column window (all 100 levels) of the same analytic basin,
-    stepped until about 10 s of work, single-threaded."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_window_rate(args):
+    """Steps one oracle window for about seconds; returns (cells x steps, seconds)."""
     import oracle
 
-    win = w.replace(name=w.name + "_window", nx=240, ny=120, periodic_x=False, x0=150.0, y0=-10.0)
-    inp = inputs.make_inputs(win)
-    m = oracle.OracleModel.from_inputs(win, inp)
+    w, lon0, seconds = args
+    win = w.replace(name=w.name + "_window", nx=240, ny=120, periodic_x=False, x0=lon0, y0=-10.0)
+    m = oracle.OracleModel.from_inputs(win, inputs.make_inputs(win))
     steps = 0
     t0 = time.perf_counter()
     while True:
         m.step(1)
         steps += 1
         el = time.perf_counter() - t0
-        if el > 10.0 or steps >= 20 or el > max_seconds:
+        if el > seconds or steps >= 20:
             break
-    rate = metrics.cell_updates_per_second(win.nx, win.ny, win.nz, steps, el)
-    return {"value": rate, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{win.nx}x{win.ny}x{win.nz} window of the 1/12-degree basin (lon 150-170E, 10S-0), "
-                      f"{steps} steps, {el:.1f} s, FP64, one thread",
-            "sypd_at_full_size": metrics.sypd(w.dt, w.cells / rate)}
+    m.close()
+    return win.cells * steps, el, steps
+
+
+def cpu_baseline(w):
+    """The oracle as it stands (plain FP64 C, gcc -O2 -ffp-contract=off) on
+    bounded windows of the same 1/12-degree workload: one 240 x 120 column
+    window (all 100 levels) stepped for about 10 s on one thread, then one such
+    window per host core (at most 16, the host share of one GPU), each on its
+    own thread (the oracle is serial; ctypes releases the interpreter lock), for
+    about 10 s. The full grid is not run on the CPU."""
+    import concurrent.futures as cf
+
+    cu1, el1, st1 = _oracle_window_rate((w, 150.0, 10.0))
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    cores = max(1, min(16, ncpu))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        res = list(ex.map(_oracle_window_rate, [(w, 10.0 + 20.0 * q, 10.0) for q in range(cores)]))
+    wall = time.perf_counter() - t0
+    rate_all = sum(r[0] for r in res) / wall
+    return {"value": cu1 / el1, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"240x120x100 window of the 1/12-degree basin (150-170E, 10S-0), {st1} steps in {el1:.1f} s, "
+                      f"FP64, one thread, gcc -O2 -ffp-contract=off",
+            "all_cores": {"value": rate_all, "unit": "cell-updates/s", "cores": cores,
+                          "sample": f"{cores} windows of 240x120x100 (10S-0, 20 degrees apart), one per thread, "
+                                    f"{min(r[2] for r in res)}-{max(r[2] for r in res)} steps each in {wall:.1f} s"},
+            "cpu_model": _cpu_model(), "host_cpus": ncpu}
+
+
+def copy_probe(mib=1024, repeat=3):
+    """A plain device-to-device copy of known size, for calibrating the
+    memory-traffic counters: under a counter collector, the bytes the counters
+    report for the copy kernel are compared with the bytes it must move."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    x = torch.empty(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    for _ in range(repeat):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_floats": n, "bytes_read": 4 * n, "bytes_written": 4 * n, "repeat": repeat}))
+
+
+def _per_dispatch(path, counter, name_part):
+    """Counter values per dispatch of kernels whose name contains name_part, in dispatch order."""
+    import csv
+
+    vals = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") != counter or name_part not in r.get("Kernel_Name", ""):
+                continue
+            d = int(r.get("Dispatch_Id", r.get("Correlation_Id", 0)))
+            vals[d] = vals.get(d, 0.0) + float(r["Counter_Value"])
+    return [vals[d] for d in sorted(vals)]
+
+
+def pmc_summary(a):
+    """Per-launch HBM traffic of a kernel from the counter_collection.csv files
+    of four rocprofv3 runs: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the
+    benchmark and of the copy probe. The copy reads and writes a known number
+    of bytes; the ratio of those bytes to its counters scales the kernel's. The
+    record keeps the hash of the kernel's source so that a reader can tell
+    whether it still applies."""
+    cf_ = _per_dispatch(a.copy_fetch, "FETCH_SIZE", "copy")
+    cw_ = _per_dispatch(a.copy_write, "WRITE_SIZE", "copy")
+    kf = _per_dispatch(a.fetch, "FETCH_SIZE", a.name or a.kernel)
+    kw = _per_dispatch(a.write, "WRITE_SIZE", a.name or a.kernel)
+    if not (cf_ and cw_ and kf and kw):
+        raise SystemExit("missing dispatches in the counter files")
+    # the largest copy dispatch is the probe's copy; the last kernel dispatches are steady steps
+    f_scale = a.copy_bytes / (max(cf_) * 1024.0)
+    w_scale = a.copy_bytes / (max(cw_) * 1024.0)
+    tail = kf[-a.steady:], kw[-a.steady:]
+    fetch_b = sum(tail[0]) / len(tail[0]) * 1024.0 * f_scale
+    write_b = sum(tail[1]) / len(tail[1]) * 1024.0 * w_scale
+    rec = {"kernel": a.kernel, "dispatch_name_filter": a.name or a.kernel, "workload": a.workload,
+           "precision": a.precision,
+           "source_sha256_16": _src_hash(_kernel_src(a.kernel)),
+           "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw, "steady_dispatches_averaged": a.steady,
+           "copy_fetch_kib": max(cf_), "copy_write_kib": max(cw_), "copy_bytes": a.copy_bytes,
+           "fetch_scale": f_scale, "write_scale": w_scale,
+           "hbm_fetch_bytes_per_launch": fetch_b, "hbm_write_bytes_per_launch": write_b,
+           "hbm_bytes_per_launch": fetch_b + write_b, "commands": a.command}
+    with open(a.out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps({k: rec[k] for k in ("fetch_scale", "write_scale", "hbm_bytes_per_launch")}))
 
 
 def main():
@@ -302,7 +444,28 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble measurement")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the small-basin graph timing, the 1/4-degree runs and the copy bandwidth")
+    ap.add_argument("--copy-probe", action="store_true", help="run the counter-calibration copy and exit")
+    ap.add_argument("--mib", type=int, default=1024, help="copy probe: size of each buffer in MiB")
+    ap.add_argument("--pmc-summary", action="store_true", help="write a kernel's traffic record and exit")
+    ap.add_argument("--kernel", default="k_tend", choices=sorted(KERNEL_SOURCES))
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-fetch")
+    ap.add_argument("--copy-write")
+    ap.add_argument("--copy-bytes", type=float, help="bytes the copy kernel reads (= writes)")
+    ap.add_argument("--steady", type=int, default=1, help="pmc summary: average of the last N dispatches")
+    ap.add_argument("--name", help="pmc summary: substring of the dispatches' kernel name (default: --kernel)")
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--out")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        copy_probe(args.mib)
+        return
+    if args.pmc_summary:
+        pmc_summary(argparse.Namespace(**{**vars(args), "workload": args.workload}))
+        return
 
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -324,6 +487,8 @@ def main():
             "sypd": metrics.sypd(w.dt, ms * 1e-3),
             "stage_ms": {k: round(v, 4) for k, v in stages.items()},
             "finite": diag["nonfinite"] == 0,
+            "max_abs_u": diag["max_abs_u"],
+            "steps_taken": args.warmup + args.steps,
         }
         print(f"[bench] {prec}: {ms:.3f} ms/step, stages {results[prec]['stage_ms']}, "
               f"finite={diag['nonfinite'] == 0}", file=sys.stderr, flush=True)
@@ -343,7 +508,8 @@ def main():
         print(f"[bench] 1/4 degree: {extra['quarter']}", file=sys.stderr, flush=True)
 
     main_rec = results["fp32"]
-    roof, other = roofline(w, "fp32", main_rec["stage_ms"])
+    n_baro = -(-(w.n_substeps + w.n_substeps // 2) // 7)  # substeps per step in groups of 7 per launch
+    roof, other, stage_roofs = roofline(w, "fp32", main_rec["stage_ms"], n_baro)
     if "copy_gbs" in extra and roof["unit"] == "GB/s":
         roof["frac_of_measured_copy"] = round(roof["achieved"] / extra["copy_gbs"], 4)
     cpu = None
@@ -368,20 +534,30 @@ def main():
         "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "dt_s": w.dt, "n_substeps": w.n_substeps,
                    "halo": w.halo, "precision": "FP32 bulk, FP64 barotropic substeps, averages and sums"},
         "sypd": main_rec["sypd"],
+        "finite": main_rec["finite"],
+        "max_abs_u": main_rec["max_abs_u"],
+        "steps_taken": main_rec["steps_taken"],
         "stage_ms": main_rec["stage_ms"],
         "roofline": roof,
         "roofline_other_view": other,
+        "stage_rooflines": stage_roofs,
         "cpu_baseline": cpu,
     }
     if "fp64" in results:
         r64 = results["fp64"]
+        r64_main, _, r64_stages = roofline(w, "fp64", r64["stage_ms"], n_baro)
         line["fp64"] = {"value": r64["cell_updates_per_s"], "ms_per_step": r64["ms_per_step"], "sypd": r64["sypd"],
-                        "stage_ms": r64["stage_ms"], "roofline": roofline(w, "fp64", r64["stage_ms"])[0]}
+                        "finite": r64["finite"], "max_abs_u": r64["max_abs_u"],
+                        "stage_ms": r64["stage_ms"], "roofline": r64_main, "stage_rooflines": r64_stages}
         line["fp32_speedup_over_fp64"] = r64["ms_per_step"] / main_rec["ms_per_step"]
     if ens is not None:
         line["ensemble"] = ens
     line.update(extra)
     print(json.dumps(line), flush=True)
+    if not main_rec["finite"]:
+        print("[bench] the headline leg ended with non-finite values: its throughput is not a valid measurement",
+              file=sys.stderr, flush=True)
+        sys.exit(3)
 
 
 if __name__ == "__main__":

@@ -77,7 +77,7 @@ typedef struct ocn_grid_desc {
 typedef struct ocn_params {
     int32_t precision;        /* ocn_precision                                      */
     int32_t n_substeps;       /* barotropic substeps per step, >= 1                 */
-    int32_t baro_fuse;        /* substeps per barotropic launch: 0 = library default,
+    int32_t baro_fuse;        /* substeps per barotropic launch: 0 = library default (7),
                                  1 = one substep per launch pair, 2..8 = that many
                                  substeps per launch on an LDS tile whose halo is as
                                  wide as the substep count (the paper's wide
@@ -123,11 +123,37 @@ typedef enum {
                                  the face between layers k-1 and k; get returns 0 on
                                  dry faces (and the constant when no closure is
                                  attached); set only with a prescribed-field closure */
-    OCN_FIELD_VISC = 18       /* 3D momentum coefficient on tracer z-faces (m^2/s), get
+    OCN_FIELD_VISC = 18,      /* 3D momentum coefficient on tracer z-faces (m^2/s), get
                                  only: the viscosity of Richardson-number mixing, else
                                  the same as KAPPA; u and v faces take the mean of
                                  their two neighbouring columns */
+    OCN_FIELD_U_PRED = 19,    /* 3D AB2-predicted u* (m/s), output of the tendency stage */
+    OCN_FIELD_V_PRED = 20,    /* 3D AB2-predicted v* (m/s)                           */
+    OCN_FIELD_T_PRED = 21,    /* 3D AB2-predicted T* (degC)                          */
+    OCN_FIELD_GU_SLOW = 22,   /* 2D barotropic slow forcing: depth integral of the
+                                 AB2 u tendency (m^2/s^2), output of the tendency stage */
+    OCN_FIELD_GV_SLOW = 23    /* 2D the same for v                                   */
 } ocn_field;
+
+/* Stages of one step, in the order ocn_step runs them (paper Sec. 5.1-5.3;
+ * the order is a reading of the time-stepping sequence, whose figure the
+ * paper's text lacks):
+ *  MIXING      the face diffusivity diagnosed from the current state
+ *              (convective adjustment, Richardson-number mixing or the
+ *              network of an attached closure; nothing otherwise);
+ *  TENDENCY    w and hydrostatic pressure, the tendencies, the AB2 predictor
+ *              (U_PRED, V_PRED, T_PRED, new histories) and the slow forcing
+ *              (GU_SLOW, GV_SLOW);
+ *  BAROTROPIC  the substeps from ETA, UBT, VBT and the slow forcing (new ETA,
+ *              UBT, VBT and the window averages);
+ *  COLUMN      backward-Euler vertical diffusion of the predicted fields and
+ *              the depth-mean correction with UBT_MEAN, VBT_MEAN (new U, V, T). */
+typedef enum {
+    OCN_STAGE_MIXING = 0,
+    OCN_STAGE_TENDENCY = 1,
+    OCN_STAGE_BAROTROPIC = 2,
+    OCN_STAGE_COLUMN = 3
+} ocn_stage;
 
 typedef struct ocn_diag {
     int64_t step;             /* steps taken                                        */
@@ -141,7 +167,10 @@ typedef struct ocn_diag {
     double eta_min, eta_max;  /* over wet columns                                   */
     double cfl_adv;           /* max(|u| dt/dx, |v| dt/dy, |w| dt/dz)               */
     double wet_area;          /* sum A_c over wet columns (m^2)                     */
-    int64_t nonfinite;        /* non-finite values among u, v, T, eta, U, V         */
+    int64_t nonfinite;        /* cells with a non-finite u, v or T, plus columns with
+                                 a non-finite eta, U or V                           */
+    double cfl_bt;            /* barotropic CFL of a substep: max over wet columns of
+                                 sqrt(g H) (dt / n_substeps) sqrt(1/dx^2 + 1/dy^2)   */
 } ocn_diag;
 
 typedef struct ocn_grid ocn_grid;
@@ -198,6 +227,14 @@ int ocn_diagnostics(ocn_state* state, ocn_diag* out);
 /* Wait for all work enqueued on the state's stream. */
 int ocn_synchronize(ocn_state* state);
 
+/* Enqueue one stage of a step (ocn_stage) and nothing else: no step count,
+ * time or AB2 start flag changes (the flag is read by the TENDENCY stage).
+ * Running MIXING, TENDENCY, BAROTROPIC and COLUMN in turn enqueues the same
+ * kernels as one ocn_step. For stage-by-stage checks: set a stage's inputs
+ * (ocn_set_field), run it, read its outputs. OCN_E_INVALID for an unknown
+ * stage. Asynchronous. */
+int ocn_debug_run_stage(ocn_state* state, int32_t stage);
+
 /* Batched ensembles (many independent basins stepped together). An ensemble
  * holds n member states of possibly different grids but one ocn_params, laid
  * out in one caller arena of ocn_ensemble_arena_bytes. ocn_ensemble_step
@@ -213,8 +250,8 @@ int ocn_synchronize(ocn_state* state);
  * ocn_ensemble_member returns a borrowed handle of member m for the state
  * calls (set/get fields, diagnostics, checkpoints); do not destroy it.
  * ocn_ensemble_set_tiles selects the tendency workgroup rows (4 or 8; 0 =
- * precision default) and the barotropic substeps per launch (2..8; 0 =
- * default); every choice gives bitwise-identical results. ocn_ensemble_autotune
+ * precision default) and the barotropic substeps per launch (2..8; 0 = 7,
+ * the default); every choice gives bitwise-identical results. ocn_ensemble_autotune
  * times trial_steps steps of each choice, keeps the fastest, restores the
  * state it started from and reports the choice and its time per step. */
 typedef struct ocn_ensemble ocn_ensemble;

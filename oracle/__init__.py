@@ -17,17 +17,18 @@ ORC_ETA_MEAN, ORC_UBT_MEAN, ORC_VBT_MEAN, ORC_W = 6, 7, 8, 9
 ORC_GU_PREV, ORC_GV_PREV, ORC_GT_PREV = 10, 11, 12
 ORC_TAUX, ORC_TAUY, ORC_TSTAR, ORC_P, ORC_KAPPA, ORC_VISC = 13, 14, 15, 16, 17, 18
 TERM_ADV, TERM_COR, TERM_PGF, TERM_WIND, TERM_RESTORE, TERM_ALL = 1, 2, 4, 8, 16, 31
-NDIAG = 16
+NDIAG = 17
 DIAG_NAMES = ["step", "time", "tracer_content", "volume", "volume_mean", "kinetic_energy",
               "max_abs_u", "max_abs_v", "max_abs_w", "t_min", "t_max", "eta_min", "eta_max",
-              "nonfinite", "cfl_adv", "wet_area"]
+              "nonfinite", "cfl_adv", "wet_area", "cfl_bt"]
+STAGE_MIXING, STAGE_TENDENCY, STAGE_BAROTROPIC, STAGE_COLUMN = 0, 1, 2, 3
 
 FIELD_IDS = {"u": ORC_U, "v": ORC_V, "T": ORC_T, "eta": ORC_ETA, "U": ORC_UBT, "V": ORC_VBT,
              "eta_mean": ORC_ETA_MEAN, "U_mean": ORC_UBT_MEAN, "V_mean": ORC_VBT_MEAN,
              "w": ORC_W, "gu_prev": ORC_GU_PREV, "gv_prev": ORC_GV_PREV, "gt_prev": ORC_GT_PREV,
              "taux": ORC_TAUX, "tauy": ORC_TAUY, "tstar": ORC_TSTAR, "p": ORC_P, "kappa": ORC_KAPPA,
-             "visc": ORC_VISC}
-FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "p", "kappa", "visc"}
+             "visc": ORC_VISC, "u_pred": 19, "v_pred": 20, "T_pred": 21, "gU_slow": 22, "gV_slow": 23}
+FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "p", "kappa", "visc", "u_pred", "v_pred", "T_pred"}
 # Richardson-number mixing constants of the reading (Pacanowski and Philander 1981 form)
 RI_DEFAULTS = {"nu0": 1e-2, "alpha": 5.0, "nu_b": 1e-4, "kappa_b": 1e-5, "conv": 1.0}
 
@@ -65,6 +66,7 @@ def lib():
         L.orc_set_first_step.argtypes = [C.c_void_p, C.c_int]
         L.orc_get_first_step.argtypes = [C.c_void_p]
         L.orc_step.argtypes = [C.c_void_p, C.c_int]
+        L.orc_run_stage.argtypes = [C.c_void_p, C.c_int]
         L.orc_diagnostics.argtypes = [C.c_void_p, _D]
         L.orc_eval_tendencies.argtypes = [C.c_void_p, C.c_int, _D, _D, _D]
         for name in ("orc_weno5z",):
@@ -172,6 +174,11 @@ class OracleModel:
 
     def step(self, n: int = 1):
         lib().orc_step(self._h, int(n))
+
+    def run_stage(self, stage: int):
+        """One stage of a step (STAGE_*), without advancing the step count, time or start flag."""
+        if lib().orc_run_stage(self._h, int(stage)) != 0:
+            raise ValueError(stage)
 
     def diagnostics(self) -> dict:
         out = np.zeros(NDIAG, dtype=np.float64)

@@ -39,6 +39,8 @@ struct orc_model {
     double *eta, *U, *V; /* barotropic state: free surface (m), depth-integrated velocity (m^2/s) */
     double *gu_prev, *gv_prev, *gt_prev;      /* AB2 history */
     double *eta_mean, *U_mean, *V_mean;       /* substep averages of the last step */
+    double *us, *vs, *ts;                     /* AB2-predicted u*, v*, T* (tendency stage output) */
+    double *gU, *gV;                          /* barotropic slow forcing (tendency stage output) */
     double *taux, *tauy, *tstar;              /* surface forcing (N/m^2, N/m^2, degC) */
     double *kw;          /* prescribed diffusivity on z-faces (m^2/s), or NULL for the constant */
     double *kvw;         /* viscosity on z-faces for u and v, or NULL: they then use kw */
@@ -585,27 +587,22 @@ static void implicit_column(const orc_model* m, int kind, int i, int j, const do
 /* ------------------------------------------------------------------------- */
 /* One baroclinic step followed by the barotropic substeps. Stage order
  * (reading of the time-stepping sequence of Fig. 2, whose image is missing):
- * diagnostics w and p -> tendencies -> AB2 predictor -> implicit vertical
- * diffusion -> barotropic slow forcing -> substeps -> depth-mean correction. */
-static void step_once(orc_model* m) {
-    const int nx = m->nx, ny = m->ny, nz = m->nz;
-    const size_t n3 = (size_t)nx * ny * nz, n2 = (size_t)nx * ny;
-    const double dt = m->d.dt, chi = m->d.chi, eps = m->d.pgf_weight;
-    double* tfb = (double*)malloc(sizeof(double) * n3);
-    double* pfb = (double*)malloc(sizeof(double) * n3);
-    double* gu = (double*)malloc(sizeof(double) * n3);
-    double* gv = (double*)malloc(sizeof(double) * n3);
-    double* gt = (double*)malloc(sizeof(double) * n3);
-    double* us = (double*)malloc(sizeof(double) * n3);
-    double* vs = (double*)malloc(sizeof(double) * n3);
-    double* ts = (double*)malloc(sizeof(double) * n3);
-    double* gU = (double*)calloc(n2, sizeof(double));
-    double* gV = (double*)calloc(n2, sizeof(double));
+ * diffusivity diagnosis -> diagnostics w and p -> tendencies -> AB2 predictor
+ * and barotropic slow forcing -> substeps -> implicit vertical diffusion and
+ * depth-mean correction. The implicit diffusion of the predicted fields does
+ * not depend on the substeps, so it runs beside the correction that needs
+ * them. Each stage is also callable on its own (orc_run_stage). */
 
-    /* convective adjustment (a diffusivity diagnosed from the state at the
-     * start of the step, Sec. 5.1): kappa_conv on interior wet faces where the
-     * water above is denser than the water below (N^2 = g alpha dT/dz < 0),
-     * the constant elsewhere */
+/* Stage 0: the face diffusivity of convective adjustment or Richardson-number
+ * mixing, diagnosed from the state at the start of the step (Sec. 5.1: the
+ * diffusivity is a diagnostic of the current state). Nothing with the
+ * constant or a prescribed field. */
+static void stage_mixing(orc_model* m) {
+    const int nx = m->nx, ny = m->ny, nz = m->nz;
+    const size_t n3 = (size_t)nx * ny * nz;
+    /* convective adjustment: kappa_conv on interior wet faces where the water
+     * above is denser than the water below (N^2 = g alpha dT/dz < 0), the
+     * constant elsewhere */
     if (m->ri_on) richardson_faces(m);
     else if (m->kappa_conv > 0.0) {
         if (!m->kw) m->kw = (double*)malloc(sizeof(double) * n3);
@@ -618,6 +615,19 @@ static void step_once(orc_model* m) {
                     m->kw[id3(m, i, j, k)] = kap;
                 }
     }
+}
+
+/* Stage 1: tendencies, AB2 predictor (u*, v*, T*, new histories) and the
+ * barotropic slow forcing. */
+static void stage_tendency(orc_model* m) {
+    const int nx = m->nx, ny = m->ny, nz = m->nz;
+    const size_t n3 = (size_t)nx * ny * nz;
+    const double dt = m->d.dt, chi = m->d.chi, eps = m->d.pgf_weight;
+    double* tfb = (double*)malloc(sizeof(double) * n3);
+    double* pfb = (double*)malloc(sizeof(double) * n3);
+    double* gu = (double*)malloc(sizeof(double) * n3);
+    double* gv = (double*)malloc(sizeof(double) * n3);
+    double* gt = (double*)malloc(sizeof(double) * n3);
 
     /* tendencies G^n of the current state: advection, Coriolis, wind and
      * restoring; the baroclinic pressure gradient is added below */
@@ -628,7 +638,7 @@ static void step_once(orc_model* m) {
      * The tracer goes first: T* = T^n + dt Ghat_T. */
     for (size_t c = 0; c < n3; ++c) {
         const double ht = m->first_step ? gt[c] : (1.5 + chi) * gt[c] - (0.5 + chi) * m->gt_prev[c];
-        ts[c] = m->T[c] + dt * ht;
+        m->ts[c] = m->T[c] + dt * ht;
         tfb[c] = m->T[c] + eps * dt * ht;
         m->gt_prev[c] = gt[c];
     }
@@ -653,19 +663,11 @@ static void step_once(orc_model* m) {
                 m->gv_prev[c] = gv[c];
                 if (u_wet(m, i, j, k)) hu += pgf_u(m, pfb, i, j, k);
                 if (v_wet(m, i, j, k)) hv += pgf_v(m, pfb, i, j, k);
-                us[c] = m->u[c] + dt * hu;
-                vs[c] = m->v[c] + dt * hv;
+                m->us[c] = m->u[c] + dt * hu;
+                m->vs[c] = m->v[c] + dt * hv;
                 gu[c] = hu;  /* keep Ghat for the barotropic slow forcing */
                 gv[c] = hv;
             }
-
-    /* implicit vertical diffusion: phi** from phi* */
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            implicit_column(m, 0, i, j, ts, m->T);
-            implicit_column(m, 1, i, j, us, us);
-            implicit_column(m, 2, i, j, vs, vs);
-        }
 
     /* barotropic slow forcing: depth integral of the AB2 momentum tendency */
     for (int j = 0; j < ny; ++j)
@@ -675,102 +677,136 @@ static void step_once(orc_model* m) {
                 if (u_wet(m, i, j, k)) su += m->dz[k] * gu[id3(m, i, j, k)];
                 if (v_wet(m, i, j, k)) sv += m->dz[k] * gv[id3(m, i, j, k)];
             }
-            gU[id2(m, i, j)] = su;
-            gV[id2(m, i, j)] = sv;
+            m->gU[id2(m, i, j)] = su;
+            m->gV[id2(m, i, j)] = sv;
         }
+    free(tfb); free(pfb); free(gu); free(gv); free(gt);
+}
 
-    /* barotropic substeps (Sec. 5.3: explicit sub-cycling of the 2D mode).
-     * Reading: forward-backward, free surface first, then transports from the
-     * new surface gradient plus the slow forcing, dtau = dt/Ns. The substeps
-     * run on to t^n + 3dt/2 (M = Ns + Ns/2 of them); the new eta, U, V are the
-     * averages of eta^q, U^q, V^q (q = 1..M) with weights a_q proportional to
-     * cos^2(pi t), t = q/Ns - 1, |t| < 1/2, a window centred on t^{n+1}; the
-     * transport that moves the free surface over the step is
-     * Ubar = sum_l A_l U^l / Ns with A_l = sum_{q>l} a_q, so that
-     * eta^{n+1} - eta^n = -dt div Ubar exactly. */
-    {
-        const int ns = m->d.n_substeps, M = ns + ns / 2;
-        const double dtau = dt / ns, g = m->d.g, dy = dy_m(m);
-        double* en = (double*)malloc(sizeof(double) * n2);
-        double* Un = (double*)malloc(sizeof(double) * n2);
-        double* Vn = (double*)malloc(sizeof(double) * n2);
-        double* Hu = (double*)malloc(sizeof(double) * n2);
-        double* Hv = (double*)malloc(sizeof(double) * n2);
-        double* sU = (double*)calloc(n2, sizeof(double));   /* sum_l A_l U^l */
-        double* sV = (double*)calloc(n2, sizeof(double));
-        double* fE = (double*)calloc(n2, sizeof(double));   /* sum_q a_q eta^q */
-        double* fU = (double*)calloc(n2, sizeof(double));
-        double* fV = (double*)calloc(n2, sizeof(double));
-        double* a = (double*)calloc((size_t)M + 1, sizeof(double));
-        double asum = 0.0;
-        for (int q = 1; q <= M; ++q) {
-            const double t = (double)q / ns - 1.0;
-            const double c = fabs(t) < 0.5 ? cos(PI * t) : 0.0;
-            a[q] = c * c;
-            asum += a[q];
-        }
-        for (int q = 1; q <= M; ++q) a[q] /= asum;
-        for (int j = 0; j < ny; ++j)
-            for (int i = 0; i < nx; ++i) { Hu[id2(m, i, j)] = depth_u(m, i, j); Hv[id2(m, i, j)] = depth_v(m, i, j); }
-        for (int l = 0; l < M; ++l) {
-            double Al = 0.0;
-            for (int q = l + 1; q <= M; ++q) Al += a[q];
-            for (int j = 0; j < ny; ++j)
-                for (int i = 0; i < nx; ++i) {
-                    double div = dy * (at2(m, m->U, i + 1, j) - at2(m, m->U, i, j))
-                               + dx_v(m, j + 1) * at2(m, m->V, i, j + 1) - dx_v(m, j) * at2(m, m->V, i, j);
-                    en[id2(m, i, j)] = m->eta[id2(m, i, j)] - dtau / area_c(m, j) * div;
-                    sU[id2(m, i, j)] += Al * m->U[id2(m, i, j)];
-                    sV[id2(m, i, j)] += Al * m->V[id2(m, i, j)];
-                }
-            for (int j = 0; j < ny; ++j)
-                for (int i = 0; i < nx; ++i) {
-                    size_t c = id2(m, i, j);
-                    double hu = Hu[c], hv = Hv[c];
-                    Un[c] = hu > 0.0 ? m->U[c] + dtau * (-g * hu * (en[c] - at2(m, en, i - 1, j)) / dx_c(m, j) + gU[c]) : 0.0;
-                    Vn[c] = hv > 0.0 ? m->V[c] + dtau * (-g * hv * (en[c] - at2(m, en, i, j - 1)) / dy + gV[c]) : 0.0;
-                }
-            for (size_t c = 0; c < n2; ++c) {
-                m->eta[c] = en[c];
-                m->U[c] = Un[c];
-                m->V[c] = Vn[c];
-                fE[c] += a[l + 1] * en[c];
-                fU[c] += a[l + 1] * Un[c];
-                fV[c] += a[l + 1] * Vn[c];
-            }
-        }
-        for (size_t c = 0; c < n2; ++c) {
-            m->eta[c] = fE[c];
-            m->U[c] = fU[c];
-            m->V[c] = fV[c];
-            m->eta_mean[c] = fE[c];
-            m->U_mean[c] = sU[c] / ns;
-            m->V_mean[c] = sV[c] / ns;
-        }
-        /* depth-mean correction: replace the depth mean of u** by Ubar/H, the
-         * transport that moved the free surface over the step, so
-         * sum dz u^{n+1} = Ubar exactly. */
+/* Stage 2: barotropic substeps (Sec. 5.3: explicit sub-cycling of the 2D
+ * mode). Reading: forward-backward, free surface first, then transports from
+ * the new surface gradient plus the slow forcing, dtau = dt/Ns. The substeps
+ * run on to t^n + 3dt/2 (M = Ns + Ns/2 of them); the new eta, U, V are the
+ * averages of eta^q, U^q, V^q (q = 1..M) with weights a_q proportional to
+ * cos^2(pi t), t = q/Ns - 1, |t| < 1/2, a window centred on t^{n+1}; the
+ * transport that moves the free surface over the step is
+ * Ubar = sum_l A_l U^l / Ns with A_l = sum_{q>l} a_q, so that
+ * eta^{n+1} - eta^n = -dt div Ubar exactly. */
+static void stage_barotropic(orc_model* m) {
+    const int nx = m->nx, ny = m->ny;
+    const size_t n2 = (size_t)nx * ny;
+    const int ns = m->d.n_substeps, M = ns + ns / 2;
+    const double dt = m->d.dt, dtau = dt / ns, g = m->d.g, dy = dy_m(m);
+    double* en = (double*)malloc(sizeof(double) * n2);
+    double* Un = (double*)malloc(sizeof(double) * n2);
+    double* Vn = (double*)malloc(sizeof(double) * n2);
+    double* Hu = (double*)malloc(sizeof(double) * n2);
+    double* Hv = (double*)malloc(sizeof(double) * n2);
+    double* sU = (double*)calloc(n2, sizeof(double));   /* sum_l A_l U^l */
+    double* sV = (double*)calloc(n2, sizeof(double));
+    double* fE = (double*)calloc(n2, sizeof(double));   /* sum_q a_q eta^q */
+    double* fU = (double*)calloc(n2, sizeof(double));
+    double* fV = (double*)calloc(n2, sizeof(double));
+    double* a = (double*)calloc((size_t)M + 1, sizeof(double));
+    double asum = 0.0;
+    for (int q = 1; q <= M; ++q) {
+        const double t = (double)q / ns - 1.0;
+        const double c = fabs(t) < 0.5 ? cos(PI * t) : 0.0;
+        a[q] = c * c;
+        asum += a[q];
+    }
+    for (int q = 1; q <= M; ++q) a[q] /= asum;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) { Hu[id2(m, i, j)] = depth_u(m, i, j); Hv[id2(m, i, j)] = depth_v(m, i, j); }
+    for (int l = 0; l < M; ++l) {
+        double Al = 0.0;
+        for (int q = l + 1; q <= M; ++q) Al += a[q];
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
-                size_t c2 = id2(m, i, j);
-                double su = 0.0, sv = 0.0;
-                for (int k = 0; k < nz; ++k) {
-                    if (u_wet(m, i, j, k)) su += m->dz[k] * us[id3(m, i, j, k)];
-                    if (v_wet(m, i, j, k)) sv += m->dz[k] * vs[id3(m, i, j, k)];
-                }
-                for (int k = 0; k < nz; ++k) {
-                    size_t c = id3(m, i, j, k);
-                    m->u[c] = (Hu[c2] > 0.0 && u_wet(m, i, j, k)) ? us[c] + (m->U_mean[c2] - su) / Hu[c2] : 0.0;
-                    m->v[c] = (Hv[c2] > 0.0 && v_wet(m, i, j, k)) ? vs[c] + (m->V_mean[c2] - sv) / Hv[c2] : 0.0;
-                }
+                double div = dy * (at2(m, m->U, i + 1, j) - at2(m, m->U, i, j))
+                           + dx_v(m, j + 1) * at2(m, m->V, i, j + 1) - dx_v(m, j) * at2(m, m->V, i, j);
+                en[id2(m, i, j)] = m->eta[id2(m, i, j)] - dtau / area_c(m, j) * div;
+                sU[id2(m, i, j)] += Al * m->U[id2(m, i, j)];
+                sV[id2(m, i, j)] += Al * m->V[id2(m, i, j)];
             }
-        free(en); free(Un); free(Vn); free(Hu); free(Hv); free(sU); free(sV); free(fE); free(fU); free(fV); free(a);
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = id2(m, i, j);
+                double hu = Hu[c], hv = Hv[c];
+                Un[c] = hu > 0.0 ? m->U[c] + dtau * (-g * hu * (en[c] - at2(m, en, i - 1, j)) / dx_c(m, j) + m->gU[c]) : 0.0;
+                Vn[c] = hv > 0.0 ? m->V[c] + dtau * (-g * hv * (en[c] - at2(m, en, i, j - 1)) / dy + m->gV[c]) : 0.0;
+            }
+        for (size_t c = 0; c < n2; ++c) {
+            m->eta[c] = en[c];
+            m->U[c] = Un[c];
+            m->V[c] = Vn[c];
+            fE[c] += a[l + 1] * en[c];
+            fU[c] += a[l + 1] * Un[c];
+            fV[c] += a[l + 1] * Vn[c];
+        }
     }
+    for (size_t c = 0; c < n2; ++c) {
+        m->eta[c] = fE[c];
+        m->U[c] = fU[c];
+        m->V[c] = fV[c];
+        m->eta_mean[c] = fE[c];
+        m->U_mean[c] = sU[c] / ns;
+        m->V_mean[c] = sV[c] / ns;
+    }
+    free(en); free(Un); free(Vn); free(Hu); free(Hv); free(sU); free(sV); free(fE); free(fU); free(fV); free(a);
+}
 
+/* Stage 3: implicit vertical diffusion of the predicted fields, then the
+ * depth-mean correction: the depth mean of u** is replaced by Ubar/H, the
+ * transport that moved the free surface over the step, so
+ * sum dz u^{n+1} = Ubar exactly. */
+static void stage_column(orc_model* m) {
+    const int nx = m->nx, ny = m->ny, nz = m->nz;
+    const size_t n3 = (size_t)nx * ny * nz;
+    double* uss = (double*)malloc(sizeof(double) * n3);
+    double* vss = (double*)malloc(sizeof(double) * n3);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            implicit_column(m, 0, i, j, m->ts, m->T);
+            implicit_column(m, 1, i, j, m->us, uss);
+            implicit_column(m, 2, i, j, m->vs, vss);
+        }
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const size_t c2 = id2(m, i, j);
+            const double hu = depth_u(m, i, j), hv = depth_v(m, i, j);
+            double su = 0.0, sv = 0.0;
+            for (int k = 0; k < nz; ++k) {
+                if (u_wet(m, i, j, k)) su += m->dz[k] * uss[id3(m, i, j, k)];
+                if (v_wet(m, i, j, k)) sv += m->dz[k] * vss[id3(m, i, j, k)];
+            }
+            for (int k = 0; k < nz; ++k) {
+                size_t c = id3(m, i, j, k);
+                m->u[c] = (hu > 0.0 && u_wet(m, i, j, k)) ? uss[c] + (m->U_mean[c2] - su) / hu : 0.0;
+                m->v[c] = (hv > 0.0 && v_wet(m, i, j, k)) ? vss[c] + (m->V_mean[c2] - sv) / hv : 0.0;
+            }
+        }
+    free(uss); free(vss);
+}
+
+int orc_run_stage(orc_model* m, int stage) {
+    switch (stage) {
+    case ORC_STAGE_MIXING: stage_mixing(m); return 0;
+    case ORC_STAGE_TENDENCY: stage_tendency(m); return 0;
+    case ORC_STAGE_BAROTROPIC: stage_barotropic(m); return 0;
+    case ORC_STAGE_COLUMN: stage_column(m); return 0;
+    default: return -1;
+    }
+}
+
+static void step_once(orc_model* m) {
+    stage_mixing(m);
+    stage_tendency(m);
+    stage_barotropic(m);
+    stage_column(m);
     m->first_step = 0;
     m->step += 1;
-    m->time += dt;
-    free(gu); free(gv); free(gt); free(us); free(vs); free(ts); free(gU); free(gV); free(tfb); free(pfb);
+    m->time += m->d.dt;
 }
 
 void orc_step(orc_model* m, int n) {
@@ -784,7 +820,8 @@ void orc_step(orc_model* m, int n) {
  * [6] max|u|, [7] max|v|, [8] max|w| on interior wet faces, [9] T min, [10] T max
  * (wet cells), [11] eta min, [12] eta max (wet columns), [13] non-finite count,
  * [14] advective CFL max(|u| dt/dx, |v| dt/dy, |w| dt/dz_c), [15] sum of A_c
- * over wet columns. */
+ * over wet columns, [16] barotropic CFL of a substep max sqrt(g H) dtau
+ * sqrt(1/dx^2 + 1/dy^2) over wet columns. */
 void orc_diagnostics(const orc_model* m, double* out) {
     const int nx = m->nx, ny = m->ny, nz = m->nz;
     const size_t n3 = (size_t)nx * ny * nz, n2 = (size_t)nx * ny;
@@ -857,6 +894,21 @@ void orc_diagnostics(const orc_model* m, double* out) {
         for (int i = 0; i < nx; ++i)
             if (m->kb[id2(m, i, j)] > 0) buf[n++] = area_c(m, j);
     out[15] = orc_neumaier_sum(buf, (int64_t)n);
+    /* barotropic gravity-wave CFL of a substep: sqrt(g H) dtau sqrt(1/dx^2 + 1/dy^2)
+     * over wet columns, H the column's depth */
+    double cflbt = 0.0;
+    const double dtau = dt / m->d.n_substeps;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const int kb = m->kb[id2(m, i, j)];
+            if (kb <= 0) continue;
+            double hc = 0.0;
+            for (int k = nz - kb; k < nz; ++k) hc += m->dz[k];
+            const double dxc = dx_c(m, j);
+            const double c = sqrt(m->d.g * hc) * dtau * sqrt(1.0 / (dxc * dxc) + 1.0 / (dy * dy));
+            if (c > cflbt) cflbt = c;
+        }
+    out[16] = cflbt;
 
     out[0] = (double)m->step;
     out[1] = m->time;
@@ -883,9 +935,10 @@ orc_model* orc_create(const orc_desc* d, const double* dz, const int32_t* kbotto
         int32_t kb = kbottom ? kbottom[c] : m->nz;
         m->kb[c] = kb < 0 ? 0 : (kb > m->nz ? m->nz : kb);
     }
-    double** f3[] = {&m->u, &m->v, &m->T, &m->gu_prev, &m->gv_prev, &m->gt_prev};
+    double** f3[] = {&m->u, &m->v, &m->T, &m->gu_prev, &m->gv_prev, &m->gt_prev, &m->us, &m->vs, &m->ts};
     for (size_t q = 0; q < sizeof(f3) / sizeof(f3[0]); ++q) *f3[q] = (double*)calloc(n3, sizeof(double));
-    double** f2[] = {&m->eta, &m->U, &m->V, &m->eta_mean, &m->U_mean, &m->V_mean, &m->taux, &m->tauy, &m->tstar};
+    double** f2[] = {&m->eta, &m->U, &m->V, &m->eta_mean, &m->U_mean, &m->V_mean, &m->taux, &m->tauy, &m->tstar,
+                     &m->gU, &m->gV};
     for (size_t q = 0; q < sizeof(f2) / sizeof(f2[0]); ++q) *f2[q] = (double*)calloc(n2, sizeof(double));
     m->first_step = 1;
     return m;
@@ -894,7 +947,8 @@ orc_model* orc_create(const orc_desc* d, const double* dz, const int32_t* kbotto
 void orc_destroy(orc_model* m) {
     if (!m) return;
     double* all[] = {m->dz, m->u, m->v, m->T, m->gu_prev, m->gv_prev, m->gt_prev, m->eta, m->U, m->V,
-                     m->eta_mean, m->U_mean, m->V_mean, m->taux, m->tauy, m->tstar, m->kw, m->kvw};
+                     m->eta_mean, m->U_mean, m->V_mean, m->taux, m->tauy, m->tstar, m->kw, m->kvw,
+                     m->us, m->vs, m->ts, m->gU, m->gV};
     for (size_t q = 0; q < sizeof(all) / sizeof(all[0]); ++q) free(all[q]);
     free(m->kb);
     free(m);
@@ -918,6 +972,11 @@ static double* field_ptr(orc_model* m, int f, size_t* n) {
     case ORC_TAUX: *n = n2; return m->taux;
     case ORC_TAUY: *n = n2; return m->tauy;
     case ORC_TSTAR: *n = n2; return m->tstar;
+    case ORC_U_PRED: *n = n3; return m->us;
+    case ORC_V_PRED: *n = n3; return m->vs;
+    case ORC_T_PRED: *n = n3; return m->ts;
+    case ORC_GU_SLOW: *n = n2; return m->gU;
+    case ORC_GV_SLOW: *n = n2; return m->gV;
     default: return NULL;
     }
 }

@@ -49,16 +49,25 @@ enum {
     ORC_TAUX = 13, ORC_TAUY = 14, ORC_TSTAR = 15, ORC_P = 16,
     ORC_KAPPA = 17,  /* z-face diffusivity, nz*ny*nx, slot k = face between layers k-1 and k;
                         setting NULL returns to the constant */
-    ORC_VISC = 18    /* z-face momentum coefficient on tracer faces (get only): the viscosity
+    ORC_VISC = 18,   /* z-face momentum coefficient on tracer faces (get only): the viscosity
                         of Richardson-number mixing, else the diffusivity */
+    ORC_U_PRED = 19, ORC_V_PRED = 20, ORC_T_PRED = 21,  /* AB2-predicted u*, v*, T* */
+    ORC_GU_SLOW = 22, ORC_GV_SLOW = 23                  /* barotropic slow forcing (m^2/s^2) */
 };
+
+/* Stages of one step, in order (orc_run_stage): the diffusivity diagnosis of
+ * convective or Richardson-number mixing; tendencies, AB2 predictor and slow
+ * forcing; barotropic substeps; implicit vertical diffusion and depth-mean
+ * correction. orc_step runs all four and then advances the step count, the
+ * time and the AB2 start flag; orc_run_stage does not. */
+enum { ORC_STAGE_MIXING = 0, ORC_STAGE_TENDENCY = 1, ORC_STAGE_BAROTROPIC = 2, ORC_STAGE_COLUMN = 3 };
 
 /* Tendency term selectors for orc_eval_tendencies. */
 enum { ORC_TERM_ADV = 1, ORC_TERM_COR = 2, ORC_TERM_PGF = 4, ORC_TERM_WIND = 8,
        ORC_TERM_RESTORE = 16, ORC_TERM_ALL = 31 };
 
 /* Number of doubles written by orc_diagnostics. */
-#define ORC_NDIAG 16
+#define ORC_NDIAG 17
 
 orc_model* orc_create(const orc_desc* d, const double* dz, const int32_t* kbottom);
 void       orc_destroy(orc_model* m);
@@ -77,6 +86,7 @@ void       orc_set_convective(orc_model* m, double kappa_conv);
 void       orc_set_richardson(orc_model* m, double nu0, double alpha, double nub, double kappab, double conv);
 int        orc_get_first_step(const orc_model* m);
 void       orc_step(orc_model* m, int n);
+int        orc_run_stage(orc_model* m, int stage);
 void       orc_diagnostics(const orc_model* m, double* out);
 
 /* Stage-level entry points used by the physics and unit pins. */

@@ -14,6 +14,7 @@
 #include "ocn_dev.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace ocn {
 
@@ -100,15 +101,24 @@ hipError_t launch_barotropic(const DevState& s, hipStream_t st) {
 
 namespace ocn {
 
-// Temporally blocked substeps: one launch advances s substeps of a 64 x 32
-// (or, on small grids, 32 x 16) tile held in LDS with an s-wide halo. Each substep the region of correct
-// values shrinks by one cell on every side, so after s substeps the tile
-// interior is exact; the halo cells are recomputed redundantly instead of
-// exchanged. Every point carries the same arithmetic as the one-substep path.
-// A tile's halo is its neighbours' interior, which they overwrite during the
-// same launch, so launches read one buffer of eta, U, V and write the other
-// (parity selects which); after an odd number of launches a copy kernel
-// returns the result to the primary buffers.
+// Temporally blocked substeps: one launch advances SH substeps of a 64 x 32
+// (or, on small grids, 32 x 16) tile held in LDS with an SH-wide halo (the
+// halo width is a template parameter, so the LDS of a launch is sized to its
+// substep count). Each substep the region of correct values shrinks by one
+// cell on every side, so after SH substeps the tile interior is exact; the
+// halo cells are recomputed redundantly instead of exchanged. Every point
+// carries the same arithmetic as the one-substep path. A tile's halo is its
+// neighbours' interior, which they overwrite during the same launch, so
+// launches read one buffer of eta, U, V and write the other (parity selects
+// which); after an odd number of launches a copy kernel returns the result to
+// the primary buffers.
+//
+// Within a substep each thread updates its own points in place: the surface
+// update reads a point's own eta and its neighbours' transports, the
+// transport update its own transports and its neighbours' eta, so two
+// barriers per substep suffice (after each update). The window sums of the
+// interior points read eta after the first barrier and U, V after the
+// second, while no thread writes them.
 constexpr int FSMAX = 8, FT = 512;
 // Tile shapes: kBaroTileX x kBaroTileY for large grids and the ensembles;
 // 32 x 16 for grids with fewer large tiles than CUs, where the number of
@@ -120,13 +130,12 @@ constexpr int kManyTiles = 256;
 // Registers hold only what each halo-inclusive point needs every substep
 // (depths and slow forcing); row metrics sit in small LDS tables, and the
 // window sums live with a second mapping over the interior points only (FI
-// per thread), read from LDS between the barriers the substep has anyway.
-template <int BX, int BY>
+// per thread).
+template <int BX, int BY, int SH>
 __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const int by, const double dtau,
-                                          const int m0, const int s, const int first, const int last,
-                                          const int parity) {
+                                          const int m0, const int first, const int last, const int parity) {
     constexpr int FBX = BX, FBY = BY;
-    constexpr int FEW = FBX + 2 * FSMAX, FEH = FBY + 2 * FSMAX, FEN = FEW * FEH;
+    constexpr int FEW = FBX + 2 * SH, FEH = FBY + 2 * SH, FEN = FEW * FEH;
     constexpr int FQ = (FEN + FT - 1) / FT;  // halo-inclusive points per thread
     constexpr int FI = FBX * FBY / FT;       // interior points per thread
     static_assert(FBX * FBY % FT == 0, "interior points must divide evenly over the threads");
@@ -140,13 +149,11 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
     double* __restrict__ outV = parity ? S.vbt : S.vbt2;
     const int tid = threadIdx.x;
     const int i0 = bx * FBX, j0 = by * FBY;
-    const int ew = FBX + 2 * s;  // extent of this launch's tile (row stride stays FEW)
-    const int eh = FBY + 2 * s;
     const int nx = S.nx, ny = S.ny;
 
     // row metrics (rows past a closed edge take the nearest row; unused)
-    for (int lj = tid; lj < eh; lj += FT) {
-        int gj = j0 - s + lj;
+    for (int lj = tid; lj < FEH; lj += FT) {
+        int gj = j0 - SH + lj;
         if (S.periodic_y) gj = ((gj % ny) + ny) % ny;
         const int jm = min(max(gj, 0), ny - 1);
         sRdxc[lj] = 1.0 / S.dxc[jm];
@@ -160,9 +167,8 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
     for (int q = 0; q < FQ; ++q) {
         const int e = tid + q * FT;
         const int li = e % FEW, lj = e / FEW;
-        const bool in_tile = (e < FEN) && (li < ew) && (lj < eh);
-        int gi = i0 - s + li, gj = j0 - s + lj;
-        bool inside = in_tile;
+        int gi = i0 - SH + li, gj = j0 - SH + lj;
+        bool inside = e < FEN;
         if (S.periodic_x) gi = ((gi % nx) + nx) % nx;
         else inside = inside && gi >= 0 && gi < nx;
         if (S.periodic_y) gj = ((gj % ny) + ny) % ny;
@@ -188,7 +194,7 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
         const int pp = tid + p * FT;
         const int ti = i0 + pp % FBX, tj = j0 + pp / FBX;
         const bool live = ti < nx && tj < ny;
-        ie[p] = live ? (s + pp / FBX) * FEW + s + pp % FBX : -1;
+        ie[p] = live ? (SH + pp / FBX) * FEW + SH + pp % FBX : -1;
         const long long c = idx2(S, live ? ti : 0, live ? tj : 0);
         const bool carry = live && !first;
         aU[p] = carry ? S.su[c] : 0.0;
@@ -198,65 +204,69 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
         fV[p] = carry ? S.sfv[c] : 0.0;
     }
     __syncthreads();
+    // the transport sum takes U^l at the start of each substep l
+    {
+        const double A0 = S.baro_A[m0];
+#pragma unroll
+        for (int p = 0; p < FI; ++p) {
+            if (ie[p] < 0) continue;
+            aU[p] += A0 * sU[ie[p]];
+            aV[p] += A0 * sV[ie[p]];
+        }
+    }
 
     const double dy = S.dy, g = S.g;
-    for (int m = 0; m < s; ++m) {
-        const double Am = S.baro_A[m0 + m], am = S.baro_a[m0 + m + 1];
-        // free surface from the divergence of the transports
-        double en[FQ];
+    int tq = tid;
+    for (int m = 0; m < SH; ++m) {
+        // each point's LDS neighbours are recomputed from the thread index every
+        // substep (a few integer operations) rather than kept in registers
+        asm volatile("" : "+v"(tq));
+        const double am = S.baro_a[m0 + m + 1];
+        // free surface from the divergence of the transports, in place
 #pragma unroll
         for (int q = 0; q < FQ; ++q) {
-            const int e = tid + q * FT;
-            en[q] = 0.0;
+            const int e = tq + q * FT;
             if (e < FEN) {
                 const int li = e % FEW, lj = e / FEW;
-                const int ee = (li + 1 < ew) ? e + 1 : e;    // tile edge: garbage stays in the halo
-                const int en_ = (lj + 1 < eh) ? e + FEW : e;
+                const int ee = (li + 1 < FEW) ? e + 1 : e;    // tile edge: garbage stays in the halo
+                const int en_ = (lj + 1 < FEH) ? e + FEW : e;
                 const double div = dy * (sU[ee] - sU[e]) + sDxv1[lj] * sV[en_] - sDxv0[lj] * sV[e];
-                en[q] = sE[e] - dtau * sRarea[lj] * div;
+                sE[e] = sE[e] - dtau * sRarea[lj] * div;
             }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < FQ; ++q) {
-            const int e = tid + q * FT;
-            if (e < FEN) sE[e] = en[q];
         }
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < FI; ++p) {
             if (ie[p] < 0) continue;
-            aU[p] += Am * sU[ie[p]];
-            aV[p] += Am * sV[ie[p]];
             fE[p] += am * sE[ie[p]];
         }
-        // transports from the new surface slope plus the slow forcing
-        double un[FQ], vn[FQ];
+        // transports from the new surface slope plus the slow forcing, in place
 #pragma unroll
         for (int q = 0; q < FQ; ++q) {
-            const int e = tid + q * FT;
-            un[q] = 0.0;
-            vn[q] = 0.0;
+            const int e = tq + q * FT;
             if (e < FEN) {
                 const int li = e % FEW, lj = e / FEW;
                 const int ew_ = (li >= 1) ? e - 1 : e;
                 const int es_ = (lj >= 1) ? e - FEW : e;
-                un[q] = Hu[q] > 0.0 ? sU[e] + dtau * (-g * Hu[q] * (sE[e] - sE[ew_]) * sRdxc[lj] + gU[q]) : 0.0;
-                vn[q] = Hv[q] > 0.0 ? sV[e] + dtau * (-g * Hv[q] * (sE[e] - sE[es_]) / dy + gV[q]) : 0.0;
+                const double hu = Hu[q], hv = Hv[q];
+                const double un = hu > 0.0 ? sU[e] + dtau * (-g * hu * (sE[e] - sE[ew_]) * sRdxc[lj] + gU[q]) : 0.0;
+                const double vn = hv > 0.0 ? sV[e] + dtau * (-g * hv * (sE[e] - sE[es_]) / dy + gV[q]) : 0.0;
+                sU[e] = un;
+                sV[e] = vn;
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int q = 0; q < FQ; ++q) {
-            const int e = tid + q * FT;
-            if (e < FEN) { sU[e] = un[q]; sV[e] = vn[q]; }
-        }
-        __syncthreads();
+        const double An = (m + 1 < SH) ? S.baro_A[m0 + m + 1] : 0.0;
 #pragma unroll
         for (int p = 0; p < FI; ++p) {
             if (ie[p] < 0) continue;
-            fU[p] += am * sU[ie[p]];
-            fV[p] += am * sV[ie[p]];
+            const double u = sU[ie[p]], v = sV[ie[p]];
+            fU[p] += am * u;
+            fV[p] += am * v;
+            if (m + 1 < SH) {
+                aU[p] += An * u;
+                aV[p] += An * v;
+            }
         }
     }
 
@@ -296,10 +306,10 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
     }
 }
 
-template <int BX, int BY>
-__global__ __launch_bounds__(FT) void k_baro_fused(const DevState S, const double dtau, const int m0, const int s,
+template <int BX, int BY, int SH>
+__global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(4))) void k_baro_fused(const DevState S, const double dtau, const int m0,
                                                    const int first, const int last, const int parity) {
-    baro_tile<BX, BY>(S, blockIdx.x, blockIdx.y, dtau, m0, s, first, last, parity);
+    baro_tile<BX, BY, SH>(S, blockIdx.x, blockIdx.y, dtau, m0, first, last, parity);
 }
 
 // Second buffers back to the primary ones (whole padded arrays, halos included).
@@ -325,12 +335,29 @@ __global__ __launch_bounds__(256) void k_baro_copyback_batched(const DevState* _
 }
 
 // Ensemble: entry blockIdx.x of the table is (member, bx, by).
+template <int SH>
 __global__ __launch_bounds__(FT) void k_baro_fused_batched(const DevState* __restrict__ members,
                                                            const int4* __restrict__ tiles, const double dtau,
-                                                           const int m0, const int s, const int first,
-                                                           const int last, const int parity) {
+                                                           const int m0, const int first, const int last,
+                                                           const int parity) {
     const int4 e = tiles[blockIdx.x];
-    baro_tile<kBaroTileX, kBaroTileY>(members[e.x], e.y, e.z, dtau, m0, s, first, last, parity);
+    baro_tile<kBaroTileX, kBaroTileY, SH>(members[e.x], e.y, e.z, dtau, m0, first, last, parity);
+}
+
+// Instantiations per halo width 1..FSMAX: f<SH>() launches the kernel of that width.
+template <class F>
+hipError_t by_halo(int s, F&& f) {
+    switch (s) {
+    case 1: return f(std::integral_constant<int, 1>());
+    case 2: return f(std::integral_constant<int, 2>());
+    case 3: return f(std::integral_constant<int, 3>());
+    case 4: return f(std::integral_constant<int, 4>());
+    case 5: return f(std::integral_constant<int, 5>());
+    case 6: return f(std::integral_constant<int, 6>());
+    case 7: return f(std::integral_constant<int, 7>());
+    case 8: return f(std::integral_constant<int, 8>());
+    default: return hipErrorInvalidValue;
+    }
 }
 
 int baro_substeps(int n_substeps) { return n_substeps + n_substeps / 2; }
@@ -344,8 +371,14 @@ hipError_t launch_barotropic_batched(const DevState* members, int n_members, con
     int parity = 0;
     for (int m0 = 0; m0 < M; m0 += sub, parity ^= 1) {
         const int ss = std::min(sub, M - m0);
-        hipLaunchKernelGGL(k_baro_fused_batched, dim3(ntiles), dim3(FT), 0, st, members, tiles, dtau, m0, ss,
-                           (int)(m0 == 0), (int)(m0 + ss == M), parity);
+        const int first = m0 == 0, last = m0 + ss == M;
+        hipError_t e = by_halo(ss, [&](auto h) {
+            constexpr int SH = decltype(h)::value;
+            hipLaunchKernelGGL((k_baro_fused_batched<SH>), dim3(ntiles), dim3(FT), 0, st, members, tiles, dtau, m0,
+                               first, last, parity);
+            return hipSuccess;
+        });
+        if (e != hipSuccess) return e;
     }
     if (parity) {  // the result sits in the second buffers
         for (int m0 = 0; m0 < n_members; m0 += 65535)
@@ -366,12 +399,18 @@ hipError_t launch_barotropic_fused(const DevState& s, hipStream_t st) {
     int parity = 0;
     for (int m0 = 0; m0 < M; m0 += sub, parity ^= 1) {
         const int ss = std::min(sub, M - m0);
-        if (small)
-            hipLaunchKernelGGL((k_baro_fused<kSmallTileX, kSmallTileY>), grid, dim3(FT), 0, st, s, dtau, m0, ss,
-                               (int)(m0 == 0), (int)(m0 + ss == M), parity);
-        else
-            hipLaunchKernelGGL((k_baro_fused<kBaroTileX, kBaroTileY>), grid, dim3(FT), 0, st, s, dtau, m0, ss,
-                               (int)(m0 == 0), (int)(m0 + ss == M), parity);
+        const int first = m0 == 0, last = m0 + ss == M;
+        hipError_t e = by_halo(ss, [&](auto h) {
+            constexpr int SH = decltype(h)::value;
+            if (small)
+                hipLaunchKernelGGL((k_baro_fused<kSmallTileX, kSmallTileY, SH>), grid, dim3(FT), 0, st, s, dtau, m0,
+                                   first, last, parity);
+            else
+                hipLaunchKernelGGL((k_baro_fused<kBaroTileX, kBaroTileY, SH>), grid, dim3(FT), 0, st, s, dtau, m0,
+                                   first, last, parity);
+            return hipSuccess;
+        });
+        if (e != hipSuccess) return e;
     }
     if (parity) {  // the result sits in the second buffers
         const long long n = (long long)s.p2 * (s.ny + 2 * s.h);

@@ -188,6 +188,10 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     __shared__ int sK[KN];
     __shared__ R fxT[NT], fyT[NT], fxu[NT], fyu[NT], fxv[NT], fyv[NT];
     __shared__ R sQv[NT], sQu[NT], sP[2 * NT], sWm[NT];
+    // per-row metrics of the tile's rows (a row's threads read one address):
+    // dxv south, dxv north, area, f, tan(phi)/a, 1/area, 1/(dxv dy), 1/dxc
+    __shared__ R sRow[8][TY];
+    __shared__ R sTop[NT];  // surface volume flux times the full top temperature
 
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
     const int i0 = bx * (TX - 1), j0 = by * (TY - 1);
@@ -248,30 +252,52 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     const int KuE = min(Kc, Kat(1, 0)), KuSE = min(Kat(0, -1), Kat(1, -1));
     const int KvN = min(Kc, Kat(0, 1)), KvNW = min(Kat(-1, 0), Kat(-1, 1));
     // smallest wet count over each horizontal stencil: all six points are
-    // valid at level k when it reaches nz - k
-    int mTx = Kc, mTy = Kc, mux = Kc, muy = Kc, mvx = Kc, mvy = Kc, mTw = Kc, mTs = Kc;
+    // valid at level k when it reaches nz - k. The eight minima (each <= 128)
+    // are kept as bytes of two registers.
+    unsigned minA, minB;
+    {
+        int mTx = Kc, mTy = Kc, mux = Kc, muy = Kc, mvx = Kc, mvy = Kc, mTw = Kc, mTs = Kc;
 #pragma unroll
-    for (int r = -3; r <= 3; ++r) {
-        mux = min(mux, Kat(r, 0));
-        mvy = min(mvy, Kat(0, r));
-        if (r >= -2) {
-            mTx = min(mTx, Kat(r, 0));
-            mTy = min(mTy, Kat(0, r));
-            muy = min(muy, min(Kat(-1, r), Kat(0, r)));
-            mvx = min(mvx, min(Kat(r, -1), Kat(r, 0)));
+        for (int r = -3; r <= 3; ++r) {
+            mux = min(mux, Kat(r, 0));
+            mvy = min(mvy, Kat(0, r));
+            if (r >= -2) {
+                mTx = min(mTx, Kat(r, 0));
+                mTy = min(mTy, Kat(0, r));
+                muy = min(muy, min(Kat(-1, r), Kat(0, r)));
+                mvx = min(mvx, min(Kat(r, -1), Kat(r, 0)));
+            }
+            if (r <= 2) {  // the west and south faces of this point
+                mTw = min(mTw, Kat(r, 0));
+                mTs = min(mTs, Kat(0, r));
+            }
         }
-        if (r <= 2) {  // the west and south faces of this point
-            mTw = min(mTw, Kat(r, 0));
-            mTs = min(mTs, Kat(0, r));
-        }
+        minA = unsigned(mTx) | unsigned(mTy) << 8 | unsigned(mux) << 16 | unsigned(muy) << 24;
+        minB = unsigned(mvx) | unsigned(mvy) << 8 | unsigned(mTw) << 16 | unsigned(mTs) << 24;
     }
+    auto byte_of = [](unsigned v, int q) { return int((v >> (8 * q)) & 0xffu); };
+#define mTx byte_of(minA, 0)
+#define mTy byte_of(minA, 1)
+#define mux byte_of(minA, 2)
+#define muy byte_of(minA, 3)
+#define mvx byte_of(minB, 0)
+#define mvy byte_of(minB, 1)
+#define mTw byte_of(minB, 2)
+#define mTs byte_of(minB, 3)
 
     // row metrics of the point (clamped for points past the domain, which are unused)
     const int jr = min(max(pj, -h), ny + h - 2);
     const int ir = min(max(pi, -h), nx + h - 2);
-    const R dxc = R(S.dxc[jr]), dxv0 = R(S.dxv[jr]), dxv1 = R(S.dxv[jr + 1]);
-    const R area = R(S.area[jr]), fc = R(S.fcor[jr]), met = R(S.metric[jr]);
-    const R inv_area = R(1.0 / S.area[jr]), inv_areav = R(1.0 / (S.dxv[jr] * S.dy)), inv_dxc = R(1.0 / S.dxc[jr]);
+    if (tx == 0) {
+        sRow[0][ty] = R(S.dxv[jr]);
+        sRow[1][ty] = R(S.dxv[jr + 1]);
+        sRow[2][ty] = R(S.area[jr]);
+        sRow[3][ty] = R(S.fcor[jr]);
+        sRow[4][ty] = R(S.metric[jr]);
+        sRow[5][ty] = R(1.0 / S.area[jr]);
+        sRow[6][ty] = R(1.0 / (S.dxv[jr] * S.dy));
+        sRow[7][ty] = R(1.0 / S.dxc[jr]);
+    }
     const R dy = R(S.dy), inv_dy = R(1.0 / S.dy);
     const R ga = R(S.g * S.alpha);
     const R dt = R(S.dt);
@@ -283,31 +309,31 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     // depth-integrated transport of the current u, v (their column sums).
     double Wc = -(S.dy * (S.cu[idx2(S, ir + 1, jr)] - S.cu[idx2(S, ir, jr)]) +
                   S.dxv[jr + 1] * S.cv[idx2(S, ir, jr + 1)] - S.dxv[jr] * S.cv[idx2(S, ir, jr)]);
-    const double Wsurf = Wc;
+    sTop[tid] = R(Wc) * R(S.tref[nz - 1]);
 
     // own-column windows: w[r] holds level k + 2 - r
     R wt[6], wu[6], wv[6];
 #pragma unroll
     for (int r = 0; r < 6; ++r) { wt[r] = R(0); wu[r] = R(0); wv[r] = R(0); }
     const long long pl = S.plane3;
-    const long long own = idx3(S, tcell ? pi : 0, tcell ? pj : 0, 0);
-    // the tracer history of a ring column in a periodic halo is read at its
-    // interior image (only interior values are written)
+    // this column's offset in a level (a level's offset k * pl is uniform
+    // across the workgroup); a ring column in a periodic halo is read at its
+    // interior image, the only copy of its tracer history that is written
     const int hi = (pi < 0 && S.periodic_x) ? pi + nx : pi;
     const int hj = (pj < 0 && S.periodic_y) ? pj + ny : pj;
-    const long long ownh = idx3(S, tcell ? hi : 0, tcell ? hj : 0, 0);
+    int own = tcell ? hj * S.p3 + hi : 0;
     if (tcell) {
 #pragma unroll
         for (int r = 1; r < 6; ++r) {
             const int k = nz + 2 - r;  // before the first shift: levels nz+1 .. nz-3
-            if (k >= 0 && k < nz) wt[r] = gT[own + k * pl];
+            if (k >= 0 && k < nz) wt[r] = gT[k * pl + own];
         }
     }
     if (cell) {
 #pragma unroll
         for (int r = 1; r < 6; ++r) {
             const int k = nz + 2 - r;
-            if (k >= 0 && k < nz) { wu[r] = gU[own + k * pl]; wv[r] = gV[own + k * pl]; }
+            if (k >= 0 && k < nz) { wu[r] = gU[k * pl + own]; wv[r] = gV[k * pl + own]; }
         }
     }
 
@@ -326,9 +352,6 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     R p_prev = R(0), b_prev = R(0);
     R GUp = R(0), GVp = R(0);  // momentum tendencies of level k+1 without the pressure gradient
     double gUacc = 0.0, gVacc = 0.0;
-    const R wind_u = cell ? R(S.taux[idx2(S, pi, pj)] / (S.rho0 * S.dz[nz - 1])) : R(0);
-    const R wind_v = cell ? R(S.tauy[idx2(S, pi, pj)] / (S.rho0 * S.dz[nz - 1])) : R(0);
-    const R tstar = tcell ? R(S.tstar[idx2(S, pi, pj)]) : R(0);
     const R rinv = R(S.restore_inv);
     R* __restrict__ gto = f3<R>(S.gt_out);
     const R* __restrict__ gti = f3<R>(S.gt);
@@ -342,13 +365,13 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     // marched) once the pressure of level kk of every point is in LDS:
     // AB2 of the other terms plus the forward-backward pressure gradient.
     auto finish_uv = [&](int kk, const R* P) {
-        const long long o = own + (long long)kk * pl;
+        const long long o = (long long)kk * pl + own;
         const int kw = nz - kk;
         R hU = c_new * GUp - c_old * gup[o];
         R hV = c_new * GVp - c_old * gvp[o];
         gup[o] = GUp;
         gvp[o] = GVp;
-        if (Ku >= kw) hU -= (P[tid] - P[tid - 1]) * inv_dxc;
+        if (Ku >= kw) hU -= (P[tid] - P[tid - 1]) * sRow[7][ty];
         if (Kv >= kw) hV -= (P[tid] - P[tid - TX]) * inv_dy;
         uso[o] = wu[1] + dt * hU;
         vso[o] = wv[1] + dt * hV;
@@ -357,13 +380,22 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     };
 
     for (int k = nz - 1; k >= 0; --k) {
+        // The column and slot offsets are marked as redefined at every level so
+        // that the compiler rebuilds each field's 64-bit address per level (two
+        // instructions) instead of keeping a dozen of them live across the
+        // march, which spilled registers.
+        asm volatile("" : "+v"(own));
+#pragma unroll
+        for (int q = 0; q < NS; ++q) asm volatile("" : "+v"(slot_off[q]));
+#pragma unroll
+        for (int q = 0; q < NST; ++q) asm volatile("" : "+v"(slot_offT[q]));
         // shift the windows and load level k-3
 #pragma unroll
         for (int r = 0; r < 5; ++r) { wt[r] = wt[r + 1]; wu[r] = wu[r + 1]; wv[r] = wv[r + 1]; }
         wt[5] = R(0); wu[5] = R(0); wv[5] = R(0);
-        if (tcell && k - 3 >= 0) wt[5] = gT[own + (long long)(k - 3) * pl];
+        if (tcell && k - 3 >= 0) wt[5] = gT[(long long)(k - 3) * pl + own];
         if (cell && k - 3 >= 0) {
-            const long long o = own + (long long)(k - 3) * pl;
+            const long long o = (long long)(k - 3) * pl + own;
             wu[5] = gU[o]; wv[5] = gV[o];
         }
         // stage level k from the prefetch registers, then prefetch level k-1
@@ -401,7 +433,8 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
         if (used) {
             const R U00 = (Ku >= kwet) ? at(sU, 0, 0) * dy * dzk : R(0);
             const R U10 = (KuE >= kwet) ? at(sU, 1, 0) * dy * dzk : R(0);
-            const R V00 = (Kv >= kwet) ? at(sV, 0, 0) * dxv0 * dzk : R(0);
+            const R dxv1 = sRow[1][ty];
+            const R V00 = (Kv >= kwet) ? at(sV, 0, 0) * sRow[0][ty] * dzk : R(0);
             const R V01 = (KvN >= kwet) ? at(sV, 0, 1) * dxv1 * dzk : R(0);
             R p[6];
             bool ok[6];
@@ -489,7 +522,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                 // Coriolis: Q = (f + u_c tan(phi)/a) V_c on wet cells
                 const R uc = R(0.5) * (at(sU, 0, 0) + at(sU, 1, 0));
                 const R vc = R(0.5) * (at(sV, 0, 0) + at(sV, 0, 1));
-                const R Q = (Kc >= kwet) ? (fc + met * uc) * area * dzk : R(0);
+                const R Q = (Kc >= kwet) ? (sRow[3][ty] + sRow[4][ty] * uc) * sRow[2][ty] * dzk : R(0);
                 sQv[tid] = Q * vc;
                 sQu[tid] = Q * uc;
             }
@@ -506,7 +539,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
         R* const Pk = &sP[(k & 1) * NT];
         if (tcell) {
             const int c = tid, cw = tid - 1, cs = tid - TX;
-            const long long o = own + (long long)k * pl;
+            const long long o = (long long)k * pl + own;
 
             // vertical fluxes through the bottom face (between levels k-1 and k)
             R fzT_bot = R(0), fzu_bot = R(0), fzv_bot = R(0);
@@ -578,7 +611,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
             if (Kc >= kwet) {
                 R E_top;
                 if (k == nz - 1) {
-                    E_top = R(Wsurf) * R(S.tref[k]);  // volume flux through the surface, full T
+                    E_top = sTop[c];
                 } else {
                     // upwind cell k+1 when the face transport is downward
                     E_top = (Wm_top > R(0)) ? R(0) : Wm_top * (-dtr[k * 4 + 2]);
@@ -586,12 +619,12 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                 const R fw = (tx == 0) ? fyu[c] : fxT[cw];
                 const R fs = (ty == 0) ? fxu[c] : fyT[cs];
                 const R divF = (fxT[c] - fw) + (fyT[c] - fs) + (fzT_top - fzT_bot);
-                GT = (-divF + (E_top - E_bot)) * (inv_area * inv_dz);
-                if (k == nz - 1) GT += (tstar - wt[2]) * rinv;
+                GT = (-divF + (E_top - E_bot)) * (sRow[5][ty] * inv_dz);
+                if (k == nz - 1) GT += (R(S.tstar[idx2(S, pi, pj)]) - wt[2]) * rinv;
             }
             // AB2 of the tracer (G^n goes to the other history buffer), and the
             // pressure of T^n + eps dt Ghat_T from p = 0 at z = 0 downward
-            const R hT = c_new * GT - c_old * gti[ownh + (long long)k * pl];
+            const R hT = c_new * GT - c_old * gti[o];
             if (cell) {
                 gto[o] = GT;
                 tso[o] = wt[2] + dt * hT;
@@ -608,17 +641,17 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                 if (k + 1 < nz) finish_uv(k + 1, &sP[((k + 1) & 1) * NT]);
                 R GUm = R(0);
                 if (Ku >= kwet) {
-                    const R ivol = inv_area * inv_dz;
+                    const R ivol = sRow[5][ty] * inv_dz;
                     const R divF = (fxu[c] - fxu[cw]) + (fyu[c] - fyu[cs]) + (fzu_top - fzu_bot);
                     GUm = -divF * ivol + (sQv[cw] + sQv[c]) * (R(0.5) * ivol);
-                    if (k == nz - 1) GUm += wind_u;
+                    if (k == nz - 1) GUm += R(S.taux[idx2(S, pi, pj)] / (S.rho0 * S.dz[nz - 1]));
                 }
                 R GVm = R(0);
                 if (Kv >= kwet) {
-                    const R ivol = inv_areav * inv_dz;
+                    const R ivol = sRow[6][ty] * inv_dz;
                     const R divF = (fxv[c] - fxv[cw]) + (fyv[c] - fyv[cs]) + (fzv_top - fzv_bot);
                     GVm = -divF * ivol - (sQu[cs] + sQu[c]) * (R(0.5) * ivol);
-                    if (k == nz - 1) GVm += wind_v;
+                    if (k == nz - 1) GVm += R(S.tauy[idx2(S, pi, pj)] / (S.rho0 * S.dz[nz - 1]));
                 }
                 GUp = GUm;
                 GVp = GVm;
@@ -640,6 +673,14 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
         S.gU[idx2(S, pi, pj)] = gUacc;
         S.gV[idx2(S, pi, pj)] = gVacc;
     }
+#undef mTx
+#undef mTy
+#undef mux
+#undef muy
+#undef mvx
+#undef mvy
+#undef mTw
+#undef mTs
 }
 
 template <typename R, int TX, int TY>

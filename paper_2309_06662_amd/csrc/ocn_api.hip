@@ -87,6 +87,7 @@ struct ocn_state {
     void* kv_ws = nullptr;        // the workspace's viscosity field (interior origin)
     // the two tracer-history buffers; d.gt is the one the next step reads
     void* gtb[2] = {nullptr, nullptr};
+    double cfl_bt = 0.0;  // barotropic CFL of a substep (static: grid and parameters)
     // one step captured as a HIP graph per history buffer (ocn_step_graph)
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -468,6 +469,13 @@ int set_field_t(ocn_state* s, int32_t f, const double* host) {
     case OCN_FIELD_GU_PREV: return set3<R>(s, d.gu, host, nullptr, 0);
     case OCN_FIELD_GV_PREV: return set3<R>(s, d.gv, host, nullptr, 0);
     case OCN_FIELD_GT_PREV: return set3<R>(s, d.gt, host, nullptr, 0);
+    case OCN_FIELD_U_PRED: return set3<R>(s, d.us, host, nullptr, 0);
+    case OCN_FIELD_V_PRED: return set3<R>(s, d.vs, host, nullptr, 0);
+    case OCN_FIELD_T_PRED:
+        if (!s->t_set) return fail(OCN_E_STATE, "set T first: T_PRED is stored relative to T's reference profile");
+        return set3<R>(s, d.ts, host, s->tref.data(), 0);
+    case OCN_FIELD_GU_SLOW: return set2(s, d.gU, host);
+    case OCN_FIELD_GV_SLOW: return set2(s, d.gV, host);
     case OCN_FIELD_ETA: return set2(s, d.eta, host);
     case OCN_FIELD_UBT: return set2(s, d.ubt, host);
     case OCN_FIELD_VBT: return set2(s, d.vbt, host);
@@ -504,6 +512,11 @@ int get_field_t(ocn_state* s, int32_t f, double* host) {
     case OCN_FIELD_GU_PREV: return get3<R>(s, d.gu, host, nullptr, g->nz);
     case OCN_FIELD_GV_PREV: return get3<R>(s, d.gv, host, nullptr, g->nz);
     case OCN_FIELD_GT_PREV: return get3<R>(s, d.gt, host, nullptr, g->nz);
+    case OCN_FIELD_U_PRED: return get3<R>(s, d.us, host, nullptr, g->nz);
+    case OCN_FIELD_V_PRED: return get3<R>(s, d.vs, host, nullptr, g->nz);
+    case OCN_FIELD_T_PRED: return get3<R>(s, d.ts, host, s->tref.data(), g->nz);
+    case OCN_FIELD_GU_SLOW: return get2(s, d.gU, host);
+    case OCN_FIELD_GV_SLOW: return get2(s, d.gV, host);
     case OCN_FIELD_ETA: return get2(s, d.eta, host);
     case OCN_FIELD_UBT: return get2(s, d.ubt, host);
     case OCN_FIELD_VBT: return get2(s, d.vbt, host);
@@ -553,9 +566,13 @@ int get_field_t(ocn_state* s, int32_t f, double* host) {
         return OCN_OK;
     }
     case OCN_FIELD_W: {
-        HIPCHK(ocn::launch_w_faces<R>(d, nullptr, s->st));
+        // faces 0..nz-1 go to the tracer-history buffer the next step writes
+        // (its contents are dead between steps), the surface face to 2D scratch
+        DevState dw = d;
+        dw.ts = d.gt_out;
+        HIPCHK(ocn::launch_w_faces<R>(dw, nullptr, s->st));
         const size_t n2 = (size_t)g->nx * g->ny;
-        int rc = get3<R>(s, d.ts, host, nullptr, g->nz);
+        int rc = get3<R>(s, d.gt_out, host, nullptr, g->nz);
         if (rc) return rc;
         return get2(s, d.scratch2d, host + (size_t)g->nz * n2);
     }
@@ -567,7 +584,9 @@ size_t field_count(const ocn_grid* g, int32_t f) {
     const size_t n2 = (size_t)g->nx * g->ny, n3 = n2 * g->nz;
     switch (f) {
     case OCN_FIELD_U: case OCN_FIELD_V: case OCN_FIELD_T: case OCN_FIELD_KAPPA: case OCN_FIELD_VISC:
-    case OCN_FIELD_GU_PREV: case OCN_FIELD_GV_PREV: case OCN_FIELD_GT_PREV: return n3;
+    case OCN_FIELD_GU_PREV: case OCN_FIELD_GV_PREV: case OCN_FIELD_GT_PREV:
+    case OCN_FIELD_U_PRED: case OCN_FIELD_V_PRED: case OCN_FIELD_T_PRED: return n3;
+    case OCN_FIELD_GU_SLOW: case OCN_FIELD_GV_SLOW: return n2;
     case OCN_FIELD_W: return n2 * (g->nz + 1);
     case OCN_FIELD_TREF: return g->nz;
     case OCN_FIELD_ETA: case OCN_FIELD_UBT: case OCN_FIELD_VBT: case OCN_FIELD_ETA_MEAN:
@@ -719,7 +738,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         d.restore_inv = params->restore_tau > 0.0 ? 1.0 / params->restore_tau : 0.0;
         d.pgf_w = params->pgf_weight;
         d.n_substeps = params->n_substeps;
-        d.baro_fuse = params->baro_fuse == 0 ? 8 : params->baro_fuse;
+        d.baro_fuse = params->baro_fuse == 0 ? ocn::kBaroFuseDefault : params->baro_fuse;
         d.baro_m = ocn::baro_substeps(params->n_substeps);
         d.baro_a = reinterpret_cast<double*>(A + P.off_bw);
         d.baro_A = d.baro_a + d.baro_m + 1;
@@ -730,6 +749,22 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         if (e != hipSuccess) {
             delete s;
             return fail(OCN_E_DEVICE, std::string("arena clear: ") + hipGetErrorString(e));
+        }
+        // barotropic CFL of a substep: sqrt(g H) dtau sqrt(1/dx^2 + 1/dy^2) over wet columns
+        {
+            const double dtau = params->dt / params->n_substeps;
+            for (int j = 0; j < grid->ny; ++j) {
+                const double dxc = grid->dxc[grid->row(j)];
+                for (int i = 0; i < grid->nx; ++i) {
+                    const int kb = grid->kb[(size_t)j * grid->nx + i];
+                    if (kb <= 0) continue;
+                    double hc = 0.0;
+                    for (int k = grid->nz - kb; k < grid->nz; ++k) hc += grid->dz[k];
+                    const double c = std::sqrt(params->g * hc) * dtau *
+                                     std::sqrt(1.0 / (dxc * dxc) + 1.0 / (grid->dy * grid->dy));
+                    s->cfl_bt = std::max(s->cfl_bt, c);
+                }
+            }
         }
         int rc = params->precision == OCN_FP32 ? init_static<float>(s) : init_static<double>(s);
         if (!rc) rc = upload_substep_weights(s);
@@ -838,24 +873,47 @@ ClosurePlan closure_plan(const ocn_state* s, int din, int h1, int h2, int dout) 
 
 namespace {
 
-// Enqueue the kernels of one step on the state's stream (no host bookkeeping).
-int enqueue_step(ocn_state* s) {
+// Enqueue the kernels of one stage on the state's stream. The tendency stage
+// writes G^n of the tracer to the second history buffer, which then becomes
+// the history the next step reads.
+int enqueue_stage(ocn_state* s, int stage) {
     const bool f32 = s->esize == 4;
+    switch (stage) {
+    case OCN_STAGE_MIXING: {
+        int rc;
+        if (s->closure && s->net && (rc = closure_update(s))) return rc;
+        if (s->closure && !s->net && s->ri_on)
+            HIPCHK(f32 ? ocn::launch_richardson<float>(s->d, s->ri, s->st)
+                       : ocn::launch_richardson<double>(s->d, s->ri, s->st));
+        else if (s->closure && !s->net && s->kappa_conv > 0.0)
+            HIPCHK(f32 ? ocn::launch_convective<float>(s->d, s->kappa_conv, s->p.kappa, s->st)
+                       : ocn::launch_convective<double>(s->d, s->kappa_conv, s->p.kappa, s->st));
+        return OCN_OK;
+    }
+    case OCN_STAGE_TENDENCY:
+        HIPCHK(f32 ? ocn::launch_tendency<float>(s->d, s->first, s->st)
+                   : ocn::launch_tendency<double>(s->d, s->first, s->st));
+        std::swap(s->d.gt, s->d.gt_out);
+        return OCN_OK;
+    case OCN_STAGE_BAROTROPIC:
+        HIPCHK(ocn::launch_barotropic(s->d, s->st));
+        return OCN_OK;
+    case OCN_STAGE_COLUMN:
+        HIPCHK(f32 ? ocn::launch_column<float>(s->d, s->st) : ocn::launch_column<double>(s->d, s->st));
+        return OCN_OK;
+    default:
+        return fail(OCN_E_INVALID, "unknown stage");
+    }
+}
+
+// Enqueue the kernels of one step on the state's stream (no host bookkeeping
+// beyond the history buffers).
+int enqueue_step(ocn_state* s) {
     int rc;
-    if (s->timing && (rc = record(s))) return rc;
-    if (s->closure && s->net && (rc = closure_update(s))) return rc;
-    if (s->closure && !s->net && s->ri_on)
-        HIPCHK(s->esize == 4 ? ocn::launch_richardson<float>(s->d, s->ri, s->st)
-                             : ocn::launch_richardson<double>(s->d, s->ri, s->st));
-    else if (s->closure && !s->net && s->kappa_conv > 0.0)
-        HIPCHK(s->esize == 4 ? ocn::launch_convective<float>(s->d, s->kappa_conv, s->p.kappa, s->st)
-                             : ocn::launch_convective<double>(s->d, s->kappa_conv, s->p.kappa, s->st));
-    if (s->timing && (rc = record(s))) return rc;
-    HIPCHK(f32 ? ocn::launch_tendency<float>(s->d, s->first, s->st) : ocn::launch_tendency<double>(s->d, s->first, s->st));
-    if (s->timing && (rc = record(s))) return rc;
-    HIPCHK(ocn::launch_barotropic(s->d, s->st));
-    if (s->timing && (rc = record(s))) return rc;
-    HIPCHK(f32 ? ocn::launch_column<float>(s->d, s->st) : ocn::launch_column<double>(s->d, s->st));
+    for (int stage = OCN_STAGE_MIXING; stage <= OCN_STAGE_COLUMN; ++stage) {
+        if (s->timing && (rc = record(s))) return rc;
+        if ((rc = enqueue_stage(s, stage))) return rc;
+    }
     if (s->timing) {
         if ((rc = record(s))) return rc;
         s->timed_steps += 1;
@@ -867,7 +925,6 @@ void advance(ocn_state* s) {
     s->first = 0;
     s->step += 1;
     s->time += s->p.dt;
-    std::swap(s->d.gt, s->d.gt_out);  // G^n becomes the history of the next step
 }
 
 }  // namespace
@@ -898,6 +955,9 @@ int ocn_step_graph(ocn_state* s, int32_t n) {
                 rc = enqueue_step(s);
                 hipGraph_t g = nullptr;
                 hipError_t ce = hipStreamEndCapture(s->st, &g);
+                // the capture recorded the step without running it; its tendency
+                // stage swapped the history buffers, which the replay below does
+                if (s->parity() != par) std::swap(s->d.gt, s->d.gt_out);
                 if (rc) {
                     if (g) (void)hipGraphDestroy(g);
                     return rc;
@@ -907,10 +967,17 @@ int ocn_step_graph(ocn_state* s, int32_t n) {
                 HIPCHK(hipGraphInstantiate(&s->exec[par], s->graph[par], nullptr, nullptr, 0));
             }
             HIPCHK(hipGraphLaunch(s->exec[par], s->st));
+            std::swap(s->d.gt, s->d.gt_out);  // what the replayed tendency stage did
         }
         advance(s);
     }
     return OCN_OK;
+}
+
+int ocn_debug_run_stage(ocn_state* s, int32_t stage) {
+    if (!s) return fail(OCN_E_INVALID, "state must not be NULL");
+    if (stage < OCN_STAGE_MIXING || stage > OCN_STAGE_COLUMN) return fail(OCN_E_INVALID, "unknown stage");
+    return enqueue_stage(s, stage);
 }
 
 int ocn_closure_workspace_bytes(const ocn_state* s, const ocn_mlp* net, size_t* bytes) {
@@ -1090,6 +1157,7 @@ int ocn_diagnostics(ocn_state* s, ocn_diag* out) {
     out->eta_max = r[ocn::DG_ETA_MAX];
     out->eta_min = -r[ocn::DG_NEG_ETA_MIN];
     out->nonfinite = (int64_t)r[ocn::DG_NONFINITE];
+    out->cfl_bt = s->cfl_bt;
     if (out->nonfinite > 0) return fail(OCN_E_UNSTABLE, "non-finite values in the state");
     return OCN_OK;
 }
@@ -1192,7 +1260,7 @@ struct ocn_ensemble {
     int max_nz = 1;
     int first = 1;
     int tend_ty = 0;   // 0 = precision default
-    int fuse = 8;
+    int fuse = ocn::kBaroFuseDefault;
     DevState* d_members = nullptr;  // two tables of the members: as they are, and with
                                     // their tracer-history buffers swapped
     std::vector<DevState> tab[2];   // host copies of both tables
@@ -1388,7 +1456,7 @@ int ocn_ensemble_init(const ocn_grid* const* grids, int32_t n, const ocn_params*
         e->p = *params;
         e->st = static_cast<hipStream_t>(hip_stream);
         e->esize = params->precision == OCN_FP32 ? 4 : 8;
-        e->fuse = params->baro_fuse < 2 ? 8 : params->baro_fuse;
+        e->fuse = params->baro_fuse < 2 ? ocn::kBaroFuseDefault : params->baro_fuse;
         unsigned char* A = static_cast<unsigned char*>(device_arena);
         for (int m = 0; m < n; ++m) {
             ocn_state* s = nullptr;
@@ -1451,7 +1519,7 @@ int ocn_ensemble_set_tiles(ocn_ensemble* e, int32_t tend_rows, int32_t baro_fuse
     if (e->st) HIPCHK(hipStreamSynchronize(e->st));
     drop_graph(e);
     e->tend_ty = tend_rows;
-    e->fuse = baro_fuse == 0 ? 8 : baro_fuse;
+    e->fuse = baro_fuse == 0 ? ocn::kBaroFuseDefault : baro_fuse;
     return ens_tables(e);
 }
 
@@ -1470,9 +1538,9 @@ int ocn_ensemble_autotune(ocn_ensemble* e, int32_t trial_steps, int32_t* tend_ro
     }
     const int first0 = e->first;
     const int rows_c[2] = {4, 8};
-    const int fuse_c[4] = {3, 5, 6, 8};
+    const int fuse_c[4] = {5, 6, 7, 8};
     double best = 1e300;
-    int brow = 0, bfuse = 8;
+    int brow = 0, bfuse = ocn::kBaroFuseDefault;
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));

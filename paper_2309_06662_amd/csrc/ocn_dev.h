@@ -186,6 +186,9 @@ hipError_t launch_column_batched(const DevState* members, const int4* tiles, int
 int baro_substeps(int n_substeps);  // Ns + Ns/2
 hipError_t launch_barotropic_batched(const DevState* members, int n_members, const int4* tiles, int ntiles,
                                      int n_substeps, int fuse, double dt, hipStream_t st);
-constexpr int kBaroTileX = 64, kBaroTileY = 32;
+constexpr int kBaroTileX = 64, kBaroTileY = 24;
+// substeps per barotropic launch unless chosen: 7 keeps the 64 x 24 tile's LDS
+// (72 KB) and registers (119) within two workgroups per CU
+constexpr int kBaroFuseDefault = 7;
 
 }  // namespace ocn

@@ -24,8 +24,10 @@ OCN_CARTESIAN, OCN_LATLON = 0, 1
 
 FIELDS = {"u": 0, "v": 1, "T": 2, "eta": 3, "U": 4, "V": 5, "eta_mean": 6, "U_mean": 7, "V_mean": 8,
           "w": 9, "gu_prev": 10, "gv_prev": 11, "gt_prev": 12, "taux": 13, "tauy": 14, "tstar": 15, "tref": 16,
-          "kappa": 17, "visc": 18}
-FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "kappa", "visc"}
+          "kappa": 17, "visc": 18, "u_pred": 19, "v_pred": 20, "T_pred": 21, "gU_slow": 22, "gV_slow": 23}
+FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "kappa", "visc", "u_pred", "v_pred", "T_pred"}
+# stages of a step (ocn_stage)
+STAGE_MIXING, STAGE_TENDENCY, STAGE_BAROTROPIC, STAGE_COLUMN = 0, 1, 2, 3
 # Richardson-number mixing constants (Pacanowski and Philander 1981 form)
 RI_DEFAULTS = {"nu0": 1e-2, "alpha": 5.0, "nu_b": 1e-4, "kappa_b": 1e-5, "conv": 1.0}
 
@@ -41,7 +43,7 @@ ABI_FUNCTIONS = ["ocn_abi_version", "ocn_last_error", "ocn_grid_create", "ocn_gr
                  "ocn_mlp_set_params", "ocn_mlp_get_params", "ocn_mlp_forward", "ocn_mlp_gradients",
                  "ocn_mlp_train_step", "ocn_closure_workspace_bytes", "ocn_closure_attach",
                  "ocn_closure_detach", "ocn_closure_features", "ocn_closure_kappa", "ocn_closure_convective",
-                 "ocn_closure_richardson"]
+                 "ocn_closure_richardson", "ocn_debug_run_stage"]
 
 
 class OcnError(RuntimeError):
@@ -70,7 +72,8 @@ class Diag(C.Structure):
                 ("volume", C.c_double), ("volume_mean", C.c_double), ("kinetic_energy", C.c_double),
                 ("max_abs_u", C.c_double), ("max_abs_v", C.c_double), ("max_abs_w", C.c_double),
                 ("t_min", C.c_double), ("t_max", C.c_double), ("eta_min", C.c_double), ("eta_max", C.c_double),
-                ("cfl_adv", C.c_double), ("wet_area", C.c_double), ("nonfinite", C.c_int64)]
+                ("cfl_adv", C.c_double), ("wet_area", C.c_double), ("nonfinite", C.c_int64),
+                ("cfl_bt", C.c_double)]
 
 
 _lib = None
@@ -98,6 +101,7 @@ def lib():
         L.ocn_set_first_step.argtypes = [C.c_void_p, C.c_int32]
         L.ocn_get_first_step.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
         L.ocn_step.argtypes = [C.c_void_p, C.c_int32]
+        L.ocn_debug_run_stage.argtypes = [C.c_void_p, C.c_int32]
         L.ocn_step_graph.argtypes = [C.c_void_p, C.c_int32]
         L.ocn_diagnostics.argtypes = [C.c_void_p, C.POINTER(Diag)]
         L.ocn_synchronize.argtypes = [C.c_void_p]
@@ -256,6 +260,10 @@ class Model:
             _check(lib().ocn_step_graph(self.handle, int(n)), "ocn_step_graph")
         else:
             _check(lib().ocn_step(self.handle, int(n)), "ocn_step")
+
+    def run_stage(self, stage: int):
+        """Enqueue one stage of a step (STAGE_*); no step count, time or start-flag change."""
+        _check(lib().ocn_debug_run_stage(self.handle, int(stage)), "ocn_debug_run_stage")
 
     def checkpoint(self) -> bytes:
         n = C.c_size_t()

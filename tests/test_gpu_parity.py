@@ -171,8 +171,9 @@ def test_diagnostics_match_oracle():
     gpu.step(3)
     dg, do = gpu.diagnostics(), ref.diagnostics()
     for key in ("tracer_content", "wet_area", "kinetic_energy", "max_abs_u", "max_abs_v", "max_abs_w",
-                "t_min", "t_max", "eta_min", "eta_max", "cfl_adv"):
+                "t_min", "t_max", "eta_min", "eta_max", "cfl_adv", "cfl_bt"):
         assert dg[key] == pytest.approx(do[key], rel=1e-10), key
+    assert 0.0 < dg["cfl_bt"] < 1.0
     # volumes vanish to round-off on both sides
     scale = do["wet_area"] * max(abs(do["eta_max"]), abs(do["eta_min"]))
     assert abs(dg["volume"]) <= 1e-12 * scale and abs(dg["volume_mean"]) <= 1e-12 * scale

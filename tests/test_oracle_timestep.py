@@ -134,3 +134,20 @@ def test_high_latitude_windows_stay_bounded():
         assert d["max_abs_u"] < 1.0 and d["max_abs_v"] < 1.0, (job, d["max_abs_u"], d["max_abs_v"])
         assert max(abs(d["eta_min"]), abs(d["eta_max"])) < 1.0, job
         assert d["cfl_adv"] < 0.2, job
+
+
+def test_stages_in_turn_equal_a_step():
+    """The four stages run one by one give bitwise what a step gives."""
+    w = small_latlon(nx=20, ny=12, nz=6)
+    inp = inputs.make_inputs(w)
+    a = oracle.OracleModel.from_inputs(w, inp)
+    b = oracle.OracleModel.from_inputs(w, inp)
+    a.set_convective(0.5)
+    b.set_convective(0.5)
+    for n in range(3):
+        a.step(1)
+        for st in (oracle.STAGE_MIXING, oracle.STAGE_TENDENCY, oracle.STAGE_BAROTROPIC, oracle.STAGE_COLUMN):
+            b.run_stage(st)
+        b.first_step = False
+        for name in ("u", "v", "T", "eta", "U", "V", "U_mean", "gu_prev", "gt_prev"):
+            assert np.array_equal(a.get(name), b.get(name)), (n, name)
