@@ -224,6 +224,17 @@ int ocn_step(ocn_state* state, int32_t n);
  * when any prognostic value is non-finite. */
 int ocn_diagnostics(ocn_state* state, ocn_diag* out);
 
+/* The same diagnostics for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * per-workgroup partial sums and the reduced values live in a fixed device
+ * array of the library instead of the state's arena, and the call allocates
+ * nothing. The array holds the partials of grids of up to 8,388,608 columns
+ * (nx ny; larger grids return OCN_E_UNSUPPORTED) and is shared by every call
+ * on a GPU: calls that overlap on one GPU (several streams or host threads)
+ * race and must be serialised by the caller. Results equal ocn_diagnostics'.
+ * Synchronises the stream. */
+int ocn_diagnostics_noalloc(ocn_state* state, ocn_diag* out);
+
 /* Wait for all work enqueued on the state's stream. */
 int ocn_synchronize(ocn_state* state);
 

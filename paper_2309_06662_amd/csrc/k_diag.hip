@@ -9,6 +9,8 @@
 // order, so the result does not depend on scheduling.
 #include "ocn_dev.h"
 
+#include <mutex>
+
 namespace ocn {
 
 constexpr int DX = 64, DY = 4, DT = DX * DY;
@@ -176,5 +178,39 @@ hipError_t launch_diagnostics(const DevState& s, hipStream_t st) {
 
 template hipError_t launch_diagnostics<double>(const DevState&, hipStream_t);
 template hipError_t launch_diagnostics<float>(const DevState&, hipStream_t);
+
+// Fixed scratch of the no-allocation diagnostics: the per-workgroup partials
+// of up to kDiagScratchBlocks workgroups (64 x 4 columns each, so grids of up
+// to 8.4 million columns), then the DG_COUNT final values. Each GPU holds its
+// own copy until the process ends; concurrent calls on one GPU share it.
+constexpr int kDiagScratchBlocks = 32768;
+static __device__ __align__(256) double scratch[(kDiagScratchBlocks + 1) * DG_COUNT];
+
+// Device address of this GPU's scratch array, looked up once per device with
+// that device current (host code never passes the symbol itself).
+hipError_t diag_scratch(int device, double** ptr, int* max_blocks) {
+    constexpr int kMaxDevices = 64;
+    static double* addr[kMaxDevices] = {};
+    static std::mutex lock;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> guard(lock);
+    if (!addr[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) {
+            const hipError_t r = hipSetDevice(cur);
+            if (e == hipSuccess) e = r;
+        }
+        if (e != hipSuccess) return e;
+        addr[device] = static_cast<double*>(p);
+    }
+    *ptr = addr[device];
+    *max_blocks = kDiagScratchBlocks;
+    return hipSuccess;
+}
 
 }  // namespace ocn

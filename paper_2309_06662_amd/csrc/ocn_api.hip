@@ -1135,11 +1135,12 @@ int ocn_stage_times(ocn_state* s, double* ms, int32_t n, int64_t* steps) {
     return OCN_OK;
 }
 
-int ocn_diagnostics(ocn_state* s, ocn_diag* out) {
-    if (!s || !out) return fail(OCN_E_INVALID, "state and out must not be NULL");
-    HIPCHK(s->esize == 4 ? ocn::launch_diagnostics<float>(s->d, s->st) : ocn::launch_diagnostics<double>(s->d, s->st));
+namespace {
+
+// Copy the reduced values out and fill the diagnostics record.
+int diag_finish(ocn_state* s, const double* dev_out, ocn_diag* out) {
     double r[ocn::DG_COUNT];
-    HIPCHK(hipMemcpyAsync(r, s->d.diag_out, sizeof(r), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(r, dev_out, sizeof(r), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
     out->step = s->step;
     out->time = s->time;
@@ -1160,6 +1161,34 @@ int ocn_diagnostics(ocn_state* s, ocn_diag* out) {
     out->cfl_bt = s->cfl_bt;
     if (out->nonfinite > 0) return fail(OCN_E_UNSTABLE, "non-finite values in the state");
     return OCN_OK;
+}
+
+}  // namespace
+
+int ocn_diagnostics(ocn_state* s, ocn_diag* out) {
+    if (!s || !out) return fail(OCN_E_INVALID, "state and out must not be NULL");
+    HIPCHK(s->esize == 4 ? ocn::launch_diagnostics<float>(s->d, s->st) : ocn::launch_diagnostics<double>(s->d, s->st));
+    return diag_finish(s, s->d.diag_out, out);
+}
+
+int ocn_diagnostics_noalloc(ocn_state* s, ocn_diag* out) {
+    if (!s || !out) return fail(OCN_E_INVALID, "state and out must not be NULL");
+    int dev = 0;
+    if (s->st) HIPCHK(hipStreamGetDevice(s->st, &dev));
+    else HIPCHK(hipGetDevice(&dev));
+    double* scratch = nullptr;
+    int max_blocks = 0;
+    HIPCHK(ocn::diag_scratch(dev, &scratch, &max_blocks));
+    const long long blocks = (long long)((s->g->nx + 63) / 64) * ((s->g->ny + 3) / 4);
+    if (blocks > max_blocks)
+        return fail(OCN_E_UNSUPPORTED, "grid too large for the fixed diagnostics scratch: at most " +
+                                           std::to_string((long long)max_blocks * 256) + " columns");
+    DevState d = s->d;  // the same kernels, with the partials and results in the fixed scratch
+    d.diag_part = scratch;
+    d.diag_out = scratch + (size_t)max_blocks * ocn::DG_COUNT;
+    d.diag_blocks = max_blocks;
+    HIPCHK(s->esize == 4 ? ocn::launch_diagnostics<float>(d, s->st) : ocn::launch_diagnostics<double>(d, s->st));
+    return diag_finish(s, d.diag_out, out);
 }
 
 namespace {

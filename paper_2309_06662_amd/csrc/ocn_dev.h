@@ -172,6 +172,8 @@ void mlp_shape(const ::ocn_mlp* net, int* din, int* h1, int* h2, int* dout);
 hipError_t mlp_infer(const ::ocn_mlp* net, const uint16_t* Xb, int rows, uint16_t* H1b, uint16_t* H2b, float* Y,
                      hipStream_t st);
 template <typename R> hipError_t launch_diagnostics(const DevState& s, hipStream_t st);
+// the fixed diagnostics scratch of a device (k_diag.hip): its address and capacity in workgroups
+hipError_t diag_scratch(int device, double** ptr, int* max_blocks);
 template <typename R> hipError_t launch_w_faces(const DevState& s, double* out_faces_dev, hipStream_t st);
 hipError_t launch_barotropic(const DevState& s, hipStream_t st);
 int tend_tile_rows(int precision_bytes, int ty_choice);

@@ -43,7 +43,7 @@ ABI_FUNCTIONS = ["ocn_abi_version", "ocn_last_error", "ocn_grid_create", "ocn_gr
                  "ocn_mlp_set_params", "ocn_mlp_get_params", "ocn_mlp_forward", "ocn_mlp_gradients",
                  "ocn_mlp_train_step", "ocn_closure_workspace_bytes", "ocn_closure_attach",
                  "ocn_closure_detach", "ocn_closure_features", "ocn_closure_kappa", "ocn_closure_convective",
-                 "ocn_closure_richardson", "ocn_debug_run_stage"]
+                 "ocn_closure_richardson", "ocn_debug_run_stage", "ocn_diagnostics_noalloc"]
 
 
 class OcnError(RuntimeError):
@@ -104,6 +104,7 @@ def lib():
         L.ocn_debug_run_stage.argtypes = [C.c_void_p, C.c_int32]
         L.ocn_step_graph.argtypes = [C.c_void_p, C.c_int32]
         L.ocn_diagnostics.argtypes = [C.c_void_p, C.POINTER(Diag)]
+        L.ocn_diagnostics_noalloc.argtypes = [C.c_void_p, C.POINTER(Diag)]
         L.ocn_synchronize.argtypes = [C.c_void_p]
         L.ocn_checkpoint_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
         L.ocn_checkpoint_save.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
