@@ -17,18 +17,20 @@ ORC_ETA_MEAN, ORC_UBT_MEAN, ORC_VBT_MEAN, ORC_W = 6, 7, 8, 9
 ORC_GU_PREV, ORC_GV_PREV, ORC_GT_PREV = 10, 11, 12
 ORC_TAUX, ORC_TAUY, ORC_TSTAR, ORC_P, ORC_KAPPA, ORC_VISC = 13, 14, 15, 16, 17, 18
 TERM_ADV, TERM_COR, TERM_PGF, TERM_WIND, TERM_RESTORE, TERM_ALL = 1, 2, 4, 8, 16, 31
-NDIAG = 17
+NDIAG = 18
 DIAG_NAMES = ["step", "time", "tracer_content", "volume", "volume_mean", "kinetic_energy",
               "max_abs_u", "max_abs_v", "max_abs_w", "t_min", "t_max", "eta_min", "eta_max",
-              "nonfinite", "cfl_adv", "wet_area", "cfl_bt"]
+              "nonfinite", "cfl_adv", "wet_area", "cfl_bt", "salt_content"]
 STAGE_MIXING, STAGE_TENDENCY, STAGE_BAROTROPIC, STAGE_COLUMN = 0, 1, 2, 3
 
 FIELD_IDS = {"u": ORC_U, "v": ORC_V, "T": ORC_T, "eta": ORC_ETA, "U": ORC_UBT, "V": ORC_VBT,
              "eta_mean": ORC_ETA_MEAN, "U_mean": ORC_UBT_MEAN, "V_mean": ORC_VBT_MEAN,
              "w": ORC_W, "gu_prev": ORC_GU_PREV, "gv_prev": ORC_GV_PREV, "gt_prev": ORC_GT_PREV,
              "taux": ORC_TAUX, "tauy": ORC_TAUY, "tstar": ORC_TSTAR, "p": ORC_P, "kappa": ORC_KAPPA,
-             "visc": ORC_VISC, "u_pred": 19, "v_pred": 20, "T_pred": 21, "gU_slow": 22, "gV_slow": 23}
-FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "p", "kappa", "visc", "u_pred", "v_pred", "T_pred"}
+             "visc": ORC_VISC, "u_pred": 19, "v_pred": 20, "T_pred": 21, "gU_slow": 22, "gV_slow": 23,
+             "S": 24, "gs_prev": 25, "sstar": 26, "S_pred": 27}
+FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "p", "kappa", "visc", "u_pred", "v_pred", "T_pred",
+             "S", "gs_prev", "S_pred"}
 # Richardson-number mixing constants of the reading (Pacanowski and Philander 1981 form)
 RI_DEFAULTS = {"nu0": 1e-2, "alpha": 5.0, "nu_b": 1e-4, "kappa_b": 1e-5, "conv": 1.0}
 
@@ -36,12 +38,15 @@ RI_DEFAULTS = {"nu0": 1e-2, "alpha": 5.0, "nu_b": 1e-4, "kappa_b": 1e-5, "conv":
 class OrcDesc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("periodic_x", C.c_int32), ("periodic_y", C.c_int32), ("coords", C.c_int32),
-                ("n_substeps", C.c_int32), ("reserved", C.c_int32),
+                ("n_substeps", C.c_int32), ("salinity", C.c_int32),
                 ("x0", C.c_double), ("y0", C.c_double), ("dx", C.c_double), ("dy", C.c_double),
                 ("f0", C.c_double), ("beta", C.c_double), ("radius", C.c_double), ("omega", C.c_double),
                 ("dt", C.c_double), ("chi", C.c_double), ("g", C.c_double), ("alpha", C.c_double),
                 ("rho0", C.c_double), ("t_ref", C.c_double), ("kappa", C.c_double),
-                ("restore_tau", C.c_double), ("pgf_weight", C.c_double)]
+                ("restore_tau", C.c_double), ("pgf_weight", C.c_double),
+                ("eos_a0", C.c_double), ("eos_b0", C.c_double), ("eos_lambda1", C.c_double),
+                ("eos_lambda2", C.c_double), ("eos_mu1", C.c_double), ("eos_mu2", C.c_double),
+                ("eos_nu", C.c_double), ("eos_t0", C.c_double), ("eos_s0", C.c_double)]
 
 
 _lib = None
@@ -68,7 +73,9 @@ def lib():
         L.orc_step.argtypes = [C.c_void_p, C.c_int]
         L.orc_run_stage.argtypes = [C.c_void_p, C.c_int]
         L.orc_diagnostics.argtypes = [C.c_void_p, _D]
-        L.orc_eval_tendencies.argtypes = [C.c_void_p, C.c_int, _D, _D, _D]
+        L.orc_eval_tendencies.argtypes = [C.c_void_p, C.c_int, _D, _D, _D, _D]
+        L.orc_buoyancy.restype = C.c_double
+        L.orc_buoyancy.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double]
         for name in ("orc_weno5z",):
             getattr(L, name).restype = C.c_double
             getattr(L, name).argtypes = [C.c_double] * 5
@@ -112,6 +119,9 @@ def desc_from_workload(w) -> OrcDesc:
     d.kappa = w.kappa
     d.restore_tau = w.restore_days * 86400.0 if w.restore_days > 0 else 0.0
     d.pgf_weight = w.pgf_weight
+    d.salinity = int(w.salinity)
+    (d.eos_a0, d.eos_b0, d.eos_lambda1, d.eos_lambda2, d.eos_mu1, d.eos_mu2, d.eos_nu, d.eos_t0,
+     d.eos_s0) = w.eos
     return d
 
 
@@ -136,6 +146,9 @@ class OracleModel:
         m.set("taux", inp["taux"])
         m.set("tauy", inp["tauy"])
         m.set("tstar", inp["tstar"])
+        if w.salinity:
+            m.set("S", inp["S0"])
+            m.set("sstar", inp["sstar"])
         return m
 
     def close(self):
@@ -211,11 +224,16 @@ class OracleModel:
         lib().orc_closure_kappa(self._h, _dptr(Y), kappa0, _dptr(kw))
         return kw
 
-    def tendencies(self, terms: int = TERM_ALL):
+    def tendencies(self, terms: int = TERM_ALL, salinity: bool = False):
+        """(gu, gv, gt), or (gu, gv, gt, gs) with salinity=True."""
         shape = (self.nz, self.ny, self.nx)
-        gu, gv, gt = (np.zeros(shape) for _ in range(3))
-        lib().orc_eval_tendencies(self._h, terms, _dptr(gu), _dptr(gv), _dptr(gt))
-        return gu, gv, gt
+        gu, gv, gt, gs = (np.zeros(shape) for _ in range(4))
+        lib().orc_eval_tendencies(self._h, terms, _dptr(gu), _dptr(gv), _dptr(gt), _dptr(gs))
+        return (gu, gv, gt, gs) if salinity else (gu, gv, gt)
+
+    def buoyancy(self, T: float, S: float, z: float) -> float:
+        """b = -g rho'/rho0 of water (T, S) at depth z (m) under the model's equation of state."""
+        return lib().orc_buoyancy(self._h, float(T), float(S), float(z))
 
 
 def weno5z(a, b, c, d, e) -> float:

@@ -40,6 +40,8 @@ struct orc_model {
     double *gu_prev, *gv_prev, *gt_prev;      /* AB2 history */
     double *eta_mean, *U_mean, *V_mean;       /* substep averages of the last step */
     double *us, *vs, *ts;                     /* AB2-predicted u*, v*, T* (tendency stage output) */
+    double *S, *gs_prev, *sstar, *ss;         /* salinity, its AB2 history, restoring target, S* */
+    double* zc;                               /* depth of each layer centre (m, positive down) */
     double *gU, *gV;                          /* barotropic slow forcing (tendency stage output) */
     double *taux, *tauy, *tstar;              /* surface forcing (N/m^2, N/m^2, degC) */
     double *kw;          /* prescribed diffusivity on z-faces (m^2/s), or NULL for the constant */
@@ -279,24 +281,58 @@ static void compute_w(const orc_model* m, const double* u, const double* v, doub
         }
 }
 
-/* Hydrostatic kinematic pressure p with dp/dz = b, b = g alpha (T - t_ref), and
- * p = 0 at the rigid-lid surface z = 0 (the surface-elevation part of the
- * pressure lives in the barotropic mode). Integrated downward: half the top
- * layer with the top buoyancy, then the trapezoid rule between adjacent layer
- * centres (centre spacing times the mean buoyancy). This is the first of the
- * two 3D diagnostics of Sec. 5.1. */
-static void compute_p(const orc_model* m, const double* T, double* p) {
-    const double ga = m->d.g * m->d.alpha;
+/* Equation of state. Temperature only (the benchmarked configurations): a
+ * linear buoyancy b = g alpha (T - t_ref). With salinity (reading: the paper's
+ * realistic runs carry heat and salt, Sec. 6, and name no equation of state;
+ * the simplified seawater equation of state of Roquet et al. 2015 is taken):
+ * the density anomaly rho' = -a0 (1 + lambda1 Ta/2 + mu1 z) Ta
+ * + b0 (1 - lambda2 Sa/2 - mu2 z) Sa - nu Ta Sa with Ta = T - t0, Sa = S - s0
+ * and z the depth, quadratic in T and S (cabbeling) with pressure-dependent
+ * expansion coefficients (thermobaricity), and b = -g rho' / rho0. */
+double orc_buoyancy(const orc_model* m, double T, double S, double z) {
+    const orc_desc* d = &m->d;
+    if (!d->salinity) return d->g * d->alpha * (T - d->t_ref);
+    const double ta = T - d->eos_t0, sa = S - d->eos_s0;
+    const double rho = -d->eos_a0 * (1.0 + 0.5 * d->eos_lambda1 * ta + d->eos_mu1 * z) * ta
+                     + d->eos_b0 * (1.0 - 0.5 * d->eos_lambda2 * sa - d->eos_mu2 * z) * sa
+                     - d->eos_nu * ta * sa;
+    return -d->g * rho / d->rho0;
+}
+
+/* buoyancy of cell (i, j, k) at its own depth */
+static double cell_b(const orc_model* m, const double* T, const double* S, int i, int j, int k) {
+    const size_t c = id3(m, i, j, k);
+    return orc_buoyancy(m, T[c], S ? S[c] : 0.0, m->zc[k]);
+}
+
+/* Squared buoyancy frequency on the interior face below layer k: the buoyancy
+ * difference of the two layers, both taken at the face's depth (with the
+ * linear equation of state g alpha (T_k - T_{k-1})), over the centre spacing. */
+static double face_n2(const orc_model* m, const double* T, const double* S, int i, int j, int k) {
+    const double dzc = 0.5 * (m->dz[k - 1] + m->dz[k]);
+    const size_t c = id3(m, i, j, k), b = id3(m, i, j, k - 1);
+    if (!m->d.salinity) return m->d.g * m->d.alpha * (T[c] - T[b]) / dzc;
+    const double zf = m->zc[k] + 0.5 * m->dz[k];
+    return (orc_buoyancy(m, T[c], S[c], zf) - orc_buoyancy(m, T[b], S[b], zf)) / dzc;
+}
+
+/* Hydrostatic kinematic pressure p with dp/dz = b and p = 0 at the rigid-lid
+ * surface z = 0 (the surface-elevation part of the pressure lives in the
+ * barotropic mode). Integrated downward: half the top layer with the top
+ * buoyancy, then the trapezoid rule between adjacent layer centres (centre
+ * spacing times the mean buoyancy). This is the first of the two 3D
+ * diagnostics of Sec. 5.1. S is ignored (and may be NULL) without salinity. */
+static void compute_p(const orc_model* m, const double* T, const double* S, double* p) {
     for (int j = 0; j < m->ny; ++j)
         for (int i = 0; i < m->nx; ++i) {
             double pk = 0.0;
             for (int k = m->nz - 1; k >= 0; --k) {
                 if (!cell_wet(m, i, j, k)) { p[id3(m, i, j, k)] = 0.0; continue; }
-                double bk = ga * (T[id3(m, i, j, k)] - m->d.t_ref);
+                double bk = cell_b(m, T, S, i, j, k);
                 if (k == m->nz - 1) {
                     pk = -0.5 * m->dz[k] * bk;
                 } else {
-                    double bk1 = ga * (T[id3(m, i, j, k + 1)] - m->d.t_ref);
+                    double bk1 = cell_b(m, T, S, i, j, k + 1);
                     double dzc = 0.5 * (m->dz[k] + m->dz[k + 1]);
                     pk = pk - dzc * 0.5 * (bk + bk1);
                 }
@@ -408,13 +444,31 @@ static double cell_ubar(const orc_model* m, const double* u, int i, int j, int k
     return 0.5 * (at3(m, u, i, j, k) + at3(m, u, i + 1, j, k));
 }
 
-void orc_eval_tendencies(const orc_model* m, int terms, double* gu, double* gv, double* gt) {
+/* Tendency of a tracer (T or S) in a wet cell: flux-form advection and, in
+ * the top layer, restoring towards the target field. */
+static double tracer_tendency(const orc_model* m, int terms, const double* q, const double* qstar,
+                              const double* w3, int i, int j, int k) {
+    double g = 0.0;
+    if (!cell_wet(m, i, j, k)) return 0.0;
+    const double vol = area_c(m, j) * m->dz[k];
+    if (terms & ORC_TERM_ADV) {
+        double div = tracer_xflux(m, m->u, q, i + 1, j, k) - tracer_xflux(m, m->u, q, i, j, k)
+                   + tracer_yflux(m, m->v, q, i, j + 1, k) - tracer_yflux(m, m->v, q, i, j, k)
+                   + tracer_zflux(m, w3, q, i, j, k + 1) - tracer_zflux(m, w3, q, i, j, k);
+        g += -div / vol;
+    }
+    if ((terms & ORC_TERM_RESTORE) && k == m->nz - 1 && m->d.restore_tau > 0.0)
+        g += (qstar[id2(m, i, j)] - q[id3(m, i, j, k)]) / m->d.restore_tau;
+    return g;
+}
+
+void orc_eval_tendencies(const orc_model* m, int terms, double* gu, double* gv, double* gt, double* gs) {
     const size_t n3 = (size_t)m->nx * m->ny * m->nz;
     const size_t nf = (size_t)m->nx * m->ny * (m->nz + 1);
     double* w3 = (double*)calloc(nf, sizeof(double));
     double* p = (double*)calloc(n3, sizeof(double));
     compute_w(m, m->u, m->v, w3);
-    compute_p(m, m->T, p);
+    compute_p(m, m->T, m->S, p);
     const double* u = m->u;
     const double* v = m->v;
     const double* T = m->T;
@@ -426,20 +480,10 @@ void orc_eval_tendencies(const orc_model* m, int terms, double* gu, double* gv, 
             for (int i = 0; i < m->nx; ++i) {
                 const size_t c = id3(m, i, j, k);
                 const double dz = m->dz[k];
-                /* tracer */
-                double g = 0.0;
-                if (cell_wet(m, i, j, k)) {
-                    double vol = area_c(m, j) * dz;
-                    if (terms & ORC_TERM_ADV) {
-                        double div = tracer_xflux(m, u, T, i + 1, j, k) - tracer_xflux(m, u, T, i, j, k)
-                                   + tracer_yflux(m, v, T, i, j + 1, k) - tracer_yflux(m, v, T, i, j, k)
-                                   + tracer_zflux(m, w3, T, i, j, k + 1) - tracer_zflux(m, w3, T, i, j, k);
-                        g += -div / vol;
-                    }
-                    if ((terms & ORC_TERM_RESTORE) && k == top && m->d.restore_tau > 0.0)
-                        g += (m->tstar[id2(m, i, j)] - T[c]) / m->d.restore_tau;
-                }
-                gt[c] = g;
+                /* tracers */
+                gt[c] = tracer_tendency(m, terms, T, m->tstar, w3, i, j, k);
+                if (gs && m->d.salinity) gs[c] = tracer_tendency(m, terms, m->S, m->sstar, w3, i, j, k);
+                double g;
                 /* u momentum */
                 g = 0.0;
                 if (u_wet(m, i, j, k)) {
@@ -516,7 +560,8 @@ static double face_kappa(const orc_model* m, int kind, int i, int j, int kf) {
  * parameterization of shear and convective mixing; it gives no formula, so
  * the Pacanowski-Philander (1981) form is the reading). On an interior wet
  * face k of column (i, j), from the state at the start of the step:
- *   N^2 = g alpha (T_k - T_{k-1}) / dzc_k,
+ *   N^2 = g alpha (T_k - T_{k-1}) / dzc_k (with salinity, the buoyancy
+ *         difference of the two layers at the face's depth over dzc_k),
  *   S^2 = ((uc_k - uc_{k-1})^2 + (vc_k - vc_{k-1})^2) / dzc_k^2, with uc, vc
  *         the velocities averaged to the cell centre (a dry or closed-edge
  *         face counts as 0),
@@ -529,7 +574,6 @@ static void richardson_faces(orc_model* m) {
     const size_t n3 = (size_t)nx * ny * nz;
     if (!m->kw) m->kw = (double*)malloc(sizeof(double) * n3);
     if (!m->kvw) m->kvw = (double*)malloc(sizeof(double) * n3);
-    const double ga = m->d.g * m->d.alpha;
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -546,7 +590,7 @@ static void richardson_faces(orc_model* m) {
                         vc[q] = 0.5 * (m->v[id3(m, i, j, kk)] + vn);
                     }
                     const double dzc = 0.5 * (m->dz[k - 1] + m->dz[k]);
-                    const double n2 = ga * (m->T[id3(m, i, j, k)] - m->T[id3(m, i, j, k - 1)]) / dzc;
+                    const double n2 = face_n2(m, m->T, m->S, i, j, k);
                     const double du = uc[1] - uc[0], dv = vc[1] - vc[0];
                     const double s2 = (du * du + dv * dv) / (dzc * dzc);
                     if (n2 < 0.0) {
@@ -610,8 +654,11 @@ static void stage_mixing(orc_model* m) {
             for (int j = 0; j < ny; ++j)
                 for (int i = 0; i < nx; ++i) {
                     double kap = 0.0;
-                    if (w_wet(m, i, j, k))
-                        kap = (m->T[id3(m, i, j, k)] < m->T[id3(m, i, j, k - 1)]) ? m->kappa_conv : m->d.kappa;
+                    if (w_wet(m, i, j, k)) {
+                        const int unstable = m->d.salinity ? face_n2(m, m->T, m->S, i, j, k) < 0.0
+                                                           : m->T[id3(m, i, j, k)] < m->T[id3(m, i, j, k - 1)];
+                        kap = unstable ? m->kappa_conv : m->d.kappa;
+                    }
                     m->kw[id3(m, i, j, k)] = kap;
                 }
     }
@@ -628,10 +675,12 @@ static void stage_tendency(orc_model* m) {
     double* gu = (double*)malloc(sizeof(double) * n3);
     double* gv = (double*)malloc(sizeof(double) * n3);
     double* gt = (double*)malloc(sizeof(double) * n3);
+    double* gs = m->d.salinity ? (double*)malloc(sizeof(double) * n3) : NULL;
+    double* sfb = m->d.salinity ? (double*)malloc(sizeof(double) * n3) : NULL;
 
     /* tendencies G^n of the current state: advection, Coriolis, wind and
      * restoring; the baroclinic pressure gradient is added below */
-    orc_eval_tendencies(m, ORC_TERM_ALL & ~ORC_TERM_PGF, gu, gv, gt);
+    orc_eval_tendencies(m, ORC_TERM_ALL & ~ORC_TERM_PGF, gu, gv, gt, gs);
 
     /* AB2 predictor: Ghat = (3/2+chi) G^n - (1/2+chi) G^{n-1}; forward Euler on
      * the first step (reading of the "second-order Adams-Bashforth" start).
@@ -641,6 +690,12 @@ static void stage_tendency(orc_model* m) {
         m->ts[c] = m->T[c] + dt * ht;
         tfb[c] = m->T[c] + eps * dt * ht;
         m->gt_prev[c] = gt[c];
+        if (gs) {  /* salinity likewise */
+            const double hs = m->first_step ? gs[c] : (1.5 + chi) * gs[c] - (0.5 + chi) * m->gs_prev[c];
+            m->ss[c] = m->S[c] + dt * hs;
+            sfb[c] = m->S[c] + eps * dt * hs;
+            m->gs_prev[c] = gs[c];
+        }
     }
 
     /* Forward-backward pressure gradient (reading of the implicit-explicit AB2
@@ -652,7 +707,7 @@ static void stage_tendency(orc_model* m) {
      * meridians reach at the benchmarked resolutions; with epsilon = 3/4 the
      * coupled pair stays damped up to about 1.3. The AB2 history of u and v
      * holds their other terms only. */
-    compute_p(m, tfb, pfb);
+    compute_p(m, tfb, sfb, pfb);
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -680,7 +735,7 @@ static void stage_tendency(orc_model* m) {
             m->gU[id2(m, i, j)] = su;
             m->gV[id2(m, i, j)] = sv;
         }
-    free(tfb); free(pfb); free(gu); free(gv); free(gt);
+    free(tfb); free(pfb); free(gu); free(gv); free(gt); free(gs); free(sfb);
 }
 
 /* Stage 2: barotropic substeps (Sec. 5.3: explicit sub-cycling of the 2D
@@ -768,6 +823,7 @@ static void stage_column(orc_model* m) {
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             implicit_column(m, 0, i, j, m->ts, m->T);
+            if (m->d.salinity) implicit_column(m, 0, i, j, m->ss, m->S);
             implicit_column(m, 1, i, j, m->us, uss);
             implicit_column(m, 2, i, j, m->vs, vss);
         }
@@ -821,7 +877,9 @@ void orc_step(orc_model* m, int n) {
  * (wet cells), [11] eta min, [12] eta max (wet columns), [13] non-finite count,
  * [14] advective CFL max(|u| dt/dx, |v| dt/dy, |w| dt/dz_c), [15] sum of A_c
  * over wet columns, [16] barotropic CFL of a substep max sqrt(g H) dtau
- * sqrt(1/dx^2 + 1/dy^2) over wet columns. */
+ * sqrt(1/dx^2 + 1/dy^2) over wet columns, [17] salt content sum V_c S (0
+ * without salinity); [13] counts cells with a non-finite u, v, T (or S) and
+ * columns with a non-finite eta, U or V. */
 void orc_diagnostics(const orc_model* m, double* out) {
     const int nx = m->nx, ny = m->ny, nz = m->nz;
     const size_t n3 = (size_t)nx * ny * nz, n2 = (size_t)nx * ny;
@@ -837,7 +895,9 @@ void orc_diagnostics(const orc_model* m, double* out) {
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t c = id3(m, i, j, k);
-                if (!isfinite(m->u[c]) || !isfinite(m->v[c]) || !isfinite(m->T[c])) nonfinite += 1;
+                if (!isfinite(m->u[c]) || !isfinite(m->v[c]) || !isfinite(m->T[c]) ||
+                    (m->d.salinity && !isfinite(m->S[c])))
+                    nonfinite += 1;
                 if (cell_wet(m, i, j, k)) {
                     buf[n++] = area_c(m, j) * m->dz[k] * m->T[c];
                     if (m->T[c] < tmin) tmin = m->T[c];
@@ -909,6 +969,14 @@ void orc_diagnostics(const orc_model* m, double* out) {
             if (c > cflbt) cflbt = c;
         }
     out[16] = cflbt;
+    /* salt content sum V_c S over wet cells (0 without salinity) */
+    n = 0;
+    if (m->d.salinity)
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i)
+                    if (cell_wet(m, i, j, k)) buf[n++] = area_c(m, j) * m->dz[k] * m->S[id3(m, i, j, k)];
+    out[17] = orc_neumaier_sum(buf, (int64_t)n);
 
     out[0] = (double)m->step;
     out[1] = m->time;
@@ -935,11 +1003,20 @@ orc_model* orc_create(const orc_desc* d, const double* dz, const int32_t* kbotto
         int32_t kb = kbottom ? kbottom[c] : m->nz;
         m->kb[c] = kb < 0 ? 0 : (kb > m->nz ? m->nz : kb);
     }
-    double** f3[] = {&m->u, &m->v, &m->T, &m->gu_prev, &m->gv_prev, &m->gt_prev, &m->us, &m->vs, &m->ts};
+    double** f3[] = {&m->u, &m->v, &m->T, &m->gu_prev, &m->gv_prev, &m->gt_prev, &m->us, &m->vs, &m->ts,
+                     &m->S, &m->gs_prev, &m->ss};
     for (size_t q = 0; q < sizeof(f3) / sizeof(f3[0]); ++q) *f3[q] = (double*)calloc(n3, sizeof(double));
     double** f2[] = {&m->eta, &m->U, &m->V, &m->eta_mean, &m->U_mean, &m->V_mean, &m->taux, &m->tauy, &m->tstar,
-                     &m->gU, &m->gV};
+                     &m->gU, &m->gV, &m->sstar};
     for (size_t q = 0; q < sizeof(f2) / sizeof(f2[0]); ++q) *f2[q] = (double*)calloc(n2, sizeof(double));
+    m->zc = (double*)malloc(sizeof(double) * m->nz);
+    {
+        double depth = 0.0;  /* from the surface down */
+        for (int k = m->nz - 1; k >= 0; --k) {
+            m->zc[k] = depth + 0.5 * m->dz[k];
+            depth += m->dz[k];
+        }
+    }
     m->first_step = 1;
     return m;
 }
@@ -948,7 +1025,7 @@ void orc_destroy(orc_model* m) {
     if (!m) return;
     double* all[] = {m->dz, m->u, m->v, m->T, m->gu_prev, m->gv_prev, m->gt_prev, m->eta, m->U, m->V,
                      m->eta_mean, m->U_mean, m->V_mean, m->taux, m->tauy, m->tstar, m->kw, m->kvw,
-                     m->us, m->vs, m->ts, m->gU, m->gV};
+                     m->us, m->vs, m->ts, m->gU, m->gV, m->S, m->gs_prev, m->sstar, m->ss, m->zc};
     for (size_t q = 0; q < sizeof(all) / sizeof(all[0]); ++q) free(all[q]);
     free(m->kb);
     free(m);
@@ -977,6 +1054,10 @@ static double* field_ptr(orc_model* m, int f, size_t* n) {
     case ORC_T_PRED: *n = n3; return m->ts;
     case ORC_GU_SLOW: *n = n2; return m->gU;
     case ORC_GV_SLOW: *n = n2; return m->gV;
+    case ORC_S: *n = n3; return m->S;
+    case ORC_GS_PREV: *n = n3; return m->gs_prev;
+    case ORC_SSTAR: *n = n2; return m->sstar;
+    case ORC_S_PRED: *n = n3; return m->ss;
     default: return NULL;
     }
 }
@@ -1017,7 +1098,7 @@ int orc_get_field(orc_model* m, int f, double* dst) {
         return 0;
     }
     if (f == ORC_P) {
-        compute_p(m, m->T, dst);
+        compute_p(m, m->T, m->S, dst);
         return 0;
     }
     if (f == ORC_KAPPA) {  /* the tracer diffusivity in use on every face (0 where dry) */
@@ -1074,7 +1155,8 @@ int orc_get_first_step(const orc_model* m) { return m->first_step; }
  *   [0, nz)        T at layer centres
  *   [nz, 2nz)      u at centres, mean of the west and east faces
  *   [2nz, 3nz)     v at centres, mean of the south and north faces
- *   [3nz, 4nz)     N^2 = g alpha dT/dz on face k (slot k; the bottom face k = 0
+ *   [3nz, 4nz)     N^2 on face k (g alpha dT/dz, or from the equation of state
+ *                  with salinity; slot k; the bottom face k = 0
  *                  and faces without water on both sides count as dry)
  *   4nz, 4nz+1     wind stress at the centre, means of the two faces' tau_x, tau_y
  *   4nz+2          surface restoring flux dz_top (T* - T_top) / tau (K m/s), 0 when off
@@ -1095,10 +1177,7 @@ int orc_closure_features(const orc_model* m, int din, const double* mean, const 
                 PUT(k, at3(m, m->T, i, j, k));
                 PUT(nz + k, 0.5 * (at3(m, m->u, i, j, k) + at3(m, m->u, i + 1, j, k)));
                 PUT(2 * nz + k, 0.5 * (at3(m, m->v, i, j, k) + at3(m, m->v, i, j + 1, k)));
-                if (w_wet(m, i, j, k)) {
-                    const double dzc = 0.5 * (m->dz[k - 1] + m->dz[k]);
-                    PUT(3 * nz + k, m->d.g * m->d.alpha * (at3(m, m->T, i, j, k) - at3(m, m->T, i, j, k - 1)) / dzc);
-                }
+                if (w_wet(m, i, j, k)) PUT(3 * nz + k, face_n2(m, m->T, m->S, i, j, k));
             }
             PUT(4 * nz, 0.5 * (at2(m, m->taux, i, j) + at2(m, m->taux, i + 1, j)));
             PUT(4 * nz + 1, 0.5 * (at2(m, m->tauy, i, j) + at2(m, m->tauy, i, j + 1)));

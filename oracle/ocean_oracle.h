@@ -26,7 +26,9 @@ typedef struct orc_desc {
     int32_t periodic_x, periodic_y;/* 1 = periodic, 0 = bounded by walls          */
     int32_t coords;                /* 0 = Cartesian beta-plane, 1 = lat-lon sphere */
     int32_t n_substeps;            /* barotropic substeps per baroclinic step     */
-    int32_t reserved;
+    int32_t salinity;              /* 1: salinity S is carried and the equation of
+                                      state is the nonlinear eos_* form; 0: T only,
+                                      linear in T with alpha                      */
     double x0, y0, dx, dy;         /* Cartesian: metres. lat-lon: lon0, lat_south, dlon, dlat in degrees */
     double f0, beta;               /* beta-plane Coriolis f = f0 + beta (y - Ly/2) */
     double radius, omega;          /* sphere radius (m) and rotation rate (1/s)   */
@@ -36,6 +38,10 @@ typedef struct orc_desc {
     double restore_tau;            /* surface restoring time (s); <= 0 turns it off */
     double pgf_weight;             /* epsilon: the pressure gradient of the momentum step is
                                       taken from T^n + epsilon dt Ghat_T (0..1)            */
+    /* equation of state with salinity (density anomaly in kg/m^3, z the depth in
+     * m, Ta = T - eos_t0, Sa = S - eos_s0):
+     * rho' = -a0 (1 + lambda1 Ta / 2 + mu1 z) Ta + b0 (1 - lambda2 Sa / 2 - mu2 z) Sa - nu Ta Sa */
+    double eos_a0, eos_b0, eos_lambda1, eos_lambda2, eos_mu1, eos_mu2, eos_nu, eos_t0, eos_s0;
 } orc_desc;
 
 typedef struct orc_model orc_model;
@@ -52,7 +58,9 @@ enum {
     ORC_VISC = 18,   /* z-face momentum coefficient on tracer faces (get only): the viscosity
                         of Richardson-number mixing, else the diffusivity */
     ORC_U_PRED = 19, ORC_V_PRED = 20, ORC_T_PRED = 21,  /* AB2-predicted u*, v*, T* */
-    ORC_GU_SLOW = 22, ORC_GV_SLOW = 23                  /* barotropic slow forcing (m^2/s^2) */
+    ORC_GU_SLOW = 22, ORC_GV_SLOW = 23,                 /* barotropic slow forcing (m^2/s^2) */
+    ORC_S = 24, ORC_GS_PREV = 25,                       /* salinity (g/kg) and its AB2 history */
+    ORC_SSTAR = 26, ORC_S_PRED = 27                     /* surface restoring salinity; predicted S* */
 };
 
 /* Stages of one step, in order (orc_run_stage): the diffusivity diagnosis of
@@ -67,7 +75,7 @@ enum { ORC_TERM_ADV = 1, ORC_TERM_COR = 2, ORC_TERM_PGF = 4, ORC_TERM_WIND = 8,
        ORC_TERM_RESTORE = 16, ORC_TERM_ALL = 31 };
 
 /* Number of doubles written by orc_diagnostics. */
-#define ORC_NDIAG 17
+#define ORC_NDIAG 18
 
 orc_model* orc_create(const orc_desc* d, const double* dz, const int32_t* kbottom);
 void       orc_destroy(orc_model* m);
@@ -90,7 +98,12 @@ int        orc_run_stage(orc_model* m, int stage);
 void       orc_diagnostics(const orc_model* m, double* out);
 
 /* Stage-level entry points used by the physics and unit pins. */
-void   orc_eval_tendencies(const orc_model* m, int terms, double* gu, double* gv, double* gt);
+/* gs (salinity tendency) may be NULL; it is written only when salinity is on. */
+void   orc_eval_tendencies(const orc_model* m, int terms, double* gu, double* gv, double* gt, double* gs);
+/* Buoyancy b = -g rho'/rho0 of water with temperature T and salinity S at depth
+ * z (m, positive down) under the model's equation of state (S ignored when
+ * salinity is off, where b = g alpha (T - t_ref)). */
+double orc_buoyancy(const orc_model* m, double T, double S, double z);
 double orc_weno5z(double a, double b, double c, double d, double e);
 double orc_weno3(double b, double c, double d);
 double orc_reconstruct(const double* s, const int32_t* ok);

@@ -19,7 +19,7 @@ so any element can be drawn independently of the others. A draw is
 mix64(base(seed, stream) + (n + 1) * GOLDEN) with base = mix64(seed ^ (stream << 32)).
 Uniforms take the top 53 bits; normals use Box-Muller (cosine branch) on the
 uniform pair drawn at counters 2n and 2n+1. Streams: 0 temperature noise,
-1 bathymetry, 2 ensemble-member parameters.
+1 bathymetry, 2 ensemble-member parameters, 3 salinity noise.
 """
 from __future__ import annotations
 
@@ -38,6 +38,7 @@ _M2 = np.uint64(0x94D049BB133111EB)
 STREAM_TEMPERATURE = 0
 STREAM_BATHYMETRY = 1
 STREAM_MEMBERS = 2
+STREAM_SALINITY = 3
 
 
 def _mix64(z: np.ndarray) -> np.ndarray:
@@ -126,6 +127,17 @@ class Workload:
     strat_scale: float = 1000.0
     noise_std: float = 0.01
     seed: int = 0
+    # salinity and the nonlinear equation of state (off in the benchmarked
+    # configurations, which are temperature-only with a linear equation of state)
+    salinity: bool = False
+    # S = sal_s0 - sal_ds exp(z / strat_scale) + noise_std_s N(0, 1): fresher at the surface
+    sal_s0: float = 35.0
+    sal_ds: float = 1.0
+    noise_std_s: float = 0.01
+    # (a0, b0, lambda1, lambda2, mu1, mu2, nu, t0, s0) of the simplified seawater
+    # equation of state (Roquet et al. 2015 form): kg/m^3/K, kg/m^3/(g/kg), 1/K,
+    # 1/(g/kg), 1/(K m), 1/((g/kg) m), kg/m^3/(K g/kg), degC, g/kg
+    eos: tuple = (1.6550e-1, 7.6554e-1, 5.9520e-2, 5.4914e-4, 1.4970e-4, 1.1090e-5, 2.4341e-3, 10.0, 35.0)
 
     @property
     def cells(self) -> int:
@@ -302,10 +314,41 @@ def restoring_target(w: Workload) -> np.ndarray:
     return np.repeat(prof[:, None], w.nx, axis=1).astype(np.float64)
 
 
+def initial_salinity(w: Workload) -> np.ndarray:
+    """S = sal_s0 - sal_ds exp(z / strat_scale) + noise_std_s N(0, 1), [nz, ny, nx]:
+    fresher water at the surface (stabilising, like the temperature profile).
+
+    The noise of cell (i, j, k) is the normal deviate at counter i + nx (j + ny k)
+    of the salinity stream.
+    """
+    zc = layer_centre_z(w)
+    out = np.empty((w.nz, w.ny, w.nx), dtype=np.float64)
+    plane = np.arange(w.nx * w.ny, dtype=np.uint64)
+    for k in range(w.nz):
+        base = w.sal_s0 - w.sal_ds * math.exp(zc[k] / w.strat_scale)
+        n = normal(w.seed, STREAM_SALINITY, plane + np.uint64(k * w.nx * w.ny)) if w.noise_std_s else 0.0
+        out[k] = base + w.noise_std_s * np.reshape(n, (w.ny, w.nx)) if w.noise_std_s else base
+    return out
+
+
+def salinity_target(w: Workload) -> np.ndarray:
+    """Surface restoring salinity S* = 34 + 2 cos^2(lat) g/kg (sphere; the basin
+    mapped onto latitudes -90..90 on the beta-plane), [ny, nx]."""
+    if w.coords == "latlon":
+        _, lat = _centres_deg(w)
+        phi = np.radians(lat)
+    else:
+        ly = w.ny * w.dy
+        phi = math.pi * ((np.arange(w.ny) + 0.5) * w.dy - 0.5 * ly) / ly
+    prof = 34.0 + 2.0 * np.cos(phi) ** 2
+    return np.repeat(prof[:, None], w.nx, axis=1).astype(np.float64)
+
+
 def make_inputs(w: Workload) -> Dict[str, np.ndarray]:
-    """All inputs of a workload: dz, kbottom, T0, taux, tauy, tstar."""
+    """All inputs of a workload: dz, kbottom, T0, taux, tauy, tstar (and S0,
+    sstar with salinity)."""
     taux, tauy = wind_stress(w)
-    return {
+    out = {
         "dz": layer_thickness(w),
         "kbottom": wet_layers(w),
         "T0": initial_temperature(w),
@@ -313,3 +356,7 @@ def make_inputs(w: Workload) -> Dict[str, np.ndarray]:
         "tauy": tauy,
         "tstar": restoring_target(w),
     }
+    if w.salinity:
+        out["S0"] = initial_salinity(w)
+        out["sstar"] = salinity_target(w)
+    return out
