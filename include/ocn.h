@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define OCN_ABI_VERSION 2u
+#define OCN_ABI_VERSION 3u
 
 typedef enum {
     OCN_OK = 0,
@@ -82,7 +82,11 @@ typedef struct ocn_params {
                                  substeps per launch on an LDS tile whose halo is as
                                  wide as the substep count (the paper's wide
                                  barotropic halo, Sec. 5.3, applied within one GPU) */
-    int32_t reserved1;        /* must be 0                                          */
+    int32_t salinity;         /* 1: carry salinity S (advected, restored and diffused
+                                 like T) and take the buoyancy from the equation of
+                                 state eos[] below; 0: temperature only with the
+                                 linear b = g alpha (T - t_ref). Ensembles and the
+                                 closure network take temperature only.            */
     double dt;                /* baroclinic step (s)                                */
     double chi;               /* AB2 offset: G = (3/2+chi) G^n - (1/2+chi) G^{n-1}  */
     double g;                 /* gravity (m/s^2)                                    */
@@ -97,6 +101,14 @@ typedef struct ocn_params {
                                  backward treatment of internal gravity waves, a
                                  reading of the implicit-explicit AB2 of Sec. 5.2);
                                  the other momentum terms take AB2               */
+    double eos[9];            /* with salinity: a0, b0, lambda1, lambda2, mu1, mu2, nu,
+                                 t0, s0 of the simplified seawater equation of state
+                                 (Roquet et al. 2015 form, the paper's realistic runs
+                                 carrying heat and salt, Sec. 6): density anomaly
+                                 rho' = -a0 (1 + lambda1 Ta/2 + mu1 z) Ta
+                                 + b0 (1 - lambda2 Sa/2 - mu2 z) Sa - nu Ta Sa,
+                                 Ta = T - t0, Sa = S - s0, z the depth (m), and
+                                 b = -g rho'/rho0; unused without salinity         */
 } ocn_params;
 
 /* Field identifiers. */
@@ -132,7 +144,13 @@ typedef enum {
     OCN_FIELD_T_PRED = 21,    /* 3D AB2-predicted T* (degC)                          */
     OCN_FIELD_GU_SLOW = 22,   /* 2D barotropic slow forcing: depth integral of the
                                  AB2 u tendency (m^2/s^2), output of the tendency stage */
-    OCN_FIELD_GV_SLOW = 23    /* 2D the same for v                                   */
+    OCN_FIELD_GV_SLOW = 23,   /* 2D the same for v                                   */
+    OCN_FIELD_S = 24,         /* 3D salinity (g/kg), with salinity only; as for T the
+                                 first set fixes the per-level reference profile   */
+    OCN_FIELD_GS_PREV = 25,   /* 3D AB2 history of S                                */
+    OCN_FIELD_SSTAR = 26,     /* 2D surface restoring salinity (g/kg)               */
+    OCN_FIELD_S_PRED = 27,    /* 3D AB2-predicted S*                                 */
+    OCN_FIELD_SREF = 28       /* nz reference profile of the stored S anomaly         */
 } ocn_field;
 
 /* Stages of one step, in the order ocn_step runs them (paper Sec. 5.1-5.3;
@@ -167,10 +185,11 @@ typedef struct ocn_diag {
     double eta_min, eta_max;  /* over wet columns                                   */
     double cfl_adv;           /* max(|u| dt/dx, |v| dt/dy, |w| dt/dz)               */
     double wet_area;          /* sum A_c over wet columns (m^2)                     */
-    int64_t nonfinite;        /* cells with a non-finite u, v or T, plus columns with
+    int64_t nonfinite;        /* cells with a non-finite u, v, T (or S), plus columns with
                                  a non-finite eta, U or V                           */
     double cfl_bt;            /* barotropic CFL of a substep: max over wet columns of
                                  sqrt(g H) (dt / n_substeps) sqrt(1/dx^2 + 1/dy^2)   */
+    double salt_content;      /* sum V_c S over wet cells (g/kg m^3; 0 without salinity) */
 } ocn_diag;
 
 typedef struct ocn_grid ocn_grid;

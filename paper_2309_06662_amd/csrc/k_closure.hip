@@ -204,9 +204,28 @@ __global__ __launch_bounds__(FW * FG) void k_kappa_map(const DevState S, const f
     }
 }
 
+// Buoyancy of water (T, S) at depth z under the quadratic equation of state
+// (Roquet et al. 2015, the simplified form): rho' = -a0 (1 + lambda1 Ta/2 +
+// mu1 z) Ta + b0 (1 - lambda2 Sa/2 - mu2 z) Sa - nu Ta Sa, b = -g rho'/rho0.
+__device__ __forceinline__ double eos_buoyancy(const DevState& S, double T, double Sal, double z) {
+    const double* e = S.eos;  // a0, b0, lambda1, lambda2, mu1, mu2, nu, t0, s0
+    const double ta = T - e[7], sa = Sal - e[8];
+    const double rho = -e[0] * (1.0 + 0.5 * e[2] * ta + e[4] * z) * ta + e[1] * (1.0 - 0.5 * e[3] * sa - e[5] * z) * sa -
+                       e[6] * ta * sa;
+    return -S.g * rho / S.rho0;
+}
+
+// N^2 on the face below layer k with salinity: both layers' buoyancy at the
+// face's depth, differenced over the centre spacing.
+__device__ __forceinline__ double eos_face_n2(const DevState& S, int k, double tk, double sk, double tb, double sb) {
+    const double zf = S.zc[k] + 0.5 * S.dz[k];
+    return (eos_buoyancy(S, tk, sk, zf) - eos_buoyancy(S, tb, sb, zf)) / S.dzc[k];
+}
+
 // Convective adjustment: from the state at the start of the step, kappa_conv
-// on interior wet faces where the water above is colder, hence denser, than
-// the water below (N^2 < 0), kappa0 on the other wet faces, 0 on dry ones.
+// on interior wet faces where the water above is denser than the water below
+// (N^2 < 0: colder, with temperature alone), kappa0 on the other wet faces, 0
+// on dry ones.
 template <typename R>
 __global__ __launch_bounds__(FW) void k_convective(const DevState S, double kappa_conv, double kappa0) {
     const int i = blockIdx.x * FW + threadIdx.x, j = blockIdx.y;
@@ -214,21 +233,27 @@ __global__ __launch_bounds__(FW) void k_convective(const DevState S, double kapp
     const int nz = S.nz;
     const int kbot = nz - S.kb[idxk(S, i, j)];
     const R* T = f3<R>(S.t);
+    const R* Sf = f3<R>(S.s);
     R* kw = f3<R>(S.kw);
-    double below = 0.0;
+    double below = 0.0, sbelow = 0.0;
     for (int k = 0; k < nz; ++k) {
         const double tk = (k >= kbot) ? double(T[idx3(S, i, j, k)]) + S.tref[k] : 0.0;
-        const R val = (k > kbot) ? R(tk < below ? kappa_conv : kappa0) : R(0);
+        const double sk = (S.salinity && k >= kbot) ? double(Sf[idx3(S, i, j, k)]) + S.sref[k] : 0.0;
+        bool unstable = false;
+        if (k > kbot) unstable = S.salinity ? eos_face_n2(S, k, tk, sk, below, sbelow) < 0.0 : tk < below;
+        const R val = (k > kbot) ? R(unstable ? kappa_conv : kappa0) : R(0);
         kw[idx3(S, i, j, k)] = val;
         for_each_image(S, i, j, S.h, [&](int x, int y) { kw[idx3(S, x, y, k)] = val; });
         below = tk;
+        sbelow = sk;
     }
 }
 
 // Richardson-number mixing (Sec. 6 runs a Richardson-number-based mixing
 // parameterization without giving its form; the Pacanowski-Philander form is
 // the reading): on an interior wet face k, from the state at the start of
-// the step, N^2 = g alpha dT/dz and S^2 = |d(u_c, v_c)/dz|^2 with the
+// the step, N^2 = g alpha dT/dz (with salinity, the buoyancy difference of the
+// two layers at the face's depth over the centre spacing) and S^2 = |d(u_c, v_c)/dz|^2 with the
 // velocities averaged to the cell centre; where N^2 < 0 both coefficients are
 // conv, else with Ri = N^2 / max(S^2, 1e-16) and r = 1 / (1 + alpha Ri) the
 // viscosity is nu0 r^2 + nu_b and the diffusivity nu r + kappa_b. Dry faces
@@ -252,19 +277,21 @@ __global__ __launch_bounds__(RW) void k_richardson(const DevState S, const RiPar
     const int Kvn = jn >= 0 ? min(K, S.kb[idxk(S, i, jn)]) : 0;
     const int iec = ie >= 0 ? ie : i, jnc = jn >= 0 ? jn : j;
     const R* T = f3<R>(S.t);
+    const R* Sf = f3<R>(S.s);
     const R* U = f3<R>(S.u);
     const R* V = f3<R>(S.v);
     R* kw = f3<R>(S.kw);
     R* kv = f3<R>(S.kv);
     const double ga = S.g * S.alpha;
-    double tb = 0.0, ub = 0.0, vb = 0.0;  // the level below
+    double tb = 0.0, sb = 0.0, ub = 0.0, vb = 0.0;  // the level below
     constexpr int CH = 8;                 // levels whose loads are issued together
     for (int k0 = 0; k0 < nz; k0 += CH) {
-        R lT[CH], lUw[CH], lUe[CH], lVs[CH], lVn[CH];
+        R lT[CH], lUw[CH], lUe[CH], lVs[CH], lVn[CH], lS[CH];
 #pragma unroll
         for (int m = 0; m < CH; ++m) {
             const int k = min(k0 + m, nz - 1);  // clamped: valid addresses, results unused past nz
             lT[m] = T[idx3(S, i, j, k)];
+            lS[m] = S.salinity ? Sf[idx3(S, i, j, k)] : R(0);
             lUw[m] = U[idx3(S, i, j, k)];
             lUe[m] = U[idx3(S, iec, j, k)];
             lVs[m] = V[idx3(S, i, j, k)];
@@ -277,6 +304,7 @@ __global__ __launch_bounds__(RW) void k_richardson(const DevState S, const RiPar
             double kap = 0.0, nu = 0.0;
             if (k >= kbot) {
                 const double tk = double(lT[m]) + S.tref[k];
+                const double sk = S.salinity ? double(lS[m]) + S.sref[k] : 0.0;
                 const double uw = (k >= nz - Kuw) ? double(lUw[m]) : 0.0;
                 const double ue = (k >= nz - Kue) ? double(lUe[m]) : 0.0;
                 const double vs = (k >= nz - Kvs) ? double(lVs[m]) : 0.0;
@@ -284,7 +312,7 @@ __global__ __launch_bounds__(RW) void k_richardson(const DevState S, const RiPar
                 const double uk = 0.5 * (uw + ue), vk = 0.5 * (vs + vn);
                 if (k > kbot) {
                     const double dzc = S.dzc[k];
-                    const double n2 = ga * (tk - tb) / dzc;
+                    const double n2 = S.salinity ? eos_face_n2(S, k, tk, sk, tb, sb) : ga * (tk - tb) / dzc;
                     const double du = uk - ub, dv = vk - vb;
                     const double s2 = (du * du + dv * dv) / (dzc * dzc);
                     if (n2 < 0.0) {
@@ -298,6 +326,7 @@ __global__ __launch_bounds__(RW) void k_richardson(const DevState S, const RiPar
                     }
                 }
                 tb = tk;
+                sb = sk;
                 ub = uk;
                 vb = vk;
             }

@@ -68,7 +68,17 @@ __device__ __forceinline__ void copy_images(const DevState& S, R* dst, int i, in
     }
 }
 
-// Output of one solved column: T as is; u and v with the depth-mean
+// Field of a column solve and its predicted source: 0 = T, 1 = u, 2 = v, 3 = S.
+template <typename R>
+__device__ __forceinline__ R* col_dst(const DevState& S, int field) {
+    return f3<R>(field == 0 ? S.t : field == 1 ? S.u : field == 2 ? S.v : S.s);
+}
+template <typename R>
+__device__ __forceinline__ const R* col_src(const DevState& S, int field) {
+    return f3<R>(field == 0 ? S.ts : field == 1 ? S.us : field == 2 ? S.vs : S.ss);
+}
+
+// Output of one solved column: T and S as they are; u and v with the depth-mean
 // correction u = u** + (Ubar - sum dz u**) / H on wet layers, which also
 // leaves the column sum sum_k dz u m_u of the stored result (it seeds the
 // vertical transport of the next step). Periodic images are written too.
@@ -76,9 +86,9 @@ template <typename R, int NZB>
 __device__ __forceinline__ void column_store(const DevState& S, const R (&x)[NZB], const int i, const int j,
                                              const int field, const int kbot, const double colsum) {
     const int nz = S.nz;
-    R* dst = f3<R>(field == 0 ? S.t : field == 1 ? S.u : S.v);
+    R* dst = col_dst<R>(S, field);
     const long long o0 = idx3(S, i, j, 0), pl = S.plane3;
-    if (field == 0) {
+    if (field == 0 || field == 3) {
         R* q = dst + o0;
 #pragma unroll
         for (int k = 0; k < NZB; ++k) {
@@ -109,7 +119,7 @@ __device__ __forceinline__ void column_store(const DevState& S, const R (&x)[NZB
     store_wrapped2(S, field == 1 ? S.cu : S.cv, i, j, newsum);
 }
 
-// One block of W columns (bx, j) of one field: 0 = T, 1 = u, 2 = v.
+// One block of W columns (bx, j) of one field: 0 = T, 1 = u, 2 = v, 3 = S.
 // Backward Euler with the constant diffusivity, eliminated from the surface
 // down: r'_k = r_k - (c_k / b'_{k+1}) r'_{k+1}, then from the bottom layer up
 // x_k = (r'_k - a_k x_{k-1}) / b'_k, the bottom layer with its own pivot b''.
@@ -127,10 +137,11 @@ __device__ __forceinline__ void column_regs(const DevState& S, const int bx, con
     if (field == 1) K = min(kc, S.kb[idxk(S, ic - 1, j)]);
     if (field == 2) K = min(kc, S.kb[idxk(S, ic, j - 1)]);
     const int kbot = nz - K;  // lowest wet layer
+    const bool mom = field == 1 || field == 2;
 
-    const R* src = f3<R>(field == 0 ? S.ts : field == 1 ? S.us : S.vs) + idx3(S, ic, j, 0);
+    const R* src = col_src<R>(S, field) + idx3(S, ic, j, 0);
     const R* tab = static_cast<const R*>(S.thomas_tab);
-    const R* dtr = static_cast<const R*>(S.dtr);
+    const R* dtr = static_cast<const R*>(field == 3 ? S.dsr : S.dtr);
     const long long pl = S.plane3;
 
     R x[NZB];
@@ -151,7 +162,7 @@ __device__ __forceinline__ void column_regs(const DevState& S, const int bx, con
     for (int k = 0; k < NZB; ++k) {
         if (k < nz && k >= kbot) {
             R rhs = R(S.dz[k]) * x[k];
-            if (field == 0) {
+            if (!mom) {
                 const R a = (k > kbot) ? tab[4 * k + 3] : R(0);         // face k wet: layers k-1 and k
                 const R c = (k < nz - 1) ? tab[4 * (k + 1) + 3] : R(0);  // face k+1
                 rhs += -c * dtr[k * 4 + 2] - a * dtr[k * 4 + 1];
@@ -200,11 +211,12 @@ __device__ __forceinline__ void column_block_vk(const DevState& S, R* sd, R* sc,
     int K = kc;
     if (field == 1) K = min(kc, S.kb[idxk(S, ic - 1, j)]);
     if (field == 2) K = min(kc, S.kb[idxk(S, ic, j - 1)]);
+    const bool mom = field == 1 || field == 2;
 
-    const R* src = f3<R>(field == 0 ? S.ts : field == 1 ? S.us : S.vs) + idx3(S, ic, j, 0);
-    R* dst = f3<R>(field == 0 ? S.t : field == 1 ? S.u : S.v);
-    const R* dtr = static_cast<const R*>(S.dtr);
-    const R* kwf = static_cast<const R*>(field != 0 && S.kv ? S.kv : S.kw);  // u, v: viscosity when set
+    const R* src = col_src<R>(S, field) + idx3(S, ic, j, 0);
+    R* dst = col_dst<R>(S, field);
+    const R* dtr = static_cast<const R*>(field == 3 ? S.dsr : S.dtr);
+    const R* kwf = static_cast<const R*>(mom && S.kv ? S.kv : S.kw);  // u, v: viscosity when set
     const long long o0 = idx3(S, ic, j, 0);
     const long long on = field == 1 ? idx3(S, ic - 1, j, 0) : idx3(S, ic, j - 1, 0);
     const int kbot = nz - K;
@@ -214,7 +226,7 @@ __device__ __forceinline__ void column_block_vk(const DevState& S, R* sd, R* sc,
     auto coef = [&](int k) -> R {  // a_k of face k, 0 unless the face is wet
         if (k <= kbot || k >= nz) return R(0);
         R kap = kwf[o0 + k * pl];
-        if (field != 0) kap = R(0.5) * (kwf[on + k * pl] + kap);
+        if (mom) kap = R(0.5) * (kwf[on + k * pl] + kap);
         return -rdt * kap / R(S.dzc[k]);
     };
 
@@ -230,7 +242,7 @@ __device__ __forceinline__ void column_block_vk(const DevState& S, R* sd, R* sc,
     for (int k = 0; k < nz; ++k) {
         const R ck = (k + 1 < nz) ? sc[(k + 1) * W + t] : R(0);
         R rhs = R(S.dz[k]) * sd[k * W + t];
-        if (field == 0) rhs += -ck * dtr[k * 4 + 2] - ak * dtr[k * 4 + 1];
+        if (!mom) rhs += -ck * dtr[k * 4 + 2] - ak * dtr[k * 4 + 1];
         const R rden = R(1) / (R(S.dz[k]) - ak - ck - ak * cprev);
         const R cpk = ck * rden;
         const R dk = (rhs - ak * dprev) * rden;
@@ -250,7 +262,7 @@ __device__ __forceinline__ void column_block_vk(const DevState& S, R* sd, R* sc,
     }
     if (!live) return;
 
-    if (field == 0) {
+    if (!mom) {
         for (int k = 0; k < nz; ++k) {
             const R x = sd[k * W + t];
             dst[idx3(S, i, j, k)] = x;
@@ -296,10 +308,11 @@ __device__ __forceinline__ void column_regs_vk(const DevState& S, const int bx, 
     if (field == 1) K = min(kc, S.kb[idxk(S, ic - 1, j)]);
     if (field == 2) K = min(kc, S.kb[idxk(S, ic, j - 1)]);
     const int kbot = nz - K;
+    const bool mom = field == 1 || field == 2;
 
-    const R* src = f3<R>(field == 0 ? S.ts : field == 1 ? S.us : S.vs) + idx3(S, ic, j, 0);
-    const R* kwf = static_cast<const R*>(field != 0 && S.kv ? S.kv : S.kw);  // u, v: viscosity when set
-    const R* dtr = static_cast<const R*>(S.dtr);
+    const R* src = col_src<R>(S, field) + idx3(S, ic, j, 0);
+    const R* kwf = static_cast<const R*>(mom && S.kv ? S.kv : S.kw);  // u, v: viscosity when set
+    const R* dtr = static_cast<const R*>(field == 3 ? S.dsr : S.dtr);
     const long long o0 = idx3(S, ic, j, 0);
     const long long on = field == 1 ? idx3(S, ic - 1, j, 0) : idx3(S, ic, j - 1, 0);
     const long long pl = S.plane3;
@@ -316,7 +329,7 @@ __device__ __forceinline__ void column_regs_vk(const DevState& S, const int bx, 
             a[k] = R(0);
             if (k < nz && k > kbot) {  // face k wet: layers k-1 and k
                 R kap = *qk;
-                if (field != 0) kap = R(0.5) * (*qn + kap);
+                if (mom) kap = R(0.5) * (*qn + kap);
                 a[k] = -rdt * kap / R(S.dzc[k]);
             }
             qx += pl;
@@ -331,7 +344,7 @@ __device__ __forceinline__ void column_regs_vk(const DevState& S, const int bx, 
             const R ak = a[k];
             const R ck = (k + 1 < NZB) ? a[k + 1 < NZB ? k + 1 : k] : R(0);  // a_{k+1} (0 above the top)
             R rhs = R(S.dz[k]) * x[k];
-            if (field == 0) rhs += -ck * dtr[k * 4 + 2] - ak * dtr[k * 4 + 1];
+            if (!mom) rhs += -ck * dtr[k * 4 + 2] - ak * dtr[k * 4 + 1];
             const R rden = recip(R(S.dz[k]) - ak - ck - ak * cprev);
             cprev = ck * rden;
             dprev = (rhs - ak * dprev) * rden;
@@ -450,7 +463,7 @@ hipError_t with_bucket(int nz, A... args) {
 template <typename R, int NZB>
 struct LaunchColumn {
     static hipError_t go(const DevState& s, hipStream_t st) {
-        dim3 grid((s.nx + CW - 1) / CW, s.ny, 3);
+        dim3 grid((s.nx + CW - 1) / CW, s.ny, s.salinity ? 4 : 3);
         hipLaunchKernelGGL((k_column<R, NZB>), grid, dim3(CW), 0, st, s);
         return hipGetLastError();
     }
@@ -459,17 +472,17 @@ struct LaunchColumn {
 template <typename R, int NZB>
 struct LaunchColumnVk {
     static hipError_t go(const DevState& s, hipStream_t st) {
-        dim3 grid((s.nx + CW - 1) / CW, s.ny, 3);
+        dim3 grid((s.nx + CW - 1) / CW, s.ny, s.salinity ? 4 : 3);
         if constexpr (VkRegs<R, NZB>::ok) {
             hipLaunchKernelGGL((k_column_vkr<R, NZB>), grid, dim3(CW), 0, st, s);
         } else {
             const size_t lds = (size_t)s.nz * CWL * sizeof(R) * 2;
             if (lds <= 64 * 1024) {
-                dim3 g1((s.nx + CWL - 1) / CWL, s.ny, 3);
+                dim3 g1((s.nx + CWL - 1) / CWL, s.ny, s.salinity ? 4 : 3);
                 hipLaunchKernelGGL((k_column_vk<R, CWL>), g1, dim3(CWL), lds, st, s);
             } else {
                 if (lds / 2 > 64 * 1024) return hipErrorInvalidValue;  // per-workgroup LDS limit
-                dim3 g2((s.nx + CWL / 2 - 1) / (CWL / 2), s.ny, 3);
+                dim3 g2((s.nx + CWL / 2 - 1) / (CWL / 2), s.ny, s.salinity ? 4 : 3);
                 hipLaunchKernelGGL((k_column_vk<R, CWL / 2>), g2, dim3(CWL / 2), lds / 2, st, s);
             }
         }

@@ -98,16 +98,19 @@ __global__ __launch_bounds__(DT) void k_diag_partial(const DevState S) {
         const R* u = f3<R>(S.u);
         const R* v = f3<R>(S.v);
         const R* t = f3<R>(S.t);
+        const R* sal = f3<R>(S.s);  // salinity only
         const double area = S.area[j], dxc = S.dxc[j], dxv = S.dxv[j], dy = S.dy, dt = S.dt;
         double W = 0.0;
         for (int k = 0; k < nz; ++k) {
             const long long o = idx3(S, i, j, k);
             const double uu = double(u[o]), vv = double(v[o]), tt = double(t[o]) + S.tref[k];
-            if (!isfinite(uu) || !isfinite(vv) || !isfinite(tt)) a.nonfinite += 1.0;
+            const double ss = S.salinity ? double(sal[o]) + S.sref[k] : 0.0;
+            if (!isfinite(uu) || !isfinite(vv) || !isfinite(tt) || !isfinite(ss)) a.nonfinite += 1.0;
             const int kw = nz - k;
             const double dz = S.dz[k];
             if (K >= kw) {
                 two_sum_add(a.s[DG_TRACER], a.c[DG_TRACER], area * dz * tt);
+                if (S.salinity) two_sum_add(a.s[DG_SALT], a.c[DG_SALT], area * dz * ss);
                 a.m[DG_T_MAX - DG_NSUM] = fmax(a.m[DG_T_MAX - DG_NSUM], tt);
                 a.m[DG_NEG_T_MIN - DG_NSUM] = fmax(a.m[DG_NEG_T_MIN - DG_NSUM], -tt);
             }

@@ -152,10 +152,10 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 }
 
 // Occupancy target per precision: four waves per SIMD (two FP32 workgroups of
-// 8 waves per CU) keeps the FP32 kernel within 128 VGPRs.
-template <typename R> struct TendWaves;
-template <> struct TendWaves<float> { static constexpr int n = 4; };
-template <> struct TendWaves<double> { static constexpr int n = 2; };
+// 8 waves per CU) keeps the FP32 kernel within 128 VGPRs; the second tracer
+// takes the FP32 kernel to the FP64 budget.
+template <typename R, bool SALT> struct TendWaves { static constexpr int n = 2; };
+template <> struct TendWaves<float, false> { static constexpr int n = 4; };
 
 // One tile (bx, by) of one state. Called by the single-state kernel and by the
 // batched kernel that steps an ensemble of basins in one launch.
@@ -175,7 +175,7 @@ template <> struct TendWaves<double> { static constexpr int n = 2; };
 // to LDS; the momentum tendencies of level k are completed one level later,
 // when the pressure of level k of the neighbours is in LDS, so the march keeps
 // three barriers per level.
-template <typename R, int TX, int TY>
+template <typename R, int TX, int TY, bool SALT>
 __device__ __forceinline__ void tend_tile(const DevState& S, const int first, const int bx, const int by) {
     constexpr int NT = TX * TY;
     constexpr int LW = TX + 5, LH = TY + 5, LN = LW * LH;  // u, v tiles: points -2 .. +3 around the block
@@ -192,6 +192,10 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     // dxv south, dxv north, area, f, tan(phi)/a, 1/area, 1/(dxv dy), 1/dxc
     __shared__ R sRow[8][TY];
     __shared__ R sTop[NT];  // surface volume flux times the full top temperature
+    // salinity: its tile, its face fluxes and the surface term, as for T
+    constexpr int SN = SALT ? TN : 1, SNT = SALT ? NT : 1;
+    __shared__ R sS[SN];
+    __shared__ R fxS[SNT], fyS[SNT], sTopS[SNT];
 
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
     const int i0 = bx * (TX - 1), j0 = by * (TY - 1);
@@ -208,6 +212,9 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     const R* __restrict__ gU = f3<R>(S.u);
     const R* __restrict__ gV = f3<R>(S.v);
     const R* __restrict__ dtr = static_cast<const R*>(S.dtr);
+    const R* __restrict__ gS = SALT ? f3<R>(S.s) : nullptr;
+    const R* __restrict__ dsr = SALT ? static_cast<const R*>(S.dsr) : nullptr;
+    const R* __restrict__ eost = SALT ? static_cast<const R*>(S.eos_tab) : nullptr;
 
     // wet-layer counts of the tile (static over the march), origin (i0-4, j0-4)
     for (int q = tid; q < KN; q += NT) {
@@ -302,6 +309,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     const R ga = R(S.g * S.alpha);
     const R dt = R(S.dt);
     const R fbdt = R(S.pgf_w * S.dt);
+    const R qT = R(S.eos_qT), qTS = R(S.eos_qTS), qS = R(S.eos_qS);
     const R c_new = first ? R(1) : R(1.5 + S.chi);
     const R c_old = first ? R(0) : R(0.5 + S.chi);
 
@@ -310,6 +318,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     double Wc = -(S.dy * (S.cu[idx2(S, ir + 1, jr)] - S.cu[idx2(S, ir, jr)]) +
                   S.dxv[jr + 1] * S.cv[idx2(S, ir, jr + 1)] - S.dxv[jr] * S.cv[idx2(S, ir, jr)]);
     sTop[tid] = R(Wc) * R(S.tref[nz - 1]);
+    if constexpr (SALT) sTopS[tid] = R(Wc) * R(S.sref[nz - 1]);
 
     // own-column windows: w[r] holds level k + 2 - r
     R wt[6], wu[6], wv[6];
@@ -322,11 +331,16 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     const int hi = (pi < 0 && S.periodic_x) ? pi + nx : pi;
     const int hj = (pj < 0 && S.periodic_y) ? pj + ny : pj;
     int own = tcell ? hj * S.p3 + hi : 0;
+    R ws[SALT ? 6 : 1];
+#pragma unroll
+    for (int r = 0; r < (SALT ? 6 : 1); ++r) ws[r] = R(0);
     if (tcell) {
 #pragma unroll
         for (int r = 1; r < 6; ++r) {
             const int k = nz + 2 - r;  // before the first shift: levels nz+1 .. nz-3
             if (k >= 0 && k < nz) wt[r] = gT[k * pl + own];
+            if constexpr (SALT)
+                if (k >= 0 && k < nz) ws[r] = gS[k * pl + own];
         }
     }
     if (cell) {
@@ -338,9 +352,12 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     }
 
     // prefetch of the top level's tile slots
-    R pT[NST], pU[NS], pV[NS];
+    R pT[NST], pU[NS], pV[NS], pS[SALT ? NST : 1];
 #pragma unroll
     for (int q = 0; q < NST; ++q) pT[q] = gT[(long long)(nz - 1) * pl + slot_offT[q]];
+    if constexpr (SALT)
+#pragma unroll
+        for (int q = 0; q < NST; ++q) pS[q] = gS[(long long)(nz - 1) * pl + slot_offT[q]];
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
         const long long o = (long long)(nz - 1) * pl + slot_off[q];
@@ -348,6 +365,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     }
 
     R fzT_top = R(0), fzu_top = R(0), fzv_top = R(0);  // fluxes through the top face of level k
+    R fzS_top = R(0);
     R Wm_top = R(0);                                     // masked W on that face
     R p_prev = R(0), b_prev = R(0);
     R GUp = R(0), GVp = R(0);  // momentum tendencies of level k+1 without the pressure gradient
@@ -360,6 +378,9 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     R* __restrict__ tso = f3<R>(S.ts);
     R* __restrict__ uso = f3<R>(S.us);
     R* __restrict__ vso = f3<R>(S.vs);
+    R* __restrict__ gso = SALT ? f3<R>(S.gs_out) : nullptr;
+    const R* __restrict__ gsi = SALT ? f3<R>(S.gs) : nullptr;
+    R* __restrict__ sso = SALT ? f3<R>(S.ss) : nullptr;
 
     // Completes the momentum step of level kk (one above the level being
     // marched) once the pressure of level kk of every point is in LDS:
@@ -394,6 +415,11 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
         for (int r = 0; r < 5; ++r) { wt[r] = wt[r + 1]; wu[r] = wu[r + 1]; wv[r] = wv[r + 1]; }
         wt[5] = R(0); wu[5] = R(0); wv[5] = R(0);
         if (tcell && k - 3 >= 0) wt[5] = gT[(long long)(k - 3) * pl + own];
+        if constexpr (SALT) {
+#pragma unroll
+            for (int r = 0; r < 5; ++r) ws[r] = ws[r + 1];
+            ws[5] = (tcell && k - 3 >= 0) ? gS[(long long)(k - 3) * pl + own] : R(0);
+        }
         if (cell && k - 3 >= 0) {
             const long long o = (long long)(k - 3) * pl + own;
             wu[5] = gU[o]; wv[5] = gV[o];
@@ -403,6 +429,8 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
         for (int q = 0; q < NST; ++q) {
             const int e = tid + q * NT;
             if (e < TN) sT[e] = pT[q];
+            if constexpr (SALT)
+                if (e < TN) sS[e] = pS[q];
         }
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
@@ -412,6 +440,9 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
         if (k >= 1) {
 #pragma unroll
             for (int q = 0; q < NST; ++q) pT[q] = gT[(long long)(k - 1) * pl + slot_offT[q]];
+            if constexpr (SALT)
+#pragma unroll
+                for (int q = 0; q < NST; ++q) pS[q] = gS[(long long)(k - 1) * pl + slot_offT[q]];
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
                 const long long o = (long long)(k - 1) * pl + slot_off[q];
@@ -448,6 +479,12 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                     for (int r = 0; r < 6; ++r) ok[r] = wet(r - 2, 0);
                     fxT[tid] = upwind_flux(U10, p, ok);
                 }
+                if constexpr (SALT) {
+#pragma unroll
+                    for (int r = 0; r < 6; ++r) p[r] = sS[meT + r - 2];
+                    if (mTx >= kwet) fxS[tid] = (U10 == R(0)) ? R(0) : upwind_flux_wet(U10, p);
+                    else fxS[tid] = upwind_flux(U10, p, ok);
+                }
             }
             // u through the cell centre (between u(pi) and u(pi+1)); in the
             // ring row: T through the south face
@@ -477,6 +514,17 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                     for (int r = 0; r < 6; ++r) ok[r] = mv(r - 2, 0);
                     fxv[tid] = upwind_flux(Fv, p, ok);
                 }
+            } else if constexpr (SALT) {
+                if (used && tx >= 1) {  // ring row: S through the south face
+#pragma unroll
+                    for (int r = 0; r < 6; ++r) p[r] = sS[meT + (r - 3) * TW];
+                    if (mTs >= kwet) fxv[tid] = (V00 == R(0)) ? R(0) : upwind_flux_wet(V00, p);
+                    else {
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) ok[r] = wet(0, r - 3);
+                        fxv[tid] = upwind_flux(V00, p, ok);
+                    }
+                }
             }
             // T through the north face (every point: the ring column's cells need it too)
             {
@@ -487,6 +535,12 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
 #pragma unroll
                     for (int r = 0; r < 6; ++r) ok[r] = wet(0, r - 2);
                     fyT[tid] = upwind_flux(V01, p, ok);
+                }
+                if constexpr (SALT) {
+#pragma unroll
+                    for (int r = 0; r < 6; ++r) p[r] = sS[meT + (r - 2) * TW];
+                    if (mTy >= kwet) fyS[tid] = (V01 == R(0)) ? R(0) : upwind_flux_wet(V01, p);
+                    else fyS[tid] = upwind_flux(V01, p, ok);
                 }
             }
             // u through the north-west corner (between u(pi,pj) and u(pi,pj+1));
@@ -517,6 +571,17 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                     for (int r = 0; r < 6; ++r) ok[r] = mv(0, r - 2);
                     fyv[tid] = upwind_flux(Fv, p, ok);
                 }
+            } else if constexpr (SALT) {
+                if (used && ty >= 1) {  // ring column: S through the west face
+#pragma unroll
+                    for (int r = 0; r < 6; ++r) p[r] = sS[meT + r - 3];
+                    if (mTw >= kwet) fyv[tid] = (U00 == R(0)) ? R(0) : upwind_flux_wet(U00, p);
+                    else {
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) ok[r] = wet(r - 3, 0);
+                        fyv[tid] = upwind_flux(U00, p, ok);
+                    }
+                }
             }
             if (need_c) {
                 // Coriolis: Q = (f + u_c tan(phi)/a) V_c on wet cells
@@ -543,30 +608,34 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
 
             // vertical fluxes through the bottom face (between levels k-1 and k)
             R fzT_bot = R(0), fzu_bot = R(0), fzv_bot = R(0);
-            R E_bot = R(0);
+            R E_bot = R(0), fzS_bot = R(0), ES_bot = R(0);
             if (k >= 1) {
                 // levels k-3 .. k+2 all inside the column: the open-ocean path
                 const bool zin = (k >= 3) && (k + 2 < nz);
                 if (Wm_b != R(0)) {
-                    // reconstruct the full temperature from differences relative to the
+                    // reconstruct the full tracer from differences relative to the
                     // upwind cell (anomaly steps plus reference-profile steps)
                     const bool pos = Wm_b > R(0);
                     const int kc = pos ? k - 1 : k;
-                    const R ta = pos ? wt[5] : wt[0], tb = pos ? wt[4] : wt[1], tcv = pos ? wt[3] : wt[2];
-                    const R td = pos ? wt[2] : wt[3], te = pos ? wt[1] : wt[4];
                     const int la = pos ? k - 3 : k + 2, lb = pos ? k - 2 : k + 1;
                     const int ld = pos ? k : k - 1, le = pos ? k + 1 : k - 2;
                     auto okl = [&](int l) { return l >= 0 && l < nz && Kc >= nz - l; };
-                    const R da = (ta - tcv) + (pos ? dtr[kc * 4 + 0] : dtr[kc * 4 + 3]);
-                    const R db = (tb - tcv) + (pos ? dtr[kc * 4 + 1] : dtr[kc * 4 + 2]);
-                    const R dd = (td - tcv) + (pos ? dtr[kc * 4 + 2] : dtr[kc * 4 + 1]);
-                    const R de = (te - tcv) + (pos ? dtr[kc * 4 + 3] : dtr[kc * 4 + 0]);
-                    const R rel = (zin && Kc >= nz - (k - 3))
-                                      ? weno5z(da, db, R(0), dd, de)
-                                      : recon(da, db, R(0), dd, de, okl(la), okl(lb), true, okl(ld), okl(le));
-                    fzT_bot = Wm_b * (tcv + rel);
-                    // reference profile carried through this face, relative to tref(k)
-                    E_bot = pos ? Wm_b * (-dtr[k * 4 + 1]) : R(0);
+                    const bool open = zin && Kc >= nz - (k - 3);
+                    auto zflux = [&](const R* w, const R* __restrict__ tab, R& Eb) {
+                        const R ta = pos ? w[5] : w[0], tb = pos ? w[4] : w[1], tcv = pos ? w[3] : w[2];
+                        const R td = pos ? w[2] : w[3], te = pos ? w[1] : w[4];
+                        const R da = (ta - tcv) + (pos ? tab[kc * 4 + 0] : tab[kc * 4 + 3]);
+                        const R db = (tb - tcv) + (pos ? tab[kc * 4 + 1] : tab[kc * 4 + 2]);
+                        const R dd = (td - tcv) + (pos ? tab[kc * 4 + 2] : tab[kc * 4 + 1]);
+                        const R de = (te - tcv) + (pos ? tab[kc * 4 + 3] : tab[kc * 4 + 0]);
+                        const R rel = open ? weno5z(da, db, R(0), dd, de)
+                                           : recon(da, db, R(0), dd, de, okl(la), okl(lb), true, okl(ld), okl(le));
+                        // reference profile carried through this face, relative to the level's reference
+                        Eb = pos ? Wm_b * (-tab[k * 4 + 1]) : R(0);
+                        return Wm_b * (tcv + rel);
+                    };
+                    fzT_bot = zflux(wt, dtr, E_bot);
+                    if constexpr (SALT) fzS_bot = zflux(ws, dsr, ES_bot);
                 }
                 if (cell) {
                     const R Fu = R(0.5) * (sWm[cw] + Wm_b);
@@ -622,6 +691,20 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                 GT = (-divF + (E_top - E_bot)) * (sRow[5][ty] * inv_dz);
                 if (k == nz - 1) GT += (R(S.tstar[idx2(S, pi, pj)]) - wt[2]) * rinv;
             }
+            // salinity the same way; the ring's far-face fluxes sit in the v slots
+            R GS = R(0);
+            if constexpr (SALT) {
+                if (Kc >= kwet) {
+                    R ES_top;
+                    if (k == nz - 1) ES_top = sTopS[c];
+                    else ES_top = (Wm_top > R(0)) ? R(0) : Wm_top * (-dsr[k * 4 + 2]);
+                    const R fw = (tx == 0) ? fyv[c] : fxS[cw];
+                    const R fs = (ty == 0) ? fxv[c] : fyS[cs];
+                    const R divF = (fxS[c] - fw) + (fyS[c] - fs) + (fzS_top - fzS_bot);
+                    GS = (-divF + (ES_top - ES_bot)) * (sRow[5][ty] * inv_dz);
+                    if (k == nz - 1) GS += (R(S.sstar[idx2(S, pi, pj)]) - ws[2]) * rinv;
+                }
+            }
             // AB2 of the tracer (G^n goes to the other history buffer), and the
             // pressure of T^n + eps dt Ghat_T from p = 0 at z = 0 downward
             const R hT = c_new * GT - c_old * gti[o];
@@ -629,7 +712,20 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                 gto[o] = GT;
                 tso[o] = wt[2] + dt * hT;
             }
-            const R b = ga * (wt[2] + fbdt * hT);
+            R b;
+            if constexpr (SALT) {
+                // buoyancy anomaly of T' + eps dt Ghat_T, S' + eps dt Ghat_S
+                // (quadratic equation of state about the level's reference water)
+                const R hS = c_new * GS - c_old * gsi[o];
+                if (cell) {
+                    gso[o] = GS;
+                    sso[o] = ws[2] + dt * hS;
+                }
+                const R tf = wt[2] + fbdt * hT, sf = ws[2] + fbdt * hS;
+                b = tf * (eost[2 * k] + qT * tf + qTS * sf) + sf * (eost[2 * k + 1] + qS * sf);
+            } else {
+                b = ga * (wt[2] + fbdt * hT);
+            }
             const R pk = (k == nz - 1) ? -R(0.5) * dzk * b : p_prev - R(S.dzc[k + 1]) * (R(0.5) * (b + b_prev));
             p_prev = pk;
             b_prev = b;
@@ -658,6 +754,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
             }
 
             fzT_top = fzT_bot;
+            if constexpr (SALT) fzS_top = fzS_bot;
             fzu_top = fzu_bot;
             fzv_top = fzv_bot;
         }
@@ -683,20 +780,20 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
 #undef mTs
 }
 
-template <typename R, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R>::n)))
+template <typename R, int TX, int TY, bool SALT>
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R, SALT>::n)))
 void k_tend(const DevState S, const int first, const int gx) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    tend_tile<R, TX, TY>(S, first, tile % gx, tile / gx);
+    tend_tile<R, TX, TY, SALT>(S, first, tile % gx, tile / gx);
 }
 
 // Ensemble: entry b of the tile table names (member, bx, by); the host orders
 // the table so that each XCD receives contiguous tiles of a member.
 template <typename R, int TY>
-__global__ __launch_bounds__(TXB * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R>::n)))
+__global__ __launch_bounds__(TXB * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R, false>::n)))
 void k_tend_batched(const DevState* __restrict__ members, const int4* __restrict__ tiles, const int first) {
     const int4 e = tiles[blockIdx.x];
-    tend_tile<R, TXB, TY>(members[e.x], first, e.y, e.z);
+    tend_tile<R, TXB, TY, false>(members[e.x], first, e.y, e.z);
 }
 
 // Rows of the 64-wide ensemble tiles: 4 or 8 as chosen, else 8 in FP32 and 4 in FP64.
@@ -709,7 +806,10 @@ template <typename R, int TX, int TY>
 hipError_t launch_tend_shape(const DevState& s, int first, hipStream_t st) {
     const int gx = (s.nx + TX - 2) / (TX - 1);
     const int gy = (s.ny + TY - 2) / (TY - 1);
-    hipLaunchKernelGGL((k_tend<R, TX, TY>), dim3(gx * gy), dim3(TX, TY), 0, st, s, first, gx);
+    if (s.salinity)
+        hipLaunchKernelGGL((k_tend<R, TX, TY, true>), dim3(gx * gy), dim3(TX, TY), 0, st, s, first, gx);
+    else
+        hipLaunchKernelGGL((k_tend<R, TX, TY, false>), dim3(gx * gy), dim3(TX, TY), 0, st, s, first, gx);
     return hipGetLastError();
 }
 

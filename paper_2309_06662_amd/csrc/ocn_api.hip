@@ -67,6 +67,9 @@ struct ocn_state {
     bool t_set = false;
     std::vector<double> tref;   // nz
     std::vector<double> tstar;  // ny * nx, absolute
+    bool s_set = false;         // salinity: reference profile fixed by the first set of S
+    std::vector<double> sref;   // nz (salinity)
+    std::vector<double> sstar;  // ny * nx, absolute (salinity)
     // stage timing (events recorded on the state's stream)
     bool timing = false;
     std::vector<hipEvent_t> events;  // 4 per timed step
@@ -87,6 +90,10 @@ struct ocn_state {
     void* kv_ws = nullptr;        // the workspace's viscosity field (interior origin)
     // the two tracer-history buffers; d.gt is the one the next step reads
     void* gtb[2] = {nullptr, nullptr};
+    void swap_history() {  // G^n becomes the history the next step reads
+        std::swap(d.gt, d.gt_out);
+        std::swap(d.gs, d.gs_out);
+    }
     double cfl_bt = 0.0;  // barotropic CFL of a substep (static: grid and parameters)
     // one step captured as a HIP graph per history buffer (ocn_step_graph)
     hipGraph_t graph[2] = {nullptr, nullptr};
@@ -147,13 +154,17 @@ struct Plan {
     size_t oxk, pk, nk;
     size_t nrow;  // metric rows
     size_t diag_blocks;
-    size_t off_f3[10], off_f2[24], off_bw, off_kb, off_rows[5], off_dz, off_dzc, off_tref, off_dtr, off_tab;
+    int nf3, nf2;  // 3D and 2D arrays of the state (more with salinity)
+    size_t off_f3[14], off_f2[25], off_bw, off_kb, off_rows[5], off_dz, off_dzc, off_tref, off_dtr, off_tab;
+    size_t off_sref, off_dsr, off_eos, off_zc;
     size_t off_part, off_out;
     size_t total;
 };
 
-Plan make_plan(const ocn_grid* g, int precision, int n_substeps) {
+Plan make_plan(const ocn_grid* g, int precision, int n_substeps, int salinity) {
     Plan P{};
+    P.nf3 = salinity ? 14 : 10;
+    P.nf2 = salinity ? 25 : 24;
     P.esize = precision == OCN_FP32 ? 4 : 8;
     const size_t h = g->h;
     P.rows = g->ny + 2 * h;
@@ -170,8 +181,8 @@ Plan make_plan(const ocn_grid* g, int precision, int n_substeps) {
     P.nrow = g->ny + 2 * h + 1;
     P.diag_blocks = ((g->nx + 63) / 64) * ((g->ny + 3) / 4);
     Layout L;
-    for (auto& o : P.off_f3) o = L.add(P.n3 * P.esize);
-    for (auto& o : P.off_f2) o = L.add(P.n2 * sizeof(double));
+    for (int q = 0; q < P.nf3; ++q) P.off_f3[q] = L.add(P.n3 * P.esize);
+    for (int q = 0; q < P.nf2; ++q) P.off_f2[q] = L.add(P.n2 * sizeof(double));
     P.off_kb = L.add(P.nk * sizeof(int32_t));
     for (auto& o : P.off_rows) o = L.add(P.nrow * sizeof(double));
     P.off_dz = L.add(g->nz * sizeof(double));
@@ -179,6 +190,12 @@ Plan make_plan(const ocn_grid* g, int precision, int n_substeps) {
     P.off_tref = L.add(g->nz * sizeof(double));
     P.off_dtr = L.add(g->nz * 4 * P.esize);
     P.off_tab = L.add((size_t)4 * g->nz * P.esize);
+    if (salinity) {
+        P.off_sref = L.add(g->nz * sizeof(double));
+        P.off_dsr = L.add(g->nz * 4 * P.esize);
+        P.off_eos = L.add(g->nz * 2 * P.esize);
+        P.off_zc = L.add(g->nz * sizeof(double));
+    }
     P.off_part = L.add(P.diag_blocks * ocn::DG_COUNT * sizeof(double));
     P.off_out = L.add(ocn::DG_COUNT * sizeof(double));
     P.off_bw = L.add((size_t)(2 * ocn::baro_substeps(std::max(n_substeps, 1)) + 1) * sizeof(double));
@@ -218,7 +235,10 @@ bool valid_params(const ocn_params* p, std::string& why) {
     if (!(p->kappa >= 0.0)) { why = "kappa must be >= 0"; return false; }
     if (!(p->rho0 > 0.0)) { why = "rho0 must be positive"; return false; }
     if (p->baro_fuse < 0 || p->baro_fuse > 8) { why = "baro_fuse must be in 0..8"; return false; }
-    if (p->reserved1 != 0) { why = "reserved1 must be 0"; return false; }
+    if (p->salinity != 0 && p->salinity != 1) { why = "salinity must be 0 or 1"; return false; }
+    if (p->salinity)
+        for (int q = 0; q < 9; ++q)
+            if (!std::isfinite(p->eos[q])) { why = "eos coefficients must be finite"; return false; }
     if (!(p->pgf_weight >= 0.0 && p->pgf_weight <= 1.0)) { why = "pgf_weight must be in [0, 1]"; return false; }
     return true;
 }
@@ -315,7 +335,63 @@ int upload_tables(ocn_state* s) {
     pack2(s, ts.data(), img);
     HIPCHK(hipMemcpyAsync(base2(s, s->d.tstar), img.data(), img.size() * sizeof(double), hipMemcpyHostToDevice, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
+    if (!s->d.salinity) return OCN_OK;
+    // salinity: reference steps, restoring target anomaly and the per-level
+    // buoyancy coefficients of anomalies. With Ta = tref - t0 + T',
+    // Sa = sref - s0 + S', the density anomaly relative to the reference water
+    // of the level is T' (cT - a0 lambda1 T'/2 - nu S') + S' (cS - b0 lambda2 S'/2)
+    // with cT = -a0 (1 + mu1 z + lambda1 (tref - t0)) - nu (sref - s0) and
+    // cS = b0 (1 - mu2 z - lambda2 (sref - s0)) - nu (tref - t0); b' = -g rho'/rho0.
+    std::vector<R> dsr(nz * 4, R(0));
+    for (int k = 0; k < nz; ++k)
+        for (int q = 0; q < 4; ++q) {
+            const int l = k + offs[q];
+            dsr[k * 4 + q] = (l >= 0 && l < nz) ? R(s->sref[l] - s->sref[k]) : R(0);
+        }
+    const double* e = s->d.eos;
+    const double gr = s->p.g / s->p.rho0;
+    std::vector<R> tab(nz * 2);
+    std::vector<double> zc(nz);
+    double depth = 0.0;
+    for (int k = nz - 1; k >= 0; --k) {
+        zc[k] = depth + 0.5 * g->dz[k];
+        depth += g->dz[k];
+    }
+    for (int k = 0; k < nz; ++k) {
+        const double ta = s->tref[k] - e[7], sa = s->sref[k] - e[8];
+        const double cT = -e[0] * (1.0 + e[4] * zc[k] + e[2] * ta) - e[6] * sa;
+        const double cS = e[1] * (1.0 - e[5] * zc[k] - e[3] * sa) - e[6] * ta;
+        tab[2 * k] = R(-gr * cT);
+        tab[2 * k + 1] = R(-gr * cS);
+    }
+    std::vector<double> ss(s->sstar.size());
+    for (size_t c = 0; c < ss.size(); ++c) ss[c] = s->sstar[c] - s->sref[nz - 1];
+    pack2(s, ss.data(), img);
+    HIPCHK(hipMemcpyAsync(s->d.dsr, dsr.data(), dsr.size() * sizeof(R), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(s->d.sref, s->sref.data(), nz * sizeof(double), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(s->d.eos_tab, tab.data(), tab.size() * sizeof(R), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(s->d.zc, zc.data(), nz * sizeof(double), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(base2(s, s->d.sstar), img.data(), img.size() * sizeof(double), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
     return OCN_OK;
+}
+
+// The per-level reference of a tracer's stored anomaly: the mean over the wet
+// cells of each level of the first field set.
+void level_means(const ocn_grid* g, const double* host, std::vector<double>& ref) {
+    const int nz = g->nz;
+    const size_t n2 = (size_t)g->nx * g->ny;
+    for (int k = 0; k < nz; ++k) {
+        double sum = 0.0, all = 0.0;
+        size_t n = 0;
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                const double v = host[(size_t)k * n2 + (size_t)j * g->nx + i];
+                all += v;
+                if (g->kb[(size_t)j * g->nx + i] >= nz - k) { sum += v; ++n; }
+            }
+        ref[k] = n ? sum / n : all / n2;
+    }
 }
 
 template <typename R>
@@ -448,23 +524,40 @@ int set_field_t(ocn_state* s, int32_t f, const double* host) {
     case OCN_FIELD_T: {
         if (!s->t_set) {
             // reference profile: mean of T over the wet cells of each level
-            const size_t n2 = (size_t)g->nx * g->ny;
-            for (int k = 0; k < nz; ++k) {
-                double sum = 0.0, all = 0.0;
-                size_t n = 0;
-                for (int j = 0; j < g->ny; ++j)
-                    for (int i = 0; i < g->nx; ++i) {
-                        const double v = host[(size_t)k * n2 + (size_t)j * g->nx + i];
-                        all += v;
-                        if (g->kb[(size_t)j * g->nx + i] >= nz - k) { sum += v; ++n; }
-                    }
-                s->tref[k] = n ? sum / n : all / n2;
-            }
+            level_means(g, host, s->tref);
             s->t_set = true;
             int rc = upload_tables<R>(s);
             if (rc) return rc;
         }
         return set3<R>(s, d.t, host, s->tref.data(), 0);
+    }
+    case OCN_FIELD_S:
+    case OCN_FIELD_S_PRED:
+    case OCN_FIELD_GS_PREV:
+    case OCN_FIELD_SSTAR:
+    case OCN_FIELD_SREF: {
+        if (!d.salinity) return fail(OCN_E_STATE, "the state carries no salinity");
+        if (f == OCN_FIELD_S) {
+            if (!s->s_set) {
+                level_means(g, host, s->sref);
+                s->s_set = true;
+                int rc = upload_tables<R>(s);
+                if (rc) return rc;
+            }
+            return set3<R>(s, d.s, host, s->sref.data(), 0);
+        }
+        if (f == OCN_FIELD_S_PRED) {
+            if (!s->s_set) return fail(OCN_E_STATE, "set S first: S_PRED is stored relative to S's reference profile");
+            return set3<R>(s, d.ss, host, s->sref.data(), 0);
+        }
+        if (f == OCN_FIELD_GS_PREV) return set3<R>(s, d.gs, host, nullptr, 0);
+        if (f == OCN_FIELD_SSTAR) {
+            s->sstar.assign(host, host + (size_t)g->nx * g->ny);
+            return upload_tables<R>(s);
+        }
+        if (s->s_set) return fail(OCN_E_STATE, "SREF can only be set before S");
+        s->sref.assign(host, host + nz);
+        return upload_tables<R>(s);
     }
     case OCN_FIELD_GU_PREV: return set3<R>(s, d.gu, host, nullptr, 0);
     case OCN_FIELD_GV_PREV: return set3<R>(s, d.gv, host, nullptr, 0);
@@ -517,6 +610,21 @@ int get_field_t(ocn_state* s, int32_t f, double* host) {
     case OCN_FIELD_T_PRED: return get3<R>(s, d.ts, host, s->tref.data(), g->nz);
     case OCN_FIELD_GU_SLOW: return get2(s, d.gU, host);
     case OCN_FIELD_GV_SLOW: return get2(s, d.gV, host);
+    case OCN_FIELD_S:
+    case OCN_FIELD_S_PRED:
+    case OCN_FIELD_GS_PREV:
+    case OCN_FIELD_SSTAR:
+    case OCN_FIELD_SREF:
+        if (!d.salinity) return fail(OCN_E_STATE, "the state carries no salinity");
+        if (f == OCN_FIELD_S) return get3<R>(s, d.s, host, s->sref.data(), g->nz);
+        if (f == OCN_FIELD_S_PRED) return get3<R>(s, d.ss, host, s->sref.data(), g->nz);
+        if (f == OCN_FIELD_GS_PREV) return get3<R>(s, d.gs, host, nullptr, g->nz);
+        if (f == OCN_FIELD_SSTAR) {
+            std::copy(s->sstar.begin(), s->sstar.end(), host);
+            return OCN_OK;
+        }
+        std::copy(s->sref.begin(), s->sref.end(), host);
+        return OCN_OK;
     case OCN_FIELD_ETA: return get2(s, d.eta, host);
     case OCN_FIELD_UBT: return get2(s, d.ubt, host);
     case OCN_FIELD_VBT: return get2(s, d.vbt, host);
@@ -587,6 +695,9 @@ size_t field_count(const ocn_grid* g, int32_t f) {
     case OCN_FIELD_GU_PREV: case OCN_FIELD_GV_PREV: case OCN_FIELD_GT_PREV:
     case OCN_FIELD_U_PRED: case OCN_FIELD_V_PRED: case OCN_FIELD_T_PRED: return n3;
     case OCN_FIELD_GU_SLOW: case OCN_FIELD_GV_SLOW: return n2;
+    case OCN_FIELD_S: case OCN_FIELD_S_PRED: case OCN_FIELD_GS_PREV: return n3;
+    case OCN_FIELD_SSTAR: return n2;
+    case OCN_FIELD_SREF: return g->nz;
     case OCN_FIELD_W: return n2 * (g->nz + 1);
     case OCN_FIELD_TREF: return g->nz;
     case OCN_FIELD_ETA: case OCN_FIELD_UBT: case OCN_FIELD_VBT: case OCN_FIELD_ETA_MEAN:
@@ -669,7 +780,7 @@ int ocn_state_arena_bytes(const ocn_grid* grid, const ocn_params* params, size_t
     if (!grid || !bytes) return fail(OCN_E_INVALID, "grid and bytes must not be NULL");
     std::string why;
     if (!valid_params(params, why)) return fail(OCN_E_INVALID, why);
-    *bytes = make_plan(grid, params->precision, params->n_substeps).total;
+    *bytes = make_plan(grid, params->precision, params->n_substeps, params->salinity).total;
     return OCN_OK;
 }
 
@@ -680,7 +791,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         std::string why;
         if (!valid_params(params, why)) return fail(OCN_E_INVALID, why);
         if (reinterpret_cast<uintptr_t>(device_arena) % 256) return fail(OCN_E_INVALID, "arena must be 256-byte aligned");
-        const Plan P = make_plan(grid, params->precision, params->n_substeps);
+        const Plan P = make_plan(grid, params->precision, params->n_substeps, params->salinity);
         if (arena_bytes < P.total) return fail(OCN_E_NOMEM, "arena smaller than ocn_state_arena_bytes");
         if (grid->nz > 128) return fail(OCN_E_UNSUPPORTED, "nz above 128 is not supported by the column kernel");
 
@@ -708,15 +819,30 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         d.ox2 = (int)P.ox2;
         d.plane3 = (long long)P.p3 * (long long)P.rows;
         const size_t o3 = ((size_t)h * P.p3 + P.ox3) * P.esize;
-        void** f3s[10] = {&d.u, &d.v, &d.t, &d.us, &d.vs, &d.ts, &d.gu, &d.gv, &d.gt, &d.gt_out};
-        for (int q = 0; q < 10; ++q) *f3s[q] = A + P.off_f3[q] + o3;
+        void** f3s[14] = {&d.u, &d.v, &d.t, &d.us, &d.vs, &d.ts, &d.gu, &d.gv, &d.gt, &d.gt_out,
+                          &d.s, &d.ss, &d.gs, &d.gs_out};
+        for (int q = 0; q < P.nf3; ++q) *f3s[q] = A + P.off_f3[q] + o3;
         s->gtb[0] = d.gt;
         s->gtb[1] = d.gt_out;
-        double** f2s[24] = {&d.eta, &d.ubt, &d.vbt, &d.se, &d.su, &d.sv, &d.eta_mean, &d.ubt_mean, &d.vbt_mean,
+        double** f2s[25] = {&d.eta, &d.ubt, &d.vbt, &d.se, &d.su, &d.sv, &d.eta_mean, &d.ubt_mean, &d.vbt_mean,
                             &d.gU, &d.gV, &d.hu, &d.hv, &d.cu, &d.cv, &d.taux, &d.tauy, &d.tstar, &d.scratch2d,
-                            &d.eta2, &d.ubt2, &d.vbt2, &d.sfu, &d.sfv};
+                            &d.eta2, &d.ubt2, &d.vbt2, &d.sfu, &d.sfv, &d.sstar};
         const size_t o2 = (size_t)h * P.p2 + P.ox2;
-        for (int q = 0; q < 24; ++q) *f2s[q] = reinterpret_cast<double*>(A + P.off_f2[q]) + o2;
+        for (int q = 0; q < P.nf2; ++q) *f2s[q] = reinterpret_cast<double*>(A + P.off_f2[q]) + o2;
+        d.salinity = params->salinity;
+        if (d.salinity) {
+            d.sref = reinterpret_cast<double*>(A + P.off_sref);
+            d.dsr = A + P.off_dsr;
+            d.eos_tab = A + P.off_eos;
+            d.zc = reinterpret_cast<double*>(A + P.off_zc);
+            for (int q = 0; q < 9; ++q) d.eos[q] = params->eos[q];
+            const double gr = params->g / params->rho0;
+            d.eos_qT = gr * 0.5 * params->eos[0] * params->eos[2];
+            d.eos_qTS = gr * params->eos[6];
+            d.eos_qS = gr * 0.5 * params->eos[1] * params->eos[3];
+            s->sref.assign(grid->nz, 0.0);
+            s->sstar.assign((size_t)grid->nx * grid->ny, 0.0);
+        }
         d.kb = reinterpret_cast<int*>(A + P.off_kb) + ((size_t)(h + 1) * P.pk + P.oxk);
         double** rows[5] = {&d.dxc, &d.dxv, &d.area, &d.fcor, &d.metric};
         for (int q = 0; q < 5; ++q) *rows[q] = reinterpret_cast<double*>(A + P.off_rows[q]) + h;
@@ -893,7 +1019,7 @@ int enqueue_stage(ocn_state* s, int stage) {
     case OCN_STAGE_TENDENCY:
         HIPCHK(f32 ? ocn::launch_tendency<float>(s->d, s->first, s->st)
                    : ocn::launch_tendency<double>(s->d, s->first, s->st));
-        std::swap(s->d.gt, s->d.gt_out);
+        s->swap_history();
         return OCN_OK;
     case OCN_STAGE_BAROTROPIC:
         HIPCHK(ocn::launch_barotropic(s->d, s->st));
@@ -957,7 +1083,7 @@ int ocn_step_graph(ocn_state* s, int32_t n) {
                 hipError_t ce = hipStreamEndCapture(s->st, &g);
                 // the capture recorded the step without running it; its tendency
                 // stage swapped the history buffers, which the replay below does
-                if (s->parity() != par) std::swap(s->d.gt, s->d.gt_out);
+                if (s->parity() != par) s->swap_history();
                 if (rc) {
                     if (g) (void)hipGraphDestroy(g);
                     return rc;
@@ -967,7 +1093,7 @@ int ocn_step_graph(ocn_state* s, int32_t n) {
                 HIPCHK(hipGraphInstantiate(&s->exec[par], s->graph[par], nullptr, nullptr, 0));
             }
             HIPCHK(hipGraphLaunch(s->exec[par], s->st));
-            std::swap(s->d.gt, s->d.gt_out);  // what the replayed tendency stage did
+            s->swap_history();  // what the replayed tendency stage did
         }
         advance(s);
     }
@@ -997,6 +1123,7 @@ int ocn_closure_attach(ocn_state* s, const ocn_mlp* net, const float* norm, size
         return fail(OCN_E_UNSUPPORTED, "nz too large for the variable-diffusivity column solve");
     int din = 0, h1 = 0, h2 = 0, dout = 0;
     if (net) {
+        if (s->d.salinity) return fail(OCN_E_UNSUPPORTED, "the closure network takes temperature-only states");
         ocn::mlp_shape(net, &din, &h1, &h2, &dout);
         if (dout != nz) return fail(OCN_E_INVALID, "network output width must equal nz");
         if (din < 4 * nz + 3) return fail(OCN_E_INVALID, "network input width must be at least 4 nz + 3");
@@ -1093,6 +1220,7 @@ int ocn_closure_detach(ocn_state* s) {
 
 int ocn_closure_features(ocn_state* s, int32_t din, const float* norm_dev, float* x_dev) {
     if (!s || !x_dev) return fail(OCN_E_INVALID, "state and x must not be NULL");
+    if (s->d.salinity) return fail(OCN_E_UNSUPPORTED, "the closure features take temperature-only states");
     if (din < 4 * s->g->nz + 3) return fail(OCN_E_INVALID, "din must be at least 4 nz + 3");
     if (ocn::features_lds(din) > 64 * 1024) return fail(OCN_E_UNSUPPORTED, "din too large");
     HIPCHK(s->esize == 4 ? ocn::launch_features<float>(s->d, din, norm_dev, x_dev, 0, s->st)
@@ -1159,6 +1287,7 @@ int diag_finish(ocn_state* s, const double* dev_out, ocn_diag* out) {
     out->eta_min = -r[ocn::DG_NEG_ETA_MIN];
     out->nonfinite = (int64_t)r[ocn::DG_NONFINITE];
     out->cfl_bt = s->cfl_bt;
+    out->salt_content = r[ocn::DG_SALT];
     if (out->nonfinite > 0) return fail(OCN_E_UNSTABLE, "non-finite values in the state");
     return OCN_OK;
 }
@@ -1207,13 +1336,15 @@ std::vector<std::pair<void*, size_t>> ckpt_regions(ocn_state* s) {
     DevState& d = s->d;
     std::vector<std::pair<void*, size_t>> r;
     for (void* f : {d.u, d.v, d.t, d.gu, d.gv, d.gt}) r.push_back({base3(s, f), s->n3 * s->esize});
+    if (d.salinity)
+        for (void* f : {d.s, d.gs}) r.push_back({base3(s, f), s->n3 * s->esize});
     for (double* f : {d.eta, d.ubt, d.vbt, d.eta_mean, d.ubt_mean, d.vbt_mean, d.cu, d.cv})
         r.push_back({base2(s, f), s->n2 * sizeof(double)});
     return r;
 }
 
 size_t ckpt_size(ocn_state* s) {
-    size_t n = sizeof(CkptHeader) + s->g->nz * sizeof(double);
+    size_t n = sizeof(CkptHeader) + s->g->nz * sizeof(double) * (s->d.salinity ? 2 : 1);
     for (auto& r : ckpt_regions(s)) n += r.second;
     return n;
 }
@@ -1236,6 +1367,10 @@ int ocn_checkpoint_save(ocn_state* s, void* host, size_t bytes) {
     p += sizeof(h);
     std::memcpy(p, s->tref.data(), s->g->nz * sizeof(double));
     p += s->g->nz * sizeof(double);
+    if (s->d.salinity) {
+        std::memcpy(p, s->sref.data(), s->g->nz * sizeof(double));
+        p += s->g->nz * sizeof(double);
+    }
     for (auto& r : ckpt_regions(s)) {
         HIPCHK(hipMemcpyAsync(p, r.first, r.second, hipMemcpyDeviceToHost, s->st));
         p += r.second;
@@ -1254,15 +1389,23 @@ int ocn_checkpoint_load(ocn_state* s, const void* host, size_t bytes) {
         h.nz != s->g->nz || h.h != s->g->h)
         return fail(OCN_E_INVALID, "checkpoint does not match this state's grid or precision");
     p += sizeof(h);
-    std::vector<double> tref(s->g->nz);
+    std::vector<double> tref(s->g->nz), sref(s->g->nz, 0.0);
     std::memcpy(tref.data(), p, s->g->nz * sizeof(double));
     p += s->g->nz * sizeof(double);
+    if (s->d.salinity) {
+        std::memcpy(sref.data(), p, s->g->nz * sizeof(double));
+        p += s->g->nz * sizeof(double);
+    }
     for (auto& r : ckpt_regions(s)) {
         HIPCHK(hipMemcpyAsync(r.first, p, r.second, hipMemcpyHostToDevice, s->st));
         p += r.second;
     }
     HIPCHK(hipStreamSynchronize(s->st));
     s->tref = tref;
+    if (s->d.salinity) {
+        s->sref = sref;
+        s->s_set = true;
+    }
     s->t_set = h.t_set != 0;
     s->first = h.first;
     s->step = h.step;
@@ -1319,7 +1462,7 @@ int ens_plan(const ocn_grid* const* grids, int n, const ocn_params* params, EnsP
     Layout L;
     P.cap_tend = P.cap_col = P.cap_baro = 0;
     for (int m = 0; m < n; ++m) {
-        const size_t b = make_plan(grids[m], params->precision, params->n_substeps).total;
+        const size_t b = make_plan(grids[m], params->precision, params->n_substeps, params->salinity).total;
         P.member_off.push_back(L.add(b));
         P.member_bytes.push_back(b);
         P.cap_tend += tend_tiles(grids[m], 4);  // the larger of the two tile shapes
@@ -1381,6 +1524,7 @@ int ens_tables(ocn_ensemble* e) {
         e->tab[0].push_back(s->d);
         DevState o = s->d;
         std::swap(o.gt, o.gt_out);
+        std::swap(o.gs, o.gs_out);
         e->tab[1].push_back(o);
     }
     e->epar = 0;
@@ -1449,7 +1593,7 @@ int ens_step(ocn_ensemble* e, int n) {
             s->first = 0;
             s->step += 1;
             s->time += s->p.dt;
-            std::swap(s->d.gt, s->d.gt_out);
+            s->swap_history();
         }
     }
     return OCN_OK;
@@ -1478,6 +1622,7 @@ int ocn_ensemble_init(const ocn_grid* const* grids, int32_t n, const ocn_params*
         if (reinterpret_cast<uintptr_t>(device_arena) % 256) return fail(OCN_E_INVALID, "arena must be 256-byte aligned");
         for (int m = 0; m < n; ++m)
             if (!grids[m]) return fail(OCN_E_INVALID, "NULL grid");
+        if (params->salinity) return fail(OCN_E_UNSUPPORTED, "ensembles take temperature only");
         EnsPlan P;
         ens_plan(grids, n, params, P);
         if (arena_bytes < P.total) return fail(OCN_E_NOMEM, "arena smaller than ocn_ensemble_arena_bytes");

@@ -21,11 +21,11 @@ namespace ocn {
 
 // Diagnostics slots reduced on the device.
 enum DiagSlot {
-    DG_TRACER = 0, DG_VOLUME, DG_VOLUME_MEAN, DG_KE, DG_WET_AREA,  // compensated sums
-    DG_NSUM = 5,
-    DG_MAX_U = 5, DG_MAX_V, DG_MAX_W, DG_CFL, DG_T_MAX, DG_NEG_T_MIN, DG_ETA_MAX, DG_NEG_ETA_MIN,  // maxima
-    DG_NONFINITE = 13,
-    DG_COUNT = 14
+    DG_TRACER = 0, DG_VOLUME, DG_VOLUME_MEAN, DG_KE, DG_WET_AREA, DG_SALT,  // compensated sums
+    DG_NSUM = 6,
+    DG_MAX_U = 6, DG_MAX_V, DG_MAX_W, DG_CFL, DG_T_MAX, DG_NEG_T_MIN, DG_ETA_MAX, DG_NEG_ETA_MIN,  // maxima
+    DG_NONFINITE = 14,
+    DG_COUNT = 15
 };
 
 struct DevState {
@@ -45,6 +45,10 @@ struct DevState {
                             // pressure gradient), overwritten with G^n
     void *gt, *gt_out;      // AB2 history of T: G^{n-1} is read from gt and G^n
                             // written to gt_out (the host swaps them every step)
+    // salinity (when salinity != 0): S - sref(k), its predictor, and its
+    // double-buffered AB2 history like T's
+    int salinity;
+    void *s, *ss, *gs, *gs_out;
     // 2D FP64
     double *eta, *ubt, *vbt;             // barotropic state
     double *se, *su, *sv;                // window sums of eta^q; transport sums of U^l, V^l
@@ -54,6 +58,7 @@ struct DevState {
     double *cu, *cv;                     // sum_k dz u m_u of the current u, v (vertical-transport seed)
     double *taux, *tauy;                 // wind stress
     double *tstar;                       // restoring target minus tref(top)
+    double *sstar;                       // salinity restoring target minus sref(top) (salinity only)
     double *scratch2d;                   // one 2D field of scratch
     double *eta2, *ubt2, *vbt2;          // second buffers of the temporally blocked substeps
     double *sfu, *sfv;                   // window sums of U^q, V^q
@@ -71,6 +76,16 @@ struct DevState {
     double* dzc;      // nz + 1: centre spacing below layer k (dzc[0] and dzc[nz] unused)
     double* tref;     // nz
     void* dtr;        // nz * 4 of the field type: tref(k+o) - tref(k), o = -2, -1, +1, +2
+    // salinity only: the reference profile of S and its steps (as tref, dtr);
+    // the buoyancy of anomalies b' = T'(eT + qT T' + qTS S') + S'(eS + qS S')
+    // with eT, eS per level (2 nz of the field type) and, for N^2 at any depth
+    // in FP64, the equation-of-state constants and layer-centre depths
+    double* sref;
+    void* dsr;
+    void* eos_tab;
+    double eos_qT, eos_qTS, eos_qS;
+    double eos[9];    // a0, b0, lambda1, lambda2, mu1, mu2, nu, t0, s0
+    double* zc;       // nz depths of the layer centres (m, positive down)
     // constant-diffusivity solve, eliminated from the surface down: per level k
     // of the field type {1 / b'_k, c_k / b'_{k+1}, 1 / b''_k, a_k}, with b' the
     // pivot of a layer above the bottom, b'' the pivot of layer k when it is

@@ -24,8 +24,10 @@ OCN_CARTESIAN, OCN_LATLON = 0, 1
 
 FIELDS = {"u": 0, "v": 1, "T": 2, "eta": 3, "U": 4, "V": 5, "eta_mean": 6, "U_mean": 7, "V_mean": 8,
           "w": 9, "gu_prev": 10, "gv_prev": 11, "gt_prev": 12, "taux": 13, "tauy": 14, "tstar": 15, "tref": 16,
-          "kappa": 17, "visc": 18, "u_pred": 19, "v_pred": 20, "T_pred": 21, "gU_slow": 22, "gV_slow": 23}
-FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "kappa", "visc", "u_pred", "v_pred", "T_pred"}
+          "kappa": 17, "visc": 18, "u_pred": 19, "v_pred": 20, "T_pred": 21, "gU_slow": 22, "gV_slow": 23,
+          "S": 24, "gs_prev": 25, "sstar": 26, "S_pred": 27, "sref": 28}
+FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "kappa", "visc", "u_pred", "v_pred", "T_pred",
+             "S", "gs_prev", "S_pred"}
 # stages of a step (ocn_stage)
 STAGE_MIXING, STAGE_TENDENCY, STAGE_BAROTROPIC, STAGE_COLUMN = 0, 1, 2, 3
 # Richardson-number mixing constants (Pacanowski and Philander 1981 form)
@@ -62,9 +64,9 @@ class GridDesc(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("precision", C.c_int32), ("n_substeps", C.c_int32), ("baro_fuse", C.c_int32),
-                ("reserved1", C.c_int32), ("dt", C.c_double), ("chi", C.c_double), ("g", C.c_double),
+                ("salinity", C.c_int32), ("dt", C.c_double), ("chi", C.c_double), ("g", C.c_double),
                 ("alpha", C.c_double), ("rho0", C.c_double), ("t_ref", C.c_double), ("kappa", C.c_double),
-                ("restore_tau", C.c_double), ("pgf_weight", C.c_double)]
+                ("restore_tau", C.c_double), ("pgf_weight", C.c_double), ("eos", C.c_double * 9)]
 
 
 class Diag(C.Structure):
@@ -73,7 +75,7 @@ class Diag(C.Structure):
                 ("max_abs_u", C.c_double), ("max_abs_v", C.c_double), ("max_abs_w", C.c_double),
                 ("t_min", C.c_double), ("t_max", C.c_double), ("eta_min", C.c_double), ("eta_max", C.c_double),
                 ("cfl_adv", C.c_double), ("wet_area", C.c_double), ("nonfinite", C.c_int64),
-                ("cfl_bt", C.c_double)]
+                ("cfl_bt", C.c_double), ("salt_content", C.c_double)]
 
 
 _lib = None
@@ -171,6 +173,10 @@ def params(w: "_inputs.Workload", precision: str, baro_fuse: int = 0) -> Params:
     p.dt, p.chi, p.g, p.alpha, p.rho0, p.t_ref, p.kappa = w.dt, w.chi, w.g, w.alpha, w.rho0, w.t_ref, w.kappa
     p.restore_tau = w.restore_days * 86400.0 if w.restore_days > 0 else 0.0
     p.pgf_weight = w.pgf_weight
+    p.salinity = 1 if getattr(w, "salinity", False) else 0
+    if p.salinity:
+        for q, c in enumerate(w.eos):
+            p.eos[q] = c
     return p
 
 
@@ -221,6 +227,10 @@ class Model:
         for name in ("T0", "taux", "tauy", "tstar"):
             if name in inp:
                 self.set("T" if name == "T0" else name, inp[name])
+        if self._params.salinity:
+            for name in ("S0", "sstar"):
+                if name in inp:
+                    self.set("S" if name == "S0" else name, inp[name])
 
     def close(self):
         if getattr(self, "handle", None):
@@ -232,7 +242,7 @@ class Model:
     def _shape(self, name):
         if name == "w":
             return (self.nz + 1, self.ny, self.nx)
-        if name == "tref":
+        if name in ("tref", "sref"):
             return (self.nz,)
         return (self.nz, self.ny, self.nx) if name in FIELDS_3D else (self.ny, self.nx)
 

@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     L = ocn.lib()
     for name in _declared():
         assert hasattr(L, name), name
-    assert L.ocn_abi_version() == 2
+    assert L.ocn_abi_version() == 3
 
 
 def _grid(w, **over):
@@ -71,6 +71,18 @@ def test_arena_size_scales_with_precision_and_validates_params():
     assert n64.value >= 9 * cells * 8 + 22 * 400 * 300 * 8
     assert n64.value - n32.value >= 9 * cells * 4
     assert n32.value < n64.value
+    # salinity adds four 3D fields (S, S*, and the two AB2 histories of S)
+    ns = C.c_size_t()
+    ps = ocn.params(w.replace(salinity=True), "fp64")
+    assert ps.salinity == 1 and list(ps.eos) == list(w.eos)
+    assert L.ocn_state_arena_bytes(h, C.byref(ps), C.byref(ns)) == 0
+    assert ns.value - n64.value >= 4 * cells * 8
+    bad = ocn.params(w.replace(salinity=True), "fp64")
+    bad.eos[3] = float("nan")
+    assert L.ocn_state_arena_bytes(h, C.byref(bad), C.byref(ns)) == ocn.OCN_E_INVALID
+    bad.salinity = 2
+    bad.eos[3] = 0.0
+    assert L.ocn_state_arena_bytes(h, C.byref(bad), C.byref(ns)) == ocn.OCN_E_INVALID
     bad = ocn.params(w, "fp64")
     bad.n_substeps = 0
     assert L.ocn_state_arena_bytes(h, C.byref(bad), C.byref(n64)) == ocn.OCN_E_INVALID
