@@ -43,7 +43,7 @@ __device__ __forceinline__ void store_wrapped2(const DevState& S, double* f, int
 
 // Level-count buckets of the register-resident solve.
 constexpr int kNzBuckets[] = {16, 32, 48, 64, 80, 100, 128};
-constexpr int kMaxNz = 128;
+constexpr int kMaxNz = kMaxLevels;
 
 // Copy a stored column into its periodic images (edge columns only): the
 // values are read back from the column just written by this thread, so the

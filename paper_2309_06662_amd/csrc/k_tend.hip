@@ -65,6 +65,12 @@ __device__ __forceinline__ double rcp(double x) {
     return r;
 }
 
+// 1/dz of a level: the FP64 quotient in FP64, the hardware reciprocal of the
+// rounded thickness in FP32 (a level value that every lane would otherwise
+// divide in FP64).
+__device__ __forceinline__ double inv_level(double dz, double) { return 1.0 / dz; }
+__device__ __forceinline__ float inv_level(double dz, float) { return __builtin_amdgcn_rcpf(float(dz)); }
+
 // Fifth-order WENO-Z face value (Borges et al. 2008) on Jiang-Shu smoothness
 // indicators; c is the upwind cell, the face lies between c and d. Written in
 // the differences d1..d4 of neighbouring values, with exact rescalings that
@@ -153,9 +159,11 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 
 // Occupancy target per precision: four waves per SIMD (two FP32 workgroups of
 // 8 waves per CU) keeps the FP32 kernel within 128 VGPRs; the second tracer
-// takes the FP32 kernel to the FP64 budget.
-template <typename R, bool SALT> struct TendWaves { static constexpr int n = 2; };
-template <> struct TendWaves<float, false> { static constexpr int n = 4; };
+// takes the FP32 kernel to the FP64 budget. The FP64 salinity kernel on
+// 64 x 4 tiles holds one workgroup per CU (two would exceed the LDS).
+template <typename R, bool SALT, int TY> struct TendWaves {
+    static constexpr int n = (sizeof(R) == 4 && !SALT) ? 4 : (sizeof(R) == 8 && SALT && TY == 4) ? 1 : 2;
+};
 
 // One tile (bx, by) of one state. Called by the single-state kernel and by the
 // batched kernel that steps an ensemble of basins in one launch.
@@ -173,8 +181,14 @@ template <> struct TendWaves<float, false> { static constexpr int n = 4; };
 // ring threads otherwise leave idle (u through the north-west corner for the
 // column, u through the cell centre for the row). Every point's pressure goes
 // to LDS; the momentum tendencies of level k are completed one level later,
-// when the pressure of level k of the neighbours is in LDS, so the march keeps
-// three barriers per level.
+// when the pressure of level k of the neighbours is in LDS.
+//
+// Barriers: two per level, after the staging of the level's value tiles and
+// after the point quantities. The tiles are double-buffered by level parity,
+// so a wave may stage level k-1 while others still read level k; the flux,
+// Coriolis and transport arrays of level k are only rewritten after the next
+// level's first barrier, which every wave reaches only once it has assembled
+// level k; the pressure is double-buffered by parity as well.
 template <typename R, int TX, int TY, bool SALT>
 __device__ __forceinline__ void tend_tile(const DevState& S, const int first, const int bx, const int by) {
     constexpr int NT = TX * TY;
@@ -184,7 +198,9 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     constexpr int NS = (LN + NT - 1) / NT;                 // u, v tile slots per thread
     constexpr int NST = (TN + NT - 1) / NT;                // T tile slots per thread
 
-    __shared__ R sT[TN], sU[LN], sV[LN];
+    // value tiles, double-buffered by level parity: level k-1 is staged while
+    // slower waves may still read level k, so a level needs two barriers
+    __shared__ R sT2[2][TN], sU2[2][LN], sV2[2][LN];
     __shared__ int sK[KN];
     __shared__ R fxT[NT], fyT[NT], fxu[NT], fyu[NT], fxv[NT], fyv[NT];
     __shared__ R sQv[NT], sQu[NT], sP[2 * NT], sWm[NT];
@@ -194,8 +210,18 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     __shared__ R sTop[NT];  // surface volume flux times the full top temperature
     // salinity: its tile, its face fluxes and the surface term, as for T
     constexpr int SN = SALT ? TN : 1, SNT = SALT ? NT : 1;
-    __shared__ R sS[SN];
+    __shared__ R sS2[2][SN];
     __shared__ R fxS[SNT], fyS[SNT], sTopS[SNT];
+    // Per-level constants, staged once (a level's loads from memory inside the
+    // march would be vector loads whose wait also drains the prefetch): dz,
+    // 1/dz, the centre spacing above (0 at the top), the four reference steps
+    // of T (see dtr) and with salinity those of S and the two linear
+    // equation-of-state coefficients; the FP64 thickness for the FP64 sums.
+    constexpr int LV_DZ = 0, LV_IDZ = 1, LV_DZC = 2, LV_T = 3, LV_S = 7, LV_ET = 11, LV_ES = 12;
+    constexpr int NLV = SALT ? 13 : 7;
+    constexpr bool kF32 = sizeof(R) == 4;
+    __shared__ R sLev[kMaxLevels][NLV];
+    __shared__ double sDzD[kF32 ? kMaxLevels : 1];
 
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
     const int i0 = bx * (TX - 1), j0 = by * (TY - 1);
@@ -216,6 +242,24 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     const R* __restrict__ dsr = SALT ? static_cast<const R*>(S.dsr) : nullptr;
     const R* __restrict__ eost = SALT ? static_cast<const R*>(S.eos_tab) : nullptr;
 
+    for (int q = tid; q < S.nz; q += NT) {
+        sLev[q][LV_DZ] = R(S.dz[q]);
+        sLev[q][LV_IDZ] = inv_level(S.dz[q], R(0));
+        sLev[q][LV_DZC] = (q + 1 < S.nz) ? R(S.dzc[q + 1]) : R(0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sLev[q][LV_T + j] = dtr[q * 4 + j];
+        if constexpr (SALT) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) sLev[q][LV_S + j] = dsr[q * 4 + j];
+            sLev[q][LV_ET] = eost[2 * q];
+            sLev[q][LV_ES] = eost[2 * q + 1];
+        }
+        if constexpr (kF32) sDzD[q] = S.dz[q];
+    }
+    auto dz_d = [&](int kk) -> double {
+        if constexpr (kF32) return sDzD[kk];
+        else return sLev[kk][LV_DZ];
+    };
     // wet-layer counts of the tile (static over the march), origin (i0-4, j0-4)
     for (int q = tid; q < KN; q += NT) {
         const int li = q % KW, lj = q / KW;
@@ -350,6 +394,15 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
             if (k >= 0 && k < nz) { wu[r] = gU[k * pl + own]; wv[r] = gV[k * pl + own]; }
         }
     }
+    // the level that enters the windows at the next shift (loaded a level ahead)
+    R wtn = R(0), wun = R(0), wvn = R(0), wsn = R(0);
+    if (nz - 4 >= 0) {
+        const long long o = (long long)(nz - 4) * pl + own;
+        if (tcell) wtn = gT[o];
+        if constexpr (SALT)
+            if (tcell) wsn = gS[o];
+        if (cell) { wun = gU[o]; wvn = gV[o]; }
+    }
 
     // prefetch of the top level's tile slots
     R pT[NST], pU[NS], pV[NS], pS[SALT ? NST : 1];
@@ -385,19 +438,31 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     // Completes the momentum step of level kk (one above the level being
     // marched) once the pressure of level kk of every point is in LDS:
     // AB2 of the other terms plus the forward-backward pressure gradient.
+    // AB2 histories of the level being assembled (T, S) and of the level one
+    // above (u, v: its momentum completes now), loaded with the next level's
+    // tiles, before the level's barriers, so that no load in the march is
+    // waited for right after it is issued (a wait drains every earlier load)
+    R hgt = R(0), hgs = R(0), hgu = R(0), hgv = R(0);
+    auto load_hist = [&](int k) {
+        const long long o = (long long)k * pl + own;
+        if (tcell) hgt = gti[o];
+        if constexpr (SALT)
+            if (tcell) hgs = gsi[o];
+        if (cell && k + 1 < nz) { hgu = gup[o + pl]; hgv = gvp[o + pl]; }
+    };
     auto finish_uv = [&](int kk, const R* P) {
-        const long long o = (long long)kk * pl + own;
         const int kw = nz - kk;
-        R hU = c_new * GUp - c_old * gup[o];
-        R hV = c_new * GVp - c_old * gvp[o];
+        const long long o = (long long)kk * pl + own;
+        R hU = c_new * GUp - c_old * hgu;
+        R hV = c_new * GVp - c_old * hgv;
         gup[o] = GUp;
         gvp[o] = GVp;
         if (Ku >= kw) hU -= (P[tid] - P[tid - 1]) * sRow[7][ty];
         if (Kv >= kw) hV -= (P[tid] - P[tid - TX]) * inv_dy;
         uso[o] = wu[1] + dt * hU;
         vso[o] = wv[1] + dt * hV;
-        if (Ku >= kw) gUacc += double(S.dz[kk]) * double(hU);
-        if (Kv >= kw) gVacc += double(S.dz[kk]) * double(hV);
+        if (Ku >= kw) gUacc += dz_d(kk) * double(hU);
+        if (Kv >= kw) gVacc += dz_d(kk) * double(hV);
     };
 
     for (int k = nz - 1; k >= 0; --k) {
@@ -410,21 +475,21 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
         for (int q = 0; q < NS; ++q) asm volatile("" : "+v"(slot_off[q]));
 #pragma unroll
         for (int q = 0; q < NST; ++q) asm volatile("" : "+v"(slot_offT[q]));
-        // shift the windows and load level k-3
+        // shift the windows (level k-3 was loaded a level ahead)
 #pragma unroll
         for (int r = 0; r < 5; ++r) { wt[r] = wt[r + 1]; wu[r] = wu[r + 1]; wv[r] = wv[r + 1]; }
-        wt[5] = R(0); wu[5] = R(0); wv[5] = R(0);
-        if (tcell && k - 3 >= 0) wt[5] = gT[(long long)(k - 3) * pl + own];
+        wt[5] = wtn; wu[5] = wun; wv[5] = wvn;
         if constexpr (SALT) {
 #pragma unroll
             for (int r = 0; r < 5; ++r) ws[r] = ws[r + 1];
-            ws[5] = (tcell && k - 3 >= 0) ? gS[(long long)(k - 3) * pl + own] : R(0);
+            ws[5] = wsn;
         }
-        if (cell && k - 3 >= 0) {
-            const long long o = (long long)(k - 3) * pl + own;
-            wu[5] = gU[o]; wv[5] = gV[o];
-        }
-        // stage level k from the prefetch registers, then prefetch level k-1
+        // stage level k from the prefetch registers, then issue every load
+        // of the next level
+        R* const sT = sT2[k & 1];
+        R* const sU = sU2[k & 1];
+        R* const sV = sV2[k & 1];
+        R* const sS = sS2[SALT ? (k & 1) : 0];
 #pragma unroll
         for (int q = 0; q < NST; ++q) {
             const int e = tid + q * NT;
@@ -437,6 +502,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
             const int e = tid + q * NT;
             if (e < LN) { sU[e] = pU[q]; sV[e] = pV[q]; }
         }
+        load_hist(k);
         if (k >= 1) {
 #pragma unroll
             for (int q = 0; q < NST; ++q) pT[q] = gT[(long long)(k - 1) * pl + slot_offT[q]];
@@ -449,10 +515,18 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                 pU[q] = gU[o]; pV[q] = gV[o];
             }
         }
+        wtn = R(0); wun = R(0); wvn = R(0); wsn = R(0);
+        if (k - 4 >= 0) {
+            const long long o = (long long)(k - 4) * pl + own;
+            if (tcell) wtn = gT[o];
+            if constexpr (SALT)
+                if (tcell) wsn = gS[o];
+            if (cell) { wun = gU[o]; wvn = gV[o]; }
+        }
         __syncthreads();
 
-        const R dzk = R(S.dz[k]);
-        const R inv_dz = R(1.0 / S.dz[k]);
+        const R dzk = sLev[k][LV_DZ];
+        const R inv_dz = sLev[k][LV_IDZ];
         const int kwet = nz - k;  // a column with K wet layers is wet at k iff K >= nz - k
         auto wet = [&](int a, int b) { return Kat(a, b) >= kwet; };
         auto mu = [&](int a, int b) { return wet(a, b) && wet(a - 1, b); };
@@ -604,7 +678,6 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
         R* const Pk = &sP[(k & 1) * NT];
         if (tcell) {
             const int c = tid, cw = tid - 1, cs = tid - TX;
-            const long long o = (long long)k * pl + own;
 
             // vertical fluxes through the bottom face (between levels k-1 and k)
             R fzT_bot = R(0), fzu_bot = R(0), fzv_bot = R(0);
@@ -621,21 +694,22 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                     const int ld = pos ? k : k - 1, le = pos ? k + 1 : k - 2;
                     auto okl = [&](int l) { return l >= 0 && l < nz && Kc >= nz - l; };
                     const bool open = zin && Kc >= nz - (k - 3);
-                    auto zflux = [&](const R* w, const R* __restrict__ tab, R& Eb) {
+                    auto zflux = [&](const R* w, const int tab, R& Eb) {
                         const R ta = pos ? w[5] : w[0], tb = pos ? w[4] : w[1], tcv = pos ? w[3] : w[2];
                         const R td = pos ? w[2] : w[3], te = pos ? w[1] : w[4];
-                        const R da = (ta - tcv) + (pos ? tab[kc * 4 + 0] : tab[kc * 4 + 3]);
-                        const R db = (tb - tcv) + (pos ? tab[kc * 4 + 1] : tab[kc * 4 + 2]);
-                        const R dd = (td - tcv) + (pos ? tab[kc * 4 + 2] : tab[kc * 4 + 1]);
-                        const R de = (te - tcv) + (pos ? tab[kc * 4 + 3] : tab[kc * 4 + 0]);
+                        const R* st = &sLev[kc][tab];
+                        const R da = (ta - tcv) + (pos ? st[0] : st[3]);
+                        const R db = (tb - tcv) + (pos ? st[1] : st[2]);
+                        const R dd = (td - tcv) + (pos ? st[2] : st[1]);
+                        const R de = (te - tcv) + (pos ? st[3] : st[0]);
                         const R rel = open ? weno5z(da, db, R(0), dd, de)
                                            : recon(da, db, R(0), dd, de, okl(la), okl(lb), true, okl(ld), okl(le));
                         // reference profile carried through this face, relative to the level's reference
-                        Eb = pos ? Wm_b * (-tab[k * 4 + 1]) : R(0);
+                        Eb = pos ? Wm_b * (-sLev[k][tab + 1]) : R(0);
                         return Wm_b * (tcv + rel);
                     };
-                    fzT_bot = zflux(wt, dtr, E_bot);
-                    if constexpr (SALT) fzS_bot = zflux(ws, dsr, ES_bot);
+                    fzT_bot = zflux(wt, LV_T, E_bot);
+                    if constexpr (SALT) fzS_bot = zflux(ws, LV_S, ES_bot);
                 }
                 if (cell) {
                     const R Fu = R(0.5) * (sWm[cw] + Wm_b);
@@ -683,7 +757,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                     E_top = sTop[c];
                 } else {
                     // upwind cell k+1 when the face transport is downward
-                    E_top = (Wm_top > R(0)) ? R(0) : Wm_top * (-dtr[k * 4 + 2]);
+                    E_top = (Wm_top > R(0)) ? R(0) : Wm_top * (-sLev[k][LV_T + 2]);
                 }
                 const R fw = (tx == 0) ? fyu[c] : fxT[cw];
                 const R fs = (ty == 0) ? fxu[c] : fyT[cs];
@@ -697,7 +771,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                 if (Kc >= kwet) {
                     R ES_top;
                     if (k == nz - 1) ES_top = sTopS[c];
-                    else ES_top = (Wm_top > R(0)) ? R(0) : Wm_top * (-dsr[k * 4 + 2]);
+                    else ES_top = (Wm_top > R(0)) ? R(0) : Wm_top * (-sLev[k][LV_S + 2]);
                     const R fw = (tx == 0) ? fyv[c] : fxS[cw];
                     const R fs = (ty == 0) ? fxv[c] : fyS[cs];
                     const R divF = (fxS[c] - fw) + (fyS[c] - fs) + (fzS_top - fzS_bot);
@@ -707,7 +781,8 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
             }
             // AB2 of the tracer (G^n goes to the other history buffer), and the
             // pressure of T^n + eps dt Ghat_T from p = 0 at z = 0 downward
-            const R hT = c_new * GT - c_old * gti[o];
+            const R hT = c_new * GT - c_old * hgt;
+            const long long o = (long long)k * pl + own;
             if (cell) {
                 gto[o] = GT;
                 tso[o] = wt[2] + dt * hT;
@@ -716,23 +791,23 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
             if constexpr (SALT) {
                 // buoyancy anomaly of T' + eps dt Ghat_T, S' + eps dt Ghat_S
                 // (quadratic equation of state about the level's reference water)
-                const R hS = c_new * GS - c_old * gsi[o];
+                const R hS = c_new * GS - c_old * hgs;
                 if (cell) {
                     gso[o] = GS;
                     sso[o] = ws[2] + dt * hS;
                 }
                 const R tf = wt[2] + fbdt * hT, sf = ws[2] + fbdt * hS;
-                b = tf * (eost[2 * k] + qT * tf + qTS * sf) + sf * (eost[2 * k + 1] + qS * sf);
+                b = tf * (sLev[k][LV_ET] + qT * tf + qTS * sf) + sf * (sLev[k][LV_ES] + qS * sf);
             } else {
                 b = ga * (wt[2] + fbdt * hT);
             }
-            const R pk = (k == nz - 1) ? -R(0.5) * dzk * b : p_prev - R(S.dzc[k + 1]) * (R(0.5) * (b + b_prev));
+            const R pk = (k == nz - 1) ? -R(0.5) * dzk * b : p_prev - sLev[k][LV_DZC] * (R(0.5) * (b + b_prev));
             p_prev = pk;
             b_prev = b;
             Pk[tid] = pk;
 
             // momentum of the cells: level k+1 completes with its pressure
-            // (written before the last barrier); level k waits for its own
+            // (written one level earlier); level k waits for its own
             if (cell) {
                 if (k + 1 < nz) finish_uv(k + 1, &sP[((k + 1) & 1) * NT]);
                 R GUm = R(0);
@@ -759,11 +834,13 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
             fzv_top = fzv_bot;
         }
         Wm_top = Wm_b;
-        __syncthreads();
     }
-    // the bottom level's pressure is in LDS after the last barrier; the window
+    __syncthreads();
+    // the bottom level's pressure is in LDS after this barrier; the window
     // is shifted once more so that w[1] holds level 0
     if (cell) {
+        hgu = gup[own];  // level 0
+        hgv = gvp[own];
 #pragma unroll
         for (int r = 0; r < 5; ++r) { wu[r] = wu[r + 1]; wv[r] = wv[r + 1]; }
         finish_uv(0, &sP[0]);
@@ -781,7 +858,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
 }
 
 template <typename R, int TX, int TY, bool SALT>
-__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R, SALT>::n)))
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R, SALT, TY>::n)))
 void k_tend(const DevState S, const int first, const int gx) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     tend_tile<R, TX, TY, SALT>(S, first, tile % gx, tile / gx);
@@ -790,7 +867,7 @@ void k_tend(const DevState S, const int first, const int gx) {
 // Ensemble: entry b of the tile table names (member, bx, by); the host orders
 // the table so that each XCD receives contiguous tiles of a member.
 template <typename R, int TY>
-__global__ __launch_bounds__(TXB * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R, false>::n)))
+__global__ __launch_bounds__(TXB * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R, false, TY>::n)))
 void k_tend_batched(const DevState* __restrict__ members, const int4* __restrict__ tiles, const int first) {
     const int4 e = tiles[blockIdx.x];
     tend_tile<R, TXB, TY, false>(members[e.x], first, e.y, e.z);

@@ -793,7 +793,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         if (reinterpret_cast<uintptr_t>(device_arena) % 256) return fail(OCN_E_INVALID, "arena must be 256-byte aligned");
         const Plan P = make_plan(grid, params->precision, params->n_substeps, params->salinity);
         if (arena_bytes < P.total) return fail(OCN_E_NOMEM, "arena smaller than ocn_state_arena_bytes");
-        if (grid->nz > 128) return fail(OCN_E_UNSUPPORTED, "nz above 128 is not supported by the column kernel");
+        if (grid->nz > ocn::kMaxLevels) return fail(OCN_E_UNSUPPORTED, "nz above 128 is not supported (column solve, tendency level table)");
 
         ocn_state* s = new ocn_state();
         s->g = grid;

@@ -203,6 +203,9 @@ hipError_t launch_column_batched(const DevState* members, const int4* tiles, int
 int baro_substeps(int n_substeps);  // Ns + Ns/2
 hipError_t launch_barotropic_batched(const DevState* members, int n_members, const int4* tiles, int ntiles,
                                      int n_substeps, int fuse, double dt, hipStream_t st);
+// Most levels a state may have (the column solve's register buckets and the
+// tendency kernel's per-level LDS table are sized for it).
+constexpr int kMaxLevels = 128;
 constexpr int kBaroTileX = 64, kBaroTileY = 24;
 // substeps per barotropic launch unless chosen: 7 keeps the 64 x 24 tile's LDS
 // (72 KB) and registers (119) within two workgroups per CU
