@@ -56,9 +56,15 @@ TEND_WORDS_PER_CELL = 12
 # 12 AB2, 2 for the predicted tracer of the pressure, 4 slow-forcing sums and
 # 3 surface forcing = 782.
 TEND_FLOPS_PER_CELL = 782
-# Barotropic launch (FP64): read eta, U, V, G_U, G_V, H_u, H_v and the five
-# window sums, write eta, U, V and the five sums = 20 words per column.
-BARO_WORDS_PER_COLUMN = 20
+# Barotropic stage (FP64), per column and launch of up to 7 substeps: read
+# eta, U, V, G_U, G_V and the wet-layer count (half a word), the two transport
+# sums (not in the first launch) and the three window sums (only once the
+# averaging window has begun); write eta, U, V, the two transport sums and the
+# three window sums (only once the window has begun), or in the last launch
+# eta, U, V and the three step means; plus the copy back of eta, U, V after an
+# odd number of launches. Summed over the launches of a step by
+# baro_words_per_step().
+BARO_FUSE = 7
 # Column solve with the constant diffusivity: read u*, v*, T* and write u, v, T.
 COLUMN_WORDS_PER_CELL = 6
 KERNEL_SOURCES = {"k_tend": "k_tend.hip", "k_baro_fused": "k_baro.hip", "k_column": "k_column.hip"}
@@ -279,12 +285,30 @@ def copy_bandwidth(mib=2048, repeat=5):
     return 2.0 * 4 * n * repeat / el / 1e9
 
 
+def baro_words_per_step(n_substeps, fuse=BARO_FUSE):
+    """FP64 words per column that the barotropic stage of one step must move."""
+    M = n_substeps + n_substeps // 2
+    qf = next((q for q in range(1, M + 1) if abs(q / n_substeps - 1.0) < 0.5), M + 1)
+    words, launches = 0.0, 0
+    for m0 in range(0, M, fuse):
+        ss = min(fuse, M - m0)
+        first, last = m0 == 0, m0 + ss == M
+        rd = 5.5 + (0 if first else 2) + (3 if m0 >= qf else 0)
+        wr = 6 if last else 3 + 2 + (3 if m0 + ss >= qf else 0)
+        words += rd + wr
+        launches += 1
+    if launches % 2:
+        words += 6
+    return words, launches
+
+
 def roofline(w, precision, stage_ms, n_baro_launches):
     """Rooflines of the three stages from their HIP-event times per step.
 
     Tendency: 12 words per cell, or 782 flops per cell against the vector
-    peak, whichever fraction is larger (the dominant kernel). Barotropic: 20
-    FP64 words per column per launch. Column solve: 6 words per cell."""
+    peak, whichever fraction is larger (the dominant kernel). Barotropic: the
+    FP64 words per column of baro_words_per_step(). Column solve: 6 words per
+    cell."""
     esize = 4 if precision == "fp32" else 8
     t = stage_ms["tendency"] * 1e-3
     cells = w.cells
@@ -297,11 +321,14 @@ def roofline(w, precision, stage_ms, n_baro_launches):
     main, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
     main = dict(main, kernel="k_tend", traffic=_traffic_from_profiles(w.name, precision, "k_tend"))
     cols = w.nx * w.ny
-    baro_bytes = BARO_WORDS_PER_COLUMN * 8 * cols  # per launch
-    tb = stage_ms["barotropic"] * 1e-3 / max(n_baro_launches, 1)
+    words, _ = baro_words_per_step(w.n_substeps)
+    baro_step_bytes = words * 8 * cols
+    tb = stage_ms["barotropic"] * 1e-3
     baro = {"kernel": "k_baro_fused", "bound": "hbm", "launches_per_step": n_baro_launches,
-            "bytes_per_launch": baro_bytes, "achieved": round(baro_bytes / tb / 1e9, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(baro_bytes / tb / 1e9 / HBM_PEAK_GBS, 4),
+            "words_per_column_step": words, "bytes_per_step": baro_step_bytes,
+            "bytes_per_launch": round(baro_step_bytes / max(n_baro_launches, 1)),
+            "achieved": round(baro_step_bytes / tb / 1e9, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(baro_step_bytes / tb / 1e9 / HBM_PEAK_GBS, 4),
             "share_of_step": round(stage_ms["barotropic"] / sum(stage_ms[k] for k in ("tendency", "barotropic", "column")), 4),
             "traffic": _traffic_from_profiles(w.name, precision, "k_baro_fused")}
     col_bytes = COLUMN_WORDS_PER_CELL * esize * cells
@@ -508,7 +535,7 @@ def main():
         print(f"[bench] 1/4 degree: {extra['quarter']}", file=sys.stderr, flush=True)
 
     main_rec = results["fp32"]
-    n_baro = -(-(w.n_substeps + w.n_substeps // 2) // 7)  # substeps per step in groups of 7 per launch
+    n_baro = baro_words_per_step(w.n_substeps)[1]  # launches per step
     roof, other, stage_roofs = roofline(w, "fp32", main_rec["stage_ms"], n_baro)
     if "copy_gbs" in extra and roof["unit"] == "GB/s":
         roof["frac_of_measured_copy"] = round(roof["achieved"] / extra["copy_gbs"], 4)

@@ -14,6 +14,7 @@
 #include "ocn_dev.h"
 
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 namespace ocn {
@@ -130,17 +131,34 @@ constexpr int kManyTiles = 256;
 // Registers hold only what each halo-inclusive point needs every substep
 // (depths and slow forcing); row metrics sit in small LDS tables, and the
 // window sums live with a second mapping over the interior points only (FI
-// per thread).
+// per thread). The depths of a point's u and v columns are looked up from
+// their wet-layer counts (one 4-byte count per point instead of two 8-byte
+// depths from memory). Window flags: bit 0, the sums of the averaging window
+// carried in are not all zero (read them); bit 1, they are not all zero after
+// this launch (write them); launches before the window's first nonzero weight
+// skip both.
 template <int BX, int BY, int SH>
 __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const int by, const double dtau,
-                                          const int m0, const int first, const int last, const int parity) {
+                                          const int m0, const int first, const int last, const int parity,
+                                          const int wflags) {
     constexpr int FBX = BX, FBY = BY;
     constexpr int FEW = FBX + 2 * SH, FEH = FBY + 2 * SH, FEN = FEW * FEH;
     constexpr int FQ = (FEN + FT - 1) / FT;  // halo-inclusive points per thread
     constexpr int FI = FBX * FBY / FT;       // interior points per thread
     static_assert(FBX * FBY % FT == 0, "interior points must divide evenly over the threads");
-    __shared__ double sE[FEN], sU[FEN], sV[FEN];
-    __shared__ double sRdxc[FEH], sDxv0[FEH], sDxv1[FEH], sRarea[FEH];
+    // state tiles with a row of padding before and after, so that the
+    // neighbours e +- 1 and e +- FEW of every point are addresses of the tile
+    // (values there are garbage by the halo argument and never reach the
+    // interior)
+    __shared__ double sEp[FEN + 2 * FEW], sUp[FEN + 2 * FEW], sVp[FEN + 2 * FEW];
+    double* const sE = sEp + FEW;
+    double* const sU = sUp + FEW;
+    double* const sV = sVp + FEW;
+    // per-row coefficients of the surface update (dtau/A times dy, dxv south,
+    // dxv north) and of the zonal transport update (-g dtau / dxc)
+    __shared__ double sCdy[FEH], sC0[FEH], sC1[FEH], sCu[FEH];
+    __shared__ double sCum[kMaxLevels + 1];
+    __shared__ double sWa[SH], sWA[SH];  // a_{m0+1+m} and A_{m0+m} of the launch's substeps
     const double* __restrict__ inE = parity ? S.eta2 : S.eta;
     const double* __restrict__ inU = parity ? S.ubt2 : S.ubt;
     const double* __restrict__ inV = parity ? S.vbt2 : S.vbt;
@@ -150,63 +168,117 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
     const int tid = threadIdx.x;
     const int i0 = bx * FBX, j0 = by * FBY;
     const int nx = S.nx, ny = S.ny;
+    const double dy = S.dy, g = S.g;
 
+    for (int k = tid; k <= S.nz; k += FT) sCum[k] = S.cumh[k];
+    if (tid < SH) {
+        sWa[tid] = S.baro_a[m0 + tid + 1];
+        sWA[tid] = S.baro_A[m0 + tid];
+    }
     // row metrics (rows past a closed edge take the nearest row; unused)
     for (int lj = tid; lj < FEH; lj += FT) {
         int gj = j0 - SH + lj;
         if (S.periodic_y) gj = ((gj % ny) + ny) % ny;
         const int jm = min(max(gj, 0), ny - 1);
-        sRdxc[lj] = 1.0 / S.dxc[jm];
-        sDxv0[lj] = S.dxv[jm];
-        sDxv1[lj] = S.dxv[jm + 1];
-        sRarea[lj] = 1.0 / S.area[jm];
+        const double ra = dtau / S.area[jm];
+        sCdy[lj] = ra * S.dy;
+        sC0[lj] = ra * S.dxv[jm];
+        sC1[lj] = ra * S.dxv[jm + 1];
+        sCu[lj] = -S.g * dtau / S.dxc[jm];
     }
-    // halo-inclusive points: forcing and depths, and the state into LDS
+    for (int q = tid; q < FEW; q += FT) {
+        sEp[q] = 0.0; sUp[q] = 0.0; sVp[q] = 0.0;
+        sEp[FEN + FEW + q] = 0.0; sUp[FEN + FEW + q] = 0.0; sVp[FEN + FEW + q] = 0.0;
+    }
+    // halo-inclusive points: forcing and wet-layer counts of the u and v
+    // columns, and the state into LDS. Every load is issued (at a valid,
+    // clamped address) before any is used, so that the waits for them do not
+    // serialise the points. The transport update of a point is
+    // U + Cu (eta - eta_west) + Gu with Cu = -g dtau Hu / dxc and Gu = dtau gU
+    // (V likewise with dy), Cu = 0 on dry faces.
     double gU[FQ], gV[FQ], Hu[FQ], Hv[FQ];
-#pragma unroll
-    for (int q = 0; q < FQ; ++q) {
-        const int e = tid + q * FT;
-        const int li = e % FEW, lj = e / FEW;
-        int gi = i0 - SH + li, gj = j0 - SH + lj;
-        bool inside = e < FEN;
-        if (S.periodic_x) gi = ((gi % nx) + nx) % nx;
-        else inside = inside && gi >= 0 && gi < nx;
-        if (S.periodic_y) gj = ((gj % ny) + ny) % ny;
-        else inside = inside && gj >= 0 && gj < ny;
-        const int jm = min(max(gj, 0), ny - 1);
-        const long long c = idx2(S, inside ? gi : 0, inside ? jm : 0);
-        gU[q] = inside ? S.gU[c] : 0.0;
-        gV[q] = inside ? S.gV[c] : 0.0;
-        Hu[q] = inside ? S.hu[c] : 0.0;
-        Hv[q] = inside ? S.hv[c] : 0.0;
-        if (e < FEN) {
-            sE[e] = inside ? inE[c] : 0.0;
-            sU[e] = inside ? inU[c] : 0.0;
-            sV[e] = inside ? inV[c] : 0.0;
-        }
-    }
-    // interior points: window sums carried between launches
-    double aU[FI], aV[FI];          // sum_l A_l U^l, V^l (transport of the step)
+    int Ku[FQ], Kv[FQ];
+    double aU[FI], aV[FI];          // interior points: sum_l A_l U^l, V^l (transport of the step)
     double fE[FI], fU[FI], fV[FI];  // sum_q a_q eta^q, U^q, V^q (new state)
     int ie[FI];                     // LDS index, -1 outside the domain
+    {
+        double lE[FQ], lU[FQ], lV[FQ];
+        int kc[FQ], kw[FQ], ks[FQ];
+        bool in[FQ];
 #pragma unroll
-    for (int p = 0; p < FI; ++p) {
-        const int pp = tid + p * FT;
-        const int ti = i0 + pp % FBX, tj = j0 + pp / FBX;
-        const bool live = ti < nx && tj < ny;
-        ie[p] = live ? (SH + pp / FBX) * FEW + SH + pp % FBX : -1;
-        const long long c = idx2(S, live ? ti : 0, live ? tj : 0);
-        const bool carry = live && !first;
-        aU[p] = carry ? S.su[c] : 0.0;
-        aV[p] = carry ? S.sv[c] : 0.0;
-        fE[p] = carry ? S.se[c] : 0.0;
-        fU[p] = carry ? S.sfu[c] : 0.0;
-        fV[p] = carry ? S.sfv[c] : 0.0;
+        for (int q = 0; q < FQ; ++q) {
+            const int e = tid + q * FT;
+            const int li = e % FEW, lj = e / FEW;
+            int gi = i0 - SH + li, gj = j0 - SH + lj;
+            bool inside = e < FEN;
+            if (S.periodic_x) gi = ((gi % nx) + nx) % nx;
+            else inside = inside && gi >= 0 && gi < nx;
+            if (S.periodic_y) gj = ((gj % ny) + ny) % ny;
+            else inside = inside && gj >= 0 && gj < ny;
+            const int gic = inside ? gi : 0, jmc = inside ? min(max(gj, 0), ny - 1) : 0;
+            const long long c = idx2(S, gic, jmc);
+            in[q] = inside;
+            gU[q] = S.gU[c];
+            gV[q] = S.gV[c];
+            lE[q] = inE[c];
+            lU[q] = inU[c];
+            lV[q] = inV[c];
+            kc[q] = S.kb[idxk(S, gic, jmc)];
+            kw[q] = S.kb[idxk(S, gic - 1, jmc)];
+            ks[q] = S.kb[idxk(S, gic, jmc - 1)];
+        }
+        // interior points: window sums carried between launches (issued with
+        // the point loads)
+#pragma unroll
+        for (int p = 0; p < FI; ++p) {
+            const int pp = tid + p * FT;
+            const int ti = i0 + pp % FBX, tj = j0 + pp / FBX;
+            const bool live = ti < nx && tj < ny;
+            ie[p] = live ? (SH + pp / FBX) * FEW + SH + pp % FBX : -1;
+            const long long c = idx2(S, live ? ti : 0, live ? tj : 0);
+            const bool carry = live && !first;
+            const bool carryw = carry && (wflags & 1);
+            aU[p] = carry ? S.su[c] : 0.0;
+            aV[p] = carry ? S.sv[c] : 0.0;
+            fE[p] = 0.0;
+            fU[p] = 0.0;
+            fV[p] = 0.0;
+            if (carryw) {
+                fE[p] = S.se[c];
+                fU[p] = S.sfu[c];
+                fV[p] = S.sfv[c];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < FQ; ++q) {
+            const int e = tid + q * FT;
+            const bool inside = in[q];
+            gU[q] = inside ? gU[q] : 0.0;
+            gV[q] = inside ? gV[q] : 0.0;
+            Ku[q] = inside ? min(kc[q], kw[q]) : 0;
+            Kv[q] = inside ? min(kc[q], ks[q]) : 0;
+            if (e < FEN) {
+                sE[e] = inside ? lE[q] : 0.0;
+                sU[e] = inside ? lU[q] : 0.0;
+                sV[e] = inside ? lV[q] : 0.0;
+            }
+        }
     }
     __syncthreads();
+    {
+        const double cv = -g * dtau / dy;
+#pragma unroll
+        for (int q = 0; q < FQ; ++q) {
+            const int lj = min((tid + q * FT) / FEW, FEH - 1);
+            Hu[q] = sCum[Ku[q]] * sCu[lj];
+            Hv[q] = sCum[Kv[q]] * cv;
+            gU[q] *= dtau;
+            gV[q] *= dtau;
+        }
+    }
     // the transport sum takes U^l at the start of each substep l
     {
-        const double A0 = S.baro_A[m0];
+        const double A0 = sWA[0];
 #pragma unroll
         for (int p = 0; p < FI; ++p) {
             if (ie[p] < 0) continue;
@@ -215,23 +287,26 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
         }
     }
 
-    const double dy = S.dy, g = S.g;
     int tq = tid;
     for (int m = 0; m < SH; ++m) {
         // each point's LDS neighbours are recomputed from the thread index every
         // substep (a few integer operations) rather than kept in registers
         asm volatile("" : "+v"(tq));
-        const double am = S.baro_a[m0 + m + 1];
+        const double am = sWa[m];
+        // Rows that matter at substep m: below row m the transports and
+        // above row FEH-2-m the surface are already invalid (the region of
+        // correct values shrinks by a row on each side per substep, as
+        // eta(r) reads V(r), V(r+1) and V(r) reads eta(r-1), eta(r)), so only
+        // rows m .. FEH-2-m are updated; whole waves outside skip the work.
+        const int rlo = m, rhi = FEH - 2 - m;
         // free surface from the divergence of the transports, in place
 #pragma unroll
         for (int q = 0; q < FQ; ++q) {
             const int e = tq + q * FT;
-            if (e < FEN) {
-                const int li = e % FEW, lj = e / FEW;
-                const int ee = (li + 1 < FEW) ? e + 1 : e;    // tile edge: garbage stays in the halo
-                const int en_ = (lj + 1 < FEH) ? e + FEW : e;
-                const double div = dy * (sU[ee] - sU[e]) + sDxv1[lj] * sV[en_] - sDxv0[lj] * sV[e];
-                sE[e] = sE[e] - dtau * sRarea[lj] * div;
+            const int lj = e / FEW;
+            if (e < FEN && lj >= rlo && lj <= rhi) {
+                const double div = sCdy[lj] * (sU[e + 1] - sU[e]) + sC1[lj] * sV[e + FEW] - sC0[lj] * sV[e];
+                sE[e] = sE[e] - div;
             }
         }
         __syncthreads();
@@ -244,19 +319,17 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
 #pragma unroll
         for (int q = 0; q < FQ; ++q) {
             const int e = tq + q * FT;
-            if (e < FEN) {
-                const int li = e % FEW, lj = e / FEW;
-                const int ew_ = (li >= 1) ? e - 1 : e;
-                const int es_ = (lj >= 1) ? e - FEW : e;
-                const double hu = Hu[q], hv = Hv[q];
-                const double un = hu > 0.0 ? sU[e] + dtau * (-g * hu * (sE[e] - sE[ew_]) * sRdxc[lj] + gU[q]) : 0.0;
-                const double vn = hv > 0.0 ? sV[e] + dtau * (-g * hv * (sE[e] - sE[es_]) / dy + gV[q]) : 0.0;
+            const int lj = e / FEW;
+            if (e < FEN && lj >= rlo && lj <= rhi) {
+                const double ec = sE[e];
+                const double un = Hu[q] != 0.0 ? sU[e] + fma(Hu[q], ec - sE[e - 1], gU[q]) : 0.0;
+                const double vn = Hv[q] != 0.0 ? sV[e] + fma(Hv[q], ec - sE[e - FEW], gV[q]) : 0.0;
                 sU[e] = un;
                 sV[e] = vn;
             }
         }
         __syncthreads();
-        const double An = (m + 1 < SH) ? S.baro_A[m0 + m + 1] : 0.0;
+        const double An = (m + 1 < SH) ? sWA[m + 1 < SH ? m + 1 : 0] : 0.0;
 #pragma unroll
         for (int p = 0; p < FI; ++p) {
             if (ie[p] < 0) continue;
@@ -299,17 +372,29 @@ __device__ __forceinline__ void baro_tile(const DevState& S, const int bx, const
         } else {
             S.su[c] = aU[p];
             S.sv[c] = aV[p];
-            S.se[c] = fE[p];
-            S.sfu[c] = fU[p];
-            S.sfv[c] = fV[p];
+            if (wflags & 2) {
+                S.se[c] = fE[p];
+                S.sfu[c] = fU[p];
+                S.sfv[c] = fV[p];
+            }
         }
     }
 }
 
+// Occupancy target: two 8-wave workgroups per CU while their LDS fits (halo
+// widths up to 7 on 64 x 24 tiles), else one.
+template <int BX, int BY, int SH> struct BaroWaves {
+    static constexpr int n = ((BX + 2 * SH) * (BY + 2 * SH) + 2 * (BX + 2 * SH)) * 24 <= 78 * 1024 ? 4 : 2;
+};
+
 template <int BX, int BY, int SH>
-__global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(4))) void k_baro_fused(const DevState S, const double dtau, const int m0,
-                                                   const int first, const int last, const int parity) {
-    baro_tile<BX, BY, SH>(S, blockIdx.x, blockIdx.y, dtau, m0, first, last, parity);
+__global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(BaroWaves<BX, BY, SH>::n))) void k_baro_fused(
+    const DevState S, const double dtau, const int m0, const int first, const int last, const int parity,
+    const int wflags, const int gx) {
+    // row-major tiles in per-XCD ranges (halo rows of a tile come from the L2
+    // its neighbours filled)
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    baro_tile<BX, BY, SH>(S, t % gx, t / gx, dtau, m0, first, last, parity, wflags);
 }
 
 // Second buffers back to the primary ones (whole padded arrays, halos included).
@@ -336,12 +421,12 @@ __global__ __launch_bounds__(256) void k_baro_copyback_batched(const DevState* _
 
 // Ensemble: entry blockIdx.x of the table is (member, bx, by).
 template <int SH>
-__global__ __launch_bounds__(FT) void k_baro_fused_batched(const DevState* __restrict__ members,
+__global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(BaroWaves<kBaroTileX, kBaroTileY, SH>::n))) void k_baro_fused_batched(const DevState* __restrict__ members,
                                                            const int4* __restrict__ tiles, const double dtau,
                                                            const int m0, const int first, const int last,
-                                                           const int parity) {
+                                                           const int parity, const int wflags) {
     const int4 e = tiles[blockIdx.x];
-    baro_tile<kBaroTileX, kBaroTileY, SH>(members[e.x], e.y, e.z, dtau, m0, first, last, parity);
+    baro_tile<kBaroTileX, kBaroTileY, SH>(members[e.x], e.y, e.z, dtau, m0, first, last, parity, wflags);
 }
 
 // Instantiations per halo width 1..FSMAX: f<SH>() launches the kernel of that width.
@@ -362,6 +447,23 @@ hipError_t by_halo(int s, F&& f) {
 
 int baro_substeps(int n_substeps) { return n_substeps + n_substeps / 2; }
 
+// First substep q (1-based) whose window weight a_q is nonzero: the weights
+// are cos^2(pi t), t = q/Ns - 1, on |t| < 1/2 (the same test as the table's).
+static int window_first(int n_substeps) {
+    const int M = baro_substeps(n_substeps);
+    for (int q = 1; q <= M; ++q)
+        if (std::fabs(double(q) / n_substeps - 1.0) < 0.5) return q;
+    return M + 1;
+}
+
+// Window flags of a launch running substeps m0 .. m0+ss-1 (weights a_{m0+1} ..
+// a_{m0+ss}): read the carried sums if a weight before m0+1 was nonzero, write
+// them if one up to m0+ss was.
+static int window_flags(int n_substeps, int m0, int ss) {
+    const int qf = window_first(n_substeps);
+    return (m0 >= qf ? 1 : 0) | (m0 + ss >= qf ? 2 : 0);
+}
+
 hipError_t launch_barotropic_batched(const DevState* members, int n_members, const int4* tiles, int ntiles,
                                      int n_substeps, int fuse, double dt, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
@@ -375,7 +477,7 @@ hipError_t launch_barotropic_batched(const DevState* members, int n_members, con
         hipError_t e = by_halo(ss, [&](auto h) {
             constexpr int SH = decltype(h)::value;
             hipLaunchKernelGGL((k_baro_fused_batched<SH>), dim3(ntiles), dim3(FT), 0, st, members, tiles, dtau, m0,
-                               first, last, parity);
+                               first, last, parity, window_flags(n_substeps, m0, ss));
             return hipSuccess;
         });
         if (e != hipSuccess) return e;
@@ -393,7 +495,8 @@ hipError_t launch_barotropic_fused(const DevState& s, hipStream_t st) {
     const bool small = (long long)((s.nx + kBaroTileX - 1) / kBaroTileX) * ((s.ny + kBaroTileY - 1) / kBaroTileY) <
                        kManyTiles;
     const int bx = small ? kSmallTileX : kBaroTileX, by = small ? kSmallTileY : kBaroTileY;
-    dim3 grid((s.nx + bx - 1) / bx, (s.ny + by - 1) / by);
+    const int gx = (s.nx + bx - 1) / bx, gy = (s.ny + by - 1) / by;
+    const dim3 grid(gx * gy);
     const double dtau = s.dt / s.n_substeps;
     const int M = s.baro_m;
     int parity = 0;
@@ -402,12 +505,13 @@ hipError_t launch_barotropic_fused(const DevState& s, hipStream_t st) {
         const int first = m0 == 0, last = m0 + ss == M;
         hipError_t e = by_halo(ss, [&](auto h) {
             constexpr int SH = decltype(h)::value;
+            const int wf = window_flags(s.n_substeps, m0, ss);
             if (small)
                 hipLaunchKernelGGL((k_baro_fused<kSmallTileX, kSmallTileY, SH>), grid, dim3(FT), 0, st, s, dtau, m0,
-                                   first, last, parity);
+                                   first, last, parity, wf, gx);
             else
                 hipLaunchKernelGGL((k_baro_fused<kBaroTileX, kBaroTileY, SH>), grid, dim3(FT), 0, st, s, dtau, m0,
-                                   first, last, parity);
+                                   first, last, parity, wf, gx);
             return hipSuccess;
         });
         if (e != hipSuccess) return e;

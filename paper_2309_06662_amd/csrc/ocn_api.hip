@@ -155,7 +155,7 @@ struct Plan {
     size_t nrow;  // metric rows
     size_t diag_blocks;
     int nf3, nf2;  // 3D and 2D arrays of the state (more with salinity)
-    size_t off_f3[14], off_f2[25], off_bw, off_kb, off_rows[5], off_dz, off_dzc, off_tref, off_dtr, off_tab;
+    size_t off_f3[14], off_f2[25], off_bw, off_kb, off_rows[5], off_dz, off_dzc, off_tref, off_dtr, off_tab, off_cumh;
     size_t off_sref, off_dsr, off_eos, off_zc;
     size_t off_part, off_out;
     size_t total;
@@ -187,6 +187,7 @@ Plan make_plan(const ocn_grid* g, int precision, int n_substeps, int salinity) {
     for (auto& o : P.off_rows) o = L.add(P.nrow * sizeof(double));
     P.off_dz = L.add(g->nz * sizeof(double));
     P.off_dzc = L.add((g->nz + 1) * sizeof(double));
+    P.off_cumh = L.add((g->nz + 1) * sizeof(double));
     P.off_tref = L.add(g->nz * sizeof(double));
     P.off_dtr = L.add(g->nz * 4 * P.esize);
     P.off_tab = L.add((size_t)4 * g->nz * P.esize);
@@ -427,6 +428,16 @@ int init_static(ocn_state* s) {
             hu[(size_t)j * nx + i] = a;
             hv[(size_t)j * nx + i] = b;
         }
+    // the same sums per wet-layer count (the fused barotropic kernel looks
+    // depths up from the counts instead of reading hu, hv)
+    std::vector<double> cumh(nz + 1);
+    for (int K = 0; K <= nz; ++K) {
+        double a = 0.0;
+        for (int k = 0; k < nz; ++k)
+            if (k >= nz - K) a += g->dz[k];
+        cumh[K] = a;
+    }
+    HIPCHK(hipMemcpyAsync(d.cumh, cumh.data(), (nz + 1) * sizeof(double), hipMemcpyHostToDevice, s->st));
     std::vector<double> img;
     pack2(s, hu.data(), img);
     HIPCHK(hipMemcpyAsync(base2(s, d.hu), img.data(), img.size() * sizeof(double), hipMemcpyHostToDevice, s->st));
@@ -849,6 +860,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         d.dy = grid->dy;
         d.dz = reinterpret_cast<double*>(A + P.off_dz);
         d.dzc = reinterpret_cast<double*>(A + P.off_dzc);
+        d.cumh = reinterpret_cast<double*>(A + P.off_cumh);
         d.tref = reinterpret_cast<double*>(A + P.off_tref);
         d.dtr = A + P.off_dtr;
         d.thomas_tab = A + P.off_tab;

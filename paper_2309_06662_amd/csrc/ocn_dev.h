@@ -55,6 +55,8 @@ struct DevState {
     double *eta_mean, *ubt_mean, *vbt_mean;
     double *gU, *gV;                     // slow forcing: depth integral of the AB2 momentum tendency
     double *hu, *hv;                     // depth of u and v columns
+    double *cumh;                        // nz + 1: depth of a column of K wet layers, K = 0..nz
+                                         // (summed as hu, hv are: the same doubles)
     double *cu, *cv;                     // sum_k dz u m_u of the current u, v (vertical-transport seed)
     double *taux, *tauy;                 // wind stress
     double *tstar;                       // restoring target minus tref(top)
@@ -203,6 +205,15 @@ hipError_t launch_column_batched(const DevState* members, const int4* tiles, int
 int baro_substeps(int n_substeps);  // Ns + Ns/2
 hipError_t launch_barotropic_batched(const DevState* members, int n_members, const int4* tiles, int ntiles,
                                      int n_substeps, int fuse, double dt, hipStream_t st);
+// Hardware workgroups are dealt to the 8 XCDs round-robin; give XCD x the
+// contiguous range of tiles [x*q + min(x, r), ...) of a tile order, so that
+// neighbouring tiles share an L2 and read each other's halos from it.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb / 8, r = nb % 8;
+    const int x = b % 8, slot = b / 8;
+    return (x < r) ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
+}
+
 // Most levels a state may have (the column solve's register buckets and the
 // tendency kernel's per-level LDS table are sized for it).
 constexpr int kMaxLevels = 128;
