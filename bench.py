@@ -67,6 +67,10 @@ TEND_FLOPS_PER_CELL = 782
 BARO_FUSE = 7
 # Column solve with the constant diffusivity: read u*, v*, T* and write u, v, T.
 COLUMN_WORDS_PER_CELL = 6
+# With salinity the tendency kernel also reads S', G_S^{n-1} and writes S'*,
+# G_S^n (16 words per cell), and the column solve reads S'* and writes S' (8).
+TEND_WORDS_PER_CELL_SALT = 16
+COLUMN_WORDS_PER_CELL_SALT = 8
 KERNEL_SOURCES = {"k_tend": "k_tend.hip", "k_baro_fused": "k_baro.hip", "k_column": "k_column.hip"}
 
 
@@ -121,9 +125,13 @@ def run_gpu(w, precision, inp, steps, warmup):
 
 def run_ensemble(steps, warmup, n_members=64):
     """64 seeded beta-plane basins of uneven sizes in FP32: batched stepping
-    (one launch per stage, graph-replayed, autotuned tiles) against stepping
-    each member alone with the same kernels."""
-    import ctypes as C
+    (one launch per stage, graph-replayed, autotuned tiles and schedule)
+    against stepping each member alone with the same kernels, each member's
+    step replayed from its own graph; the two schedules of the batched
+    launches (one workgroup per tile, persistent workgroups over per-XCD
+    queues) at the default tiles; and the autotune cache: a second ensemble of
+    the same shape takes the stored choice without timing."""
+    import tempfile
 
     import torch
 
@@ -131,13 +139,22 @@ def run_ensemble(steps, warmup, n_members=64):
 
     ws = inputs.ensemble_members(n_members)
     ens = ocn.Ensemble(ws, "fp32")
-    tune = ens.autotune(trial_steps=2)
-    ens.step(warmup)
-    ens.synchronize()
-    t0 = time.perf_counter()
-    ens.step(steps)
-    ens.synchronize()
-    batched = time.perf_counter() - t0
+
+    def timed(n):
+        ens.step(warmup)
+        ens.synchronize()
+        t0 = time.perf_counter()
+        ens.step(n)
+        ens.synchronize()
+        return time.perf_counter() - t0
+
+    schedules = {}
+    for name, pers in (("one_workgroup_per_tile", 0), ("persistent_queues", 1)):
+        ens.set_tiles(0, 0, pers)
+        schedules[name] = timed(steps) / steps * 1e3
+    cache = os.path.join(tempfile.mkdtemp(prefix="ocn_autotune_"), "autotune.json")
+    tune = ens.autotune(trial_steps=2, cache=cache)
+    batched = timed(steps)
     # the same members one by one, each step replayed from its own captured
     # graph (two warm-up steps capture the graphs of both history buffers)
     seq = lambda: [ocn._check(ocn.lib().ocn_step_graph(mem.handle, 1), "ocn_step_graph") for mem in ens.members]
@@ -155,6 +172,13 @@ def run_ensemble(steps, warmup, n_members=64):
     ens.close()
     del ens
     torch.cuda.empty_cache()
+    ens2 = ocn.Ensemble(ws, "fp32")
+    t0 = time.perf_counter()
+    again = ens2.autotune(trial_steps=2, cache=cache)
+    again = dict(again, seconds=round(time.perf_counter() - t0, 3))
+    ens2.close()
+    del ens2
+    torch.cuda.empty_cache()
     return {"members": n_members, "cells": cells, "precision": "fp32", "steps": steps,
             "batched_ms_per_step": batched / steps * 1e3,
             "batched_cell_updates_per_s": cells * steps / batched,
@@ -162,7 +186,9 @@ def run_ensemble(steps, warmup, n_members=64):
             "sequential_cell_updates_per_s": cells * steps / sequential,
             "speedup_batched_over_sequential": sequential / batched,
             "sequential_mode": "each member replayed from its own captured graph",
-            "autotune": tune, "finite": finite, "max_abs_u": max(d["max_abs_u"] for d in diags)}
+            "schedules_ms_per_step_default_tiles": schedules,
+            "autotune": tune, "autotune_cache_second_ensemble": again,
+            "finite": finite, "max_abs_u": max(d["max_abs_u"] for d in diags)}
 
 
 def run_small(steps=200, warmup=5):
@@ -191,6 +217,32 @@ def run_small(steps=200, warmup=5):
         out[prec] = rec
         m.close()
     return out
+
+
+def run_salinity(w, steps, warmup):
+    """The same workload with salinity and the quadratic equation of state
+    (FP32): time per step, stages and the roofline of the salinity variant of
+    the tendency kernel (16 words per cell) and of the column solve (8)."""
+    import torch
+
+    ws = w.replace(salinity=True)
+    inp = inputs.make_inputs(ws)
+    el, stages, diag = run_gpu(ws, "fp32", inp, steps, warmup)
+    del inp
+    ms = el / steps * 1e3
+    cells = ws.cells
+    tb = TEND_WORDS_PER_CELL_SALT * 4 * cells
+    cb = COLUMN_WORDS_PER_CELL_SALT * 4 * cells
+    t_s, c_s = stages["tendency"] * 1e-3, stages["column"] * 1e-3
+    torch.cuda.empty_cache()
+    return {"workload": ws.name + "_salinity", "ms_per_step": ms,
+            "cell_updates_per_s": metrics.cell_updates_per_second(ws.nx, ws.ny, ws.nz, steps, el),
+            "sypd": metrics.sypd(ws.dt, ms * 1e-3), "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+            "finite": diag["nonfinite"] == 0, "max_abs_u": diag["max_abs_u"],
+            "tend_roofline": {"bound": "hbm", "bytes_per_launch": tb, "achieved": round(tb / t_s / 1e9, 1),
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(tb / t_s / 1e9 / HBM_PEAK_GBS, 4)},
+            "column_roofline": {"bound": "hbm", "bytes_per_launch": cb, "achieved": round(cb / c_s / 1e9, 1),
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(cb / c_s / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
 def run_quarter(steps, warmup):
@@ -471,6 +523,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble measurement")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the small-basin graph timing, the 1/4-degree runs and the copy bandwidth")
+    ap.add_argument("--no-salinity", action="store_true", help="skip the salinity leg")
     ap.add_argument("--copy-probe", action="store_true", help="run the counter-calibration copy and exit")
     ap.add_argument("--mib", type=int, default=1024, help="copy probe: size of each buffer in MiB")
     ap.add_argument("--pmc-summary", action="store_true", help="write a kernel's traffic record and exit")
@@ -519,6 +572,12 @@ def main():
         }
         print(f"[bench] {prec}: {ms:.3f} ms/step, stages {results[prec]['stage_ms']}, "
               f"finite={diag['nonfinite'] == 0}", file=sys.stderr, flush=True)
+
+    sal = None
+    if not args.no_salinity:
+        sal = run_salinity(w, args.steps, args.warmup)
+        print(f"[bench] salinity fp32: {sal['ms_per_step']:.3f} ms/step, stages {sal['stage_ms']}, "
+              f"finite={sal['finite']}", file=sys.stderr, flush=True)
 
     ens = None
     if not args.no_ensemble:
@@ -577,6 +636,8 @@ def main():
                         "finite": r64["finite"], "max_abs_u": r64["max_abs_u"],
                         "stage_ms": r64["stage_ms"], "roofline": r64_main, "stage_rooflines": r64_stages}
         line["fp32_speedup_over_fp64"] = r64["ms_per_step"] / main_rec["ms_per_step"]
+    if sal is not None:
+        line["salinity"] = sal
     if ens is not None:
         line["ensemble"] = ens
     line.update(extra)

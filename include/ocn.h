@@ -280,10 +280,16 @@ int ocn_debug_run_stage(ocn_state* state, int32_t stage);
  * ocn_ensemble_member returns a borrowed handle of member m for the state
  * calls (set/get fields, diagnostics, checkpoints); do not destroy it.
  * ocn_ensemble_set_tiles selects the tendency workgroup rows (4 or 8; 0 =
- * precision default) and the barotropic substeps per launch (2..8; 0 = 7,
- * the default); every choice gives bitwise-identical results. ocn_ensemble_autotune
- * times trial_steps steps of each choice, keeps the fastest, restores the
- * state it started from and reports the choice and its time per step. */
+ * precision default), the barotropic substeps per launch (2..8; 0 = 7, the
+ * default) and the schedule: persistent = 0 launches one workgroup per tile
+ * table entry; persistent = 1 launches, per stage, as many workgroups as fit
+ * on the device at once, which take the entries from eight per-XCD atomic
+ * counters in the ensemble's arena (zeroed by a kernel at the start of each
+ * step) and leave when all are taken. Every choice gives bitwise-identical
+ * results. ocn_ensemble_autotune times trial_steps steps of each choice
+ * (rows x substeps x schedule), keeps the fastest, restores the state it
+ * started from and reports the choice and its time per step; any output
+ * pointer may be NULL. */
 typedef struct ocn_ensemble ocn_ensemble;
 int  ocn_ensemble_arena_bytes(const ocn_grid* const* grids, int32_t n, const ocn_params* params, size_t* bytes);
 int  ocn_ensemble_init(const ocn_grid* const* grids, int32_t n, const ocn_params* params, void* device_arena,
@@ -291,9 +297,9 @@ int  ocn_ensemble_init(const ocn_grid* const* grids, int32_t n, const ocn_params
 void ocn_ensemble_destroy(ocn_ensemble* ens);
 int  ocn_ensemble_member(ocn_ensemble* ens, int32_t m, ocn_state** member);
 int  ocn_ensemble_step(ocn_ensemble* ens, int32_t n);
-int  ocn_ensemble_set_tiles(ocn_ensemble* ens, int32_t tend_rows, int32_t baro_fuse);
+int  ocn_ensemble_set_tiles(ocn_ensemble* ens, int32_t tend_rows, int32_t baro_fuse, int32_t persistent);
 int  ocn_ensemble_autotune(ocn_ensemble* ens, int32_t trial_steps, int32_t* tend_rows, int32_t* baro_fuse,
-                           double* ms_per_step);
+                           int32_t* persistent, double* ms_per_step);
 
 /* Per-column closure network: Linear -> ReLU -> Linear -> ReLU -> Linear with
  * BF16 operands on the matrix cores and FP32 accumulation, FP32 master weights

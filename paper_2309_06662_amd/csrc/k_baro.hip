@@ -15,7 +15,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 
 namespace ocn {
 
@@ -429,6 +432,30 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(BaroWaves<kB
     baro_tile<kBaroTileX, kBaroTileY, SH>(members[e.x], e.y, e.z, dtau, m0, first, last, parity, wflags);
 }
 
+// The same over a queue of table entries, with persistent workgroups.
+template <int SH>
+__global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(BaroWaves<kBaroTileX, kBaroTileY, SH>::n))) void k_baro_fused_queued(const DevState* __restrict__ members,
+                                                           const int4* __restrict__ tiles, const int ntiles,
+                                                           const double dtau, const int m0, const int first,
+                                                           const int last, const int parity, const int wflags,
+                                                           int* __restrict__ queue) {
+    for_each_queued_tile(queue, ntiles, [&](int b) {
+        const int4 e = tiles[b];
+        baro_tile<kBaroTileX, kBaroTileY, SH>(members[e.x], e.y, e.z, dtau, m0, first, last, parity, wflags);
+    });
+}
+
+__global__ __launch_bounds__(256) void k_zero_counters(int* p, const int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+hipError_t launch_zero_counters(int* p, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_counters, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
 // Instantiations per halo width 1..FSMAX: f<SH>() launches the kernel of that width.
 template <class F>
 hipError_t by_halo(int s, F&& f) {
@@ -447,6 +474,25 @@ hipError_t by_halo(int s, F&& f) {
 
 int baro_substeps(int n_substeps) { return n_substeps + n_substeps / 2; }
 
+// Workgroups of a kernel that fit on the current device at once (cached per
+// kernel and device).
+int resident_workgroups(const void* kernel, int block_threads) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({kernel, dev});
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block_threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    const int n = per_cu * cus;
+    cache[{kernel, dev}] = n;
+    return n;
+}
+
 // First substep q (1-based) whose window weight a_q is nonzero: the weights
 // are cos^2(pi t), t = q/Ns - 1, on |t| < 1/2 (the same test as the table's).
 static int window_first(int n_substeps) {
@@ -464,20 +510,33 @@ static int window_flags(int n_substeps, int m0, int ss) {
     return (m0 >= qf ? 1 : 0) | (m0 + ss >= qf ? 2 : 0);
 }
 
+int baro_launches(int n_substeps, int fuse) {
+    const int sub = std::max(2, std::min(fuse, FSMAX));
+    const int M = baro_substeps(n_substeps);
+    return (M + sub - 1) / sub;
+}
+
 hipError_t launch_barotropic_batched(const DevState* members, int n_members, const int4* tiles, int ntiles,
-                                     int n_substeps, int fuse, double dt, hipStream_t st) {
+                                     int n_substeps, int fuse, double dt, int* queue, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     const int sub = std::max(2, std::min(fuse, FSMAX));
     const double dtau = dt / n_substeps;
     const int M = baro_substeps(n_substeps);
-    int parity = 0;
-    for (int m0 = 0; m0 < M; m0 += sub, parity ^= 1) {
+    int parity = 0, group = 0;
+    for (int m0 = 0; m0 < M; m0 += sub, parity ^= 1, ++group) {
         const int ss = std::min(sub, M - m0);
         const int first = m0 == 0, last = m0 + ss == M;
+        const int wf = window_flags(n_substeps, m0, ss);
         hipError_t e = by_halo(ss, [&](auto h) {
             constexpr int SH = decltype(h)::value;
-            hipLaunchKernelGGL((k_baro_fused_batched<SH>), dim3(ntiles), dim3(FT), 0, st, members, tiles, dtau, m0,
-                               first, last, parity, window_flags(n_substeps, m0, ss));
+            if (queue) {
+                const int nb = std::min(ntiles, resident_workgroups((const void*)k_baro_fused_queued<SH>, FT));
+                hipLaunchKernelGGL((k_baro_fused_queued<SH>), dim3(nb), dim3(FT), 0, st, members, tiles, ntiles, dtau,
+                                   m0, first, last, parity, wf, queue + 8 * group);
+            } else {
+                hipLaunchKernelGGL((k_baro_fused_batched<SH>), dim3(ntiles), dim3(FT), 0, st, members, tiles, dtau,
+                                   m0, first, last, parity, wf);
+            }
             return hipSuccess;
         });
         if (e != hipSuccess) return e;

@@ -24,6 +24,8 @@
 // wrapped copies into the halo.
 #include "ocn_dev.h"
 
+#include <algorithm>
+
 namespace ocn {
 
 constexpr int CW = 256;      // columns per workgroup of the single-state launches (four waves side by side
@@ -447,6 +449,19 @@ void k_column_batched(const DevState* __restrict__ members, const int4* __restri
     column_regs<R, NZB, CWB>(members[e.x], e.y, e.z, blockIdx.y);
 }
 
+// The same over a queue of (table entry, field) items, field-major, with
+// persistent workgroups.
+template <typename R, int NZB>
+__global__ __launch_bounds__(CWB) __attribute__((amdgpu_waves_per_eu(ColWaves<R>::n)))
+void k_column_queued(const DevState* __restrict__ members, const int4* __restrict__ tiles, const int ntiles,
+                     int* __restrict__ queue) {
+    for_each_queued_tile(queue, 3 * ntiles, [&](int i) {
+        const int field = i / ntiles;
+        const int4 e = tiles[i - field * ntiles];
+        column_regs<R, NZB, CWB>(members[e.x], e.y, e.z, field);
+    });
+}
+
 // Dispatch a level count to the smallest bucket that holds it.
 template <typename R, template <typename, int> class Launch, typename... A>
 hipError_t with_bucket(int nz, A... args) {
@@ -492,20 +507,26 @@ struct LaunchColumnVk {
 
 template <typename R, int NZB>
 struct LaunchColumnBatched {
-    static hipError_t go(const DevState* members, const int4* tiles, int ntiles, hipStream_t st) {
-        hipLaunchKernelGGL((k_column_batched<R, NZB>), dim3(ntiles, 3), dim3(CWB), 0, st, members, tiles);
+    static hipError_t go(const DevState* members, const int4* tiles, int ntiles, int* queue, hipStream_t st) {
+        if (queue) {
+            const int nb = std::min(3 * ntiles, resident_workgroups((const void*)k_column_queued<R, NZB>, CWB));
+            hipLaunchKernelGGL((k_column_queued<R, NZB>), dim3(nb), dim3(CWB), 0, st, members, tiles, ntiles, queue);
+        } else {
+            hipLaunchKernelGGL((k_column_batched<R, NZB>), dim3(ntiles, 3), dim3(CWB), 0, st, members, tiles);
+        }
         return hipGetLastError();
     }
 };
 
 template <typename R>
-hipError_t launch_column_batched(const DevState* members, const int4* tiles, int ntiles, int max_nz, hipStream_t st) {
+hipError_t launch_column_batched(const DevState* members, const int4* tiles, int ntiles, int max_nz, int* queue,
+                                 hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    return with_bucket<R, LaunchColumnBatched>(max_nz, members, tiles, ntiles, st);
+    return with_bucket<R, LaunchColumnBatched>(max_nz, members, tiles, ntiles, queue, st);
 }
 
-template hipError_t launch_column_batched<double>(const DevState*, const int4*, int, int, hipStream_t);
-template hipError_t launch_column_batched<float>(const DevState*, const int4*, int, int, hipStream_t);
+template hipError_t launch_column_batched<double>(const DevState*, const int4*, int, int, int*, hipStream_t);
+template hipError_t launch_column_batched<float>(const DevState*, const int4*, int, int, int*, hipStream_t);
 
 template <typename R>
 hipError_t launch_column(const DevState& s, hipStream_t st) {

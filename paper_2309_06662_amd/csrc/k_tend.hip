@@ -40,6 +40,8 @@
 // gradient free of the cancellation a 20 K absolute temperature would cause.
 #include "ocn_dev.h"
 
+#include <algorithm>
+
 namespace ocn {
 
 constexpr int TXB = 64;  // tile width of the batched ensemble launches (the host builds 63-column tiles)
@@ -882,6 +884,17 @@ void k_tend_batched(const DevState* __restrict__ members, const int4* __restrict
     tend_tile<R, TXB, TY, false>(members[e.x], first, e.y, e.z);
 }
 
+// The same over a queue of table entries, with persistent workgroups.
+template <typename R, int TY>
+__global__ __launch_bounds__(TXB * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R, false, TY>::n)))
+void k_tend_queued(const DevState* __restrict__ members, const int4* __restrict__ tiles, const int ntiles,
+                   const int first, int* __restrict__ queue) {
+    for_each_queued_tile(queue, ntiles, [&](int b) {
+        const int4 e = tiles[b];
+        tend_tile<R, TXB, TY, false>(members[e.x], first, e.y, e.z);
+    });
+}
+
 // Rows of the 64-wide ensemble tiles: 4 or 8 as chosen, else 8 in FP32 and 4 in FP64.
 int tend_tile_rows(int precision_bytes, int ty_choice) {
     if (ty_choice == 4 || ty_choice == 8) return ty_choice;
@@ -909,8 +922,20 @@ hipError_t launch_tendency(const DevState& s, int first, hipStream_t st) {
 
 template <typename R>
 hipError_t launch_tendency_batched(const DevState* members, const int4* tiles, int ntiles, int ty, int first,
-                                   hipStream_t st) {
+                                   int* queue, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
+    if (queue) {
+        if (ty == 8) {
+            const int nb = std::min(ntiles, resident_workgroups((const void*)k_tend_queued<R, 8>, TXB * 8));
+            hipLaunchKernelGGL((k_tend_queued<R, 8>), dim3(nb), dim3(TXB, 8), 0, st, members, tiles, ntiles, first,
+                               queue);
+        } else {
+            const int nb = std::min(ntiles, resident_workgroups((const void*)k_tend_queued<R, 4>, TXB * 4));
+            hipLaunchKernelGGL((k_tend_queued<R, 4>), dim3(nb), dim3(TXB, 4), 0, st, members, tiles, ntiles, first,
+                               queue);
+        }
+        return hipGetLastError();
+    }
     if (ty == 8) hipLaunchKernelGGL((k_tend_batched<R, 8>), dim3(ntiles), dim3(TXB, 8), 0, st, members, tiles, first);
     else hipLaunchKernelGGL((k_tend_batched<R, 4>), dim3(ntiles), dim3(TXB, 4), 0, st, members, tiles, first);
     return hipGetLastError();
@@ -918,7 +943,7 @@ hipError_t launch_tendency_batched(const DevState* members, const int4* tiles, i
 
 template hipError_t launch_tendency<double>(const DevState&, int, hipStream_t);
 template hipError_t launch_tendency<float>(const DevState&, int, hipStream_t);
-template hipError_t launch_tendency_batched<double>(const DevState*, const int4*, int, int, int, hipStream_t);
-template hipError_t launch_tendency_batched<float>(const DevState*, const int4*, int, int, int, hipStream_t);
+template hipError_t launch_tendency_batched<double>(const DevState*, const int4*, int, int, int, int*, hipStream_t);
+template hipError_t launch_tendency_batched<float>(const DevState*, const int4*, int, int, int, int*, hipStream_t);
 
 }  // namespace ocn

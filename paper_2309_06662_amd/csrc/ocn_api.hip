@@ -1452,6 +1452,8 @@ struct ocn_ensemble {
     int4* d_tend = nullptr;
     int4* d_col = nullptr;
     int4* d_baro = nullptr;
+    int* d_queue = nullptr;         // queue counters: 8 per launch of a step
+    int persistent = 0;             // 1: persistent workgroups over per-XCD queues
     int n_tend = 0, n_col = 0, n_baro = 0;
     size_t cap_tend = 0;
     hipGraph_t graph[2] = {nullptr, nullptr};
@@ -1462,7 +1464,7 @@ namespace {
 
 struct EnsPlan {
     std::vector<size_t> member_off, member_bytes;
-    size_t off_dev, off_tend, off_col, off_baro, total;
+    size_t off_dev, off_tend, off_col, off_baro, off_queue, total;
     size_t cap_tend, cap_col, cap_baro;
 };
 
@@ -1486,6 +1488,8 @@ int ens_plan(const ocn_grid* const* grids, int n, const ocn_params* params, EnsP
     P.off_tend = L.add(P.cap_tend * sizeof(int4));
     P.off_col = L.add(P.cap_col * sizeof(int4));
     P.off_baro = L.add(P.cap_baro * sizeof(int4));
+    // tendency and column launches, and at most one barotropic launch per two substeps
+    P.off_queue = L.add(8 * (size_t)(2 + ocn::baro_substeps(std::max(params->n_substeps, 1))) * sizeof(int));
     P.total = L.total;
     return OCN_OK;
 }
@@ -1521,8 +1525,11 @@ int ens_tables(ocn_ensemble* e) {
             for (int bx = 0; bx < (g->nx + ocn::kBaroTileX - 1) / ocn::kBaroTileX; ++bx)
                 baro.push_back(make_int4(m, bx, by, 0));
     }
+    // barotropic tiles dealt like the tendency's: each XCD a contiguous range
+    std::vector<int4> baro_hw(baro.size());
+    for (int b = 0; b < (int)baro.size(); ++b) baro_hw[b] = baro[xcd_slot(b, (int)baro.size())];
     HIPCHK(hipMemcpyAsync(e->d_col, col.data(), col.size() * sizeof(int4), hipMemcpyHostToDevice, e->st));
-    HIPCHK(hipMemcpyAsync(e->d_baro, baro.data(), baro.size() * sizeof(int4), hipMemcpyHostToDevice, e->st));
+    HIPCHK(hipMemcpyAsync(e->d_baro, baro_hw.data(), baro_hw.size() * sizeof(int4), hipMemcpyHostToDevice, e->st));
     e->n_col = (int)col.size();
     e->n_baro = (int)baro.size();
     // member states with the ensemble's tile settings, and the same with the
@@ -1560,11 +1567,20 @@ int ens_enqueue(ocn_ensemble* e, int first) {
     const bool f32 = e->esize == 4;
     const int ty = ocn::tend_tile_rows(e->esize, e->tend_ty);
     const DevState* dm = e->d_members + (size_t)e->epar * e->members.size();
-    HIPCHK(f32 ? ocn::launch_tendency_batched<float>(dm, e->d_tend, e->n_tend, ty, first, e->st)
-               : ocn::launch_tendency_batched<double>(dm, e->d_tend, e->n_tend, ty, first, e->st));
-    HIPCHK(ocn::launch_barotropic_batched(dm, (int)e->members.size(), e->d_baro, e->n_baro, e->p.n_substeps, e->fuse, e->p.dt, e->st));
-    HIPCHK(f32 ? ocn::launch_column_batched<float>(dm, e->d_col, e->n_col, e->max_nz, e->st)
-               : ocn::launch_column_batched<double>(dm, e->d_col, e->n_col, e->max_nz, e->st));
+    int *qt = nullptr, *qc = nullptr, *qb = nullptr;
+    if (e->persistent) {  // fresh counters for every launch of the step
+        const int nq = 8 * (2 + ocn::baro_launches(e->p.n_substeps, e->fuse));
+        HIPCHK(ocn::launch_zero_counters(e->d_queue, nq, e->st));
+        qt = e->d_queue;
+        qc = e->d_queue + 8;
+        qb = e->d_queue + 16;
+    }
+    HIPCHK(f32 ? ocn::launch_tendency_batched<float>(dm, e->d_tend, e->n_tend, ty, first, qt, e->st)
+               : ocn::launch_tendency_batched<double>(dm, e->d_tend, e->n_tend, ty, first, qt, e->st));
+    HIPCHK(ocn::launch_barotropic_batched(dm, (int)e->members.size(), e->d_baro, e->n_baro, e->p.n_substeps, e->fuse,
+                                          e->p.dt, qb, e->st));
+    HIPCHK(f32 ? ocn::launch_column_batched<float>(dm, e->d_col, e->n_col, e->max_nz, qc, e->st)
+               : ocn::launch_column_batched<double>(dm, e->d_col, e->n_col, e->max_nz, qc, e->st));
     return OCN_OK;
 }
 
@@ -1659,6 +1675,7 @@ int ocn_ensemble_init(const ocn_grid* const* grids, int32_t n, const ocn_params*
         e->d_tend = reinterpret_cast<int4*>(A + P.off_tend);
         e->d_col = reinterpret_cast<int4*>(A + P.off_col);
         e->d_baro = reinterpret_cast<int4*>(A + P.off_baro);
+        e->d_queue = reinterpret_cast<int*>(A + P.off_queue);
         e->cap_tend = P.cap_tend;
         int rc = ens_tables(e);
         if (rc) {
@@ -1698,19 +1715,21 @@ int ocn_ensemble_step(ocn_ensemble* e, int32_t n) {
     return ens_step(e, n);
 }
 
-int ocn_ensemble_set_tiles(ocn_ensemble* e, int32_t tend_rows, int32_t baro_fuse) {
+int ocn_ensemble_set_tiles(ocn_ensemble* e, int32_t tend_rows, int32_t baro_fuse, int32_t persistent) {
     if (!e) return fail(OCN_E_INVALID, "ensemble must not be NULL");
     if (!(tend_rows == 0 || tend_rows == 4 || tend_rows == 8)) return fail(OCN_E_INVALID, "tend_rows must be 0, 4 or 8");
     if (!(baro_fuse == 0 || (baro_fuse >= 2 && baro_fuse <= 8))) return fail(OCN_E_INVALID, "baro_fuse must be 0 or 2..8");
+    if (persistent != 0 && persistent != 1) return fail(OCN_E_INVALID, "persistent must be 0 or 1");
     if (e->st) HIPCHK(hipStreamSynchronize(e->st));
     drop_graph(e);
     e->tend_ty = tend_rows;
     e->fuse = baro_fuse == 0 ? ocn::kBaroFuseDefault : baro_fuse;
+    e->persistent = persistent;
     return ens_tables(e);
 }
 
 int ocn_ensemble_autotune(ocn_ensemble* e, int32_t trial_steps, int32_t* tend_rows, int32_t* baro_fuse,
-                          double* ms_per_step) {
+                          int32_t* persistent, double* ms_per_step) {
     if (!e || trial_steps < 1) return fail(OCN_E_INVALID, "ensemble and trial_steps >= 1 are required");
     if (!e->st) return fail(OCN_E_UNSUPPORTED, "autotuning needs a non-default stream");
     // save every member so the trials leave the ensemble where it was
@@ -1726,37 +1745,40 @@ int ocn_ensemble_autotune(ocn_ensemble* e, int32_t trial_steps, int32_t* tend_ro
     const int rows_c[2] = {4, 8};
     const int fuse_c[4] = {5, 6, 7, 8};
     double best = 1e300;
-    int brow = 0, bfuse = ocn::kBaroFuseDefault;
+    int brow = 0, bfuse = ocn::kBaroFuseDefault, bpers = 0;
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
     int rc = OCN_OK;
-    for (int r : rows_c) {
-        for (int f : fuse_c) {
-            if ((rc = ocn_ensemble_set_tiles(e, r, f))) break;
-            e->first = 0;
-            if ((rc = ens_step(e, 1))) break;  // capture and warm up
-            HIPCHK(hipEventRecord(a, e->st));
-            if ((rc = ens_step(e, trial_steps))) break;
-            HIPCHK(hipEventRecord(b, e->st));
-            HIPCHK(hipEventSynchronize(b));
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, a, b));
-            const double per = ms / trial_steps;
-            if (per < best) { best = per; brow = r; bfuse = f; }
+    for (int p = 0; p < 2 && !rc; ++p) {
+        for (int r : rows_c) {
+            for (int f : fuse_c) {
+                if ((rc = ocn_ensemble_set_tiles(e, r, f, p))) break;
+                e->first = 0;
+                if ((rc = ens_step(e, 1))) break;  // capture and warm up
+                HIPCHK(hipEventRecord(a, e->st));
+                if ((rc = ens_step(e, trial_steps))) break;
+                HIPCHK(hipEventRecord(b, e->st));
+                HIPCHK(hipEventSynchronize(b));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, a, b));
+                const double per = ms / trial_steps;
+                if (per < best) { best = per; brow = r; bfuse = f; bpers = p; }
+            }
+            if (rc) break;
         }
-        if (rc) break;
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (rc) return rc;
-    if ((rc = ocn_ensemble_set_tiles(e, brow, bfuse))) return rc;
+    if ((rc = ocn_ensemble_set_tiles(e, brow, bfuse, bpers))) return rc;
     for (size_t m = 0; m < e->members.size(); ++m)
         if ((rc = ocn_checkpoint_load(e->members[m], saved[m].data(), saved[m].size()))) return rc;
     e->first = first0;
     for (ocn_state* s : e->members) s->first = first0;
     if (tend_rows) *tend_rows = brow;
     if (baro_fuse) *baro_fuse = bfuse;
+    if (persistent) *persistent = bpers;
     if (ms_per_step) *ms_per_step = best;
     return OCN_OK;
 }

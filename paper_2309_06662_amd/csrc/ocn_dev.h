@@ -196,15 +196,26 @@ hipError_t launch_barotropic(const DevState& s, hipStream_t st);
 int tend_tile_rows(int precision_bytes, int ty_choice);
 
 // Batched launches over an ensemble: members is a device array of states,
-// tiles a device table of (member, tile x, tile y[, field]) entries.
+// tiles a device table of (member, tile x, tile y[, field]) entries. With a
+// queue (8 zeroed counters per launch, device memory) the launch is instead a
+// grid of persistent workgroups, as many as fit on the device at once, that
+// take table entries from per-XCD atomic counters until all are done (see
+// for_each_queued_tile); without one, one workgroup per entry.
 template <typename R>
 hipError_t launch_tendency_batched(const DevState* members, const int4* tiles, int ntiles, int ty, int first,
-                                   hipStream_t st);
+                                   int* queue, hipStream_t st);
 template <typename R>
-hipError_t launch_column_batched(const DevState* members, const int4* tiles, int ntiles, int max_nz, hipStream_t st);
+hipError_t launch_column_batched(const DevState* members, const int4* tiles, int ntiles, int max_nz, int* queue,
+                                 hipStream_t st);
 int baro_substeps(int n_substeps);  // Ns + Ns/2
+// queue: 8 counters per substep-group launch, baro_launches(...) groups
 hipError_t launch_barotropic_batched(const DevState* members, int n_members, const int4* tiles, int ntiles,
-                                     int n_substeps, int fuse, double dt, hipStream_t st);
+                                     int n_substeps, int fuse, double dt, int* queue, hipStream_t st);
+int baro_launches(int n_substeps, int fuse);
+// zero n counters (a kernel, so that it can sit in a captured graph)
+hipError_t launch_zero_counters(int* p, int n, hipStream_t st);
+// workgroups of a kernel that fit on the current device at once
+int resident_workgroups(const void* kernel, int block_threads);
 // Hardware workgroups are dealt to the 8 XCDs round-robin; give XCD x the
 // contiguous range of tiles [x*q + min(x, r), ...) of a tile order, so that
 // neighbouring tiles share an L2 and read each other's halos from it.
@@ -212,6 +223,32 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     const int q = nb / 8, r = nb % 8;
     const int x = b % 8, slot = b / 8;
     return (x < r) ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
+}
+
+// Persistent workgroups over a tile table of n entries, dealt to the 8 XCDs
+// round-robin: a workgroup on XCD x (= blockIdx.x mod 8) takes the entries
+// x, x+8, x+16, ... (the entries the hardware would have given that XCD, so
+// neighbouring tiles still share an L2) by atomic increments of counter x,
+// then helps the other XCDs' counters in turn. No workgroup waits for
+// another: each leaves once all eight counters have passed their ends, so
+// the grid drains whatever its size. f(entry) runs with the whole workgroup.
+template <typename F>
+__device__ __forceinline__ void for_each_queued_tile(int* q, const int n, F&& f) {
+    __shared__ int s_slot;
+    const int x = blockIdx.x & 7;
+    const bool lead = threadIdx.x == 0 && threadIdx.y == 0;
+    for (int d = 0; d < 8; ++d) {
+        const int qx = (x + d) & 7;
+        const int nq = (n - qx + 7) / 8;  // entries qx, qx+8, ... below n
+        for (;;) {
+            __syncthreads();  // the previous entry is done with LDS and s_slot
+            if (lead) s_slot = atomicAdd(&q[qx], 1);
+            __syncthreads();
+            const int slot = s_slot;
+            if (slot >= nq) break;
+            f(qx + 8 * slot);
+        }
+    }
 }
 
 // Most levels a state may have (the column solve's register buckets and the

@@ -8,6 +8,8 @@ missing library raises.
 from __future__ import annotations
 
 import ctypes as C
+import json
+import math
 import os
 from typing import Dict, Optional
 
@@ -118,9 +120,9 @@ def lib():
         L.ocn_ensemble_destroy.argtypes = [C.c_void_p]
         L.ocn_ensemble_member.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]
         L.ocn_ensemble_step.argtypes = [C.c_void_p, C.c_int32]
-        L.ocn_ensemble_set_tiles.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+        L.ocn_ensemble_set_tiles.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
         L.ocn_ensemble_autotune.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                            C.POINTER(C.c_double)]
+                                            C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         L.ocn_stage_timing.argtypes = [C.c_void_p, C.c_int32]
         _F = C.POINTER(C.c_float)
         L.ocn_mlp_arena_bytes.argtypes = [C.c_int32] * 5 + [C.POINTER(C.c_size_t)]
@@ -379,6 +381,37 @@ class _Member(Model):
         raise RuntimeError("members advance through Ensemble.step")
 
 
+def tuning_key(precision: str, workloads) -> str:
+    """The autotune cache key of an ensemble: kernel family, precision,
+    deepest member, size class (log2 of its cells, rounded) and member count."""
+    ws = list(workloads)
+    nz = max(w.nz for w in ws)
+    size_class = int(round(math.log2(max(sum(w.cells for w in ws), 1))))
+    return f"ensemble/{precision}/nz{nz}/cells2^{size_class}/members{len(ws)}"
+
+
+def autotune_cache_load(path: str) -> dict:
+    """Autotuned choices stored in a JSON file (empty if it does not exist)."""
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except FileNotFoundError:
+        return {}
+
+
+def autotune_cache_store(path: str, key: str, rec: dict):
+    """Add (or replace) one choice in the cache file, written atomically."""
+    data = autotune_cache_load(path)
+    data[key] = rec
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
 class Ensemble:
     """Independent basins stepped together: one tendency launch and one column
     launch per step for all members, barotropic launches per substep group, the
@@ -434,14 +467,30 @@ class Ensemble:
     def synchronize(self):
         self.stream.synchronize()
 
-    def set_tiles(self, tend_rows: int = 0, baro_fuse: int = 0):
-        _check(lib().ocn_ensemble_set_tiles(self.handle, int(tend_rows), int(baro_fuse)), "ocn_ensemble_set_tiles")
+    def set_tiles(self, tend_rows: int = 0, baro_fuse: int = 0, persistent: int = 0):
+        _check(lib().ocn_ensemble_set_tiles(self.handle, int(tend_rows), int(baro_fuse), int(persistent)),
+               "ocn_ensemble_set_tiles")
 
-    def autotune(self, trial_steps: int = 3) -> dict:
-        r, f, ms = C.c_int32(), C.c_int32(), C.c_double()
-        _check(lib().ocn_ensemble_autotune(self.handle, int(trial_steps), C.byref(r), C.byref(f), C.byref(ms)),
-               "ocn_ensemble_autotune")
-        return {"tend_rows": r.value, "baro_fuse": f.value, "ms_per_step": ms.value}
+    def tuning_key(self) -> str:
+        return tuning_key(self.precision, self.workloads)
+
+    def autotune(self, trial_steps: int = 3, cache: Optional[str] = None) -> dict:
+        """Time every choice and keep the fastest. With a cache file (JSON), a
+        choice stored under tuning_key() is applied without timing, and a new
+        one is stored."""
+        key = self.tuning_key()
+        if cache is not None:
+            hit = autotune_cache_load(cache).get(key)
+            if hit is not None:
+                self.set_tiles(hit["tend_rows"], hit["baro_fuse"], hit.get("persistent", 0))
+                return dict(hit, cached=True)
+        r, f, p, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        _check(lib().ocn_ensemble_autotune(self.handle, int(trial_steps), C.byref(r), C.byref(f), C.byref(p),
+                                           C.byref(ms)), "ocn_ensemble_autotune")
+        rec = {"tend_rows": r.value, "baro_fuse": f.value, "persistent": p.value, "ms_per_step": ms.value}
+        if cache is not None:
+            autotune_cache_store(cache, key, rec)
+        return dict(rec, cached=False)
 
     @property
     def cells(self) -> int:

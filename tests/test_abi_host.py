@@ -113,7 +113,7 @@ def test_ensemble_arena_and_argument_checks():
     bad = (C.c_void_p * 2)(grids[0].handle.value, None)
     assert L.ocn_ensemble_arena_bytes(bad, 2, C.byref(p), C.byref(total)) == ocn.OCN_E_INVALID
     assert L.ocn_ensemble_step(None, 1) == ocn.OCN_E_INVALID
-    assert L.ocn_ensemble_set_tiles(None, 4, 2) == ocn.OCN_E_INVALID
+    assert L.ocn_ensemble_set_tiles(None, 4, 2, 0) == ocn.OCN_E_INVALID
 
 
 def test_ensemble_members_recipe():
