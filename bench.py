@@ -421,16 +421,15 @@ def _oracle_window_rate(args):
     return win.cells * steps, el, steps
 
 
-def cpu_baseline(w):
-    """The oracle as it stands (plain FP64 C, gcc -O2 -ffp-contract=off) on
-    bounded windows of the same 1/12-degree workload: one 240 x 120 column
-    window (all 100 levels) stepped for about 10 s on one thread, then one such
-    window per host core (at most 16, the host share of one GPU), each on its
-    own thread (the oracle is serial; ctypes releases the interpreter lock), for
-    about 10 s. The full grid is not run on the CPU."""
+def oracle_rates(w, seconds=10.0):
+    """The oracle's rate on bounded windows of a workload: one 240 x 120
+    column window (all levels) stepped for about `seconds` on one thread, then
+    one such window per host core (at most 16, the host share of one GPU),
+    each on its own thread (the oracle is serial; ctypes releases the
+    interpreter lock)."""
     import concurrent.futures as cf
 
-    cu1, el1, st1 = _oracle_window_rate((w, 150.0, 10.0))
+    cu1, el1, st1 = _oracle_window_rate((w, 150.0, seconds))
     try:
         ncpu = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -438,16 +437,41 @@ def cpu_baseline(w):
     cores = max(1, min(16, ncpu))
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=cores) as ex:
-        res = list(ex.map(_oracle_window_rate, [(w, 10.0 + 20.0 * q, 10.0) for q in range(cores)]))
+        res = list(ex.map(_oracle_window_rate, [(w, 10.0 + 20.0 * q, seconds) for q in range(cores)]))
     wall = time.perf_counter() - t0
-    rate_all = sum(r[0] for r in res) / wall
-    return {"value": cu1 / el1, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"240x120x100 window of the 1/12-degree basin (150-170E, 10S-0), {st1} steps in {el1:.1f} s, "
-                      f"FP64, one thread, gcc -O2 -ffp-contract=off",
-            "all_cores": {"value": rate_all, "unit": "cell-updates/s", "cores": cores,
-                          "sample": f"{cores} windows of 240x120x100 (10S-0, 20 degrees apart), one per thread, "
-                                    f"{min(r[2] for r in res)}-{max(r[2] for r in res)} steps each in {wall:.1f} s"},
-            "cpu_model": _cpu_model(), "host_cpus": ncpu}
+    return {"one": cu1 / el1, "one_steps": st1, "one_s": el1, "all": sum(r[0] for r in res) / wall,
+            "cores": cores, "all_steps": (min(r[2] for r in res), max(r[2] for r in res)), "all_s": wall,
+            "host_cpus": ncpu}
+
+
+def cpu_baseline(w):
+    """The oracle as it stands (plain FP64 C, gcc -O2 -ffp-contract=off, the
+    build the tests use) on bounded windows of the same 1/12-degree workload,
+    one thread and all host cores (oracle_rates); beside it the same sources
+    built -O3 -march=x86-64-v3 (no contraction: the same arithmetic), timed in
+    a child process. The full grid is not run on the CPU."""
+    import subprocess
+
+    r = oracle_rates(w)
+    o3 = None
+    try:
+        env = dict(os.environ, OCN_ORACLE_BUILD="o3")
+        out = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-rates", "--workload", w.name],
+                             env=env, capture_output=True, text=True, timeout=300, check=True)
+        o3 = json.loads(out.stdout.strip().splitlines()[-1])
+    except Exception as exc:  # the -O3 figure is context only
+        print(f"[bench] -O3 oracle timing skipped: {exc}", file=sys.stderr, flush=True)
+    rec = {"value": r["one"], "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+           "sample": f"240x120x100 window of the 1/12-degree basin (150-170E, 10S-0), {r['one_steps']} steps in "
+                     f"{r['one_s']:.1f} s, FP64, one thread, gcc -O2 -ffp-contract=off",
+           "all_cores": {"value": r["all"], "unit": "cell-updates/s", "cores": r["cores"],
+                         "sample": f"{r['cores']} windows of 240x120x100 (10S-0, 20 degrees apart), one per thread, "
+                                   f"{r['all_steps'][0]}-{r['all_steps'][1]} steps each in {r['all_s']:.1f} s"},
+           "cpu_model": _cpu_model(), "host_cpus": r["host_cpus"]}
+    if o3 is not None:
+        rec["o3_build"] = {"flags": "gcc -O3 -march=x86-64-v3 -ffp-contract=off", "one_thread": o3["one"],
+                           "all_cores": o3["all"], "cores": o3["cores"], "unit": "cell-updates/s"}
+    return rec
 
 
 def copy_probe(mib=1024, repeat=3):
@@ -524,6 +548,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the small-basin graph timing, the 1/4-degree runs and the copy bandwidth")
     ap.add_argument("--no-salinity", action="store_true", help="skip the salinity leg")
+    ap.add_argument("--oracle-rates", action="store_true",
+                    help="print the oracle's one-thread and all-cores rates as JSON and exit (no GPU)")
     ap.add_argument("--copy-probe", action="store_true", help="run the counter-calibration copy and exit")
     ap.add_argument("--mib", type=int, default=1024, help="copy probe: size of each buffer in MiB")
     ap.add_argument("--pmc-summary", action="store_true", help="write a kernel's traffic record and exit")
@@ -542,6 +568,9 @@ def main():
 
     if args.copy_probe:
         copy_probe(args.mib)
+        return
+    if args.oracle_rates:
+        print(json.dumps(oracle_rates(inputs.WORKLOADS[args.workload])))
         return
     if args.pmc_summary:
         pmc_summary(argparse.Namespace(**{**vars(args), "workload": args.workload}))

