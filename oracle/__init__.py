@@ -35,6 +35,10 @@ FIELDS_3D = {"u", "v", "T", "gu_prev", "gv_prev", "gt_prev", "p", "kappa", "visc
 RI_DEFAULTS = {"nu0": 1e-2, "alpha": 5.0, "nu_b": 1e-4, "kappa_b": 1e-5, "conv": 1.0}
 
 
+# momentum advection forms (orc_desc.momentum_form)
+MOMENTUM_FORMS = {"flux": 0, "vector_invariant": 1}
+
+
 class OrcDesc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("periodic_x", C.c_int32), ("periodic_y", C.c_int32), ("coords", C.c_int32),
@@ -46,7 +50,8 @@ class OrcDesc(C.Structure):
                 ("restore_tau", C.c_double), ("pgf_weight", C.c_double),
                 ("eos_a0", C.c_double), ("eos_b0", C.c_double), ("eos_lambda1", C.c_double),
                 ("eos_lambda2", C.c_double), ("eos_mu1", C.c_double), ("eos_mu2", C.c_double),
-                ("eos_nu", C.c_double), ("eos_t0", C.c_double), ("eos_s0", C.c_double)]
+                ("eos_nu", C.c_double), ("eos_t0", C.c_double), ("eos_s0", C.c_double),
+                ("momentum_form", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -122,6 +127,7 @@ def desc_from_workload(w) -> OrcDesc:
     d.restore_tau = w.restore_days * 86400.0 if w.restore_days > 0 else 0.0
     d.pgf_weight = w.pgf_weight
     d.salinity = int(w.salinity)
+    d.momentum_form = MOMENTUM_FORMS[getattr(w, "momentum_form", "flux")]
     (d.eos_a0, d.eos_b0, d.eos_lambda1, d.eos_lambda2, d.eos_mu1, d.eos_mu2, d.eos_nu, d.eos_t0,
      d.eos_s0) = w.eos
     return d

@@ -84,6 +84,14 @@ static double coriolis_c(const orc_model* m, int j) {
     }
     return 2.0 * m->d.omega * sin(rad(lat_centre(m, j)));
 }
+/* Coriolis parameter on the south face of row j (where v lives) */
+static double coriolis_s(const orc_model* m, int j) {
+    if (m->d.coords == 0) {
+        double ly = m->ny * m->d.dy;
+        return m->d.f0 + m->d.beta * (j * m->d.dy - 0.5 * ly);
+    }
+    return 2.0 * m->d.omega * sin(rad(lat_south(m, j)));
+}
 /* spherical metric factor tan(phi)/a; zero on the beta-plane */
 static double metric_c(const orc_model* m, int j) {
     if (m->d.coords == 0) return 0.0;
@@ -444,6 +452,110 @@ static double cell_ubar(const orc_model* m, const double* u, int i, int j, int k
     return 0.5 * (at3(m, u, i, j, k) + at3(m, u, i + 1, j, k));
 }
 
+/* Momentum in vector-invariant form (paper Sec. 5.2 names WENO momentum
+ * advection on curvilinear grids, after Silvestri et al.; this form is a
+ * reading). The advection and Coriolis terms of (u.grad)u + f k x u are
+ * written as (f + zeta) k x u + grad(|u|^2 / 2) + w du/dz:
+ *  - zeta is the relative vorticity at a cell corner, the circulation of u, v
+ *    around it over its area (on the sphere this carries the metric term),
+ *    and 0 at a corner that touches land (free slip);
+ *  - at a u point, zeta is reconstructed along y from the six corners of its
+ *    column by the WENO rule (order reduced where corners touch land),
+ *    upwind of vbar, the mean of the four surrounding v, on zeta / ZETA_REF:
+ *    WENO's epsilon (1e-8) is absolute, and vorticity of order 1e-5 1/s
+ *    would leave every smoothness indicator far below it, so that the
+ *    weights would stay linear; in units of a typical Coriolis parameter
+ *    they act as they do on order-one data; the term is
+ *    (f + zeta) vbar with f at the u point's latitude; a v point likewise
+ *    reconstructs zeta along x upwind of ubar and takes -(f + zeta) ubar;
+ *  - the kinetic energy K = (u_w^2 + u_e^2 + v_s^2 + v_n^2) / 4 lives at cell
+ *    centres and its difference over the centre distance gives the gradient;
+ *  - w du/dz is the vertical flux divergence of the flux form minus u times
+ *    the divergence of the vertical transport of the velocity's control
+ *    volume.
+ * The Coriolis part f vbar (f ubar) counts as ORC_TERM_COR, the rest as
+ * ORC_TERM_ADV. */
+#define ZETA_REF 1e-4
+static double uvel(const orc_model* m, const double* u, int i, int j, int k) {
+    return u_wet(m, i, j, k) ? at3(m, u, i, j, k) : 0.0;
+}
+static double vvel(const orc_model* m, const double* v, int i, int j, int k) {
+    return v_wet(m, i, j, k) ? at3(m, v, i, j, k) : 0.0;
+}
+/* corner (i-1/2, j-1/2): water in all four cells around it */
+static int corner_wet(const orc_model* m, int i, int j, int k) {
+    return cell_wet(m, i - 1, j - 1, k) && cell_wet(m, i, j - 1, k) && cell_wet(m, i - 1, j, k) && cell_wet(m, i, j, k);
+}
+static double corner_zeta(const orc_model* m, const double* u, const double* v, int i, int j, int k) {
+    if (!corner_wet(m, i, j, k)) return 0.0;
+    const int jj = map_j(m, j), js = map_j(m, j - 1);
+    const double dy = dy_m(m);
+    const double circ = dy * (vvel(m, v, i, j, k) - vvel(m, v, i - 1, j, k))
+                      - (dx_c(m, jj) * uvel(m, u, i, j, k) - dx_c(m, js) * uvel(m, u, i, j - 1, k));
+    return circ / (dx_v(m, jj) * dy);
+}
+static double cell_ke(const orc_model* m, const double* u, const double* v, int i, int j, int k) {
+    const double uw = uvel(m, u, i, j, k), ue = uvel(m, u, i + 1, j, k);
+    const double vs = vvel(m, v, i, j, k), vn = vvel(m, v, i, j + 1, k);
+    return 0.25 * (uw * uw + ue * ue) + 0.25 * (vs * vs + vn * vn);
+}
+/* upwind reconstruction of the value between points 2 and 3 of p[0..5] */
+static double upwind_value(double F, const double* p, const int32_t* ok) {
+    double s[5];
+    int32_t o[5];
+    if (F > 0.0) {
+        for (int r = 0; r < 5; ++r) { s[r] = p[r]; o[r] = ok[r]; }
+    } else {
+        for (int r = 0; r < 5; ++r) { s[r] = p[5 - r]; o[r] = ok[5 - r]; }
+    }
+    return orc_reconstruct(s, o);
+}
+/* u point (i, j): advection (ADV) and Coriolis (COR) parts of the vector-invariant form */
+static void vi_u(const orc_model* m, const double* u, const double* v, const double* w3, int i, int j, int k,
+                 double* adv, double* cor) {
+    const double vbar = 0.25 * (vvel(m, v, i - 1, j, k) + vvel(m, v, i - 1, j + 1, k) + vvel(m, v, i, j, k)
+                                + vvel(m, v, i, j + 1, k));
+    double p[6];
+    int32_t ok[6];
+    for (int r = 0; r < 6; ++r) {
+        p[r] = corner_zeta(m, u, v, i, j - 2 + r, k) / ZETA_REF;
+        ok[r] = corner_wet(m, i, j - 2 + r, k);
+    }
+    const double zeta = ZETA_REF * upwind_value(vbar, p, ok);
+    const int jj = map_j(m, j);
+    const double vol = area_c(m, jj) * m->dz[k];
+    const double ke = -(cell_ke(m, u, v, i, j, k) - cell_ke(m, u, v, i - 1, j, k)) / dx_c(m, jj);
+    const double wt = 0.5 * (wmask(m, w3, i - 1, j, k + 1) + wmask(m, w3, i, j, k + 1));
+    const double wb = 0.5 * (wmask(m, w3, i - 1, j, k) + wmask(m, w3, i, j, k));
+    const double vert = ((u_zflux(m, u, w3, i, j, k + 1) - u_zflux(m, u, w3, i, j, k))
+                         - uvel(m, u, i, j, k) * (wt - wb)) / vol;
+    *adv = zeta * vbar + ke - vert;
+    *cor = coriolis_c(m, jj) * vbar;
+}
+/* v point (i, j) */
+static void vi_v(const orc_model* m, const double* u, const double* v, const double* w3, int i, int j, int k,
+                 double* adv, double* cor) {
+    const double ubar = 0.25 * (uvel(m, u, i, j - 1, k) + uvel(m, u, i + 1, j - 1, k) + uvel(m, u, i, j, k)
+                                + uvel(m, u, i + 1, j, k));
+    double p[6];
+    int32_t ok[6];
+    for (int r = 0; r < 6; ++r) {
+        p[r] = corner_zeta(m, u, v, i - 2 + r, j, k) / ZETA_REF;
+        ok[r] = corner_wet(m, i - 2 + r, j, k);
+    }
+    const double zeta = ZETA_REF * upwind_value(ubar, p, ok);
+    const int jj = map_j(m, j);
+    const double dy = dy_m(m);
+    const double vol = dx_v(m, jj) * dy * m->dz[k];
+    const double ke = -(cell_ke(m, u, v, i, j, k) - cell_ke(m, u, v, i, j - 1, k)) / dy;
+    const double wt = 0.5 * (wmask(m, w3, i, j - 1, k + 1) + wmask(m, w3, i, j, k + 1));
+    const double wb = 0.5 * (wmask(m, w3, i, j - 1, k) + wmask(m, w3, i, j, k));
+    const double vert = ((v_zflux(m, v, w3, i, j, k + 1) - v_zflux(m, v, w3, i, j, k))
+                         - vvel(m, v, i, j, k) * (wt - wb)) / vol;
+    *adv = -zeta * ubar + ke - vert;
+    *cor = -coriolis_s(m, jj) * ubar;
+}
+
 /* Tendency of a tracer (T or S) in a wet cell: flux-form advection and, in
  * the top layer, restoring towards the target field. */
 static double tracer_tendency(const orc_model* m, int terms, const double* q, const double* qstar,
@@ -486,7 +598,15 @@ void orc_eval_tendencies(const orc_model* m, int terms, double* gu, double* gv, 
                 double g;
                 /* u momentum */
                 g = 0.0;
-                if (u_wet(m, i, j, k)) {
+                if (u_wet(m, i, j, k) && m->d.momentum_form == 1) {
+                    double adv, cor;
+                    vi_u(m, u, v, w3, i, j, k, &adv, &cor);
+                    if (terms & ORC_TERM_ADV) g += adv;
+                    if (terms & ORC_TERM_COR) g += cor;
+                    if (terms & ORC_TERM_PGF) g += pgf_u(m, p, i, j, k);
+                    if ((terms & ORC_TERM_WIND) && k == top)
+                        g += m->taux[id2(m, i, j)] / (m->d.rho0 * dz);
+                } else if (u_wet(m, i, j, k)) {
                     double vol = area_c(m, j) * dz;
                     if (terms & ORC_TERM_ADV) {
                         double div = u_xflux(m, u, i, j, k) - u_xflux(m, u, i - 1, j, k)
@@ -504,7 +624,15 @@ void orc_eval_tendencies(const orc_model* m, int terms, double* gu, double* gv, 
                 gu[c] = g;
                 /* v momentum */
                 g = 0.0;
-                if (v_wet(m, i, j, k)) {
+                if (v_wet(m, i, j, k) && m->d.momentum_form == 1) {
+                    double adv, cor;
+                    vi_v(m, u, v, w3, i, j, k, &adv, &cor);
+                    if (terms & ORC_TERM_ADV) g += adv;
+                    if (terms & ORC_TERM_COR) g += cor;
+                    if (terms & ORC_TERM_PGF) g += pgf_v(m, p, i, j, k);
+                    if ((terms & ORC_TERM_WIND) && k == top)
+                        g += m->tauy[id2(m, i, j)] / (m->d.rho0 * dz);
+                } else if (v_wet(m, i, j, k)) {
                     double vol = dx_v(m, j) * dy * dz;
                     if (terms & ORC_TERM_ADV) {
                         double div = v_xflux(m, u, v, i + 1, j, k) - v_xflux(m, u, v, i, j, k)

@@ -42,6 +42,8 @@ typedef struct orc_desc {
      * m, Ta = T - eos_t0, Sa = S - eos_s0):
      * rho' = -a0 (1 + lambda1 Ta / 2 + mu1 z) Ta + b0 (1 - lambda2 Sa / 2 - mu2 z) Sa - nu Ta Sa */
     double eos_a0, eos_b0, eos_lambda1, eos_lambda2, eos_mu1, eos_mu2, eos_nu, eos_t0, eos_s0;
+    int32_t momentum_form;         /* 0: flux form; 1: vector-invariant form       */
+    int32_t reserved;
 } orc_desc;
 
 typedef struct orc_model orc_model;

@@ -138,6 +138,9 @@ class Workload:
     # equation of state (Roquet et al. 2015 form): kg/m^3/K, kg/m^3/(g/kg), 1/K,
     # 1/(g/kg), 1/(K m), 1/((g/kg) m), kg/m^3/(K g/kg), degC, g/kg
     eos: tuple = (1.6550e-1, 7.6554e-1, 5.9520e-2, 5.4914e-4, 1.4970e-4, 1.1090e-5, 2.4341e-3, 10.0, 35.0)
+    # momentum advection: "flux" (flux form, the benchmarked configurations) or
+    # "vector_invariant"
+    momentum_form: str = "flux"
 
     @property
     def cells(self) -> int:
