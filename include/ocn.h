@@ -109,6 +109,15 @@ typedef struct ocn_params {
                                  + b0 (1 - lambda2 Sa/2 - mu2 z) Sa - nu Ta Sa,
                                  Ta = T - t0, Sa = S - s0, z the depth (m), and
                                  b = -g rho'/rho0; unused without salinity         */
+    int32_t momentum_form;    /* 0: flux form (advection of u, v by the face
+                                 transports, Coriolis with the spherical metric
+                                 term); 1: vector-invariant form, (f + zeta) k x u
+                                 + grad(|u|^2/2) + w du/dz with the corner
+                                 vorticity reconstructed by WENO upwind of the
+                                 transverse velocity (paper Sec. 5.2: WENO
+                                 momentum advection on curvilinear grids).
+                                 Ensembles take the flux form.                    */
+    int32_t reserved2;        /* must be 0                                        */
 } ocn_params;
 
 /* Field identifiers. */

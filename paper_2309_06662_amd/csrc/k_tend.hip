@@ -153,6 +153,27 @@ __device__ __forceinline__ R upwind_flux_wet(R F, const R* p) {
     return F * weno5z(a, b, c, d, e);
 }
 
+// The reconstructed value (not the flux) at the point between p2 and p3,
+// upwind of F (the right-biased stencil when F <= 0), all six points valid
+// or with validity flags.
+template <typename R>
+__device__ __forceinline__ R upwind_value_wet(R F, const R* p) {
+    const bool pos = F > R(0);
+    return weno5z(pos ? p[0] : p[5], pos ? p[1] : p[4], pos ? p[2] : p[3], pos ? p[3] : p[2], pos ? p[4] : p[1]);
+}
+template <typename R>
+__device__ __forceinline__ R upwind_value(R F, const R* p, const bool* ok) {
+    const bool pos = F > R(0);
+    return recon(pos ? p[0] : p[5], pos ? p[1] : p[4], pos ? p[2] : p[3], pos ? p[3] : p[2], pos ? p[4] : p[1],
+                 pos ? ok[0] : ok[5], pos ? ok[1] : ok[4], pos ? ok[2] : ok[3], pos ? ok[3] : ok[2],
+                 pos ? ok[4] : ok[1]);
+}
+
+// Vorticity is reconstructed in units of a typical Coriolis parameter (1/s),
+// so that WENO's absolute epsilon sits below the smoothness indicators of
+// ocean vorticity as it does for order-one data.
+constexpr double kZetaRef = 1e-4;
+
 // The tile order: bands of kTendBand tile rows, each walked column by column
 // (down the band, then one column east), so that some of the north and south
 // halo rows of the tiles an XCD runs at once are read from its L2 by the
@@ -172,9 +193,9 @@ __device__ __forceinline__ int2 band_tile(int t, int gx, int gy) {
 
 // Occupancy target per precision: four waves per SIMD (two FP32 workgroups of
 // 8 waves per CU) keeps the FP32 kernel within 128 VGPRs. The second tracer
-// needs about 170 VGPRs in FP32: its 32 x 8 tiles run at three waves per
-// SIMD (three 4-wave workgroups per CU; 25 % faster than 32 x 16 tiles at
-// two). The FP64 salinity kernel on 64 x 4 tiles holds one workgroup per CU
+// (or the vector-invariant momentum form) needs about 170 VGPRs in FP32: its
+// 32 x 8 tiles run at three waves per SIMD (three 4-wave workgroups per CU;
+// 25 % faster than 32 x 16 tiles at two). The FP64 salinity kernel on 64 x 4 tiles holds one workgroup per CU
 // (two would exceed the LDS).
 template <typename R, bool SALT, int TY> struct TendWaves {
     static constexpr int n = (sizeof(R) == 4 && !SALT)            ? 4
@@ -207,7 +228,16 @@ template <typename R, bool SALT, int TY> struct TendWaves {
 // Coriolis and transport arrays of level k are only rewritten after the next
 // level's first barrier, which every wave reaches only once it has assembled
 // level k; the pressure is double-buffered by parity as well.
-template <typename R, int TX, int TY, bool SALT>
+//
+// Vector-invariant momentum (VI): the momentum flux slots of the cells stay
+// idle (the ring keeps using its slots for the tracers); each cell forms
+// (f + zeta_hat) vbar for u and -(f + zeta_hat) ubar for v in the point
+// phase, zeta_hat reconstructed from corner vorticities that it computes from
+// the u, v tiles (six corners along y for u, along x for v); every point puts
+// its kinetic energy in LDS for the gradients, and the vertical term is the
+// flux form's vertical divergence minus u times the divergence of the
+// velocity point's vertical transport.
+template <typename R, int TX, int TY, bool SALT, bool VI>
 __device__ __forceinline__ void tend_tile(const DevState& S, const int first, const int bx, const int by) {
     constexpr int NT = TX * TY;
     constexpr int LW = TX + 5, LH = TY + 5, LN = LW * LH;  // u, v tiles: points -2 .. +3 around the block
@@ -224,7 +254,12 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     __shared__ R sQv[NT], sQu[NT], sP[2 * NT], sWm[NT];
     // per-row metrics of the tile's rows (a row's threads read one address):
     // dxv south, dxv north, area, f, tan(phi)/a, 1/area, 1/(dxv dy), 1/dxc
-    __shared__ R sRow[8][TY];
+    __shared__ R sRow[9][TY];
+    // vector-invariant form: kinetic energy of every point, and the metrics of
+    // rows j0-4 .. j0+TY+1 (dxc; 1 / (dxv dy zeta_ref)) for corner vorticities
+    constexpr int VNT = VI ? NT : 1, VRR = VI ? TY + 6 : 1;
+    __shared__ R sKE[VNT];
+    __shared__ R sRX[2][VRR];
     __shared__ R sTop[NT];  // surface volume flux times the full top temperature
     // salinity: its tile, its face fluxes and the surface term, as for T
     constexpr int SN = SALT ? TN : 1, SNT = SALT ? NT : 1;
@@ -344,6 +379,19 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
         minA = unsigned(mTx) | unsigned(mTy) << 8 | unsigned(mux) << 16 | unsigned(muy) << 24;
         minB = unsigned(mvx) | unsigned(mvy) << 8 | unsigned(mTw) << 16 | unsigned(mTs) << 24;
     }
+    // vector-invariant form: smallest wet count over the cells around the six
+    // corners of the u point's column (x -1..0, y -3..3) and of the v point's
+    // row (x -3..3, y -1..0)
+    unsigned minC = 0;
+    if constexpr (VI) {
+        int mzu = Kc, mzv = Kc;
+#pragma unroll
+        for (int r = -3; r <= 3; ++r) {
+            mzu = min(mzu, min(Kat(-1, r), Kat(0, r)));
+            mzv = min(mzv, min(Kat(r, -1), Kat(r, 0)));
+        }
+        minC = unsigned(mzu) | unsigned(mzv) << 8;
+    }
     auto byte_of = [](unsigned v, int q) { return int((v >> (8 * q)) & 0xffu); };
 #define mTx byte_of(minA, 0)
 #define mTy byte_of(minA, 1)
@@ -366,6 +414,14 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
         sRow[5][ty] = R(1.0 / S.area[jr]);
         sRow[6][ty] = R(1.0 / (S.dxv[jr] * S.dy));
         sRow[7][ty] = R(1.0 / S.dxc[jr]);
+        sRow[8][ty] = R(S.fcor_s[jr]);
+    }
+    if constexpr (VI) {
+        if (tid < TY + 6) {
+            const int row = min(max(j0 - 4 + tid, -h), ny + h - 1);
+            sRX[0][tid] = R(S.dxc[row]);
+            sRX[1][tid] = R(1.0 / (S.dxv[row] * S.dy * kZetaRef));
+        }
     }
     const R dy = R(S.dy), inv_dy = R(1.0 / S.dy);
     const R ga = R(S.g * S.alpha);
@@ -440,6 +496,9 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
     R Wm_top = R(0);                                     // masked W on that face
     R p_prev = R(0), b_prev = R(0);
     R GUp = R(0), GVp = R(0);  // momentum tendencies of level k+1 without the pressure gradient
+    // vector-invariant form: the (f + zeta_hat) terms of the level, and the
+    // vertical transports of the u and v control volumes on the top face
+    R vi_u = R(0), vi_v = R(0), FuT = R(0), FvT = R(0);
     double gUacc = 0.0, gVacc = 0.0;
     const R rinv = R(S.restore_inv);
     R* __restrict__ gto = f3<R>(S.gt_out);
@@ -579,8 +638,9 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                 }
             }
             // u through the cell centre (between u(pi) and u(pi+1)); in the
-            // ring row: T through the south face
-            if (used && (ty >= 1 || tx >= 1)) {
+            // ring row: T through the south face (the vector-invariant form
+            // only uses the ring row's)
+            if (used && (VI ? (ty == 0 && tx >= 1) : (ty >= 1 || tx >= 1))) {
                 const bool alt = ty == 0;
                 const R* base = alt ? &sT[meT - 3 * TW] : &sU[me - 2];
                 const int stride = alt ? TW : 1;
@@ -594,7 +654,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                     fxu[tid] = upwind_flux(F, p, ok);
                 }
             }
-            if (need_x) {
+            if (!VI && need_x) {
                 const R U1m = (KuSE >= kwet) ? at(sU, 1, -1) * dy * dzk : R(0);
                 // v through the south-east corner (between v(pi,pj) and v(pi+1,pj))
                 const R Fv = R(0.5) * (U1m + U10);
@@ -607,7 +667,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                     fxv[tid] = upwind_flux(Fv, p, ok);
                 }
             } else if constexpr (SALT) {
-                if (used && tx >= 1) {  // ring row: S through the south face
+                if (used && ty == 0 && tx >= 1) {  // ring row: S through the south face
 #pragma unroll
                     for (int r = 0; r < 6; ++r) p[r] = sS[meT + (r - 3) * TW];
                     if (mTs >= kwet) fxv[tid] = (V00 == R(0)) ? R(0) : upwind_flux_wet(V00, p);
@@ -637,7 +697,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
             }
             // u through the north-west corner (between u(pi,pj) and u(pi,pj+1));
             // in the ring column: T through the west face
-            {
+            if (!VI || (tx == 0 && ty >= 1)) {
                 const bool alt = tx == 0;
                 const R Vm1 = (KvNW >= kwet) ? at(sV, -1, 1) * dxv1 * dzk : R(0);
                 const R* base = alt ? &sT[meT - 3] : &sU[me - 2 * LW];
@@ -652,7 +712,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                     fyu[tid] = upwind_flux(F, p, ok);
                 }
             }
-            if (need_y) {
+            if (!VI && need_y) {
                 // v through the cell centre (between v(pj) and v(pj+1))
                 const R Fv = R(0.5) * (V00 + V01);
 #pragma unroll
@@ -664,7 +724,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                     fyv[tid] = upwind_flux(Fv, p, ok);
                 }
             } else if constexpr (SALT) {
-                if (used && ty >= 1) {  // ring column: S through the west face
+                if (used && tx == 0 && ty >= 1) {  // ring column: S through the west face
 #pragma unroll
                     for (int r = 0; r < 6; ++r) p[r] = sS[meT + r - 3];
                     if (mTw >= kwet) fyv[tid] = (U00 == R(0)) ? R(0) : upwind_flux_wet(U00, p);
@@ -675,13 +735,63 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                     }
                 }
             }
-            if (need_c) {
+            if (!VI && need_c) {
                 // Coriolis: Q = (f + u_c tan(phi)/a) V_c on wet cells
                 const R uc = R(0.5) * (at(sU, 0, 0) + at(sU, 1, 0));
                 const R vc = R(0.5) * (at(sV, 0, 0) + at(sV, 0, 1));
                 const R Q = (Kc >= kwet) ? (sRow[3][ty] + sRow[4][ty] * uc) * sRow[2][ty] * dzk : R(0);
                 sQv[tid] = Q * vc;
                 sQu[tid] = Q * uc;
+            }
+            if constexpr (VI) {
+                auto muu = [&](int a, int b) { return mu(a, b) ? at(sU, a, b) : R(0); };
+                auto mvv = [&](int a, int b) { return mv(a, b) ? at(sV, a, b) : R(0); };
+                {  // kinetic energy at this point
+                    const R uw = muu(0, 0), ue = muu(1, 0), vs = mvv(0, 0), vn = mvv(0, 1);
+                    sKE[tid] = R(0.25) * (uw * uw + ue * ue) + R(0.25) * (vs * vs + vn * vn);
+                }
+                if (cell) {
+                    // corner (pi+a, pj+b), the south-west corner of cell (pi+a, pj+b):
+                    // its circulation over dxv dy zeta_ref, 0 where it touches land
+                    auto cwet = [&](int a, int b) {
+                        return wet(a - 1, b - 1) && wet(a, b - 1) && wet(a - 1, b) && wet(a, b);
+                    };
+                    auto zc = [&](int a, int b) {
+                        const int rr = ty + 3 + b;
+                        const R circ = dy * (at(sV, a, b) - at(sV, a - 1, b)) -
+                                       (sRX[0][rr] * at(sU, a, b) - sRX[0][rr - 1] * at(sU, a, b - 1));
+                        return circ * sRX[1][rr];
+                    };
+                    const R vbar = R(0.25) * (mvv(-1, 0) + mvv(-1, 1) + mvv(0, 0) + mvv(0, 1));
+                    const R ubar = R(0.25) * (muu(0, -1) + muu(1, -1) + muu(0, 0) + muu(1, 0));
+                    R zu, zv;
+                    if (int(minC & 0xffu) >= kwet) {  // the six corners along y
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) p[r] = zc(0, r - 2);
+                        zu = upwind_value_wet(vbar, p);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) {
+                            ok[r] = cwet(0, r - 2);
+                            p[r] = ok[r] ? zc(0, r - 2) : R(0);
+                        }
+                        zu = upwind_value(vbar, p, ok);
+                    }
+                    if (int((minC >> 8) & 0xffu) >= kwet) {  // the six corners along x
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) p[r] = zc(r - 2, 0);
+                        zv = upwind_value_wet(ubar, p);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) {
+                            ok[r] = cwet(r - 2, 0);
+                            p[r] = ok[r] ? zc(r - 2, 0) : R(0);
+                        }
+                        zv = upwind_value(ubar, p, ok);
+                    }
+                    vi_u = (sRow[3][ty] + R(kZetaRef) * zu) * vbar;
+                    vi_v = -(sRow[8][ty] + R(kZetaRef) * zv) * ubar;
+                }
             }
             // vertical transport on the bottom face of level k
             const double div = double(U10) - double(U00) + (double(V01) - double(V00));
@@ -700,6 +810,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
             // vertical fluxes through the bottom face (between levels k-1 and k)
             R fzT_bot = R(0), fzu_bot = R(0), fzv_bot = R(0);
             R E_bot = R(0), fzS_bot = R(0), ES_bot = R(0);
+            R Fu_b = R(0), Fv_b = R(0);  // vertical transports of the u, v control volumes
             if (k >= 1) {
                 // levels k-3 .. k+2 all inside the column: the open-ocean path
                 const bool zin = (k >= 3) && (k + 2 < nz);
@@ -731,6 +842,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                 }
                 if (cell) {
                     const R Fu = R(0.5) * (sWm[cw] + Wm_b);
+                    Fu_b = Fu;
                     if (Fu != R(0)) {
                         R pu[6];
 #pragma unroll
@@ -748,6 +860,7 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                         }
                     }
                     const R Fv = R(0.5) * (sWm[cs] + Wm_b);
+                    Fv_b = Fv;
                     if (Fv != R(0)) {
                         R pv[6];
 #pragma unroll
@@ -831,15 +944,27 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
                 R GUm = R(0);
                 if (Ku >= kwet) {
                     const R ivol = sRow[5][ty] * inv_dz;
-                    const R divF = (fxu[c] - fxu[cw]) + (fyu[c] - fyu[cs]) + (fzu_top - fzu_bot);
-                    GUm = -divF * ivol + (sQv[cw] + sQv[c]) * (R(0.5) * ivol);
+                    if constexpr (VI) {
+                        // (f + zeta_hat) vbar - dK/dx - w du/dz
+                        GUm = vi_u - (sKE[c] - sKE[cw]) * sRow[7][ty] -
+                              ((fzu_top - fzu_bot) - wu[2] * (FuT - Fu_b)) * ivol;
+                    } else {
+                        const R divF = (fxu[c] - fxu[cw]) + (fyu[c] - fyu[cs]) + (fzu_top - fzu_bot);
+                        GUm = -divF * ivol + (sQv[cw] + sQv[c]) * (R(0.5) * ivol);
+                    }
                     if (k == nz - 1) GUm += R(S.taux[idx2(S, pi, pj)] / (S.rho0 * S.dz[nz - 1]));
                 }
                 R GVm = R(0);
                 if (Kv >= kwet) {
                     const R ivol = sRow[6][ty] * inv_dz;
-                    const R divF = (fxv[c] - fxv[cw]) + (fyv[c] - fyv[cs]) + (fzv_top - fzv_bot);
-                    GVm = -divF * ivol - (sQu[cs] + sQu[c]) * (R(0.5) * ivol);
+                    if constexpr (VI) {
+                        // -(f + zeta_hat) ubar - dK/dy - w dv/dz
+                        GVm = vi_v - (sKE[c] - sKE[cs]) * inv_dy -
+                              ((fzv_top - fzv_bot) - wv[2] * (FvT - Fv_b)) * ivol;
+                    } else {
+                        const R divF = (fxv[c] - fxv[cw]) + (fyv[c] - fyv[cs]) + (fzv_top - fzv_bot);
+                        GVm = -divF * ivol - (sQu[cs] + sQu[c]) * (R(0.5) * ivol);
+                    }
                     if (k == nz - 1) GVm += R(S.tauy[idx2(S, pi, pj)] / (S.rho0 * S.dz[nz - 1]));
                 }
                 GUp = GUm;
@@ -850,6 +975,10 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
             if constexpr (SALT) fzS_top = fzS_bot;
             fzu_top = fzu_bot;
             fzv_top = fzv_bot;
+            if constexpr (VI) {
+                FuT = Fu_b;
+                FvT = Fv_b;
+            }
         }
         Wm_top = Wm_b;
     }
@@ -875,11 +1004,11 @@ __device__ __forceinline__ void tend_tile(const DevState& S, const int first, co
 #undef mTs
 }
 
-template <typename R, int TX, int TY, bool SALT>
-__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R, SALT, TY>::n)))
+template <typename R, int TX, int TY, bool SALT, bool VI>
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R, SALT || VI, TY>::n)))
 void k_tend(const DevState S, const int first, const int gx) {
     const int2 t = band_tile(xcd_tile(blockIdx.x, gridDim.x), gx, gridDim.x / gx);
-    tend_tile<R, TX, TY, SALT>(S, first, t.x, t.y);
+    tend_tile<R, TX, TY, SALT, VI>(S, first, t.x, t.y);
 }
 
 // Ensemble: entry b of the tile table names (member, bx, by); the host orders
@@ -888,7 +1017,7 @@ template <typename R, int TY>
 __global__ __launch_bounds__(TXB * TY) __attribute__((amdgpu_waves_per_eu(TendWaves<R, false, TY>::n)))
 void k_tend_batched(const DevState* __restrict__ members, const int4* __restrict__ tiles, const int first) {
     const int4 e = tiles[blockIdx.x];
-    tend_tile<R, TXB, TY, false>(members[e.x], first, e.y, e.z);
+    tend_tile<R, TXB, TY, false, false>(members[e.x], first, e.y, e.z);
 }
 
 // The same over a queue of table entries, with persistent workgroups.
@@ -898,7 +1027,7 @@ void k_tend_queued(const DevState* __restrict__ members, const int4* __restrict_
                    const int first, int* __restrict__ queue) {
     for_each_queued_tile(queue, ntiles, [&](int b) {
         const int4 e = tiles[b];
-        tend_tile<R, TXB, TY, false>(members[e.x], first, e.y, e.z);
+        tend_tile<R, TXB, TY, false, false>(members[e.x], first, e.y, e.z);
     });
 }
 
@@ -908,24 +1037,26 @@ int tend_tile_rows(int precision_bytes, int ty_choice) {
     return precision_bytes == 4 ? 8 : 4;
 }
 
-template <typename R, int TX, int TY>
+template <typename R, int TX, int TY, bool SALT, bool VI>
 hipError_t launch_tend_shape(const DevState& s, int first, hipStream_t st) {
     const int gx = (s.nx + TX - 2) / (TX - 1);
     const int gy = (s.ny + TY - 2) / (TY - 1);
-    if (s.salinity)
-        hipLaunchKernelGGL((k_tend<R, TX, TY, true>), dim3(gx * gy), dim3(TX, TY), 0, st, s, first, gx);
-    else
-        hipLaunchKernelGGL((k_tend<R, TX, TY, false>), dim3(gx * gy), dim3(TX, TY), 0, st, s, first, gx);
+    hipLaunchKernelGGL((k_tend<R, TX, TY, SALT, VI>), dim3(gx * gy), dim3(TX, TY), 0, st, s, first, gx);
     return hipGetLastError();
 }
 
-// Single state: the precision's shape, or a 64-wide tile of 4 or 8 rows when chosen.
+// Single state: the precision's shape; with salinity or the vector-invariant
+// form the wider-register shape; a 64-wide tile of 4 or 8 rows when chosen
+// (temperature only, flux form).
 template <typename R>
 hipError_t launch_tendency(const DevState& s, int first, hipStream_t st) {
-    if (s.tend_ty == 8) return launch_tend_shape<R, TXB, 8>(s, first, st);
-    if (s.tend_ty == 4) return launch_tend_shape<R, TXB, 4>(s, first, st);
-    if (s.salinity) return launch_tend_shape<R, TendShapeSalt<R>::TX, TendShapeSalt<R>::TY>(s, first, st);
-    return launch_tend_shape<R, TendShape<R>::TX, TendShape<R>::TY>(s, first, st);
+    constexpr int WX = TendShapeSalt<R>::TX, WY = TendShapeSalt<R>::TY;
+    if (s.salinity && s.vi) return launch_tend_shape<R, WX, WY, true, true>(s, first, st);
+    if (s.salinity) return launch_tend_shape<R, WX, WY, true, false>(s, first, st);
+    if (s.vi) return launch_tend_shape<R, WX, WY, false, true>(s, first, st);
+    if (s.tend_ty == 8) return launch_tend_shape<R, TXB, 8, false, false>(s, first, st);
+    if (s.tend_ty == 4) return launch_tend_shape<R, TXB, 4, false, false>(s, first, st);
+    return launch_tend_shape<R, TendShape<R>::TX, TendShape<R>::TY, false, false>(s, first, st);
 }
 
 template <typename R>

@@ -48,7 +48,7 @@ struct ocn_grid {
     std::vector<double> dz, dzc;
     std::vector<int32_t> kb;              // ny * nx interior
     // row metrics for j = -h .. ny + h (index j + h)
-    std::vector<double> dxc, dxv, area, fcor, metric;
+    std::vector<double> dxc, dxv, area, fcor, metric, fcor_s;
     double dy;
     int row(int j) const { return j + h; }
 };
@@ -155,7 +155,7 @@ struct Plan {
     size_t nrow;  // metric rows
     size_t diag_blocks;
     int nf3, nf2;  // 3D and 2D arrays of the state (more with salinity)
-    size_t off_f3[14], off_f2[25], off_bw, off_kb, off_rows[5], off_dz, off_dzc, off_tref, off_dtr, off_tab, off_cumh;
+    size_t off_f3[14], off_f2[25], off_bw, off_kb, off_rows[6], off_dz, off_dzc, off_tref, off_dtr, off_tab, off_cumh;
     size_t off_sref, off_dsr, off_eos, off_zc;
     size_t off_part, off_out;
     size_t total;
@@ -241,6 +241,8 @@ bool valid_params(const ocn_params* p, std::string& why) {
         for (int q = 0; q < 9; ++q)
             if (!std::isfinite(p->eos[q])) { why = "eos coefficients must be finite"; return false; }
     if (!(p->pgf_weight >= 0.0 && p->pgf_weight <= 1.0)) { why = "pgf_weight must be in [0, 1]"; return false; }
+    if (p->momentum_form != 0 && p->momentum_form != 1) { why = "momentum_form must be 0 or 1"; return false; }
+    if (p->reserved2 != 0) { why = "reserved2 must be 0"; return false; }
     return true;
 }
 
@@ -408,9 +410,9 @@ int init_static(ocn_state* s) {
     HIPCHK(hipMemcpyAsync(d.kb - ((size_t)hk * d.pk + s->oxk), kbimg.data(), kbimg.size() * 4, hipMemcpyHostToDevice, s->st));
     // row metrics
     const size_t nr = ny + 2 * h + 1;
-    double* rows[5] = {d.dxc, d.dxv, d.area, d.fcor, d.metric};
-    const std::vector<double>* src[5] = {&g->dxc, &g->dxv, &g->area, &g->fcor, &g->metric};
-    for (int q = 0; q < 5; ++q)
+    double* rows[6] = {d.dxc, d.dxv, d.area, d.fcor, d.metric, d.fcor_s};
+    const std::vector<double>* src[6] = {&g->dxc, &g->dxv, &g->area, &g->fcor, &g->metric, &g->fcor_s};
+    for (int q = 0; q < 6; ++q)
         HIPCHK(hipMemcpyAsync(rows[q] - h, src[q]->data(), nr * sizeof(double), hipMemcpyHostToDevice, s->st));
     HIPCHK(hipMemcpyAsync(d.dz, g->dz.data(), nz * sizeof(double), hipMemcpyHostToDevice, s->st));
     HIPCHK(hipMemcpyAsync(d.dzc, g->dzc.data(), (nz + 1) * sizeof(double), hipMemcpyHostToDevice, s->st));
@@ -757,6 +759,7 @@ int ocn_grid_create(const ocn_grid_desc* desc, ocn_grid** out) {
             for (size_t c = 0; c < g->kb.size(); ++c) g->kb[c] = std::max(0, std::min<int32_t>(d.nz, d.kbottom[c]));
         const int nr = d.ny + 2 * d.halo + 1;
         g->dxc.resize(nr); g->dxv.resize(nr); g->area.resize(nr); g->fcor.resize(nr); g->metric.resize(nr);
+        g->fcor_s.resize(nr);
         const double rad = kPi / 180.0;
         g->dy = d.coords == OCN_LATLON ? d.radius * d.dy * rad : d.dy;
         for (int q = 0; q < nr; ++q) {
@@ -767,11 +770,13 @@ int ocn_grid_create(const ocn_grid_desc* desc, ocn_grid** out) {
                 g->dxc[q] = d.radius * std::cos(latc * rad) * (d.dx * rad);
                 g->dxv[q] = d.radius * std::cos(lats * rad) * (d.dx * rad);
                 g->fcor[q] = 2.0 * d.omega * std::sin(latc * rad);
+                g->fcor_s[q] = 2.0 * d.omega * std::sin(lats * rad);
                 g->metric[q] = std::tan(latc * rad) / d.radius;
             } else {
                 g->dxc[q] = d.dx;
                 g->dxv[q] = d.dx;
                 g->fcor[q] = d.f0 + d.beta * ((j + 0.5) * d.dy - 0.5 * d.ny * d.dy);
+                g->fcor_s[q] = d.f0 + d.beta * (j * d.dy - 0.5 * d.ny * d.dy);
                 g->metric[q] = 0.0;
             }
             g->area[q] = g->dxc[q] * g->dy;
@@ -855,8 +860,8 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
             s->sstar.assign((size_t)grid->nx * grid->ny, 0.0);
         }
         d.kb = reinterpret_cast<int*>(A + P.off_kb) + ((size_t)(h + 1) * P.pk + P.oxk);
-        double** rows[5] = {&d.dxc, &d.dxv, &d.area, &d.fcor, &d.metric};
-        for (int q = 0; q < 5; ++q) *rows[q] = reinterpret_cast<double*>(A + P.off_rows[q]) + h;
+        double** rows[6] = {&d.dxc, &d.dxv, &d.area, &d.fcor, &d.metric, &d.fcor_s};
+        for (int q = 0; q < 6; ++q) *rows[q] = reinterpret_cast<double*>(A + P.off_rows[q]) + h;
         d.dy = grid->dy;
         d.dz = reinterpret_cast<double*>(A + P.off_dz);
         d.dzc = reinterpret_cast<double*>(A + P.off_dzc);
@@ -875,6 +880,7 @@ int ocn_state_init(const ocn_grid* grid, const ocn_params* params, void* device_
         d.kappa = params->kappa;
         d.restore_inv = params->restore_tau > 0.0 ? 1.0 / params->restore_tau : 0.0;
         d.pgf_w = params->pgf_weight;
+        d.vi = params->momentum_form;
         d.n_substeps = params->n_substeps;
         d.baro_fuse = params->baro_fuse == 0 ? ocn::kBaroFuseDefault : params->baro_fuse;
         d.baro_m = ocn::baro_substeps(params->n_substeps);
@@ -1651,6 +1657,7 @@ int ocn_ensemble_init(const ocn_grid* const* grids, int32_t n, const ocn_params*
         for (int m = 0; m < n; ++m)
             if (!grids[m]) return fail(OCN_E_INVALID, "NULL grid");
         if (params->salinity) return fail(OCN_E_UNSUPPORTED, "ensembles take temperature only");
+        if (params->momentum_form) return fail(OCN_E_UNSUPPORTED, "ensembles take the flux form of momentum");
         EnsPlan P;
         ens_plan(grids, n, params, P);
         if (arena_bytes < P.total) return fail(OCN_E_NOMEM, "arena smaller than ocn_ensemble_arena_bytes");

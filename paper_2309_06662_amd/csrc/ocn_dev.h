@@ -48,6 +48,7 @@ struct DevState {
     // salinity (when salinity != 0): S - sref(k), its predictor, and its
     // double-buffered AB2 history like T's
     int salinity;
+    int vi;           // momentum advection: 0 flux form, 1 vector-invariant form
     void *s, *ss, *gs, *gs_out;
     // 2D FP64
     double *eta, *ubt, *vbt;             // barotropic state
@@ -72,6 +73,7 @@ struct DevState {
     int* kb;
     // row metrics, index j from -h to ny + h (FP64), interior origin
     double *dxc, *dxv, *area, *fcor, *metric;
+    double *fcor_s;   // Coriolis parameter on the south face of each row (vector-invariant form)
     double dy;
     // level tables
     double* dz;       // nz

@@ -68,7 +68,8 @@ class Params(C.Structure):
     _fields_ = [("precision", C.c_int32), ("n_substeps", C.c_int32), ("baro_fuse", C.c_int32),
                 ("salinity", C.c_int32), ("dt", C.c_double), ("chi", C.c_double), ("g", C.c_double),
                 ("alpha", C.c_double), ("rho0", C.c_double), ("t_ref", C.c_double), ("kappa", C.c_double),
-                ("restore_tau", C.c_double), ("pgf_weight", C.c_double), ("eos", C.c_double * 9)]
+                ("restore_tau", C.c_double), ("pgf_weight", C.c_double), ("eos", C.c_double * 9),
+                ("momentum_form", C.c_int32), ("reserved2", C.c_int32)]
 
 
 class Diag(C.Structure):
@@ -176,6 +177,7 @@ def params(w: "_inputs.Workload", precision: str, baro_fuse: int = 0) -> Params:
     p.restore_tau = w.restore_days * 86400.0 if w.restore_days > 0 else 0.0
     p.pgf_weight = w.pgf_weight
     p.salinity = 1 if getattr(w, "salinity", False) else 0
+    p.momentum_form = {"flux": 0, "vector_invariant": 1}[getattr(w, "momentum_form", "flux")]
     if p.salinity:
         for q, c in enumerate(w.eos):
             p.eos[q] = c
