@@ -83,6 +83,8 @@ __device__ __forceinline__ float inv_level(double dz, float) { return __builtin_
 //    r_k^2 with s the second and r the first difference of stencil k; the
 //    WENO-Z ratios tau / (beta_k + eps) are unchanged, and the three share
 //    one reciprocal of the product of their denominators (all >= 4 eps);
+//    eps enters each indicator inside its fused multiply-adds, and
+//    tau = |beta_0 - beta_2| is taken from the sums with eps (it cancels);
 //  - with w_k = 1 + (tau / (beta_k + eps))^2 the nonlinear weights are
 //    d_k w_k (d = 1/10, 6/10, 3/10), so d_k is folded into the candidate
 //    values: c + sum w_k (d_k q_k) / sum d_k w_k, where q_k - c is the
@@ -92,12 +94,11 @@ __device__ __forceinline__ R weno5z(R a, R b, R c, R d, R e) {
     const R d1 = b - a, d2 = c - b, d3 = d - c, d4 = e - d;
     const R s0 = d2 - d1, s1 = d3 - d2, s2 = d4 - d3;          // second differences
     const R r0 = fma(R(2), d2, s0), r1 = d2 + d3, r2 = fma(R(-2), d3, s2);
-    const R k13 = R(13) / R(3);
-    const R b0 = fma(s0 * s0, k13, r0 * r0);
-    const R b1 = fma(s1 * s1, k13, r1 * r1);
-    const R b2 = fma(s2 * s2, k13, r2 * r2);
-    const R tau = fabs(b0 - b2);
-    const R e0 = b0 + R(4) * Eps<R>::v, e1 = b1 + R(4) * Eps<R>::v, e2 = b2 + R(4) * Eps<R>::v;
+    const R k13 = R(13) / R(3), eps4 = R(4) * Eps<R>::v;
+    const R e0 = fma(s0 * s0, k13, fma(r0, r0, eps4));  // beta'_k + eps
+    const R e1 = fma(s1 * s1, k13, fma(r1, r1, eps4));
+    const R e2 = fma(s2 * s2, k13, fma(r2, r2, eps4));
+    const R tau = fabs(e0 - e2);
     const R p12 = e1 * e2, p02 = e0 * e2, p01 = e0 * e1;
     const R tr = tau * rcp(p01 * e2);
     const R z0 = tr * p12, z1 = tr * p02, z2 = tr * p01;
