@@ -14,8 +14,13 @@ before the timed region starts; the timed region is K whole steps (tendency +
 AB2, barotropic substeps, column solve + correction), bracketed by device
 synchronisation.
 
-Every leg reports whether its state stayed finite and its largest speed; the
-run exits with status 3 when the headline leg ended non-finite.
+Beside the headline legs: the same grid with salinity and the quadratic
+equation of state, and with vector-invariant momentum advection (FP32 each);
+a 64-member ensemble of uneven basins; a small basin under graph replay; the
+1/4-degree basin in both precisions, with the learned closure and with
+Richardson-number mixing. Every leg reports whether its state stayed finite
+and its largest speed; the run exits with status 3 when the headline leg
+ended non-finite.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 
@@ -243,6 +248,28 @@ def run_salinity(w, steps, warmup):
                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(tb / t_s / 1e9 / HBM_PEAK_GBS, 4)},
             "column_roofline": {"bound": "hbm", "bytes_per_launch": cb, "achieved": round(cb / c_s / 1e9, 1),
                                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(cb / c_s / 1e9 / HBM_PEAK_GBS, 4)}}
+
+
+def run_vector_invariant(w, steps, warmup):
+    """The same workload with vector-invariant momentum advection (FP32): time
+    per step, stages and the tendency kernel's roofline (the same 12 words per
+    cell as the flux form: only the arithmetic between them differs)."""
+    import torch
+
+    wv = w.replace(momentum_form="vector_invariant")
+    inp = inputs.make_inputs(wv)
+    el, stages, diag = run_gpu(wv, "fp32", inp, steps, warmup)
+    del inp
+    ms = el / steps * 1e3
+    tb = TEND_WORDS_PER_CELL * 4 * wv.cells
+    t_s = stages["tendency"] * 1e-3
+    torch.cuda.empty_cache()
+    return {"workload": wv.name + "_vector_invariant", "ms_per_step": ms,
+            "cell_updates_per_s": metrics.cell_updates_per_second(wv.nx, wv.ny, wv.nz, steps, el),
+            "sypd": metrics.sypd(wv.dt, ms * 1e-3), "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+            "finite": diag["nonfinite"] == 0, "max_abs_u": diag["max_abs_u"],
+            "tend_roofline": {"bound": "hbm", "bytes_per_launch": tb, "achieved": round(tb / t_s / 1e9, 1),
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(tb / t_s / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
 def run_quarter(steps, warmup):
@@ -548,6 +575,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the small-basin graph timing, the 1/4-degree runs and the copy bandwidth")
     ap.add_argument("--no-salinity", action="store_true", help="skip the salinity leg")
+    ap.add_argument("--no-vi", action="store_true", help="skip the vector-invariant momentum leg")
     ap.add_argument("--oracle-rates", action="store_true",
                     help="print the oracle's one-thread and all-cores rates as JSON and exit (no GPU)")
     ap.add_argument("--copy-probe", action="store_true", help="run the counter-calibration copy and exit")
@@ -608,6 +636,12 @@ def main():
         print(f"[bench] salinity fp32: {sal['ms_per_step']:.3f} ms/step, stages {sal['stage_ms']}, "
               f"finite={sal['finite']}", file=sys.stderr, flush=True)
 
+    vi = None
+    if not args.no_vi:
+        vi = run_vector_invariant(w, args.steps, args.warmup)
+        print(f"[bench] vector-invariant fp32: {vi['ms_per_step']:.3f} ms/step, stages {vi['stage_ms']}, "
+              f"finite={vi['finite']}", file=sys.stderr, flush=True)
+
     ens = None
     if not args.no_ensemble:
         ens = run_ensemble(args.steps, args.warmup)
@@ -667,6 +701,8 @@ def main():
         line["fp32_speedup_over_fp64"] = r64["ms_per_step"] / main_rec["ms_per_step"]
     if sal is not None:
         line["salinity"] = sal
+    if vi is not None:
+        line["vector_invariant"] = vi
     if ens is not None:
         line["ensemble"] = ens
     line.update(extra)
