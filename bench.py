@@ -132,7 +132,8 @@ def run_ensemble(steps, warmup, n_members=64):
     """64 seeded beta-plane basins of uneven sizes in FP32: batched stepping
     (one launch per stage, graph-replayed, autotuned tiles and schedule)
     against stepping each member alone with the same kernels, each member's
-    step replayed from its own graph; the two schedules of the batched
+    step replayed from its own graph, and against the plain method (each
+    member alone in FP64, graph-replayed); the two schedules of the batched
     launches (one workgroup per tile, persistent workgroups over per-XCD
     queues) at the default tiles; and the autotune cache: a second ensemble of
     the same shape takes the stored choice without timing."""
@@ -177,6 +178,24 @@ def run_ensemble(steps, warmup, n_members=64):
     ens.close()
     del ens
     torch.cuda.empty_cache()
+    # the plain method: each member alone in FP64, its step replayed from its own graph
+    side = torch.cuda.Stream()
+    plain = [ocn.Model(w, "fp64", inputs.make_inputs(w), stream=side) for w in ws]
+    for _ in range(2):
+        for mem in plain:
+            mem.step(1, graph=True)
+    side.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for mem in plain:
+            mem.step(1, graph=True)
+    side.synchronize()
+    plain64 = time.perf_counter() - t0
+    finite = finite and all(mem.diagnostics(allow_unstable=True)["nonfinite"] == 0 for mem in plain)
+    for mem in plain:
+        mem.close()
+    del plain
+    torch.cuda.empty_cache()
     ens2 = ocn.Ensemble(ws, "fp32")
     t0 = time.perf_counter()
     again = ens2.autotune(trial_steps=2, cache=cache)
@@ -191,6 +210,8 @@ def run_ensemble(steps, warmup, n_members=64):
             "sequential_cell_updates_per_s": cells * steps / sequential,
             "speedup_batched_over_sequential": sequential / batched,
             "sequential_mode": "each member replayed from its own captured graph",
+            "plain_fp64_sequential_ms_per_step": plain64 / steps * 1e3,
+            "speedup_batched_fp32_over_plain_fp64": plain64 / batched,
             "schedules_ms_per_step_default_tiles": schedules,
             "autotune": tune, "autotune_cache_second_ensemble": again,
             "finite": finite, "max_abs_u": max(d["max_abs_u"] for d in diags)}
@@ -316,6 +337,7 @@ def run_quarter(steps, warmup):
     cl_ms = st["closure"] / max(n, 1)
     out["closure"] = {"network": [din, h, h, dout], "ms_per_step": el / steps * 1e3,
                       "closure_stage_ms": cl_ms, "slowdown_vs_constant_kappa": (el / steps * 1e3) / out["fp32"]["ms_per_step"],
+                      "speedup_over_plain_fp64": out["fp64"]["ms_per_step"] / (el / steps * 1e3),
                       "network_tflops_in_closure_stage": gemm_flops / (cl_ms * 1e-3) / 1e12,
                       "finite": dg["nonfinite"] == 0, "max_abs_u": dg["max_abs_u"]}
     # Richardson-number mixing: viscosity and diffusivity diagnosed from the state every step
@@ -646,7 +668,9 @@ def main():
     if not args.no_ensemble:
         ens = run_ensemble(args.steps, args.warmup)
         print(f"[bench] ensemble: batched {ens['batched_ms_per_step']:.3f} ms/step, sequential "
-              f"{ens['sequential_ms_per_step']:.3f} ms/step, tiles {ens['autotune']}", file=sys.stderr, flush=True)
+              f"{ens['sequential_ms_per_step']:.3f} ms/step, plain FP64 one by one "
+              f"{ens['plain_fp64_sequential_ms_per_step']:.3f} ms/step, tiles {ens['autotune']}",
+              file=sys.stderr, flush=True)
 
     extra = {}
     if not args.no_extra:
