@@ -19,6 +19,10 @@ make the internal waves fastest relative to the grid, and a ridge crest with
 land. Both sides start from the same inputs; nothing the GPU computed enters
 the oracle.
 
+The same check covers the variants at 1/12 degree (salinity with the
+quadratic equation of state together with vector-invariant momentum
+advection) on three of the samples.
+
 Stability: 100 steps of the whole 1/12-degree grid and 200 of the 1/4-degree
 grid stay finite with bounded velocities and free surface, in both precisions.
 """
@@ -42,6 +46,12 @@ SAMPLES = {
     TWELFTH.name: [(100, 900), (2160, 300), (4300, 1500), (1800, 60), (1080, 900)],
     QUARTER.name: [(720, 30), (0, 412), (1100, 560)],
 }
+# grids by key: the two lat-lon workloads, and the 1/12-degree one with salinity
+# and vector-invariant momentum
+VARIANT = TWELFTH.name + "+salinity+vector_invariant"
+GRIDS = {TWELFTH.name: TWELFTH, QUARTER.name: QUARTER,
+         VARIANT: TWELFTH.replace(salinity=True, momentum_form="vector_invariant")}
+SAMPLES[VARIANT] = [(2160, 300), (1800, 60), (1080, 900)]
 
 
 def _window(W, ic, jc):
@@ -55,9 +65,13 @@ def _window(W, ic, jc):
 
 
 @functools.lru_cache(maxsize=2)
-def _inputs(name):
-    print(f"full-size {name}: inputs", flush=True)
-    return inputs.make_inputs(inputs.WORKLOADS[name])
+def _inputs(key):
+    print(f"full-size {key}: inputs", flush=True)
+    return inputs.make_inputs(GRIDS[key])
+
+
+def _fields(W):
+    return ("u", "v", "T", "eta", "U", "V") + (("S",) if W.salinity else ())
 
 
 def _oracle_window(args):
@@ -67,40 +81,47 @@ def _oracle_window(args):
     for n, a in fields.items():
         ref.set(n, a)
     ref.step(STEPS)
-    out = {n: ref.get(n)[..., jcw - P:jcw + P + 1, R - P:R + P + 1] for n in ("u", "v", "T", "eta", "U", "V")}
+    out = {n: ref.get(n)[..., jcw - P:jcw + P + 1, R - P:R + P + 1] for n in _fields(win)}
     ref.close()
     return out
 
 
 @functools.lru_cache(maxsize=None)
-def _oracle_patches(name):
+def _oracle_patches(key):
     """The oracle's centre patches of every sample of a grid (shared by both precisions)."""
     import concurrent.futures as cf
 
-    W = inputs.WORKLOADS[name]
-    inp = _inputs(name)
+    W = GRIDS[key]
+    inp = _inputs(key)
     jobs = []
-    for ic, jc in SAMPLES[name]:
+    for ic, jc in SAMPLES[key]:
         win, sub, jcw = _window(W, ic, jc)
         print(f"  oracle window {win.nx}x{win.ny}x{win.nz} around ({ic},{jc})", flush=True)
         fields = {"T": sub(inp["T0"]), "taux": sub(inp["taux"]), "tauy": sub(inp["tauy"]), "tstar": sub(inp["tstar"])}
+        if W.salinity:
+            fields.update(S=sub(inp["S0"]), sstar=sub(inp["sstar"]))
         jobs.append((win, inp["dz"], sub(inp["kbottom"]), fields, jcw))
     with cf.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
-        return dict(zip(SAMPLES[name], ex.map(_oracle_window, jobs)))
+        return dict(zip(SAMPLES[key], ex.map(_oracle_window, jobs)))
 
 
-def _check(W, precision, tol):
+def _check(key, precision, tol):
     from paper_2309_06662_amd import ocn
 
-    ref_all = _oracle_patches(W.name)
-    inp = _inputs(W.name)
+    W = GRIDS[key]
+    ref_all = _oracle_patches(key)
+    inp = _inputs(key)
     gpu = ocn.Model(W, precision, inp)
-    print(f"full-size {W.name} {precision}: {STEPS} steps on the GPU", flush=True)
+    print(f"full-size {key} {precision}: {STEPS} steps on the GPU", flush=True)
     gpu.step(STEPS)
-    got_all = {n: gpu.get(n) for n in ("u", "v", "T", "eta", "U", "V")}
+    got_all = {n: gpu.get(n) for n in _fields(W)}
+    gpu.close()
     del gpu
+    import torch
+
+    torch.cuda.empty_cache()  # the next grid's arena is a different size
     worst = 0.0
-    for ic, jc in SAMPLES[W.name]:
+    for ic, jc in SAMPLES[key]:
         _, sub, jcw = _window(W, ic, jc)
         ref = ref_all[(ic, jc)]
         for n, a in got_all.items():
@@ -115,12 +136,17 @@ def _check(W, precision, tol):
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
 def test_fullsize_twelfth_sampled_columns(precision, tol):
-    _check(TWELFTH, precision, tol)
+    _check(TWELFTH.name, precision, tol)
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
 def test_fullsize_quarter_sampled_columns(precision, tol):
-    _check(QUARTER, precision, tol)
+    _check(QUARTER.name, precision, tol)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+def test_fullsize_twelfth_variants_sampled_columns(precision, tol):
+    _check(VARIANT, precision, tol)
 
 
 @pytest.mark.parametrize("name,steps", [(TWELFTH.name, 100), (QUARTER.name, 200)])
@@ -128,7 +154,7 @@ def test_fullsize_quarter_sampled_columns(precision, tol):
 def test_fullsize_long_run_stays_bounded(name, steps, precision):
     from paper_2309_06662_amd import ocn
 
-    W = inputs.WORKLOADS[name]
+    W = GRIDS[name]
     gpu = ocn.Model(W, precision, _inputs(name))
     for done in range(0, steps, 25):
         gpu.step(25)
