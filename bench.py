@@ -27,6 +27,9 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 Counter tooling (for the traffic records under profiles/):
   python bench.py --copy-probe [--mib N]      a plain device copy of known size,
                                               to calibrate FETCH_SIZE / WRITE_SIZE
+  python bench.py --sq-summary --sq1 A --sq2 B --out F
+                                              SQ counter summary (VALU busy, instructions
+                                              per cell) of two counter passes
   python bench.py --pmc-summary ...           per-launch HBM bytes of a kernel from
                                               two counter runs, scaled by the copy's
 """
@@ -585,6 +588,73 @@ def pmc_summary(a):
     print(json.dumps({k: rec[k] for k in ("fetch_scale", "write_scale", "hbm_bytes_per_launch")}))
 
 
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM", "SQ_INSTS_SALU", "SQ_WAIT_INST_ANY",
+               "SQ_BUSY_CYCLES", "SQ_ACTIVE_INST_VALU", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "SQ_WAVE_CYCLES",
+               "SQ_THREAD_CYCLES_VALU", "GRBM_GUI_ACTIVE")
+
+
+def sq_summary(a):
+    """Text summary of two rocprofv3 SQ counter passes (counter_collection.csv
+    of each) for the last dispatch of the tendency, barotropic and column
+    kernels: the counters, VALU and LDS instructions per cell (per
+    column-substep for the barotropic kernel) and VALU busy, taken as
+    SQ_INSTS_VALU x 4 cycles (a wave64 VALU instruction holds a 16-lane SIMD
+    for 4 cycles) over 1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs."""
+    import csv
+
+    def load(path):
+        per = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                key = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+                per.setdefault(key, {})
+                per[key][r["Counter_Name"]] = per[key].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        return per
+
+    w = inputs.WORKLOADS[a.workload]
+    cells, cols = w.nx * w.ny * w.nz, w.nx * w.ny
+    p1, p2 = load(a.sq1), load(a.sq2)
+    # a run of both precisions steps FP32 first: the FP64 dispatches start at
+    # the first FP64 tendency launch
+    for p in (p1, p2):
+        split = min([k[0] for k in p if "ocn::k_tend<double" in k[1]] or [1 << 62])
+        for k in list(p):
+            if (k[0] >= split) != (a.precision == "fp64"):
+                del p[k]
+    lines = [f"# rocprofv3 SQ counters of the last dispatch of each kernel, {a.precision.upper()} step of {w.name}"]
+    lines += [f"# command: {c}" for c in a.command]
+    lines += ["# VALU busy = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs); per-cell figures",
+              "# are instructions x 64 lanes / cells (columns x substeps for the barotropic kernel)", ""]
+    for part in ("ocn::k_tend<", "ocn::k_baro_fused<", "ocn::k_column<"):
+        sel = lambda p: sorted(k for k in p if part in k[1])
+        if part == "ocn::k_baro_fused<":  # the launches of the full substep count, not a step's shorter last one
+            depth = lambda k: int(k[1].split("<")[1].split(">")[0].split(",")[2])
+            sel = lambda p, _s=sel: [k for k in _s(p) if depth(k) == max(map(depth, _s(p)))]
+        k1, k2 = sel(p1), sel(p2)
+        if not (k1 and k2):
+            continue
+        c = dict(p1[k1[-1]])
+        c.update(p2[k2[-1]])
+        name = k1[-1][1].split("(")[0]
+        if part == "ocn::k_baro_fused<":
+            sh = int(name.split("<")[1].split(">")[0].split(",")[2])
+            n, unit = cols * sh, "column-substep"
+        else:
+            n, unit = cells, "cell"
+        cyc = c["GRBM_GUI_ACTIVE"] / 8
+        lines.append(f"{name} (dispatch {k1[-1][0]}/{k2[-1][0]}): {cyc:.0f} cycles per XCD "
+                     f"({cyc / 2.4e9 * 1e3:.2f} ms at 2.4 GHz)")
+        lines += [f"  {k:24s} {c[k]:.4e}" for k in SQ_COUNTERS if k in c]
+        lines.append(f"  VALU lane-instructions per {unit}: {c['SQ_INSTS_VALU'] * 64 / n:.0f}; LDS per {unit}: "
+                     f"{c['SQ_INSTS_LDS'] * 64 / n:.1f}; SALU/VALU {c['SQ_INSTS_SALU'] / c['SQ_INSTS_VALU']:.2f}")
+        lines.append(f"  VALU busy {c['SQ_INSTS_VALU'] * 4 / (1024 * cyc):.2f}; LDS bank-conflict cycles / LDS active "
+                     f"cycles {c['SQ_LDS_BANK_CONFLICT'] / max(c['SQ_LDS_IDX_ACTIVE'], 1):.3f}; waves {c['SQ_WAVES']:.0f}")
+        lines.append("")
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -603,6 +673,9 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="run the counter-calibration copy and exit")
     ap.add_argument("--mib", type=int, default=1024, help="copy probe: size of each buffer in MiB")
     ap.add_argument("--pmc-summary", action="store_true", help="write a kernel's traffic record and exit")
+    ap.add_argument("--sq-summary", action="store_true", help="write the SQ counter summary of two passes and exit")
+    ap.add_argument("--sq1", help="sq summary: counter_collection.csv of the first pass")
+    ap.add_argument("--sq2", help="sq summary: counter_collection.csv of the second pass")
     ap.add_argument("--kernel", default="k_tend", choices=sorted(KERNEL_SOURCES))
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--fetch")
@@ -624,6 +697,9 @@ def main():
         return
     if args.pmc_summary:
         pmc_summary(argparse.Namespace(**{**vars(args), "workload": args.workload}))
+        return
+    if args.sq_summary:
+        sq_summary(args)
         return
 
     if args.gpus != 1:
