@@ -27,6 +27,8 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 Counter tooling (for the traffic records under profiles/):
   python bench.py --copy-probe [--mib N]      a plain device copy of known size,
                                               to calibrate FETCH_SIZE / WRITE_SIZE
+  python bench.py --stats-summary --stats-dir D --out F
+                                              kernel table of a --kernel-trace --stats run
   python bench.py --sq-summary --sq1 A --sq2 B --out F
                                               SQ counter summary (VALU busy, instructions
                                               per cell) of two counter passes
@@ -655,6 +657,38 @@ def sq_summary(a):
     print("\n".join(lines))
 
 
+def stats_summary(a):
+    """Text summary of a rocprofv3 --kernel-trace --stats run: the per-kernel
+    table (microseconds) and the duration of every tendency launch, with the
+    mean of the steady ones (the first launch of a run is the forward-Euler
+    start step)."""
+    import csv
+
+    rows = list(csv.DictReader(open(os.path.join(a.stats_dir, "run_kernel_stats.csv"))))
+    lines = [f"# rocprofv3 kernel summary of {a.workload} (durations in microseconds)"]
+    lines += [f"# command: {c}" for c in a.command]
+    lines.append(f"{'kernel':72s} {'calls':>6s} {'total_us':>12s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}")
+    for r in rows:
+        name = r["Name"][:72]
+        lines.append(f"{name:72s} {int(r['Calls']):6d} {float(r['TotalDurationNs']) / 1e3:12.1f} "
+                     f"{float(r['AverageNs']) / 1e3:10.1f} {float(r['MinNs']) / 1e3:10.1f} "
+                     f"{float(r['MaxNs']) / 1e3:10.1f} {float(r['Percentage']):6.2f}")
+    per = {}
+    for r in csv.DictReader(open(os.path.join(a.stats_dir, "run_kernel_trace.csv"))):
+        if "ocn::k_tend<" in r["Kernel_Name"]:
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            per.setdefault(name, []).append((int(r["Dispatch_Id"]),
+                                             (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
+    for name, calls in per.items():
+        us = [d for _, d in sorted(calls)]
+        steady = us[1:] or us
+        lines.append(f"# {name} per call: {', '.join(f'{d:.1f}' for d in us)}; steady (AB2) mean "
+                     f"{sum(steady) / len(steady):.1f} us")
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -674,6 +708,8 @@ def main():
     ap.add_argument("--mib", type=int, default=1024, help="copy probe: size of each buffer in MiB")
     ap.add_argument("--pmc-summary", action="store_true", help="write a kernel's traffic record and exit")
     ap.add_argument("--sq-summary", action="store_true", help="write the SQ counter summary of two passes and exit")
+    ap.add_argument("--stats-summary", action="store_true", help="write the kernel summary of a --stats run and exit")
+    ap.add_argument("--stats-dir", help="stats summary: the rocprofv3 output directory")
     ap.add_argument("--sq1", help="sq summary: counter_collection.csv of the first pass")
     ap.add_argument("--sq2", help="sq summary: counter_collection.csv of the second pass")
     ap.add_argument("--kernel", default="k_tend", choices=sorted(KERNEL_SOURCES))
@@ -700,6 +736,9 @@ def main():
         return
     if args.sq_summary:
         sq_summary(args)
+        return
+    if args.stats_summary:
+        stats_summary(args)
         return
 
     if args.gpus != 1:
