@@ -34,6 +34,11 @@ library's own runs:
    coarse-grained truth at the end, the RMSE over valid columns of the
    mixed-layer depth (first depth where T falls 0.2 K below the top layer)
    and of the change in column heat content sum dz T are reported for both.
+6. Optionally (basin_eval), the trained network runs on the whole 1/4-degree
+   basin, whose grid spacing, levels and time step the training box shares,
+   beside the constant diffusivity and the fine run's own parameterization,
+   which stands in for a finer truth of the whole basin; the time per step of
+   each run is the closure's cost with trained weights.
 
     python -m paper_2309_06662_amd.closure_train --out DIR [--days 20 --eval-days 4 ...]
 """
@@ -163,10 +168,78 @@ def _log(msg):
     print(f"[closure] {msg}", flush=True)
 
 
+def attach_mixing(model, mixing, convective):
+    """The fine run's mixing parameterization on a model."""
+    model.attach_closure()
+    if mixing == "richardson":
+        model.set_richardson(conv=convective)
+    else:
+        model.set_convective(convective)
+
+
+def basin_eval(net, norm, mixing, convective, days, w=None, band=None):
+    """The trained network on the whole 1/4-degree basin (1440 x 600 x 50, the
+    training box's grid spacing, levels and time step), from the seeded
+    initial state for `days`: FP32 runs with the constant diffusivity, with the
+    network, and with the fine run's own mixing parameterization at this
+    resolution. No finer truth of the whole basin is run; the physical
+    parameterization stands in for it: the mixed-layer depth and column heat
+    content of the constant and learned runs are compared with it (RMSE over
+    ocean columns, and over the ocean columns of the latitude band `band` =
+    (south, north) in degrees, the training box's), and each run's time per
+    step is reported (the learned one is the closure's cost with trained
+    weights)."""
+    import torch
+
+    from . import ocn
+
+    w = inputs.LATLON_QUARTER if w is None else w
+    inp = inputs.make_inputs(w)
+    dz, ocean = inp["dz"], inp["kbottom"] > 0
+    steps = int(round(days * 86400.0 / w.dt))
+    out, T_end = {"workload": w.name, "days": days, "steps": steps, "comparator": mixing}, {}
+    for mode in ("constant", "learned", mixing):
+        m = ocn.Model(w, "fp32", inp)
+        if mode == "learned":
+            m.attach_closure(net, norm)
+        elif mode == mixing:
+            attach_mixing(m, mixing, convective)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.step(steps)
+        m.synchronize()
+        el = time.perf_counter() - t0
+        T_end[mode] = m.get("T")
+        d = m.diagnostics(allow_unstable=True)
+        out[mode] = {"ms_per_step": el / steps * 1e3, "finite": d["nonfinite"] == 0}
+        if mode != "constant":
+            m.detach_closure()
+        m.close()
+        torch.cuda.empty_cache()
+    ref = T_end[mixing]
+    mld_ref, hc_ref = mixed_layer_depth(ref, dz), heat_content(ref, dz)
+    lat = w.y0 + (np.arange(w.ny) + 0.5) * w.dy
+    regions = {"": ocean}
+    if band is not None:
+        regions["_band"] = ocean & ((lat >= band[0]) & (lat <= band[1]))[:, None]
+        out["band_deg"] = list(band)
+    for mode in ("constant", "learned"):
+        mld_err = mixed_layer_depth(T_end[mode], dz) - mld_ref
+        hc_err = heat_content(T_end[mode], dz) - hc_ref
+        for suffix, cols in regions.items():
+            out[mode]["mld_rmse_vs_comparator_m" + suffix] = float(np.sqrt(np.mean(mld_err[cols] ** 2)))
+            out[mode]["heat_content_rmse_vs_comparator_Km" + suffix] = float(np.sqrt(np.mean(hc_err[cols] ** 2)))
+    out["comparator_mld_mean_m"] = float(np.mean(mld_ref[ocean]))
+    _log(f"basin: {json.dumps(out)}")
+    return out
+
+
 def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_samples=2, epochs=60,
-        batch=4096, lr=1e-3, hidden=128, seed=0, convective=1.0, coarse_kw=None, mixing="convective"):
+        batch=4096, lr=1e-3, hidden=128, seed=0, convective=1.0, coarse_kw=None, mixing="convective",
+        basin_days=0.0):
     """mixing: the fine run's parameterization, "convective" (kappa = convective where
-    N^2 < 0) or "richardson" (Richardson-number mixing with its default constants)."""
+    N^2 < 0) or "richardson" (Richardson-number mixing with its default constants).
+    basin_days > 0 adds basin_eval of the trained network over that many days."""
     if mixing not in ("convective", "richardson"):
         raise ValueError("mixing must be 'convective' or 'richardson'")
     import torch
@@ -183,17 +256,10 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
     _log(f"coarse {coarse.nx}x{coarse.ny}x{nz}, fine {fine.nx}x{fine.ny}x{nz}, "
          f"{int(cg.valid_col.sum())} fully resolved coarse columns, mixing {mixing}, convective {convective}")
 
-    def attach_mixing(model):
-        model.attach_closure()
-        if mixing == "richardson":
-            model.set_richardson(conv=convective)
-        else:
-            model.set_convective(convective)
-
     mixed = mixing == "richardson" or convective > 0.0
     fm = ocn.Model(fine, "fp32", inp_f)
     if mixed:
-        attach_mixing(fm)
+        attach_mixing(fm, mixing, convective)
     cm = ocn.Model(coarse, "fp32", inp_c)   # holds coarse-grained states for the features
 
     steps_per_sample = max(1, int(round(sample_hours * 3600.0 / fine.dt)))
@@ -291,7 +357,7 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
         if mode == "learned":
             m.attach_closure(net, norm)
         elif mode == mixing:
-            attach_mixing(m)
+            attach_mixing(m, mixing, convective)
         m.step(eval_steps)
         T_end = m.get("T")
         d = m.diagnostics(allow_unstable=True)
@@ -312,6 +378,9 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
               "truth_heat_content_drift_rms_Km": float(np.sqrt(np.mean(truth_drift[vc] ** 2))),
               "truth_mld_mean_m": float(np.mean(mixed_layer_depth(truth["T"], dz)[vc])),
               "eval": results}
+    if basin_days > 0:
+        report["basin"] = basin_eval(net, norm, mixing, convective, basin_days,
+                                     band=(coarse.y0, coarse.y0 + coarse.ny * coarse.dy))
     with open(os.path.join(out_dir, "closure_report.json"), "w") as f:
         json.dump(report, f, indent=1)
     np.save(os.path.join(out_dir, "closure_params.npy"), net.get_params())
@@ -335,10 +404,12 @@ def main():
     ap.add_argument("--convective", type=float, default=1.0, help="kappa where N^2 < 0 in the fine run (0: off)")
     ap.add_argument("--mixing", choices=("convective", "richardson"), default="convective",
                     help="the fine run's mixing parameterization")
+    ap.add_argument("--basin-days", type=float, default=0.0,
+                    help="also run the trained network on the whole 1/4-degree basin for this many days")
     a = ap.parse_args()
     run(a.out, factor=a.factor, days=a.days, eval_days=a.eval_days, sample_hours=a.sample_hours,
         window_samples=a.window, epochs=a.epochs, convective=a.convective,
-        coarse_kw={"nx": a.nx, "ny": a.ny, "nz": a.nz}, mixing=a.mixing)
+        coarse_kw={"nx": a.nx, "ny": a.ny, "nz": a.nz}, mixing=a.mixing, basin_days=a.basin_days)
 
 
 if __name__ == "__main__":
