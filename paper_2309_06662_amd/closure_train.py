@@ -234,28 +234,21 @@ def basin_eval(net, norm, mixing, convective, days, w=None, band=None):
     return out
 
 
-def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_samples=2, epochs=60,
-        batch=4096, lr=1e-3, hidden=128, seed=0, convective=1.0, coarse_kw=None, mixing="convective",
-        basin_days=0.0):
-    """mixing: the fine run's parameterization, "convective" (kappa = convective where
-    N^2 < 0) or "richardson" (Richardson-number mixing with its default constants).
-    basin_days > 0 adds basin_eval of the trained network over that many days."""
-    if mixing not in ("convective", "richardson"):
-        raise ValueError("mixing must be 'convective' or 'richardson'")
-    import torch
-
+def _box_samples(coarse, fine, factor, mixing, convective, days, eval_days, sample_hours, window_samples, din,
+                 collect=True):
+    """The fine run of one box. Returns its training pairs (features X and
+    log10 kappa targets Y of the fully resolved coarse columns, for the
+    windows before the held-out period; empty when collect is false), the
+    coarse-grained states at the start and at the end of the held-out period,
+    the coarse inputs and the coarse-grainer."""
     from . import ocn
 
-    os.makedirs(out_dir, exist_ok=True)
-    coarse, fine = regional_pair(factor=factor, **(coarse_kw or {}))
     inp_c, inp_f = inputs.make_inputs(coarse), inputs.make_inputs(fine)
     dz = inp_c["dz"]
     cg = CoarseGrainer(coarse, fine, inp_f["kbottom"], inp_c["kbottom"], factor)
     nz = coarse.nz
-    din = (4 * nz + 3 + 7) // 8 * 8
-    _log(f"coarse {coarse.nx}x{coarse.ny}x{nz}, fine {fine.nx}x{fine.ny}x{nz}, "
+    _log(f"box {coarse.x0:.1f}E {coarse.y0:.1f}N: coarse {coarse.nx}x{coarse.ny}x{nz}, fine {fine.nx}x{fine.ny}x{nz}, "
          f"{int(cg.valid_col.sum())} fully resolved coarse columns, mixing {mixing}, convective {convective}")
-
     mixed = mixing == "richardson" or convective > 0.0
     fm = ocn.Model(fine, "fp32", inp_f)
     if mixed:
@@ -286,19 +279,19 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
         if s % window_samples == 0:
             flux_w = acc / window_samples
             acc = None
-            y = kappa_target(flux_w, start_state["T"], dz, coarse.kappa)
-            kwet = np.zeros((nz, coarse.ny, coarse.nx), bool)           # wet interior faces
-            kk = np.arange(nz)[:, None, None]
-            kwet[1:] = (kk[1:] > nz - inp_c["kbottom"][None])
-            y = np.where(kwet, y, math.log10(coarse.kappa))
-            for n in ("u", "v", "T"):
-                cm.set(n, start_state[n])
-            start_state = None
-            X = cm.closure_features(din).cpu().numpy()
-            cols = cg.valid_col.reshape(-1)
-            if s <= eval_start:
+            if collect and s <= eval_start:
+                y = kappa_target(flux_w, start_state["T"], dz, coarse.kappa)
+                kwet = np.zeros((nz, coarse.ny, coarse.nx), bool)           # wet interior faces
+                kk = np.arange(nz)[:, None, None]
+                kwet[1:] = (kk[1:] > nz - inp_c["kbottom"][None])
+                y = np.where(kwet, y, math.log10(coarse.kappa))
+                for n in ("u", "v", "T"):
+                    cm.set(n, start_state[n])
+                X = cm.closure_features(din).cpu().numpy()
+                cols = cg.valid_col.reshape(-1)
                 X_list.append(X[cols])
                 Y_list.append(y.reshape(nz, -1).T[cols])
+            start_state = None
         if s in (eval_start, n_samples):
             snaps[s] = st
         if s % 8 == 0:
@@ -308,47 +301,25 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
             if d["nonfinite"]:
                 raise RuntimeError("the fine run became non-finite")
     fm.close()
+    cm.close()
+    return X_list, Y_list, (snaps[eval_start], snaps[n_samples]), inp_c, cg
 
-    X = np.concatenate(X_list).astype(np.float64)
-    Y = np.concatenate(Y_list).astype(np.float64)
-    wet = X != 0
-    mean = np.array([X[:, f][wet[:, f]].mean() if wet[:, f].any() else 0.0 for f in range(din)])
-    std = np.array([X[:, f][wet[:, f]].std() if wet[:, f].any() else 1.0 for f in range(din)])
-    std[~(std > 1e-12)] = 1.0
-    Xn = np.where(wet, (X - mean) / std, 0.0).astype(np.float32)
-    _log(f"training set: {len(Xn)} columns, target log10 kappa mean {Y.mean():.2f} sd {Y.std():.2f}")
 
-    rng = np.random.default_rng(seed)
-    P = [rng.normal(size=(din, hidden)) * math.sqrt(2.0 / din), np.zeros(hidden),
-         rng.normal(size=(hidden, hidden)) * math.sqrt(2.0 / hidden), np.zeros(hidden),
-         rng.normal(size=(hidden, nz)) * math.sqrt(1.0 / hidden), np.full(nz, float(Y.mean()))]
-    net = ocn.Mlp(din, hidden, hidden, nz, max_batch=max(batch, coarse.nx * coarse.ny))
-    net.set_params(np.concatenate([p.reshape(-1) for p in P]).astype(np.float32))
-    xd = torch.from_numpy(Xn).cuda()
-    yd = torch.from_numpy(Y.astype(np.float32)).cuda()
-    n = len(Xn)
-    losses = []
-    for ep in range(epochs):
-        perm = torch.from_numpy(rng.permutation(n)).cuda()
-        tot, cnt = 0.0, 0
-        for b0 in range(0, n - batch + 1 if n >= batch else 1, batch):
-            idx = perm[b0:b0 + batch]
-            loss = net.train_step(xd[idx].contiguous(), yd[idx].contiguous(), lr)
-            tot += loss
-            cnt += 1
-        losses.append(tot / max(cnt, 1))
-    _log(f"training loss {losses[0]:.4f} -> {losses[-1]:.4f} over {epochs} epochs")
-    # baseline loss of predicting log10(kappa0) everywhere, for scale
-    base = 0.5 * float(np.mean((Y - math.log10(coarse.kappa)) ** 2))
+def _evaluate(coarse, inp_c, cg, snaps, net, norm, mixing, convective, eval_days):
+    """From the coarse-grained state at the start of the held-out period, the
+    coarse model with the constant diffusivity, with the network and with the
+    fine run's parameterization; RMSE of the mixed-layer depth and of the
+    change of column heat content against the coarse-grained truth at the
+    end, over the fully resolved columns."""
+    from . import ocn
 
-    # ---- evaluation from the start of the held-out period ----
-    start, truth = snaps[eval_start], snaps[n_samples]
+    dz = inp_c["dz"]
+    start, truth = snaps
     eval_steps = int(round(eval_days * 86400.0 / coarse.dt))
-    norm = np.concatenate([mean, std]).astype(np.float32)
+    mixed = mixing == "richardson" or convective > 0.0
     results = {}
     vc = cg.valid_col
-    modes = ("constant", "learned", mixing) if mixed else ("constant", "learned")
-    for mode in modes:
+    for mode in (("constant", "learned", mixing) if mixed else ("constant", "learned")):
         m = ocn.Model(coarse, "fp32", inp_c)
         for n_ in ("u", "v", "T", "eta"):
             m.set(n_, start[n_])
@@ -371,13 +342,99 @@ def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_sa
             m.detach_closure()
         m.close()
     truth_drift = heat_content(truth["T"], dz) - heat_content(start["T"], dz)
-    report = {"coarse": coarse.name, "fine": fine.name, "factor": factor, "days": days, "eval_days": eval_days,
-              "mixing": mixing, "convective_kappa": convective,
-              "train_columns": int(n), "din": din, "hidden": hidden, "epochs": epochs,
-              "loss_first": losses[0], "loss_last": losses[-1], "loss_constant_kappa": base,
-              "truth_heat_content_drift_rms_Km": float(np.sqrt(np.mean(truth_drift[vc] ** 2))),
-              "truth_mld_mean_m": float(np.mean(mixed_layer_depth(truth["T"], dz)[vc])),
-              "eval": results}
+    results["truth_heat_content_drift_rms_Km"] = float(np.sqrt(np.mean(truth_drift[vc] ** 2)))
+    results["truth_mld_mean_m"] = float(np.mean(mixed_layer_depth(truth["T"], dz)[vc]))
+    return results
+
+
+def run(out_dir, factor=4, days=20.0, eval_days=4.0, sample_hours=3.0, window_samples=2, epochs=60,
+        batch=4096, lr=1e-3, hidden=128, seed=0, convective=1.0, coarse_kw=None, mixing="convective",
+        basin_days=0.0, boxes=None, eval_box=None):
+    """mixing: the fine run's parameterization, "convective" (kappa = convective where
+    N^2 < 0) or "richardson" (Richardson-number mixing with its default constants).
+    boxes: south-west corners (lon, lat in degrees) of the training boxes (default
+    the one of coarse_kw, else 150E 60S); the first is also evaluated over its
+    held-out period. eval_box: the corner of a box left out of training, whose
+    own fine run is the truth of a second evaluation over the same period.
+    basin_days > 0 adds basin_eval of the trained network over that many days."""
+    if mixing not in ("convective", "richardson"):
+        raise ValueError("mixing must be 'convective' or 'richardson'")
+    import torch
+
+    from . import ocn
+
+    os.makedirs(out_dir, exist_ok=True)
+    kw = dict(coarse_kw or {})
+    if boxes is None:
+        boxes = [(kw.pop("lon0", 150.0), kw.pop("lat0", -60.0))]
+    else:
+        kw.pop("lon0", None)
+        kw.pop("lat0", None)
+    pairs = [regional_pair(factor=factor, lon0=lo, lat0=la, **kw) for lo, la in boxes]
+    coarse = pairs[0][0]
+    nz = coarse.nz
+    din = (4 * nz + 3 + 7) // 8 * 8
+    args = (factor, mixing, convective, days, eval_days, sample_hours, window_samples, din)
+    X_list, Y_list, first = [], [], None
+    for c, f in pairs:
+        xl, yl, snaps, inp_c, cg = _box_samples(c, f, *args)
+        X_list += xl
+        Y_list += yl
+        if first is None:
+            first = (c, inp_c, cg, snaps)
+    held = None
+    if eval_box is not None:
+        c, f = regional_pair(factor=factor, lon0=eval_box[0], lat0=eval_box[1], **kw)
+        _, _, snaps, inp_c, cg = _box_samples(c, f, *args, collect=False)
+        held = (c, inp_c, cg, snaps)
+
+    X = np.concatenate(X_list).astype(np.float64)
+    Y = np.concatenate(Y_list).astype(np.float64)
+    wet = X != 0
+    mean = np.array([X[:, f][wet[:, f]].mean() if wet[:, f].any() else 0.0 for f in range(din)])
+    std = np.array([X[:, f][wet[:, f]].std() if wet[:, f].any() else 1.0 for f in range(din)])
+    std[~(std > 1e-12)] = 1.0
+    Xn = np.where(wet, (X - mean) / std, 0.0).astype(np.float32)
+    _log(f"training set: {len(Xn)} columns from {len(pairs)} boxes, target log10 kappa mean {Y.mean():.2f} "
+         f"sd {Y.std():.2f}")
+
+    rng = np.random.default_rng(seed)
+    P = [rng.normal(size=(din, hidden)) * math.sqrt(2.0 / din), np.zeros(hidden),
+         rng.normal(size=(hidden, hidden)) * math.sqrt(2.0 / hidden), np.zeros(hidden),
+         rng.normal(size=(hidden, nz)) * math.sqrt(1.0 / hidden), np.full(nz, float(Y.mean()))]
+    net = ocn.Mlp(din, hidden, hidden, nz, max_batch=max(batch, max(c.nx * c.ny for c, _ in pairs)))
+    net.set_params(np.concatenate([p.reshape(-1) for p in P]).astype(np.float32))
+    xd = torch.from_numpy(Xn).cuda()
+    yd = torch.from_numpy(Y.astype(np.float32)).cuda()
+    n = len(Xn)
+    losses = []
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(n)).cuda()
+        tot, cnt = 0.0, 0
+        for b0 in range(0, n - batch + 1 if n >= batch else 1, batch):
+            idx = perm[b0:b0 + batch]
+            loss = net.train_step(xd[idx].contiguous(), yd[idx].contiguous(), lr)
+            tot += loss
+            cnt += 1
+        losses.append(tot / max(cnt, 1))
+    _log(f"training loss {losses[0]:.4f} -> {losses[-1]:.4f} over {epochs} epochs")
+    # baseline loss of predicting log10(kappa0) everywhere, for scale
+    base = 0.5 * float(np.mean((Y - math.log10(coarse.kappa)) ** 2))
+
+    # ---- evaluation from the start of the held-out period ----
+    norm = np.concatenate([mean, std]).astype(np.float32)
+    c0, inp0, cg0, snaps0 = first
+    ev = _evaluate(c0, inp0, cg0, snaps0, net, norm, mixing, convective, eval_days)
+    report = {"coarse": coarse.name, "fine": pairs[0][1].name, "factor": factor, "days": days,
+              "eval_days": eval_days, "mixing": mixing, "convective_kappa": convective,
+              "boxes": [list(b) for b in boxes], "train_columns": int(n), "din": din, "hidden": hidden,
+              "epochs": epochs, "loss_first": losses[0], "loss_last": losses[-1], "loss_constant_kappa": base,
+              "truth_heat_content_drift_rms_Km": ev.pop("truth_heat_content_drift_rms_Km"),
+              "truth_mld_mean_m": ev.pop("truth_mld_mean_m"), "eval": ev}
+    if held is not None:
+        report["eval_box"] = list(eval_box)
+        report["eval_region"] = _evaluate(*held, net, norm, mixing, convective, eval_days)
+        _log(f"held-out region: {json.dumps(report['eval_region'])}")
     if basin_days > 0:
         report["basin"] = basin_eval(net, norm, mixing, convective, basin_days,
                                      band=(coarse.y0, coarse.y0 + coarse.ny * coarse.dy))
