@@ -236,7 +236,10 @@ void ocn_state_destroy(ocn_state* state);
 int ocn_set_field(ocn_state* state, int32_t field, const double* host, size_t count);
 int ocn_get_field(ocn_state* state, int32_t field, double* host, size_t count);
 
-/* AB2 start flag: 1 makes the next step forward Euler (paper Sec. 5.2 AB2). */
+/* AB2 start flag: 1 makes the next step forward Euler (paper Sec. 5.2 AB2).
+ * A new state starts with it set. Setting fields leaves it as it is, so that
+ * a caller can restore a state together with its AB2 histories; a caller
+ * that replaces u, v or T without their histories sets it to 1. */
 int ocn_set_first_step(ocn_state* state, int32_t first);
 int ocn_get_first_step(ocn_state* state, int32_t* first);
 
