@@ -393,12 +393,14 @@ def tuning_key(precision: str, workloads) -> str:
 
 
 def autotune_cache_load(path: str) -> dict:
-    """Autotuned choices stored in a JSON file (empty if it does not exist)."""
+    """Autotuned choices stored in a JSON file (empty if it does not exist or
+    does not hold a JSON object: the tuner then times the choices again and
+    the next store rewrites the file)."""
     try:
         with open(path) as f:
             data = json.load(f)
         return data if isinstance(data, dict) else {}
-    except FileNotFoundError:
+    except (FileNotFoundError, ValueError):
         return {}
 
 
@@ -483,7 +485,7 @@ class Ensemble:
         key = self.tuning_key()
         if cache is not None:
             hit = autotune_cache_load(cache).get(key)
-            if hit is not None:
+            if isinstance(hit, dict) and all(isinstance(hit.get(k), int) for k in ("tend_rows", "baro_fuse")):
                 self.set_tiles(hit["tend_rows"], hit["baro_fuse"], hit.get("persistent", 0))
                 return dict(hit, cached=True)
         r, f, p, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()

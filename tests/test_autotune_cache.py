@@ -27,3 +27,13 @@ def test_cache_round_trip(tmp_path):
     assert got == {"k1": a, "k2": b}
     ocn.autotune_cache_store(path, "k1", b)
     assert ocn.autotune_cache_load(path) == {"k1": b, "k2": b}
+
+
+def test_unreadable_cache_reads_as_empty(tmp_path):
+    path = tmp_path / "autotune.json"
+    path.write_text('{"fp32|nz=32": {"tend_rows": 8,')   # cut off mid-write
+    assert ocn.autotune_cache_load(str(path)) == {}
+    ocn.autotune_cache_store(str(path), "k", {"tend_rows": 4, "baro_fuse": 6, "persistent": 0})
+    assert ocn.autotune_cache_load(str(path)) == {"k": {"tend_rows": 4, "baro_fuse": 6, "persistent": 0}}
+    path.write_text("[1, 2]")                                  # valid JSON, not an object
+    assert ocn.autotune_cache_load(str(path)) == {}
