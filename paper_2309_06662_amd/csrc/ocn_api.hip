@@ -235,6 +235,12 @@ bool valid_params(const ocn_params* p, std::string& why) {
     if (!(p->dt > 0.0) || !std::isfinite(p->dt)) { why = "dt must be positive"; return false; }
     if (!(p->kappa >= 0.0)) { why = "kappa must be >= 0"; return false; }
     if (!(p->rho0 > 0.0)) { why = "rho0 must be positive"; return false; }
+    if (!(p->g > 0.0)) { why = "g must be positive"; return false; }
+    {
+        const double v[] = {p->chi, p->g, p->alpha, p->rho0, p->t_ref, p->kappa, p->restore_tau};
+        for (double x : v)
+            if (!std::isfinite(x)) { why = "chi, g, alpha, rho0, t_ref, kappa and restore_tau must be finite"; return false; }
+    }
     if (p->baro_fuse < 0 || p->baro_fuse > 8) { why = "baro_fuse must be in 0..8"; return false; }
     if (p->salinity != 0 && p->salinity != 1) { why = "salinity must be 0 or 1"; return false; }
     if (p->salinity)

@@ -89,6 +89,14 @@ def test_arena_size_scales_with_precision_and_validates_params():
     bad = ocn.params(w, "fp64")
     bad.dt = -5.0
     assert L.ocn_state_arena_bytes(h, C.byref(bad), C.byref(n64)) == ocn.OCN_E_INVALID
+    for name, value in (("chi", float("nan")), ("g", 0.0), ("g", float("inf")), ("alpha", float("nan")),
+                        ("t_ref", float("inf")), ("restore_tau", float("nan")), ("momentum_form", 2),
+                        ("pgf_weight", 1.5), ("reserved2", 1)):
+        bad = ocn.params(w, "fp64")
+        setattr(bad, name, value)
+        assert L.ocn_state_arena_bytes(h, C.byref(bad), C.byref(n64)) == ocn.OCN_E_INVALID, name
+    vi = ocn.params(w.replace(momentum_form="vector_invariant"), "fp64")
+    assert vi.momentum_form == 1 and L.ocn_state_arena_bytes(h, C.byref(vi), C.byref(n64)) == 0
     # state calls reject NULL handles without touching a device
     assert L.ocn_step(None, 1) == ocn.OCN_E_INVALID
     assert L.ocn_synchronize(None) == ocn.OCN_E_INVALID
