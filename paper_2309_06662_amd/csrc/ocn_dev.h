@@ -258,7 +258,7 @@ __device__ __forceinline__ void for_each_queued_tile(int* q, const int n, F&& f)
 constexpr int kMaxLevels = 128;
 constexpr int kBaroTileX = 64, kBaroTileY = 24;
 // substeps per barotropic launch unless chosen: 7 keeps the 64 x 24 tile's LDS
-// (72 KB) and registers (119) within two workgroups per CU
+// (77 KB) and registers (128) within two workgroups per CU
 constexpr int kBaroFuseDefault = 7;
 
 }  // namespace ocn
