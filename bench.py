@@ -742,8 +742,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the decomposition it would use is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     w = inputs.WORKLOADS[args.workload]

@@ -47,7 +47,7 @@ typedef enum {
     OCN_E_DEVICE = -3,      /* a HIP call failed                                   */
     OCN_E_UNSTABLE = -4,    /* diagnostics found non-finite values                 */
     OCN_E_STATE = -5,       /* call not allowed in the current state               */
-    OCN_E_UNSUPPORTED = -6  /* valid request this build does not implement         */
+    OCN_E_UNSUPPORTED = -6  /* valid request the library does not implement        */
 } ocn_status;
 
 /* Arithmetic of the 3D path. OCN_FP32: tendencies, AB2 and the column solve in
