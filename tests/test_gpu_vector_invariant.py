@@ -9,6 +9,9 @@ on the same seeded inputs.
   levels) and a closed beta-plane basin; with salinity as well;
 - the tendency stage alone within 1e-12: u*, v*, the momentum histories and
   the barotropic slow forcing;
+- with a variable vertical mixing: a prescribed diffusivity field, and
+  Richardson-number mixing (its own viscosity for u and v) diagnosed every
+  step from a sheared state, steps within the same bounds;
 - graph replay is bitwise the eager run; ensembles refuse the form.
 """
 import numpy as np
@@ -93,6 +96,37 @@ def test_tendency_stage(case, first):
     gpu.run_stage(_ocn().STAGE_TENDENCY)
     _compare(ref, gpu, w, inp["kbottom"], 1e-12,
              ("u_pred", "v_pred", "T_pred", "gu_prev", "gv_prev", "gU_slow", "gV_slow"))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+@pytest.mark.parametrize("mixing", ["prescribed", "richardson"])
+def test_with_variable_mixing(mixing, precision, tol):
+    w = CASES["latlon"]()
+    inp = inputs.make_inputs(w)
+    rng = np.random.default_rng(17)
+    _, mu, mv = masks(w, inp["kbottom"])
+    shape = (w.nz, w.ny, w.nx)
+    # a sheared start, so that Richardson numbers fall below the critical value in places
+    u0 = np.where(mu, 0.05 * rng.standard_normal(shape), 0.0)
+    v0 = np.where(mv, 0.05 * rng.standard_normal(shape), 0.0)
+    print(f"case {w.name} {precision} vector-invariant, {mixing} mixing", flush=True)
+    ref = oracle.OracleModel.from_inputs(w, inp)
+    gpu = _ocn().Model(w, precision, inp)
+    gpu.attach_closure()
+    for m in (ref, gpu):
+        m.set("u", u0)
+        m.set("v", v0)
+    if mixing == "prescribed":
+        kw = 10 ** rng.uniform(-5, -2, size=shape)
+        kw[0] = 0.0
+        ref.set("kappa", kw)
+        gpu.set("kappa", kw)
+    else:
+        ref.set_richardson()
+        gpu.set_richardson()
+    ref.step(6)
+    gpu.step(6)
+    _compare(ref, gpu, w, inp["kbottom"], tol, FIELDS)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
