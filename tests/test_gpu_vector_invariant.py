@@ -12,6 +12,8 @@ on the same seeded inputs.
 - with a variable vertical mixing: a prescribed diffusivity field, and
   Richardson-number mixing (its own viscosity for u and v) diagnosed every
   step from a sheared state, steps within the same bounds;
+- small and shallow domains (one to four levels, fewer columns than a tile
+  and than the stencil's reach, periodic or walled) from a random flow;
 - graph replay is bitwise the eager run; ensembles refuse the form.
 """
 import numpy as np
@@ -127,6 +129,29 @@ def test_with_variable_mixing(mixing, precision, tol):
     ref.step(6)
     gpu.step(6)
     _compare(ref, gpu, w, inp["kbottom"], tol, FIELDS)
+
+
+@pytest.mark.parametrize("shape,periodic", [((9, 7, 1), True), ((12, 5, 2), True), ((4, 3, 3), True),
+                                            ((2, 2, 4), True), ((7, 6, 2), False), ((3, 9, 3), False)])
+def test_small_and_shallow_domains(shape, periodic):
+    nx, ny, nz = shape
+    w = inputs.Workload(name=f"tiny_{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, periodic_x=periodic, periodic_y=periodic,
+                        dx=30e3, dy=30e3, depth=200.0 * nz, f0=1e-4, beta=2e-11, dt=900.0, n_substeps=15,
+                        momentum_form="vector_invariant")
+    inp = inputs.make_inputs(w)
+    rng = np.random.default_rng(nx * 100 + ny)
+    _, mu, mv = masks(w, inp["kbottom"])
+    u = np.where(mu, 0.1 * rng.normal(size=(nz, ny, nx)), 0.0)
+    v = np.where(mv, 0.1 * rng.normal(size=(nz, ny, nx)), 0.0)
+    print(f"case {w.name} fp64 vector-invariant, periodic {periodic}", flush=True)
+    ref = oracle.OracleModel.from_inputs(w, inp)
+    gpu = _ocn().Model(w, "fp64", inp)
+    for m in (ref, gpu):
+        m.set("u", u)
+        m.set("v", v)
+    ref.step(3)
+    gpu.step(3)
+    _compare(ref, gpu, w, inp["kbottom"], 1e-11, FIELDS)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
