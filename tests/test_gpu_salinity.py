@@ -14,7 +14,9 @@ inputs:
 - salt content and the non-finite count of the diagnostics;
 - graph replay and restart from a checkpoint are bitwise the eager run;
 - a salinity run whose equation of state is linear in T alone equals the
-  temperature-only kernel's run (S passive) within 1e-12.
+  temperature-only kernel's run (S passive) within 1e-12;
+- small and shallow domains (one to three levels, fewer columns than a tile,
+  periodic or walled) from a random flow and salinity.
 """
 import math
 
@@ -227,3 +229,25 @@ def test_linear_temperature_equation_of_state_equals_temperature_only_kernel():
     for name in ("u", "v", "T", "eta", "U", "V"):
         err = rel_l2(b.get(name), a.get(name), mk[name])
         assert err <= 1e-12, (name, err)
+
+
+@pytest.mark.parametrize("shape,periodic", [((9, 7, 1), True), ((4, 3, 3), True), ((7, 6, 2), False)])
+def test_small_and_shallow_domains(shape, periodic):
+    nx, ny, nz = shape
+    w = inputs.Workload(name=f"tiny_{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, periodic_x=periodic, periodic_y=periodic,
+                        dx=30e3, dy=30e3, depth=200.0 * nz, f0=1e-4, beta=2e-11, dt=900.0, n_substeps=15,
+                        salinity=True)
+    inp = inputs.make_inputs(w)
+    rng = np.random.default_rng(nx * 100 + ny + 7)
+    _, mu, mv = masks(w, inp["kbottom"])
+    shape3 = (nz, ny, nx)
+    f = {"u": np.where(mu, 0.1 * rng.normal(size=shape3), 0.0),
+         "v": np.where(mv, 0.1 * rng.normal(size=shape3), 0.0),
+         "S": inp["S0"] + 0.2 * rng.normal(size=shape3)}
+    ref, gpu, _ = _pair(w, "fp64", inp)
+    for n, a in f.items():
+        ref.set(n, a)
+        gpu.set(n, a)
+    ref.step(3)
+    gpu.step(3)
+    _compare(ref, gpu, w, inp["kbottom"], 1e-11)
