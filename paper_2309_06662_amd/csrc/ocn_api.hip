@@ -802,6 +802,7 @@ int ocn_state_arena_bytes(const ocn_grid* grid, const ocn_params* params, size_t
     if (!grid || !bytes) return fail(OCN_E_INVALID, "grid and bytes must not be NULL");
     std::string why;
     if (!valid_params(params, why)) return fail(OCN_E_INVALID, why);
+    if (grid->nz > ocn::kMaxLevels) return fail(OCN_E_UNSUPPORTED, "nz above 128 is not supported (column solve, tendency level table)");
     *bytes = make_plan(grid, params->precision, params->n_substeps, params->salinity).total;
     return OCN_OK;
 }

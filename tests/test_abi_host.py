@@ -97,6 +97,14 @@ def test_arena_size_scales_with_precision_and_validates_params():
         assert L.ocn_state_arena_bytes(h, C.byref(bad), C.byref(n64)) == ocn.OCN_E_INVALID, name
     vi = ocn.params(w.replace(momentum_form="vector_invariant"), "fp64")
     assert vi.momentum_form == 1 and L.ocn_state_arena_bytes(h, C.byref(vi), C.byref(n64)) == 0
+    # 128 levels is the most a state may have
+    for nz, rc_expect in ((128, 0), (129, ocn.OCN_E_UNSUPPORTED)):
+        wz = w.replace(nx=8, ny=6, nz=nz)
+        rc, hz, keepz = _grid(wz)
+        assert rc == 0
+        pz = ocn.params(wz, "fp64")
+        assert L.ocn_state_arena_bytes(hz, C.byref(pz), C.byref(n64)) == rc_expect, nz
+        L.ocn_grid_destroy(hz)
     # state calls reject NULL handles without touching a device
     assert L.ocn_step(None, 1) == ocn.OCN_E_INVALID
     assert L.ocn_synchronize(None) == ocn.OCN_E_INVALID

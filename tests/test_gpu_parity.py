@@ -131,6 +131,22 @@ def test_small_and_shallow_domains_fp64(shape):
     _compare(ref, gpu, w, inp["kbottom"], 1e-11)
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+def test_most_levels(precision, tol):
+    """128 levels, the most a state may have (the largest column-solve bucket
+    and level table), over random wet-layer counts 0..128."""
+    w = inputs.BETA_BASIN_64.replace(name="beta_24x20x128", nx=24, ny=20, nz=128)
+    inp = inputs.make_inputs(w)
+    rng = np.random.default_rng(128)
+    kb = rng.integers(0, w.nz + 1, size=(w.ny, w.nx)).astype(np.int32)
+    kb[kb == 1] = 0
+    inp["kbottom"] = kb
+    ref, gpu, _ = _pair(w, precision, inp=inp)
+    ref.step(4)
+    gpu.step(4)
+    _compare(ref, gpu, w, kb, tol)
+
+
 @pytest.mark.parametrize("periodic", [False, True])
 def test_uneven_bathymetry_fp64(periodic):
     """Random wet-layer counts with land everywhere, including next to periodic
