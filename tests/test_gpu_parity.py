@@ -215,6 +215,27 @@ def test_gpu_conserves_tracer_and_volume():
     assert abs(math.fsum(a)) <= 1e-12 * np.abs(a).sum()
 
 
+def test_zero_and_negative_step_counts():
+    """n = 0 changes nothing, eagerly or from a graph; n < 0 is an error with no side effect."""
+    import torch
+
+    ocn = _ocn()
+    w = small_latlon(nx=40, ny=28, nz=5)
+    inp = inputs.make_inputs(w)
+    m = ocn.Model(w, "fp64", inp, stream=torch.cuda.Stream())
+    m.step(2, graph=True)
+    m.synchronize()
+    before = {n: m.get(n) for n in ("u", "v", "T", "eta", "U", "V", "gu_prev")}
+    for graph in (False, True):
+        m.step(0, graph=graph)
+        with pytest.raises(ocn.OcnError):
+            m.step(-1, graph=graph)
+    m.synchronize()
+    assert not m.first_step
+    for n, a in before.items():
+        assert np.array_equal(m.get(n), a), n
+
+
 def test_restart_and_determinism_bitwise():
     w = small_latlon(nx=70, ny=28, nz=6)
     ocn = _ocn()
