@@ -193,14 +193,17 @@ __device__ __forceinline__ int2 band_tile(int t, int gx, int gy) {
 }
 
 // Occupancy target per precision: four waves per SIMD (two FP32 workgroups of
-// 8 waves per CU) keeps the FP32 kernel within 128 VGPRs. The second tracer
-// (or the vector-invariant momentum form) needs about 170 VGPRs in FP32: its
-// 32 x 8 tiles run at three waves per SIMD (three 4-wave workgroups per CU;
-// 25 % faster than 32 x 16 tiles at two). The FP64 salinity kernel on 64 x 4 tiles holds one workgroup per CU
-// (two would exceed the LDS).
+// 8 waves per CU) keeps the FP32 kernel within 128 VGPRs, and so does the
+// vector-invariant momentum form on the same 32 x 16 tiles (11 % faster than
+// 32 x 8 tiles at three waves). The second tracer needs about 170 VGPRs in
+// FP32: its 32 x 8 tiles run at three waves per SIMD (three 4-wave workgroups
+// per CU; 25 % faster than 32 x 16 tiles at two), with or without the
+// vector-invariant form. The FP64 salinity kernel on 64 x 4 tiles holds one
+// workgroup per CU (two would exceed the LDS).
 template <typename R, bool SALT, int TY> struct TendWaves {
     static constexpr int n = (sizeof(R) == 4 && !SALT)            ? 4
                              : (sizeof(R) == 4 && SALT && TY == 8) ? 3
+                             : (sizeof(R) == 4 && SALT && TY == 16) ? 4
                              : (sizeof(R) == 8 && SALT && TY == 4) ? 1
                                                                    : 2;
 };
@@ -1054,7 +1057,7 @@ hipError_t launch_tendency(const DevState& s, int first, hipStream_t st) {
     constexpr int WX = TendShapeSalt<R>::TX, WY = TendShapeSalt<R>::TY;
     if (s.salinity && s.vi) return launch_tend_shape<R, WX, WY, true, true>(s, first, st);
     if (s.salinity) return launch_tend_shape<R, WX, WY, true, false>(s, first, st);
-    if (s.vi) return launch_tend_shape<R, WX, WY, false, true>(s, first, st);
+    if (s.vi) return launch_tend_shape<R, TendShape<R>::TX, TendShape<R>::TY, false, true>(s, first, st);
     if (s.tend_ty == 8) return launch_tend_shape<R, TXB, 8, false, false>(s, first, st);
     if (s.tend_ty == 4) return launch_tend_shape<R, TXB, 4, false, false>(s, first, st);
     return launch_tend_shape<R, TendShape<R>::TX, TendShape<R>::TY, false, false>(s, first, st);
