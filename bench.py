@@ -445,6 +445,44 @@ def roofline(w, precision, stage_ms, n_baro_launches):
     return main, other, {"barotropic": baro, "column": col}
 
 
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions per
+# second (a wave64 instruction holds a SIMD for 4 cycles)
+VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
+
+
+def _valu_per_cell_from_profiles(workload, precision, path=None):
+    """VALU lane-instructions per cell of the tendency kernel from the
+    committed SQ counter summary, if it was taken on the current source."""
+    path = path or os.path.join(ROOT, "profiles", f"sq_counters_{workload}_{precision}.txt")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    want = f"# source sha256/16 of {KERNEL_SOURCES['k_tend']}: {_src_hash(_kernel_src('k_tend'))}"
+    if want not in text:
+        return None
+    block = text.split("ocn::k_tend<", 1)
+    if len(block) < 2:
+        return None
+    for line in block[1].split("\n"):
+        if "VALU lane-instructions per cell:" in line:
+            return float(line.split("VALU lane-instructions per cell:")[1].split(";")[0])
+    return None
+
+
+def valu_issue_view(w, precision, stage_ms, per_cell=None):
+    """The tendency kernel against the VALU issue rate: instructions per cell
+    (SQ counters of the committed summary) x cells / the measured kernel time."""
+    n = _valu_per_cell_from_profiles(w.name, precision) if per_cell is None else per_cell
+    if n is None:
+        return None
+    rate = n * w.cells / (stage_ms["tendency"] * 1e-3)
+    return {"kernel": "k_tend", "bound": "valu_issue", "instructions_per_cell": n,
+            "achieved": round(rate / 1e12, 2), "peak": round(VALU_ISSUE_PEAK / 1e12, 2),
+            "unit": "T lane-instructions/s", "frac": round(rate / VALU_ISSUE_PEAK, 4),
+            "source": f"profiles/sq_counters_{w.name}_{precision}.txt"}
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -625,6 +663,7 @@ def sq_summary(a):
                 del p[k]
     lines = [f"# rocprofv3 SQ counters of the last dispatch of each kernel, {a.precision.upper()} step of {w.name}"]
     lines += [f"# command: {c}" for c in a.command]
+    lines += [f"# source sha256/16 of {KERNEL_SOURCES[k]}: {_src_hash(_kernel_src(k))}" for k in sorted(KERNEL_SOURCES)]
     lines += ["# VALU busy = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs); per-cell figures",
               "# are instructions x 64 lanes / cells (columns x substeps for the barotropic kernel)", ""]
     for part in ("ocn::k_tend<", "ocn::k_baro_fused<", "ocn::k_column<"):
@@ -827,6 +866,7 @@ def main():
         "stage_ms": main_rec["stage_ms"],
         "roofline": roof,
         "roofline_other_view": other,
+        "roofline_valu_issue": valu_issue_view(w, "fp32", main_rec["stage_ms"]),
         "stage_rooflines": stage_roofs,
         "cpu_baseline": cpu,
     }

@@ -144,3 +144,20 @@ def test_stats_summary_table_and_tendency_launches(tmp_path):
     assert "20000.0" in text and "60000.0" in text
     # the first launch is the start step; the steady mean is over the others
     assert "16000.0, 22000.0, 21000.0; steady (AB2) mean 21500.0 us" in text
+
+
+def test_valu_issue_view_reads_the_summary_of_the_current_source(tmp_path):
+    cur = bench._src_hash(bench._kernel_src("k_tend"))
+    body = ("void ocn::k_tend<float, 32, 16, false, false> (dispatch 5/5): 1 cycles per XCD\n"
+            "  VALU lane-instructions per cell: 800; LDS per cell: 90.0; SALU/VALU 0.35\n")
+    good, stale = tmp_path / "good.txt", tmp_path / "stale.txt"
+    good.write_text(f"# source sha256/16 of k_tend.hip: {cur}\n" + body)
+    stale.write_text("# source sha256/16 of k_tend.hip: 0000000000000000\n" + body)
+    w = inputs.LATLON_TWELFTH
+    assert bench._valu_per_cell_from_profiles(w.name, "fp32", path=str(good)) == 800.0
+    assert bench._valu_per_cell_from_profiles(w.name, "fp32", path=str(stale)) is None
+    # 800 instructions x 7.776e8 cells in 20 ms against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+    v = bench.valu_issue_view(w, "fp32", {"tendency": 20.0}, per_cell=800.0)
+    rate = 800.0 * 4320 * 1800 * 100 / 0.020
+    assert v["achieved"] == pytest.approx(rate / 1e12, abs=0.01)
+    assert v["frac"] == pytest.approx(rate / (256 * 4 * 16 * 2.4e9), abs=1e-4)
