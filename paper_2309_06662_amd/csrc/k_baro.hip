@@ -125,10 +125,9 @@ namespace ocn {
 // second, while no thread writes them.
 constexpr int FSMAX = 8, FT = 512;
 // Tile shapes: kBaroTileX x kBaroTileY for large grids and the ensembles;
-// 32 x 16 for grids with fewer large tiles than CUs, where the number of
-// workgroups, not the recomputed halo, sets the time.
+// 32 x 16 where that costs less (use_small_tiles): small tiles recompute more
+// halo per interior point but fill the last round of workgroups better.
 constexpr int kSmallTileX = 32, kSmallTileY = 16;
-constexpr int kManyTiles = 256;
 
 
 // Registers hold only what each halo-inclusive point needs every substep
@@ -549,10 +548,28 @@ hipError_t launch_barotropic_batched(const DevState* members, int n_members, con
     return hipGetLastError();
 }
 
+// Small tiles recompute more halo per interior point: (32 + 2s)(16 + 2s) /
+// 512 against (64 + 2s)(24 + 2s) / 1536, 1.40 times as many points at s = 7.
+// They pay where the large tiles leave the device idle: a launch runs
+// ceil(tiles / resident) rounds of workgroups, and the large tiles fill the
+// fraction tiles / (rounds x resident) of them. Small tiles are taken when
+// that fill times the halo ratio is below 1. At 1/4 degree (1440 x 600) the
+// 575 large tiles fill 0.56 of two rounds and the small tiles cost less
+// (0.56 against 0.66 ms per step); at 1/12 degree the 5100 large tiles fill
+// ten rounds and win (small tiles there took 4.06 against 3.86 ms).
+static bool use_small_tiles(const DevState& s, int sub) {
+    const long long n = (long long)((s.nx + kBaroTileX - 1) / kBaroTileX) * ((s.ny + kBaroTileY - 1) / kBaroTileY);
+    const long long slots =
+        std::max(1, resident_workgroups((const void*)k_baro_fused<kBaroTileX, kBaroTileY, kBaroFuseDefault>, FT));
+    const double fill = double(n) / double(((n + slots - 1) / slots) * slots);
+    const double halo = (double((kSmallTileX + 2 * sub) * (kSmallTileY + 2 * sub)) / (kSmallTileX * kSmallTileY)) /
+                        (double((kBaroTileX + 2 * sub) * (kBaroTileY + 2 * sub)) / (kBaroTileX * kBaroTileY));
+    return fill * halo < 1.0;
+}
+
 hipError_t launch_barotropic_fused(const DevState& s, hipStream_t st) {
     const int sub = std::min(s.baro_fuse, FSMAX);
-    const bool small = (long long)((s.nx + kBaroTileX - 1) / kBaroTileX) * ((s.ny + kBaroTileY - 1) / kBaroTileY) <
-                       kManyTiles;
+    const bool small = use_small_tiles(s, sub);
     const int bx = small ? kSmallTileX : kBaroTileX, by = small ? kSmallTileY : kBaroTileY;
     const int gx = (s.nx + bx - 1) / bx, gy = (s.ny + by - 1) / by;
     const dim3 grid(gx * gy);
