@@ -698,9 +698,9 @@ def sq_summary(a):
 
 def stats_summary(a):
     """Text summary of a rocprofv3 --kernel-trace --stats run: the per-kernel
-    table (microseconds) and the duration of every tendency launch, with the
-    mean of the steady ones (the first launch of a run is the forward-Euler
-    start step)."""
+    table (microseconds) and, for a tendency kernel launched at most 24
+    times (one workload), the duration of every launch with the mean of the
+    steady ones (the first launch of a run is the forward-Euler start step)."""
     import csv
 
     rows = list(csv.DictReader(open(os.path.join(a.stats_dir, "run_kernel_stats.csv"))))
@@ -719,6 +719,8 @@ def stats_summary(a):
             per.setdefault(name, []).append((int(r["Dispatch_Id"]),
                                              (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
     for name, calls in per.items():
+        if len(calls) > 24:  # launches of several workloads: the table's figures stand alone
+            continue
         us = [d for _, d in sorted(calls)]
         steady = us[1:] or us
         lines.append(f"# {name} per call: {', '.join(f'{d:.1f}' for d in us)}; steady (AB2) mean "
