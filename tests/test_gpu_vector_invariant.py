@@ -3,7 +3,7 @@ momentum advection on curvilinear grids; the form is the oracle's reading,
 pinned in its own tests): the HIP path through the C ABI against the oracle
 on the same seeded inputs.
 
-- full steps: FP64 within 1e-11 and FP32 within 1e-4 relative L2 on u, v, T,
+- ten full steps: FP64 within 1e-11 and FP32 within 1e-4 relative L2 on u, v, T,
   eta, U, V over wet points, on a periodic lat-lon basin with seamounts
   (several tendency tiles, ragged tails, corners touching land at many
   levels) and a closed beta-plane basin; with salinity as well;
@@ -68,8 +68,8 @@ def test_steps_match_oracle(case, precision, tol):
     print(f"case {w.name} {precision} vector-invariant", flush=True)
     ref = oracle.OracleModel.from_inputs(w, inp)
     gpu = _ocn().Model(w, precision, inp)
-    ref.step(6)
-    gpu.step(6)
+    ref.step(10)
+    gpu.step(10)
     names = FIELDS + (("S",) if w.salinity else ())
     _compare(ref, gpu, w, inp["kbottom"], tol, names)
 
